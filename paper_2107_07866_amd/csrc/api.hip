@@ -1,0 +1,695 @@
+// Host side of the C ABI declared in misa.h: descriptor validation, the
+// lattice-id map and Neighbor Offset Index (Sec. 3), spline coefficient records
+// (Sec. 4.1), placement of atoms into the Lattice List (Sec. 3, Hash
+// Initialization, with the slot tolerance), and the per-step orchestration of
+// the kernels on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "misa_internal.h"
+
+using namespace misa;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(misa_lattice *h, int code, const std::string &msg) {
+    if (h)
+        h->err = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+
+#define HIPCHK(h, expr)                                                                            \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((h), MISA_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+int64_t next_pow2(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+template <typename T>
+hipError_t dev_alloc(T **p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * (size_t)count);
+}
+
+// ---------------------------------------------------------------------------
+// Neighbor Offset Index: all lattice-id offsets (dX, dY, dZ) whose site lies
+// strictly closer than R to a site of the given parity.
+
+struct CanonOffset {
+    int dX, dY, dZ;
+    double d2;
+};
+
+std::vector<CanonOffset> enumerate_offsets(double a, double R, int parity) {
+    std::vector<CanonOffset> out;
+    const int w = (int)std::ceil(R / a) + 1;
+    for (int dZ = -w; dZ <= w; ++dZ)
+        for (int dY = -w; dY <= w; ++dY)
+            for (int dX = -2 * w; dX <= 2 * w; ++dX) {
+                if (!dX && !dY && !dZ) continue;
+                const int pn = ((parity + dX) % 2 + 2) % 2;
+                const double ox = dX * 0.5 * a;
+                const double oy = (dY + 0.5 * pn - 0.5 * parity) * a;
+                const double oz = (dZ + 0.5 * pn - 0.5 * parity) * a;
+                const double d2 = ox * ox + oy * oy + oz * oz;
+                if (d2 < R * R) out.push_back({dX, dY, dZ, d2});
+            }
+    // shell order (nearest first) so consecutive offsets of a wave read one band of the tables
+    std::sort(out.begin(), out.end(), [](const CanonOffset &l, const CanonOffset &r) {
+        if (l.d2 != r.d2) return l.d2 < r.d2;
+        if (l.dZ != r.dZ) return l.dZ < r.dZ;
+        if (l.dY != r.dY) return l.dY < r.dY;
+        return l.dX < r.dX;
+    });
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// spline records: local cubic Hermite per segment, node slopes from fourth-order
+// central differences (second-order / one-sided next to the ends), in units of
+// the sample spacing.
+
+void node_slopes(const double *y, int n, std::vector<double> &m) {
+    m.assign(n, 0.0);
+    m[0] = y[1] - y[0];
+    m[1] = (y[2] - y[0]) / 2.0;
+    for (int k = 2; k <= n - 3; ++k) m[k] = (y[k - 2] - 8.0 * y[k - 1] + 8.0 * y[k + 1] - y[k + 2]) / 12.0;
+    m[n - 2] = (y[n - 1] - y[n - 3]) / 2.0;
+    m[n - 1] = y[n - 1] - y[n - 2];
+}
+
+struct SegCoef {
+    double c0, c1, c2, c3;  // value in the local variable t in [0, 1]
+    double d0, d1, d2;      // d/dx
+};
+
+std::vector<SegCoef> segments(const misa_table &t) {
+    std::vector<double> m;
+    node_slopes(t.y, t.n, m);
+    std::vector<SegCoef> s(t.n - 1);
+    for (int k = 0; k < t.n - 1; ++k) {
+        const double dy = t.y[k + 1] - t.y[k];
+        SegCoef c;
+        c.c0 = t.y[k];
+        c.c1 = m[k];
+        c.c2 = 3.0 * dy - 2.0 * m[k] - m[k + 1];
+        c.c3 = m[k] + m[k + 1] - 2.0 * dy;
+        c.d0 = c.c1 / t.dx;
+        c.d1 = 2.0 * c.c2 / t.dx;
+        c.d2 = 3.0 * c.c3 / t.dx;
+        s[k] = c;
+    }
+    return s;
+}
+
+template <typename Real>
+TabMeta<Real> meta_of(const misa_table &t) {
+    std::vector<double> m;
+    node_slopes(t.y, t.n, m);
+    TabMeta<Real> M{};
+    M.x0 = (Real)t.x0;
+    M.inv_h = (Real)(1.0 / t.dx);
+    M.nseg = t.n - 1;
+    M.x_last = (Real)(t.x0 + (t.n - 1) * t.dx);
+    M.y_last = (Real)t.y[t.n - 1];
+    M.d_last = (Real)(m[t.n - 1] / t.dx);
+    return M;
+}
+
+template <typename Real>
+int upload_tables(misa_lattice *h, DevTables<Real> &D, const std::vector<SegCoef> &sf,
+                  const std::vector<SegCoef> &sp, const std::vector<SegCoef> &se, const misa_table &f,
+                  const misa_table &e) {
+    const size_t nf = sf.size(), ne = se.size();
+    std::vector<Q4<Real>> F(nf), FO(2 * nf), PH(nf), EM(2 * ne);
+    for (size_t k = 0; k < nf; ++k) {
+        F[k] = {(Real)sf[k].c0, (Real)sf[k].c1, (Real)sf[k].c2, (Real)sf[k].c3};
+        FO[2 * k] = {(Real)sf[k].d0, (Real)sf[k].d1, (Real)sf[k].d2, (Real)sp[k].d0};
+        FO[2 * k + 1] = {(Real)sp[k].d1, (Real)sp[k].d2, (Real)0, (Real)0};
+        PH[k] = {(Real)sp[k].c0, (Real)sp[k].c1, (Real)sp[k].c2, (Real)sp[k].c3};
+    }
+    for (size_t k = 0; k < ne; ++k) {
+        EM[2 * k] = {(Real)se[k].c0, (Real)se[k].c1, (Real)se[k].c2, (Real)se[k].c3};
+        EM[2 * k + 1] = {(Real)se[k].d0, (Real)se[k].d1, (Real)se[k].d2, (Real)0};
+    }
+    (void)hipFree(D.f);
+    (void)hipFree(D.force);
+    (void)hipFree(D.phi);
+    (void)hipFree(D.emb);
+    D.f = D.force = D.phi = D.emb = nullptr;
+    HIPCHK(h, dev_alloc(&D.f, (int64_t)nf));
+    HIPCHK(h, dev_alloc(&D.force, (int64_t)(2 * nf)));
+    HIPCHK(h, dev_alloc(&D.phi, (int64_t)nf));
+    HIPCHK(h, dev_alloc(&D.emb, (int64_t)(2 * ne)));
+    HIPCHK(h, hipMemcpy(D.f, F.data(), sizeof(Q4<Real>) * nf, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(D.force, FO.data(), sizeof(Q4<Real>) * 2 * nf, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(D.phi, PH.data(), sizeof(Q4<Real>) * nf, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(D.emb, EM.data(), sizeof(Q4<Real>) * 2 * ne, hipMemcpyHostToDevice));
+    D.fm = meta_of<Real>(f);
+    D.em = meta_of<Real>(e);
+    return MISA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// state layout inside the caller's buffer
+
+int64_t carve(misa_lattice *h, char *base, State *S) {
+    const int64_t ns = h->g.nsites, rc = h->rcap;
+    const int64_t rs = h->precision == MISA_FP32 ? 4 : 8;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    State s{};
+    s.ux = (double *)take(8 * ns);
+    s.uy = (double *)take(8 * ns);
+    s.uz = (double *)take(8 * ns);
+    s.vx = (double *)take(8 * ns);
+    s.vy = (double *)take(8 * ns);
+    s.vz = (double *)take(8 * ns);
+    s.fx = take(rs * ns);
+    s.fy = take(rs * ns);
+    s.fz = take(rs * ns);
+    s.rho = take(rs * ns);
+    s.fp = take(rs * ns);
+    s.atom = (int32_t *)take(4 * ns);
+    s.r_id = (int32_t *)take(4 * rc);
+    double **rd[] = {&s.r_x, &s.r_y, &s.r_z, &s.r_vx, &s.r_vy, &s.r_vz, &s.r_fx, &s.r_fy, &s.r_fz, &s.r_rho, &s.r_fp};
+    for (double **p : rd) *p = (double *)take(8 * rc);
+    s.r_e = (double *)take(16 * rc);
+    if (S) *S = s;
+    return off;
+}
+
+hipError_t ensure_staging(misa_lattice *h, int64_t bytes) {
+    if (bytes <= h->staging_bytes) return hipSuccess;
+    (void)hipFree(h->staging);
+    h->staging = nullptr;
+    h->staging_bytes = 0;
+    hipError_t e = hipMalloc((void **)&h->staging, (size_t)bytes);
+    if (e == hipSuccess) h->staging_bytes = bytes;
+    return e;
+}
+
+int check_ready(misa_lattice *h, bool need_tables) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    if (!h->state_bound) return fail(h, MISA_ESTATE, "no state buffer bound (misa_bind_state)");
+    if (!h->state_set) return fail(h, MISA_ESTATE, "no atoms loaded (misa_set_state)");
+    if (need_tables && !h->tables_set) return fail(h, MISA_ESTATE, "no potential tables (misa_set_potential_tables)");
+    return MISA_OK;
+}
+
+hipError_t clear_marks(misa_lattice *h);
+
+int do_rho(misa_lattice *h) {
+    if (h->pending_clear) {
+        HIPCHK(h, clear_marks(h));
+        HIPCHK(h, launch_runaway_clear(h));
+        h->pending_clear = false;
+    }
+    HIPCHK(h, launch_runaway_build(h));
+    HIPCHK(h, launch_rho(h));
+    HIPCHK(h, launch_runaway_rho(h));
+    h->pending_clear = true;
+    h->rho_valid = true;
+    h->force_valid = false;
+    return MISA_OK;
+}
+
+int do_force(misa_lattice *h, bool energy, double *energies_dev) {
+    HIPCHK(h, launch_force(h, energy));
+    HIPCHK(h, launch_runaway_force(h, energy));
+    if (energy) HIPCHK(h, launch_energy_reduce(h, energies_dev));
+    HIPCHK(h, launch_runaway_clear(h));
+    h->pending_clear = false;
+    h->force_valid = true;
+    return MISA_OK;
+}
+
+}  // namespace
+
+// k_clear_marks lives here: it only zeroes mark words of listed sites.
+namespace misa {
+__global__ void k_clear_marks(Scratch sc) {
+    int na = sc.cnt->n_affected;
+    na = na < sc.affected_cap ? na : (int)sc.affected_cap;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < na; q += gridDim.x * blockDim.x)
+        sc.mark[sc.affected[q] >> 5] = 0u;
+}
+}  // namespace misa
+
+namespace {
+hipError_t clear_marks(misa_lattice *h) {
+    hipLaunchKernelGGL(misa::k_clear_marks, dim3(SMALL_GRID), dim3(256), 0, h->stream, h->sc);
+    return hipGetLastError();
+}
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+const char *misa_last_error(const misa_lattice *h) {
+    if (!h) return g_create_error.c_str();
+    return h->err.c_str();
+}
+
+int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_lattice **out) {
+    if (!d || !out) return fail(nullptr, MISA_EINVAL, "null descriptor or output pointer");
+    *out = nullptr;
+    for (int k = 0; k < 3; ++k)
+        if (d->n_cells[k] < 1) return fail(nullptr, MISA_EINVAL, "n_cells must be >= 1");
+    if (!(d->a > 0) || !(d->rc > 0) || !(d->mass > 0)) return fail(nullptr, MISA_EINVAL, "a, rc and mass must be > 0");
+    if (!(d->delta > 0) || !(d->delta < d->a * std::sqrt(3.0) / 4.0))
+        return fail(nullptr, MISA_EINVAL, "delta must lie in (0, a sqrt(3)/4)");
+    if (d->pair_precision != MISA_FP64 && d->pair_precision != MISA_FP32)
+        return fail(nullptr, MISA_EINVAL, "pair_precision must be MISA_FP64 or MISA_FP32");
+    const double R = d->rc + 2.0 * d->delta;
+    for (int k = 0; k < 3; ++k)
+        if (!(d->n_cells[k] * d->a > 2.0 * R))
+            return fail(nullptr, MISA_EINVAL, "box too small: n_cells * a must exceed 2 (rc + 2 delta) on every axis");
+    const int64_t ncell = (int64_t)d->n_cells[0] * d->n_cells[1] * d->n_cells[2];
+    if (2 * ncell >= (int64_t)INT32_MAX) return fail(nullptr, MISA_EINVAL, "too many sites (max 2^31 - 1)");
+
+    misa_lattice *h = new (std::nothrow) misa_lattice();
+    if (!h) return fail(nullptr, MISA_ENOMEM, "host allocation failed");
+    h->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&h->device);
+    h->precision = d->pair_precision;
+    h->mass = d->mass;
+    Geom &g = h->g;
+    g.nx = d->n_cells[0];
+    g.ny = d->n_cells[1];
+    g.nz = d->n_cells[2];
+    g.ntx = (g.nx + TX - 1) / TX;
+    g.nty = (g.ny + TY - 1) / TY;
+    g.ntz = (g.nz + TZ - 1) / TZ;
+    g.ntiles = g.ntx * g.nty * g.ntz;
+    g.ntiles_pad = (g.ntiles + 7) / 8 * 8;
+    g.ncell = ncell;
+    g.nsites = 2 * ncell;
+    g.a = d->a;
+    g.inv_a = 1.0 / d->a;
+    const int32_t n3[3] = {g.nx, g.ny, g.nz};
+    for (int k = 0; k < 3; ++k) g.L[k] = (double)n3[k] * d->a;
+    g.rc = d->rc;
+    g.rc2 = d->rc * d->rc;
+    g.delta2 = d->delta * d->delta;
+    g.pre2 = (d->rc * (1.0 + 1e-9)) * (d->rc * (1.0 + 1e-9));
+    for (int k = 0; k < 3; ++k) {
+        int nc = (int)std::floor(g.L[k] / (d->rc * (1.0 + 1e-9)));
+        if (nc < 1) nc = 1;
+        g.nc[k] = nc;
+        g.inv_cs[k] = (double)nc / g.L[k];
+    }
+    if ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] >= (int64_t)INT32_MAX) {
+        delete h;
+        return fail(nullptr, MISA_EINVAL, "too many coarse cells");
+    }
+    g.reach = (d->rc + d->delta) / d->a;
+    g.win = (int)std::ceil(2.0 * g.reach + 0.5);
+    for (int k = 0; k < 3; ++k)
+        if (g.win > n3[k]) {
+            delete h;
+            return fail(nullptr, MISA_EINVAL, "box too small for the run-away search window");
+        }
+    h->rcap = d->runaway_capacity > 0 ? d->runaway_capacity : std::max<int64_t>(16384, g.nsites / 1024);
+    if (h->rcap > (int64_t)1 << 28) {
+        delete h;
+        return fail(nullptr, MISA_EINVAL, "runaway_capacity too large");
+    }
+
+    // Neighbor Offset Index per parity
+    std::vector<CanonOffset> st[2] = {enumerate_offsets(d->a, R, 0), enumerate_offsets(d->a, R, 1)};
+    if (st[0].size() != st[1].size() || st[0].size() > (size_t)KMAX) {
+        delete h;
+        return fail(nullptr, MISA_EINVAL, "stencil larger than the kernels support (rc + 2 delta too large)");
+    }
+    h->K = (int)st[0].size();
+    h->stencil_canon.resize(2 * h->K * 3);
+    std::vector<StencilEntry<double>> s64(2 * KMAX);
+    std::vector<StencilEntry<float>> s32(2 * KMAX);
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < h->K; ++k) {
+            const CanonOffset &o = st[p][k];
+            const int pn = ((p + o.dX) % 2 + 2) % 2;
+            const int dcx = (p + o.dX - pn) / 2, dcy = o.dY, dcz = o.dZ;
+            if (std::abs(dcx) > HALO || std::abs(dcy) > HALO || std::abs(dcz) > HALO) {
+                delete h;
+                return fail(nullptr, MISA_EINVAL, "stencil reaches beyond the LDS halo (rc + 2 delta too large)");
+            }
+            const int lds = (pn - p) * PZ * PY * PX + (dcz * PY + dcy) * PX + dcx;
+            const double ox = o.dX * 0.5 * d->a;
+            const double oy = (o.dY + 0.5 * pn - 0.5 * p) * d->a;
+            const double oz = (o.dZ + 0.5 * pn - 0.5 * p) * d->a;
+            s64[p * KMAX + k] = StencilEntry<double>{lds, 0, ox, oy, oz};
+            s32[p * KMAX + k] = StencilEntry<float>{lds, (float)ox, (float)oy, (float)oz};
+            int64_t *c = &h->stencil_canon[(p * h->K + k) * 3];
+            c[0] = o.dX;
+            c[1] = o.dY;
+            c[2] = o.dZ;
+        }
+
+    // scratch
+    Scratch &sc = h->sc;
+    const int64_t rcap = h->rcap;
+    const int64_t H = next_pow2(2 * rcap);
+    sc.hmask = (int32_t)(H - 1);
+    sc.affected_cap = std::min<int64_t>(g.nsites, 128 * rcap);
+    auto bail = [&](hipError_t e) {
+        std::string m = std::string("device allocation failed: ") + hipGetErrorString(e);
+        misa_destroy_lattice(h);
+        return fail(nullptr, MISA_ENOMEM, m);
+    };
+    hipError_t e;
+#define ALLOC(ptr, n)                          \
+    if ((e = dev_alloc(&(ptr), (n))) != hipSuccess) return bail(e);
+    ALLOC(h->st64, 2 * KMAX);
+    ALLOC(h->st32, 2 * KMAX);
+    ALLOC(sc.cnt, 1);
+    ALLOC(sc.scal, 8);
+    ALLOC(sc.part, 2 * (int64_t)g.ntiles_pad + 2 * 1024);
+    ALLOC(sc.l_site, rcap);
+    ALLOC(sc.l_id, rcap);
+    ALLOC(sc.l_x, rcap);
+    ALLOC(sc.l_y, rcap);
+    ALLOC(sc.l_z, rcap);
+    ALLOC(sc.l_vx, rcap);
+    ALLOC(sc.l_vy, rcap);
+    ALLOC(sc.l_vz, rcap);
+    ALLOC(sc.cand, rcap);
+    ALLOC(sc.settled, rcap);
+    ALLOC(sc.sortbuf, next_pow2(rcap));
+    ALLOC(sc.skey, rcap);
+    ALLOC(sc.sidx, rcap);
+    ALLOC(sc.hslot, rcap);
+    ALLOC(sc.hkey, H);
+    ALLOC(sc.hval, H);
+    ALLOC(sc.mark, (g.nsites + 31) / 32);
+    ALLOC(sc.affected, sc.affected_cap);
+#undef ALLOC
+    if ((e = hipMemcpy(h->st64, s64.data(), sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(h->st32, s32.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
+        (e = hipMemset(sc.cnt, 0, sizeof(Counters))) || (e = hipMemset(sc.scal, 0, 8 * sizeof(double))) ||
+        (e = hipMemset(sc.hkey, 0xff, sizeof(int32_t) * (size_t)H)) ||
+        (e = hipMemset(sc.mark, 0, sizeof(uint32_t) * (size_t)((g.nsites + 31) / 32))) ||
+        (e = hipDeviceSynchronize())) {
+        std::string m = std::string("device initialisation failed: ") + hipGetErrorString(e);
+        misa_destroy_lattice(h);
+        return fail(nullptr, MISA_EHIP, m);
+    }
+    *out = h;
+    return MISA_OK;
+}
+
+int misa_destroy_lattice(misa_lattice *h) {
+    if (!h) return MISA_OK;
+    if (h->stream)
+        (void)hipStreamSynchronize(h->stream);
+    else
+        (void)hipDeviceSynchronize();
+    void *ptrs[] = {h->st64, h->st32, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t32.f, h->t32.force,
+                    h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
+                    h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
+                    h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,
+                    h->sc.affected, h->staging};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete h;
+    return MISA_OK;
+}
+
+int misa_state_bytes(const misa_lattice *h, int64_t *bytes) {
+    if (!h || !bytes) return fail(nullptr, MISA_EINVAL, "null argument");
+    *bytes = carve(const_cast<misa_lattice *>(h), nullptr, nullptr);
+    return MISA_OK;
+}
+
+int misa_bind_state(misa_lattice *h, void *device_ptr, int64_t bytes) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    const int64_t need = carve(h, nullptr, nullptr);
+    if (!device_ptr || bytes < need) return fail(h, MISA_EINVAL, "state buffer missing or smaller than misa_state_bytes");
+    if (((uintptr_t)device_ptr & 255u) != 0) return fail(h, MISA_EINVAL, "state buffer must be 256-byte aligned");
+    h->state_ptr = device_ptr;
+    h->state_bytes = bytes;
+    carve(h, (char *)device_ptr, &h->S);
+    h->state_bound = true;
+    h->state_set = h->rho_valid = h->force_valid = false;
+    return MISA_OK;
+}
+
+int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_table *phi, const misa_table *emb) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    const misa_table *t3[3] = {f, phi, emb};
+    for (const misa_table *t : t3) {
+        if (!t || !t->y) return fail(h, MISA_EINVAL, "null table");
+        if (t->n < 8 || !(t->dx > 0) || !std::isfinite(t->x0)) return fail(h, MISA_EINVAL, "tables need n >= 8 and dx > 0");
+        for (int k = 0; k < t->n; ++k)
+            if (!std::isfinite(t->y[k])) return fail(h, MISA_EINVAL, "non-finite table sample");
+    }
+    if (f->x0 != phi->x0 || f->dx != phi->dx || f->n != phi->n)
+        return fail(h, MISA_EINVAL, "f and phi must share one grid");
+    if (f->x0 < 0.0 || f->x0 + (f->n - 1) * f->dx < h->g.rc * (1.0 - 1e-12))
+        return fail(h, MISA_EINVAL, "f/phi grid must start at x0 >= 0 and reach rc");
+    const std::vector<SegCoef> sf = segments(*f), sp = segments(*phi), se = segments(*emb);
+    int rc = upload_tables<double>(h, h->t64, sf, sp, se, *f, *emb);
+    if (rc) return rc;
+    rc = upload_tables<float>(h, h->t32, sf, sp, se, *f, *emb);
+    if (rc) return rc;
+    h->tables_set = true;
+    h->rho_valid = h->force_valid = false;
+    return MISA_OK;
+}
+
+int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n, int where) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    if (!h->state_bound) return fail(h, MISA_ESTATE, "no state buffer bound (misa_bind_state)");
+    if (n < 0 || n >= (int64_t)INT32_MAX) return fail(h, MISA_EINVAL, "atom count out of range");
+    if (n > 0 && (!x || !v)) return fail(h, MISA_EINVAL, "null positions or velocities");
+    if (where != MISA_HOST && where != MISA_DEVICE) return fail(h, MISA_EINVAL, "bad memory kind");
+    const Geom &g = h->g;
+    std::vector<double> hx, hv;
+    const double *X = x, *V = v;
+    if (where == MISA_DEVICE && n > 0) {
+        hx.resize(3 * n);
+        hv.resize(3 * n);
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, hipMemcpy(hx.data(), x, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+        HIPCHK(h, hipMemcpy(hv.data(), v, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+        X = hx.data();
+        V = hv.data();
+    }
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(X[i]) || !std::isfinite(V[i])) return fail(h, MISA_EINVAL, "non-finite position or velocity");
+    // placement: ascending atom id, first claimant of a slot is the lowest id
+    const int64_t ns = g.nsites;
+    std::vector<int32_t> atom(ns, VACANT_ID);
+    std::vector<double> u(3 * ns, VACANT_U), vel(3 * ns, 0.0);
+    std::vector<int32_t> rid;
+    std::vector<double> rpos, rvel;
+    for (int64_t i = 0; i < n; ++i) {
+        double uu[3], u2;
+        const int64_t s = hash_site(X + 3 * i, g, uu, &u2);
+        if (u2 <= g.delta2 && atom[s] == VACANT_ID) {
+            atom[s] = (int32_t)i;
+            for (int k = 0; k < 3; ++k) {
+                u[k * ns + s] = uu[k];
+                vel[k * ns + s] = V[3 * i + k];
+            }
+        } else {
+            rid.push_back((int32_t)i);
+            for (int k = 0; k < 3; ++k) {
+                rpos.push_back(wrap_coord(X[3 * i + k], g.L[k]));
+                rvel.push_back(V[3 * i + k]);
+            }
+        }
+    }
+    const int64_t R = (int64_t)rid.size();
+    if (R > h->rcap)
+        return fail(h, MISA_EOVERFLOW, "more atoms off their sites (" + std::to_string(R) +
+                                           ") than the run-away capacity (" + std::to_string(h->rcap) + ")");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    State &S = h->S;
+    double *ud[3] = {S.ux, S.uy, S.uz}, *vd[3] = {S.vx, S.vy, S.vz};
+    for (int k = 0; k < 3; ++k) {
+        HIPCHK(h, hipMemcpy(ud[k], u.data() + k * ns, sizeof(double) * ns, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(vd[k], vel.data() + k * ns, sizeof(double) * ns, hipMemcpyHostToDevice));
+    }
+    HIPCHK(h, hipMemcpy(S.atom, atom.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice));
+    const int64_t rs = h->precision == MISA_FP32 ? 4 : 8;
+    HIPCHK(h, hipMemset(S.fx, 0, rs * ns));
+    HIPCHK(h, hipMemset(S.fy, 0, rs * ns));
+    HIPCHK(h, hipMemset(S.fz, 0, rs * ns));
+    HIPCHK(h, hipMemset(S.rho, 0, rs * ns));
+    HIPCHK(h, hipMemset(S.fp, 0, rs * ns));
+    if (R > 0) {
+        std::vector<double> col(R);
+        double *rpd[3] = {S.r_x, S.r_y, S.r_z}, *rvd[3] = {S.r_vx, S.r_vy, S.r_vz};
+        for (int k = 0; k < 3; ++k) {
+            for (int64_t r = 0; r < R; ++r) col[r] = rpos[3 * r + k];
+            HIPCHK(h, hipMemcpy(rpd[k], col.data(), sizeof(double) * R, hipMemcpyHostToDevice));
+            for (int64_t r = 0; r < R; ++r) col[r] = rvel[3 * r + k];
+            HIPCHK(h, hipMemcpy(rvd[k], col.data(), sizeof(double) * R, hipMemcpyHostToDevice));
+        }
+        HIPCHK(h, hipMemcpy(S.r_id, rid.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemset(S.r_fx, 0, 8 * R));
+        HIPCHK(h, hipMemset(S.r_fy, 0, 8 * R));
+        HIPCHK(h, hipMemset(S.r_fz, 0, 8 * R));
+    }
+    Counters c{};
+    c.n_run = (int32_t)R;
+    HIPCHK(h, hipMemcpy(h->sc.cnt, &c, sizeof(c), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemset(h->sc.scal, 0, 8 * sizeof(double)));
+    HIPCHK(h, hipMemset(h->sc.mark, 0, sizeof(uint32_t) * (size_t)((g.nsites + 31) / 32)));
+    HIPCHK(h, hipMemset(h->sc.hkey, 0xff, sizeof(int32_t) * (size_t)(h->sc.hmask + 1)));
+    HIPCHK(h, hipDeviceSynchronize());
+    h->n_atoms = n;
+    h->steps_done = 0;
+    h->state_set = true;
+    h->rho_valid = h->force_valid = h->pending_clear = false;
+    return MISA_OK;
+}
+
+int misa_atom_count(const misa_lattice *h, int64_t *n_atoms) {
+    if (!h || !n_atoms) return fail(nullptr, MISA_EINVAL, "null argument");
+    *n_atoms = h->n_atoms;
+    return MISA_OK;
+}
+
+int misa_get_state(misa_lattice *h, double *x, double *v, int where) {
+    int rc = check_ready(h, false);
+    if (rc) return rc;
+    if (where != MISA_HOST && where != MISA_DEVICE) return fail(h, MISA_EINVAL, "bad memory kind");
+    const int64_t n = h->n_atoms;
+    if (n == 0 || (!x && !v)) return MISA_OK;
+    if (where == MISA_DEVICE) {
+        HIPCHK(h, launch_gather_state(h, x, v));
+        return MISA_OK;
+    }
+    HIPCHK(h, ensure_staging(h, sizeof(double) * 6 * n));
+    double *dx = h->staging, *dv = h->staging + 3 * n;
+    HIPCHK(h, launch_gather_state(h, x ? dx : nullptr, v ? dv : nullptr));
+    if (x) HIPCHK(h, hipMemcpyAsync(x, dx, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, h->stream));
+    if (v) HIPCHK(h, hipMemcpyAsync(v, dv, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MISA_OK;
+}
+
+int misa_compute_rho(misa_lattice *h) {
+    int rc = check_ready(h, true);
+    if (rc) return rc;
+    return do_rho(h);
+}
+
+int misa_compute_force(misa_lattice *h, double *energies_dev) {
+    int rc = check_ready(h, true);
+    if (rc) return rc;
+    if (!h->rho_valid || !h->pending_clear)
+        return fail(h, MISA_ESTATE, "misa_compute_force needs misa_compute_rho on the same state first");
+    return do_force(h, energies_dev != nullptr, energies_dev);
+}
+
+int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, misa_step_stats *stats) {
+    int rc = check_ready(h, true);
+    if (rc) return rc;
+    if (nsteps < 0 || !(dt_max > 0) || !std::isfinite(dt_max) || !std::isfinite(dx_max))
+        return fail(h, MISA_EINVAL, "nsteps >= 0 and dt_max > 0 required");
+    if (!h->force_valid) {
+        if ((rc = do_rho(h))) return rc;
+        if ((rc = do_force(h, false, nullptr))) return rc;
+    }
+    HIPCHK(h, launch_dt_update(h, dt_max, dx_max, true));
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const bool last = s == nsteps - 1;
+        HIPCHK(h, launch_kick_drift(h));
+        HIPCHK(h, launch_rehash(h));
+        if ((rc = do_rho(h))) return rc;
+        if ((rc = do_force(h, last, nullptr))) return rc;
+        HIPCHK(h, launch_final_kick(h));
+        HIPCHK(h, launch_dt_update(h, dt_max, dx_max, false));
+    }
+    h->steps_done += nsteps;
+    if (!stats) return MISA_OK;
+    double scal[8];
+    Counters c;
+    HIPCHK(h, hipMemcpyAsync(scal, h->sc.scal, sizeof(scal), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&c, h->sc.cnt, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    std::memset(stats, 0, sizeof(*stats));
+    stats->dt_next = scal[0];
+    stats->time = scal[1];
+    stats->vmax = scal[2];
+    stats->e_kin = scal[3];
+    stats->e_emb = nsteps > 0 ? scal[4] : 0.0;
+    stats->e_pair = nsteps > 0 ? scal[5] : 0.0;
+    stats->steps = h->steps_done;
+    stats->n_runaway = c.n_run;
+    stats->range_violations = c.range_viol;
+    stats->overflow = c.overflow;
+    stats->dt = scal[6];
+    if (c.overflow) return fail(h, MISA_EOVERFLOW, "run-away capacity exceeded; forces inexact since");
+    return MISA_OK;
+}
+
+int misa_get_atom_field(misa_lattice *h, int field, double *out, int where) {
+    int rc = check_ready(h, false);
+    if (rc) return rc;
+    if (field < MISA_FIELD_RHO || field > MISA_FIELD_FORCE) return fail(h, MISA_EINVAL, "unknown field");
+    if (where != MISA_HOST && where != MISA_DEVICE) return fail(h, MISA_EINVAL, "bad memory kind");
+    if (!out) return fail(h, MISA_EINVAL, "null output");
+    const int64_t n = h->n_atoms * (field == MISA_FIELD_FORCE ? 3 : 1);
+    if (n == 0) return MISA_OK;
+    if (where == MISA_DEVICE) {
+        HIPCHK(h, launch_gather_field(h, field, out));
+        return MISA_OK;
+    }
+    HIPCHK(h, ensure_staging(h, sizeof(double) * n));
+    HIPCHK(h, launch_gather_field(h, field, h->staging));
+    HIPCHK(h, hipMemcpyAsync(out, h->staging, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MISA_OK;
+}
+
+int64_t misa_debug_export(misa_lattice *h, int what, int64_t *host_out, int64_t capacity) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    if (what == MISA_EXPORT_STENCIL) {
+        const int64_t need = (int64_t)h->stencil_canon.size();
+        if (host_out) std::memcpy(host_out, h->stencil_canon.data(), sizeof(int64_t) * std::min(need, capacity));
+        return h->K;
+    }
+    if (what == MISA_EXPORT_SLOTS) {
+        int rc = check_ready(h, false);
+        if (rc) return rc;
+        const int64_t n = h->n_atoms;
+        if (n == 0 || !host_out) return n;
+        if (capacity < n) return fail(h, MISA_EINVAL, "capacity smaller than the atom count");
+        HIPCHK(h, ensure_staging(h, sizeof(int64_t) * n));
+        HIPCHK(h, launch_gather_slots(h, (int64_t *)h->staging));
+        HIPCHK(h, hipMemcpyAsync(host_out, h->staging, sizeof(int64_t) * n, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return n;
+    }
+    return fail(h, MISA_EINVAL, "unknown export");
+}
+
+}  // extern "C"

@@ -1,0 +1,345 @@
+// Time integration (Sec. 2.1, Fig. 1: force, velocity and position update per
+// step, read as kick-drift-kick velocity Verlet) fused with the first half of
+// the hash update of Algorithm 2 (atoms farther than delta from their site
+// leave the array), the adaptive step length, and the copies out of the store.
+#include "misa_internal.h"
+
+namespace misa {
+
+constexpr int KICK_BLOCKS = 1024;  // fixed grid => fixed reduction order
+constexpr int KICK_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum_i(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_i(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// v += (dt/2) C F / m;  u += dt v;  an atom now farther than delta from its
+// site is appended to this step's leavers and its slot emptied.
+template <typename Real>
+__global__ __launch_bounds__(KICK_THREADS) void k_kick_drift(State S, Scratch sc, Geom g, double kf, int64_t rcap) {
+    const double dt = sc.scal[0];
+    const double hk = 0.5 * dt * kf;
+    const int64_t room = rcap - sc.cnt->n_run;
+    const Real *fx = (const Real *)S.fx;
+    const Real *fy = (const Real *)S.fy;
+    const Real *fz = (const Real *)S.fz;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        double ux = S.ux[s];
+        if (ux > VACANT_TEST) continue;
+        double uy = S.uy[s], uz = S.uz[s];
+        const double vx = S.vx[s] + hk * (double)fx[s];
+        const double vy = S.vy[s] + hk * (double)fy[s];
+        const double vz = S.vz[s] + hk * (double)fz[s];
+        ux += dt * vx;
+        uy += dt * vy;
+        uz += dt * vz;
+        if (ux * ux + uy * uy + uz * uz > g.delta2) {
+            const int slot = atomicAdd(&sc.cnt->n_leave, 1);
+            if (slot < room) {
+                const int p = s >= g.ncell ? 1 : 0;
+                const int64_t c = s - p * g.ncell;
+                double sp[3];
+                site_pos((int)(c % g.nx), (int)((c / g.nx) % g.ny), (int)(c / ((int64_t)g.nx * g.ny)), p, g.a, sp);
+                sc.l_site[slot] = (int32_t)s;
+                sc.l_id[slot] = S.atom[s];
+                sc.l_x[slot] = wrap_coord(sp[0] + ux, g.L[0]);
+                sc.l_y[slot] = wrap_coord(sp[1] + uy, g.L[1]);
+                sc.l_z[slot] = wrap_coord(sp[2] + uz, g.L[2]);
+                sc.l_vx[slot] = vx;
+                sc.l_vy[slot] = vy;
+                sc.l_vz[slot] = vz;
+                S.ux[s] = VACANT_U;
+                S.uy[s] = VACANT_U;
+                S.uz[s] = VACANT_U;
+                S.vx[s] = 0.0;
+                S.vy[s] = 0.0;
+                S.vz[s] = 0.0;
+                S.atom[s] = VACANT_ID;
+                continue;
+            }
+            atomicExch(&sc.cnt->overflow, 1);  // stays in its slot; forces on it become inexact
+        }
+        S.ux[s] = ux;
+        S.uy[s] = uy;
+        S.uz[s] = uz;
+        S.vx[s] = vx;
+        S.vy[s] = vy;
+        S.vz[s] = vz;
+    }
+}
+
+__global__ void k_kick_drift_runaway(State S, Scratch sc, Geom g, double kf) {
+    const double dt = sc.scal[0];
+    const double hk = 0.5 * dt * kf;
+    const int n = sc.cnt->n_run;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const double vx = S.r_vx[r] + hk * S.r_fx[r];
+        const double vy = S.r_vy[r] + hk * S.r_fy[r];
+        const double vz = S.r_vz[r] + hk * S.r_fz[r];
+        S.r_vx[r] = vx;
+        S.r_vy[r] = vy;
+        S.r_vz[r] = vz;
+        S.r_x[r] = wrap_coord(S.r_x[r] + dt * vx, g.L[0]);
+        S.r_y[r] = wrap_coord(S.r_y[r] + dt * vy, g.L[1]);
+        S.r_z[r] = wrap_coord(S.r_z[r] + dt * vz, g.L[2]);
+    }
+}
+
+// Second half-kick (kick = 1) or plain velocity statistics (kick = 0):
+// per-block max |v|^2 and sum |v|^2 over the lattice atoms.
+template <typename Real>
+__global__ __launch_bounds__(KICK_THREADS) void k_final_kick(State S, Scratch sc, Geom g, double kf, int kick,
+                                                             double *__restrict__ part) {
+    __shared__ double red[2][KICK_THREADS / 64];
+    const double hk = 0.5 * sc.scal[0] * kf;
+    const Real *fx = (const Real *)S.fx;
+    const Real *fy = (const Real *)S.fy;
+    const Real *fz = (const Real *)S.fz;
+    double vm = 0.0, ks = 0.0;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        if (S.ux[s] > VACANT_TEST) continue;
+        double vx = S.vx[s], vy = S.vy[s], vz = S.vz[s];
+        if (kick) {
+            vx += hk * (double)fx[s];
+            vy += hk * (double)fy[s];
+            vz += hk * (double)fz[s];
+            S.vx[s] = vx;
+            S.vy[s] = vy;
+            S.vz[s] = vz;
+        }
+        const double q = vx * vx + vy * vy + vz * vz;
+        vm = fmax(vm, q);
+        ks += q;
+    }
+    vm = wave_max_i(vm);
+    ks = wave_sum_i(ks);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = vm;
+        red[1][w] = ks;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < KICK_THREADS / 64; ++k) {
+            a = fmax(a, red[0][k]);
+            b += red[1][k];
+        }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void k_final_kick_runaway(State S, Scratch sc, double kf) {
+    const double hk = 0.5 * sc.scal[0] * kf;
+    const int n = sc.cnt->n_run;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        S.r_vx[r] += hk * S.r_fx[r];
+        S.r_vy[r] += hk * S.r_fy[r];
+        S.r_vz[r] += hk * S.r_fz[r];
+    }
+}
+
+// max |v|, kinetic energy, and the next step length
+// dt = min(dt_max, dx_max / max|v|)  (dx_max <= 0: dt = dt_max).
+__global__ __launch_bounds__(1024) void k_dt_update(State S, Scratch sc, const double *__restrict__ part, int nblk,
+                                                    double mass, double dt_max, double dx_max, int first) {
+    __shared__ double red[2][1024 / 64];
+    double vm = 0.0, ks = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 1024) {
+        vm = fmax(vm, part[2 * i]);
+        ks += part[2 * i + 1];
+    }
+    const int n = sc.cnt->n_run;
+    for (int r = threadIdx.x; r < n; r += 1024) {
+        const double q = S.r_vx[r] * S.r_vx[r] + S.r_vy[r] * S.r_vy[r] + S.r_vz[r] * S.r_vz[r];
+        vm = fmax(vm, q);
+        ks += q;
+    }
+    vm = wave_max_i(vm);
+    ks = wave_sum_i(ks);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = vm;
+        red[1][w] = ks;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < 1024 / 64; ++k) {
+            a = fmax(a, red[0][k]);
+            b += red[1][k];
+        }
+        const double vmax = sqrt(a);
+        double dt = dt_max;
+        if (dx_max > 0.0 && vmax > 0.0 && dx_max / vmax < dt_max) dt = dx_max / vmax;
+        if (!first) {
+            sc.scal[1] += sc.scal[0];
+            sc.scal[6] = sc.scal[0];
+        }
+        sc.scal[0] = dt;
+        sc.scal[2] = vmax;
+        sc.scal[3] = 0.5 * mass * b / ACC_UNIT;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// copies out of the store, in atom-id order
+
+__global__ void k_gather_state(State S, Scratch sc, Geom g, double *__restrict__ x, double *__restrict__ v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites; s += stride) {
+        const int32_t id = S.atom[s];
+        if (id == VACANT_ID) continue;
+        if (x) {
+            const int p = s >= g.ncell ? 1 : 0;
+            const int64_t c = s - p * g.ncell;
+            double sp[3];
+            site_pos((int)(c % g.nx), (int)((c / g.nx) % g.ny), (int)(c / ((int64_t)g.nx * g.ny)), p, g.a, sp);
+            x[3 * (int64_t)id] = wrap_coord(sp[0] + S.ux[s], g.L[0]);
+            x[3 * (int64_t)id + 1] = wrap_coord(sp[1] + S.uy[s], g.L[1]);
+            x[3 * (int64_t)id + 2] = wrap_coord(sp[2] + S.uz[s], g.L[2]);
+        }
+        if (v) {
+            v[3 * (int64_t)id] = S.vx[s];
+            v[3 * (int64_t)id + 1] = S.vy[s];
+            v[3 * (int64_t)id + 2] = S.vz[s];
+        }
+    }
+    const int n = sc.cnt->n_run;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const int64_t id = S.r_id[r];
+        if (x) {
+            x[3 * id] = S.r_x[r];
+            x[3 * id + 1] = S.r_y[r];
+            x[3 * id + 2] = S.r_z[r];
+        }
+        if (v) {
+            v[3 * id] = S.r_vx[r];
+            v[3 * id + 1] = S.r_vy[r];
+            v[3 * id + 2] = S.r_vz[r];
+        }
+    }
+}
+
+template <typename Real>
+__global__ void k_gather_field(State S, Scratch sc, Geom g, int field, double *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const Real *rho = (const Real *)S.rho;
+    const Real *fp = (const Real *)S.fp;
+    const Real *fx = (const Real *)S.fx;
+    const Real *fy = (const Real *)S.fy;
+    const Real *fz = (const Real *)S.fz;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites; s += stride) {
+        const int32_t id = S.atom[s];
+        if (id == VACANT_ID) continue;
+        if (field == MISA_FIELD_RHO) out[id] = (double)rho[s];
+        else if (field == MISA_FIELD_FPRIME) out[id] = (double)fp[s];
+        else {
+            out[3 * (int64_t)id] = (double)fx[s];
+            out[3 * (int64_t)id + 1] = (double)fy[s];
+            out[3 * (int64_t)id + 2] = (double)fz[s];
+        }
+    }
+    const int n = sc.cnt->n_run;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const int64_t id = S.r_id[r];
+        if (field == MISA_FIELD_RHO) out[id] = S.r_rho[r];
+        else if (field == MISA_FIELD_FPRIME) out[id] = S.r_fp[r];
+        else {
+            out[3 * id] = S.r_fx[r];
+            out[3 * id + 1] = S.r_fy[r];
+            out[3 * id + 2] = S.r_fz[r];
+        }
+    }
+}
+
+__global__ void k_gather_slots(State S, Scratch sc, Geom g, int64_t *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites; s += stride) {
+        const int32_t id = S.atom[s];
+        if (id != VACANT_ID) out[id] = lattice_id_of(s, g);
+    }
+    const int n = sc.cnt->n_run;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) out[S.r_id[r]] = -1;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static int site_blocks(const Geom &g) {
+    int64_t b = (g.nsites + KICK_THREADS - 1) / KICK_THREADS;
+    return (int)(b < 65536 * 4 ? (b > 0 ? b : 1) : 65536 * 4);
+}
+
+hipError_t launch_kick_drift(misa_lattice *h) {
+    const double kf = ACC_UNIT / h->mass;
+    const int nb = site_blocks(h->g);
+    if (h->precision == MISA_FP32)
+        hipLaunchKernelGGL(k_kick_drift<float>, dim3(nb), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc, h->g, kf,
+                           h->rcap);
+    else
+        hipLaunchKernelGGL(k_kick_drift<double>, dim3(nb), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc, h->g, kf,
+                           h->rcap);
+    hipLaunchKernelGGL(k_kick_drift_runaway, dim3(SMALL_GRID), dim3(256), 0, h->stream, h->S, h->sc, h->g, kf);
+    return hipGetLastError();
+}
+
+static hipError_t kick_impl(misa_lattice *h, int kick) {
+    const double kf = ACC_UNIT / h->mass;
+    double *part = h->sc.part + 2 * (int64_t)h->g.ntiles_pad;  // after the per-tile energy partials
+    if (h->precision == MISA_FP32)
+        hipLaunchKernelGGL(k_final_kick<float>, dim3(KICK_BLOCKS), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc,
+                           h->g, kf, kick, part);
+    else
+        hipLaunchKernelGGL(k_final_kick<double>, dim3(KICK_BLOCKS), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc,
+                           h->g, kf, kick, part);
+    if (kick)
+        hipLaunchKernelGGL(k_final_kick_runaway, dim3(SMALL_GRID), dim3(256), 0, h->stream, h->S, h->sc, kf);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_kick(misa_lattice *h) { return kick_impl(h, 1); }
+
+hipError_t launch_dt_update(misa_lattice *h, double dt_max, double dx_max, bool first) {
+    if (first) {
+        hipError_t e = kick_impl(h, 0);
+        if (e != hipSuccess) return e;
+    }
+    double *part = h->sc.part + 2 * (int64_t)h->g.ntiles_pad;
+    hipLaunchKernelGGL(k_dt_update, dim3(1), dim3(1024), 0, h->stream, h->S, h->sc, part, KICK_BLOCKS, h->mass,
+                       dt_max, dx_max, first ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_state(misa_lattice *h, double *x, double *v) {
+    hipLaunchKernelGGL(k_gather_state, dim3(site_blocks(h->g)), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc, h->g,
+                       x, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_field(misa_lattice *h, int field, double *out) {
+    if (h->precision == MISA_FP32)
+        hipLaunchKernelGGL(k_gather_field<float>, dim3(site_blocks(h->g)), dim3(KICK_THREADS), 0, h->stream, h->S,
+                           h->sc, h->g, field, out);
+    else
+        hipLaunchKernelGGL(k_gather_field<double>, dim3(site_blocks(h->g)), dim3(KICK_THREADS), 0, h->stream, h->S,
+                           h->sc, h->g, field, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_slots(misa_lattice *h, int64_t *out) {
+    hipLaunchKernelGGL(k_gather_slots, dim3(site_blocks(h->g)), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc, h->g,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace misa

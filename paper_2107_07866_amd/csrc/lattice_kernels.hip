@@ -1,0 +1,335 @@
+// Lattice-array kernels: the array-array part of the EAM evaluation
+// (Algorithm 1, first loop; Sec. 2.2 steps 1-5) as a full-neighbour gather.
+//
+// Every work-group stages a TX x TY x TZ brick of cells of both sublattices,
+// plus a periodic halo of HALO cells, in LDS (the paper's ghost region, D6,
+// realised as a wrap at tile load).  One lane owns one site; the loop over the
+// Neighbor Offset Index is wave-uniform, so the table look-ups of a wave fall in
+// one narrow band of r (the same locality the paper gains by moving the offset
+// loop outermost, Sec. 4.1).  Each pair is evaluated from both ends, so no
+// write conflicts arise and no colouring or atomics are needed.
+#include "misa_internal.h"
+
+namespace misa {
+
+template <typename Real>
+__device__ __forceinline__ void seg_index(Real x, const TabMeta<Real> &m, int &k, Real &t) {
+    const Real p = (x - m.x0) * m.inv_h;
+    int kk = (int)p;
+    kk = kk < m.nseg - 1 ? kk : m.nseg - 1;
+    kk = kk > 0 ? kk : 0;  // below the first node: cubic continuation of segment 0
+    k = kk;
+    t = p - (Real)kk;
+}
+
+// F(rho) and F'(rho); linear continuation beyond the last node (flagged).
+template <typename Real>
+__device__ __forceinline__ Real emb_eval(Real rho, const Q4<Real> *__restrict__ emb, const TabMeta<Real> &m,
+                                         Real &Fval, bool &beyond) {
+    if (rho > m.x_last) {
+        beyond = true;
+        Fval = m.y_last + m.d_last * (rho - m.x_last);
+        return m.d_last;
+    }
+    int k;
+    Real t;
+    seg_index(rho, m, k, t);
+    const Q4<Real> c = emb[2 * k];
+    const Q4<Real> d = emb[2 * k + 1];
+    Fval = ((c.w * t + c.z) * t + c.y) * t + c.x;
+    return (d.z * t + d.y) * t + d.x;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real pair_r(Real r2);
+template <>
+__device__ __forceinline__ double pair_r<double>(double r2) { return sqrt(r2); }
+template <>
+__device__ __forceinline__ float pair_r<float>(float r2) { return __builtin_amdgcn_sqrtf(r2); }
+
+template <typename Real>
+__device__ __forceinline__ void pair_r_rinv(Real r2, Real &r, Real &rinv);
+template <>
+__device__ __forceinline__ void pair_r_rinv<double>(double r2, double &r, double &rinv) {
+    r = sqrt(r2);
+    rinv = 1.0 / r;
+}
+template <>
+__device__ __forceinline__ void pair_r_rinv<float>(float r2, float &r, float &rinv) {
+    rinv = __builtin_amdgcn_rsqf(r2);
+    r = r2 * rinv;
+}
+
+__device__ __forceinline__ int wrapg(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Load the tile (interior + halo) of both sublattices into LDS.  w_src (may
+// be null) supplies the fourth component (F' for the force pass).
+template <typename Real>
+__device__ __forceinline__ void load_tile(Q4<Real> *__restrict__ tile, const double *__restrict__ ux,
+                                          const double *__restrict__ uy, const double *__restrict__ uz,
+                                          const Real *__restrict__ w_src, const Geom &g, int bx, int by,
+                                          int bz) {
+    for (int e = threadIdx.x; e < TILE_SITES; e += TILE_THREADS) {
+        int lx = e % PX;
+        int r = e / PX;
+        int ly = r % PY;
+        r /= PY;
+        int lz = r % PZ;
+        int p = r / PZ;
+        int gx = wrapg(bx + lx, g.nx), gy = wrapg(by + ly, g.ny), gz = wrapg(bz + lz, g.nz);
+        int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+        Q4<Real> q;
+        q.x = (Real)ux[idx];
+        q.y = (Real)uy[idx];
+        q.z = (Real)uz[idx];
+        q.w = w_src ? w_src[idx] : (Real)0;
+        tile[e] = q;
+    }
+}
+
+// rho_i = sum_j f(r_ij) over the stencil, then F'(rho_i) (Sec. 2.2 steps 1-2).
+template <typename Real>
+__global__ __launch_bounds__(TILE_THREADS) void k_rho_tile(
+    const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
+    Real *__restrict__ rho, Real *__restrict__ fp, const StencilEntry<Real> *__restrict__ st, int K,
+    const Q4<Real> *__restrict__ ftab, TabMeta<Real> fm, const Q4<Real> *__restrict__ etab,
+    TabMeta<Real> em, Geom g, uint32_t *__restrict__ range_viol) {
+    __shared__ Q4<Real> tile[TILE_SITES];
+    const int tid = tile_of_block(blockIdx.x, g);
+    if (tid >= g.ntiles) return;  // whole work-group leaves together
+    const int tx = tid % g.ntx;
+    const int tyz = tid / g.ntx;
+    const int ty = tyz % g.nty;
+    const int tz = tyz / g.nty;
+    load_tile<Real>(tile, ux, uy, uz, nullptr, g, tx * TX - HALO, ty * TY - HALO, tz * TZ - HALO);
+    __syncthreads();
+
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = w / TZ, lz = w % TZ, lx = lane % TX, ly = lane / TX;
+    const int gx = tx * TX + lx, gy = ty * TY + ly, gz = tz * TZ + lz;
+    if (gx >= g.nx || gy >= g.ny || gz >= g.nz) return;
+    const int me = ((p * PZ + lz + HALO) * PY + ly + HALO) * PX + lx + HALO;
+    const Q4<Real> ui = tile[me];
+    const Real rc2 = (Real)g.rc2;
+    const StencilEntry<Real> *sp = st + p * KMAX;
+    Real acc = 0;
+    for (int k = 0; k < K; ++k) {
+        const StencilEntry<Real> e = sp[k];
+        const Q4<Real> uj = tile[me + e.lds];
+        const Real dx = (uj.x - ui.x) + e.ox;
+        const Real dy = (uj.y - ui.y) + e.oy;
+        const Real dz = (uj.z - ui.z) + e.oz;
+        const Real r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < rc2) {
+            int s;
+            Real t;
+            seg_index(pair_r<Real>(r2), fm, s, t);
+            const Q4<Real> c = ftab[s];
+            acc += ((c.w * t + c.z) * t + c.y) * t + c.x;
+        }
+    }
+    const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+    Real fpv = 0;
+    bool beyond = false;
+    if (ui.x > (Real)VACANT_TEST) {
+        acc = 0;
+    } else {
+        Real Fv;
+        fpv = emb_eval<Real>(acc, etab, em, Fv, beyond);
+    }
+    rho[idx] = acc;
+    fp[idx] = fpv;
+    if (beyond) atomicAdd(range_viol, 1u);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// F_i = sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (x_j - x_i) / r   (Eq. eam_force_ij)
+// With kEnergy: per-tile partial sums of F(rho_i) and 1/2 sum_j phi(r_ij).
+template <typename Real, bool kEnergy>
+__global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
+    const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
+    const Real *__restrict__ fp, const Real *__restrict__ rho, Real *__restrict__ fx, Real *__restrict__ fy,
+    Real *__restrict__ fz, const StencilEntry<Real> *__restrict__ st, int K, Tables<Real> T, Geom g,
+    double *__restrict__ part) {
+    __shared__ Q4<Real> tile[TILE_SITES];
+    __shared__ double red[2][TILE_THREADS / 64];
+    const int tid = tile_of_block(blockIdx.x, g);
+    if (tid >= g.ntiles) return;
+    const int tx = tid % g.ntx;
+    const int tyz = tid / g.ntx;
+    const int ty = tyz % g.nty;
+    const int tz = tyz / g.nty;
+    load_tile<Real>(tile, ux, uy, uz, fp, g, tx * TX - HALO, ty * TY - HALO, tz * TZ - HALO);
+    __syncthreads();
+
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = w / TZ, lz = w % TZ, lx = lane % TX, ly = lane / TX;
+    const int gx = tx * TX + lx, gy = ty * TY + ly, gz = tz * TZ + lz;
+    const bool active = gx < g.nx && gy < g.ny && gz < g.nz;
+    double e_emb = 0.0, e_pair = 0.0;
+    if (active) {
+        const int me = ((p * PZ + lz + HALO) * PY + ly + HALO) * PX + lx + HALO;
+        const Q4<Real> ui = tile[me];
+        const Real rc2 = (Real)g.rc2;
+        const StencilEntry<Real> *sp = st + p * KMAX;
+        Real ax = 0, ay = 0, az = 0, ep = 0;
+        for (int k = 0; k < K; ++k) {
+            const StencilEntry<Real> e = sp[k];
+            const Q4<Real> uj = tile[me + e.lds];
+            const Real dx = (uj.x - ui.x) + e.ox;
+            const Real dy = (uj.y - ui.y) + e.oy;
+            const Real dz = (uj.z - ui.z) + e.oz;
+            const Real r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rc2) {
+                Real r, rinv;
+                pair_r_rinv<Real>(r2, r, rinv);
+                int s;
+                Real t;
+                seg_index(r, T.fm, s, t);
+                const Q4<Real> a = T.force[2 * s];
+                const Q4<Real> b = T.force[2 * s + 1];
+                const Real dfr = (a.z * t + a.y) * t + a.x;   // f'(r)
+                const Real dph = (b.y * t + b.x) * t + a.w;   // phi'(r)
+                const Real sc = ((ui.w + uj.w) * dfr + dph) * rinv;
+                ax += sc * dx;
+                ay += sc * dy;
+                az += sc * dz;
+                if (kEnergy) {
+                    const Q4<Real> c = T.phi[s];
+                    ep += ((c.w * t + c.z) * t + c.y) * t + c.x;
+                }
+            }
+        }
+        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+        const bool vac = ui.x > (Real)VACANT_TEST;
+        if (vac) ax = ay = az = 0;
+        fx[idx] = ax;
+        fy[idx] = ay;
+        fz[idx] = az;
+        if (kEnergy && !vac) {
+            Real Fv;
+            bool beyond = false;
+            emb_eval<Real>(rho[idx], T.emb, T.em, Fv, beyond);
+            e_emb = (double)Fv;
+            e_pair = 0.5 * (double)ep;
+        }
+    }
+    if (kEnergy) {
+        e_emb = wave_sum(e_emb);
+        e_pair = wave_sum(e_pair);
+        if (lane == 0) {
+            red[0][w] = e_emb;
+            red[1][w] = e_pair;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int q = 0; q < TILE_THREADS / 64; ++q) {
+                s0 += red[0][q];
+                s1 += red[1][q];
+            }
+            part[2 * tid] = s0;
+            part[2 * tid + 1] = s1;
+        }
+    }
+}
+
+template <typename Real>
+static Tables<Real> tables_of(const DevTables<Real> &t) {
+    Tables<Real> T;
+    T.f = t.f;
+    T.force = t.force;
+    T.phi = t.phi;
+    T.emb = t.emb;
+    T.fm = t.fm;
+    T.em = t.em;
+    return T;
+}
+
+template <typename Real>
+static hipError_t rho_impl(misa_lattice *h, const StencilEntry<Real> *st, const DevTables<Real> &t) {
+    const Geom &g = h->g;
+    hipLaunchKernelGGL(k_rho_tile<Real>, dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux, h->S.uy,
+                       h->S.uz, (Real *)h->S.rho, (Real *)h->S.fp, st, h->K, t.f, t.fm, t.emb, t.em, g,
+                       &h->sc.cnt->range_viol);
+    return hipGetLastError();
+}
+
+hipError_t launch_rho(misa_lattice *h) {
+    if (h->precision == MISA_FP32) return rho_impl<float>(h, h->st32, h->t32);
+    return rho_impl<double>(h, h->st64, h->t64);
+}
+
+template <typename Real>
+static hipError_t force_impl(misa_lattice *h, bool energy, const StencilEntry<Real> *st, const DevTables<Real> &t) {
+    const Geom &g = h->g;
+    Tables<Real> T = tables_of(t);
+    if (energy)
+        hipLaunchKernelGGL((k_force_tile<Real, true>), dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux,
+                           h->S.uy, h->S.uz, (const Real *)h->S.fp, (const Real *)h->S.rho, (Real *)h->S.fx,
+                           (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, T, g, h->sc.part);
+    else
+        hipLaunchKernelGGL((k_force_tile<Real, false>), dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream,
+                           h->S.ux, h->S.uy, h->S.uz, (const Real *)h->S.fp, (const Real *)h->S.rho,
+                           (Real *)h->S.fx, (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, T, g, h->sc.part);
+    return hipGetLastError();
+}
+
+hipError_t launch_force(misa_lattice *h, bool energy) {
+    if (h->precision == MISA_FP32) return force_impl<float>(h, energy, h->st32, h->t32);
+    return force_impl<double>(h, energy, h->st64, h->t64);
+}
+
+// Final energy sums: per-tile partials and per-run-away terms, fixed order.
+__global__ __launch_bounds__(1024) void k_energy_reduce(const double *__restrict__ part, int ntiles,
+                                                        const double *__restrict__ r_e,
+                                                        const Counters *__restrict__ cnt,
+                                                        double *__restrict__ scal, double *__restrict__ out) {
+    __shared__ double red[2][1024 / 64];
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += 1024) {
+        s0 += part[2 * i];
+        s1 += part[2 * i + 1];
+    }
+    const int nr = cnt->n_run;
+    for (int i = threadIdx.x; i < nr; i += 1024) {
+        s0 += r_e[2 * i];
+        s1 += r_e[2 * i + 1];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = s0;
+        red[1][w] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < 1024 / 64; ++q) {
+            a += red[0][q];
+            b += red[1][q];
+        }
+        scal[4] = a;
+        scal[5] = b;
+        if (out) {
+            out[0] = a;
+            out[1] = b;
+        }
+    }
+}
+
+hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev) {
+    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, h->stream, h->sc.part, h->g.ntiles, h->S.r_e,
+                       h->sc.cnt, h->sc.scal, energies_dev);
+    return hipGetLastError();
+}
+
+}  // namespace misa

@@ -1,0 +1,283 @@
+// Internal declarations of the MI355X EAM lattice MD library (not installed).
+//
+// Data layout in device memory (one structure-of-arrays slot per BCC site):
+//   sites are split into two simple-cubic sublattices p = 0 (cube corners) and
+//   p = 1 (body centres); storage index  s = p * ncell + (z * ny + y) * nx + x
+//   for cell (x, y, z).  The paper's lattice id (Sec. 3) of the same site is
+//   2 nx ny z + 2 nx y + 2 x + p; the library converts at its boundary.
+//   Per site: displacement u = atom position - site position (float64 x3;
+//   an empty slot stores VACANT_U), velocity (float64 x3), force (x3, float64
+//   or float32 by pair precision), rho and F'(rho) (pair precision), atom id
+//   (int32; VACANT_ID for an empty slot).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "misa.h"
+
+namespace misa {
+
+// ---------------------------------------------------------------------------
+// Compile-time tiling of the lattice kernels.
+// A work-group owns a TX x TY x TZ brick of cells (both sublattices) and stages
+// it in LDS with a HALO-cell periodic halo; one lane per site; the stencil loop
+// runs over a wave-uniform offset, so every wave serves one parity and one z plane.
+constexpr int TX = 8, TY = 8, TZ = 4, HALO = 2;
+constexpr int PX = TX + 2 * HALO, PY = TY + 2 * HALO, PZ = TZ + 2 * HALO;
+constexpr int TILE_SITES = 2 * PX * PY * PZ;   // LDS entries per work-group (with halo)
+constexpr int TILE_THREADS = 2 * TX * TY * TZ; // 512: one lane per interior site
+static_assert(TX * TY == 64, "one wave covers one TX x TY plane of one parity");
+constexpr int KMAX = 96;                       // max stencil entries per parity
+
+constexpr double VACANT_U = 1.0e6;             // displacement stored in an empty slot
+constexpr double VACANT_TEST = 0.5e6;          // ux above this means the slot is empty
+constexpr int32_t VACANT_ID = 0x7fffffff;      // atom id stored in an empty slot
+
+// run-away / hash scratch
+constexpr int SORT_THREADS = 1024;
+constexpr int SORT_LDS_MAX = 4096;             // single-block LDS bitonic sort up to this many keys
+constexpr int RUNAWAY_WAVES_PER_BLOCK = 4;     // one wave per run-away atom
+constexpr int SMALL_GRID = 1024;               // blocks of grid-stride kernels over run-away lists
+
+// 1 eV/(Angstrom amu) in Angstrom/fs^2 (exact SI e, CODATA-2018 amu)
+constexpr double ACC_UNIT = (1.602176634e-19 / 1.66053906660e-27) * 1e-10;
+
+template <typename Real>
+struct alignas(4 * sizeof(Real)) Q4 {
+    Real x, y, z, w;
+};
+
+// One Neighbor Offset Index entry, prepared for the LDS tile of a given parity:
+// lds = offset of the neighbour's LDS entry from the centre's, o = site offset vector.
+template <typename Real>
+struct StencilEntry;
+template <>
+struct alignas(32) StencilEntry<double> {
+    int32_t lds, pad;
+    double ox, oy, oz;
+};
+template <>
+struct alignas(16) StencilEntry<float> {
+    int32_t lds;
+    float ox, oy, oz;
+};
+
+// Interpolation table metadata (records live in device memory).
+template <typename Real>
+struct TabMeta {
+    Real x0, inv_h;
+    int32_t nseg;          // number of segments = samples - 1
+    int32_t pad;
+    Real x_last;           // position of the last node
+    Real y_last, d_last;   // value and d/dx at the last node (linear continuation)
+};
+
+// Device pointers to the coefficient records of one precision.
+//  f:     Q4 per segment  {c0, c1, c2, c3}      value of f  = ((c3 t + c2) t + c1) t + c0
+//  force: 2 x Q4 per seg. {f'0, f'1, f'2, p'0}, {p'1, p'2, 0, 0}:  f' = (f'2 t + f'1) t + f'0 (per Angstrom)
+//  phi:   Q4 per segment  {c0, c1, c2, c3}      value of phi
+//  emb:   2 x Q4 per seg. {c0, c1, c2, c3}, {d0, d1, d2, 0}: F and F' (per unit rho)
+template <typename Real>
+struct Tables {
+    const Q4<Real> *f, *force, *phi, *emb;
+    TabMeta<Real> fm, em;  // f / phi share one grid; emb has its own
+};
+
+struct Geom {
+    int32_t nx, ny, nz;
+    int32_t ntx, nty, ntz;  // tiles per axis
+    int32_t ntiles, ntiles_pad;
+    int64_t ncell;          // cells per sublattice
+    int64_t nsites;
+    double a, inv_a;
+    double L[3];
+    double rc, rc2, delta2;
+    double pre2;            // slightly generous rc^2 for candidate searches followed by an exact test
+    // coarse cells (edge >= rc) that bucket run-away atoms in the device hash
+    int32_t nc[3];
+    int32_t pad;
+    double inv_cs[3];
+    // lattice search window around a run-away atom: cells [lo, lo + win) per axis
+    int32_t win;
+    int32_t pad2;
+    double reach;           // (rc + delta) / a
+};
+
+// Caller-owned state, carved from the bound buffer.
+struct State {
+    double *ux, *uy, *uz;
+    double *vx, *vy, *vz;
+    void *fx, *fy, *fz;     // Real
+    void *rho, *fp;         // Real
+    int32_t *atom;
+    // run-away atoms (capacity rcap), list order is deterministic
+    int32_t *r_id;
+    double *r_x, *r_y, *r_z, *r_vx, *r_vy, *r_vz, *r_fx, *r_fy, *r_fz, *r_rho, *r_fp, *r_e;
+};
+
+// Device counters (library scratch).
+struct Counters {
+    int32_t n_run;        // run-away atoms in the list
+    int32_t n_leave;      // atoms that left their slot this step
+    int32_t n_affected;   // lattice atoms within rc of a run-away atom
+    int32_t overflow;     // run-away capacity exceeded
+    uint32_t range_viol;  // densities beyond the embedding table
+    int32_t pad[3];
+};
+
+// Library scratch (hipMalloc'd by the handle).
+struct Scratch {
+    Counters *cnt;
+    double *scal;         // [0] dt of the next step, [1] time, [2] vmax, [3] e_kin, [4] e_emb, [5] e_pair, [6] dt of the last step
+    double *part;         // per-tile partial sums (2 per tile) and per-block partials
+    double *part_run;     // per-run-away partials
+    // leavers of one step
+    int32_t *l_site, *l_id;
+    double *l_x, *l_y, *l_z, *l_vx, *l_vy, *l_vz;
+    // claims / settling
+    int32_t *cand;        // candidate site per (run-away or leaver) entry, -1 if none
+    uint8_t *settled;
+    // sort buffers
+    uint64_t *sortbuf;
+    // device hash of run-away atoms: sorted (coarse key, index), key -> first position
+    int32_t *skey, *sidx;
+    int32_t *hkey, *hval, *hslot;
+    int32_t hmask;
+    // lattice atoms near run-away atoms
+    uint32_t *mark;       // 1 bit per site
+    int32_t *affected;
+    int64_t affected_cap;
+};
+
+template <typename Real>
+struct DevTables {
+    Q4<Real> *f = nullptr, *force = nullptr, *phi = nullptr, *emb = nullptr;
+    TabMeta<Real> fm{}, em{};
+};
+
+}  // namespace misa
+
+struct misa_lattice {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    misa::Geom g{};
+    int precision = MISA_FP64;
+    double mass = 0.0;
+    int64_t rcap = 0;
+    int K = 0;                                    // stencil entries per parity
+    std::vector<int64_t> stencil_canon;           // [2][K][3] (dX, dY, dZ)
+    misa::StencilEntry<double> *st64 = nullptr;   // device [2][KMAX]
+    misa::StencilEntry<float> *st32 = nullptr;
+    misa::DevTables<double> t64;
+    misa::DevTables<float> t32;
+    bool tables_set = false;
+    misa::Scratch sc{};
+    void *state_ptr = nullptr;
+    int64_t state_bytes = 0;
+    misa::State S{};
+    bool state_bound = false, state_set = false, rho_valid = false, force_valid = false;
+    bool pending_clear = false;                   // hash and marks of a rho pass await the force pass
+    int64_t n_atoms = 0;
+    int64_t steps_done = 0;
+    double *staging = nullptr;                    // device staging for host copies
+    int64_t staging_bytes = 0;
+    std::string err;
+};
+
+namespace misa {
+
+// ----------------------------------------------------------------------------
+// Launchers (defined in the kernel translation units).  All enqueue on h->stream.
+hipError_t launch_rho(misa_lattice *h);
+hipError_t launch_force(misa_lattice *h, bool energy);
+hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev);
+hipError_t launch_runaway_build(misa_lattice *h);      // keys, sort, hash insert
+hipError_t launch_runaway_rho(misa_lattice *h);        // run-away rho + affected-site fixup
+hipError_t launch_runaway_force(misa_lattice *h, bool energy);
+hipError_t launch_runaway_clear(misa_lattice *h);      // hash and marks back to empty
+hipError_t launch_kick_drift(misa_lattice *h);         // lattice + run-aways, leavers appended
+hipError_t launch_rehash(misa_lattice *h);             // sort leavers, claims, settle, compact
+hipError_t launch_final_kick(misa_lattice *h);         // + vmax / KE partials
+hipError_t launch_dt_update(misa_lattice *h, double dt_max, double dx_max, bool first);
+hipError_t launch_gather_state(misa_lattice *h, double *x, double *v);
+hipError_t launch_gather_field(misa_lattice *h, int field, double *out);
+hipError_t launch_gather_slots(misa_lattice *h, int64_t *out);
+
+// ----------------------------------------------------------------------------
+// Small device helpers shared by the kernel translation units.
+
+__host__ __device__ inline int wrap_index(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+__device__ inline int tile_of_block(int b, const Geom &g) {
+    // Work-groups are dispatched round-robin over the 8 XCDs; give every XCD a
+    // contiguous run of tiles so halo re-reads of neighbouring tiles hit its own L2.
+    int per = g.ntiles_pad >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// Wrap a coordinate into [0, L).
+__host__ __device__ inline double wrap_coord(double x, double L) {
+#pragma clang fp contract(off)
+    return x - L * floor(x / L);
+}
+
+// Site position of storage cell (cx, cy, cz) (unwrapped integers) of sublattice p.
+__host__ __device__ inline void site_pos(int cx, int cy, int cz, int p, double a, double out[3]) {
+#pragma clang fp contract(off)
+    double h = p ? 0.5 : 0.0;
+    out[0] = ((double)cx + h) * a;
+    out[1] = ((double)cy + h) * a;
+    out[2] = ((double)cz + h) * a;
+}
+
+// The hash (nearest lattice site), float64 without contraction so host and
+// device take identical decisions: position wrapped into the box; nearest
+// corner rounds each coordinate / a to the nearest integer (ties to even),
+// nearest body centre takes floor + 1/2; the closer wins, the corner on a tie.
+// Returns the storage index; u = x - site; *u2 = |u|^2.
+__host__ __device__ inline int64_t hash_site(const double x[3], const Geom &g, double u[3], double *u2) {
+#pragma clang fp contract(off)
+    const int32_t n[3] = {g.nx, g.ny, g.nz};
+    double uc[3], ub[3];
+    int ic[3], ib[3];
+    for (int k = 0; k < 3; ++k) {
+        double xw = x[k] - g.L[k] * floor(x[k] / g.L[k]);
+        double q = xw * g.inv_a;
+        double c = rint(q);
+        double fl = floor(q);
+        double b = fl + 0.5;
+        uc[k] = xw - c * g.a;
+        ub[k] = xw - b * g.a;
+        ic[k] = (int)c;
+        ib[k] = (int)fl;
+    }
+    double dc = uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2];
+    double db = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+    int centre = db < dc ? 1 : 0;
+    int c3[3];
+    for (int k = 0; k < 3; ++k) {
+        int c = (centre ? ib[k] : ic[k]) % n[k];  // full modulo: in range even for non-finite input
+        if (c < 0) c += n[k];
+        c3[k] = c;
+        u[k] = centre ? ub[k] : uc[k];
+    }
+    *u2 = centre ? db : dc;
+    return (int64_t)centre * g.ncell + ((int64_t)c3[2] * g.ny + c3[1]) * g.nx + c3[0];
+}
+
+// Storage index <-> lattice id of Sec. 3.
+__host__ __device__ inline int64_t lattice_id_of(int64_t s, const Geom &g) {
+    int64_t p = s >= g.ncell ? 1 : 0;
+    int64_t c = s - p * g.ncell;
+    int64_t cx = c % g.nx, cy = (c / g.nx) % g.ny, cz = c / ((int64_t)g.nx * g.ny);
+    return 2 * (int64_t)g.nx * g.ny * cz + 2 * (int64_t)g.nx * cy + 2 * cx + p;
+}
+
+}  // namespace misa

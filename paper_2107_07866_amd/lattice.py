@@ -1,0 +1,84 @@
+"""Convenience owner of one lattice handle and its torch-allocated state buffer."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import misa as M
+
+
+class Lattice:
+    """One periodic BCC box driven by libmisa on the current CUDA (HIP) device.
+
+    The state buffer is a torch uint8 tensor owned by this object; the HIP
+    stream is torch's current stream at construction.
+    """
+
+    def __init__(self, n_cells, a, rc, delta, mass, precision="fp64", runaway_capacity=0, device="cuda"):
+        if isinstance(n_cells, int):
+            n_cells = (n_cells,) * 3
+        self.n_cells = tuple(int(k) for k in n_cells)
+        self.a, self.rc, self.delta, self.mass = float(a), float(rc), float(delta), float(mass)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        prec = M.MISA_FP32 if precision == "fp32" else M.MISA_FP64
+        self.h = M.misa_create_lattice(self.n_cells, a, rc, delta, mass, prec, runaway_capacity,
+                                       self.stream.cuda_stream)
+        nbytes = M.misa_state_bytes(self.h)
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._buf.data_ptr()
+        self._ptr = (base + 255) // 256 * 256
+        M.misa_bind_state(self.h, self._ptr, nbytes)
+        self.state_bytes = nbytes
+
+    @property
+    def box(self):
+        return tuple(k * self.a for k in self.n_cells)
+
+    def set_tables(self, tables):
+        M.misa_set_potential_tables(self.h, tables["f"], tables["phi"], tables["F"])
+
+    def set_state(self, x, v):
+        M.misa_set_state(self.h, x, v)
+
+    def get_state(self):
+        return M.misa_get_state(self.h)
+
+    def compute(self, energies=True):
+        M.misa_compute_rho(self.h)
+        e = torch.zeros(2, dtype=torch.float64, device=self.device) if energies else None
+        M.misa_compute_force(self.h, e)
+        return e
+
+    def field(self, which):
+        return M.misa_get_atom_field(self.h, which)
+
+    def rho(self):
+        return self.field(M.MISA_FIELD_RHO)
+
+    def fprime(self):
+        return self.field(M.MISA_FIELD_FPRIME)
+
+    def forces(self):
+        return self.field(M.MISA_FIELD_FORCE)
+
+    def slots(self):
+        return M.misa_debug_export(self.h, M.MISA_EXPORT_SLOTS)
+
+    def stencil(self):
+        return M.misa_debug_export(self.h, M.MISA_EXPORT_STENCIL)
+
+    def step(self, nsteps, dt_max, dx_max=0.0):
+        return M.misa_step(self.h, nsteps, dt_max, dx_max)
+
+    def close(self):
+        if self.h is not None:
+            M.misa_destroy_lattice(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,225 @@
+"""ctypes binding of libmisa.so: argument marshalling only, same names as misa.h.
+
+PyTorch supplies device memory (the caller-owned state buffer, device-side
+outputs) and the HIP stream; every step of the computation runs in the
+library's HIP kernels.  Importing this module fails loudly when libmisa.so
+is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmisa.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "misa.h")
+
+MISA_OK, MISA_EINVAL, MISA_ENOMEM, MISA_EHIP, MISA_ESTATE, MISA_EOVERFLOW = 0, -1, -2, -3, -4, -5
+MISA_FP64, MISA_FP32 = 0, 1
+MISA_HOST, MISA_DEVICE = 0, 1
+MISA_FIELD_RHO, MISA_FIELD_FPRIME, MISA_FIELD_FORCE = 0, 1, 2
+MISA_EXPORT_STENCIL, MISA_EXPORT_SLOTS = 0, 1
+
+_ERRNAMES = {MISA_EINVAL: "MISA_EINVAL", MISA_ENOMEM: "MISA_ENOMEM", MISA_EHIP: "MISA_EHIP",
+             MISA_ESTATE: "MISA_ESTATE", MISA_EOVERFLOW: "MISA_EOVERFLOW"}
+
+
+class MisaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class misa_lattice_desc(C.Structure):
+    _fields_ = [("n_cells", C.c_int32 * 3), ("pair_precision", C.c_int32), ("a", C.c_double),
+                ("rc", C.c_double), ("delta", C.c_double), ("mass", C.c_double),
+                ("runaway_capacity", C.c_int64)]
+
+
+class misa_table(C.Structure):
+    _fields_ = [("x0", C.c_double), ("dx", C.c_double), ("n", C.c_int32), ("reserved", C.c_int32),
+                ("y", C.POINTER(C.c_double))]
+
+
+class misa_step_stats(C.Structure):
+    _fields_ = [("dt", C.c_double), ("dt_next", C.c_double), ("vmax", C.c_double), ("e_kin", C.c_double),
+                ("e_emb", C.c_double), ("e_pair", C.c_double), ("time", C.c_double), ("steps", C.c_int64),
+                ("n_runaway", C.c_int64), ("range_violations", C.c_int64), ("overflow", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950). There is no CPU fallback.")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, dp = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
+    sig = {
+        "misa_create_lattice": ([C.POINTER(misa_lattice_desc), vp, C.POINTER(vp)], C.c_int),
+        "misa_destroy_lattice": ([vp], C.c_int),
+        "misa_last_error": ([vp], C.c_char_p),
+        "misa_state_bytes": ([vp, C.POINTER(i64)], C.c_int),
+        "misa_bind_state": ([vp, vp, i64], C.c_int),
+        "misa_set_potential_tables": ([vp, C.POINTER(misa_table), C.POINTER(misa_table), C.POINTER(misa_table)],
+                                      C.c_int),
+        "misa_set_state": ([vp, vp, vp, i64, C.c_int], C.c_int),
+        "misa_get_state": ([vp, vp, vp, C.c_int], C.c_int),
+        "misa_atom_count": ([vp, C.POINTER(i64)], C.c_int),
+        "misa_compute_rho": ([vp], C.c_int),
+        "misa_compute_force": ([vp, vp], C.c_int),
+        "misa_step": ([vp, i64, C.c_double, C.c_double, C.POINTER(misa_step_stats)], C.c_int),
+        "misa_get_atom_field": ([vp, C.c_int, vp, C.c_int], C.c_int),
+        "misa_debug_export": ([vp, C.c_int, C.POINTER(i64), i64], i64),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def declared_functions(header: str = HEADER):
+    """Names of the entry points misa.h declares."""
+    text = open(header).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char \*)\s*\*?\s*(misa_\w+)\s*\(", text, re.M)))
+
+
+def _check(code, h=None):
+    if code < 0:
+        msg = lib.misa_last_error(h)
+        raise MisaError(code, msg.decode() if msg else "")
+    return code
+
+
+def _ptr(a):
+    """Data pointer of a torch tensor or a numpy array, and its memory kind."""
+    if a is None:
+        return None, MISA_HOST
+    if hasattr(a, "data_ptr"):  # torch.Tensor
+        return C.c_void_p(a.data_ptr()), (MISA_DEVICE if a.is_cuda else MISA_HOST)
+    return C.c_void_p(a.ctypes.data), MISA_HOST
+
+
+# ---------------------------------------------------------------------------
+# entry points, same names as the C ABI
+
+def misa_create_lattice(n_cells, a, rc, delta, mass, pair_precision=MISA_FP64, runaway_capacity=0,
+                        hip_stream=None):
+    d = misa_lattice_desc()
+    d.n_cells[:] = [int(k) for k in n_cells]
+    d.pair_precision, d.a, d.rc, d.delta, d.mass = int(pair_precision), float(a), float(rc), float(delta), float(mass)
+    d.runaway_capacity = int(runaway_capacity)
+    h = C.c_void_p()
+    _check(lib.misa_create_lattice(C.byref(d), C.c_void_p(hip_stream or 0), C.byref(h)))
+    return h
+
+
+def misa_destroy_lattice(h):
+    return _check(lib.misa_destroy_lattice(h))
+
+
+def misa_last_error(h):
+    return lib.misa_last_error(h).decode()
+
+
+def misa_state_bytes(h):
+    b = C.c_int64()
+    _check(lib.misa_state_bytes(h, C.byref(b)), h)
+    return b.value
+
+
+def misa_bind_state(h, device_ptr, nbytes):
+    return _check(lib.misa_bind_state(h, C.c_void_p(device_ptr), int(nbytes)), h)
+
+
+def _table(x0, dx, y):
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    t = misa_table(float(x0), float(dx), len(y), 0, y.ctypes.data_as(C.POINTER(C.c_double)))
+    return t, y
+
+
+def misa_set_potential_tables(h, f, phi, emb):
+    """f, phi, emb: (x0, dx, y) sample tuples."""
+    tf, kf = _table(*f)
+    tp, kp = _table(*phi)
+    te, ke = _table(*emb)
+    return _check(lib.misa_set_potential_tables(h, C.byref(tf), C.byref(tp), C.byref(te)), h)
+
+
+def misa_set_state(h, x, v):
+    """x, v: (N, 3) float64 numpy arrays or CUDA tensors (same kind for both)."""
+    if not hasattr(x, "data_ptr"):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)
+    n = x.shape[0]
+    px, where = _ptr(x)
+    pv, where_v = _ptr(v)
+    if where != where_v:
+        raise ValueError("x and v must live in the same memory")
+    return _check(lib.misa_set_state(h, px, pv, n, where), h)
+
+
+def misa_atom_count(h):
+    n = C.c_int64()
+    _check(lib.misa_atom_count(h, C.byref(n)), h)
+    return n.value
+
+
+def misa_get_state(h, x=None, v=None):
+    """Fill x / v ((N, 3) float64 numpy arrays or CUDA tensors); allocates numpy arrays if both are None."""
+    if x is None and v is None:
+        n = misa_atom_count(h)
+        x, v = np.empty((n, 3)), np.empty((n, 3))
+    px, wx = _ptr(x)
+    pv, wv = _ptr(v)
+    where = wx if x is not None else wv
+    _check(lib.misa_get_state(h, px, pv, where), h)
+    return x, v
+
+
+def misa_compute_rho(h):
+    return _check(lib.misa_compute_rho(h), h)
+
+
+def misa_compute_force(h, energies_dev=None):
+    p, _ = _ptr(energies_dev)
+    return _check(lib.misa_compute_force(h, p), h)
+
+
+def misa_step(h, nsteps, dt_max, dx_max=0.0, want_stats=True):
+    st = misa_step_stats()
+    code = lib.misa_step(h, int(nsteps), float(dt_max), float(dx_max), C.byref(st) if want_stats else None)
+    if code == MISA_EOVERFLOW:
+        raise MisaError(code, misa_last_error(h))
+    _check(code, h)
+    return st.as_dict() if want_stats else None
+
+
+def misa_get_atom_field(h, field, out=None):
+    n = misa_atom_count(h) * (3 if field == MISA_FIELD_FORCE else 1)
+    if out is None:
+        out = np.empty(n)
+    p, where = _ptr(out)
+    _check(lib.misa_get_atom_field(h, int(field), p, where), h)
+    return out.reshape(-1, 3) if (field == MISA_FIELD_FORCE and not hasattr(out, "data_ptr")) else out
+
+
+def misa_debug_export(h, what):
+    if what == MISA_EXPORT_STENCIL:
+        k = _check(lib.misa_debug_export(h, what, None, 0), h)
+        out = np.empty(2 * k * 3, dtype=np.int64)
+        _check(lib.misa_debug_export(h, what, out.ctypes.data_as(C.POINTER(C.c_int64)), out.size), h)
+        return out.reshape(2, k, 3)
+    n = misa_atom_count(h)
+    out = np.empty(max(n, 1), dtype=np.int64)
+    _check(lib.misa_debug_export(h, what, out.ctypes.data_as(C.POINTER(C.c_int64)), out.size), h)
+    return out[:n]

@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on identical
+seeded inputs.  Bars: lattice indexing and classification bit-exact; FP64 forces
+within 1e-6 relative (max |dF| / rms |F|), densities within 1e-12 relative;
+the FP32 pair-arithmetic form is reported against the FP64 oracle with loose bounds.
+"""
+import numpy as np
+import pytest
+
+import misa_workloads as w
+
+pytestmark = pytest.mark.gpu
+
+A, RC, DELTA, M = w.A_FE, w.RC, w.DELTA, w.MASS_FE
+TABLES = w.potential_samples()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pot(orc):
+    return orc.Potential(orc.TABLE, tables=TABLES)
+
+
+def _lattice(n, precision="fp64", delta=DELTA, cap=0, tables=TABLES):
+    from paper_2107_07866_amd import Lattice
+    lat = Lattice(n, A, RC, delta, M, precision, runaway_capacity=cap)
+    lat.set_tables(tables)
+    return lat
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _ferr(F, ref):
+    scale = max(float(np.sqrt(np.mean(ref ** 2))), 1e-3)
+    return float(np.max(np.abs(F - ref))) / scale if len(ref) else 0.0
+
+
+def _compare_state(orc, pot, lat, x, box, ftol=1e-6, rtol=1e-12, etol=1e-12):
+    import torch
+    e = lat.compute(energies=True)
+    torch.cuda.synchronize()
+    ref = orc.eam(pot, x, box)
+    F, rho, fp = lat.forces(), lat.rho(), lat.fprime()
+    e = e.cpu().numpy()
+    out = dict(ferr=_ferr(F, ref["F"]))
+    nz = np.abs(ref["rho"]) > 0
+    out["rerr"] = float(np.max(np.abs(rho[nz] - ref["rho"][nz]) / np.abs(ref["rho"][nz]))) if nz.any() else 0.0
+    out["fperr"] = float(np.max(np.abs(fp[nz] - ref["fp"][nz]) / np.abs(ref["fp"][nz]))) if nz.any() else 0.0
+    etot = ref["e_emb"] + ref["e_pair"]
+    out["eerr"] = abs(e[0] + e[1] - etot) / max(abs(etot), 1e-12)
+    assert out["ferr"] <= ftol, out
+    assert out["rerr"] <= rtol, out
+    assert out["fperr"] <= max(rtol, 1e-11), out
+    assert out["eerr"] <= etol, out
+    # the empty / isolated atoms: rho exactly zero on both sides
+    assert np.all(rho[~nz] == 0.0)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# indexing
+
+@pytest.mark.parametrize("delta,K", [(0.3, 58), (0.6, 64), (0.65, 88)])
+def test_stencil_matches_oracle(torch_cuda, orc, delta, K):
+    _say(f"stencil delta={delta}")
+    lat = _lattice(8, delta=delta)
+    st = lat.stencil()
+    assert st.shape == (2, K, 3)
+    for p in (0, 1):
+        ref = {tuple(r) for r in orc.stencil(A, RC + 2 * delta, p)}
+        assert {tuple(r) for r in st[p]} == ref
+    lat.close()
+
+
+def _defect_states(n, seed=0):
+    rng = np.random.default_rng(seed)
+    x, v, box = w.thermal_state(n, sigma=0.05, seed=seed + 1)
+    L = np.asarray(box)
+    out = {"thermal": (x, v)}
+    keep = np.ones(len(x), bool)
+    keep[[5, 77]] = False
+    out["vacancies"] = (x[keep], v[keep])
+    oct_site = np.array([[2.5 * A + 0.03, 2.0 * A - 0.02, 3.0 * A + 0.01]])
+    out["interstitial"] = (np.vstack([x, oct_site]), np.vstack([v, [[0.02, 0.0, -0.01]]]))
+    xf = x.copy()
+    xf[9] = oct_site[0] + [A, A, 0.0]  # Frenkel pair: atom 9 leaves its site for an interstitial position
+    out["frenkel"] = (xf, v)
+    xe = x.copy()
+    xe[0] = [L[0] - 0.05, 0.03, L[2] - 0.7]  # run-away straddling the periodic corner
+    xe[1] = [0.7, L[1] - 0.02, 0.01]
+    out["edge_runaways"] = (xe, v)
+    xm = w.bcc_positions(n) + rng.normal(0, 0.45, size=x.shape)  # many atoms beyond delta
+    out["many_runaways"] = (xm, v)
+    return out, box
+
+
+@pytest.mark.parametrize("n", [5, 7])
+def test_placement_matches_oracle(torch_cuda, orc, n):
+    states, box = _defect_states(n)
+    lat = _lattice(n)
+    for name, (x, v) in states.items():
+        _say(f"placement n={n} {name}")
+        lat.set_state(x, v)
+        got = lat.slots()
+        ref = orc.place((n, n, n), A, DELTA, x)
+        assert np.array_equal(got, ref), name
+    lat.close()
+
+
+# ---------------------------------------------------------------------------
+# per-state densities, forces, energies (FP64)
+
+@pytest.mark.parametrize("n", [5, 7, 16])
+def test_fp64_state_parity(torch_cuda, orc, pot, n):
+    states, box = _defect_states(n, seed=n)
+    lat = _lattice(n)
+    for name, (x, v) in states.items():
+        _say(f"fp64 parity n={n} {name}")
+        lat.set_state(x, v)
+        r = _compare_state(orc, pot, lat, x, box)
+        _say(f"  {name}: {r}")
+    lat.close()
+
+
+def test_c1_state_parity(torch_cuda, orc, pot):
+    _say("c1 state parity")
+    x, v, box, _ = w.make_state(w.CONFIGS["c1"])
+    lat = _lattice(16)
+    lat.set_state(x, v)
+    r = _compare_state(orc, pot, lat, x, box)
+    _say(f"  c1: {r}")
+    assert r["ferr"] < 1e-10  # FP64 path: rounding-level agreement expected
+    lat.close()
+
+
+def test_ragged_box_parity(torch_cuda, orc, pot):
+    _say("ragged 13x11x9")
+    n = (13, 11, 9)
+    x, v, box = w.thermal_state(n, sigma=0.08, seed=3)
+    lat = _lattice(n)
+    lat.set_state(x, v)
+    _compare_state(orc, pot, lat, x, box)
+    lat.close()
+
+
+def test_perfect_lattice_and_empty(torch_cuda, orc, pot):
+    import torch
+    _say("perfect lattice / empty box")
+    n = 6
+    x = w.bcc_positions(n)
+    lat = _lattice(n)
+    lat.set_state(x, np.zeros_like(x))
+    e = lat.compute()
+    torch.cuda.synchronize()
+    assert np.max(np.abs(lat.forces())) < 1e-12
+    rho = lat.rho()
+    assert np.ptp(rho) < 1e-12
+    lat.set_state(np.zeros((0, 3)), np.zeros((0, 3)))
+    e = lat.compute()
+    torch.cuda.synchronize()
+    assert np.all(e.cpu().numpy() == 0.0)
+    lat.close()
+
+
+def test_shifted_force_tables(torch_cuda, orc):
+    _say("shifted-force tables")
+    tabs = w.potential_samples(variant="shifted")
+    p = orc.Potential(orc.TABLE, tables=tabs)
+    x, v, box = w.thermal_state(6, sigma=0.1, seed=8)
+    lat = _lattice(6, tables=tabs)
+    lat.set_state(x, v)
+    _compare_state(orc, p, lat, x, box)
+    lat.close()
+
+
+def test_sum_of_forces_and_determinism(torch_cuda):
+    import torch
+    _say("newton + determinism")
+    x, v, box = w.thermal_state(9, sigma=0.3, seed=12)
+    lat = _lattice(9)
+    lat.set_state(x, v)
+    lat.compute()
+    F1 = lat.forces()
+    lat.set_state(x, v)
+    lat.compute()
+    F2 = lat.forces()
+    torch.cuda.synchronize()
+    assert np.array_equal(F1, F2)
+    assert np.max(np.abs(F1.sum(axis=0))) <= 1e-10 * np.abs(F1).sum()
+    lat.close()
+
+
+# ---------------------------------------------------------------------------
+# FP32 pair arithmetic (parity unpinned: error reported against the FP64 oracle)
+
+def test_fp32_form_error(torch_cuda, orc, pot):
+    import torch
+    _say("fp32 form")
+    x, v, box, _ = w.make_state(w.CONFIGS["c1"])
+    lat = _lattice(16, "fp32")
+    lat.set_state(x, v)
+    e = lat.compute()
+    torch.cuda.synchronize()
+    ref = orc.eam(pot, x, box)
+    ferr = _ferr(lat.forces(), ref["F"])
+    rerr = float(np.max(np.abs(lat.rho() - ref["rho"]) / ref["rho"]))
+    e = e.cpu().numpy()
+    eerr = abs(e.sum() - ref["e_emb"] - ref["e_pair"]) / len(x)
+    _say(f"  fp32: force {ferr:.3e} rho {rerr:.3e} energy/atom {eerr:.3e} eV")
+    assert ferr < 1e-3 and rerr < 1e-5 and eerr < 1e-5
+    lat.close()
+
+
+# ---------------------------------------------------------------------------
+# trajectories
+
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_trajectory_parity(torch_cuda, orc, pot, nsteps):
+    _say(f"trajectory {nsteps} steps")
+    x, v, box, _ = w.make_state(w.CONFIGS["c1"], n_cells=8)
+    lat = _lattice(8)
+    lat.set_state(x, v)
+    st = lat.step(nsteps, 1.0)
+    xg, vg = lat.get_state()
+    xo, vo, Fo, log = orc.run(pot, x, v, box, M, nsteps, 1.0)
+    L = np.asarray(box)
+    d = xg - xo
+    d -= L * np.rint(d / L)
+    assert np.max(np.abs(d)) < 1e-11
+    assert np.max(np.abs(vg - vo)) < 1e-12
+    assert abs(st["e_kin"] - log[-1, 1]) < 1e-9 * abs(log[-1, 1])
+    assert abs(st["e_emb"] + st["e_pair"] - log[-1, 2] - log[-1, 3]) < 1e-10 * abs(log[-1, 2] + log[-1, 3])
+    assert st["steps"] == nsteps and abs(st["time"] - nsteps) < 1e-12
+    lat.close()
+
+
+def test_recoil_adaptive_dt_and_runaways(torch_cuda, orc, pot):
+    """A 1 keV recoil: adaptive steps, atoms leave and re-enter slots; the
+    trajectory and the hash update match the oracle's rule."""
+    _say("recoil adaptive dt")
+    cfg = w.CONFIGS["c2"]
+    n = 8
+    x, v, box, rec = w.make_state(cfg, n_cells=n)
+    lat = _lattice(n)
+    lat.set_state(x, v)
+    xo, vo = x.copy(), v.copy()
+    Fo = None
+    L = np.asarray(box)
+    nrun_seen = 0
+    for chunk in range(6):
+        st = lat.step(5, 1.0, 0.05)
+        xo, vo, Fo, log = orc.run(pot, xo, vo, box, M, 5, 1.0, dx_max=0.05, F=Fo)
+        xg, vg = lat.get_state()
+        d = xg - xo
+        d -= L * np.rint(d / L)
+        assert np.max(np.abs(d)) < 1e-8, (chunk, np.max(np.abs(d)))
+        assert abs(st["dt"] - log[-1, 0]) < 1e-12 * log[-1, 0]
+        nrun_seen = max(nrun_seen, st["n_runaway"])
+    assert nrun_seen >= 1
+    lat.close()
+
+
+def test_classification_follows_hash_update(torch_cuda, orc, pot):
+    """After every step the GPU's slot table equals the oracle's incremental
+    hash update applied to the oracle trajectory (atoms within 1e-9 of the
+    delta boundary excluded)."""
+    _say("classification over steps")
+    n = 6
+    x, v, box = w.thermal_state(n, sigma=0.25, temperature=2000.0, seed=31)
+    lat = _lattice(n)
+    lat.set_state(x, v)
+    slots = orc.place((n, n, n), A, DELTA, x)
+    assert np.array_equal(lat.slots(), slots)
+    xo, vo, Fo = x, v, None
+    L = np.asarray(box)
+    checked = 0
+    for s in range(10):
+        lat.step(1, 1.0)
+        xo, vo, Fo, _ = orc.run(pot, xo, vo, box, M, 1, 1.0, F=Fo)
+        slots = orc.rehash((n, n, n), A, DELTA, xo, slots)
+        got = lat.slots()
+        diff = np.nonzero(got != slots)[0]
+        for i in diff:  # only atoms on the decision boundary may differ
+            s_i = slots[i] if slots[i] >= 0 else got[i]
+            X, Y, Z = orc.lattice_coords(n, n, s_i)
+            dd = xo[i] - orc.site_position(A, X, Y, Z)
+            dd -= L * np.rint(dd / L)
+            assert abs(dd @ dd - DELTA ** 2) < 1e-9, (s, i)
+        checked += len(slots)
+    assert checked > 0
+    lat.close()
