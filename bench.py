@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the EAM lattice MD step (the MISA-MD hot path) on one MI355X.
+
+Prints ONE JSON line.  `value` is atom-steps/s of the headline form (the first
+of --forms) on the chosen workload; every form's atom-steps/s, sampled force
+error against the FP64 oracle and per-kernel times go under "forms".
+
+Workloads (synthetic, seeded; the recipe lives in misa_workloads.synth):
+  c3: 320^3 BCC cells = 65,536,000 atoms, 300 K + 5 recoils at 2 keV, adaptive dt
+      (0.05 A per step, at most 1 fs), FP32 pair arithmetic (one GPU's share at
+      real shape);
+  c2: 128^3 cells = 4,194,304 atoms, 1 recoil at 1 keV, adaptive dt;
+  c1: 16^3 cells = 8,192 atoms, fixed dt = 1 fs.
+Inputs are resident in HBM before the timed region; the timed region is
+exactly --steps steps of misa_step between two synchronisations.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s + HBM GB/s: FP64-table vs FP32 vs MLP forms at stated force error"
+
+# Algorithmic cost model (one directed pair i <- j per stencil candidate):
+FLOP_CANDIDATE = 8      # separation (3) and squared distance (5) for every stencil candidate
+FLOP_RHO_PAIR = 10      # sqrt, table index (2), cubic (6), accumulate
+FLOP_FORCE_PAIR = 21    # sqrt, index (2), f' and phi' (8), (F'_i+F'_j) f' + phi' (3), / r, x d and accumulate (6)
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+HBM_PEAK_GBS = 8000.0
+# bytes each pass must move per atom (each datum once): u, v, F, rho, F' as stored per form
+BYTES_PER_ATOM_STEP = {
+    "fp64": {"kick_drift": 120, "rho": 40, "force": 56, "final_kick": 72},
+    "fp32": {"kick_drift": 108, "rho": 32, "force": 40, "final_kick": 60},
+}
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7):
+    import numpy as np
+    import torch
+
+    import misa_workloads as w
+    from paper_2107_07866_amd import Lattice
+
+    tabs = w.potential_samples()
+    t0 = time.time()
+    lat = Lattice(cfg.n_cells, w.A_FE, w.RC, w.DELTA, w.MASS_FE, form)
+    lat.set_tables(tabs)
+    lat.set_state(x, v)
+    torch.cuda.synchronize()
+    _log(f"[bench] {form}: state loaded in {time.time() - t0:.1f} s ({lat.state_bytes / 1e9:.2f} GB)")
+    dx_max = cfg.dx_max
+    if warmup > 0:
+        lat.step(warmup, cfg.dt_max, dx_max)
+    torch.cuda.synchronize()
+    lat.set_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = lat.step(steps, cfg.dt_max, dx_max)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    timing = lat.timing()
+    lat.set_timing(False)
+    wall = t2 - t1
+    n = x.shape[0]
+    out = {
+        "atom_steps_per_s": n * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "kernel_ms_per_step": {k: ms / max(steps, 1) for k, (ms, cnt) in timing.items()},
+        "kernel_launches": {k: cnt for k, (ms, cnt) in timing.items()},
+        "last_dt_fs": st["dt"],
+        "simulated_fs": st["time"],
+        "n_runaway": st["n_runaway"],
+        "range_violations": st["range_violations"],
+        "e_kin_eV": st["e_kin"],
+        "e_pot_eV": st["e_emb"] + st["e_pair"],
+    }
+    _log(f"[bench] {form}: {out['atom_steps_per_s']:.3e} atom-steps/s, {out['ms_per_step']:.3f} ms/step, "
+         f"run-aways {st['n_runaway']}")
+    # sampled force error of the final state against the FP64 oracle (outside the timed region)
+    if err_sample > 0:
+        import oracle
+        xg, _ = lat.get_state()
+        Fg = lat.forces()
+        rng = np.random.default_rng(seed)
+        sample = rng.choice(n, size=min(err_sample, n), replace=False)
+        t3 = time.time()
+        ref = oracle.eam_sampled(oracle.Potential(oracle.TABLE, tables=tabs), xg, box, sample)
+        scale = float(np.sqrt(np.mean(ref["F"] ** 2)))
+        out["force_err_max_rel_rms"] = float(np.max(np.abs(Fg[sample] - ref["F"]))) / max(scale, 1e-3)
+        out["force_err_sample"] = int(len(sample))
+        out["mean_pairs_per_atom"] = float(np.mean(ref["npairs"]))
+        _log(f"[bench] {form}: force error {out['force_err_max_rel_rms']:.2e} "
+             f"(oracle sample of {len(sample)} atoms, {time.time() - t3:.1f} s)")
+    out["K"] = int(lat.stencil().shape[1])
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline(form, res, n_atoms):
+    """Dominant lattice kernel (by measured time) against the ALU peak of its precision."""
+    kms = res["kernel_ms_per_step"]
+    dom = "force" if kms["force"] >= kms["rho"] else "rho"
+    pairs = res.get("mean_pairs_per_atom", 58.0)
+    per_atom = res["K"] * FLOP_CANDIDATE + pairs * (FLOP_FORCE_PAIR if dom == "force" else FLOP_RHO_PAIR)
+    flops = n_atoms * per_atom
+    avg_ms = kms[dom]
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[form]
+    return {"kernel": f"k_{dom}_tile<{'float' if form == 'fp32' else 'double'}>", "bound": "alu",
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": None, "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_atom": round(per_atom, 1)}
+
+
+def cpu_baseline(cfg, budget_s=15.0):
+    """The oracle (exact cell-binned FP64 EAM + velocity Verlet) on a bounded sample of the workload."""
+    import misa_workloads as w
+    import oracle
+    n = 24
+    x, v, box, _ = w.make_state(cfg, n_cells=n)
+    pot = oracle.Potential(oracle.TABLE, tables=w.potential_samples())
+    steps, F = 0, None
+    t0 = time.perf_counter()
+    while True:
+        x, v, F, _ = oracle.run(pot, x, v, box, w.MASS_FE, 5, cfg.dt_max, dx_max=cfg.dx_max, cells=True, F=F)
+        steps += 5
+        if time.perf_counter() - t0 > budget_s or steps >= 400:
+            break
+    dt = time.perf_counter() - t0
+    N = x.shape[0]
+    return {"value": N * steps / dt, "unit": "atom-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{cfg.name} recipe on a {n}^3-cell box ({N} atoms), {steps} steps, exact cell-binned "
+                      f"FP64 EAM from the same spline tables, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's step count)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--forms", default=None, help="comma list of fp32,fp64; first is the headline value")
+    ap.add_argument("--error-sample", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs one GPU only (the multi-GPU halo-exchange path is design-only); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import misa_workloads as w
+
+    cfg = w.CONFIGS[args.workload]
+    steps = args.steps if args.steps is not None else cfg.steps
+    forms = (args.forms or (cfg.precision + "," + ("fp64" if cfg.precision == "fp32" else "fp32"))).split(",")
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    x, v, box, rec = w.make_state(cfg)
+    _log(f"[bench] {cfg.name}: {x.shape[0]} atoms generated in {time.time() - t0:.1f} s; recoils {rec}")
+
+    results = {}
+    for form in forms:
+        results[form] = run_form(form, x, v, box, cfg, steps, args.warmup, args.error_sample)
+    head = results[forms[0]]
+    n = x.shape[0]
+    bpa = sum(BYTES_PER_ATOM_STEP[forms[0]].values())
+    line = {
+        "metric": METRIC,
+        "value": head["atom_steps_per_s"],
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if forms[0] == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "atoms": n, "cells": [cfg.n_cells] * 3,
+                   "pair_precision": forms[0], "integration": "f64", "dt_max_fs": cfg.dt_max,
+                   "dx_max_A": cfg.dx_max, "recoils": cfg.n_recoils, "recoil_eV": cfg.recoil_ev,
+                   "temperature_K": cfg.temperature, "table_points": w.N_TABLE},
+        "roofline": roofline(forms[0], head, n),
+        "hbm_model": {"bytes_per_atom_step": bpa,
+                      "achieved_GBps": round(head["atom_steps_per_s"] * bpa / 1e9, 1),
+                      "frac": round(head["atom_steps_per_s"] * bpa / 1e9 / HBM_PEAK_GBS, 4)},
+        "forms": results,
+    }
+    if not args.no_cpu_baseline:
+        _log("[bench] cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

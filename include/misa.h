@@ -186,6 +186,27 @@ int misa_compute_force(misa_lattice *h, double *energies_dev);
  */
 int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, misa_step_stats *stats);
 
+/* Kernel classes timed by misa_set_timing. */
+#define MISA_TIMER_RHO 0     /* lattice rho pass (one launch per step) */
+#define MISA_TIMER_FORCE 1   /* lattice force pass (one launch per step) */
+#define MISA_TIMER_KICK 2    /* kick-drift and final kick of the integrator */
+#define MISA_TIMER_RUNAWAY 3 /* hash update, device hash and run-away interactions */
+#define MISA_TIMER_OTHER 4   /* step length, energy sums */
+#define MISA_TIMER_COUNT 5
+
+typedef struct {
+    double ms[MISA_TIMER_COUNT];        /* summed GPU time per class [ms] */
+    int64_t launches[MISA_TIMER_COUNT]; /* timed launch groups per class */
+} misa_timing;
+
+/* enable != 0: record HIP events on the handle's stream around every kernel
+ * group of compute/step calls (profiling; a few microseconds per step).
+ * Resets the accumulated times. */
+int misa_set_timing(misa_lattice *h, int enable);
+
+/* Accumulated times since misa_set_timing (synchronises the stream). */
+int misa_get_timing(misa_lattice *h, misa_timing *out);
+
 /* Per-atom rho, F' or force, in atom-id order, to float64 memory (n_atoms or
  * 3 n_atoms values).  Values are those of the last compute/step. */
 int misa_get_atom_field(misa_lattice *h, int field, double *out, int where);

@@ -559,9 +559,12 @@ int64_t orc_neighbours(const double *x, int64_t N, const double L[3], double rc,
  * large system, without evaluating the whole system: rho is computed for the
  * sample and for every neighbour of a sampled atom (their F' enters the
  * sampled forces), then F for the sampled atoms.  Exact (cell-binned pair set).
+ * npairs_s (optional) receives the number of neighbours within rc of each
+ * sampled atom.
  */
 int orc_eam_sampled(const orc_potential *P, const double *x, int64_t N, const double L[3],
-                    const int64_t *sample, int64_t M, double *rho_s, double *fp_s, double *F_s)
+                    const int64_t *sample, int64_t M, double *rho_s, double *fp_s, double *F_s,
+                    int64_t *npairs_s)
 {
     const double rc2 = P->rc * P->rc;
     cell_list C;
@@ -633,6 +636,7 @@ int orc_eam_sampled(const orc_potential *P, const double *x, int64_t N, const do
             }
             rho_s[s] = rho_n[slot[i]];
             fp_s[s] = fpi;
+            if (npairs_s) npairs_s[s] = b.n;
             F_s[3 * s] = fx;
             F_s[3 * s + 1] = fy;
             F_s[3 * s + 2] = fz;

@@ -68,7 +68,8 @@ def _declare(lib):
     for nm in ("orc_eam_brute", "orc_eam_cells"):
         getattr(lib, nm).argtypes = [C.POINTER(_Potential), _dp, C.c_int64, _dp, _dp, _dp, _dp, _dp, _ip]
         getattr(lib, nm).restype = C.c_int
-    lib.orc_eam_sampled.argtypes = [C.POINTER(_Potential), _dp, C.c_int64, _dp, _ip, C.c_int64, _dp, _dp, _dp]
+    lib.orc_eam_sampled.argtypes = [C.POINTER(_Potential), _dp, C.c_int64, _dp, _ip, C.c_int64, _dp, _dp, _dp,
+                                    _ip]
     lib.orc_eam_sampled.restype = C.c_int
     lib.orc_neighbours.argtypes = [_dp, C.c_int64, _dp, C.c_double, C.c_int64, C.c_int, _ip, C.c_int64]
     lib.orc_neighbours.restype = C.c_int64
@@ -208,16 +209,18 @@ def eam(pot: Potential, x, box, cells=False, want_pairs=False):
 
 
 def eam_sampled(pot: Potential, x, box, sample):
-    """rho, F' and forces of the sampled atoms only (exact, cell-binned)."""
+    """rho, F', forces and neighbour counts of the sampled atoms only (exact, cell-binned)."""
     lib = _load()
     x = _f64(x, (-1, 3))
     L = _f64(box)
     sample = np.ascontiguousarray(sample, dtype=np.int64)
     M = len(sample)
     rho, fp, F = np.empty(M), np.empty(M), np.empty((M, 3))
-    if lib.orc_eam_sampled(pot.ref, _d(x), x.shape[0], _d(L), _i(sample), M, _d(rho), _d(fp), _d(F)) < 0:
+    npairs = np.empty(M, dtype=np.int64)
+    if lib.orc_eam_sampled(pot.ref, _d(x), x.shape[0], _d(L), _i(sample), M, _d(rho), _d(fp), _d(F),
+                           _i(npairs)) < 0:
         raise MemoryError("oracle allocation failed")
-    return dict(rho=rho, fp=fp, F=F)
+    return dict(rho=rho, fp=fp, F=F, npairs=npairs)
 
 
 def neighbours(x, box, rc, i, cells=False):

@@ -220,15 +220,70 @@ int check_ready(misa_lattice *h, bool need_tables) {
 
 hipError_t clear_marks(misa_lattice *h);
 
+// Records HIP events around one group of launches when timing is enabled.
+class GroupTimer {
+  public:
+    GroupTimer(misa_lattice *h, int cls) : h_(h), cls_(cls) {
+        if (!h->timing) return;
+        if (!h->event_pool.empty()) {
+            ev_ = h->event_pool.back();
+            h->event_pool.pop_back();
+        } else if (hipEventCreate(&ev_.first) != hipSuccess || hipEventCreate(&ev_.second) != hipSuccess) {
+            ev_ = {nullptr, nullptr};
+            return;
+        }
+        if (hipEventRecord(ev_.first, h->stream) != hipSuccess) ev_ = {nullptr, nullptr};
+    }
+    ~GroupTimer() {
+        if (!ev_.first) return;
+        if (hipEventRecord(ev_.second, h_->stream) == hipSuccess)
+            h_->timed.push_back({ev_.first, ev_.second, cls_});
+        else
+            h_->event_pool.push_back(ev_);
+    }
+
+  private:
+    misa_lattice *h_;
+    int cls_;
+    std::pair<hipEvent_t, hipEvent_t> ev_{nullptr, nullptr};
+};
+
+// Sum recorded groups into the totals (synchronises the stream).
+hipError_t fold_timing(misa_lattice *h) {
+    if (h->timed.empty()) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    for (auto &t : h->timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+            h->timer_ms[t.cls] += ms;
+            h->timer_n[t.cls] += 1;
+        }
+        h->event_pool.push_back({t.start, t.stop});
+    }
+    h->timed.clear();
+    return hipSuccess;
+}
+
 int do_rho(misa_lattice *h) {
     if (h->pending_clear) {
+        GroupTimer t(h, MISA_TIMER_RUNAWAY);
         HIPCHK(h, clear_marks(h));
         HIPCHK(h, launch_runaway_clear(h));
         h->pending_clear = false;
     }
-    HIPCHK(h, launch_runaway_build(h));
-    HIPCHK(h, launch_rho(h));
-    HIPCHK(h, launch_runaway_rho(h));
+    {
+        GroupTimer t(h, MISA_TIMER_RUNAWAY);
+        HIPCHK(h, launch_runaway_build(h));
+    }
+    {
+        GroupTimer t(h, MISA_TIMER_RHO);
+        HIPCHK(h, launch_rho(h));
+    }
+    {
+        GroupTimer t(h, MISA_TIMER_RUNAWAY);
+        HIPCHK(h, launch_runaway_rho(h));
+    }
     h->pending_clear = true;
     h->rho_valid = true;
     h->force_valid = false;
@@ -236,10 +291,22 @@ int do_rho(misa_lattice *h) {
 }
 
 int do_force(misa_lattice *h, bool energy, double *energies_dev) {
-    HIPCHK(h, launch_force(h, energy));
-    HIPCHK(h, launch_runaway_force(h, energy));
-    if (energy) HIPCHK(h, launch_energy_reduce(h, energies_dev));
-    HIPCHK(h, launch_runaway_clear(h));
+    {
+        GroupTimer t(h, MISA_TIMER_FORCE);
+        HIPCHK(h, launch_force(h, energy));
+    }
+    {
+        GroupTimer t(h, MISA_TIMER_RUNAWAY);
+        HIPCHK(h, launch_runaway_force(h, energy));
+    }
+    {
+        GroupTimer t(h, MISA_TIMER_OTHER);
+        if (energy) HIPCHK(h, launch_energy_reduce(h, energies_dev));
+    }
+    {
+        GroupTimer t(h, MISA_TIMER_RUNAWAY);
+        HIPCHK(h, launch_runaway_clear(h));
+    }
     h->pending_clear = false;
     h->force_valid = true;
     return MISA_OK;
@@ -306,6 +373,18 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     g.ntz = (g.nz + TZ - 1) / TZ;
     g.ntiles = g.ntx * g.nty * g.ntz;
     g.ntiles_pad = (g.ntiles + 7) / 8 * 8;
+    g.nt2[0] = (g.nx + T2X - 1) / T2X;
+    g.nt2[1] = (g.ny + T2Y - 1) / T2Y;
+    g.nt2[2] = (g.nz + T2Z - 1) / T2Z;
+    g.ntiles2 = g.nt2[0] * g.nt2[1] * g.nt2[2];
+    g.ntiles2_pad = (g.ntiles2 + 7) / 8 * 8;
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) ncu = 0;
+        h->n_cu = ncu;
+        // one 1024-lane work-group per compute unit (LDS-bound), a multiple of the 8 XCDs
+        h->persistent_grid = ncu >= 8 ? ncu / 8 * 8 : 0;
+    }
     g.ncell = ncell;
     g.nsites = 2 * ncell;
     g.a = d->a;
@@ -346,9 +425,10 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
         return fail(nullptr, MISA_EINVAL, "stencil larger than the kernels support (rc + 2 delta too large)");
     }
     h->K = (int)st[0].size();
+    h->d_min = h->K > 0 ? std::sqrt(st[0][0].d2) : 0.0;  // offsets are sorted nearest first
     h->stencil_canon.resize(2 * h->K * 3);
     std::vector<StencilEntry<double>> s64(2 * KMAX);
-    std::vector<StencilEntry<float>> s32(2 * KMAX);
+    std::vector<StencilEntry<float>> s32(2 * KMAX), s32p(2 * KMAX);
     for (int p = 0; p < 2; ++p)
         for (int k = 0; k < h->K; ++k) {
             const CanonOffset &o = st[p][k];
@@ -364,6 +444,8 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
             const double oz = (o.dZ + 0.5 * pn - 0.5 * p) * d->a;
             s64[p * KMAX + k] = StencilEntry<double>{lds, 0, ox, oy, oz};
             s32[p * KMAX + k] = StencilEntry<float>{lds, (float)ox, (float)oy, (float)oz};
+            const int lds2 = (pn - p) * P2Z * P2Y * P2X + (dcz * P2Y + dcy) * P2X + dcx;
+            s32p[p * KMAX + k] = StencilEntry<float>{lds2, (float)ox, (float)oy, (float)oz};
             int64_t *c = &h->stencil_canon[(p * h->K + k) * 3];
             c[0] = o.dX;
             c[1] = o.dY;
@@ -386,6 +468,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     if ((e = dev_alloc(&(ptr), (n))) != hipSuccess) return bail(e);
     ALLOC(h->st64, 2 * KMAX);
     ALLOC(h->st32, 2 * KMAX);
+    ALLOC(h->st32p, 2 * KMAX);
     ALLOC(sc.cnt, 1);
     ALLOC(sc.scal, 8);
     ALLOC(sc.part, 2 * (int64_t)g.ntiles_pad + 2 * 1024);
@@ -410,6 +493,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
 #undef ALLOC
     if ((e = hipMemcpy(h->st64, s64.data(), sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->st32, s32.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(h->st32p, s32p.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemset(sc.cnt, 0, sizeof(Counters))) || (e = hipMemset(sc.scal, 0, 8 * sizeof(double))) ||
         (e = hipMemset(sc.hkey, 0xff, sizeof(int32_t) * (size_t)H)) ||
         (e = hipMemset(sc.mark, 0, sizeof(uint32_t) * (size_t)((g.nsites + 31) / 32))) ||
@@ -428,13 +512,18 @@ int misa_destroy_lattice(misa_lattice *h) {
         (void)hipStreamSynchronize(h->stream);
     else
         (void)hipDeviceSynchronize();
-    void *ptrs[] = {h->st64, h->st32, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t32.f, h->t32.force,
+    void *ptrs[] = {h->st64, h->st32, h->st32p, h->lds32.f, h->lds32.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
                     h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,
                     h->sc.affected, h->staging};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto &t : h->timed) h->event_pool.push_back({t.start, t.stop});
+    for (auto &ev : h->event_pool) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
     delete h;
     return MISA_OK;
 }
@@ -476,6 +565,37 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
     if (rc) return rc;
     rc = upload_tables<float>(h, h->t32, sf, sp, se, *f, *emb);
     if (rc) return rc;
+    // LDS window for the persistent float32 kernels: two slotted atoms are never
+    // closer than the nearest-neighbour site distance minus 2 delta.
+    {
+        LdsTables &W = h->lds32;
+        (void)hipFree(W.f);
+        (void)hipFree(W.force);
+        W = LdsTables{};
+        const double delta = std::sqrt(h->g.delta2);
+        const double r_lo = h->d_min - 2.0 * delta - 2.0 * f->dx;
+        int64_t k0 = (int64_t)std::floor((r_lo - f->x0) / f->dx);
+        k0 = std::max<int64_t>(0, std::min<int64_t>(k0, f->n - 2));
+        const int64_t nwin = (f->n - 1) - k0;
+        if (nwin <= LDS_TAB_SEGS) {
+            std::vector<Q4<float>> wf(nwin);
+            std::vector<FRec32> wr(nwin);
+            for (int64_t q = 0; q < nwin; ++q) {
+                const SegCoef &a = sf[k0 + q], &b = sp[k0 + q];
+                wf[q] = {(float)a.c0, (float)a.c1, (float)a.c2, (float)a.c3};
+                wr[q].a = make_float2((float)a.d0, (float)a.d1);
+                wr[q].b = make_float2((float)a.d2, (float)b.d0);
+                wr[q].c = make_float2((float)b.d1, (float)b.d2);
+            }
+            HIPCHK(h, dev_alloc(&W.f, nwin));
+            HIPCHK(h, dev_alloc(&W.force, nwin));
+            HIPCHK(h, hipMemcpy(W.f, wf.data(), sizeof(Q4<float>) * nwin, hipMemcpyHostToDevice));
+            HIPCHK(h, hipMemcpy(W.force, wr.data(), sizeof(FRec32) * nwin, hipMemcpyHostToDevice));
+            W.k0 = (int32_t)k0;
+            W.nwin = (int32_t)nwin;
+            W.usable = true;
+        }
+    }
     h->tables_set = true;
     h->rho_valid = h->force_valid = false;
     return MISA_OK;
@@ -618,15 +738,31 @@ int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, mis
         if ((rc = do_rho(h))) return rc;
         if ((rc = do_force(h, false, nullptr))) return rc;
     }
-    HIPCHK(h, launch_dt_update(h, dt_max, dx_max, true));
+    {
+        GroupTimer t(h, MISA_TIMER_OTHER);
+        HIPCHK(h, launch_dt_update(h, dt_max, dx_max, true));
+    }
     for (int64_t s = 0; s < nsteps; ++s) {
         const bool last = s == nsteps - 1;
-        HIPCHK(h, launch_kick_drift(h));
-        HIPCHK(h, launch_rehash(h));
+        {
+            GroupTimer t(h, MISA_TIMER_KICK);
+            HIPCHK(h, launch_kick_drift(h));
+        }
+        {
+            GroupTimer t(h, MISA_TIMER_RUNAWAY);
+            HIPCHK(h, launch_rehash(h));
+        }
         if ((rc = do_rho(h))) return rc;
         if ((rc = do_force(h, last, nullptr))) return rc;
-        HIPCHK(h, launch_final_kick(h));
-        HIPCHK(h, launch_dt_update(h, dt_max, dx_max, false));
+        {
+            GroupTimer t(h, MISA_TIMER_KICK);
+            HIPCHK(h, launch_final_kick(h));
+        }
+        {
+            GroupTimer t(h, MISA_TIMER_OTHER);
+            HIPCHK(h, launch_dt_update(h, dt_max, dx_max, false));
+        }
+        if (h->timed.size() > 50000) HIPCHK(h, fold_timing(h));  // bound the event backlog
     }
     h->steps_done += nsteps;
     if (!stats) return MISA_OK;
@@ -648,6 +784,27 @@ int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, mis
     stats->overflow = c.overflow;
     stats->dt = scal[6];
     if (c.overflow) return fail(h, MISA_EOVERFLOW, "run-away capacity exceeded; forces inexact since");
+    return MISA_OK;
+}
+
+int misa_set_timing(misa_lattice *h, int enable) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    HIPCHK(h, fold_timing(h));
+    for (int k = 0; k < MISA_TIMER_COUNT; ++k) {
+        h->timer_ms[k] = 0.0;
+        h->timer_n[k] = 0;
+    }
+    h->timing = enable != 0;
+    return MISA_OK;
+}
+
+int misa_get_timing(misa_lattice *h, misa_timing *out) {
+    if (!h || !out) return fail(h, MISA_EINVAL, "null argument");
+    HIPCHK(h, fold_timing(h));
+    for (int k = 0; k < MISA_TIMER_COUNT; ++k) {
+        out->ms[k] = h->timer_ms[k];
+        out->launches[k] = h->timer_n[k];
+    }
     return MISA_OK;
 }
 

@@ -263,6 +263,7 @@ static hipError_t rho_impl(misa_lattice *h, const StencilEntry<Real> *st, const 
 }
 
 hipError_t launch_rho(misa_lattice *h) {
+    if (lds_path(h)) return launch_rho_lds(h);
     if (h->precision == MISA_FP32) return rho_impl<float>(h, h->st32, h->t32);
     return rho_impl<double>(h, h->st64, h->t64);
 }
@@ -283,6 +284,7 @@ static hipError_t force_impl(misa_lattice *h, bool energy, const StencilEntry<Re
 }
 
 hipError_t launch_force(misa_lattice *h, bool energy) {
+    if (lds_path(h)) return launch_force_lds(h, energy);
     if (h->precision == MISA_FP32) return force_impl<float>(h, energy, h->st32, h->t32);
     return force_impl<double>(h, energy, h->st64, h->t64);
 }
@@ -327,7 +329,8 @@ __global__ __launch_bounds__(1024) void k_energy_reduce(const double *__restrict
 }
 
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev) {
-    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, h->stream, h->sc.part, h->g.ntiles, h->S.r_e,
+    const int nparts = lds_path(h) ? h->g.ntiles2 : h->g.ntiles;  // per-tile partials of the force pass used
+    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, h->stream, h->sc.part, nparts, h->S.r_e,
                        h->sc.cnt, h->sc.scal, energies_dev);
     return hipGetLastError();
 }

@@ -33,6 +33,14 @@ constexpr int TILE_THREADS = 2 * TX * TY * TZ; // 512: one lane per interior sit
 static_assert(TX * TY == 64, "one wave covers one TX x TY plane of one parity");
 constexpr int KMAX = 96;                       // max stencil entries per parity
 
+// Persistent float32 variant: 8 x 8 x 8-cell tiles, 1024 lanes, and the window
+// of the coefficient tables that slotted pairs can reach kept in LDS.
+constexpr int T2X = 8, T2Y = 8, T2Z = 8;
+constexpr int P2X = T2X + 2 * HALO, P2Y = T2Y + 2 * HALO, P2Z = T2Z + 2 * HALO;
+constexpr int TILE2_SITES = 2 * P2X * P2Y * P2Z;
+constexpr int TILE2_THREADS = 2 * T2X * T2Y * T2Z;  // 1024
+constexpr int LDS_TAB_SEGS = 4096;                  // max table segments held in LDS
+
 constexpr double VACANT_U = 1.0e6;             // displacement stored in an empty slot
 constexpr double VACANT_TEST = 0.5e6;          // ux above this means the slot is empty
 constexpr int32_t VACANT_ID = 0x7fffffff;      // atom id stored in an empty slot
@@ -91,6 +99,8 @@ struct Geom {
     int32_t nx, ny, nz;
     int32_t ntx, nty, ntz;  // tiles per axis
     int32_t ntiles, ntiles_pad;
+    int32_t nt2[3];         // 8 x 8 x 8 tiles per axis (persistent float32 kernels)
+    int32_t ntiles2, ntiles2_pad;
     int64_t ncell;          // cells per sublattice
     int64_t nsites;
     double a, inv_a;
@@ -159,6 +169,20 @@ struct DevTables {
     TabMeta<Real> fm{}, em{};
 };
 
+// Force record of one segment as staged in LDS: {f'0, f'1}, {f'2, phi'0}, {phi'1, phi'2}.
+struct alignas(8) FRec32 {
+    float2 a, b, c;
+};
+
+// Window [k0, k0 + nwin) of the f / phi segments that pairs of slotted atoms can
+// reach (r >= nearest-site distance - 2 delta), laid out for LDS staging.
+struct LdsTables {
+    Q4<float> *f = nullptr;   // nwin value records of f
+    FRec32 *force = nullptr;  // nwin force records
+    int32_t k0 = 0, nwin = 0;
+    bool usable = false;
+};
+
 }  // namespace misa
 
 struct misa_lattice {
@@ -174,6 +198,11 @@ struct misa_lattice {
     misa::StencilEntry<float> *st32 = nullptr;
     misa::DevTables<double> t64;
     misa::DevTables<float> t32;
+    misa::LdsTables lds32;                        // window for the persistent float32 kernels
+    double d_min = 0.0;                           // nearest-neighbour site distance
+    int n_cu = 0;                                 // compute units of the device
+    int persistent_grid = 0;                      // work-groups of the persistent kernels (multiple of 8)
+    misa::StencilEntry<float> *st32p = nullptr;   // stencil with LDS offsets of the 8x8x8 tiles
     bool tables_set = false;
     misa::Scratch sc{};
     void *state_ptr = nullptr;
@@ -185,6 +214,16 @@ struct misa_lattice {
     int64_t steps_done = 0;
     double *staging = nullptr;                    // device staging for host copies
     int64_t staging_bytes = 0;
+    // optional event timing of kernel groups
+    bool timing = false;
+    struct TimedGroup {
+        hipEvent_t start, stop;
+        int cls;
+    };
+    std::vector<TimedGroup> timed;                // recorded, not yet summed
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+    double timer_ms[MISA_TIMER_COUNT] = {0};
+    int64_t timer_n[MISA_TIMER_COUNT] = {0};
     std::string err;
 };
 
@@ -194,6 +233,9 @@ namespace misa {
 // Launchers (defined in the kernel translation units).  All enqueue on h->stream.
 hipError_t launch_rho(misa_lattice *h);
 hipError_t launch_force(misa_lattice *h, bool energy);
+bool lds_path(const misa_lattice *h);                  // persistent float32 kernels usable
+hipError_t launch_rho_lds(misa_lattice *h);
+hipError_t launch_force_lds(misa_lattice *h, bool energy);
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev);
 hipError_t launch_runaway_build(misa_lattice *h);      // keys, sort, hash insert
 hipError_t launch_runaway_rho(misa_lattice *h);        // run-away rho + affected-site fixup

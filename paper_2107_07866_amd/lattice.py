@@ -72,6 +72,12 @@ class Lattice:
     def step(self, nsteps, dt_max, dx_max=0.0):
         return M.misa_step(self.h, nsteps, dt_max, dx_max)
 
+    def set_timing(self, enable=True):
+        M.misa_set_timing(self.h, enable)
+
+    def timing(self):
+        return M.misa_get_timing(self.h)
+
     def close(self):
         if self.h is not None:
             M.misa_destroy_lattice(self.h)

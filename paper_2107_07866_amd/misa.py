@@ -54,6 +54,13 @@ class misa_step_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+MISA_TIMER_NAMES = ("rho", "force", "kick", "runaway", "other")
+
+
+class misa_timing(C.Structure):
+    _fields_ = [("ms", C.c_double * 5), ("launches", C.c_int64 * 5)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -75,6 +82,8 @@ def _load():
         "misa_compute_force": ([vp, vp], C.c_int),
         "misa_step": ([vp, i64, C.c_double, C.c_double, C.POINTER(misa_step_stats)], C.c_int),
         "misa_get_atom_field": ([vp, C.c_int, vp, C.c_int], C.c_int),
+        "misa_set_timing": ([vp, C.c_int], C.c_int),
+        "misa_get_timing": ([vp, C.POINTER(misa_timing)], C.c_int),
         "misa_debug_export": ([vp, C.c_int, C.POINTER(i64), i64], i64),
     }
     for name, (args, res) in sig.items():
@@ -202,6 +211,17 @@ def misa_step(h, nsteps, dt_max, dx_max=0.0, want_stats=True):
         raise MisaError(code, misa_last_error(h))
     _check(code, h)
     return st.as_dict() if want_stats else None
+
+
+def misa_set_timing(h, enable=True):
+    return _check(lib.misa_set_timing(h, int(bool(enable))), h)
+
+
+def misa_get_timing(h):
+    """{class: (summed ms, launch groups)} since misa_set_timing."""
+    t = misa_timing()
+    _check(lib.misa_get_timing(h, C.byref(t)), h)
+    return {n: (t.ms[k], t.launches[k]) for k, n in enumerate(MISA_TIMER_NAMES)}
 
 
 def misa_get_atom_field(h, field, out=None):

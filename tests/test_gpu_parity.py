@@ -220,6 +220,54 @@ def test_fp32_form_error(torch_cuda, orc, pot):
     lat.close()
 
 
+@pytest.mark.parametrize("npts", [5000, 9000])
+def test_fp32_defects_and_ragged(torch_cuda, orc, npts):
+    """FP32 form on defect and ragged boxes; 9000-point tables exceed the LDS
+    window of the persistent kernels and exercise the generic tile kernels."""
+    import torch
+    tabs = w.potential_samples(n_points=npts)
+    p = orc.Potential(orc.TABLE, tables=tabs)
+    states, box = _defect_states(7, seed=5)
+    n3 = (13, 11, 9)
+    xr, vr, boxr = w.thermal_state(n3, sigma=0.08, seed=3)
+    cases = [(7, name, xv, box) for name, xv in states.items()] + [(n3, "ragged", (xr, vr), boxr)]
+    lats = {}
+    for n, name, (x, v), bx in cases:
+        _say(f"fp32 npts={npts} {name}")
+        key = n if isinstance(n, tuple) else (n,) * 3
+        if key not in lats:
+            lats[key] = _lattice(n, "fp32", tables=tabs)
+        lat = lats[key]
+        lat.set_state(x, v)
+        e = lat.compute()
+        torch.cuda.synchronize()
+        ref = orc.eam(p, x, bx)
+        ferr = _ferr(lat.forces(), ref["F"])
+        nz = ref["rho"] > 0
+        rerr = float(np.max(np.abs(lat.rho()[nz] - ref["rho"][nz]) / ref["rho"][nz]))
+        eerr = abs(float(e.sum()) - ref["e_emb"] - ref["e_pair"]) / len(x)
+        _say(f"  force {ferr:.2e} rho {rerr:.2e} energy/atom {eerr:.2e}")
+        assert ferr < 1e-3 and rerr < 1e-5 and eerr < 1e-5, (name, ferr, rerr, eerr)
+    for lat in lats.values():
+        lat.close()
+
+
+def test_fp32_trajectory_close_to_fp64(torch_cuda, orc, pot):
+    _say("fp32 trajectory")
+    x, v, box, _ = w.make_state(w.CONFIGS["c1"], n_cells=8)
+    lat = _lattice(8, "fp32")
+    lat.set_state(x, v)
+    lat.step(10, 1.0)
+    xg, vg = lat.get_state()
+    xo, vo, _, _ = orc.run(pot, x, v, box, M, 10, 1.0)
+    L = np.asarray(box)
+    d = xg - xo
+    d -= L * np.rint(d / L)
+    _say(f"  max position difference after 10 steps: {np.max(np.abs(d)):.2e} A")
+    assert np.max(np.abs(d)) < 1e-5
+    lat.close()
+
+
 # ---------------------------------------------------------------------------
 # trajectories
 

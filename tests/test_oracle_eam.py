@@ -160,6 +160,7 @@ def test_cell_binned_pair_set_equals_brute_force(orc):
     rs = orc.eam_sampled(P, x, box, s)
     assert np.max(np.abs(rs["F"] - rb["F"][s])) < 1e-12
     assert np.max(np.abs(rs["rho"] - rb["rho"][s])) < 1e-12
+    assert np.array_equal(rs["npairs"], rb["npairs"][s])
 
 
 def test_small_box_cell_dedup(orc):
