@@ -120,7 +120,8 @@ def roofline(form, res, n_atoms):
     avg_ms = kms[dom]
     achieved = flops / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[form]
-    return {"kernel": f"k_{dom}_tile<{'float' if form == 'fp32' else 'double'}>", "bound": "alu",
+    kname = f"k_{dom}_lds" if form == "fp32" else f"k_{dom}_tile<double>"
+    return {"kernel": kname, "bound": "alu",
             "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": None, "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_atom": round(per_atom, 1)}
 
@@ -155,7 +156,18 @@ def main():
     ap.add_argument("--forms", default=None, help="comma list of fp32,fp64; first is the headline value")
     ap.add_argument("--error-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (scale for HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 1 << 30, "copy_calibration_bytes_written": 1 << 30}))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -577,7 +577,7 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
         int64_t k0 = (int64_t)std::floor((r_lo - f->x0) / f->dx);
         k0 = std::max<int64_t>(0, std::min<int64_t>(k0, f->n - 2));
         const int64_t nwin = (f->n - 1) - k0;
-        if (nwin <= LDS_TAB_SEGS) {
+        if (nwin + 1 <= LDS_TAB_SEGS) {  // + 1: the zero record after the window
             std::vector<Q4<float>> wf(nwin);
             std::vector<FRec32> wr(nwin);
             for (int64_t q = 0; q < nwin; ++q) {
@@ -594,6 +594,8 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
             W.k0 = (int32_t)k0;
             W.nwin = (int32_t)nwin;
             W.usable = true;
+            const double x_last = f->x0 + (f->n - 1) * f->dx;
+            W.node_cut = std::fabs(x_last - h->g.rc) <= 1e-12 * h->g.rc;
         }
     }
     h->tables_set = true;

@@ -40,10 +40,21 @@ __device__ __forceinline__ Real emb_eval(Real rho, const Q4<Real> *__restrict__ 
     return (d.z * t + d.y) * t + d.x;
 }
 
+// 1/sqrt(x) for x in a normal range (pair distances): hardware estimate refined by
+// two Newton steps y <- y (3 - x y^2) / 2, each squaring the relative error, so the
+// result is within a few ulp of the correctly rounded value.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 template <typename Real>
 __device__ __forceinline__ Real pair_r(Real r2);
 template <>
-__device__ __forceinline__ double pair_r<double>(double r2) { return sqrt(r2); }
+__device__ __forceinline__ double pair_r<double>(double r2) { return r2 * rsqrt_nr(r2); }
 template <>
 __device__ __forceinline__ float pair_r<float>(float r2) { return __builtin_amdgcn_sqrtf(r2); }
 
@@ -51,8 +62,8 @@ template <typename Real>
 __device__ __forceinline__ void pair_r_rinv(Real r2, Real &r, Real &rinv);
 template <>
 __device__ __forceinline__ void pair_r_rinv<double>(double r2, double &r, double &rinv) {
-    r = sqrt(r2);
-    rinv = 1.0 / r;
+    rinv = rsqrt_nr(r2);
+    r = r2 * rinv;
 }
 template <>
 __device__ __forceinline__ void pair_r_rinv<float>(float r2, float &r, float &rinv) {
@@ -108,7 +119,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_tile(
     __syncthreads();
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int p = w / TZ, lz = w % TZ, lx = lane % TX, ly = lane / TX;
+    // wave-uniform parity: stencil entries are fetched with scalar loads
+    const int p = __builtin_amdgcn_readfirstlane(w / TZ);
+    const int lz = w % TZ, lx = lane % TX, ly = lane / TX;
     const int gx = tx * TX + lx, gy = ty * TY + ly, gz = tz * TZ + lz;
     if (gx >= g.nx || gy >= g.ny || gz >= g.nz) return;
     const int me = ((p * PZ + lz + HALO) * PY + ly + HALO) * PX + lx + HALO;
@@ -170,7 +183,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
     __syncthreads();
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int p = w / TZ, lz = w % TZ, lx = lane % TX, ly = lane / TX;
+    // wave-uniform parity: stencil entries are fetched with scalar loads
+    const int p = __builtin_amdgcn_readfirstlane(w / TZ);
+    const int lz = w % TZ, lx = lane % TX, ly = lane / TX;
     const int gx = tx * TX + lx, gy = ty * TY + ly, gz = tz * TZ + lz;
     const bool active = gx < g.nx && gy < g.ny && gz < g.nz;
     double e_emb = 0.0, e_pair = 0.0;

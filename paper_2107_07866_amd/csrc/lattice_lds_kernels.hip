@@ -58,15 +58,18 @@ __device__ __forceinline__ void load_tile2(Q4<float> *__restrict__ tile, const d
     }
 }
 
-// Segment of r inside the LDS window [k0, nseg): local index and offset t in [0, 1].
-__device__ __forceinline__ int win_seg(float p, int k0, int nlast, float &t) {
-    int k = (int)p;
-    k = k < nlast ? k : nlast;
-    k = k > k0 ? k : k0;
-    t = p - (float)k;
-    return k - k0;
+// Local segment index and offset t for pp = (r - x0) / h - k0 (the window starts
+// at segment k0).  With kNodeCut the last node sits at the cut-off and the window
+// ends with a zero record at local index nwin: pairs at or beyond the cut-off read
+// zeros, so no separate cut-off select is needed.
+template <bool kNodeCut>
+__device__ __forceinline__ int win_seg(float pp, int nwin, float &t) {
+    const float top = kNodeCut ? (float)nwin : (float)(nwin - 1);
+    t = __builtin_amdgcn_fractf(pp);
+    return (int)__builtin_amdgcn_fmed3f(pp, 0.0f, top);
 }
 
+template <bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
     float *__restrict__ rho, float *__restrict__ fp, const StencilEntry<float> *__restrict__ st, int K,
@@ -78,14 +81,14 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(
         const Q4<float> c = fwin[e];
         ftab[e] = make_float4(c.x, c.y, c.z, c.w);
     }
+    if (kNodeCut && threadIdx.x == 0) ftab[nwin] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // wave-uniform: the stencil entries below become scalar loads
     const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
     const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
     const StencilEntry<float> *sp = st + p * KMAX;
     const float rc2 = (float)g.rc2;
-    const float pc = -fm.x0 * fm.inv_h;  // p = r / h - x0 / h
-    const int nlast = fm.nseg - 1;
+    const float pc = -fm.x0 * fm.inv_h - (float)k0;  // pp = (r - x0) / h - k0
     for (int it = 0;; ++it) {
         const int tid = persistent_tile(blockIdx.x, it, gridDim.x, g);
         if (tid < 0) break;
@@ -109,10 +112,10 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(
             const float dz = (uj.z - ui.z) + e.oz;
             const float r2 = dx * dx + dy * dy + dz * dz;
             float t;
-            const int s = win_seg(__builtin_amdgcn_sqrtf(r2) * fm.inv_h + pc, k0, nlast, t);
+            const int s = win_seg<kNodeCut>(__builtin_amdgcn_sqrtf(r2) * fm.inv_h + pc, nwin, t);
             const float4 c = ftab[s];
             const float v = ((c.w * t + c.z) * t + c.y) * t + c.x;
-            acc += r2 < rc2 ? v : 0.0f;
+            acc += (kNodeCut || r2 < rc2) ? v : 0.0f;
         }
         const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
         float fpv = 0.0f;
@@ -142,7 +145,7 @@ __device__ __forceinline__ double wave_sum_l(double v) {
     return v;
 }
 
-template <bool kEnergy>
+template <bool kEnergy, bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
     const float *__restrict__ fp, const float *__restrict__ rho, float *__restrict__ fx, float *__restrict__ fy,
@@ -157,13 +160,17 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
         fab[e] = make_float4(c.a.x, c.a.y, c.b.x, c.b.y);
         fcc[e] = c.c;
     }
+    if (kNodeCut && threadIdx.x == 0) {
+        fab[nwin] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        fcc[nwin] = make_float2(0.0f, 0.0f);
+    }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
     const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
     const StencilEntry<float> *sp = st + p * KMAX;
     const float rc2 = (float)g.rc2;
     const float inv_h = T.fm.inv_h;
-    const float pc = -T.fm.x0 * T.fm.inv_h;
+    const float pc = -T.fm.x0 * T.fm.inv_h - (float)k0;  // pp = (r - x0) / h - k0
     const int nlast = T.fm.nseg - 1;
     for (int it = 0;; ++it) {
         const int tid = persistent_tile(blockIdx.x, it, gridDim.x, g);
@@ -191,20 +198,21 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float rinv = __builtin_amdgcn_rsqf(r2);
                 float t;
-                const int s = win_seg((r2 * rinv) * inv_h + pc, k0, nlast, t);
+                const int s = win_seg<kNodeCut>((r2 * rinv) * inv_h + pc, nwin, t);
                 const float4 a = fab[s];
                 const float2 c = fcc[s];
                 const float dfr = (a.z * t + a.y) * t + a.x;  // f'(r)
                 const float dph = (c.y * t + c.x) * t + a.w;  // phi'(r)
                 float sc = ((ui.w + uj.w) * dfr + dph) * rinv;
-                sc = r2 < rc2 ? sc : 0.0f;
+                if (!kNodeCut) sc = r2 < rc2 ? sc : 0.0f;
                 ax += sc * dx;
                 ay += sc * dy;
                 az += sc * dz;
                 if (kEnergy) {
-                    const Q4<float> cp = T.phi[s + k0];
+                    const int sg = min(s + k0, nlast);
+                    const Q4<float> cp = T.phi[sg];
                     const float v = ((cp.w * t + cp.z) * t + cp.y) * t + cp.x;
-                    ep += r2 < rc2 ? v : 0.0f;
+                    ep += (kNodeCut ? s < nwin : r2 < rc2) ? v : 0.0f;  // same pair set as the force
                 }
             }
             const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
@@ -258,9 +266,10 @@ bool lds_path(const misa_lattice *h) {
 
 hipError_t launch_rho_lds(misa_lattice *h) {
     const Geom &g = h->g;
-    hipLaunchKernelGGL(k_rho_lds, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, h->S.ux, h->S.uy,
-                       h->S.uz, (float *)h->S.rho, (float *)h->S.fp, h->st32p, h->K, h->lds32.f, h->lds32.k0,
-                       h->lds32.nwin, h->t32.fm, h->t32.emb, h->t32.em, g, &h->sc.cnt->range_viol);
+    auto kern = h->lds32.node_cut ? k_rho_lds<true> : k_rho_lds<false>;
+    hipLaunchKernelGGL(kern, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
+                       (float *)h->S.rho, (float *)h->S.fp, h->st32p, h->K, h->lds32.f, h->lds32.k0, h->lds32.nwin,
+                       h->t32.fm, h->t32.emb, h->t32.em, g, &h->sc.cnt->range_viol);
     return hipGetLastError();
 }
 
@@ -273,16 +282,13 @@ hipError_t launch_force_lds(misa_lattice *h, bool energy) {
     T.emb = h->t32.emb;
     T.fm = h->t32.fm;
     T.em = h->t32.em;
-    if (energy)
-        hipLaunchKernelGGL(k_force_lds<true>, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, h->S.ux,
-                           h->S.uy, h->S.uz, (const float *)h->S.fp, (const float *)h->S.rho, (float *)h->S.fx,
-                           (float *)h->S.fy, (float *)h->S.fz, h->st32p, h->K, h->lds32.force, h->lds32.k0,
-                           h->lds32.nwin, T, g, h->sc.part);
-    else
-        hipLaunchKernelGGL(k_force_lds<false>, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream,
-                           h->S.ux, h->S.uy, h->S.uz, (const float *)h->S.fp, (const float *)h->S.rho,
-                           (float *)h->S.fx, (float *)h->S.fy, (float *)h->S.fz, h->st32p, h->K, h->lds32.force,
-                           h->lds32.k0, h->lds32.nwin, T, g, h->sc.part);
+    const bool nc = h->lds32.node_cut;
+    auto kern = energy ? (nc ? k_force_lds<true, true> : k_force_lds<true, false>)
+                       : (nc ? k_force_lds<false, true> : k_force_lds<false, false>);
+    hipLaunchKernelGGL(kern, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
+                       (const float *)h->S.fp, (const float *)h->S.rho, (float *)h->S.fx, (float *)h->S.fy,
+                       (float *)h->S.fz, h->st32p, h->K, h->lds32.force, h->lds32.k0, h->lds32.nwin, T, g,
+                       h->sc.part);
     return hipGetLastError();
 }
 

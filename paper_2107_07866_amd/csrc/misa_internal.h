@@ -181,6 +181,7 @@ struct LdsTables {
     FRec32 *force = nullptr;  // nwin force records
     int32_t k0 = 0, nwin = 0;
     bool usable = false;
+    bool node_cut = false;    // last node at rc: a zero record after the window implements the cut-off
 };
 
 }  // namespace misa
