@@ -110,6 +110,29 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7):
     return out
 
 
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_force_lds_c3_fp32_hbm_counters.txt")
+LDS_KERNEL_SRC = os.path.join(ROOT, "paper_2107_07866_amd", "csrc", "lattice_lds_kernels.hip")
+
+
+def counted_traffic():
+    """HBM bytes per launch of k_force_lds from the committed rocprofv3 counter summary
+    (FETCH_SIZE, WRITE_SIZE scaled by a plain-copy calibration), or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(COUNTER_SUMMARY):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        src = hashlib.sha256(open(LDS_KERNEL_SRC, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != src:
+            return None
+        return float(kv["dominant_traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline(form, res, n_atoms):
     """Dominant lattice kernel (by measured time) against the ALU peak of its precision."""
     kms = res["kernel_ms_per_step"]
@@ -121,9 +144,12 @@ def roofline(form, res, n_atoms):
     achieved = flops / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[form]
     kname = f"k_{dom}_lds" if form == "fp32" else f"k_{dom}_tile<double>"
+    traffic = counted_traffic() if (form == "fp32" and dom == "force" and n_atoms == 65536000) else None
     return {"kernel": kname, "bound": "alu",
             "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": None, "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_atom": round(per_atom, 1)}
+            "traffic": traffic, "traffic_unit": "B/launch", "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_flop_per_atom": round(per_atom, 1),
+            "algorithmic_bytes_per_launch": n_atoms * (BYTES_PER_ATOM_STEP[form][dom])}
 
 
 def cpu_baseline(cfg, budget_s=15.0):
