@@ -290,25 +290,29 @@ int do_rho(misa_lattice *h) {
     return MISA_OK;
 }
 
-int do_force(misa_lattice *h, bool energy, double *energies_dev) {
+// Force pass (kick: with the fused second half-kick).  The hash and the affected
+// list stay alive for the step statistics until finish_force.
+int do_force(misa_lattice *h, bool energy, double *energies_dev, bool kick) {
     {
         GroupTimer t(h, MISA_TIMER_FORCE);
-        HIPCHK(h, launch_force(h, energy));
+        HIPCHK(h, launch_force(h, energy, kick));
     }
     {
         GroupTimer t(h, MISA_TIMER_RUNAWAY);
-        HIPCHK(h, launch_runaway_force(h, energy));
+        HIPCHK(h, launch_runaway_force(h, energy, kick));
     }
     {
         GroupTimer t(h, MISA_TIMER_OTHER);
         if (energy) HIPCHK(h, launch_energy_reduce(h, energies_dev));
     }
-    {
-        GroupTimer t(h, MISA_TIMER_RUNAWAY);
-        HIPCHK(h, launch_runaway_clear(h));
-    }
-    h->pending_clear = false;
     h->force_valid = true;
+    return MISA_OK;
+}
+
+int finish_force(misa_lattice *h) {
+    GroupTimer t(h, MISA_TIMER_RUNAWAY);
+    HIPCHK(h, launch_runaway_clear(h));
+    h->pending_clear = false;
     return MISA_OK;
 }
 
@@ -489,7 +493,9 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(sc.hkey, H);
     ALLOC(sc.hval, H);
     ALLOC(sc.mark, (g.nsites + 31) / 32);
-    ALLOC(sc.affected, sc.affected_cap);
+    ALLOC(sc.affected, next_pow2(sc.affected_cap));
+    ALLOC(sc.aff_v2, sc.affected_cap);
+    ALLOC(sc.part_kick, 2 * (int64_t)std::max(g.ntiles2_pad, 8));
 #undef ALLOC
     if ((e = hipMemcpy(h->st64, s64.data(), sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->st32, s32.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
@@ -516,7 +522,7 @@ int misa_destroy_lattice(misa_lattice *h) {
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
                     h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,
-                    h->sc.affected, h->staging};
+                    h->sc.affected, h->sc.aff_v2, h->sc.part_kick, h->staging};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : h->timed) h->event_pool.push_back({t.start, t.stop});
@@ -728,7 +734,8 @@ int misa_compute_force(misa_lattice *h, double *energies_dev) {
     if (rc) return rc;
     if (!h->rho_valid || !h->pending_clear)
         return fail(h, MISA_ESTATE, "misa_compute_force needs misa_compute_rho on the same state first");
-    return do_force(h, energies_dev != nullptr, energies_dev);
+    if ((rc = do_force(h, energies_dev != nullptr, energies_dev, false))) return rc;
+    return finish_force(h);
 }
 
 int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, misa_step_stats *stats) {
@@ -738,8 +745,10 @@ int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, mis
         return fail(h, MISA_EINVAL, "nsteps >= 0 and dt_max > 0 required");
     if (!h->force_valid) {
         if ((rc = do_rho(h))) return rc;
-        if ((rc = do_force(h, false, nullptr))) return rc;
+        if ((rc = do_force(h, false, nullptr, false))) return rc;
+        if ((rc = finish_force(h))) return rc;
     }
+    const bool fused = fused_kick(h);
     {
         GroupTimer t(h, MISA_TIMER_OTHER);
         HIPCHK(h, launch_dt_update(h, dt_max, dx_max, true));
@@ -755,7 +764,7 @@ int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, mis
             HIPCHK(h, launch_rehash(h));
         }
         if ((rc = do_rho(h))) return rc;
-        if ((rc = do_force(h, last, nullptr))) return rc;
+        if ((rc = do_force(h, last, nullptr, fused))) return rc;
         {
             GroupTimer t(h, MISA_TIMER_KICK);
             HIPCHK(h, launch_final_kick(h));
@@ -764,6 +773,7 @@ int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, mis
             GroupTimer t(h, MISA_TIMER_OTHER);
             HIPCHK(h, launch_dt_update(h, dt_max, dx_max, false));
         }
+        if ((rc = finish_force(h))) return rc;  // after the step statistics read the affected list
         if (h->timed.size() > 50000) HIPCHK(h, fold_timing(h));  // bound the event backlog
     }
     h->steps_done += nsteps;

@@ -150,13 +150,24 @@ __global__ void k_final_kick_runaway(State S, Scratch sc, double kf) {
 
 // max |v|, kinetic energy, and the next step length
 // dt = min(dt_max, dx_max / max|v|)  (dx_max <= 0: dt = dt_max).
+// use_aff: lattice atoms next to run-aways were left out of the per-tile partials of
+// the fused kick; their |v|^2 come from the (sorted) affected list.
 __global__ __launch_bounds__(1024) void k_dt_update(State S, Scratch sc, const double *__restrict__ part, int nblk,
-                                                    double mass, double dt_max, double dx_max, int first) {
+                                                    int use_aff, double mass, double dt_max, double dx_max,
+                                                    int first) {
     __shared__ double red[2][1024 / 64];
     double vm = 0.0, ks = 0.0;
     for (int i = threadIdx.x; i < nblk; i += 1024) {
         vm = fmax(vm, part[2 * i]);
         ks += part[2 * i + 1];
+    }
+    if (use_aff) {
+        int na = sc.cnt->n_affected;
+        na = na < sc.affected_cap ? na : (int)sc.affected_cap;
+        for (int q = threadIdx.x; q < na; q += 1024) {
+            vm = fmax(vm, sc.aff_v2[q]);
+            ks += sc.aff_v2[q];
+        }
     }
     const int n = sc.cnt->n_run;
     for (int r = threadIdx.x; r < n; r += 1024) {
@@ -307,16 +318,24 @@ static hipError_t kick_impl(misa_lattice *h, int kick) {
     return hipGetLastError();
 }
 
-hipError_t launch_final_kick(misa_lattice *h) { return kick_impl(h, 1); }
+hipError_t launch_final_kick(misa_lattice *h) {
+    if (!fused_kick(h)) return kick_impl(h, 1);
+    // lattice atoms were kicked inside the force pass; only run-away atoms remain
+    hipLaunchKernelGGL(k_final_kick_runaway, dim3(SMALL_GRID), dim3(256), 0, h->stream, h->S, h->sc,
+                       ACC_UNIT / h->mass);
+    return hipGetLastError();
+}
 
 hipError_t launch_dt_update(misa_lattice *h, double dt_max, double dx_max, bool first) {
     if (first) {
         hipError_t e = kick_impl(h, 0);
         if (e != hipSuccess) return e;
     }
-    double *part = h->sc.part + 2 * (int64_t)h->g.ntiles_pad;
-    hipLaunchKernelGGL(k_dt_update, dim3(1), dim3(1024), 0, h->stream, h->S, h->sc, part, KICK_BLOCKS, h->mass,
-                       dt_max, dx_max, first ? 1 : 0);
+    const bool fused = fused_kick(h) && !first;
+    const double *part = fused ? h->sc.part_kick : h->sc.part + 2 * (int64_t)h->g.ntiles_pad;
+    const int nblk = fused ? h->g.ntiles2 : KICK_BLOCKS;
+    hipLaunchKernelGGL(k_dt_update, dim3(1), dim3(1024), 0, h->stream, h->S, h->sc, part, nblk, fused ? 1 : 0,
+                       h->mass, dt_max, dx_max, first ? 1 : 0);
     return hipGetLastError();
 }
 

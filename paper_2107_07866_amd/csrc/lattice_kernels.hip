@@ -298,8 +298,11 @@ static hipError_t force_impl(misa_lattice *h, bool energy, const StencilEntry<Re
     return hipGetLastError();
 }
 
-hipError_t launch_force(misa_lattice *h, bool energy) {
-    if (lds_path(h)) return launch_force_lds(h, energy);
+bool fused_kick(const misa_lattice *h) { return lds_path(h); }
+
+hipError_t launch_force(misa_lattice *h, bool energy, bool kick) {
+    if (lds_path(h)) return launch_force_lds(h, energy, kick);
+    if (kick) return hipErrorInvalidValue;  // the generic kernels keep the separate final kick
     if (h->precision == MISA_FP32) return force_impl<float>(h, energy, h->st32, h->t32);
     return force_impl<double>(h, energy, h->st64, h->t64);
 }

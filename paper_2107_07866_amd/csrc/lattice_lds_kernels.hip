@@ -7,14 +7,16 @@
 // (r >= nearest-site distance - 2 delta) into LDS, then loops over 8 x 8 x 8-cell
 // tiles, each staged with its periodic halo.  Work-groups are sized to one per
 // compute unit; tiles are dealt out so every XCD sweeps one contiguous block of
-// tiles (halo re-reads stay in that XCD's L2).
+// tiles (halo re-reads stay in that XCD's L2).  The next tile's displacements are
+// fetched into registers while the current tile computes (the GPU counterpart of
+// the paper's double-buffered DMA, Sec. 4.3).
 //
 // The pair loop is branch-free and unrolled: every stencil candidate runs the
-// full arithmetic and out-of-range pairs are dropped by a select, so the LDS
-// reads of several offsets are in flight together instead of one dependent
-// chain per offset.  Table indices are clamped into the window: a slotted atom
-// is within delta of its site, so an in-range pair can only fall below the
-// window after a run-away capacity overflow (reported on its own).
+// full arithmetic and out-of-range pairs are dropped by a select (or read a zero
+// record), so the LDS reads of several offsets are in flight together instead
+// of one dependent chain per offset.  Table indices are clamped into the window:
+// a slotted atom is within delta of its site, so an in-range pair can only fall
+// below the window after a run-away capacity overflow (reported on its own).
 #include "misa_internal.h"
 
 namespace misa {
@@ -24,37 +26,66 @@ __device__ __forceinline__ int wrap2(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-// Tile handled by work-group b on its it-th iteration, or -1 when done.
-__device__ __forceinline__ int persistent_tile(int b, int it, int grid, const Geom &g) {
-    const int per = g.ntiles2_pad >> 3;         // tiles per XCD
-    const int j = (b >> 3) + it * (grid >> 3);  // position inside this XCD's block of tiles
-    if (j >= per) return -1;
-    return (b & 7) * per + j;
+// Next real tile of work-group b at or after iteration it (advances it), or -1.
+__device__ __forceinline__ int next_tile(int b, int &it, int grid, const Geom &g) {
+    const int per = g.ntiles2_pad >> 3;  // tiles per XCD
+    for (;; ++it) {
+        const int j = (b >> 3) + it * (grid >> 3);  // position inside this XCD's block of tiles
+        if (j >= per) return -1;
+        const int tid = (b & 7) * per + j;
+        if (tid < g.ntiles2) return tid;
+    }
 }
 
-__device__ __forceinline__ void load_tile2(Q4<float> *__restrict__ tile, const double *__restrict__ ux,
-                                           const double *__restrict__ uy, const double *__restrict__ uz,
-                                           const float *__restrict__ w_src, const Geom &g, int tid) {
+constexpr int TILE2_PER_LANE = (TILE2_SITES + TILE2_THREADS - 1) / TILE2_THREADS;
+
+// One lane's share of a tile (interior + halo), held in registers between the
+// global fetch and the LDS store.
+struct TileRegs {
+    double x[TILE2_PER_LANE], y[TILE2_PER_LANE], z[TILE2_PER_LANE];
+    float w[TILE2_PER_LANE];
+};
+
+__device__ __forceinline__ void fetch_tile2(TileRegs &R, const double *__restrict__ ux,
+                                            const double *__restrict__ uy, const double *__restrict__ uz,
+                                            const float *__restrict__ w_src, const Geom &g, int tid) {
     const int tx = tid % g.nt2[0];
     const int tyz = tid / g.nt2[0];
     const int ty = tyz % g.nt2[1];
     const int tz = tyz / g.nt2[1];
     const int bx = tx * T2X - HALO, by = ty * T2Y - HALO, bz = tz * T2Z - HALO;
-    for (int e = threadIdx.x; e < TILE2_SITES; e += TILE2_THREADS) {
-        const int lx = e % P2X;
-        int r = e / P2X;
-        const int ly = r % P2Y;
-        r /= P2Y;
-        const int lz = r % P2Z;
-        const int p = r / P2Z;
-        const int gx = wrap2(bx + lx, g.nx), gy = wrap2(by + ly, g.ny), gz = wrap2(bz + lz, g.nz);
-        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
-        Q4<float> q;
-        q.x = (float)ux[idx];
-        q.y = (float)uy[idx];
-        q.z = (float)uz[idx];
-        q.w = w_src ? w_src[idx] : 0.0f;
-        tile[e] = q;
+#pragma unroll
+    for (int j = 0; j < TILE2_PER_LANE; ++j) {
+        const int e = threadIdx.x + j * TILE2_THREADS;
+        if (e < TILE2_SITES) {
+            const int lx = e % P2X;
+            int r = e / P2X;
+            const int ly = r % P2Y;
+            r /= P2Y;
+            const int lz = r % P2Z;
+            const int p = r / P2Z;
+            const int gx = wrap2(bx + lx, g.nx), gy = wrap2(by + ly, g.ny), gz = wrap2(bz + lz, g.nz);
+            const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+            R.x[j] = ux[idx];
+            R.y[j] = uy[idx];
+            R.z[j] = uz[idx];
+            R.w[j] = w_src ? w_src[idx] : 0.0f;
+        }
+    }
+}
+
+__device__ __forceinline__ void store_tile2(Q4<float> *__restrict__ tile, const TileRegs &R) {
+#pragma unroll
+    for (int j = 0; j < TILE2_PER_LANE; ++j) {
+        const int e = threadIdx.x + j * TILE2_THREADS;
+        if (e < TILE2_SITES) {
+            Q4<float> q;
+            q.x = (float)R.x[j];
+            q.y = (float)R.y[j];
+            q.z = (float)R.z[j];
+            q.w = R.w[j];
+            tile[e] = q;
+        }
     }
 }
 
@@ -89,54 +120,60 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(
     const StencilEntry<float> *sp = st + p * KMAX;
     const float rc2 = (float)g.rc2;
     const float pc = -fm.x0 * fm.inv_h - (float)k0;  // pp = (r - x0) / h - k0
-    for (int it = 0;; ++it) {
-        const int tid = persistent_tile(blockIdx.x, it, gridDim.x, g);
-        if (tid < 0) break;
-        if (tid >= g.ntiles2) continue;  // uniform across the work-group
-        __syncthreads();                 // previous tile fully consumed (and table copied)
-        load_tile2(tile, ux, uy, uz, nullptr, g, tid);
+    int it = 0;
+    int tid = next_tile(blockIdx.x, it, gridDim.x, g);
+    TileRegs R;
+    if (tid >= 0) fetch_tile2(R, ux, uy, uz, nullptr, g, tid);
+    while (tid >= 0) {
+        __syncthreads();  // previous tile fully consumed (and the table copied)
+        store_tile2(tile, R);
         __syncthreads();
+        ++it;
+        const int nxt = next_tile(blockIdx.x, it, gridDim.x, g);
+        if (nxt >= 0) fetch_tile2(R, ux, uy, uz, nullptr, g, nxt);  // in flight during this tile
         const int tx = tid % g.nt2[0];
         const int tyz = tid / g.nt2[0];
         const int gx = tx * T2X + lx, gy = (tyz % g.nt2[1]) * T2Y + ly, gz = (tyz / g.nt2[1]) * T2Z + lz;
-        if (gx >= g.nx || gy >= g.ny || gz >= g.nz) continue;
-        const int me = ((p * P2Z + lz + HALO) * P2Y + ly + HALO) * P2X + lx + HALO;
-        const Q4<float> ui = tile[me];
-        float acc = 0.0f;
+        if (gx < g.nx && gy < g.ny && gz < g.nz) {
+            const int me = ((p * P2Z + lz + HALO) * P2Y + ly + HALO) * P2X + lx + HALO;
+            const Q4<float> ui = tile[me];
+            float acc = 0.0f;
 #pragma unroll 4
-        for (int k = 0; k < K; ++k) {
-            const StencilEntry<float> e = sp[k];
-            const Q4<float> uj = tile[me + e.lds];
-            const float dx = (uj.x - ui.x) + e.ox;
-            const float dy = (uj.y - ui.y) + e.oy;
-            const float dz = (uj.z - ui.z) + e.oz;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            float t;
-            const int s = win_seg<kNodeCut>(__builtin_amdgcn_sqrtf(r2) * fm.inv_h + pc, nwin, t);
-            const float4 c = ftab[s];
-            const float v = ((c.w * t + c.z) * t + c.y) * t + c.x;
-            acc += (kNodeCut || r2 < rc2) ? v : 0.0f;
+            for (int k = 0; k < K; ++k) {
+                const StencilEntry<float> e = sp[k];
+                const Q4<float> uj = tile[me + e.lds];
+                const float dx = (uj.x - ui.x) + e.ox;
+                const float dy = (uj.y - ui.y) + e.oy;
+                const float dz = (uj.z - ui.z) + e.oz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                float t;
+                const int s = win_seg<kNodeCut>(__builtin_amdgcn_sqrtf(r2) * fm.inv_h + pc, nwin, t);
+                const float4 c = ftab[s];
+                const float v = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                acc += (kNodeCut || r2 < rc2) ? v : 0.0f;
+            }
+            const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+            float fpv = 0.0f;
+            bool beyond = false;
+            if (ui.x > (float)VACANT_TEST) {
+                acc = 0.0f;
+            } else if (acc > em.x_last) {
+                beyond = true;
+                fpv = em.d_last;
+            } else {
+                const float q = (acc - em.x0) * em.inv_h;
+                int kk = (int)q;
+                kk = kk < em.nseg - 1 ? kk : em.nseg - 1;
+                kk = kk > 0 ? kk : 0;
+                const float t = q - (float)kk;
+                const Q4<float> d = etab[2 * kk + 1];
+                fpv = (d.z * t + d.y) * t + d.x;
+            }
+            rho[idx] = acc;
+            fp[idx] = fpv;
+            if (beyond) atomicAdd(range_viol, 1u);
         }
-        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
-        float fpv = 0.0f;
-        bool beyond = false;
-        if (ui.x > (float)VACANT_TEST) {
-            acc = 0.0f;
-        } else if (acc > em.x_last) {
-            beyond = true;
-            fpv = em.d_last;
-        } else {
-            const float q = (acc - em.x0) * em.inv_h;
-            int kk = (int)q;
-            kk = kk < em.nseg - 1 ? kk : em.nseg - 1;
-            kk = kk > 0 ? kk : 0;
-            const float t = q - (float)kk;
-            const Q4<float> d = etab[2 * kk + 1];
-            fpv = (d.z * t + d.y) * t + d.x;
-        }
-        rho[idx] = acc;
-        fp[idx] = fpv;
-        if (beyond) atomicAdd(range_viol, 1u);
+        tid = nxt;
     }
 }
 
@@ -145,16 +182,33 @@ __device__ __forceinline__ double wave_sum_l(double v) {
     return v;
 }
 
-template <bool kEnergy, bool kNodeCut>
+__device__ __forceinline__ double wave_max_l(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Fused second half-kick of velocity Verlet: v += (dt/2) C F / m right after F is
+// known, plus per-tile {max |v|^2, sum |v|^2} over atoms that no run-away atom
+// touches (those get their run-away terms, kick and statistics in the fixup pass).
+struct KickArgs {
+    double *vx, *vy, *vz;
+    const uint32_t *mark;
+    const double *scal;  // scal[0] = dt of this step
+    double kf;           // C / m
+    double *part_kick;
+};
+
+template <bool kEnergy, bool kNodeCut, bool kKick>
 __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
     const float *__restrict__ fp, const float *__restrict__ rho, float *__restrict__ fx, float *__restrict__ fy,
     float *__restrict__ fz, const StencilEntry<float> *__restrict__ st, int K, const FRec32 *__restrict__ fwin,
-    int k0, int nwin, Tables<float> T, Geom g, double *__restrict__ part) {
+    int k0, int nwin, Tables<float> T, Geom g, double *__restrict__ part, KickArgs kick) {
     __shared__ Q4<float> tile[TILE2_SITES];
     __shared__ float4 fab[LDS_TAB_SEGS];  // {f'0, f'1, f'2, phi'0} per segment
     __shared__ float2 fcc[LDS_TAB_SEGS];  // {phi'1, phi'2}
-    __shared__ double red[2][TILE2_THREADS / 64];
+    __shared__ double red[4][TILE2_THREADS / 64];
+    const double hk = kKick ? 0.5 * kick.scal[0] * kick.kf : 0.0;
     for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) {
         const FRec32 c = fwin[e];
         fab[e] = make_float4(c.a.x, c.a.y, c.b.x, c.b.y);
@@ -172,18 +226,31 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
     const float inv_h = T.fm.inv_h;
     const float pc = -T.fm.x0 * T.fm.inv_h - (float)k0;  // pp = (r - x0) / h - k0
     const int nlast = T.fm.nseg - 1;
-    for (int it = 0;; ++it) {
-        const int tid = persistent_tile(blockIdx.x, it, gridDim.x, g);
-        if (tid < 0) break;
-        if (tid >= g.ntiles2) continue;
+    int it = 0;
+    int tid = next_tile(blockIdx.x, it, gridDim.x, g);
+    TileRegs R;
+    if (tid >= 0) fetch_tile2(R, ux, uy, uz, fp, g, tid);
+    while (tid >= 0) {
         __syncthreads();
-        load_tile2(tile, ux, uy, uz, fp, g, tid);
+        store_tile2(tile, R);
         __syncthreads();
+        ++it;
+        const int nxt = next_tile(blockIdx.x, it, gridDim.x, g);
+        if (nxt >= 0) fetch_tile2(R, ux, uy, uz, fp, g, nxt);  // in flight during this tile
         const int tx = tid % g.nt2[0];
         const int tyz = tid / g.nt2[0];
         const int gx = tx * T2X + lx, gy = (tyz % g.nt2[1]) * T2Y + ly, gz = (tyz / g.nt2[1]) * T2Z + lz;
         const bool active = gx < g.nx && gy < g.ny && gz < g.nz;
-        double e_emb = 0.0, e_pair = 0.0;
+        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+        double e_emb = 0.0, e_pair = 0.0, kvm = 0.0, kvs = 0.0;
+        double v0x = 0.0, v0y = 0.0, v0z = 0.0;
+        uint32_t mw = 0u;
+        if (kKick && active) {  // issued now, consumed after the pair loop
+            v0x = kick.vx[idx];
+            v0y = kick.vy[idx];
+            v0z = kick.vz[idx];
+            mw = kick.mark[idx >> 5];
+        }
         if (active) {
             const int me = ((p * P2Z + lz + HALO) * P2Y + ly + HALO) * P2X + lx + HALO;
             const Q4<float> ui = tile[me];
@@ -215,12 +282,23 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
                     ep += (kNodeCut ? s < nwin : r2 < rc2) ? v : 0.0f;  // same pair set as the force
                 }
             }
-            const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
             const bool vac = ui.x > (float)VACANT_TEST;
             if (vac) ax = ay = az = 0.0f;
             fx[idx] = ax;
             fy[idx] = ay;
             fz[idx] = az;
+            if (kKick && !vac) {
+                const double vx = v0x + hk * (double)ax;
+                const double vy = v0y + hk * (double)ay;
+                const double vz = v0z + hk * (double)az;
+                kick.vx[idx] = vx;
+                kick.vy[idx] = vy;
+                kick.vz[idx] = vz;
+                if (!((mw >> (idx & 31)) & 1u)) {
+                    kvm = vx * vx + vy * vy + vz * vz;
+                    kvs = kvm;
+                }
+            }
             if (kEnergy && !vac) {
                 const float rr = rho[idx];
                 float Fv;
@@ -239,24 +317,41 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
                 e_pair = 0.5 * (double)ep;
             }
         }
-        if (kEnergy) {
-            e_emb = wave_sum_l(e_emb);
-            e_pair = wave_sum_l(e_pair);
+        if (kEnergy || kKick) {
+            if (kEnergy) {
+                e_emb = wave_sum_l(e_emb);
+                e_pair = wave_sum_l(e_pair);
+            }
+            if (kKick) {
+                kvm = wave_max_l(kvm);
+                kvs = wave_sum_l(kvs);
+            }
             if (lane == 0) {
                 red[0][w] = e_emb;
                 red[1][w] = e_pair;
+                red[2][w] = kvm;
+                red[3][w] = kvs;
             }
             __syncthreads();
             if (threadIdx.x == 0) {
-                double s0 = 0.0, s1 = 0.0;
+                double s0 = 0.0, s1 = 0.0, m2 = 0.0, s3 = 0.0;
                 for (int q = 0; q < TILE2_THREADS / 64; ++q) {
                     s0 += red[0][q];
                     s1 += red[1][q];
+                    m2 = fmax(m2, red[2][q]);
+                    s3 += red[3][q];
                 }
-                part[2 * tid] = s0;
-                part[2 * tid + 1] = s1;
+                if (kEnergy) {
+                    part[2 * tid] = s0;
+                    part[2 * tid + 1] = s1;
+                }
+                if (kKick) {
+                    kick.part_kick[2 * tid] = m2;
+                    kick.part_kick[2 * tid + 1] = s3;
+                }
             }
         }
+        tid = nxt;
     }
 }
 
@@ -273,8 +368,16 @@ hipError_t launch_rho_lds(misa_lattice *h) {
     return hipGetLastError();
 }
 
-hipError_t launch_force_lds(misa_lattice *h, bool energy) {
-    const Geom &g = h->g;
+template <bool kEnergy, bool kKick>
+static void force_lds_variant(misa_lattice *h, const Tables<float> &T, const KickArgs &kick) {
+    auto kern = h->lds32.node_cut ? k_force_lds<kEnergy, true, kKick> : k_force_lds<kEnergy, false, kKick>;
+    hipLaunchKernelGGL(kern, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
+                       (const float *)h->S.fp, (const float *)h->S.rho, (float *)h->S.fx, (float *)h->S.fy,
+                       (float *)h->S.fz, h->st32p, h->K, h->lds32.force, h->lds32.k0, h->lds32.nwin, T, h->g,
+                       h->sc.part, kick);
+}
+
+hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick) {
     Tables<float> T;
     T.f = h->t32.f;
     T.force = h->t32.force;
@@ -282,13 +385,11 @@ hipError_t launch_force_lds(misa_lattice *h, bool energy) {
     T.emb = h->t32.emb;
     T.fm = h->t32.fm;
     T.em = h->t32.em;
-    const bool nc = h->lds32.node_cut;
-    auto kern = energy ? (nc ? k_force_lds<true, true> : k_force_lds<true, false>)
-                       : (nc ? k_force_lds<false, true> : k_force_lds<false, false>);
-    hipLaunchKernelGGL(kern, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
-                       (const float *)h->S.fp, (const float *)h->S.rho, (float *)h->S.fx, (float *)h->S.fy,
-                       (float *)h->S.fz, h->st32p, h->K, h->lds32.force, h->lds32.k0, h->lds32.nwin, T, g,
-                       h->sc.part);
+    KickArgs K{h->S.vx, h->S.vy, h->S.vz, h->sc.mark, h->sc.scal, ACC_UNIT / h->mass, h->sc.part_kick};
+    if (energy && kick) force_lds_variant<true, true>(h, T, K);
+    else if (energy) force_lds_variant<true, false>(h, T, K);
+    else if (kick) force_lds_variant<false, true>(h, T, K);
+    else force_lds_variant<false, false>(h, T, K);
     return hipGetLastError();
 }
 

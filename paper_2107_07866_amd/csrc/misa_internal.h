@@ -159,8 +159,10 @@ struct Scratch {
     int32_t hmask;
     // lattice atoms near run-away atoms
     uint32_t *mark;       // 1 bit per site
-    int32_t *affected;
+    int32_t *affected;    // capacity: next power of two >= affected_cap (room to sort in place)
     int64_t affected_cap;
+    double *aff_v2;       // |v|^2 of each affected lattice atom after the fused final kick
+    double *part_kick;    // per-tile {max |v|^2, sum |v|^2} of the fused final kick
 };
 
 template <typename Real>
@@ -233,14 +235,15 @@ namespace misa {
 // ----------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).  All enqueue on h->stream.
 hipError_t launch_rho(misa_lattice *h);
-hipError_t launch_force(misa_lattice *h, bool energy);
+hipError_t launch_force(misa_lattice *h, bool energy, bool kick);
 bool lds_path(const misa_lattice *h);                  // persistent float32 kernels usable
 hipError_t launch_rho_lds(misa_lattice *h);
-hipError_t launch_force_lds(misa_lattice *h, bool energy);
+hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick);  // kick: fused second half-kick
+bool fused_kick(const misa_lattice *h);               // the step fuses the final kick into the force pass
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev);
 hipError_t launch_runaway_build(misa_lattice *h);      // keys, sort, hash insert
 hipError_t launch_runaway_rho(misa_lattice *h);        // run-away rho + affected-site fixup
-hipError_t launch_runaway_force(misa_lattice *h, bool energy);
+hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick);
 hipError_t launch_runaway_clear(misa_lattice *h);      // hash and marks back to empty
 hipError_t launch_kick_drift(misa_lattice *h);         // lattice + run-aways, leavers appended
 hipError_t launch_rehash(misa_lattice *h);             // sort leavers, claims, settle, compact

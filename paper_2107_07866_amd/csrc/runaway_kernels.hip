@@ -578,10 +578,13 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(
     }
 }
 
+// kick != 0: the force pass already applied the second half-kick with the lattice
+// part of F; add the run-away part's kick here and record |v|^2 for the step statistics.
 template <typename Real>
-__global__ void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T) {
+__global__ void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T, int kick, double kf) {
     int na = sc.cnt->n_affected;
     na = na < sc.affected_cap ? na : (int)sc.affected_cap;
+    const double hk = kick ? 0.5 * sc.scal[0] * kf : 0.0;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < na; q += gridDim.x * blockDim.x) {
         const int64_t s = sc.affected[q];
         const int p = s >= g.ncell ? 1 : 0;
@@ -622,8 +625,55 @@ __global__ void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T) 
         fxa[s] = (Real)((double)fxa[s] + ax);
         fya[s] = (Real)((double)fya[s] + ay);
         fza[s] = (Real)((double)fza[s] + az);
+        if (kick) {
+            const double vx = S.vx[s] + hk * ax, vy = S.vy[s] + hk * ay, vz = S.vz[s] + hk * az;
+            S.vx[s] = vx;
+            S.vy[s] = vy;
+            S.vz[s] = vz;
+            sc.aff_v2[q] = vx * vx + vy * vy + vz * vz;
+        }
         sc.mark[s >> 5] = 0u;  // every bit of a touched word belongs to an affected site
     }
+}
+
+// Ascending sort of the affected list (site indices), so every later pass over it and
+// the sums taken along it run in a fixed order.  Single work-group; sorts in place in
+// global memory (capacity is a power of two) when the list exceeds the LDS buffer.
+constexpr int SORT32_LDS_MAX = 8192;
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_affected(Scratch sc) {
+    __shared__ int32_t sh[SORT32_LDS_MAX];
+    int n = sc.cnt->n_affected;
+    n = n < sc.affected_cap ? n : (int)sc.affected_cap;
+    if (n <= 1) return;
+    int P = 1;
+    while (P < n) P <<= 1;
+    const bool in_lds = P <= SORT32_LDS_MAX;
+    int32_t *A = in_lds ? sh : sc.affected;
+    for (int i = threadIdx.x; i < P; i += SORT_THREADS) {
+        if (in_lds)
+            sh[i] = i < n ? sc.affected[i] : INT32_MAX;
+        else if (i >= n)
+            sc.affected[i] = INT32_MAX;
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += SORT_THREADS) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const int32_t a = A[i], b = A[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        A[i] = b;
+                        A[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (in_lds)
+        for (int i = threadIdx.x; i < n; i += SORT_THREADS) sc.affected[i] = sh[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -673,6 +723,7 @@ hipError_t launch_runaway_rho(misa_lattice *h) {
     hipStream_t st = h->stream;
     hipLaunchKernelGGL(k_runaway_rho, dim3(SMALL_GRID), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, h->S, h->sc,
                        h->g, t64_of(h));
+    hipLaunchKernelGGL(k_sort_affected, dim3(1), dim3(SORT_THREADS), 0, st, h->sc);
     if (h->precision == MISA_FP32)
         hipLaunchKernelGGL(k_affected_rho<float>, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g, t64_of(h),
                            t32_of(h));
@@ -682,16 +733,17 @@ hipError_t launch_runaway_rho(misa_lattice *h) {
     return hipGetLastError();
 }
 
-hipError_t launch_runaway_force(misa_lattice *h, bool energy) {
+hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick) {
     hipStream_t st = h->stream;
     hipLaunchKernelGGL(k_runaway_force, dim3(SMALL_GRID), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, h->S, h->sc,
                        h->g, t64_of(h), h->precision == MISA_FP32 ? 1 : 0, energy ? 1 : 0);
+    const double kf = ACC_UNIT / h->mass;
     if (h->precision == MISA_FP32)
         hipLaunchKernelGGL(k_affected_force<float>, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g,
-                           t64_of(h));
+                           t64_of(h), kick ? 1 : 0, kf);
     else
         hipLaunchKernelGGL(k_affected_force<double>, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g,
-                           t64_of(h));
+                           t64_of(h), kick ? 1 : 0, kf);
     return hipGetLastError();
 }
 
