@@ -462,6 +462,11 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     const int64_t H = next_pow2(2 * rcap);
     sc.hmask = (int32_t)(H - 1);
     sc.affected_cap = std::min<int64_t>(g.nsites, 128 * rcap);
+    {
+        const int64_t per_blk = (int64_t)MARK_THREADS * MARK_WORDS;
+        sc.mark_nblk = (int32_t)(((g.nsites + 31) / 32 + per_blk - 1) / per_blk);
+        sc.mark_nwords = sc.mark_nblk * per_blk;
+    }
     auto bail = [&](hipError_t e) {
         std::string m = std::string("device allocation failed: ") + hipGetErrorString(e);
         misa_destroy_lattice(h);
@@ -492,8 +497,10 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(sc.hslot, rcap);
     ALLOC(sc.hkey, H);
     ALLOC(sc.hval, H);
-    ALLOC(sc.mark, (g.nsites + 31) / 32);
-    ALLOC(sc.affected, next_pow2(sc.affected_cap));
+    ALLOC(sc.mark, sc.mark_nwords);
+    ALLOC(sc.mark_blk, sc.mark_nblk);
+    ALLOC(sc.mark_off, sc.mark_nblk);
+    ALLOC(sc.affected, sc.affected_cap);
     ALLOC(sc.aff_v2, sc.affected_cap);
     ALLOC(sc.part_kick, 2 * (int64_t)std::max(g.ntiles2_pad, 8));
 #undef ALLOC
@@ -502,7 +509,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
         (e = hipMemcpy(h->st32p, s32p.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemset(sc.cnt, 0, sizeof(Counters))) || (e = hipMemset(sc.scal, 0, 8 * sizeof(double))) ||
         (e = hipMemset(sc.hkey, 0xff, sizeof(int32_t) * (size_t)H)) ||
-        (e = hipMemset(sc.mark, 0, sizeof(uint32_t) * (size_t)((g.nsites + 31) / 32))) ||
+        (e = hipMemset(sc.mark, 0, sizeof(uint32_t) * (size_t)sc.mark_nwords)) ||
         (e = hipDeviceSynchronize())) {
         std::string m = std::string("device initialisation failed: ") + hipGetErrorString(e);
         misa_destroy_lattice(h);
@@ -522,7 +529,7 @@ int misa_destroy_lattice(misa_lattice *h) {
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
                     h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,
-                    h->sc.affected, h->sc.aff_v2, h->sc.part_kick, h->staging};
+                    h->sc.mark_blk, h->sc.mark_off, h->sc.affected, h->sc.aff_v2, h->sc.part_kick, h->staging};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : h->timed) h->event_pool.push_back({t.start, t.stop});
@@ -688,7 +695,7 @@ int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n,
     c.n_run = (int32_t)R;
     HIPCHK(h, hipMemcpy(h->sc.cnt, &c, sizeof(c), hipMemcpyHostToDevice));
     HIPCHK(h, hipMemset(h->sc.scal, 0, 8 * sizeof(double)));
-    HIPCHK(h, hipMemset(h->sc.mark, 0, sizeof(uint32_t) * (size_t)((g.nsites + 31) / 32)));
+    HIPCHK(h, hipMemset(h->sc.mark, 0, sizeof(uint32_t) * (size_t)h->sc.mark_nwords));
     HIPCHK(h, hipMemset(h->sc.hkey, 0xff, sizeof(int32_t) * (size_t)(h->sc.hmask + 1)));
     HIPCHK(h, hipDeviceSynchronize());
     h->n_atoms = n;

@@ -47,9 +47,11 @@ constexpr int32_t VACANT_ID = 0x7fffffff;      // atom id stored in an empty slo
 
 // run-away / hash scratch
 constexpr int SORT_THREADS = 1024;
-constexpr int SORT_LDS_MAX = 4096;             // single-block LDS bitonic sort up to this many keys
+constexpr int SORT_LDS_MAX = 16384;            // single-block LDS bitonic sort up to this many keys (128 KB)
 constexpr int RUNAWAY_WAVES_PER_BLOCK = 4;     // one wave per run-away atom
 constexpr int SMALL_GRID = 1024;               // blocks of grid-stride kernels over run-away lists
+constexpr int MARK_THREADS = 256;              // lanes per block of the mark-bitmap compaction
+constexpr int MARK_WORDS = 8;                  // bitmap words per lane (two 16-byte loads)
 
 // 1 eV/(Angstrom amu) in Angstrom/fs^2 (exact SI e, CODATA-2018 amu)
 constexpr double ACC_UNIT = (1.602176634e-19 / 1.66053906660e-27) * 1e-10;
@@ -158,8 +160,12 @@ struct Scratch {
     int32_t *hkey, *hval, *hslot;
     int32_t hmask;
     // lattice atoms near run-away atoms
-    uint32_t *mark;       // 1 bit per site
-    int32_t *affected;    // capacity: next power of two >= affected_cap (room to sort in place)
+    uint32_t *mark;       // 1 bit per site, padded with zero words to mark_nblk blocks
+    int64_t mark_nwords;  // padded length: mark_nblk * MARK_THREADS * MARK_WORDS
+    int32_t mark_nblk;
+    int32_t *mark_blk;    // marked sites per compaction block
+    int64_t *mark_off;    // exclusive prefix of mark_blk
+    int32_t *affected;    // ascending site indices, capacity affected_cap
     int64_t affected_cap;
     double *aff_v2;       // |v|^2 of each affected lattice atom after the fused final kick
     double *part_kick;    // per-tile {max |v|^2, sum |v|^2} of the fused final kick

@@ -385,32 +385,69 @@ __global__ void k_hash_clear(Scratch sc) {
     if (blockIdx.x == 0 && threadIdx.x == 0) sc.cnt->n_affected = 0;
 }
 
-// Run-away atoms (list positions, ascending) closer than sqrt(cut2) to position x,
-// found through the hash.  Calls fn(o, d, r2) with d = x_o - x (minimum image).
+// Run-away atoms in one of the (up to) 27 coarse cells around x, cell = ax + 3 (ay + 3 az);
+// cells beyond the box's distinct neighbours are empty.  fn(o) for entries first,
+// first + stride, ... of the cell's stretch of the sorted list.
 template <typename Fn>
-__device__ __forceinline__ void for_runaway_neighbours(const double x[3], int self, int lane, int step,
-                                                       double cut2, const State &S, const Scratch &sc,
-                                                       const Geom &g, Fn fn) {
-    const int n = sc.cnt->n_run;
+__device__ __forceinline__ void for_runaways_in_cell(const double x[3], int cell, int first, int stride,
+                                                     const Scratch &sc, const Geom &g, Fn fn) {
+    const int ax = cell % 3, ay = (cell / 3) % 3, az = cell / 9;
     int cx[3], cy[3], cz[3];
-    const int nxc = axis_cells(coarse_of(x[0], g.nc[0], g.inv_cs[0]), g.nc[0], cx);
-    const int nyc = axis_cells(coarse_of(x[1], g.nc[1], g.inv_cs[1]), g.nc[1], cy);
-    const int nzc = axis_cells(coarse_of(x[2], g.nc[2], g.inv_cs[2]), g.nc[2], cz);
-    for (int az = 0; az < nzc; ++az)
-        for (int ay = 0; ay < nyc; ++ay)
-            for (int ax = 0; ax < nxc; ++ax) {
-                const int32_t key = (cz[az] * g.nc[1] + cy[ay]) * g.nc[0] + cx[ax];
-                const int32_t start = hash_find(key, sc.hkey, sc.hval, sc.hmask);
-                if (start < 0) continue;
-                for (int q = start + lane; q < n && sc.skey[q] == key; q += step) {
-                    const int o = sc.sidx[q];
-                    if (o == self) continue;
-                    double d[3] = {S.r_x[o] - x[0], S.r_y[o] - x[1], S.r_z[o] - x[2]};
-                    min_image3(d, g);
-                    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                    if (r2 < cut2) fn(o, d, r2);
-                }
-            }
+    if (ax >= axis_cells(coarse_of(x[0], g.nc[0], g.inv_cs[0]), g.nc[0], cx)) return;
+    if (ay >= axis_cells(coarse_of(x[1], g.nc[1], g.inv_cs[1]), g.nc[1], cy)) return;
+    if (az >= axis_cells(coarse_of(x[2], g.nc[2], g.inv_cs[2]), g.nc[2], cz)) return;
+    const int32_t key = (cz[az] * g.nc[1] + cy[ay]) * g.nc[0] + cx[ax];
+    const int32_t start = hash_find(key, sc.hkey, sc.hval, sc.hmask);
+    if (start < 0) return;
+    const int n = sc.cnt->n_run;
+    for (int q = start + first; q < n && sc.skey[q] == key; q += stride) fn(sc.sidx[q]);
+}
+
+// Run-away atoms other than self closer than sqrt(cut2) to x, searched by a whole wave:
+// lanes k and k + 32 share coarse cell k (k < 27) and take alternate entries of it.
+// Calls fn(o, d, r2) with d = x_o - x (minimum image).
+template <typename Fn>
+__device__ __forceinline__ void for_runaway_neighbours(const double x[3], int self, int lane, double cut2,
+                                                       const State &S, const Scratch &sc, const Geom &g,
+                                                       Fn fn) {
+    const int cell = lane & 31;
+    if (cell >= 27) return;
+    for_runaways_in_cell(x, cell, lane >> 5, 2, sc, g, [&](int o) {
+        if (o == self) return;
+        double d[3] = {S.r_x[o] - x[0], S.r_y[o] - x[1], S.r_z[o] - x[2]};
+        min_image3(d, g);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 < cut2) fn(o, d, r2);
+    });
+}
+
+// Affected lattice atoms are handled by teams of 32 lanes, lane k scanning coarse cell k
+// (lanes 27..31 idle), so one atom's 27 cell look-ups run side by side, not in series.
+constexpr int AFF_TEAM = 32;
+constexpr int AFF_THREADS = 256;
+constexpr int AFF_GRID = 2048;
+
+__device__ __forceinline__ double team_sum32(double v) {
+    // fixed butterfly: the same lanes meet in the same order on every call
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, AFF_TEAM);
+    return v;
+}
+
+// Separation x_j - x_o of lattice atom j (cell cj, parity p, displacement u) from
+// run-away o, taken from the lattice window the run-away itself uses, so both sides see
+// the same pair in the same arithmetic.  False if j lies outside that window.
+__device__ __forceinline__ bool affected_pair(const double xo[3], const int cj[3], int p, const double u[3],
+                                              const Geom &g, double d[3], double &r2) {
+    int cc[3];
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    for (int k = 0; k < 3; ++k) {
+        const int lo = window_lo(xo[k] * g.inv_a, g.reach);
+        cc[k] = lo + wrap_index(cj[k] - lo, nn[k]);
+        if (cc[k] - lo >= g.win) return false;
+    }
+    lat_sep(cc[0], cc[1], cc[2], p, u, xo, g.a, d);
+    r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    return r2 < g.rc2;
 }
 
 // ---------------------------------------------------------------------------
@@ -445,18 +482,10 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(St
             const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             if (r2 < g.rc2) {
                 acc += f_val(sqrt(r2), T);
-                const uint32_t bit = 1u << (s & 31);
-                const uint32_t old = atomicOr(&sc.mark[s >> 5], bit);
-                if (!(old & bit)) {
-                    const int pos = atomicAdd(&sc.cnt->n_affected, 1);
-                    if (pos < sc.affected_cap)
-                        sc.affected[pos] = (int32_t)s;
-                    else
-                        atomicExch(&sc.cnt->overflow, 1);
-                }
+                atomicOr(&sc.mark[s >> 5], 1u << (s & 31));  // listed in site order by k_mark_emit
             }
         }
-        for_runaway_neighbours(x, r, lane, 64, g.rc2, S, sc, g,
+        for_runaway_neighbours(x, r, lane, g.rc2, S, sc, g,
                                [&](int, const double *, double r2) { acc += f_val(sqrt(r2), T); });
         acc = wave_sum64(acc);
         if (lane == 0) {
@@ -473,43 +502,39 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(St
 
 // Lattice atoms within rc of run-aways: add the run-away terms to rho, refresh F'.
 template <typename Real>
-__global__ void k_affected_rho(State S, Scratch sc, Geom g, Tables<double> T, Tables<Real> TL) {
+__global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch sc, Geom g, Tables<double> T,
+                                                              Tables<Real> TL) {
     int na = sc.cnt->n_affected;
     na = na < sc.affected_cap ? na : (int)sc.affected_cap;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < na; q += gridDim.x * blockDim.x) {
+    const int cell = threadIdx.x & (AFF_TEAM - 1);
+    const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
+    for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < na; q += nteams) {
         const int64_t s = sc.affected[q];
         const int p = s >= g.ncell ? 1 : 0;
         const int64_t c = s - p * g.ncell;
-        const int cxj = (int)(c % g.nx), cyj = (int)((c / g.nx) % g.ny), czj = (int)(c / ((int64_t)g.nx * g.ny));
+        const int cj[3] = {(int)(c % g.nx), (int)((c / g.nx) % g.ny), (int)(c / ((int64_t)g.nx * g.ny))};
         const double u[3] = {S.ux[s], S.uy[s], S.uz[s]};
         double xj[3];
-        site_pos(cxj, cyj, czj, p, g.a, xj);
+        site_pos(cj[0], cj[1], cj[2], p, g.a, xj);
         for (int k = 0; k < 3; ++k) xj[k] = wrap_coord(xj[k] + u[k], g.L[k]);
         double acc = 0.0;
-        // candidates through the hash (generous test), exact pair test as the run-away saw it
-        for_runaway_neighbours(xj, -1, 0, 1, g.pre2, S, sc, g, [&](int o, const double *, double) {
-            const double x[3] = {S.r_x[o], S.r_y[o], S.r_z[o]};
-            int cc[3];
-            const int cj[3] = {cxj, cyj, czj};
-            const int nn[3] = {g.nx, g.ny, g.nz};
-            for (int k = 0; k < 3; ++k) {
-                const int lo = window_lo(x[k] * g.inv_a, g.reach);
-                cc[k] = lo + wrap_index(cj[k] - lo, nn[k]);
-                if (cc[k] - lo >= g.win) return;
-            }
-            double d[3];
-            lat_sep(cc[0], cc[1], cc[2], p, u, x, g.a, d);
-            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            if (r2 < g.rc2) acc += f_val(sqrt(r2), T);
-        });
-        Real *rho = (Real *)S.rho;
-        Real *fp = (Real *)S.fp;
-        const Real rj = rho[s] + (Real)acc;
-        rho[s] = rj;
-        Real Fv;
-        bool beyond = false;
-        fp[s] = emb_any<Real>(rj, TL.emb, TL.em, Fv, beyond);
-        if (beyond) atomicAdd(&sc.cnt->range_viol, 1u);
+        if (cell < 27)
+            for_runaways_in_cell(xj, cell, 0, 1, sc, g, [&](int o) {
+                const double xo[3] = {S.r_x[o], S.r_y[o], S.r_z[o]};
+                double d[3], r2;
+                if (affected_pair(xo, cj, p, u, g, d, r2)) acc += f_val(sqrt(r2), T);
+            });
+        acc = team_sum32(acc);
+        if (cell == 0) {
+            Real *rho = (Real *)S.rho;
+            Real *fp = (Real *)S.fp;
+            const Real rj = rho[s] + (Real)acc;
+            rho[s] = rj;
+            Real Fv;
+            bool beyond = false;
+            fp[s] = emb_any<Real>(rj, TL.emb, TL.em, Fv, beyond);
+            if (beyond) atomicAdd(&sc.cnt->range_viol, 1u);
+        }
     }
 }
 
@@ -555,7 +580,7 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(
                 ep += phi;  // lattice partner has no other record of this pair's energy
             }
         }
-        for_runaway_neighbours(x, r, lane, 64, g.rc2, S, sc, g, [&](int o, const double *d, double r2) {
+        for_runaway_neighbours(x, r, lane, g.rc2, S, sc, g, [&](int o, const double *d, double r2) {
             const double rr = sqrt(r2);
             double df, dphi, phi;
             fp_phi(rr, T, df, dphi, phi);
@@ -581,38 +606,29 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(
 // kick != 0: the force pass already applied the second half-kick with the lattice
 // part of F; add the run-away part's kick here and record |v|^2 for the step statistics.
 template <typename Real>
-__global__ void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T, int kick, double kf) {
+__global__ __launch_bounds__(AFF_THREADS) void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T,
+                                                                int kick, double kf) {
     int na = sc.cnt->n_affected;
     na = na < sc.affected_cap ? na : (int)sc.affected_cap;
     const double hk = kick ? 0.5 * sc.scal[0] * kf : 0.0;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < na; q += gridDim.x * blockDim.x) {
+    const int cell = threadIdx.x & (AFF_TEAM - 1);
+    const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
+    for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < na; q += nteams) {
         const int64_t s = sc.affected[q];
         const int p = s >= g.ncell ? 1 : 0;
         const int64_t c = s - p * g.ncell;
-        const int cxj = (int)(c % g.nx), cyj = (int)((c / g.nx) % g.ny), czj = (int)(c / ((int64_t)g.nx * g.ny));
+        const int cj[3] = {(int)(c % g.nx), (int)((c / g.nx) % g.ny), (int)(c / ((int64_t)g.nx * g.ny))};
         const double u[3] = {S.ux[s], S.uy[s], S.uz[s]};
-        Real *fxa = (Real *)S.fx;
-        Real *fya = (Real *)S.fy;
-        Real *fza = (Real *)S.fz;
         const double fpj = (double)((const Real *)S.fp)[s];
         double xj[3];
-        site_pos(cxj, cyj, czj, p, g.a, xj);
+        site_pos(cj[0], cj[1], cj[2], p, g.a, xj);
         for (int k = 0; k < 3; ++k) xj[k] = wrap_coord(xj[k] + u[k], g.L[k]);
         double ax = 0.0, ay = 0.0, az = 0.0;
-        for_runaway_neighbours(xj, -1, 0, 1, g.pre2, S, sc, g, [&](int o, const double *, double) {
-            const double x[3] = {S.r_x[o], S.r_y[o], S.r_z[o]};
-            int cc[3];
-            const int cj[3] = {cxj, cyj, czj};
-            const int nn[3] = {g.nx, g.ny, g.nz};
-            for (int k = 0; k < 3; ++k) {
-                const int lo = window_lo(x[k] * g.inv_a, g.reach);
-                cc[k] = lo + wrap_index(cj[k] - lo, nn[k]);
-                if (cc[k] - lo >= g.win) return;
-            }
-            double d[3];  // x_j - x_o
-            lat_sep(cc[0], cc[1], cc[2], p, u, x, g.a, d);
-            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            if (r2 < g.rc2) {
+        if (cell < 27)
+            for_runaways_in_cell(xj, cell, 0, 1, sc, g, [&](int o) {
+                const double xo[3] = {S.r_x[o], S.r_y[o], S.r_z[o]};
+                double d[3], r2;  // d = x_j - x_o
+                if (!affected_pair(xo, cj, p, u, g, d, r2)) return;
                 const double rr = sqrt(r2);
                 double df, dphi, phi;
                 fp_phi(rr, T, df, dphi, phi);
@@ -620,60 +636,131 @@ __global__ void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T, 
                 ax -= sc_ * d[0];  // separation from j to the run-away is -d
                 ay -= sc_ * d[1];
                 az -= sc_ * d[2];
+            });
+        ax = team_sum32(ax);
+        ay = team_sum32(ay);
+        az = team_sum32(az);
+        if (cell == 0) {
+            Real *fxa = (Real *)S.fx;
+            Real *fya = (Real *)S.fy;
+            Real *fza = (Real *)S.fz;
+            fxa[s] = (Real)((double)fxa[s] + ax);
+            fya[s] = (Real)((double)fya[s] + ay);
+            fza[s] = (Real)((double)fza[s] + az);
+            if (kick) {
+                const double vx = S.vx[s] + hk * ax, vy = S.vy[s] + hk * ay, vz = S.vz[s] + hk * az;
+                S.vx[s] = vx;
+                S.vy[s] = vy;
+                S.vz[s] = vz;
+                sc.aff_v2[q] = vx * vx + vy * vy + vz * vz;
             }
-        });
-        fxa[s] = (Real)((double)fxa[s] + ax);
-        fya[s] = (Real)((double)fya[s] + ay);
-        fza[s] = (Real)((double)fza[s] + az);
-        if (kick) {
-            const double vx = S.vx[s] + hk * ax, vy = S.vy[s] + hk * ay, vz = S.vz[s] + hk * az;
-            S.vx[s] = vx;
-            S.vy[s] = vy;
-            S.vz[s] = vz;
-            sc.aff_v2[q] = vx * vx + vy * vy + vz * vz;
+            sc.mark[s >> 5] = 0u;  // every bit of a touched word belongs to an affected site
         }
-        sc.mark[s >> 5] = 0u;  // every bit of a touched word belongs to an affected site
     }
 }
 
-// Ascending sort of the affected list (site indices), so every later pass over it and
-// the sums taken along it run in a fixed order.  Single work-group; sorts in place in
-// global memory (capacity is a power of two) when the list exceeds the LDS buffer.
-constexpr int SORT32_LDS_MAX = 8192;
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_affected(Scratch sc) {
-    __shared__ int32_t sh[SORT32_LDS_MAX];
-    int n = sc.cnt->n_affected;
-    n = n < sc.affected_cap ? n : (int)sc.affected_cap;
-    if (n <= 1) return;
-    int P = 1;
-    while (P < n) P <<= 1;
-    const bool in_lds = P <= SORT32_LDS_MAX;
-    int32_t *A = in_lds ? sh : sc.affected;
-    for (int i = threadIdx.x; i < P; i += SORT_THREADS) {
-        if (in_lds)
-            sh[i] = i < n ? sc.affected[i] : INT32_MAX;
-        else if (i >= n)
-            sc.affected[i] = INT32_MAX;
+// ---------------------------------------------------------------------------
+// The affected list: every lattice atom a run-away atom paired with, in ascending
+// site order, compacted from the mark bitmap (count, scan, emit), so every pass
+// over it and every sum taken along it runs in a fixed order.
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *sh_waves, int &total) {
+    // 256 lanes = 4 waves
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int n = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += n;
     }
+    if (lane == 63) sh_waves[w] = incl;
     __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += SORT_THREADS) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const int32_t a = A[i], b = A[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) {
-                        A[i] = b;
-                        A[ixj] = a;
-                    }
-                }
-            }
-            __syncthreads();
+    int off = 0;
+    total = 0;
+    for (int k = 0; k < MARK_THREADS / 64; ++k) {
+        if (k < w) off += sh_waves[k];
+        total += sh_waves[k];
+    }
+    return off + incl - v;
+}
+
+// The bitmap is padded with zero words to whole blocks, so no lane tests bounds.
+__device__ __forceinline__ void load_mark_words(const Scratch &sc, uint32_t (&m)[MARK_WORDS], int &c) {
+    const int64_t w0 = ((int64_t)blockIdx.x * MARK_THREADS + threadIdx.x) * MARK_WORDS;
+    const uint4 *p = reinterpret_cast<const uint4 *>(sc.mark + w0);
+    const uint4 a = p[0], b = p[1];
+    m[0] = a.x, m[1] = a.y, m[2] = a.z, m[3] = a.w;
+    m[4] = b.x, m[5] = b.y, m[6] = b.z, m[7] = b.w;
+    c = 0;
+#pragma unroll
+    for (int k = 0; k < MARK_WORDS; ++k) c += __popc(m[k]);
+}
+
+__global__ __launch_bounds__(MARK_THREADS) void k_mark_count(Scratch sc) {
+    __shared__ int shw[MARK_THREADS / 64];
+    if (sc.cnt->n_run == 0) return;  // nothing marked
+    uint32_t m[MARK_WORDS];
+    int c, total;
+    load_mark_words(sc, m, c);
+    block_exclusive_scan(c, shw, total);
+    if (threadIdx.x == 0) sc.mark_blk[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_mark_scan(Scratch sc, int nblk) {
+    __shared__ int64_t base_sh;
+    __shared__ int wsum[1024 / 64];
+    if (sc.cnt->n_run == 0) {
+        if (threadIdx.x == 0) sc.cnt->n_affected = 0;
+        return;
+    }
+    if (threadIdx.x == 0) base_sh = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < nblk; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nblk ? sc.mark_blk[i] : 0;
+        int incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int n = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += n;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int64_t off = base_sh;
+        int64_t tot = 0;
+        for (int k = 0; k < 1024 / 64; ++k) {
+            if (k < w) off += wsum[k];
+            tot += wsum[k];
+        }
+        if (i < nblk) sc.mark_off[i] = off + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0) base_sh += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t n = base_sh;
+        if (n > sc.affected_cap) sc.cnt->overflow = 1;
+        sc.cnt->n_affected = (int32_t)(n < sc.affected_cap ? n : sc.affected_cap);
+    }
+}
+
+__global__ __launch_bounds__(MARK_THREADS) void k_mark_emit(Scratch sc) {
+    __shared__ int shw[MARK_THREADS / 64];
+    if (sc.cnt->n_run == 0) return;
+    uint32_t m[MARK_WORDS];
+    int c, total;
+    load_mark_words(sc, m, c);
+    int64_t pos = sc.mark_off[blockIdx.x] + block_exclusive_scan(c, shw, total);
+    if (c == 0) return;
+    const int64_t w0 = ((int64_t)blockIdx.x * MARK_THREADS + threadIdx.x) * MARK_WORDS;
+    for (int k = 0; k < MARK_WORDS; ++k) {
+        uint32_t w = m[k];
+        while (w) {
+            const int b = __ffs(w) - 1;
+            w &= w - 1u;
+            if (pos < sc.affected_cap) sc.affected[pos] = (int32_t)((w0 + k) * 32 + b);
+            ++pos;
         }
     }
-    if (in_lds)
-        for (int i = threadIdx.x; i < n; i += SORT_THREADS) sc.affected[i] = sh[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -723,12 +810,14 @@ hipError_t launch_runaway_rho(misa_lattice *h) {
     hipStream_t st = h->stream;
     hipLaunchKernelGGL(k_runaway_rho, dim3(SMALL_GRID), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, h->S, h->sc,
                        h->g, t64_of(h));
-    hipLaunchKernelGGL(k_sort_affected, dim3(1), dim3(SORT_THREADS), 0, st, h->sc);
+    hipLaunchKernelGGL(k_mark_count, dim3(h->sc.mark_nblk), dim3(MARK_THREADS), 0, st, h->sc);
+    hipLaunchKernelGGL(k_mark_scan, dim3(1), dim3(1024), 0, st, h->sc, h->sc.mark_nblk);
+    hipLaunchKernelGGL(k_mark_emit, dim3(h->sc.mark_nblk), dim3(MARK_THREADS), 0, st, h->sc);
     if (h->precision == MISA_FP32)
-        hipLaunchKernelGGL(k_affected_rho<float>, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g, t64_of(h),
+        hipLaunchKernelGGL(k_affected_rho<float>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g, t64_of(h),
                            t32_of(h));
     else
-        hipLaunchKernelGGL(k_affected_rho<double>, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g,
+        hipLaunchKernelGGL(k_affected_rho<double>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g,
                            t64_of(h), t64_of(h));
     return hipGetLastError();
 }
@@ -739,10 +828,10 @@ hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick) {
                        h->g, t64_of(h), h->precision == MISA_FP32 ? 1 : 0, energy ? 1 : 0);
     const double kf = ACC_UNIT / h->mass;
     if (h->precision == MISA_FP32)
-        hipLaunchKernelGGL(k_affected_force<float>, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g,
+        hipLaunchKernelGGL(k_affected_force<float>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g,
                            t64_of(h), kick ? 1 : 0, kf);
     else
-        hipLaunchKernelGGL(k_affected_force<double>, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g,
+        hipLaunchKernelGGL(k_affected_force<double>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g,
                            t64_of(h), kick ? 1 : 0, kf);
     return hipGetLastError();
 }
