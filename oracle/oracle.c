@@ -26,6 +26,9 @@
  *     Verlet, with the adaptive step dt = min(dt_max, dx_max / max_i |v_i|)
  *     evaluated at the start of each step (the paper names adaptive time steps
  *     as a feature of MISA-MD without giving the rule).
+ *   - The learned form: a small SiLU network per potential function in place
+ *     of its table inside the network's input range, the table outside it
+ *     (an extension beyond the paper, whose functions always come from tables).
  *   - Lattice ids of BCC sites (Sec. 3, Hash Initialization: the worked 2-D
  *     example and the 3-D index equation), the neighbour offset index
  *     (Sec. 3, Neighbor Offset Index initialization), the nearest-site hash
@@ -59,7 +62,20 @@
  * and 1 amu = 1.66053906660e-27 kg (CODATA 2018). */
 #define ORC_ACC ((1.602176634e-19 / 1.66053906660e-27) * 1e-10)
 
-enum { ORC_ANALYTIC = 0, ORC_ANALYTIC_SF = 1, ORC_TABLE = 2 };
+enum { ORC_ANALYTIC = 0, ORC_ANALYTIC_SF = 1, ORC_TABLE = 2, ORC_MLP = 3 };
+
+/* Width of the hidden layers of the surrogate networks. */
+#define ORC_MLP_H 32
+
+/* A surrogate network for one potential function (the learned form): inputs in
+ * [x_lo, x_hi] map to t = (x - c) s with c = (x_lo + x_hi) / 2, s = 2 / (x_hi - x_lo);
+ * two SiLU layers of ORC_MLP_H units and a linear output y give
+ * g(x) = y_shift + y_scale y(t).  p holds W1[H], b1[H], W2[H][H] (row = output
+ * unit), b2[H], w3[H], b3 in that order. */
+typedef struct {
+    double x_lo, x_hi, y_shift, y_scale;
+    const double *p;
+} orc_mlp;
 
 /* One tabulated function: n samples y_k at x_k = x0 + k h, plus node slopes m
  * (in units of the sample spacing) filled by orc_spline_slopes. */
@@ -71,7 +87,7 @@ typedef struct {
 } orc_table;
 
 typedef struct {
-    int32_t mode;       /* ORC_ANALYTIC, ORC_ANALYTIC_SF or ORC_TABLE */
+    int32_t mode;       /* ORC_ANALYTIC, ORC_ANALYTIC_SF, ORC_TABLE or ORC_MLP */
     int32_t pad_;
     double rc;          /* cut-off radius */
     /* analytic form: f(r) = exp(-f_beta (r/f_re - 1));
@@ -79,6 +95,8 @@ typedef struct {
        F(rho) = -emb_a sqrt(rho) */
     double f_beta, f_re, m_d, m_alpha, m_r0, emb_a;
     orc_table f, phi, emb;
+    /* ORC_MLP: the networks inside their ranges, the tables above outside them */
+    orc_mlp mf, mphi, memb;
 } orc_potential;
 
 /* ------------------------------------------------------------------ */
@@ -149,10 +167,46 @@ static void an_phi(const orc_potential *P, double r, double *v, double *d)
     *d = P->m_d * (-2.0 * P->m_alpha * e1 + 2.0 * P->m_alpha * e2);
 }
 
+/* Value and d/dx of a surrogate network, straight from its definition. */
+void orc_mlp_eval(const orc_mlp *M, double x, double *v, double *d)
+{
+    const int H = ORC_MLP_H;
+    const double *W1 = M->p, *b1 = W1 + H, *W2 = b1 + H, *b2 = W2 + H * H, *w3 = b2 + H;
+    const double b3 = w3[H];
+    const double c = 0.5 * (M->x_lo + M->x_hi), s = 2.0 / (M->x_hi - M->x_lo);
+    const double t = (x - c) * s;
+    double h1[ORC_MLP_H], dh1[ORC_MLP_H];   /* layer-1 outputs and their d/dt */
+    for (int k = 0; k < H; ++k) {
+        double z = W1[k] * t + b1[k];
+        double sg = 1.0 / (1.0 + exp(-z));
+        h1[k] = z * sg;
+        dh1[k] = (sg + z * sg * (1.0 - sg)) * W1[k];
+    }
+    double y = b3, dy = 0.0;
+    for (int n = 0; n < H; ++n) {
+        double z = b2[n], dz = 0.0;
+        for (int k = 0; k < H; ++k) {
+            z += W2[n * H + k] * h1[k];
+            dz += W2[n * H + k] * dh1[k];
+        }
+        double sg = 1.0 / (1.0 + exp(-z));
+        y += w3[n] * z * sg;
+        dy += w3[n] * (sg + z * sg * (1.0 - sg)) * dz;
+    }
+    *v = M->y_shift + M->y_scale * y;
+    *d = M->y_scale * s * dy;
+}
+
+static int in_range(const orc_mlp *M, double x) { return x >= M->x_lo && x <= M->x_hi; }
+
 /* electron density contribution f(r) and f'(r) */
 void orc_pot_f(const orc_potential *P, double r, double *v, double *d)
 {
-    if (P->mode == ORC_TABLE) {
+    if (P->mode == ORC_MLP && in_range(&P->mf, r)) {
+        orc_mlp_eval(&P->mf, r, v, d);
+        return;
+    }
+    if (P->mode == ORC_TABLE || P->mode == ORC_MLP) {
         orc_spline_eval(&P->f, r, v, d);
         return;
     }
@@ -168,7 +222,11 @@ void orc_pot_f(const orc_potential *P, double r, double *v, double *d)
 /* pair potential phi(r) and phi'(r) */
 void orc_pot_phi(const orc_potential *P, double r, double *v, double *d)
 {
-    if (P->mode == ORC_TABLE) {
+    if (P->mode == ORC_MLP && in_range(&P->mphi, r)) {
+        orc_mlp_eval(&P->mphi, r, v, d);
+        return;
+    }
+    if (P->mode == ORC_TABLE || P->mode == ORC_MLP) {
         orc_spline_eval(&P->phi, r, v, d);
         return;
     }
@@ -184,7 +242,11 @@ void orc_pot_phi(const orc_potential *P, double r, double *v, double *d)
 /* embedding energy F(rho) and F'(rho); returns 1 if rho was beyond the table */
 int orc_pot_emb(const orc_potential *P, double rho, double *v, double *d)
 {
-    if (P->mode == ORC_TABLE)
+    if (P->mode == ORC_MLP && in_range(&P->memb, rho)) {
+        orc_mlp_eval(&P->memb, rho, v, d);
+        return 0;
+    }
+    if (P->mode == ORC_TABLE || P->mode == ORC_MLP)
         return orc_spline_eval(&P->emb, rho, v, d);
     if (rho <= 0.0) {
         *v = 0.0;

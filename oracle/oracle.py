@@ -11,7 +11,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-ANALYTIC, ANALYTIC_SF, TABLE = 0, 1, 2
+ANALYTIC, ANALYTIC_SF, TABLE, MLP = 0, 1, 2, 3
+MLP_H = 32
+MLP_PARAMS = MLP_H * (MLP_H + 4) + 1  # W1, b1, W2, b2, w3, b3
 
 _lib = None
 
@@ -46,11 +48,17 @@ class _Table(C.Structure):
                 ("y", C.POINTER(C.c_double)), ("m", C.POINTER(C.c_double))]
 
 
+class _Mlp(C.Structure):
+    _fields_ = [("x_lo", C.c_double), ("x_hi", C.c_double), ("y_shift", C.c_double),
+                ("y_scale", C.c_double), ("p", C.POINTER(C.c_double))]
+
+
 class _Potential(C.Structure):
     _fields_ = [("mode", C.c_int32), ("pad_", C.c_int32), ("rc", C.c_double),
                 ("f_beta", C.c_double), ("f_re", C.c_double), ("m_d", C.c_double),
                 ("m_alpha", C.c_double), ("m_r0", C.c_double), ("emb_a", C.c_double),
-                ("f", _Table), ("phi", _Table), ("emb", _Table)]
+                ("f", _Table), ("phi", _Table), ("emb", _Table),
+                ("mf", _Mlp), ("mphi", _Mlp), ("memb", _Mlp)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -64,6 +72,8 @@ def _declare(lib):
     for nm in ("orc_pot_f", "orc_pot_phi"):
         getattr(lib, nm).argtypes = [C.POINTER(_Potential), C.c_double, _dp, _dp]
     lib.orc_pot_emb.argtypes = [C.POINTER(_Potential), C.c_double, _dp, _dp]
+    lib.orc_mlp_eval.argtypes = [C.POINTER(_Mlp), C.c_double, _dp, _dp]
+    lib.orc_mlp_eval.restype = None
     lib.orc_pot_emb.restype = C.c_int
     for nm in ("orc_eam_brute", "orc_eam_cells"):
         getattr(lib, nm).argtypes = [C.POINTER(_Potential), _dp, C.c_int64, _dp, _dp, _dp, _dp, _dp, _ip]
@@ -110,13 +120,16 @@ def _f64(a, shape=None):
 
 
 class Potential:
-    """Potential for the oracle: analytic, analytic shifted-force, or splined tables.
+    """Potential for the oracle: analytic, analytic shifted-force, splined tables,
+    or surrogate networks with the tables outside their ranges.
 
     ``tables`` is {"f": (x0, h, y), "phi": (x0, h, y), "F": (x0, h, y)} of samples;
-    node slopes are computed by the oracle's own spline routine.
+    node slopes are computed by the oracle's own spline routine.  ``mlp`` (mode
+    MLP) is {"f": net, "phi": net, "F": net} with net = (x_lo, x_hi, y_shift,
+    y_scale, params[MLP_PARAMS]).
     """
 
-    def __init__(self, mode=ANALYTIC, rc=5.0, params=None, tables=None):
+    def __init__(self, mode=ANALYTIC, rc=5.0, params=None, tables=None, mlp=None):
         p = dict(f_beta=3.0, f_re=2.47, m_d=0.4, m_alpha=1.6, m_r0=2.5, emb_a=1.0)
         if params:
             p.update(params)
@@ -126,7 +139,7 @@ class Potential:
         s.mode, s.rc = mode, rc
         for k, v in p.items():
             setattr(s, k, v)
-        if mode == TABLE:
+        if mode in (TABLE, MLP):
             if tables is None:
                 raise ValueError("table mode needs tables")
             for fld, key in (("f", "f"), ("phi", "phi"), ("emb", "F")):
@@ -136,6 +149,16 @@ class Potential:
                 self._keep += [y, m]
                 t = _Table(float(x0), float(h), len(y), _d(y), _d(m))
                 setattr(s, fld, t)
+        if mode == MLP:
+            if mlp is None:
+                raise ValueError("MLP mode needs networks")
+            for fld, key in (("mf", "f"), ("mphi", "phi"), ("memb", "F")):
+                lo, hi, sh, sc, prm = mlp[key]
+                prm = _f64(prm)
+                if prm.shape != (MLP_PARAMS,):
+                    raise ValueError("network needs %d parameters" % MLP_PARAMS)
+                self._keep.append(prm)
+                setattr(s, fld, _Mlp(float(lo), float(hi), float(sh), float(sc), _d(prm)))
         self._s = s
 
     @property
@@ -162,6 +185,22 @@ class Potential:
             fn(self.ref, float(x), C.byref(a), C.byref(b))
             v[k], d[k] = a.value, b.value
         return v, d
+
+
+def mlp_eval(net, xs):
+    """Value and d/dx of one surrogate network (the C oracle's own evaluation)."""
+    lib = _load()
+    lo, hi, sh, sc, prm = net
+    prm = _f64(prm)
+    m = _Mlp(float(lo), float(hi), float(sh), float(sc), _d(prm))
+    xs = np.atleast_1d(np.asarray(xs, dtype=np.float64))
+    v = np.empty_like(xs)
+    d = np.empty_like(xs)
+    a, b = C.c_double(), C.c_double()
+    for k, x in enumerate(xs):
+        lib.orc_mlp_eval(C.byref(m), float(x), C.byref(a), C.byref(b))
+        v[k], d[k] = a.value, b.value
+    return v, d
 
 
 def spline_slopes(y):
