@@ -67,7 +67,7 @@ typedef struct misa_lattice misa_lattice;
  */
 typedef struct {
     int32_t n_cells[3];
-    int32_t pair_precision;   /* MISA_FP64 or MISA_FP32 */
+    int32_t pair_precision;   /* MISA_FP64, MISA_FP32 or MISA_MLP (below) */
     double a;                 /* lattice constant, > 0 */
     double rc;                /* cut-off radius, > 0 */
     double delta;             /* slot tolerance: an atom keeps its lattice slot while |x - site| <= delta;
@@ -215,6 +215,125 @@ int misa_get_atom_field(misa_lattice *h, int field, double *out, int where);
  * counts int64 elements; the return value is the element count (K or N) or a
  * negative error code. */
 int64_t misa_debug_export(misa_lattice *h, int what, int64_t *host_out, int64_t capacity);
+
+/* ---------------------------------------------------------------------------
+ * Learned form: surrogate networks for the potential functions.
+ *
+ * An extension beyond the paper, whose f, phi and F always come from the
+ * interpolated tables of Sec. 4.1: a handle created with pair_precision
+ * MISA_MLP evaluates f(r), phi(r) (and their derivatives) in the lattice rho and
+ * force passes, and F(rho), F'(rho) for lattice atoms, with one small network
+ * per function inside the network's input range [x_lo, x_hi], and with the
+ * spline tables outside it.  Pairs that involve a run-away atom keep the float64
+ * tables.  Storage and arithmetic are those of MISA_FP32.
+ *
+ * Network (one input x, two SiLU layers of MISA_MLP_HIDDEN units, one output):
+ *   t = (x - c) s with c = (x_lo + x_hi) / 2, s = 2 / (x_hi - x_lo)
+ *   h1 = silu(W1 t + b1), h2 = silu(W2 h1 + b2), y = w3 . h2 + b3,
+ *   g(x) = y_shift + y_scale y,  g'(x) = y_scale s dy/dt,  silu(z) = z / (1 + e^-z).
+ * params holds W1[32], b1[32], W2[32][32] (row = output unit), b2[32], w3[32], b3.
+ * Weights attached to a lattice must be exactly representable in bfloat16; the
+ * lattice kernels run the 32 x 32 layer on the matrix cores with bfloat16
+ * operands (activations split into two bfloat16 terms) and float32 accumulation.
+ */
+#define MISA_MLP 2 /* pair_precision: float32 pair arithmetic with surrogate networks for f, phi and F */
+
+#define MISA_FN_F 0   /* electron density contribution f(r) */
+#define MISA_FN_PHI 1 /* pair potential phi(r) */
+#define MISA_FN_EMB 2 /* embedding energy F(rho) */
+
+#define MISA_MLP_HIDDEN 32
+#define MISA_MLP_PARAMS 1153 /* 32 (32 + 4) + 1 */
+#define MISA_FM_SLOTS 96     /* pair slots per sampled atom in force-matching data */
+
+typedef struct {
+    double x_lo, x_hi;     /* input range served by the network (x_lo < x_hi) */
+    double y_shift, y_scale;
+    float params[MISA_MLP_PARAMS];
+    int32_t reserved;
+} misa_mlp_net;
+
+/* Attach the network for function fn to a MISA_MLP handle (copied; host memory).
+ * MISA_EINVAL if a weight is not a bfloat16 value or the range is empty;
+ * MISA_ESTATE on a handle of another pair precision.  The tables of
+ * misa_set_potential_tables remain required (fallback outside the range). */
+int misa_set_mlp(misa_lattice *h, int fn, const misa_mlp_net *net);
+
+/* The handle's float64 spline tables evaluated at n device-resident points
+ * x[n]: g(x) into y[n] and g'(x) into dy[n] (device memory; Sec. 4.1 form).
+ * These are the training targets of the surrogates. */
+int misa_table_eval(misa_lattice *h, int fn, const double *x, int64_t n, double *y, double *dy);
+
+/* Trainer: float32 master weights, Adam state and scratch for the three
+ * networks on the GPU of the given stream.  All arrays are device memory. */
+typedef struct misa_mlp_trainer misa_mlp_trainer;
+
+typedef struct {
+    int64_t iters;      /* optimiser steps */
+    int32_t batch;      /* samples per step (misa_mlp_fit) or sampled atoms per step (force matching) */
+    int32_t quantize;   /* 1: forward passes use the weights rounded to bfloat16 (quantisation-aware) */
+    double lr;          /* Adam step size at the first step */
+    double lr_final;    /* step size at the last step (cosine decay in between) */
+    double lambda;      /* weight of the derivative term of the fit loss */
+    uint64_t seed;      /* mini-batch draws: SplitMix64 of (seed, step, sample) */
+} misa_fit_opts;
+
+int misa_mlp_trainer_create(void *hip_stream, misa_mlp_trainer **out);
+int misa_mlp_trainer_destroy(misa_mlp_trainer *t);
+const char *misa_mlp_last_error(const misa_mlp_trainer *t);
+
+/* Set network fn (range, scaling and float32 master weights; resets its Adam state). */
+int misa_mlp_trainer_set(misa_mlp_trainer *t, int fn, const misa_mlp_net *net);
+/* Get network fn with its weights rounded to bfloat16 (ready for misa_set_mlp);
+ * master (may be NULL) receives the float32 master weights. */
+int misa_mlp_trainer_get(misa_mlp_trainer *t, int fn, misa_mlp_net *net, float *master);
+
+/* g(x) and g'(x) of network fn (bfloat16-rounded weights) at n points: path 0 is
+ * the float32 training forward pass, path 1 the matrix-core evaluation that the
+ * lattice kernels use. */
+int misa_mlp_eval(misa_mlp_trainer *t, int fn, int path, const double *x, int64_t n, double *y, double *dy);
+
+/* Gradient, with respect to the MISA_MLP_PARAMS weights (at their bfloat16
+ * rounding), of sum_i c_val[i] y(t_i) + c_der[i] dy/dt(t_i), where y is the
+ * network's normalised output and t_i the normalised input of x[i]; into grad
+ * (float64, MISA_MLP_PARAMS values).  The backward pass of the training. */
+int misa_mlp_grad(misa_mlp_trainer *t, int fn, const double *x, const double *c_val, const double *c_der,
+                  int64_t n, double *grad);
+
+/* One Adam step (Kingma and Ba: beta1 0.9, beta2 0.999, eps 1e-8) of network fn
+ * with gradient grad[MISA_MLP_PARAMS] and step size lr. */
+int misa_mlp_adam(misa_mlp_trainer *t, int fn, const double *grad, double lr);
+
+/* Fit network fn to samples of its function: x[n], y[n] = g(x), dy[n] = g'(x)
+ * (for instance from misa_table_eval).  Loss per mini-batch: mean over samples of
+ * (y_net - y)^2 + lambda (dy_net - dy)^2 in the network's normalised units.  The
+ * arrays stay registered with the trainer (and must stay valid) as the
+ * function's samples for misa_mlp_force_match.  *loss: mean loss of the last
+ * 1 % of steps. */
+int misa_mlp_fit(misa_mlp_trainer *t, int fn, const double *x, const double *y, const double *dy, int64_t n,
+                 const misa_fit_opts *o, double *loss);
+
+/* Force-matching data from the current state of a lattice handle after
+ * misa_compute_rho: for each of the n lattice sites sites[] (lattice ids of
+ * Sec. 3, host memory), the pairs of the atom it holds with slotted
+ * neighbours within rc: r[n][MISA_FM_SLOTS] (0 = empty slot), unit vectors
+ * dhat[n][MISA_FM_SLOTS][3] from the atom to the partner, the partner's F'
+ * fp_j[n][MISA_FM_SLOTS], the atom's F' fp_i[n] and its reference force
+ * f_ref[n][3] = sum over those pairs of the float64-table pair force.  Device
+ * outputs.  A vacant site gives an empty list and a zero force.  Pairs with
+ * run-away atoms are not part of the lists (those keep the tables). */
+int misa_mlp_collect(misa_lattice *h, const int64_t *sites, int64_t n, double *r, double *dhat, double *fp_j,
+                     double *fp_i, double *f_ref);
+
+/* Tune the f and phi networks so that the forces of collected atoms match
+ * f_ref: loss = sum |F - f_ref|^2 / (batch <|f_ref|^2>) over a mini-batch of
+ * o->batch atoms per step (o->batch == n_env: every atom once, in order), plus
+ * the fit loss of each of the two networks on its registered samples.  F'
+ * stays that of the data.  *loss: force term, mean of the last 1 % of steps,
+ * each evaluated before that step's update. */
+int misa_mlp_force_match(misa_mlp_trainer *t, const double *r, const double *dhat, const double *fp_j,
+                         const double *fp_i, const double *f_ref, int64_t n_env, const misa_fit_opts *o,
+                         double *loss);
 
 #ifdef __cplusplus
 }

@@ -215,6 +215,8 @@ int check_ready(misa_lattice *h, bool need_tables) {
     if (!h->state_bound) return fail(h, MISA_ESTATE, "no state buffer bound (misa_bind_state)");
     if (!h->state_set) return fail(h, MISA_ESTATE, "no atoms loaded (misa_set_state)");
     if (need_tables && !h->tables_set) return fail(h, MISA_ESTATE, "no potential tables (misa_set_potential_tables)");
+    if (need_tables && h->use_mlp && !(h->mlp.set[0] && h->mlp.set[1] && h->mlp.set[2]))
+        return fail(h, MISA_ESTATE, "learned form: networks for f, phi and F not all attached (misa_set_mlp)");
     return MISA_OK;
 }
 
@@ -353,8 +355,8 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     if (!(d->a > 0) || !(d->rc > 0) || !(d->mass > 0)) return fail(nullptr, MISA_EINVAL, "a, rc and mass must be > 0");
     if (!(d->delta > 0) || !(d->delta < d->a * std::sqrt(3.0) / 4.0))
         return fail(nullptr, MISA_EINVAL, "delta must lie in (0, a sqrt(3)/4)");
-    if (d->pair_precision != MISA_FP64 && d->pair_precision != MISA_FP32)
-        return fail(nullptr, MISA_EINVAL, "pair_precision must be MISA_FP64 or MISA_FP32");
+    if (d->pair_precision != MISA_FP64 && d->pair_precision != MISA_FP32 && d->pair_precision != MISA_MLP)
+        return fail(nullptr, MISA_EINVAL, "pair_precision must be MISA_FP64, MISA_FP32 or MISA_MLP");
     const double R = d->rc + 2.0 * d->delta;
     for (int k = 0; k < 3; ++k)
         if (!(d->n_cells[k] * d->a > 2.0 * R))
@@ -366,7 +368,8 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     if (!h) return fail(nullptr, MISA_ENOMEM, "host allocation failed");
     h->stream = (hipStream_t)hip_stream;
     (void)hipGetDevice(&h->device);
-    h->precision = d->pair_precision;
+    h->use_mlp = d->pair_precision == MISA_MLP;
+    h->precision = h->use_mlp ? MISA_FP32 : d->pair_precision;
     h->mass = d->mass;
     Geom &g = h->g;
     g.nx = d->n_cells[0];
@@ -529,7 +532,8 @@ int misa_destroy_lattice(misa_lattice *h) {
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
                     h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,
-                    h->sc.mark_blk, h->sc.mark_off, h->sc.affected, h->sc.aff_v2, h->sc.part_kick, h->staging};
+                    h->sc.mark_blk, h->sc.mark_off, h->sc.affected, h->sc.aff_v2, h->sc.part_kick, h->staging,
+                    h->mlp.p[0], h->mlp.p[1], h->mlp.p[2], h->mlp.w2b[0], h->mlp.w2b[1], h->mlp.w2b[2]};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : h->timed) h->event_pool.push_back({t.start, t.stop});

@@ -356,7 +356,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
 }
 
 bool lds_path(const misa_lattice *h) {
-    return h->precision == MISA_FP32 && h->lds32.usable && h->persistent_grid > 0;
+    return h->precision == MISA_FP32 && !h->use_mlp && h->lds32.usable && h->persistent_grid > 0;
 }
 
 hipError_t launch_rho_lds(misa_lattice *h) {

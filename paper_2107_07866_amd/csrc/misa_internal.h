@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "misa.h"
+#include "mlp_device.h"
 
 namespace misa {
 
@@ -192,13 +193,23 @@ struct LdsTables {
     bool node_cut = false;    // last node at rc: a zero record after the window implements the cut-off
 };
 
+// Surrogate networks attached to a handle of the learned form (device copies).
+struct MlpAttached {
+    MlpNet net[3];                        // net[f].p -> weights (float32 holding bfloat16 values)
+    float *p[3] = {nullptr, nullptr, nullptr};
+    uint16_t *w2b[3] = {nullptr, nullptr, nullptr};  // W2 as bfloat16 bits (matrix-core A operand)
+    bool set[3] = {false, false, false};
+};
+
 }  // namespace misa
 
 struct misa_lattice {
     hipStream_t stream = nullptr;
     int device = 0;
     misa::Geom g{};
-    int precision = MISA_FP64;
+    int precision = MISA_FP64;                    // storage / arithmetic precision (MISA_FP32 for MISA_MLP)
+    bool use_mlp = false;                         // learned form: networks in the lattice passes
+    misa::MlpAttached mlp;
     double mass = 0.0;
     int64_t rcap = 0;
     int K = 0;                                    // stencil entries per parity
@@ -247,6 +258,8 @@ hipError_t launch_rho_lds(misa_lattice *h);
 hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick);  // kick: fused second half-kick
 bool fused_kick(const misa_lattice *h);               // the step fuses the final kick into the force pass
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev);
+hipError_t launch_rho_mlp(misa_lattice *h);             // learned form: rho pass with the networks
+hipError_t launch_force_mlp(misa_lattice *h, bool energy);
 hipError_t launch_runaway_build(misa_lattice *h);      // keys, sort, hash insert
 hipError_t launch_runaway_rho(misa_lattice *h);        // run-away rho + affected-site fixup
 hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick);
@@ -330,6 +343,12 @@ __host__ __device__ inline int64_t lattice_id_of(int64_t s, const Geom &g) {
     int64_t c = s - p * g.ncell;
     int64_t cx = c % g.nx, cy = (c / g.nx) % g.ny, cz = c / ((int64_t)g.nx * g.ny);
     return 2 * (int64_t)g.nx * g.ny * cz + 2 * (int64_t)g.nx * cy + 2 * cx + p;
+}
+
+__host__ __device__ inline int64_t storage_of_lattice_id(int64_t id, const Geom &g) {
+    const int64_t X = id % (2 * (int64_t)g.nx), Y = (id / (2 * (int64_t)g.nx)) % g.ny,
+                  Z = id / (2 * (int64_t)g.nx * g.ny);
+    return (X & 1) * g.ncell + (Z * g.ny + Y) * g.nx + (X >> 1);
 }
 
 }  // namespace misa

@@ -1,0 +1,791 @@
+// Learned form: surrogate networks for f, phi and F.
+//
+// (1) Lattice passes.  The rho and force passes of the float32 form with every
+//     table look-up of a lattice pair replaced by a network evaluation.  A wave
+//     holds 64 sites and so, per stencil offset, 64 pair distances; the 32 x 32
+//     middle layer of those 64 evaluations runs on the matrix cores as
+//     Z2^T = W2 H1^T in two 32-column blocks (v_mfma_f32_32x32x8 bf16, float32
+//     accumulation).  W2 is the A operand, held in registers for the whole kernel;
+//     lanes l and l + 32 share a column and each computes the half of the first
+//     layer that its B-operand slots hold, so no transposition is needed.  The
+//     bfloat16 B operands carry each activation as a sum of two bfloat16 terms.
+//     Inputs outside a network's range take the float32 table instead.
+// (2) Training.  Per-sample float32 forward and backward passes of one network
+//     (the backward pass goes through the input tangent, since the loss involves
+//     g'), per-block partial gradients combined in a fixed order, and Adam.
+// (3) Force matching.  Forces of sampled atoms from their pair lists with the
+//     f and phi networks, and the per-pair coefficients of the force loss.
+#include "misa_internal.h"
+
+#include "mlp_device.h"
+
+namespace misa {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ float bf16_float(uint32_t b) { return __uint_as_float(b << 16); }
+
+// x = hi + lo with both terms bfloat16 (relative error of the pair ~2^-17).
+__device__ __forceinline__ void split4(const float (&x)[4], bf16x4_t &hi, bf16x4_t &lo) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t h = bf16_bits(x[i]);
+        hi[i] = (short)h;
+        lo[i] = (short)bf16_bits(x[i] - bf16_float(h));
+    }
+}
+
+// Per-unit constants of one network in LDS; float4 q covers units 4q .. 4q + 3.
+struct MlpLds {
+    float4 w1[8], b1[8], b2[8], w3[8];
+    float b3;
+};
+
+__device__ __forceinline__ void fill_lds(MlpLds &L, const float *__restrict__ p) {
+    const int i = threadIdx.x;
+    if (i < MLP_H) {
+        reinterpret_cast<float *>(L.w1)[i] = p[OFF_W1 + i];
+        reinterpret_cast<float *>(L.b1)[i] = p[OFF_B1 + i];
+        reinterpret_cast<float *>(L.b2)[i] = p[OFF_B2 + i];
+        reinterpret_cast<float *>(L.w3)[i] = p[OFF_W3 + i];
+    }
+    if (i == 0) L.b3 = p[OFF_B3];
+}
+
+// A operand of K-step s for this lane: W2[unit = lane % 32][8 s + 4 h + i], i = 0..3.
+__device__ __forceinline__ void load_a(bf16x4_t (&A)[4], const uint16_t *__restrict__ w2b) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, n = lane & 31;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const uint16_t *q = w2b + n * MLP_H + 8 * s + 4 * h;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) A[s][i] = (short)q[i];
+    }
+}
+
+// One 32-column block: column p = lane % 32 evaluates the network at t (lanes
+// l and l ^ 32 pass the same t).  Returns the normalised y and dy/dt in both lanes.
+// Accumulator element 4 j + i of lane l is row 8 j + 4 (l / 32) + i, column l % 32.
+template <bool kTan>
+__device__ __forceinline__ void mlp_block(const MlpLds &L, const bf16x4_t (&A)[4], float t, int h, float &y,
+                                          float &dy) {
+    f32x16_t acc, tac;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float4 b = L.b2[2 * j + h];
+        acc[4 * j + 0] = b.x;
+        acc[4 * j + 1] = b.y;
+        acc[4 * j + 2] = b.z;
+        acc[4 * j + 3] = b.w;
+    }
+    if (kTan)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) tac[v] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const float4 w = L.w1[2 * s + h], b = L.b1[2 * s + h];
+        const float wv[4] = {w.x, w.y, w.z, w.w}, bv[4] = {b.x, b.y, b.z, b.w};
+        float hv[4], dv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float z = wv[i] * t + bv[i];
+            const float sg = sigm(z);
+            hv[i] = z * sg;
+            dv[i] = (sg + hv[i] * (1.0f - sg)) * wv[i];
+        }
+        bf16x4_t bh, bl;
+        split4(hv, bh, bl);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[s], bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[s], bl, acc, 0, 0, 0);
+        if (kTan) {
+            bf16x4_t dh, dl;
+            split4(dv, dh, dl);
+            tac = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[s], dh, tac, 0, 0, 0);
+            tac = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[s], dl, tac, 0, 0, 0);
+        }
+    }
+    float py = 0.0f, pd = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float4 w = L.w3[2 * j + h];
+        const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float z = acc[4 * j + i];
+            const float sg = sigm(z);
+            const float hz = z * sg;
+            py += wv[i] * hz;
+            if (kTan) pd += wv[i] * (sg + hz * (1.0f - sg)) * tac[4 * j + i];
+        }
+    }
+    py += __shfl_xor(py, 32);
+    y = py + L.b3;
+    if (kTan) {
+        pd += __shfl_xor(pd, 32);
+        dy = pd;
+    }
+}
+
+// The network at one normalised input per lane (all 64 lanes must take part).
+template <bool kTan>
+__device__ __forceinline__ void mlp_wave(const MlpLds &L, const bf16x4_t (&A)[4], float t_own, float &y,
+                                         float &dy) {
+    const int h = (threadIdx.x >> 5) & 1;
+    const float t_par = __shfl_xor(t_own, 32);
+    float y0, d0 = 0.0f, y1, d1 = 0.0f;
+    mlp_block<kTan>(L, A, h ? t_par : t_own, h, y0, d0);  // columns = pairs of lanes 0..31
+    mlp_block<kTan>(L, A, h ? t_own : t_par, h, y1, d1);  // columns = pairs of lanes 32..63
+    y = h ? y1 : y0;
+    dy = h ? d1 : d0;
+}
+
+__device__ __forceinline__ float net_t(const MlpNet &m, float x) {
+    return (fminf(fmaxf(x, m.x_lo), m.x_hi) - m.c) * m.s;
+}
+
+// ---------------------------------------------------------------------------
+// float32 table fall-back (the same records as the float32 form)
+
+__device__ __forceinline__ void seg32(float x, const TabMeta<float> &m, int &k, float &t) {
+    const float p = (x - m.x0) * m.inv_h;
+    int kk = (int)p;
+    kk = kk < m.nseg - 1 ? kk : m.nseg - 1;
+    kk = kk > 0 ? kk : 0;
+    k = kk;
+    t = p - (float)kk;
+}
+
+__device__ __forceinline__ float emb_tab(float rho, const Tables<float> &T, float &Fv, bool &beyond) {
+    const TabMeta<float> &m = T.em;
+    if (rho > m.x_last) {
+        beyond = true;
+        Fv = m.y_last + m.d_last * (rho - m.x_last);
+        return m.d_last;
+    }
+    int k;
+    float t;
+    seg32(rho, m, k, t);
+    const Q4<float> c = T.emb[2 * k], d = T.emb[2 * k + 1];
+    Fv = ((c.w * t + c.z) * t + c.y) * t + c.x;
+    return (d.z * t + d.y) * t + d.x;
+}
+
+__device__ __forceinline__ int wrapm(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+__device__ __forceinline__ void load_tile_f(Q4<float> *__restrict__ tile, const double *__restrict__ ux,
+                                            const double *__restrict__ uy, const double *__restrict__ uz,
+                                            const float *__restrict__ w_src, const Geom &g, int bx, int by,
+                                            int bz) {
+    for (int e = threadIdx.x; e < TILE_SITES; e += TILE_THREADS) {
+        const int lx = e % PX;
+        int r = e / PX;
+        const int ly = r % PY;
+        r /= PY;
+        const int lz = r % PZ;
+        const int p = r / PZ;
+        const int gx = wrapm(bx + lx, g.nx), gy = wrapm(by + ly, g.ny), gz = wrapm(bz + lz, g.nz);
+        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+        Q4<float> q;
+        q.x = (float)ux[idx];
+        q.y = (float)uy[idx];
+        q.z = (float)uz[idx];
+        q.w = w_src ? w_src[idx] : 0.0f;
+        tile[e] = q;
+    }
+}
+
+struct MlpSet {
+    MlpNet net[3];
+    const uint16_t *w2b[3];  // W2 of each network as bfloat16 bits
+};
+
+// rho_i = sum_j f(r_ij) and F'(rho_i) with the networks.  Every lane of a wave runs
+// the pair loop (the matrix-core evaluation needs the whole wave); lanes outside the
+// box compute on wrapped data and store nothing.
+__global__ __launch_bounds__(TILE_THREADS) void k_rho_mlp(const double *__restrict__ ux,
+                                                          const double *__restrict__ uy,
+                                                          const double *__restrict__ uz, float *__restrict__ rho,
+                                                          float *__restrict__ fp,
+                                                          const StencilEntry<float> *__restrict__ st, int K,
+                                                          Tables<float> T, MlpSet M, Geom g,
+                                                          uint32_t *__restrict__ range_viol) {
+    __shared__ Q4<float> tile[TILE_SITES];
+    __shared__ MlpLds Lf, Le;
+    const int tid = tile_of_block(blockIdx.x, g);
+    if (tid >= g.ntiles) return;  // whole work-group leaves together
+    const int tx = tid % g.ntx;
+    const int tyz = tid / g.ntx;
+    const int ty = tyz % g.nty;
+    const int tz = tyz / g.nty;
+    load_tile_f(tile, ux, uy, uz, nullptr, g, tx * TX - HALO, ty * TY - HALO, tz * TZ - HALO);
+    fill_lds(Lf, M.net[0].p);
+    fill_lds(Le, M.net[2].p);
+    bf16x4_t Af[4], Ae[4];
+    load_a(Af, M.w2b[0]);
+    load_a(Ae, M.w2b[2]);
+    __syncthreads();
+
+    const MlpNet nf = M.net[0], ne = M.net[2];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = __builtin_amdgcn_readfirstlane(w / TZ);
+    const int lz = w % TZ, lx = lane % TX, ly = lane / TX;
+    const int gx = tx * TX + lx, gy = ty * TY + ly, gz = tz * TZ + lz;
+    const bool active = gx < g.nx && gy < g.ny && gz < g.nz;
+    const int me = ((p * PZ + lz + HALO) * PY + ly + HALO) * PX + lx + HALO;
+    const Q4<float> ui = tile[me];
+    const float rc2 = (float)g.rc2;
+    const StencilEntry<float> *sp = st + p * KMAX;
+    float acc = 0.0f;
+    for (int k = 0; k < K; ++k) {
+        const StencilEntry<float> e = sp[k];
+        const Q4<float> uj = tile[me + e.lds];
+        const float dx = (uj.x - ui.x) + e.ox;
+        const float dy = (uj.y - ui.y) + e.oy;
+        const float dz = (uj.z - ui.z) + e.oz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float r = __builtin_amdgcn_sqrtf(r2);
+        float y, unused;
+        mlp_wave<false>(Lf, Af, net_t(nf, r), y, unused);
+        if (r2 < rc2) {
+            float v = nf.y_shift + nf.y_scale * y;
+            if (!mlp_serves(nf, r)) {
+                int s;
+                float t;
+                seg32(r, T.fm, s, t);
+                const Q4<float> c = T.f[s];
+                v = ((c.w * t + c.z) * t + c.y) * t + c.x;
+            }
+            acc += v;
+        }
+    }
+    const bool vac = ui.x > (float)VACANT_TEST;
+    if (vac) acc = 0.0f;
+    float ye, de;
+    mlp_wave<true>(Le, Ae, net_t(ne, acc), ye, de);
+    float fpv = ne.y_scale * ne.s * de;
+    bool beyond = false;
+    if (!mlp_serves(ne, acc)) {
+        float Fv;
+        fpv = emb_tab(acc, T, Fv, beyond);
+    }
+    if (vac) fpv = 0.0f;
+    if (active) {
+        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+        rho[idx] = acc;
+        fp[idx] = fpv;
+        if (beyond) atomicAdd(range_viol, 1u);
+    }
+}
+
+__device__ __forceinline__ double wave_sum_m(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// F_i = sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (x_j - x_i) / r with the networks;
+// with kEnergy, per-tile sums of F(rho_i) and 1/2 sum_j phi(r_ij).
+template <bool kEnergy>
+__global__ __launch_bounds__(TILE_THREADS) void k_force_mlp(
+    const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
+    const float *__restrict__ fp, const float *__restrict__ rho, float *__restrict__ fx, float *__restrict__ fy,
+    float *__restrict__ fz, const StencilEntry<float> *__restrict__ st, int K, Tables<float> T, MlpSet M, Geom g,
+    double *__restrict__ part) {
+    __shared__ Q4<float> tile[TILE_SITES];
+    __shared__ MlpLds Lf, Lp, Le;
+    __shared__ double red[2][TILE_THREADS / 64];
+    const int tid = tile_of_block(blockIdx.x, g);
+    if (tid >= g.ntiles) return;
+    const int tx = tid % g.ntx;
+    const int tyz = tid / g.ntx;
+    const int ty = tyz % g.nty;
+    const int tz = tyz / g.nty;
+    load_tile_f(tile, ux, uy, uz, fp, g, tx * TX - HALO, ty * TY - HALO, tz * TZ - HALO);
+    fill_lds(Lf, M.net[0].p);
+    fill_lds(Lp, M.net[1].p);
+    if (kEnergy) fill_lds(Le, M.net[2].p);
+    bf16x4_t Af[4], Ap[4];
+    load_a(Af, M.w2b[0]);
+    load_a(Ap, M.w2b[1]);
+    __syncthreads();
+
+    const MlpNet nf = M.net[0], np = M.net[1];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = __builtin_amdgcn_readfirstlane(w / TZ);
+    const int lz = w % TZ, lx = lane % TX, ly = lane / TX;
+    const int gx = tx * TX + lx, gy = ty * TY + ly, gz = tz * TZ + lz;
+    const bool active = gx < g.nx && gy < g.ny && gz < g.nz;
+    const int me = ((p * PZ + lz + HALO) * PY + ly + HALO) * PX + lx + HALO;
+    const Q4<float> ui = tile[me];
+    const float rc2 = (float)g.rc2;
+    const StencilEntry<float> *sp = st + p * KMAX;
+    const float kf = nf.y_scale * nf.s, kp = np.y_scale * np.s;
+    float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
+    for (int k = 0; k < K; ++k) {
+        const StencilEntry<float> e = sp[k];
+        const Q4<float> uj = tile[me + e.lds];
+        const float dx = (uj.x - ui.x) + e.ox;
+        const float dy = (uj.y - ui.y) + e.oy;
+        const float dz = (uj.z - ui.z) + e.oz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float r = r2 * rinv;
+        float yf, df, yp, dp;
+        mlp_wave<true>(Lf, Af, net_t(nf, r), yf, df);
+        mlp_wave<true>(Lp, Ap, net_t(np, r), yp, dp);
+        if (r2 < rc2) {
+            float dfr = kf * df, dph = kp * dp, ph = np.y_shift + np.y_scale * yp;
+            if (!mlp_serves(nf, r) || !mlp_serves(np, r)) {
+                int s;
+                float t;
+                seg32(r, T.fm, s, t);
+                const Q4<float> a = T.force[2 * s], b = T.force[2 * s + 1];
+                if (!mlp_serves(nf, r)) dfr = (a.z * t + a.y) * t + a.x;
+                if (!mlp_serves(np, r)) {
+                    dph = (b.y * t + b.x) * t + a.w;
+                    const Q4<float> c = T.phi[s];
+                    ph = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                }
+            }
+            const float sc = ((ui.w + uj.w) * dfr + dph) * rinv;
+            ax += sc * dx;
+            ay += sc * dy;
+            az += sc * dz;
+            if (kEnergy) ep += ph;
+        }
+    }
+    const bool vac = ui.x > (float)VACANT_TEST;
+    const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+    if (vac) ax = ay = az = 0.0f;
+    if (active) {
+        fx[idx] = ax;
+        fy[idx] = ay;
+        fz[idx] = az;
+    }
+    if (kEnergy) {
+        const MlpNet ne = M.net[2];
+        bf16x4_t Ae[4];
+        load_a(Ae, M.w2b[2]);
+        const float rr = active ? rho[idx] : 0.0f;
+        float ye, unused;
+        mlp_wave<false>(Le, Ae, net_t(ne, rr), ye, unused);
+        float Fv = ne.y_shift + ne.y_scale * ye;
+        if (!mlp_serves(ne, rr)) {
+            bool beyond = false;
+            emb_tab(rr, T, Fv, beyond);
+        }
+        double e_emb = (active && !vac) ? (double)Fv : 0.0;
+        double e_pair = (active && !vac) ? 0.5 * (double)ep : 0.0;
+        e_emb = wave_sum_m(e_emb);
+        e_pair = wave_sum_m(e_pair);
+        if (lane == 0) {
+            red[0][w] = e_emb;
+            red[1][w] = e_pair;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int q = 0; q < TILE_THREADS / 64; ++q) {
+                s0 += red[0][q];
+                s1 += red[1][q];
+            }
+            part[2 * tid] = s0;
+            part[2 * tid + 1] = s1;
+        }
+    }
+}
+
+static MlpSet mlp_set_of(const misa_lattice *h) {
+    MlpSet M;
+    for (int f = 0; f < 3; ++f) {
+        M.net[f] = h->mlp.net[f];
+        M.w2b[f] = h->mlp.w2b[f];
+    }
+    return M;
+}
+
+static Tables<float> t32_tables(const misa_lattice *h) {
+    Tables<float> T;
+    T.f = h->t32.f;
+    T.force = h->t32.force;
+    T.phi = h->t32.phi;
+    T.emb = h->t32.emb;
+    T.fm = h->t32.fm;
+    T.em = h->t32.em;
+    return T;
+}
+
+hipError_t launch_rho_mlp(misa_lattice *h) {
+    const Geom &g = h->g;
+    hipLaunchKernelGGL(k_rho_mlp, dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
+                       (float *)h->S.rho, (float *)h->S.fp, h->st32, h->K, t32_tables(h), mlp_set_of(h), g,
+                       &h->sc.cnt->range_viol);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_mlp(misa_lattice *h, bool energy) {
+    const Geom &g = h->g;
+    auto kern = energy ? k_force_mlp<true> : k_force_mlp<false>;
+    hipLaunchKernelGGL(kern, dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
+                       (const float *)h->S.fp, (const float *)h->S.rho, (float *)h->S.fx, (float *)h->S.fy,
+                       (float *)h->S.fz, h->st32, h->K, t32_tables(h), mlp_set_of(h), g, h->sc.part);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation entry points of the trainer (the two forward paths).
+
+__global__ void k_eval_lane(MlpNet m, const double *__restrict__ x, int64_t n, double *__restrict__ y,
+                            double *__restrict__ dy) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float g, dg;
+        mlp_eval_lane(m, (float)x[i], g, dg);
+        y[i] = g;
+        dy[i] = dg;
+    }
+}
+
+// Matrix-core path: 64 points per wave; padding lanes repeat the last point.
+__global__ __launch_bounds__(256) void k_eval_mfma(MlpNet m, const uint16_t *__restrict__ w2b,
+                                                   const double *__restrict__ x, int64_t n, double *__restrict__ y,
+                                                   double *__restrict__ dy) {
+    __shared__ MlpLds L;
+    fill_lds(L, m.p);
+    bf16x4_t A[4];
+    load_a(A, w2b);
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += stride) {  // uniform over the block
+        const int64_t i = base + threadIdx.x;
+        const float xi = (float)x[i < n ? i : n - 1];
+        float yy, dd;
+        mlp_wave<true>(L, A, (xi - m.c) * m.s, yy, dd);
+        if (i < n) {
+            y[i] = m.y_shift + m.y_scale * yy;
+            dy[i] = m.y_scale * m.s * dd;
+        }
+    }
+}
+
+hipError_t launch_mlp_eval(hipStream_t st, int path, const MlpNet &m, const uint16_t *w2b, const double *x,
+                           int64_t n, double *y, double *dy) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    if (path == 0)
+        hipLaunchKernelGGL(k_eval_lane, dim3(blocks), dim3(256), 0, st, m, x, n, y, dy);
+    else
+        hipLaunchKernelGGL(k_eval_mfma, dim3(blocks), dim3(256), 0, st, m, w2b, x, n, y, dy);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Training: per-sample forward and backward passes, one sample per lane,
+// GRAD_SAMPLES samples per block; per-block partial gradients.
+
+constexpr int GS = MLP_H + 1;  // padded LDS row
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    // Steele, Lea and Flood, "Fast splittable pseudorandom number generators" (2014)
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(GRAD_SAMPLES) void k_grad(GradJob J) {
+    // weights and per-sample vectors in LDS (rows padded against bank conflicts)
+    __shared__ float P[MLP_NP];
+    __shared__ float sh1[GRAD_SAMPLES][GS], sd1[GRAD_SAMPLES][GS], sa1[GRAD_SAMPLES][GS];
+    __shared__ float su[GRAD_SAMPLES][GS], sv[GRAD_SAMPLES][GS], sq[GRAD_SAMPLES][GS];
+    __shared__ float sp1[GRAD_SAMPLES][GS], sz1[GRAD_SAMPLES][GS];
+    __shared__ float scv[GRAD_SAMPLES];
+    __shared__ double sloss[GRAD_SAMPLES];
+    const int b = threadIdx.x;
+    for (int j = b; j < MLP_NP; j += GRAD_SAMPLES) P[j] = J.p[j];
+    const int64_t i = (int64_t)blockIdx.x * GRAD_SAMPLES + b;
+    const bool sob = J.cval == nullptr;
+    const int64_t count = sob ? J.batch : J.n;
+    const bool live = i < count;
+    int64_t idx = i;
+    if (sob)
+        idx = live ? (int64_t)(splitmix64(J.seed ^ splitmix64(J.step * 0x100000001b3ull + (uint64_t)i)) %
+                               (uint64_t)J.n)
+                   : 0;
+    else if (!live)
+        idx = 0;
+    const float t = ((float)J.x[idx] - J.c) * J.s;
+    __syncthreads();
+    // forward with tangents
+    for (int k = 0; k < MLP_H; ++k) {
+        const float w = P[OFF_W1 + k];
+        const float z = w * t + P[OFF_B1 + k];
+        const float sg = sigm(z);
+        const float h = z * sg;
+        const float a = sg + h * (1.0f - sg);
+        sh1[b][k] = h;
+        sa1[b][k] = a;
+        sd1[b][k] = a * w;
+    }
+    float y = P[OFF_B3], dyt = 0.0f;
+    for (int n = 0; n < MLP_H; ++n) {
+        const float *w2 = P + OFF_W2 + n * MLP_H;
+        float z = P[OFF_B2 + n], dz = 0.0f;
+#pragma unroll 8
+        for (int k = 0; k < MLP_H; ++k) {
+            z += w2[k] * sh1[b][k];
+            dz += w2[k] * sd1[b][k];
+        }
+        const float sg = sigm(z);
+        const float h2 = z * sg;
+        const float a2 = sg + h2 * (1.0f - sg);
+        y += P[OFF_W3 + n] * h2;
+        dyt += P[OFF_W3 + n] * a2 * dz;
+        su[b][n] = z;   // z2 until the reverse pass
+        sv[b][n] = dz;  // dz2 until the reverse pass
+    }
+    float cv, cd;
+    double loss = 0.0;
+    if (sob) {
+        const float yn = (float)((J.y[idx] - (double)J.y_shift) / (double)J.y_scale);
+        const float dn = (float)(J.dy[idx] / ((double)J.y_scale * (double)J.s));
+        const float ey = y - yn, ed = dyt - dn;
+        const float inv = 1.0f / (float)count;
+        cv = live ? 2.0f * ey * inv : 0.0f;
+        cd = live ? 2.0f * J.lam * ed * inv : 0.0f;
+        loss = live ? (double)(ey * ey + J.lam * ed * ed) : 0.0;
+    } else {
+        cv = live ? (float)J.cval[idx] : 0.0f;
+        cd = live ? (float)J.cder[idx] : 0.0f;
+    }
+    // reverse through layer 2
+    for (int n = 0; n < MLP_H; ++n) {
+        const float z = su[b][n], dz = sv[b][n];
+        const float sg = sigm(z);
+        const float h2 = z * sg;
+        const float a2 = sg + h2 * (1.0f - sg);
+        const float s2 = sg * (1.0f - sg) * (2.0f + z * (1.0f - 2.0f * sg));  // silu''
+        const float w3 = P[OFF_W3 + n];
+        sq[b][n] = cv * h2 + cd * a2 * dz;         // d/dw3
+        su[b][n] = cv * w3 * a2 + cd * w3 * dz * s2;  // d/dz2
+        sv[b][n] = cd * w3 * a2;                   // d/d(dz2)
+    }
+    // reverse through layer 1
+    for (int k = 0; k < MLP_H; ++k) {
+        float gh = 0.0f, gd = 0.0f;
+#pragma unroll 8
+        for (int n = 0; n < MLP_H; ++n) {
+            const float w = P[OFF_W2 + n * MLP_H + k];
+            gh += w * su[b][n];
+            gd += w * sv[b][n];
+        }
+        const float w1 = P[OFF_W1 + k];
+        const float z = w1 * t + P[OFF_B1 + k];
+        const float sg = sigm(z);
+        const float s1 = sg * (1.0f - sg) * (2.0f + z * (1.0f - 2.0f * sg));
+        const float a1 = sa1[b][k];
+        const float gz1 = gh * a1 + gd * w1 * s1;
+        sp1[b][k] = gd * a1 + gz1 * t;  // d/dW1
+        sz1[b][k] = gz1;                // d/db1
+    }
+    scv[b] = cv;
+    sloss[b] = loss;
+    __syncthreads();
+    // block sums in a fixed order
+    float *out = J.part + (int64_t)blockIdx.x * MLP_NP;
+    const int n = b >> 1, k0 = (b & 1) * 16;
+    for (int j = 0; j < 16; ++j) {
+        const int k = k0 + j;
+        float s = 0.0f;
+#pragma unroll 8
+        for (int q = 0; q < GRAD_SAMPLES; ++q) s += su[q][n] * sh1[q][k] + sv[q][n] * sd1[q][k];
+        out[OFF_W2 + n * MLP_H + k] = s;
+    }
+    if (b < MLP_H) {
+        float g1 = 0.0f, gb1 = 0.0f, gb2 = 0.0f, gw3 = 0.0f;
+        for (int q = 0; q < GRAD_SAMPLES; ++q) {
+            g1 += sp1[q][b];
+            gb1 += sz1[q][b];
+            gb2 += su[q][b];
+            gw3 += sq[q][b];
+        }
+        out[OFF_W1 + b] = g1;
+        out[OFF_B1 + b] = gb1;
+        out[OFF_B2 + b] = gb2;
+        out[OFF_W3 + b] = gw3;
+    }
+    if (b == MLP_H) {
+        float g3 = 0.0f;
+        for (int q = 0; q < GRAD_SAMPLES; ++q) g3 += scv[q];
+        out[OFF_B3] = g3;
+    }
+    if (b == MLP_H + 1 && J.loss_part) {
+        double l = 0.0;
+        for (int q = 0; q < GRAD_SAMPLES; ++q) l += sloss[q];
+        J.loss_part[blockIdx.x] = l;
+    }
+}
+
+// grad[j] = sum over blocks of part[blk][j] (fixed order), float64.
+__global__ void k_grad_sum(const float *__restrict__ part, int nblk, double *__restrict__ grad) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < MLP_NP; j += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < nblk; ++q) s += (double)part[(int64_t)q * MLP_NP + j];
+        grad[j] = s;
+    }
+}
+
+// Adam on the float32 master weights; q receives them rounded to bfloat16.
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const double *__restrict__ grad, float *__restrict__ q, double lr, double bc1, double bc2) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < MLP_NP; j += gridDim.x * blockDim.x) {
+        const double g = grad[j];
+        const double mj = 0.9 * (double)m[j] + 0.1 * g;
+        const double vj = 0.999 * (double)v[j] + 0.001 * g * g;
+        m[j] = (float)mj;
+        v[j] = (float)vj;
+        const double step = lr * (mj / bc1) / (sqrt(vj / bc2) + 1e-8);
+        const float wj = (float)((double)w[j] - step);
+        w[j] = wj;
+        q[j] = bf16_float(bf16_bits(wj));
+    }
+}
+
+__global__ void k_round_weights(const float *__restrict__ w, float *__restrict__ q, uint16_t *__restrict__ w2b) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < MLP_NP; j += gridDim.x * blockDim.x) {
+        const uint32_t b = bf16_bits(w[j]);
+        q[j] = bf16_float(b);
+        if (w2b && j >= OFF_W2 && j < OFF_W2 + MLP_H * MLP_H) w2b[j - OFF_W2] = (uint16_t)b;
+    }
+}
+
+hipError_t launch_grad(hipStream_t st, const GradJob &J, int nblk) {
+    hipLaunchKernelGGL(k_grad, dim3(nblk), dim3(GRAD_SAMPLES), 0, st, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_sum(hipStream_t st, const float *part, int nblk, double *grad) {
+    hipLaunchKernelGGL(k_grad_sum, dim3((MLP_NP + 255) / 256), dim3(256), 0, st, part, nblk, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(hipStream_t st, float *w, float *m, float *v, const double *grad, float *q, double lr,
+                       int64_t step) {
+    const double bc1 = 1.0 - pow(0.9, (double)step), bc2 = 1.0 - pow(0.999, (double)step);
+    hipLaunchKernelGGL(k_adam, dim3((MLP_NP + 255) / 256), dim3(256), 0, st, w, m, v, grad, q, lr, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_weights(hipStream_t st, const float *w, float *q, uint16_t *w2b) {
+    hipLaunchKernelGGL(k_round_weights, dim3((MLP_NP + 255) / 256), dim3(256), 0, st, w, q, w2b);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Force matching
+
+// One wave per sampled atom; lanes take slots lane and lane + 64.
+__global__ __launch_bounds__(64) void k_fm(FmJob J) {
+    const int q = blockIdx.x;
+    if (q >= J.nb) return;
+    const int e = J.envs[q];
+    const int lane = threadIdx.x;
+    const double fi = J.fpi[e];
+    double F[3] = {0.0, 0.0, 0.0};
+    float dfv[2] = {0.f, 0.f}, dpv[2] = {0.f, 0.f};
+    for (int u = 0; u < 2; ++u) {
+        const int slot = lane + 64 * u;
+        if (slot >= MISA_FM_SLOTS) break;
+        const int64_t o = (int64_t)e * MISA_FM_SLOTS + slot;
+        const double r = J.r[o];
+        J.x_out[(int64_t)q * MISA_FM_SLOTS + slot] = r;
+        if (r <= 0.0) continue;
+        float g, dg;
+        mlp_eval_lane(J.nf, (float)r, g, dg);
+        dfv[u] = dg;
+        mlp_eval_lane(J.np, (float)r, g, dg);
+        dpv[u] = dg;
+        const double s = (fi + J.fpj[o]) * (double)dfv[u] + (double)dpv[u];
+        for (int c = 0; c < 3; ++c) F[c] += s * J.dhat[3 * o + c];
+    }
+    for (int c = 0; c < 3; ++c) F[c] = wave_sum_m(F[c]);
+    double res[3];
+    for (int c = 0; c < 3; ++c) res[c] = F[c] - J.fref[3 * (int64_t)e + c];
+    if (lane == 0) J.loss_part[q] = (res[0] * res[0] + res[1] * res[1] + res[2] * res[2]) * J.inv_norm;
+    const double kf = (double)J.nf.y_scale * (double)J.nf.s, kp = (double)J.np.y_scale * (double)J.np.s;
+    for (int u = 0; u < 2; ++u) {
+        const int slot = lane + 64 * u;
+        if (slot >= MISA_FM_SLOTS) break;
+        const int64_t o = (int64_t)e * MISA_FM_SLOTS + slot;
+        const int64_t w = (int64_t)q * MISA_FM_SLOTS + slot;
+        const double r = J.r[o];
+        double pf = 0.0, pp = 0.0;
+        if (r > 0.0) {
+            const double proj =
+                2.0 * J.inv_norm * (res[0] * J.dhat[3 * o] + res[1] * J.dhat[3 * o + 1] + res[2] * J.dhat[3 * o + 2]);
+            pf = proj * (fi + J.fpj[o]) * kf;
+            pp = proj * kp;
+        }
+        J.cf[w] = pf;
+        J.cp[w] = pp;
+    }
+}
+
+// Mini-batch of sampled atoms; a batch as large as the data takes every atom once, in order.
+__global__ void k_fm_draw(int32_t *envs, int nb, int64_t n_env, uint64_t seed, uint64_t step) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x)
+        envs[i] = nb == n_env ? i
+                              : (int32_t)(splitmix64(seed ^ splitmix64(step * 0x100000001b3ull + (uint64_t)i)) %
+                                          (uint64_t)n_env);
+}
+
+__global__ void k_fm_norm(const double *__restrict__ fref, int64_t n, double *__restrict__ out) {
+    __shared__ double red[1024 / 64];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < 3 * n; i += 1024) s += fref[i] * fref[i];
+    s = wave_sum_m(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < 1024 / 64; ++q) t += red[q];
+        out[0] = t / (double)n;
+    }
+}
+
+hipError_t launch_fm(hipStream_t st, const FmJob &J, uint64_t seed, uint64_t step, int32_t *envs) {
+    hipLaunchKernelGGL(k_fm_draw, dim3((J.nb + 255) / 256), dim3(256), 0, st, envs, J.nb, J.n_env, seed, step);
+    hipLaunchKernelGGL(k_fm, dim3(J.nb), dim3(64), 0, st, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_fm_norm(hipStream_t st, const double *fref, int64_t n, double *out) {
+    hipLaunchKernelGGL(k_fm_norm, dim3(1), dim3(1024), 0, st, fref, n, out);
+    return hipGetLastError();
+}
+
+// Sum of nb doubles (fixed order) into out[slot].
+__global__ void k_sum_into(const double *__restrict__ a, int n, double *__restrict__ out, int slot) {
+    __shared__ double red[256 / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += a[i];
+    s = wave_sum_m(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[slot] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_sum_into(hipStream_t st, const double *a, int n, double *out, int slot) {
+    hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, st, a, n, out, slot);
+    return hipGetLastError();
+}
+
+}  // namespace misa

@@ -501,9 +501,10 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(St
 }
 
 // Lattice atoms within rc of run-aways: add the run-away terms to rho, refresh F'.
+// emb: the embedding network of the learned form (an empty range on other handles).
 template <typename Real>
 __global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch sc, Geom g, Tables<double> T,
-                                                              Tables<Real> TL) {
+                                                              Tables<Real> TL, MlpNet emb) {
     int na = sc.cnt->n_affected;
     na = na < sc.affected_cap ? na : (int)sc.affected_cap;
     const int cell = threadIdx.x & (AFF_TEAM - 1);
@@ -532,7 +533,13 @@ __global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch s
             rho[s] = rj;
             Real Fv;
             bool beyond = false;
-            fp[s] = emb_any<Real>(rj, TL.emb, TL.em, Fv, beyond);
+            if (mlp_serves(emb, (float)rj)) {
+                float ge, dge;
+                mlp_eval_lane(emb, (float)rj, ge, dge);
+                fp[s] = (Real)dge;
+            } else {
+                fp[s] = emb_any<Real>(rj, TL.emb, TL.em, Fv, beyond);
+            }
             if (beyond) atomicAdd(&sc.cnt->range_viol, 1u);
         }
     }
@@ -815,10 +822,10 @@ hipError_t launch_runaway_rho(misa_lattice *h) {
     hipLaunchKernelGGL(k_mark_emit, dim3(h->sc.mark_nblk), dim3(MARK_THREADS), 0, st, h->sc);
     if (h->precision == MISA_FP32)
         hipLaunchKernelGGL(k_affected_rho<float>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g, t64_of(h),
-                           t32_of(h));
+                           t32_of(h), h->use_mlp ? h->mlp.net[2] : MlpNet{});
     else
         hipLaunchKernelGGL(k_affected_rho<double>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g,
-                           t64_of(h), t64_of(h));
+                           t64_of(h), t64_of(h), MlpNet{});
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ class Lattice:
         self.precision = precision
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
-        prec = M.MISA_FP32 if precision == "fp32" else M.MISA_FP64
+        prec = {"fp64": M.MISA_FP64, "fp32": M.MISA_FP32, "mlp": M.MISA_MLP}[precision]
         self.h = M.misa_create_lattice(self.n_cells, a, rc, delta, mass, prec, runaway_capacity,
                                        self.stream.cuda_stream)
         nbytes = M.misa_state_bytes(self.h)
@@ -38,6 +38,11 @@ class Lattice:
 
     def set_tables(self, tables):
         M.misa_set_potential_tables(self.h, tables["f"], tables["phi"], tables["F"])
+
+    def set_mlp(self, nets):
+        """nets: {MISA_FN_F: net, MISA_FN_PHI: net, MISA_FN_EMB: net} (learned form only)."""
+        for fn, net in nets.items():
+            M.misa_set_mlp(self.h, fn, net)
 
     def set_state(self, x, v):
         M.misa_set_state(self.h, x, v)

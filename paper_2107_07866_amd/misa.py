@@ -22,6 +22,9 @@ MISA_FP64, MISA_FP32 = 0, 1
 MISA_HOST, MISA_DEVICE = 0, 1
 MISA_FIELD_RHO, MISA_FIELD_FPRIME, MISA_FIELD_FORCE = 0, 1, 2
 MISA_EXPORT_STENCIL, MISA_EXPORT_SLOTS = 0, 1
+MISA_MLP = 2
+MISA_FN_F, MISA_FN_PHI, MISA_FN_EMB = 0, 1, 2
+MISA_MLP_HIDDEN, MISA_MLP_PARAMS, MISA_FM_SLOTS = 32, 1153, 96
 
 _ERRNAMES = {MISA_EINVAL: "MISA_EINVAL", MISA_ENOMEM: "MISA_ENOMEM", MISA_EHIP: "MISA_EHIP",
              MISA_ESTATE: "MISA_ESTATE", MISA_EOVERFLOW: "MISA_EOVERFLOW"}
@@ -61,6 +64,16 @@ class misa_timing(C.Structure):
     _fields_ = [("ms", C.c_double * 5), ("launches", C.c_int64 * 5)]
 
 
+class misa_mlp_net(C.Structure):
+    _fields_ = [("x_lo", C.c_double), ("x_hi", C.c_double), ("y_shift", C.c_double), ("y_scale", C.c_double),
+                ("params", C.c_float * MISA_MLP_PARAMS), ("reserved", C.c_int32)]
+
+
+class misa_fit_opts(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("batch", C.c_int32), ("quantize", C.c_int32), ("lr", C.c_double),
+                ("lr_final", C.c_double), ("lambda_", C.c_double), ("seed", C.c_uint64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -85,6 +98,19 @@ def _load():
         "misa_set_timing": ([vp, C.c_int], C.c_int),
         "misa_get_timing": ([vp, C.POINTER(misa_timing)], C.c_int),
         "misa_debug_export": ([vp, C.c_int, C.POINTER(i64), i64], i64),
+        "misa_set_mlp": ([vp, C.c_int, C.POINTER(misa_mlp_net)], C.c_int),
+        "misa_table_eval": ([vp, C.c_int, vp, i64, vp, vp], C.c_int),
+        "misa_mlp_trainer_create": ([vp, C.POINTER(vp)], C.c_int),
+        "misa_mlp_trainer_destroy": ([vp], C.c_int),
+        "misa_mlp_last_error": ([vp], C.c_char_p),
+        "misa_mlp_trainer_set": ([vp, C.c_int, C.POINTER(misa_mlp_net)], C.c_int),
+        "misa_mlp_trainer_get": ([vp, C.c_int, C.POINTER(misa_mlp_net), vp], C.c_int),
+        "misa_mlp_eval": ([vp, C.c_int, C.c_int, vp, i64, vp, vp], C.c_int),
+        "misa_mlp_grad": ([vp, C.c_int, vp, vp, vp, i64, vp], C.c_int),
+        "misa_mlp_adam": ([vp, C.c_int, vp, C.c_double], C.c_int),
+        "misa_mlp_fit": ([vp, C.c_int, vp, vp, vp, i64, C.POINTER(misa_fit_opts), dp], C.c_int),
+        "misa_mlp_collect": ([vp, vp, i64, vp, vp, vp, vp, vp], C.c_int),
+        "misa_mlp_force_match": ([vp, vp, vp, vp, vp, vp, i64, C.POINTER(misa_fit_opts), dp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -243,3 +269,118 @@ def misa_debug_export(h, what):
     out = np.empty(max(n, 1), dtype=np.int64)
     _check(lib.misa_debug_export(h, what, out.ctypes.data_as(C.POINTER(C.c_int64)), out.size), h)
     return out[:n]
+
+
+# ---------------------------------------------------------------------------
+# learned form (surrogate networks)
+
+def _net(net):
+    """dict(x_lo, x_hi, y_shift, y_scale, params[MISA_MLP_PARAMS]) -> misa_mlp_net."""
+    n = misa_mlp_net()
+    n.x_lo, n.x_hi = float(net["x_lo"]), float(net["x_hi"])
+    n.y_shift, n.y_scale = float(net["y_shift"]), float(net["y_scale"])
+    prm = np.ascontiguousarray(net["params"], dtype=np.float32)
+    if prm.shape != (MISA_MLP_PARAMS,):
+        raise ValueError(f"params must hold {MISA_MLP_PARAMS} values")
+    C.memmove(n.params, prm.ctypes.data, prm.nbytes)
+    return n
+
+
+def _net_dict(n):
+    return {"x_lo": n.x_lo, "x_hi": n.x_hi, "y_shift": n.y_shift, "y_scale": n.y_scale,
+            "params": np.ctypeslib.as_array(n.params).copy()}
+
+
+def _opts(o):
+    s = misa_fit_opts()
+    s.iters, s.batch, s.quantize = int(o["iters"]), int(o["batch"]), int(o.get("quantize", 1))
+    s.lr, s.lr_final, s.lambda_ = float(o["lr"]), float(o.get("lr_final", 0.0)), float(o.get("lambda", 1.0))
+    s.seed = int(o.get("seed", 0))
+    return s
+
+
+def _dev(a):
+    """Device pointer of a CUDA tensor (the trainer and table calls take device arrays only)."""
+    if a is None:
+        return None
+    if not (hasattr(a, "data_ptr") and a.is_cuda):
+        raise ValueError("device (CUDA) tensor expected")
+    return C.c_void_p(a.data_ptr())
+
+
+def _tcheck(code, t=None):
+    if code < 0:
+        msg = lib.misa_mlp_last_error(t)
+        raise MisaError(code, msg.decode() if msg else "")
+    return code
+
+
+def misa_set_mlp(h, fn, net):
+    n = _net(net)
+    return _check(lib.misa_set_mlp(h, int(fn), C.byref(n)), h)
+
+
+def misa_table_eval(h, fn, x, y, dy):
+    return _check(lib.misa_table_eval(h, int(fn), _dev(x), x.numel(), _dev(y), _dev(dy)), h)
+
+
+def misa_mlp_trainer_create(hip_stream=None):
+    t = C.c_void_p()
+    _tcheck(lib.misa_mlp_trainer_create(C.c_void_p(hip_stream or 0), C.byref(t)))
+    return t
+
+
+def misa_mlp_trainer_destroy(t):
+    return _tcheck(lib.misa_mlp_trainer_destroy(t))
+
+
+def misa_mlp_last_error(t):
+    return lib.misa_mlp_last_error(t).decode()
+
+
+def misa_mlp_trainer_set(t, fn, net):
+    n = _net(net)
+    return _tcheck(lib.misa_mlp_trainer_set(t, int(fn), C.byref(n)), t)
+
+
+def misa_mlp_trainer_get(t, fn):
+    """(network dict with bfloat16-rounded params, float32 master weights)."""
+    n = misa_mlp_net()
+    master = np.empty(MISA_MLP_PARAMS, dtype=np.float32)
+    _tcheck(lib.misa_mlp_trainer_get(t, int(fn), C.byref(n), C.c_void_p(master.ctypes.data)), t)
+    return _net_dict(n), master
+
+
+def misa_mlp_eval(t, fn, path, x, y, dy):
+    return _tcheck(lib.misa_mlp_eval(t, int(fn), int(path), _dev(x), x.numel(), _dev(y), _dev(dy)), t)
+
+
+def misa_mlp_grad(t, fn, x, c_val, c_der, grad):
+    return _tcheck(lib.misa_mlp_grad(t, int(fn), _dev(x), _dev(c_val), _dev(c_der), x.numel(), _dev(grad)), t)
+
+
+def misa_mlp_adam(t, fn, grad, lr):
+    return _tcheck(lib.misa_mlp_adam(t, int(fn), _dev(grad), float(lr)), t)
+
+
+def misa_mlp_fit(t, fn, x, y, dy, opts):
+    loss = C.c_double()
+    o = _opts(opts)
+    _tcheck(lib.misa_mlp_fit(t, int(fn), _dev(x), _dev(y), _dev(dy), x.numel(), C.byref(o), C.byref(loss)), t)
+    return loss.value
+
+
+def misa_mlp_collect(h, sites, r, dhat, fp_j, fp_i, f_ref):
+    """sites: host int64 lattice ids; outputs: CUDA float64 tensors of the documented shapes."""
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    return _check(lib.misa_mlp_collect(h, C.c_void_p(sites.ctypes.data), sites.size, _dev(r), _dev(dhat),
+                                       _dev(fp_j), _dev(fp_i), _dev(f_ref)), h)
+
+
+def misa_mlp_force_match(t, r, dhat, fp_j, fp_i, f_ref, opts):
+    loss = C.c_double()
+    o = _opts(opts)
+    n_env = fp_i.numel()
+    _tcheck(lib.misa_mlp_force_match(t, _dev(r), _dev(dhat), _dev(fp_j), _dev(fp_i), _dev(f_ref), n_env,
+                                     C.byref(o), C.byref(loss)), t)
+    return loss.value
