@@ -33,20 +33,62 @@ METRIC = "atom-steps/s + HBM GB/s: FP64-table vs FP32 vs MLP forms at stated for
 FLOP_CANDIDATE = 8      # separation (3) and squared distance (5) for every stencil candidate
 FLOP_RHO_PAIR = 10      # sqrt, table index (2), cubic (6), accumulate
 FLOP_FORCE_PAIR = 21    # sqrt, index (2), f' and phi' (8), (F'_i+F'_j) f' + phi' (3), / r, x d and accumulate (6)
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "mlp": 2500.0}  # mlp: dense bf16 matrix cores
+# learned form: per network evaluation, the 1-32-32-1 layers' multiply-adds (2 flops each);
+# the rho pass evaluates f (values), the force pass f and phi (values and input tangents)
+FLOP_MLP_VALUE = 2 * (32 + 32 * 32 + 32)
+FLOP_MLP_TANGENT = 2 * FLOP_MLP_VALUE
 HBM_PEAK_GBS = 8000.0
 # bytes each pass must move per atom (each datum once): u, v, F, rho, F' as stored per form
 BYTES_PER_ATOM_STEP = {
     "fp64": {"kick_drift": 120, "rho": 40, "force": 56, "final_kick": 72},
     "fp32": {"kick_drift": 108, "rho": 32, "force": 40, "final_kick": 60},
 }
+BYTES_PER_ATOM_STEP["mlp"] = BYTES_PER_ATOM_STEP["fp32"]
 
 
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7):
+def train_learned_form(seed=11):
+    """The learned form's networks: fit to 1e6 table samples each, then force matching
+    on 1e4 atoms sampled from a C2 cascade run (outside every timed region)."""
+    import torch
+
+    import misa_workloads as w
+    from paper_2107_07866_amd import Lattice, misa as M, surrogate as S
+
+    info = {}
+    t0 = time.time()
+    lat = Lattice(8, w.A_FE, w.RC, w.DELTA, w.MASS_FE, "fp64")
+    lat.set_tables(w.potential_samples())
+    trainer, nets, losses, samples = S.fit_surrogates(lat.h, w.RC, n_samples=1_000_000, seed=seed)
+    torch.cuda.synchronize()
+    lat.close()
+    info["fit_loss"] = {["f", "phi", "F"][k]: v for k, v in losses.items()}
+    info["fit_s"] = round(time.time() - t0, 2)
+    _log(f"[bench] mlp: fitted to table samples in {info['fit_s']} s, losses {info['fit_loss']}")
+    t1 = time.time()
+    data, run = S.cascade_snapshots(w.CONFIGS["c2"], n_env=10_000, snapshots=5, steps_between=200, seed=seed)
+    n_env = data[3].numel()
+    full = dict(batch=n_env, quantize=1, seed=seed)
+    before = M.misa_mlp_force_match(trainer, *data, dict(full, iters=1, lr=1e-12, lr_final=1e-12))
+    M.misa_mlp_force_match(trainer, *data, dict(iters=3000, batch=1024, quantize=1, lr=2e-4, lr_final=1e-6,
+                                                seed=seed))
+    after = M.misa_mlp_force_match(trainer, *data, dict(full, iters=1, lr=1e-12, lr_final=1e-12))
+    nets = {fn: M.misa_mlp_trainer_get(trainer, fn)[0] for fn in (M.MISA_FN_F, M.MISA_FN_PHI, M.MISA_FN_EMB)}
+    M.misa_mlp_trainer_destroy(trainer)
+    del samples
+    info.update(force_match_loss_before=before, force_match_loss_after=after, force_match_atoms=n_env,
+                c2_snapshot_steps=run["steps"], force_match_s=round(time.time() - t1, 2),
+                weights_bytes=3 * M.MISA_MLP_PARAMS * 2, table_bytes_fp64=3 * (w.N_TABLE - 1) * 4 * 8)
+    _log(f"[bench] mlp: force matching on {n_env} atoms from C2 snapshots: loss {before:.3e} -> {after:.3e} "
+         f"({info['force_match_s']} s)")
+    return nets, info
+
+
+def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None):
     import numpy as np
     import torch
 
@@ -57,6 +99,8 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7):
     t0 = time.time()
     lat = Lattice(cfg.n_cells, w.A_FE, w.RC, w.DELTA, w.MASS_FE, form)
     lat.set_tables(tabs)
+    if nets is not None:
+        lat.set_mlp(nets)
     lat.set_state(x, v)
     torch.cuda.synchronize()
     _log(f"[bench] {form}: state loaded in {time.time() - t0:.1f} s ({lat.state_bytes / 1e9:.2f} GB)")
@@ -138,14 +182,17 @@ def roofline(form, res, n_atoms):
     kms = res["kernel_ms_per_step"]
     dom = "force" if kms["force"] >= kms["rho"] else "rho"
     pairs = res.get("mean_pairs_per_atom", 58.0)
-    per_atom = res["K"] * FLOP_CANDIDATE + pairs * (FLOP_FORCE_PAIR if dom == "force" else FLOP_RHO_PAIR)
+    if form == "mlp":  # every stencil candidate runs the networks (the whole wave takes part)
+        per_atom = res["K"] * (2 * FLOP_MLP_TANGENT if dom == "force" else FLOP_MLP_VALUE)
+    else:
+        per_atom = res["K"] * FLOP_CANDIDATE + pairs * (FLOP_FORCE_PAIR if dom == "force" else FLOP_RHO_PAIR)
     flops = n_atoms * per_atom
     avg_ms = kms[dom]
     achieved = flops / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[form]
-    kname = f"k_{dom}_lds" if form == "fp32" else f"k_{dom}_tile<double>"
+    kname = {"fp32": f"k_{dom}_lds", "fp64": f"k_{dom}_tile<double>", "mlp": f"k_{dom}_mlp"}[form]
     traffic = counted_traffic() if (form == "fp32" and dom == "force" and n_atoms == 65536000) else None
-    return {"kernel": kname, "bound": "alu",
+    return {"kernel": kname, "bound": "mfma" if form == "mlp" else "alu",
             "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": traffic, "traffic_unit": "B/launch", "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_flop_per_atom": round(per_atom, 1),
@@ -179,7 +226,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's step count)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
-    ap.add_argument("--forms", default=None, help="comma list of fp32,fp64; first is the headline value")
+    ap.add_argument("--forms", default=None, help="comma list of fp32,fp64,mlp; first is the headline value")
+    ap.add_argument("--mlp-steps", type=int, default=5, help="timed steps of the learned form (it is slower)")
     ap.add_argument("--error-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -208,7 +256,7 @@ def main():
 
     cfg = w.CONFIGS[args.workload]
     steps = args.steps if args.steps is not None else cfg.steps
-    forms = (args.forms or (cfg.precision + "," + ("fp64" if cfg.precision == "fp32" else "fp32"))).split(",")
+    forms = (args.forms or (cfg.precision + "," + ("fp64" if cfg.precision == "fp32" else "fp32") + ",mlp")).split(",")
     torch.cuda.set_device(0)
     t0 = time.time()
     x, v, box, rec = w.make_state(cfg)
@@ -216,7 +264,14 @@ def main():
 
     results = {}
     for form in forms:
-        results[form] = run_form(form, x, v, box, cfg, steps, args.warmup, args.error_sample)
+        if form == "mlp":
+            nets, info = train_learned_form()
+            k = min(steps, args.mlp_steps)
+            results[form] = run_form(form, x, v, box, cfg, k, min(args.warmup, 2), args.error_sample, nets=nets)
+            results[form]["training"] = info
+            results[form]["timed_steps"] = k
+        else:
+            results[form] = run_form(form, x, v, box, cfg, steps, args.warmup, args.error_sample)
     head = results[forms[0]]
     n = x.shape[0]
     bpa = sum(BYTES_PER_ATOM_STEP[forms[0]].values())
@@ -231,7 +286,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if forms[0] == "fp32" else "f64",
+        "dtype": "f64" if forms[0] == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": cfg.name, "atoms": n, "cells": [cfg.n_cells] * 3,
                    "pair_precision": forms[0], "integration": "f64", "dt_max_fs": cfg.dt_max,

@@ -32,14 +32,23 @@ __device__ __forceinline__ uint32_t bf16_bits(float x) {
 
 __device__ __forceinline__ float bf16_float(uint32_t b) { return __uint_as_float(b << 16); }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// Two floats to packed bfloat16 (one v_cvt_pk_bf16_f32, round to nearest even).
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+    const f32x2_t v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
 // x = hi + lo with both terms bfloat16 (relative error of the pair ~2^-17).
 __device__ __forceinline__ void split4(const float (&x)[4], bf16x4_t &hi, bf16x4_t &lo) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t h = bf16_bits(x[i]);
-        hi[i] = (short)h;
-        lo[i] = (short)bf16_bits(x[i] - bf16_float(h));
-    }
+    const uint32_t h01 = pk_bf16(x[0], x[1]), h23 = pk_bf16(x[2], x[3]);
+    const uint32_t l01 = pk_bf16(x[0] - __uint_as_float(h01 << 16), x[1] - __uint_as_float(h01 & 0xffff0000u));
+    const uint32_t l23 = pk_bf16(x[2] - __uint_as_float(h23 << 16), x[3] - __uint_as_float(h23 & 0xffff0000u));
+    const uint2 hv = {h01, h23}, lv = {l01, l23};
+    hi = __builtin_bit_cast(bf16x4_t, hv);
+    lo = __builtin_bit_cast(bf16x4_t, lv);
 }
 
 // Per-unit constants of one network in LDS; float4 q covers units 4q .. 4q + 3.

@@ -89,3 +89,43 @@ def force_match(trainer, data, fm=None):
     loss = M.misa_mlp_force_match(trainer, *data, fm)
     nets = {fn: M.misa_mlp_trainer_get(trainer, fn)[0] for fn in (M.MISA_FN_F, M.MISA_FN_PHI)}
     return loss, nets
+
+
+def cascade_snapshots(cfg, n_env=10_000, snapshots=5, steps_between=200, seed=17, device="cuda"):
+    """Force-matching data from a cascade run of a workload (float64 table form).
+
+    The run starts from the workload's seeded initial state; after every
+    steps_between steps (and at step 0) n_env / snapshots slotted atoms are
+    sampled, half of them the closest to the first recoil atom and half uniformly,
+    and their pair lists and table forces collected.  Returns the five device
+    tensors of misa_mlp_collect, concatenated, and a short record of the run."""
+    import misa_workloads as w
+    from .lattice import Lattice
+
+    x, v, box, rec = w.make_state(cfg)
+    lat = Lattice(cfg.n_cells, w.A_FE, w.RC, w.DELTA, w.MASS_FE, "fp64")
+    lat.set_tables(w.potential_samples())
+    lat.set_state(x, v)
+    rng = np.random.default_rng(seed)
+    per = n_env // snapshots
+    parts, info = [], {"steps": [], "n_runaway": []}
+    L = np.asarray(box)
+    for k in range(snapshots):
+        if k:
+            st = lat.step(steps_between, cfg.dt_max, cfg.dx_max)
+            info["n_runaway"].append(int(st["n_runaway"]))
+        info["steps"].append(k * steps_between)
+        lat.compute(energies=False)
+        xg, _ = lat.get_state()
+        slots = lat.slots()
+        ok = np.nonzero(slots >= 0)[0]
+        centre = xg[rec[0]] if len(rec) else L / 2
+        d = xg[ok] - centre
+        d -= L * np.round(d / L)
+        near = ok[np.argsort((d * d).sum(1))[: per // 2]]
+        rest = np.setdiff1d(ok, near)
+        far = rng.choice(rest, per - len(near), replace=False)
+        parts.append(collect(lat.h, slots[np.concatenate([near, far])], device))
+    lat.close()
+    data = tuple(torch.cat([p[i] for p in parts]) for i in range(5))
+    return data, info
