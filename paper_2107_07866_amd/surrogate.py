@@ -41,7 +41,7 @@ def table_samples(h, fn, lo, hi, n, rng, device="cuda"):
     return x, y, dy
 
 
-DEFAULT_FIT = dict(iters=20000, batch=4096, quantize=1, lr=1e-2, lr_final=1e-5, seed=7)
+DEFAULT_FIT = dict(iters=60000, batch=4096, quantize=1, lr=1e-2, lr_final=1e-6, seed=7)
 
 
 def fit_surrogates(h, rc, n_samples=1_000_000, seed=11, fit=None, ranges=None, trainer=None, device="cuda"):
