@@ -335,6 +335,40 @@ int misa_mlp_force_match(misa_mlp_trainer *t, const double *r, const double *dha
                          const double *fp_i, const double *f_ref, int64_t n_env, const misa_fit_opts *o,
                          double *loss);
 
+/* ---------------------------------------------------------------------------
+ * Batched replicas: many independent periodic boxes stepped together.
+ *
+ * The paper names batch execution of simulations as a use of MISA-MD (Sec. 1);
+ * this is its single-GPU form.  A batch owns one lattice handle per box, all on
+ * one stream, all with pair_precision MISA_FP32 and the same a, rc, delta and
+ * mass (one stencil, one potential).  Boxes may differ in size and in state;
+ * each keeps its own adaptive time step, run-away atoms, hash and statistics.
+ * misa_batch_step advances every box by the same number of steps with one
+ * launch per kernel of the step for the whole batch: the rho and force passes
+ * are single persistent launches over a list of (box, tile) items, the other
+ * kernels take the box from the grid's second dimension.  Results equal those
+ * of misa_step on each box alone, bit for bit.
+ */
+typedef struct misa_batch misa_batch;
+
+/* n_boxes descriptors (host); on success *out owns the batch. */
+int misa_batch_create(const misa_lattice_desc *descs, int32_t n_boxes, void *hip_stream, misa_batch **out);
+int misa_batch_destroy(misa_batch *b);
+const char *misa_batch_last_error(const misa_batch *b);
+
+/* The lattice handle of box k (owned by the batch; bind its state, load atoms,
+ * read results and fields with the single-box calls). */
+int misa_batch_box(misa_batch *b, int32_t k, misa_lattice **out);
+
+/* misa_set_potential_tables on every box. */
+int misa_batch_set_potential_tables(misa_batch *b, const misa_table *f, const misa_table *phi,
+                                    const misa_table *emb);
+
+/* nsteps steps of every box (as misa_step); stats: n_boxes records in host
+ * memory, or NULL.  Synchronises the stream at the end.  MISA_EOVERFLOW if any
+ * box exceeded its run-away capacity (its record says which). */
+int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max, misa_step_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@ no integrator), so both the CPU oracle and the GPU path can consume it.
 """
 from .synth import (  # noqa: F401
     A_FE, RC, DELTA, MASS_FE, KB_EV, ACC_A_FS2, N_TABLE, RHO_MAX,
-    CONFIGS, Config, bcc_positions, thermal_state, add_recoils, make_state,
+    CONFIGS, Config, BATCH_CONFIGS, BatchConfig, bcc_positions, thermal_state, add_recoils, make_state,
+    make_batch,
     potential_samples, analytic_potential_params,
 )

@@ -194,3 +194,46 @@ def potential_samples(n_points=N_TABLE, rc=RC, rho_max=RHO_MAX, variant="raw"):
     rho = np.arange(n_points, dtype=np.float64) * he
     Fy = -EMB_A * np.sqrt(rho)
     return {"f": (0.0, hr, fy), "phi": (0.0, hr, py), "F": (0.0, he, Fy)}
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchConfig:
+    """Batched uneven replicas: independent periodic cubic boxes, one recoil each."""
+    name: str
+    n_boxes: int
+    n_min: int              # cells per axis drawn uniformly from n_min .. n_max
+    n_max: int
+    e_min: float            # recoil energy log-uniform in [e_min, e_max] eV
+    e_max: float
+    steps: int
+    dt_max: float
+    dx_max: float
+    seed: int
+    precision: str = "fp32"
+    temperature: float = 300.0
+    sigma: float = 0.02
+
+
+BATCH_CONFIGS = {
+    "c4": BatchConfig("c4-256-boxes-10to40-recoil0.1to2kev", 256, 10, 40, 100.0, 2000.0, 2000, 1.0, 0.05, 1003),
+}
+
+
+def make_batch(cfg: BatchConfig, n_boxes=None):
+    """Per-box (n_cells, x, v, box, recoil ids, recoil energy) of a batch configuration.
+
+    Box k uses seed cfg.seed * 1000 + k for its thermal state and recoil direction;
+    sizes and energies come from a stream of cfg.seed.  The recoil atom is the one
+    nearest the box centre."""
+    nb = cfg.n_boxes if n_boxes is None else n_boxes
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(cfg.seed)))
+    sizes = rng.integers(cfg.n_min, cfg.n_max + 1, size=cfg.n_boxes)[:nb]
+    energies = np.exp(rng.uniform(math.log(cfg.e_min), math.log(cfg.e_max), size=cfg.n_boxes))[:nb]
+    out = []
+    for k in range(nb):
+        n = int(sizes[k])
+        seed = cfg.seed * 1000 + k
+        x, v, box = thermal_state(n, A_FE, cfg.temperature, cfg.sigma, MASS_FE, seed)
+        rec = add_recoils(x, v, box, 1, float(energies[k]), True, MASS_FE, seed)
+        out.append((n, x, v, box, rec, float(energies[k])))
+    return out

@@ -810,6 +810,224 @@ int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, mis
     return MISA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched replicas
+
+}  // extern "C"
+
+struct misa_batch {
+    hipStream_t stream = nullptr;
+    std::vector<misa_lattice *> box;
+    std::string err;
+    std::vector<BoxRef> ref;
+    std::vector<BoxPass> pass;
+    std::vector<int2> items;
+    BoxRef *d_ref = nullptr;
+    BoxPass *d_pass = nullptr;
+    int2 *d_items = nullptr;
+    int64_t cap_boxes = 0, cap_items = 0;
+};
+
+namespace {
+
+int bfail(misa_batch *b, int code, const std::string &msg) {
+    if (b)
+        b->err = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+
+#define BCHK(b, expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return bfail((b), MISA_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+// Box tables and the (box, tile) work list of the persistent passes, in box order.
+int batch_tables(misa_batch *b) {
+    const int nb = (int)b->box.size();
+    b->ref.resize(nb);
+    b->pass.resize(nb);
+    b->items.clear();
+    for (int k = 0; k < nb; ++k) {
+        misa_lattice *h = b->box[k];
+        b->ref[k] = BoxRef{h->S, h->sc, h->g, h->rcap};
+        b->pass[k] = BoxPass{h->g, pass_ptrs(h)};
+        for (int t = 0; t < h->g.ntiles2; ++t) b->items.push_back(int2{k, t});
+    }
+    if (nb > b->cap_boxes) {
+        (void)hipFree(b->d_ref);
+        (void)hipFree(b->d_pass);
+        b->d_ref = nullptr;
+        b->d_pass = nullptr;
+        b->cap_boxes = 0;
+        BCHK(b, hipMalloc((void **)&b->d_ref, sizeof(BoxRef) * nb));
+        BCHK(b, hipMalloc((void **)&b->d_pass, sizeof(BoxPass) * nb));
+        b->cap_boxes = nb;
+    }
+    if ((int64_t)b->items.size() > b->cap_items) {
+        (void)hipFree(b->d_items);
+        b->d_items = nullptr;
+        b->cap_items = 0;
+        BCHK(b, hipMalloc((void **)&b->d_items, sizeof(int2) * b->items.size()));
+        b->cap_items = (int64_t)b->items.size();
+    }
+    BCHK(b, hipMemcpyAsync(b->d_ref, b->ref.data(), sizeof(BoxRef) * nb, hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipMemcpyAsync(b->d_pass, b->pass.data(), sizeof(BoxPass) * nb, hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipMemcpyAsync(b->d_items, b->items.data(), sizeof(int2) * b->items.size(), hipMemcpyHostToDevice,
+                           b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));  // the host tables may change on the next call
+    return MISA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int misa_batch_create(const misa_lattice_desc *descs, int32_t n_boxes, void *hip_stream, misa_batch **out) {
+    if (!descs || !out || n_boxes < 1) return bfail(nullptr, MISA_EINVAL, "need descriptors, n_boxes >= 1 and out");
+    *out = nullptr;
+    const misa_lattice_desc &d0 = descs[0];
+    for (int k = 0; k < n_boxes; ++k) {
+        const misa_lattice_desc &d = descs[k];
+        if (d.pair_precision != MISA_FP32)
+            return bfail(nullptr, MISA_EINVAL, "batched boxes use pair_precision MISA_FP32");
+        if (d.a != d0.a || d.rc != d0.rc || d.delta != d0.delta || d.mass != d0.mass)
+            return bfail(nullptr, MISA_EINVAL, "batched boxes share a, rc, delta and mass (one stencil, one potential)");
+    }
+    misa_batch *b = new (std::nothrow) misa_batch();
+    if (!b) return bfail(nullptr, MISA_ENOMEM, "host allocation failed");
+    b->stream = (hipStream_t)hip_stream;
+    for (int k = 0; k < n_boxes; ++k) {
+        misa_lattice *h = nullptr;
+        const int rc = misa_create_lattice(&descs[k], hip_stream, &h);
+        if (rc) {
+            const std::string m = "box " + std::to_string(k) + ": " + g_create_error;
+            misa_batch_destroy(b);
+            return bfail(nullptr, rc, m);
+        }
+        b->box.push_back(h);
+    }
+    *out = b;
+    return MISA_OK;
+}
+
+int misa_batch_destroy(misa_batch *b) {
+    if (!b) return MISA_OK;
+    for (misa_lattice *h : b->box) misa_destroy_lattice(h);
+    (void)hipFree(b->d_ref);
+    (void)hipFree(b->d_pass);
+    (void)hipFree(b->d_items);
+    delete b;
+    return MISA_OK;
+}
+
+const char *misa_batch_last_error(const misa_batch *b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+int misa_batch_box(misa_batch *b, int32_t k, misa_lattice **out) {
+    if (!b || !out) return bfail(b, MISA_EINVAL, "null argument");
+    if (k < 0 || k >= (int32_t)b->box.size()) return bfail(b, MISA_EINVAL, "box index out of range");
+    *out = b->box[k];
+    return MISA_OK;
+}
+
+int misa_batch_set_potential_tables(misa_batch *b, const misa_table *f, const misa_table *phi,
+                                    const misa_table *emb) {
+    if (!b) return MISA_EINVAL;
+    for (size_t k = 0; k < b->box.size(); ++k) {
+        const int rc = misa_set_potential_tables(b->box[k], f, phi, emb);
+        if (rc) return bfail(b, rc, "box " + std::to_string(k) + ": " + b->box[k]->err);
+    }
+    return MISA_OK;
+}
+
+int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max, misa_step_stats *stats) {
+    if (!b) return MISA_EINVAL;
+    if (nsteps < 0 || !(dt_max > 0) || !std::isfinite(dt_max) || !std::isfinite(dx_max))
+        return bfail(b, MISA_EINVAL, "nsteps >= 0 and dt_max > 0 required");
+    const int nb = (int)b->box.size();
+    misa_lattice *h0 = b->box[0];
+    int64_t max_sites = 0;
+    int max_mark = 1;
+    for (int k = 0; k < nb; ++k) {
+        misa_lattice *h = b->box[k];
+        int rc = check_ready(h, true);
+        if (rc) return bfail(b, rc, "box " + std::to_string(k) + ": " + h->err);
+        if (!lds_path(h))
+            return bfail(b, MISA_EINVAL, "box " + std::to_string(k) + ": the persistent float32 passes are not usable");
+        // the same stencil and tables serve every box
+        if (h->lds32.nwin != h0->lds32.nwin || h->lds32.k0 != h0->lds32.k0 || h->K != h0->K)
+            return bfail(b, MISA_EINVAL, "boxes differ in tables or stencil");
+        if (!h->force_valid) {
+            if ((rc = do_rho(h)) || (rc = do_force(h, false, nullptr, false)) || (rc = finish_force(h)))
+                return bfail(b, rc, "box " + std::to_string(k) + ": " + h->err);
+        }
+        if (h->pending_clear) {
+            if ((rc = finish_force(h))) return bfail(b, rc, h->err);
+        }
+        if ((rc = [&] { HIPCHK(h, launch_dt_update(h, dt_max, dx_max, true)); return MISA_OK; }()))
+            return bfail(b, rc, h->err);
+        max_sites = std::max<int64_t>(max_sites, h->g.nsites);
+        max_mark = std::max(max_mark, (int)h->sc.mark_nblk);
+    }
+    int rc = batch_tables(b);
+    if (rc) return rc;
+    const int gx_sites = (int)std::min<int64_t>((max_sites + 255) / 256, 512);
+    const int gx_small = 16;
+    const double kf = ACC_UNIT / h0->mass;
+    const hipStream_t st = b->stream;
+    const int nitems = (int)b->items.size();
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const bool last = s == nsteps - 1;
+        BCHK(b, launchb_kick_drift(st, b->d_ref, nb, gx_sites, gx_small, kf));
+        BCHK(b, launchb_rehash(st, b->d_ref, nb, gx_small));
+        BCHK(b, launchb_runaway_build(st, b->d_ref, nb, gx_small));
+        BCHK(b, launch_rho_lds_batch(h0, b->d_pass, b->d_items, nitems));
+        BCHK(b, launchb_runaway_rho(h0, b->d_ref, nb, gx_small, max_mark));
+        BCHK(b, launch_force_lds_batch(h0, b->d_pass, b->d_items, nitems, last, true));
+        BCHK(b, launchb_runaway_force(h0, b->d_ref, nb, gx_small, last));
+        if (last) BCHK(b, launchb_energy_reduce(st, b->d_ref, nb));
+        BCHK(b, launchb_final_kick_runaway(st, b->d_ref, nb, gx_small, kf));
+        BCHK(b, launchb_dt_update(st, b->d_ref, nb, h0->mass, dt_max, dx_max));
+        BCHK(b, launchb_runaway_clear(st, b->d_ref, nb, gx_small));
+    }
+    std::vector<double> scal(8 * (size_t)nb);
+    std::vector<Counters> cnt(nb);
+    for (int k = 0; k < nb; ++k) {
+        misa_lattice *h = b->box[k];
+        h->steps_done += nsteps;
+        h->rho_valid = h->force_valid = true;
+        h->pending_clear = false;
+        if (stats) {
+            BCHK(b, hipMemcpyAsync(&scal[8 * k], h->sc.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+            BCHK(b, hipMemcpyAsync(&cnt[k], h->sc.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        }
+    }
+    BCHK(b, hipStreamSynchronize(st));
+    if (!stats) return MISA_OK;
+    int worst = MISA_OK;
+    for (int k = 0; k < nb; ++k) {
+        misa_step_stats &o = stats[k];
+        const double *sc = &scal[8 * k];
+        std::memset(&o, 0, sizeof(o));
+        o.dt_next = sc[0];
+        o.time = sc[1];
+        o.vmax = sc[2];
+        o.e_kin = sc[3];
+        o.e_emb = nsteps > 0 ? sc[4] : 0.0;
+        o.e_pair = nsteps > 0 ? sc[5] : 0.0;
+        o.steps = b->box[k]->steps_done;
+        o.n_runaway = cnt[k].n_run;
+        o.range_violations = cnt[k].range_viol;
+        o.overflow = cnt[k].overflow;
+        o.dt = sc[6];
+        if (cnt[k].overflow) worst = bfail(b, MISA_EOVERFLOW, "box " + std::to_string(k) + ": run-away capacity exceeded");
+    }
+    return worst;
+}
+
 int misa_set_timing(misa_lattice *h, int enable) {
     if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
     HIPCHK(h, fold_timing(h));

@@ -22,7 +22,7 @@ __device__ __forceinline__ double wave_max_i(double v) {
 // v += (dt/2) C F / m;  u += dt v;  an atom now farther than delta from its
 // site is appended to this step's leavers and its slot emptied.
 template <typename Real>
-__global__ __launch_bounds__(KICK_THREADS) void k_kick_drift(State S, Scratch sc, Geom g, double kf, int64_t rcap) {
+__device__ __forceinline__ void kick_drift_body(State S, Scratch sc, Geom g, double kf, int64_t rcap) {
     const double dt = sc.scal[0];
     const double hk = 0.5 * dt * kf;
     const int64_t room = rcap - sc.cnt->n_run;
@@ -75,7 +75,19 @@ __global__ __launch_bounds__(KICK_THREADS) void k_kick_drift(State S, Scratch sc
     }
 }
 
-__global__ void k_kick_drift_runaway(State S, Scratch sc, Geom g, double kf) {
+template <typename Real>
+__global__ __launch_bounds__(KICK_THREADS) void k_kick_drift(State S, Scratch sc, Geom g, double kf, int64_t rcap) {
+    kick_drift_body<Real>(S, sc, g, kf, rcap);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(KICK_THREADS) void kb_kick_drift(const BoxRef *__restrict__ boxes, double kf) {
+    const BoxRef &B = boxes[blockIdx.y];
+    kick_drift_body<Real>(B.S, B.sc, B.g, kf, B.rcap);
+}
+
+
+__device__ __forceinline__ void kick_drift_runaway_body(State S, Scratch sc, Geom g, double kf) {
     const double dt = sc.scal[0];
     const double hk = 0.5 * dt * kf;
     const int n = sc.cnt->n_run;
@@ -91,6 +103,16 @@ __global__ void k_kick_drift_runaway(State S, Scratch sc, Geom g, double kf) {
         S.r_z[r] = wrap_coord(S.r_z[r] + dt * vz, g.L[2]);
     }
 }
+
+__global__ void k_kick_drift_runaway(State S, Scratch sc, Geom g, double kf) {
+    kick_drift_runaway_body(S, sc, g, kf);
+}
+
+__global__ void kb_kick_drift_runaway(const BoxRef *__restrict__ boxes, double kf) {
+    const BoxRef &B = boxes[blockIdx.y];
+    kick_drift_runaway_body(B.S, B.sc, B.g, kf);
+}
+
 
 // Second half-kick (kick = 1) or plain velocity statistics (kick = 0):
 // per-block max |v|^2 and sum |v|^2 over the lattice atoms.
@@ -138,7 +160,7 @@ __global__ __launch_bounds__(KICK_THREADS) void k_final_kick(State S, Scratch sc
     }
 }
 
-__global__ void k_final_kick_runaway(State S, Scratch sc, double kf) {
+__device__ __forceinline__ void final_kick_runaway_body(State S, Scratch sc, double kf) {
     const double hk = 0.5 * sc.scal[0] * kf;
     const int n = sc.cnt->n_run;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
@@ -148,11 +170,21 @@ __global__ void k_final_kick_runaway(State S, Scratch sc, double kf) {
     }
 }
 
+__global__ void k_final_kick_runaway(State S, Scratch sc, double kf) {
+    final_kick_runaway_body(S, sc, kf);
+}
+
+__global__ void kb_final_kick_runaway(const BoxRef *__restrict__ boxes, double kf) {
+    const BoxRef &B = boxes[blockIdx.y];
+    final_kick_runaway_body(B.S, B.sc, kf);
+}
+
+
 // max |v|, kinetic energy, and the next step length
 // dt = min(dt_max, dx_max / max|v|)  (dx_max <= 0: dt = dt_max).
 // use_aff: lattice atoms next to run-aways were left out of the per-tile partials of
 // the fused kick; their |v|^2 come from the (sorted) affected list.
-__global__ __launch_bounds__(1024) void k_dt_update(State S, Scratch sc, const double *__restrict__ part, int nblk,
+__device__ __forceinline__ void dt_update_body(State S, Scratch sc, const double *__restrict__ part, int nblk,
                                                     int use_aff, double mass, double dt_max, double dx_max,
                                                     int first) {
     __shared__ double red[2][1024 / 64];
@@ -201,6 +233,18 @@ __global__ __launch_bounds__(1024) void k_dt_update(State S, Scratch sc, const d
         sc.scal[3] = 0.5 * mass * b / ACC_UNIT;
     }
 }
+
+__global__ __launch_bounds__(1024) void k_dt_update(State S, Scratch sc, const double *__restrict__ part, int nblk,
+                                                    int use_aff, double mass, double dt_max, double dx_max,
+                                                    int first) {
+    dt_update_body(S, sc, part, nblk, use_aff, mass, dt_max, dx_max, first);
+}
+
+__global__ __launch_bounds__(1024) void kb_dt_update(const BoxRef *__restrict__ boxes, double mass, double dt_max, double dx_max) {
+    const BoxRef &B = boxes[blockIdx.y];
+    dt_update_body(B.S, B.sc, B.sc.part_kick, B.g.ntiles2, 1, mass, dt_max, dx_max, 0);
+}
+
 
 // ---------------------------------------------------------------------------
 // copies out of the store, in atom-id order
@@ -336,6 +380,24 @@ hipError_t launch_dt_update(misa_lattice *h, double dt_max, double dx_max, bool 
     const int nblk = fused ? h->g.ntiles2 : KICK_BLOCKS;
     hipLaunchKernelGGL(k_dt_update, dim3(1), dim3(1024), 0, h->stream, h->S, h->sc, part, nblk, fused ? 1 : 0,
                        h->mass, dt_max, dx_max, first ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Batched: one launch per kernel over every box (blockIdx.y = box).
+hipError_t launchb_kick_drift(hipStream_t st, const BoxRef *boxes, int nbox, int gx_sites, int gx_small, double kf) {
+    hipLaunchKernelGGL(kb_kick_drift<float>, dim3(gx_sites, nbox), dim3(KICK_THREADS), 0, st, boxes, kf);
+    hipLaunchKernelGGL(kb_kick_drift_runaway, dim3(gx_small, nbox), dim3(256), 0, st, boxes, kf);
+    return hipGetLastError();
+}
+
+hipError_t launchb_final_kick_runaway(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small, double kf) {
+    hipLaunchKernelGGL(kb_final_kick_runaway, dim3(gx_small, nbox), dim3(256), 0, st, boxes, kf);
+    return hipGetLastError();
+}
+
+hipError_t launchb_dt_update(hipStream_t st, const BoxRef *boxes, int nbox, double mass, double dt_max,
+                             double dx_max) {
+    hipLaunchKernelGGL(kb_dt_update, dim3(1, nbox), dim3(1024), 0, st, boxes, mass, dt_max, dx_max);
     return hipGetLastError();
 }
 

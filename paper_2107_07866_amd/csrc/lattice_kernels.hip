@@ -310,7 +310,7 @@ hipError_t launch_force(misa_lattice *h, bool energy, bool kick) {
 }
 
 // Final energy sums: per-tile partials and per-run-away terms, fixed order.
-__global__ __launch_bounds__(1024) void k_energy_reduce(const double *__restrict__ part, int ntiles,
+__device__ __forceinline__ void energy_reduce_body(const double *__restrict__ part, int ntiles,
                                                         const double *__restrict__ r_e,
                                                         const Counters *__restrict__ cnt,
                                                         double *__restrict__ scal, double *__restrict__ out) {
@@ -346,6 +346,24 @@ __global__ __launch_bounds__(1024) void k_energy_reduce(const double *__restrict
             out[1] = b;
         }
     }
+}
+
+__global__ __launch_bounds__(1024) void k_energy_reduce(const double *__restrict__ part, int ntiles,
+                                                        const double *__restrict__ r_e,
+                                                        const Counters *__restrict__ cnt,
+                                                        double *__restrict__ scal, double *__restrict__ out) {
+    energy_reduce_body(part, ntiles, r_e, cnt, scal, out);
+}
+
+__global__ __launch_bounds__(1024) void kb_energy_reduce(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    energy_reduce_body(B.sc.part, B.g.ntiles2, B.S.r_e, B.sc.cnt, B.sc.scal, nullptr);
+}
+
+
+hipError_t launchb_energy_reduce(hipStream_t st, const BoxRef *boxes, int nbox) {
+    hipLaunchKernelGGL(kb_energy_reduce, dim3(1, nbox), dim3(1024), 0, st, boxes);
+    return hipGetLastError();
 }
 
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev) {

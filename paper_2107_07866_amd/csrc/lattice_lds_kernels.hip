@@ -26,16 +26,73 @@ __device__ __forceinline__ int wrap2(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-// Next real tile of work-group b at or after iteration it (advances it), or -1.
-__device__ __forceinline__ int next_tile(int b, int &it, int grid, const Geom &g) {
-    const int per = g.ntiles2_pad >> 3;  // tiles per XCD
+// Next real item of work-group b at or after iteration it (advances it), or -1.
+// Items are dealt so that every XCD sweeps one contiguous block of them.
+__device__ __forceinline__ int next_item(int b, int &it, int grid, int n, int n_pad) {
+    const int per = n_pad >> 3;  // items per XCD
     for (;; ++it) {
-        const int j = (b >> 3) + it * (grid >> 3);  // position inside this XCD's block of tiles
+        const int j = (b >> 3) + it * (grid >> 3);  // position inside this XCD's block of items
         if (j >= per) return -1;
-        const int tid = (b & 7) * per + j;
-        if (tid < g.ntiles2) return tid;
+        const int id = (b & 7) * per + j;
+        if (id < n) return id;
     }
 }
+
+// What one tile of a lattice pass needs to know about its box.
+struct TileGeo {
+    int32_t nx, ny, nz, nt0, nt1, pad;
+    int64_t ncell;
+};
+
+__device__ __forceinline__ TileGeo geo_of(const Geom &g) {
+    TileGeo G;
+    G.nx = g.nx;
+    G.ny = g.ny;
+    G.nz = g.nz;
+    G.nt0 = g.nt2[0];
+    G.nt1 = g.nt2[1];
+    G.pad = 0;
+    G.ncell = g.ncell;
+    return G;
+}
+
+// Tiles of one box: item = tile id.
+struct OneBox {
+    TileGeo geo;
+    PassPtrs P;
+    int ntiles, ntiles_pad;
+    __device__ __forceinline__ int next(int b, int &it, int grid) const {
+        return next_item(b, it, grid, ntiles, ntiles_pad);
+    }
+    __device__ __forceinline__ int get(int item, TileGeo &G, PassPtrs &Q) const {
+        G = geo;
+        Q = P;
+        return item;
+    }
+};
+
+// Tiles of many boxes: item -> (box, tile) from a list built on the host.
+struct ManyBoxes {
+    const BoxPass *boxes;
+    const int2 *items;
+    int nitems, nitems_pad;
+    __device__ __forceinline__ int next(int b, int &it, int grid) const {
+        return next_item(b, it, grid, nitems, nitems_pad);
+    }
+    __device__ __forceinline__ int get(int item, TileGeo &G, PassPtrs &Q) const {
+        const int2 bt = items[item];
+        const BoxPass &B = boxes[bt.x];
+        G.nx = B.g.nx;
+        G.ny = B.g.ny;
+        G.nz = B.g.nz;
+        G.nt0 = B.g.nt2[0];
+        G.nt1 = B.g.nt2[1];
+        G.pad = 0;
+        G.ncell = B.g.ncell;
+        Q = B.P;
+        return bt.y;
+    }
+};
 
 constexpr int TILE2_PER_LANE = (TILE2_SITES + TILE2_THREADS - 1) / TILE2_THREADS;
 
@@ -48,11 +105,11 @@ struct TileRegs {
 
 __device__ __forceinline__ void fetch_tile2(TileRegs &R, const double *__restrict__ ux,
                                             const double *__restrict__ uy, const double *__restrict__ uz,
-                                            const float *__restrict__ w_src, const Geom &g, int tid) {
-    const int tx = tid % g.nt2[0];
-    const int tyz = tid / g.nt2[0];
-    const int ty = tyz % g.nt2[1];
-    const int tz = tyz / g.nt2[1];
+                                            const float *__restrict__ w_src, const TileGeo &g, int tid) {
+    const int tx = tid % g.nt0;
+    const int tyz = tid / g.nt0;
+    const int ty = tyz % g.nt1;
+    const int tz = tyz / g.nt1;
     const int bx = tx * T2X - HALO, by = ty * T2Y - HALO, bz = tz * T2Z - HALO;
 #pragma unroll
     for (int j = 0; j < TILE2_PER_LANE; ++j) {
@@ -100,12 +157,12 @@ __device__ __forceinline__ int win_seg(float pp, int nwin, float &t) {
     return (int)__builtin_amdgcn_fmed3f(pp, 0.0f, top);
 }
 
-template <bool kNodeCut>
-__global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(
-    const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
-    float *__restrict__ rho, float *__restrict__ fp, const StencilEntry<float> *__restrict__ st, int K,
-    const Q4<float> *__restrict__ fwin, int k0, int nwin, TabMeta<float> fm, const Q4<float> *__restrict__ etab,
-    TabMeta<float> em, Geom g, uint32_t *__restrict__ range_viol) {
+template <class Src, bool kNodeCut>
+__global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const StencilEntry<float> *__restrict__ st,
+                                                          int K, const Q4<float> *__restrict__ fwin, int k0,
+                                                          int nwin, TabMeta<float> fm,
+                                                          const Q4<float> *__restrict__ etab, TabMeta<float> em,
+                                                          float rc2) {
     __shared__ Q4<float> tile[TILE2_SITES];
     __shared__ float4 ftab[LDS_TAB_SEGS];
     for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) {
@@ -118,23 +175,35 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(
     const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
     const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
     const StencilEntry<float> *sp = st + p * KMAX;
-    const float rc2 = (float)g.rc2;
     const float pc = -fm.x0 * fm.inv_h - (float)k0;  // pp = (r - x0) / h - k0
     int it = 0;
-    int tid = next_tile(blockIdx.x, it, gridDim.x, g);
+    int item = src.next(blockIdx.x, it, gridDim.x);
     TileRegs R;
-    if (tid >= 0) fetch_tile2(R, ux, uy, uz, nullptr, g, tid);
-    while (tid >= 0) {
+    if (item >= 0) {
+        TileGeo G0;
+        PassPtrs P0;
+        const int t0 = src.get(item, G0, P0);
+        fetch_tile2(R, P0.ux, P0.uy, P0.uz, nullptr, G0, t0);
+    }
+    while (item >= 0) {
+        TileGeo G;
+        PassPtrs P;
+        const int tid = src.get(item, G, P);
         __syncthreads();  // previous tile fully consumed (and the table copied)
         store_tile2(tile, R);
         __syncthreads();
         ++it;
-        const int nxt = next_tile(blockIdx.x, it, gridDim.x, g);
-        if (nxt >= 0) fetch_tile2(R, ux, uy, uz, nullptr, g, nxt);  // in flight during this tile
-        const int tx = tid % g.nt2[0];
-        const int tyz = tid / g.nt2[0];
-        const int gx = tx * T2X + lx, gy = (tyz % g.nt2[1]) * T2Y + ly, gz = (tyz / g.nt2[1]) * T2Z + lz;
-        if (gx < g.nx && gy < g.ny && gz < g.nz) {
+        const int nxt = src.next(blockIdx.x, it, gridDim.x);
+        if (nxt >= 0) {
+            TileGeo Gn;
+            PassPtrs Pn;
+            const int ntid = src.get(nxt, Gn, Pn);
+            fetch_tile2(R, Pn.ux, Pn.uy, Pn.uz, nullptr, Gn, ntid);  // in flight during this tile
+        }
+        const int tx = tid % G.nt0;
+        const int tyz = tid / G.nt0;
+        const int gx = tx * T2X + lx, gy = (tyz % G.nt1) * T2Y + ly, gz = (tyz / G.nt1) * T2Z + lz;
+        if (gx < G.nx && gy < G.ny && gz < G.nz) {
             const int me = ((p * P2Z + lz + HALO) * P2Y + ly + HALO) * P2X + lx + HALO;
             const Q4<float> ui = tile[me];
             float acc = 0.0f;
@@ -152,7 +221,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(
                 const float v = ((c.w * t + c.z) * t + c.y) * t + c.x;
                 acc += (kNodeCut || r2 < rc2) ? v : 0.0f;
             }
-            const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+            const int64_t idx = (int64_t)p * G.ncell + ((int64_t)gz * G.ny + gy) * G.nx + gx;
             float fpv = 0.0f;
             bool beyond = false;
             if (ui.x > (float)VACANT_TEST) {
@@ -169,11 +238,11 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(
                 const Q4<float> d = etab[2 * kk + 1];
                 fpv = (d.z * t + d.y) * t + d.x;
             }
-            rho[idx] = acc;
-            fp[idx] = fpv;
-            if (beyond) atomicAdd(range_viol, 1u);
+            P.rho[idx] = acc;
+            P.fp[idx] = fpv;
+            if (beyond) atomicAdd(P.range_viol, 1u);
         }
-        tid = nxt;
+        item = nxt;
     }
 }
 
@@ -190,25 +259,14 @@ __device__ __forceinline__ double wave_max_l(double v) {
 // Fused second half-kick of velocity Verlet: v += (dt/2) C F / m right after F is
 // known, plus per-tile {max |v|^2, sum |v|^2} over atoms that no run-away atom
 // touches (those get their run-away terms, kick and statistics in the fixup pass).
-struct KickArgs {
-    double *vx, *vy, *vz;
-    const uint32_t *mark;
-    const double *scal;  // scal[0] = dt of this step
-    double kf;           // C / m
-    double *part_kick;
-};
-
-template <bool kEnergy, bool kNodeCut, bool kKick>
-__global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
-    const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
-    const float *__restrict__ fp, const float *__restrict__ rho, float *__restrict__ fx, float *__restrict__ fy,
-    float *__restrict__ fz, const StencilEntry<float> *__restrict__ st, int K, const FRec32 *__restrict__ fwin,
-    int k0, int nwin, Tables<float> T, Geom g, double *__restrict__ part, KickArgs kick) {
+template <class Src, bool kEnergy, bool kNodeCut, bool kKick>
+__global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const StencilEntry<float> *__restrict__ st,
+                                                            int K, const FRec32 *__restrict__ fwin, int k0,
+                                                            int nwin, Tables<float> T, float rc2, double kf) {
     __shared__ Q4<float> tile[TILE2_SITES];
     __shared__ float4 fab[LDS_TAB_SEGS];  // {f'0, f'1, f'2, phi'0} per segment
     __shared__ float2 fcc[LDS_TAB_SEGS];  // {phi'1, phi'2}
     __shared__ double red[4][TILE2_THREADS / 64];
-    const double hk = kKick ? 0.5 * kick.scal[0] * kick.kf : 0.0;
     for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) {
         const FRec32 c = fwin[e];
         fab[e] = make_float4(c.a.x, c.a.y, c.b.x, c.b.y);
@@ -222,34 +280,47 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
     const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
     const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
     const StencilEntry<float> *sp = st + p * KMAX;
-    const float rc2 = (float)g.rc2;
     const float inv_h = T.fm.inv_h;
     const float pc = -T.fm.x0 * T.fm.inv_h - (float)k0;  // pp = (r - x0) / h - k0
     const int nlast = T.fm.nseg - 1;
     int it = 0;
-    int tid = next_tile(blockIdx.x, it, gridDim.x, g);
+    int item = src.next(blockIdx.x, it, gridDim.x);
     TileRegs R;
-    if (tid >= 0) fetch_tile2(R, ux, uy, uz, fp, g, tid);
-    while (tid >= 0) {
+    if (item >= 0) {
+        TileGeo G0;
+        PassPtrs P0;
+        const int t0 = src.get(item, G0, P0);
+        fetch_tile2(R, P0.ux, P0.uy, P0.uz, P0.fp, G0, t0);
+    }
+    while (item >= 0) {
+        TileGeo G;
+        PassPtrs P;
+        const int tid = src.get(item, G, P);
         __syncthreads();
         store_tile2(tile, R);
         __syncthreads();
         ++it;
-        const int nxt = next_tile(blockIdx.x, it, gridDim.x, g);
-        if (nxt >= 0) fetch_tile2(R, ux, uy, uz, fp, g, nxt);  // in flight during this tile
-        const int tx = tid % g.nt2[0];
-        const int tyz = tid / g.nt2[0];
-        const int gx = tx * T2X + lx, gy = (tyz % g.nt2[1]) * T2Y + ly, gz = (tyz / g.nt2[1]) * T2Z + lz;
-        const bool active = gx < g.nx && gy < g.ny && gz < g.nz;
-        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+        const int nxt = src.next(blockIdx.x, it, gridDim.x);
+        if (nxt >= 0) {
+            TileGeo Gn;
+            PassPtrs Pn;
+            const int ntid = src.get(nxt, Gn, Pn);
+            fetch_tile2(R, Pn.ux, Pn.uy, Pn.uz, Pn.fp, Gn, ntid);  // in flight during this tile
+        }
+        const double hk = kKick ? 0.5 * P.scal[0] * kf : 0.0;
+        const int tx = tid % G.nt0;
+        const int tyz = tid / G.nt0;
+        const int gx = tx * T2X + lx, gy = (tyz % G.nt1) * T2Y + ly, gz = (tyz / G.nt1) * T2Z + lz;
+        const bool active = gx < G.nx && gy < G.ny && gz < G.nz;
+        const int64_t idx = (int64_t)p * G.ncell + ((int64_t)gz * G.ny + gy) * G.nx + gx;
         double e_emb = 0.0, e_pair = 0.0, kvm = 0.0, kvs = 0.0;
         double v0x = 0.0, v0y = 0.0, v0z = 0.0;
         uint32_t mw = 0u;
         if (kKick && active) {  // issued now, consumed after the pair loop
-            v0x = kick.vx[idx];
-            v0y = kick.vy[idx];
-            v0z = kick.vz[idx];
-            mw = kick.mark[idx >> 5];
+            v0x = P.vx[idx];
+            v0y = P.vy[idx];
+            v0z = P.vz[idx];
+            mw = P.mark[idx >> 5];
         }
         if (active) {
             const int me = ((p * P2Z + lz + HALO) * P2Y + ly + HALO) * P2X + lx + HALO;
@@ -284,23 +355,23 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
             }
             const bool vac = ui.x > (float)VACANT_TEST;
             if (vac) ax = ay = az = 0.0f;
-            fx[idx] = ax;
-            fy[idx] = ay;
-            fz[idx] = az;
+            P.fx[idx] = ax;
+            P.fy[idx] = ay;
+            P.fz[idx] = az;
             if (kKick && !vac) {
                 const double vx = v0x + hk * (double)ax;
                 const double vy = v0y + hk * (double)ay;
                 const double vz = v0z + hk * (double)az;
-                kick.vx[idx] = vx;
-                kick.vy[idx] = vy;
-                kick.vz[idx] = vz;
+                P.vx[idx] = vx;
+                P.vy[idx] = vy;
+                P.vz[idx] = vz;
                 if (!((mw >> (idx & 31)) & 1u)) {
                     kvm = vx * vx + vy * vy + vz * vz;
                     kvs = kvm;
                 }
             }
             if (kEnergy && !vac) {
-                const float rr = rho[idx];
+                const float rr = P.rho[idx];
                 float Fv;
                 if (rr > T.em.x_last) {
                     Fv = T.em.y_last + T.em.d_last * (rr - T.em.x_last);
@@ -342,16 +413,16 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(
                     s3 += red[3][q];
                 }
                 if (kEnergy) {
-                    part[2 * tid] = s0;
-                    part[2 * tid + 1] = s1;
+                    P.part[2 * tid] = s0;
+                    P.part[2 * tid + 1] = s1;
                 }
                 if (kKick) {
-                    kick.part_kick[2 * tid] = m2;
-                    kick.part_kick[2 * tid + 1] = s3;
+                    P.part_kick[2 * tid] = m2;
+                    P.part_kick[2 * tid + 1] = s3;
                 }
             }
         }
-        tid = nxt;
+        item = nxt;
     }
 }
 
@@ -359,25 +430,44 @@ bool lds_path(const misa_lattice *h) {
     return h->precision == MISA_FP32 && !h->use_mlp && h->lds32.usable && h->persistent_grid > 0;
 }
 
-hipError_t launch_rho_lds(misa_lattice *h) {
+PassPtrs pass_ptrs(misa_lattice *h) {
+    PassPtrs P;
+    P.ux = h->S.ux;
+    P.uy = h->S.uy;
+    P.uz = h->S.uz;
+    P.rho = (float *)h->S.rho;
+    P.fp = (float *)h->S.fp;
+    P.fx = (float *)h->S.fx;
+    P.fy = (float *)h->S.fy;
+    P.fz = (float *)h->S.fz;
+    P.vx = h->S.vx;
+    P.vy = h->S.vy;
+    P.vz = h->S.vz;
+    P.mark = h->sc.mark;
+    P.scal = h->sc.scal;
+    P.part = h->sc.part;
+    P.part_kick = h->sc.part_kick;
+    P.range_viol = &h->sc.cnt->range_viol;
+    return P;
+}
+
+static OneBox one_box(misa_lattice *h) {
+    OneBox o;
     const Geom &g = h->g;
-    auto kern = h->lds32.node_cut ? k_rho_lds<true> : k_rho_lds<false>;
-    hipLaunchKernelGGL(kern, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
-                       (float *)h->S.rho, (float *)h->S.fp, h->st32p, h->K, h->lds32.f, h->lds32.k0, h->lds32.nwin,
-                       h->t32.fm, h->t32.emb, h->t32.em, g, &h->sc.cnt->range_viol);
-    return hipGetLastError();
+    o.geo.nx = g.nx;
+    o.geo.ny = g.ny;
+    o.geo.nz = g.nz;
+    o.geo.nt0 = g.nt2[0];
+    o.geo.nt1 = g.nt2[1];
+    o.geo.pad = 0;
+    o.geo.ncell = g.ncell;
+    o.P = pass_ptrs(h);
+    o.ntiles = g.ntiles2;
+    o.ntiles_pad = g.ntiles2_pad;
+    return o;
 }
 
-template <bool kEnergy, bool kKick>
-static void force_lds_variant(misa_lattice *h, const Tables<float> &T, const KickArgs &kick) {
-    auto kern = h->lds32.node_cut ? k_force_lds<kEnergy, true, kKick> : k_force_lds<kEnergy, false, kKick>;
-    hipLaunchKernelGGL(kern, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
-                       (const float *)h->S.fp, (const float *)h->S.rho, (float *)h->S.fx, (float *)h->S.fy,
-                       (float *)h->S.fz, h->st32p, h->K, h->lds32.force, h->lds32.k0, h->lds32.nwin, T, h->g,
-                       h->sc.part, kick);
-}
-
-hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick) {
+static Tables<float> t32_tab(const misa_lattice *h) {
     Tables<float> T;
     T.f = h->t32.f;
     T.force = h->t32.force;
@@ -385,12 +475,49 @@ hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick) {
     T.emb = h->t32.emb;
     T.fm = h->t32.fm;
     T.em = h->t32.em;
-    KickArgs K{h->S.vx, h->S.vy, h->S.vz, h->sc.mark, h->sc.scal, ACC_UNIT / h->mass, h->sc.part_kick};
-    if (energy && kick) force_lds_variant<true, true>(h, T, K);
-    else if (energy) force_lds_variant<true, false>(h, T, K);
-    else if (kick) force_lds_variant<false, true>(h, T, K);
-    else force_lds_variant<false, false>(h, T, K);
+    return T;
+}
+
+// h: the handle whose stencil and tables serve (every box of a batch shares them).
+template <class Src>
+static hipError_t rho_lds_src(misa_lattice *h, const Src &src, int grid) {
+    auto kern = h->lds32.node_cut ? k_rho_lds<Src, true> : k_rho_lds<Src, false>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->lds32.f,
+                       h->lds32.k0, h->lds32.nwin, h->t32.fm, h->t32.emb, h->t32.em, (float)h->g.rc2);
     return hipGetLastError();
+}
+
+template <class Src, bool kEnergy, bool kKick>
+static void force_lds_variant(misa_lattice *h, const Src &src, int grid) {
+    auto kern = h->lds32.node_cut ? k_force_lds<Src, kEnergy, true, kKick> : k_force_lds<Src, kEnergy, false, kKick>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->lds32.force,
+                       h->lds32.k0, h->lds32.nwin, t32_tab(h), (float)h->g.rc2, ACC_UNIT / h->mass);
+}
+
+template <class Src>
+static hipError_t force_lds_src(misa_lattice *h, const Src &src, int grid, bool energy, bool kick) {
+    if (energy && kick) force_lds_variant<Src, true, true>(h, src, grid);
+    else if (energy) force_lds_variant<Src, true, false>(h, src, grid);
+    else if (kick) force_lds_variant<Src, false, true>(h, src, grid);
+    else force_lds_variant<Src, false, false>(h, src, grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_rho_lds(misa_lattice *h) { return rho_lds_src(h, one_box(h), h->persistent_grid); }
+
+hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick) {
+    return force_lds_src(h, one_box(h), h->persistent_grid, energy, kick);
+}
+
+hipError_t launch_rho_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems) {
+    ManyBoxes m{boxes, items, nitems, (nitems + 7) / 8 * 8};
+    return rho_lds_src(h0, m, h0->persistent_grid);
+}
+
+hipError_t launch_force_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems,
+                                  bool energy, bool kick) {
+    ManyBoxes m{boxes, items, nitems, (nitems + 7) / 8 * 8};
+    return force_lds_src(h0, m, h0->persistent_grid, energy, kick);
 }
 
 }  // namespace misa

@@ -193,6 +193,29 @@ struct LdsTables {
     bool node_cut = false;    // last node at rc: a zero record after the window implements the cut-off
 };
 
+// Per-box pointers of the persistent float32 lattice passes.
+struct PassPtrs {
+    const double *ux, *uy, *uz;
+    float *rho, *fp, *fx, *fy, *fz;
+    double *vx, *vy, *vz;
+    const uint32_t *mark;
+    const double *scal;  // scal[0] = dt of the current step
+    double *part, *part_kick;
+    uint32_t *range_viol;
+};
+
+// One box of a batch as the batched kernels read it.
+struct BoxPass {
+    Geom g;
+    PassPtrs P;
+};
+struct BoxRef {
+    State S;
+    Scratch sc;
+    Geom g;
+    int64_t rcap;
+};
+
 // Surrogate networks attached to a handle of the learned form (device copies).
 struct MlpAttached {
     MlpNet net[3];                        // net[f].p -> weights (float32 holding bfloat16 values)
@@ -256,6 +279,11 @@ hipError_t launch_force(misa_lattice *h, bool energy, bool kick);
 bool lds_path(const misa_lattice *h);                  // persistent float32 kernels usable
 hipError_t launch_rho_lds(misa_lattice *h);
 hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick);  // kick: fused second half-kick
+PassPtrs pass_ptrs(misa_lattice *h);
+// batched persistent passes over (box, tile) items; h0 supplies stencil, tables and stream
+hipError_t launch_rho_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems);
+hipError_t launch_force_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems,
+                                  bool energy, bool kick);
 bool fused_kick(const misa_lattice *h);               // the step fuses the final kick into the force pass
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev);
 hipError_t launch_rho_mlp(misa_lattice *h);             // learned form: rho pass with the networks
@@ -269,6 +297,16 @@ hipError_t launch_rehash(misa_lattice *h);             // sort leavers, claims, 
 hipError_t launch_final_kick(misa_lattice *h);         // + vmax / KE partials
 hipError_t launch_dt_update(misa_lattice *h, double dt_max, double dx_max, bool first);
 hipError_t launch_gather_state(misa_lattice *h, double *x, double *v);
+// batched replicas: one launch per kernel over every box (blockIdx.y = box)
+hipError_t launchb_kick_drift(hipStream_t st, const BoxRef *boxes, int nbox, int gx_sites, int gx_small, double kf);
+hipError_t launchb_final_kick_runaway(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small, double kf);
+hipError_t launchb_dt_update(hipStream_t st, const BoxRef *boxes, int nbox, double mass, double dt_max, double dx_max);
+hipError_t launchb_rehash(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
+hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
+hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, int mark_blocks);
+hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, bool energy);
+hipError_t launchb_runaway_clear(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
+hipError_t launchb_energy_reduce(hipStream_t st, const BoxRef *boxes, int nbox);
 hipError_t launch_gather_field(misa_lattice *h, int field, double *out);
 hipError_t launch_gather_slots(misa_lattice *h, int64_t *out);
 

@@ -138,7 +138,7 @@ __device__ __forceinline__ void min_image3(double d[3], const Geom &g) {
 // single-block bitonic sort of 64-bit keys (ascending); mode 0: leavers by atom
 // id, mode 1: run-aways by (coarse cell, list index)
 
-__global__ __launch_bounds__(SORT_THREADS) void k_sort(uint64_t *__restrict__ buf, int mode,
+__device__ __forceinline__ void sort_body(uint64_t *__restrict__ buf, int mode,
                                                         Counters *__restrict__ cnt, int64_t rcap,
                                                         const int32_t *__restrict__ l_id,
                                                         const double *__restrict__ rx, const double *__restrict__ ry,
@@ -209,12 +209,26 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort(uint64_t *__restrict__ bu
         for (int i = threadIdx.x; i < n; i += SORT_THREADS) buf[i] = sh[i];
 }
 
+__global__ __launch_bounds__(SORT_THREADS) void k_sort(uint64_t *__restrict__ buf, int mode,
+                                                        Counters *__restrict__ cnt, int64_t rcap,
+                                                        const int32_t *__restrict__ l_id,
+                                                        const double *__restrict__ rx, const double *__restrict__ ry,
+                                                        const double *__restrict__ rz, Geom g) {
+    sort_body(buf, mode, cnt, rcap, l_id, rx, ry, rz, g);
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void kb_sort(const BoxRef *__restrict__ boxes, int mode) {
+    const BoxRef &B = boxes[blockIdx.y];
+    sort_body(B.sc.sortbuf, mode, B.sc.cnt, B.rcap, B.sc.l_id, B.S.r_x, B.S.r_y, B.S.r_z, B.g);
+}
+
+
 // ---------------------------------------------------------------------------
 // hash update
 
 // Claims: each run-away atom and each leaver of this step that lies within
 // delta of its nearest site, and finds that slot empty, bids with its atom id.
-__global__ void k_claim(State S, Scratch sc, Geom g) {
+__device__ __forceinline__ void claim_body(State S, Scratch sc, Geom g) {
     const int nrun = sc.cnt->n_run;
     const int total = nrun + sc.cnt->n_leave;  // leavers admitted this step (clamped by k_sort)
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
@@ -243,8 +257,18 @@ __global__ void k_claim(State S, Scratch sc, Geom g) {
     }
 }
 
+__global__ void k_claim(State S, Scratch sc, Geom g) {
+    claim_body(S, sc, g);
+}
+
+__global__ void kb_claim(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    claim_body(B.S, B.sc, B.g);
+}
+
+
 // The lowest bidder of each contested slot moves in.
-__global__ void k_settle(State S, Scratch sc, Geom g) {
+__device__ __forceinline__ void settle_body(State S, Scratch sc, Geom g) {
     const int nrun = sc.cnt->n_run;
     const int total = nrun + sc.cnt->n_leave;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
@@ -287,9 +311,19 @@ __global__ void k_settle(State S, Scratch sc, Geom g) {
     }
 }
 
+__global__ void k_settle(State S, Scratch sc, Geom g) {
+    settle_body(S, sc, g);
+}
+
+__global__ void kb_settle(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    settle_body(B.S, B.sc, B.g);
+}
+
+
 // Stable compaction: surviving run-aways keep their order, surviving leavers
 // follow in ascending atom id.  Single work-group.
-__global__ __launch_bounds__(1024) void k_compact(State S, Scratch sc) {
+__device__ __forceinline__ void compact_body(State S, Scratch sc) {
     __shared__ int wsum[1024 / 64];
     __shared__ int base_sh;
     const int nrun = sc.cnt->n_run;
@@ -351,10 +385,20 @@ __global__ __launch_bounds__(1024) void k_compact(State S, Scratch sc) {
     }
 }
 
+__global__ __launch_bounds__(1024) void k_compact(State S, Scratch sc) {
+    compact_body(S, sc);
+}
+
+__global__ __launch_bounds__(1024) void kb_compact(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    compact_body(B.S, B.sc);
+}
+
+
 // ---------------------------------------------------------------------------
 // device hash of run-away atoms
 
-__global__ void k_hash_insert(Scratch sc) {
+__device__ __forceinline__ void hash_insert_body(Scratch sc) {
     const int n = sc.cnt->n_run;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
         const uint64_t v = sc.sortbuf[q];
@@ -376,7 +420,17 @@ __global__ void k_hash_insert(Scratch sc) {
     }
 }
 
-__global__ void k_hash_clear(Scratch sc) {
+__global__ void k_hash_insert(Scratch sc) {
+    hash_insert_body(sc);
+}
+
+__global__ void kb_hash_insert(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    hash_insert_body(B.sc);
+}
+
+
+__device__ __forceinline__ void hash_clear_body(Scratch sc) {
     const int n = sc.cnt->n_run;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
         const bool start = q == 0 || sc.skey[q - 1] != sc.skey[q];
@@ -384,6 +438,16 @@ __global__ void k_hash_clear(Scratch sc) {
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) sc.cnt->n_affected = 0;
 }
+
+__global__ void k_hash_clear(Scratch sc) {
+    hash_clear_body(sc);
+}
+
+__global__ void kb_hash_clear(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    hash_clear_body(B.sc);
+}
+
 
 // Run-away atoms in one of the (up to) 27 coarse cells around x, cell = ax + 3 (ay + 3 az);
 // cells beyond the box's distinct neighbours are empty.  fn(o) for entries first,
@@ -455,7 +519,7 @@ __device__ __forceinline__ bool affected_pair(const double xo[3], const int cj[3
 
 // One wave per run-away atom: rho from lattice sites in its window and from other
 // run-aways; marks every lattice atom it pairs with (they need the reaction term).
-__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(State S, Scratch sc, Geom g,
+__device__ __forceinline__ void runaway_rho_body(State S, Scratch sc, Geom g,
                                                                               Tables<double> T) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6);
@@ -500,10 +564,21 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(St
     }
 }
 
+__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(State S, Scratch sc, Geom g,
+                                                                              Tables<double> T) {
+    runaway_rho_body(S, sc, g, T);
+}
+
+__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kb_runaway_rho(const BoxRef *__restrict__ boxes, Tables<double> T) {
+    const BoxRef &B = boxes[blockIdx.y];
+    runaway_rho_body(B.S, B.sc, B.g, T);
+}
+
+
 // Lattice atoms within rc of run-aways: add the run-away terms to rho, refresh F'.
 // emb: the embedding network of the learned form (an empty range on other handles).
 template <typename Real>
-__global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch sc, Geom g, Tables<double> T,
+__device__ __forceinline__ void affected_rho_body(State S, Scratch sc, Geom g, Tables<double> T,
                                                               Tables<Real> TL, MlpNet emb) {
     int na = sc.cnt->n_affected;
     na = na < sc.affected_cap ? na : (int)sc.affected_cap;
@@ -545,10 +620,23 @@ __global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch s
     }
 }
 
+template <typename Real>
+__global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch sc, Geom g, Tables<double> T,
+                                                              Tables<Real> TL, MlpNet emb) {
+    affected_rho_body<Real>(S, sc, g, T, TL, emb);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(AFF_THREADS) void kb_affected_rho(const BoxRef *__restrict__ boxes, Tables<double> T, Tables<Real> TL, MlpNet emb) {
+    const BoxRef &B = boxes[blockIdx.y];
+    affected_rho_body<Real>(B.S, B.sc, B.g, T, TL, emb);
+}
+
+
 // ---------------------------------------------------------------------------
 // forces
 
-__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(State S, Scratch sc, Geom g,
+__device__ __forceinline__ void runaway_force_body(State S, Scratch sc, Geom g,
                                                                                 Tables<double> T, int real_is_f32,
                                                                                 int energy) {
     const int lane = threadIdx.x & 63;
@@ -610,10 +698,22 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(
     }
 }
 
+__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(State S, Scratch sc, Geom g,
+                                                                                Tables<double> T, int real_is_f32,
+                                                                                int energy) {
+    runaway_force_body(S, sc, g, T, real_is_f32, energy);
+}
+
+__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kb_runaway_force(const BoxRef *__restrict__ boxes, Tables<double> T, int real_is_f32, int energy) {
+    const BoxRef &B = boxes[blockIdx.y];
+    runaway_force_body(B.S, B.sc, B.g, T, real_is_f32, energy);
+}
+
+
 // kick != 0: the force pass already applied the second half-kick with the lattice
 // part of F; add the run-away part's kick here and record |v|^2 for the step statistics.
 template <typename Real>
-__global__ __launch_bounds__(AFF_THREADS) void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T,
+__device__ __forceinline__ void affected_force_body(State S, Scratch sc, Geom g, Tables<double> T,
                                                                 int kick, double kf) {
     int na = sc.cnt->n_affected;
     na = na < sc.affected_cap ? na : (int)sc.affected_cap;
@@ -666,6 +766,19 @@ __global__ __launch_bounds__(AFF_THREADS) void k_affected_force(State S, Scratch
     }
 }
 
+template <typename Real>
+__global__ __launch_bounds__(AFF_THREADS) void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T,
+                                                                int kick, double kf) {
+    affected_force_body<Real>(S, sc, g, T, kick, kf);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(AFF_THREADS) void kb_affected_force(const BoxRef *__restrict__ boxes, Tables<double> T, int kick, double kf) {
+    const BoxRef &B = boxes[blockIdx.y];
+    affected_force_body<Real>(B.S, B.sc, B.g, T, kick, kf);
+}
+
+
 // ---------------------------------------------------------------------------
 // The affected list: every lattice atom a run-away atom paired with, in ascending
 // site order, compacted from the mark bitmap (count, scan, emit), so every pass
@@ -702,9 +815,10 @@ __device__ __forceinline__ void load_mark_words(const Scratch &sc, uint32_t (&m)
     for (int k = 0; k < MARK_WORDS; ++k) c += __popc(m[k]);
 }
 
-__global__ __launch_bounds__(MARK_THREADS) void k_mark_count(Scratch sc) {
+__device__ __forceinline__ void mark_count_body(Scratch sc) {
     __shared__ int shw[MARK_THREADS / 64];
-    if (sc.cnt->n_run == 0) return;  // nothing marked
+    // nothing marked; or a batched grid sized for a larger box
+    if (sc.cnt->n_run == 0 || (int)blockIdx.x >= sc.mark_nblk) return;
     uint32_t m[MARK_WORDS];
     int c, total;
     load_mark_words(sc, m, c);
@@ -712,7 +826,17 @@ __global__ __launch_bounds__(MARK_THREADS) void k_mark_count(Scratch sc) {
     if (threadIdx.x == 0) sc.mark_blk[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(1024) void k_mark_scan(Scratch sc, int nblk) {
+__global__ __launch_bounds__(MARK_THREADS) void k_mark_count(Scratch sc) {
+    mark_count_body(sc);
+}
+
+__global__ __launch_bounds__(MARK_THREADS) void kb_mark_count(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    mark_count_body(B.sc);
+}
+
+
+__device__ __forceinline__ void mark_scan_body(Scratch sc, int nblk) {
     __shared__ int64_t base_sh;
     __shared__ int wsum[1024 / 64];
     if (sc.cnt->n_run == 0) {
@@ -750,9 +874,19 @@ __global__ __launch_bounds__(1024) void k_mark_scan(Scratch sc, int nblk) {
     }
 }
 
-__global__ __launch_bounds__(MARK_THREADS) void k_mark_emit(Scratch sc) {
+__global__ __launch_bounds__(1024) void k_mark_scan(Scratch sc, int nblk) {
+    mark_scan_body(sc, nblk);
+}
+
+__global__ __launch_bounds__(1024) void kb_mark_scan(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    mark_scan_body(B.sc, B.sc.mark_nblk);
+}
+
+
+__device__ __forceinline__ void mark_emit_body(Scratch sc) {
     __shared__ int shw[MARK_THREADS / 64];
-    if (sc.cnt->n_run == 0) return;
+    if (sc.cnt->n_run == 0 || (int)blockIdx.x >= sc.mark_nblk) return;
     uint32_t m[MARK_WORDS];
     int c, total;
     load_mark_words(sc, m, c);
@@ -769,6 +903,16 @@ __global__ __launch_bounds__(MARK_THREADS) void k_mark_emit(Scratch sc) {
         }
     }
 }
+
+__global__ __launch_bounds__(MARK_THREADS) void k_mark_emit(Scratch sc) {
+    mark_emit_body(sc);
+}
+
+__global__ __launch_bounds__(MARK_THREADS) void kb_mark_emit(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    mark_emit_body(B.sc);
+}
+
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -840,6 +984,47 @@ hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick) {
     else
         hipLaunchKernelGGL(k_affected_force<double>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g,
                            t64_of(h), kick ? 1 : 0, kf);
+    return hipGetLastError();
+}
+
+// Batched launches (blockIdx.y = box).  gx_*: blocks per box of the grid-stride kernels.
+hipError_t launchb_rehash(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small) {
+    hipLaunchKernelGGL(kb_sort, dim3(1, nbox), dim3(SORT_THREADS), 0, st, boxes, 0);
+    hipLaunchKernelGGL(kb_claim, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
+    hipLaunchKernelGGL(kb_settle, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
+    hipLaunchKernelGGL(kb_compact, dim3(1, nbox), dim3(1024), 0, st, boxes);
+    return hipGetLastError();
+}
+
+hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small) {
+    hipLaunchKernelGGL(kb_sort, dim3(1, nbox), dim3(SORT_THREADS), 0, st, boxes, 1);
+    hipLaunchKernelGGL(kb_hash_insert, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
+    return hipGetLastError();
+}
+
+hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, int mark_blocks) {
+    hipStream_t st = h0->stream;
+    hipLaunchKernelGGL(kb_runaway_rho, dim3(gx_small, nbox), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, boxes,
+                       t64_of(h0));
+    hipLaunchKernelGGL(kb_mark_count, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
+    hipLaunchKernelGGL(kb_mark_scan, dim3(1, nbox), dim3(1024), 0, st, boxes);
+    hipLaunchKernelGGL(kb_mark_emit, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
+    hipLaunchKernelGGL(kb_affected_rho<float>, dim3(gx_small, nbox), dim3(AFF_THREADS), 0, st, boxes, t64_of(h0),
+                       t32_of(h0), MlpNet{});
+    return hipGetLastError();
+}
+
+hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, bool energy) {
+    hipStream_t st = h0->stream;
+    hipLaunchKernelGGL(kb_runaway_force, dim3(gx_small, nbox), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, boxes,
+                       t64_of(h0), 1, energy ? 1 : 0);
+    hipLaunchKernelGGL(kb_affected_force<float>, dim3(gx_small, nbox), dim3(AFF_THREADS), 0, st, boxes, t64_of(h0),
+                       1, ACC_UNIT / h0->mass);
+    return hipGetLastError();
+}
+
+hipError_t launchb_runaway_clear(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small) {
+    hipLaunchKernelGGL(kb_hash_clear, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
     return hipGetLastError();
 }
 

@@ -39,6 +39,24 @@ class Lattice:
     def set_tables(self, tables):
         M.misa_set_potential_tables(self.h, tables["f"], tables["phi"], tables["F"])
 
+    @classmethod
+    def _adopt(cls, h, n_cells, a, rc, delta, mass, device):
+        """Wrap a handle owned elsewhere (a batch box) and bind a state buffer to it."""
+        self = cls.__new__(cls)
+        self.n_cells = tuple(int(k) for k in n_cells)
+        self.a, self.rc, self.delta, self.mass = float(a), float(rc), float(delta), float(mass)
+        self.precision = "fp32"
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = h
+        self._owned = False
+        nbytes = M.misa_state_bytes(h)
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self._ptr = (self._buf.data_ptr() + 255) // 256 * 256
+        M.misa_bind_state(h, self._ptr, nbytes)
+        self.state_bytes = nbytes
+        return self
+
     def set_mlp(self, nets):
         """nets: {MISA_FN_F: net, MISA_FN_PHI: net, MISA_FN_EMB: net} (learned form only)."""
         for fn, net in nets.items():
@@ -84,9 +102,46 @@ class Lattice:
         return M.misa_get_timing(self.h)
 
     def close(self):
-        if self.h is not None:
+        if self.h is not None and getattr(self, "_owned", True):
             M.misa_destroy_lattice(self.h)
-            self.h = None
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent periodic boxes (batched replicas) stepped by misa_batch_step.
+
+    boxes[k] is a Lattice view of box k (its handle belongs to the batch) with its
+    own torch state buffer; load atoms and read results through it."""
+
+    def __init__(self, box_cells, a, rc, delta, mass, runaway_capacity=0, device="cuda"):
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        cells = [(k, k, k) if isinstance(k, int) else tuple(k) for k in box_cells]
+        self.b = M.misa_batch_create(cells, a, rc, delta, mass, runaway_capacity, self.stream.cuda_stream)
+        self.boxes = [Lattice._adopt(M.misa_batch_box(self.b, k), c, a, rc, delta, mass, device)
+                      for k, c in enumerate(cells)]
+
+    def __len__(self):
+        return len(self.boxes)
+
+    def set_tables(self, tables):
+        M.misa_batch_set_potential_tables(self.b, tables["f"], tables["phi"], tables["F"])
+
+    def step(self, nsteps, dt_max, dx_max=0.0, want_stats=True):
+        return M.misa_batch_step(self.b, len(self.boxes), nsteps, dt_max, dx_max, want_stats)
+
+    def close(self):
+        if self.b is not None:
+            for box in self.boxes:
+                box.h = None
+            M.misa_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -111,6 +111,13 @@ def _load():
         "misa_mlp_fit": ([vp, C.c_int, vp, vp, vp, i64, C.POINTER(misa_fit_opts), dp], C.c_int),
         "misa_mlp_collect": ([vp, vp, i64, vp, vp, vp, vp, vp], C.c_int),
         "misa_mlp_force_match": ([vp, vp, vp, vp, vp, vp, i64, C.POINTER(misa_fit_opts), dp], C.c_int),
+        "misa_batch_create": ([C.POINTER(misa_lattice_desc), C.c_int32, vp, C.POINTER(vp)], C.c_int),
+        "misa_batch_destroy": ([vp], C.c_int),
+        "misa_batch_last_error": ([vp], C.c_char_p),
+        "misa_batch_box": ([vp, C.c_int32, C.POINTER(vp)], C.c_int),
+        "misa_batch_set_potential_tables": ([vp, C.POINTER(misa_table), C.POINTER(misa_table),
+                                             C.POINTER(misa_table)], C.c_int),
+        "misa_batch_step": ([vp, i64, C.c_double, C.c_double, C.POINTER(misa_step_stats)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -384,3 +391,55 @@ def misa_mlp_force_match(t, r, dhat, fp_j, fp_i, f_ref, opts):
     _tcheck(lib.misa_mlp_force_match(t, _dev(r), _dev(dhat), _dev(fp_j), _dev(fp_i), _dev(f_ref), n_env,
                                      C.byref(o), C.byref(loss)), t)
     return loss.value
+
+
+# ---------------------------------------------------------------------------
+# batched replicas
+
+def _bcheck(code, b=None):
+    if code < 0:
+        msg = lib.misa_batch_last_error(b)
+        raise MisaError(code, msg.decode() if msg else "")
+    return code
+
+
+def misa_batch_create(boxes, a, rc, delta, mass, runaway_capacity=0, hip_stream=None):
+    """boxes: list of n_cells triples; every box uses MISA_FP32 and the same a, rc, delta, mass."""
+    n = len(boxes)
+    descs = (misa_lattice_desc * n)()
+    for k, nc in enumerate(boxes):
+        d = descs[k]
+        d.n_cells[:] = [int(c) for c in nc]
+        d.pair_precision, d.a, d.rc, d.delta, d.mass = MISA_FP32, float(a), float(rc), float(delta), float(mass)
+        d.runaway_capacity = int(runaway_capacity)
+    b = C.c_void_p()
+    _bcheck(lib.misa_batch_create(descs, n, C.c_void_p(hip_stream or 0), C.byref(b)))
+    return b
+
+
+def misa_batch_destroy(b):
+    return _bcheck(lib.misa_batch_destroy(b))
+
+
+def misa_batch_last_error(b):
+    return lib.misa_batch_last_error(b).decode()
+
+
+def misa_batch_box(b, k):
+    h = C.c_void_p()
+    _bcheck(lib.misa_batch_box(b, int(k), C.byref(h)), b)
+    return h
+
+
+def misa_batch_set_potential_tables(b, f, phi, emb):
+    tf, kf = _table(*f)
+    tp, kp = _table(*phi)
+    te, ke = _table(*emb)
+    return _bcheck(lib.misa_batch_set_potential_tables(b, C.byref(tf), C.byref(tp), C.byref(te)), b)
+
+
+def misa_batch_step(b, n_boxes, nsteps, dt_max, dx_max=0.0, want_stats=True):
+    st = (misa_step_stats * n_boxes)()
+    code = lib.misa_batch_step(b, int(nsteps), float(dt_max), float(dx_max), st if want_stats else None)
+    _bcheck(code, b)
+    return [st[k].as_dict() for k in range(n_boxes)] if want_stats else None
