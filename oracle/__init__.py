@@ -9,5 +9,5 @@ float64 reference of the surrogate networks' training arithmetic.
 from .oracle import (  # noqa: F401
     ANALYTIC, ANALYTIC_SF, MLP, MLP_PARAMS, TABLE, Potential, mlp_eval, acc_unit, build, eam, eam_sampled, hash_site,
     kinetic, lattice_coords, lattice_id, library_path, nearest_site_brute, neighbours,
-    num_threads, place, rehash, run, site_position, spline_eval, spline_slopes, stencil,
+    num_threads, place, rehash, run, site_position, spline_eval, spline_slopes, stencil, wigner_seitz,
 )

@@ -907,6 +907,38 @@ int64_t orc_hash(int64_t nx, int64_t ny, int64_t nz, double a, const double x[3]
 }
 
 /*
+ * Wigner-Seitz defect count: every atom belongs to the cell of its nearest
+ * lattice site (the hash rule below, which is the nearest site); a site whose
+ * cell holds no atom is a vacancy, every atom beyond the first in a cell an
+ * interstitial.  occ (may be NULL) receives the per-site atom count, indexed
+ * by lattice id.  out[0] = vacancies, out[1] = interstitials.  The paper names
+ * direct defect analysis as a feature (Sec. 1) and counts defects of a cascade
+ * (Sec. 5.1) without fixing the method; this is the textbook one.
+ */
+int orc_wigner_seitz(int64_t nx, int64_t ny, int64_t nz, double a, const double *x, int64_t n, int64_t out[2],
+                     int32_t *occ)
+{
+    const int64_t ns = 2 * nx * ny * nz;
+    int32_t *o = occ ? occ : (int32_t *)malloc(sizeof(int32_t) * (size_t)ns);
+    if (!o) return -1;
+    for (int64_t s = 0; s < ns; ++s) o[s] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double u[3], u2;
+        o[orc_hash(nx, ny, nz, a, x + 3 * i, u, &u2)] += 1;
+    }
+    int64_t vac = 0, inter = 0;
+    for (int64_t s = 0; s < ns; ++s) {
+        if (o[s] == 0) ++vac;
+        if (o[s] > 1) inter += o[s] - 1;
+    }
+    out[0] = vac;
+    out[1] = inter;
+    if (!occ) free(o);
+    return 0;
+}
+
+
+/*
  * Fresh placement of N atoms into the lattice list: an atom is a slot
  * candidate when |x - nearest site| <= delta; among candidates of one site
  * the lowest atom id takes the slot.  slot[i] = lattice id or -1 (clash /

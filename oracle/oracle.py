@@ -334,6 +334,22 @@ def nearest_site_brute(n_cells, a, x):
     return int(s), d2.value
 
 
+def wigner_seitz(n_cells, a, x):
+    """Wigner-Seitz defect count: (vacancies, interstitials, per-site occupancy by lattice id)."""
+    nx, ny, nz = n_cells
+    x = _f64(x, (-1, 3))
+    out = np.zeros(2, dtype=np.int64)
+    occ = np.zeros(2 * nx * ny * nz, dtype=np.int32)
+    lib = _load()
+    lib.orc_wigner_seitz.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_double, _dp, C.c_int64,
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    lib.orc_wigner_seitz.restype = C.c_int
+    if lib.orc_wigner_seitz(nx, ny, nz, float(a), _d(x), x.shape[0], out.ctypes.data_as(C.POINTER(C.c_int64)),
+                            occ.ctypes.data_as(C.POINTER(C.c_int32))) < 0:
+        raise MemoryError("oracle allocation failed")
+    return int(out[0]), int(out[1]), occ
+
+
 def hash_site(n_cells, a, x):
     """Nearest site by the hash rule: (lattice id, u = x - site, |u|^2)."""
     nx, ny, nz = n_cells
