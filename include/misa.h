@@ -216,6 +216,14 @@ int misa_get_atom_field(misa_lattice *h, int field, double *out, int where);
  * negative error code. */
 int64_t misa_debug_export(misa_lattice *h, int what, int64_t *host_out, int64_t capacity);
 
+/* Wigner-Seitz defect count of the current state (the direct defect analysis
+ * the paper names in Sec. 1 and applies to cascades in Sec. 5.1): every atom
+ * belongs to the cell of its nearest lattice site (the hash rule); a site whose
+ * cell is empty is a vacancy, every atom beyond the first in a cell an
+ * interstitial.  counts (host int64[4]): vacancies, interstitials, run-away
+ * atoms, empty slots.  Uses the handle's sort scratch; synchronises the stream. */
+int misa_defects(misa_lattice *h, int64_t *counts);
+
 /* ---------------------------------------------------------------------------
  * Learned form: surrogate networks for the potential functions.
  *
@@ -366,7 +374,8 @@ int misa_batch_set_potential_tables(misa_batch *b, const misa_table *f, const mi
 
 /* nsteps steps of every box (as misa_step); stats: n_boxes records in host
  * memory, or NULL.  Synchronises the stream at the end.  MISA_EOVERFLOW if any
- * box exceeded its run-away capacity (its record says which). */
+ * box exceeded its run-away capacity (its record says which).  With
+ * misa_set_timing on box 0, the batch's kernel times accumulate on box 0. */
 int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max, misa_step_stats *stats);
 
 #ifdef __cplusplus

@@ -979,19 +979,51 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
     const double kf = ACC_UNIT / h0->mass;
     const hipStream_t st = b->stream;
     const int nitems = (int)b->items.size();
+    // kernel timing of the batch, when enabled, accumulates on box 0's timers
     for (int64_t s = 0; s < nsteps; ++s) {
         const bool last = s == nsteps - 1;
-        BCHK(b, launchb_kick_drift(st, b->d_ref, nb, gx_sites, gx_small, kf));
-        BCHK(b, launchb_rehash(st, b->d_ref, nb, gx_small));
-        BCHK(b, launchb_runaway_build(st, b->d_ref, nb, gx_small));
-        BCHK(b, launch_rho_lds_batch(h0, b->d_pass, b->d_items, nitems));
-        BCHK(b, launchb_runaway_rho(h0, b->d_ref, nb, gx_small, max_mark));
-        BCHK(b, launch_force_lds_batch(h0, b->d_pass, b->d_items, nitems, last, true));
-        BCHK(b, launchb_runaway_force(h0, b->d_ref, nb, gx_small, last));
-        if (last) BCHK(b, launchb_energy_reduce(st, b->d_ref, nb));
-        BCHK(b, launchb_final_kick_runaway(st, b->d_ref, nb, gx_small, kf));
-        BCHK(b, launchb_dt_update(st, b->d_ref, nb, h0->mass, dt_max, dx_max));
-        BCHK(b, launchb_runaway_clear(st, b->d_ref, nb, gx_small));
+        {
+            GroupTimer t(h0, MISA_TIMER_KICK);
+            BCHK(b, launchb_kick_drift(st, b->d_ref, nb, gx_sites, gx_small, kf));
+        }
+        {
+            GroupTimer t(h0, MISA_TIMER_RUNAWAY);
+            BCHK(b, launchb_rehash(st, b->d_ref, nb, gx_small));
+            BCHK(b, launchb_runaway_build(st, b->d_ref, nb, gx_small));
+        }
+        {
+            GroupTimer t(h0, MISA_TIMER_RHO);
+            BCHK(b, launch_rho_lds_batch(h0, b->d_pass, b->d_items, nitems));
+        }
+        {
+            GroupTimer t(h0, MISA_TIMER_RUNAWAY);
+            BCHK(b, launchb_runaway_rho(h0, b->d_ref, nb, gx_small, max_mark));
+        }
+        {
+            GroupTimer t(h0, MISA_TIMER_FORCE);
+            BCHK(b, launch_force_lds_batch(h0, b->d_pass, b->d_items, nitems, last, true));
+        }
+        {
+            GroupTimer t(h0, MISA_TIMER_RUNAWAY);
+            BCHK(b, launchb_runaway_force(h0, b->d_ref, nb, gx_small, last));
+        }
+        {
+            GroupTimer t(h0, MISA_TIMER_OTHER);
+            if (last) BCHK(b, launchb_energy_reduce(st, b->d_ref, nb));
+        }
+        {
+            GroupTimer t(h0, MISA_TIMER_KICK);
+            BCHK(b, launchb_final_kick_runaway(st, b->d_ref, nb, gx_small, kf));
+        }
+        {
+            GroupTimer t(h0, MISA_TIMER_OTHER);
+            BCHK(b, launchb_dt_update(st, b->d_ref, nb, h0->mass, dt_max, dx_max));
+        }
+        {
+            GroupTimer t(h0, MISA_TIMER_RUNAWAY);
+            BCHK(b, launchb_runaway_clear(st, b->d_ref, nb, gx_small));
+        }
+        if (h0->timed.size() > 50000) BCHK(b, fold_timing(h0));
     }
     std::vector<double> scal(8 * (size_t)nb);
     std::vector<Counters> cnt(nb);
@@ -1026,6 +1058,26 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         if (cnt[k].overflow) worst = bfail(b, MISA_EOVERFLOW, "box " + std::to_string(k) + ": run-away capacity exceeded");
     }
     return worst;
+}
+
+int misa_defects(misa_lattice *h, int64_t *counts) {
+    int rc = check_ready(h, false);
+    if (rc) return rc;
+    if (!counts) return fail(h, MISA_EINVAL, "null output");
+    HIPCHK(h, ensure_staging(h, 3 * sizeof(unsigned long long)));
+    unsigned long long *d = (unsigned long long *)h->staging;
+    HIPCHK(h, hipMemsetAsync(d, 0, 3 * sizeof(unsigned long long), h->stream));
+    HIPCHK(h, launch_defects(h, d));
+    unsigned long long c[3];
+    int32_t n_run = 0;
+    HIPCHK(h, hipMemcpyAsync(c, d, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&n_run, &h->sc.cnt->n_run, sizeof(n_run), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    counts[0] = (int64_t)(c[0] - c[2]);
+    counts[1] = (int64_t)c[1];
+    counts[2] = n_run;
+    counts[3] = (int64_t)c[0];
+    return MISA_OK;
 }
 
 int misa_set_timing(misa_lattice *h, int enable) {

@@ -309,6 +309,7 @@ hipError_t launchb_runaway_clear(hipStream_t st, const BoxRef *boxes, int nbox, 
 hipError_t launchb_energy_reduce(hipStream_t st, const BoxRef *boxes, int nbox);
 hipError_t launch_gather_field(misa_lattice *h, int field, double *out);
 hipError_t launch_gather_slots(misa_lattice *h, int64_t *out);
+hipError_t launch_defects(misa_lattice *h, unsigned long long *out);  // 3 zeroed device counters
 
 // ----------------------------------------------------------------------------
 // Small device helpers shared by the kernel translation units.

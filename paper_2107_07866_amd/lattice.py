@@ -92,6 +92,9 @@ class Lattice:
     def stencil(self):
         return M.misa_debug_export(self.h, M.MISA_EXPORT_STENCIL)
 
+    def defects(self):
+        return M.misa_defects(self.h)
+
     def step(self, nsteps, dt_max, dx_max=0.0):
         return M.misa_step(self.h, nsteps, dt_max, dx_max)
 

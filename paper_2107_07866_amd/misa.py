@@ -98,6 +98,7 @@ def _load():
         "misa_set_timing": ([vp, C.c_int], C.c_int),
         "misa_get_timing": ([vp, C.POINTER(misa_timing)], C.c_int),
         "misa_debug_export": ([vp, C.c_int, C.POINTER(i64), i64], i64),
+        "misa_defects": ([vp, C.POINTER(i64)], C.c_int),
         "misa_set_mlp": ([vp, C.c_int, C.POINTER(misa_mlp_net)], C.c_int),
         "misa_table_eval": ([vp, C.c_int, vp, i64, vp, vp], C.c_int),
         "misa_mlp_trainer_create": ([vp, C.POINTER(vp)], C.c_int),
@@ -276,6 +277,13 @@ def misa_debug_export(h, what):
     out = np.empty(max(n, 1), dtype=np.int64)
     _check(lib.misa_debug_export(h, what, out.ctypes.data_as(C.POINTER(C.c_int64)), out.size), h)
     return out[:n]
+
+
+def misa_defects(h):
+    """Wigner-Seitz count: dict(vacancies, interstitials, runaway, empty_slots)."""
+    c = (C.c_int64 * 4)()
+    _check(lib.misa_defects(h, c), h)
+    return {"vacancies": c[0], "interstitials": c[1], "runaway": c[2], "empty_slots": c[3]}
 
 
 # ---------------------------------------------------------------------------
