@@ -593,27 +593,65 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
         const double r_lo = h->d_min - 2.0 * delta - 2.0 * f->dx;
         int64_t k0 = (int64_t)std::floor((r_lo - f->x0) / f->dx);
         k0 = std::max<int64_t>(0, std::min<int64_t>(k0, f->n - 2));
-        const int64_t nwin = (f->n - 1) - k0;
-        if (nwin + 1 <= LDS_TAB_SEGS) {  // + 1: the zero record after the window
-            std::vector<Q4<float>> wf(nwin);
-            std::vector<FRec32> wr(nwin);
-            for (int64_t q = 0; q < nwin; ++q) {
-                const SegCoef &a = sf[k0 + q], &b = sp[k0 + q];
-                wf[q] = {(float)a.c0, (float)a.c1, (float)a.c2, (float)a.c3};
-                wr[q].a = make_float2((float)a.d0, (float)a.d1);
-                wr[q].b = make_float2((float)a.d2, (float)b.d0);
-                wr[q].c = make_float2((float)b.d1, (float)b.d2);
+        const double x_last = f->x0 + (f->n - 1) * f->dx;
+        const double r0 = std::max(f->x0 + k0 * f->dx, 1e-3);
+        const double q0 = r0 * r0, q1 = x_last * x_last;
+        const int64_t nwin = LDS_TAB_SEGS - 1;  // + 1: the zero record after the window
+        const double hq = (q1 - q0) / (double)nwin;
+        // the float64 spline (value and d/dr) of a source table at r
+        auto spline = [&](const std::vector<SegCoef> &S, double r, double &v, double &d) {
+            const double p = (r - f->x0) / f->dx;
+            int64_t k = (int64_t)std::floor(p);
+            k = std::max<int64_t>(0, std::min<int64_t>(k, f->n - 2));
+            const double t = p - (double)k;
+            const SegCoef &c = S[k];
+            v = ((c.c3 * t + c.c2) * t + c.c1) * t + c.c0;
+            d = (c.d2 * t + c.d1) * t + c.d0;
+        };
+        std::vector<Q4<float>> wf(nwin);
+        std::vector<FRec32> wr(nwin);
+        for (int64_t s = 0; s < nwin; ++s) {
+            double fv[4], gf[3], gp[3];
+            for (int i = 0; i < 4; ++i) {  // f at t = 0, 1/3, 2/3, 1
+                const double r = std::sqrt(q0 + ((double)s + i / 3.0) * hq);
+                double d;
+                spline(sf, r, fv[i], d);
             }
-            HIPCHK(h, dev_alloc(&W.f, nwin));
-            HIPCHK(h, dev_alloc(&W.force, nwin));
-            HIPCHK(h, hipMemcpy(W.f, wf.data(), sizeof(Q4<float>) * nwin, hipMemcpyHostToDevice));
-            HIPCHK(h, hipMemcpy(W.force, wr.data(), sizeof(FRec32) * nwin, hipMemcpyHostToDevice));
-            W.k0 = (int32_t)k0;
-            W.nwin = (int32_t)nwin;
-            W.usable = true;
-            const double x_last = f->x0 + (f->n - 1) * f->dx;
-            W.node_cut = std::fabs(x_last - h->g.rc) <= 1e-12 * h->g.rc;
+            for (int i = 0; i < 3; ++i) {  // f'/r and phi'/r at t = 0, 1/2, 1
+                const double r = std::sqrt(q0 + ((double)s + 0.5 * i) * hq);
+                double v, d;
+                spline(sf, r, v, d);
+                gf[i] = d / r;
+                spline(sp, r, v, d);
+                gp[i] = d / r;
+            }
+            // Newton forward differences -> power basis in t
+            const double d1 = fv[1] - fv[0], d2 = fv[2] - 2.0 * fv[1] + fv[0],
+                         d3 = fv[3] - 3.0 * fv[2] + 3.0 * fv[1] - fv[0];
+            wf[s] = {(float)fv[0], (float)(3.0 * d1 - 1.5 * d2 + d3), (float)(4.5 * d2 - 4.5 * d3), (float)(4.5 * d3)};
+            auto quad = [](const double y[3], double &a0, double &a1, double &a2) {
+                const double e1 = y[1] - y[0], e2 = y[2] - 2.0 * y[1] + y[0];
+                a0 = y[0];
+                a1 = 2.0 * e1 - e2;
+                a2 = 2.0 * e2;
+            };
+            double f0, f1, f2, p0, p1, p2;
+            quad(gf, f0, f1, f2);
+            quad(gp, p0, p1, p2);
+            wr[s].a = make_float2((float)f0, (float)f1);
+            wr[s].b = make_float2((float)f2, (float)p0);
+            wr[s].c = make_float2((float)p1, (float)p2);
         }
+        HIPCHK(h, dev_alloc(&W.f, nwin));
+        HIPCHK(h, dev_alloc(&W.force, nwin));
+        HIPCHK(h, hipMemcpy(W.f, wf.data(), sizeof(Q4<float>) * nwin, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(W.force, wr.data(), sizeof(FRec32) * nwin, hipMemcpyHostToDevice));
+        W.k0 = (int32_t)k0;
+        W.nwin = (int32_t)nwin;
+        W.inv_hq = (float)(1.0 / hq);
+        W.pcq = (float)(-q0 / hq);
+        W.usable = q1 > q0;
+        W.node_cut = std::fabs(x_last - h->g.rc) <= 1e-12 * h->g.rc;
     }
     h->tables_set = true;
     h->rho_valid = h->force_valid = false;

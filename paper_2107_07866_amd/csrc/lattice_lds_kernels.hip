@@ -2,14 +2,18 @@
 //
 // Same gather as the generic tile kernels, reorganised for the table look-ups
 // that dominate the pair loop (the same pressure the paper meets on the 64 KiB
-// local store, Sec. 4.1): each work-group copies, once, the window of the f /
-// phi coefficient records that pairs of slotted atoms can reach
-// (r >= nearest-site distance - 2 delta) into LDS, then loops over 8 x 8 x 8-cell
+// local store, Sec. 4.1): each work-group copies, once, the window of f / phi
+// records that pairs of slotted atoms can reach (r >= nearest-site distance -
+// 2 delta) into LDS, then loops over 8 x 8 x 8-cell
 // tiles, each staged with its periodic halo.  Work-groups are sized to one per
 // compute unit; tiles are dealt out so every XCD sweeps one contiguous block of
 // tiles (halo re-reads stay in that XCD's L2).  The next tile's displacements are
 // fetched into registers while the current tile computes (the GPU counterpart of
 // the paper's double-buffered DMA, Sec. 4.3).
+//
+// The window is re-tabulated from the spline on an equidistant grid in q = r^2,
+// with the force records holding f'(r)/r and phi'(r)/r, so a pair costs no square
+// root and no reciprocal (each a quarter-rate transcendental).
 //
 // The pair loop is branch-free and unrolled: every stencil candidate runs the
 // full arithmetic and out-of-range pairs are dropped by a select (or read a zero
@@ -146,10 +150,10 @@ __device__ __forceinline__ void store_tile2(Q4<float> *__restrict__ tile, const 
     }
 }
 
-// Local segment index and offset t for pp = (r - x0) / h - k0 (the window starts
-// at segment k0).  With kNodeCut the last node sits at the cut-off and the window
-// ends with a zero record at local index nwin: pairs at or beyond the cut-off read
-// zeros, so no separate cut-off select is needed.
+// Local segment index and offset t for pp = (q - q0) / hq on the window's q = r^2
+// grid.  With kNodeCut the last node sits at the cut-off and the window ends with
+// a zero record at local index nwin: pairs at or beyond the cut-off read zeros, so
+// no separate cut-off select is needed.
 template <bool kNodeCut>
 __device__ __forceinline__ int win_seg(float pp, int nwin, float &t) {
     const float top = kNodeCut ? (float)nwin : (float)(nwin - 1);
@@ -159,10 +163,9 @@ __device__ __forceinline__ int win_seg(float pp, int nwin, float &t) {
 
 template <class Src, bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const StencilEntry<float> *__restrict__ st,
-                                                          int K, const Q4<float> *__restrict__ fwin, int k0,
-                                                          int nwin, TabMeta<float> fm,
-                                                          const Q4<float> *__restrict__ etab, TabMeta<float> em,
-                                                          float rc2) {
+                                                          int K, const Q4<float> *__restrict__ fwin, float inv_hq,
+                                                          float pcq, int nwin, const Q4<float> *__restrict__ etab,
+                                                          TabMeta<float> em, float rc2) {
     __shared__ Q4<float> tile[TILE2_SITES];
     __shared__ float4 ftab[LDS_TAB_SEGS];
     for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) {
@@ -175,7 +178,6 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
     const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
     const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
     const StencilEntry<float> *sp = st + p * KMAX;
-    const float pc = -fm.x0 * fm.inv_h - (float)k0;  // pp = (r - x0) / h - k0
     int it = 0;
     int item = src.next(blockIdx.x, it, gridDim.x);
     TileRegs R;
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
                 const float dz = (uj.z - ui.z) + e.oz;
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 float t;
-                const int s = win_seg<kNodeCut>(__builtin_amdgcn_sqrtf(r2) * fm.inv_h + pc, nwin, t);
+                const int s = win_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);  // q = r^2 grid
                 const float4 c = ftab[s];
                 const float v = ((c.w * t + c.z) * t + c.y) * t + c.x;
                 acc += (kNodeCut || r2 < rc2) ? v : 0.0f;
@@ -261,8 +263,9 @@ __device__ __forceinline__ double wave_max_l(double v) {
 // touches (those get their run-away terms, kick and statistics in the fixup pass).
 template <class Src, bool kEnergy, bool kNodeCut, bool kKick>
 __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const StencilEntry<float> *__restrict__ st,
-                                                            int K, const FRec32 *__restrict__ fwin, int k0,
-                                                            int nwin, Tables<float> T, float rc2, double kf) {
+                                                            int K, const FRec32 *__restrict__ fwin, float inv_hq,
+                                                            float pcq, int nwin, Tables<float> T, float rc2,
+                                                            double kf) {
     __shared__ Q4<float> tile[TILE2_SITES];
     __shared__ float4 fab[LDS_TAB_SEGS];  // {f'0, f'1, f'2, phi'0} per segment
     __shared__ float2 fcc[LDS_TAB_SEGS];  // {phi'1, phi'2}
@@ -280,8 +283,6 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
     const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
     const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
     const StencilEntry<float> *sp = st + p * KMAX;
-    const float inv_h = T.fm.inv_h;
-    const float pc = -T.fm.x0 * T.fm.inv_h - (float)k0;  // pp = (r - x0) / h - k0
     const int nlast = T.fm.nseg - 1;
     int it = 0;
     int item = src.next(blockIdx.x, it, gridDim.x);
@@ -334,22 +335,23 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
                 const float dy = (uj.y - ui.y) + e.oy;
                 const float dz = (uj.z - ui.z) + e.oz;
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                const float rinv = __builtin_amdgcn_rsqf(r2);
                 float t;
-                const int s = win_seg<kNodeCut>((r2 * rinv) * inv_h + pc, nwin, t);
+                const int s = win_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);  // q = r^2 grid
                 const float4 a = fab[s];
                 const float2 c = fcc[s];
-                const float dfr = (a.z * t + a.y) * t + a.x;  // f'(r)
-                const float dph = (c.y * t + c.x) * t + a.w;  // phi'(r)
-                float sc = ((ui.w + uj.w) * dfr + dph) * rinv;
+                const float gf = (a.z * t + a.y) * t + a.x;  // f'(r) / r
+                const float gp = (c.y * t + c.x) * t + a.w;  // phi'(r) / r
+                float sc = (ui.w + uj.w) * gf + gp;
                 if (!kNodeCut) sc = r2 < rc2 ? sc : 0.0f;
                 ax += sc * dx;
                 ay += sc * dy;
                 az += sc * dz;
-                if (kEnergy) {
-                    const int sg = min(s + k0, nlast);
+                if (kEnergy) {  // last step only: phi(r) from the r-grid records
+                    const float pr = (__builtin_amdgcn_sqrtf(r2) - T.fm.x0) * T.fm.inv_h;
+                    const int sg = max(0, min((int)pr, nlast));
+                    const float tr = pr - (float)sg;
                     const Q4<float> cp = T.phi[sg];
-                    const float v = ((cp.w * t + cp.z) * t + cp.y) * t + cp.x;
+                    const float v = ((cp.w * tr + cp.z) * tr + cp.y) * tr + cp.x;
                     ep += (kNodeCut ? s < nwin : r2 < rc2) ? v : 0.0f;  // same pair set as the force
                 }
             }
@@ -483,7 +485,7 @@ template <class Src>
 static hipError_t rho_lds_src(misa_lattice *h, const Src &src, int grid) {
     auto kern = h->lds32.node_cut ? k_rho_lds<Src, true> : k_rho_lds<Src, false>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->lds32.f,
-                       h->lds32.k0, h->lds32.nwin, h->t32.fm, h->t32.emb, h->t32.em, (float)h->g.rc2);
+                       h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, h->t32.emb, h->t32.em, (float)h->g.rc2);
     return hipGetLastError();
 }
 
@@ -491,7 +493,8 @@ template <class Src, bool kEnergy, bool kKick>
 static void force_lds_variant(misa_lattice *h, const Src &src, int grid) {
     auto kern = h->lds32.node_cut ? k_force_lds<Src, kEnergy, true, kKick> : k_force_lds<Src, kEnergy, false, kKick>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->lds32.force,
-                       h->lds32.k0, h->lds32.nwin, t32_tab(h), (float)h->g.rc2, ACC_UNIT / h->mass);
+                       h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, t32_tab(h), (float)h->g.rc2,
+                       ACC_UNIT / h->mass);
 }
 
 template <class Src>

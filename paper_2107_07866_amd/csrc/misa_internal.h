@@ -178,17 +178,24 @@ struct DevTables {
     TabMeta<Real> fm{}, em{};
 };
 
-// Force record of one segment as staged in LDS: {f'0, f'1}, {f'2, phi'0}, {phi'1, phi'2}.
+// Force record of one q segment as staged in LDS: {g_f0, g_f1}, {g_f2, g_p0}, {g_p1, g_p2} with
+// g_f = f'(r) / r and g_p = phi'(r) / r as quadratics in t.
 struct alignas(8) FRec32 {
     float2 a, b, c;
 };
 
-// Window [k0, k0 + nwin) of the f / phi segments that pairs of slotted atoms can
-// reach (r >= nearest-site distance - 2 delta), laid out for LDS staging.
+// Window of f and phi that pairs of slotted atoms can reach (r >= nearest-site
+// distance - 2 delta), re-tabulated on an equidistant grid in q = r^2 for the LDS:
+// segment s covers q in [q0 + s hq, q0 + (s + 1) hq], local t in [0, 1].
+//   f records:     f(q)                 = ((c3 t + c2) t + c1) t + c0
+//   force records: f'(r) / r, phi'(r)/r = (a2 t + a1) t + a0 (quadratics)
+// so the pair loops need neither sqrt(q) nor 1/r.
 struct LdsTables {
     Q4<float> *f = nullptr;   // nwin value records of f
     FRec32 *force = nullptr;  // nwin force records
-    int32_t k0 = 0, nwin = 0;
+    int32_t k0 = 0, nwin = 0; // k0: first r segment of the source tables inside the window
+    float inv_hq = 0.f;       // 1 / hq
+    float pcq = 0.f;          // -q0 / hq:  pp = q inv_hq + pcq
     bool usable = false;
     bool node_cut = false;    // last node at rc: a zero record after the window implements the cut-off
 };
