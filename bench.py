@@ -39,12 +39,13 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "mlp": 2500.0}  # mlp: dense bf16 ma
 FLOP_MLP_VALUE = 2 * (32 + 32 * 32 + 32)
 FLOP_MLP_TANGENT = 2 * FLOP_MLP_VALUE
 HBM_PEAK_GBS = 8000.0
-# bytes each pass must move per atom (each datum once): u, v, F, rho, F' as stored per form
+# bytes each pass must move per atom (each datum once): u, v, F, rho, F' as stored per form.
+# The FP32 form fuses the final half-kick into the force pass (it also reads and writes v).
 BYTES_PER_ATOM_STEP = {
     "fp64": {"kick_drift": 120, "rho": 40, "force": 56, "final_kick": 72},
-    "fp32": {"kick_drift": 108, "rho": 32, "force": 40, "final_kick": 60},
+    "fp32": {"kick_drift": 108, "rho": 32, "force": 88, "final_kick": 0},
+    "mlp": {"kick_drift": 108, "rho": 32, "force": 40, "final_kick": 60},
 }
-BYTES_PER_ATOM_STEP["mlp"] = BYTES_PER_ATOM_STEP["fp32"]
 
 
 def _log(msg):

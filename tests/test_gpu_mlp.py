@@ -288,3 +288,35 @@ def test_force_matching_loss_and_descent(M, trainer, torch_cuda):
     _say(f"after 300 full-batch steps {l1:.6e}")
     assert l1 < l0
     lat.close()
+
+
+def test_mlp_form_runaway_pairs_use_the_tables(M, trainer, torch_cuda, orc):
+    """With run-away atoms present, their pairs take the float64 tables in the learned form
+    too: a run-away atom's force equals the float32 table form's up to the networks' F'
+    error of its lattice partners (the run-away kernels are shared by both forms)."""
+    torch = torch_cuda
+    lat64 = _lattice(6, "fp64")
+    nets, _, _ = _quick_fit(M, torch, trainer, lat64, iters=8000, seed=51)
+    lat64.close()
+    n = (8, 8, 8)
+    x, v, _ = w.thermal_state(n, seed=9)
+    extra = np.array([[2.5 * A + 0.05, 2.0 * A - 0.03, 2.0 * A + 0.02], [5.3 * A, 4.6 * A, 1.2 * A]])
+    x = np.vstack([x, extra])
+    v = np.vstack([v, np.zeros((2, 3))])
+    out = {}
+    for form in ("mlp", "fp32"):
+        lat = _lattice(n, form)
+        if form == "mlp":
+            lat.set_mlp(nets)
+        lat.set_state(x, v)
+        lat.compute(energies=False)
+        torch.cuda.synchronize()
+        slots = lat.slots()
+        out[form] = (lat.forces(), np.nonzero(slots < 0)[0])
+        lat.close()
+    F_mlp, run = out["mlp"]
+    F_tab, run_t = out["fp32"]
+    assert len(run) >= 2 and np.array_equal(run, run_t)
+    err = np.abs(F_mlp[run] - F_tab[run]).max() / np.abs(F_tab[run]).max()
+    print(f"run-away forces, learned vs table form: {err:.2e} ({len(run)} run-away atoms)", flush=True)
+    assert err < 1e-3
