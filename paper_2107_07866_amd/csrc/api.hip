@@ -433,6 +433,15 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     }
     h->K = (int)st[0].size();
     h->d_min = h->K > 0 ? std::sqrt(st[0][0].d2) : 0.0;  // offsets are sorted nearest first
+    {
+        int kin = 0;
+        while (kin < h->K && st[0][kin].d2 < d->rc * d->rc) ++kin;
+        h->K_in = kin;
+        if (kin < h->K) {  // |u| bound below which entries kin.. cannot reach rc (1e-3 A margin for float32)
+            const double u_cut = 0.5 * (std::sqrt(st[0][kin].d2) - d->rc) - 1e-3;
+            h->u_cut2 = u_cut > 0.0 ? (float)(u_cut * u_cut) : -1.f;
+        }
+    }
     h->stencil_canon.resize(2 * h->K * 3);
     std::vector<StencilEntry<double>> s64(2 * KMAX);
     std::vector<StencilEntry<float>> s32(2 * KMAX), s32p(2 * KMAX);

@@ -79,10 +79,11 @@ __device__ __forceinline__ int wrapg(int i, int n) {
 // Load the tile (interior + halo) of both sublattices into LDS.  w_src (may
 // be null) supplies the fourth component (F' for the force pass).
 template <typename Real>
-__device__ __forceinline__ void load_tile(Q4<Real> *__restrict__ tile, const double *__restrict__ ux,
-                                          const double *__restrict__ uy, const double *__restrict__ uz,
-                                          const Real *__restrict__ w_src, const Geom &g, int bx, int by,
-                                          int bz) {
+__device__ __forceinline__ float load_tile(Q4<Real> *__restrict__ tile, const double *__restrict__ ux,
+                                           const double *__restrict__ uy, const double *__restrict__ uz,
+                                           const Real *__restrict__ w_src, const Geom &g, int bx, int by,
+                                           int bz) {
+    float m = 0.0f;  // largest |u|^2 of the occupied sites this lane loaded
     for (int e = threadIdx.x; e < TILE_SITES; e += TILE_THREADS) {
         int lx = e % PX;
         int r = e / PX;
@@ -98,25 +99,40 @@ __device__ __forceinline__ void load_tile(Q4<Real> *__restrict__ tile, const dou
         q.z = (Real)uz[idx];
         q.w = w_src ? w_src[idx] : (Real)0;
         tile[e] = q;
+        if (q.x < (Real)VACANT_TEST) m = fmaxf(m, (float)(q.x * q.x + q.y * q.y + q.z * q.z));
     }
+    return m;
+}
+
+// Stencil length for this tile (after the tile is in LDS): entries kin .. K - 1 lie
+// beyond rc + 2 u_cut, so when every occupied site of the tile and its halo has
+// |u|^2 < u_cut2 they hold no pair within rc and are skipped.
+__device__ __forceinline__ int tile_length(float m, unsigned *slot, int K, int kin, float u_cut2) {
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(m));  // |u|^2 >= 0: integer order = float order
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(__uint_as_float(*slot) < u_cut2 ? kin : K);
 }
 
 // rho_i = sum_j f(r_ij) over the stencil, then F'(rho_i) (Sec. 2.2 steps 1-2).
 template <typename Real>
 __global__ __launch_bounds__(TILE_THREADS) void k_rho_tile(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
-    Real *__restrict__ rho, Real *__restrict__ fp, const StencilEntry<Real> *__restrict__ st, int K,
-    const Q4<Real> *__restrict__ ftab, TabMeta<Real> fm, const Q4<Real> *__restrict__ etab,
+    Real *__restrict__ rho, Real *__restrict__ fp, const StencilEntry<Real> *__restrict__ st, int K, int kin,
+    float u_cut2, const Q4<Real> *__restrict__ ftab, TabMeta<Real> fm, const Q4<Real> *__restrict__ etab,
     TabMeta<Real> em, Geom g, uint32_t *__restrict__ range_viol) {
     __shared__ Q4<Real> tile[TILE_SITES];
+    __shared__ unsigned umax;
     const int tid = tile_of_block(blockIdx.x, g);
     if (tid >= g.ntiles) return;  // whole work-group leaves together
+    if (threadIdx.x == 0) umax = 0u;
     const int tx = tid % g.ntx;
     const int tyz = tid / g.ntx;
     const int ty = tyz % g.nty;
     const int tz = tyz / g.nty;
-    load_tile<Real>(tile, ux, uy, uz, nullptr, g, tx * TX - HALO, ty * TY - HALO, tz * TZ - HALO);
+    const float m = load_tile<Real>(tile, ux, uy, uz, nullptr, g, tx * TX - HALO, ty * TY - HALO, tz * TZ - HALO);
     __syncthreads();
+    K = tile_length(m, &umax, K, kin, u_cut2);
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // wave-uniform parity: stencil entries are fetched with scalar loads
@@ -169,18 +185,21 @@ template <typename Real, bool kEnergy>
 __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
     const Real *__restrict__ fp, const Real *__restrict__ rho, Real *__restrict__ fx, Real *__restrict__ fy,
-    Real *__restrict__ fz, const StencilEntry<Real> *__restrict__ st, int K, Tables<Real> T, Geom g,
-    double *__restrict__ part) {
+    Real *__restrict__ fz, const StencilEntry<Real> *__restrict__ st, int K, int kin, float u_cut2, Tables<Real> T,
+    Geom g, double *__restrict__ part) {
     __shared__ Q4<Real> tile[TILE_SITES];
     __shared__ double red[2][TILE_THREADS / 64];
+    __shared__ unsigned umax;
     const int tid = tile_of_block(blockIdx.x, g);
     if (tid >= g.ntiles) return;
+    if (threadIdx.x == 0) umax = 0u;
     const int tx = tid % g.ntx;
     const int tyz = tid / g.ntx;
     const int ty = tyz % g.nty;
     const int tz = tyz / g.nty;
-    load_tile<Real>(tile, ux, uy, uz, fp, g, tx * TX - HALO, ty * TY - HALO, tz * TZ - HALO);
+    const float m = load_tile<Real>(tile, ux, uy, uz, fp, g, tx * TX - HALO, ty * TY - HALO, tz * TZ - HALO);
     __syncthreads();
+    K = tile_length(m, &umax, K, kin, u_cut2);
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // wave-uniform parity: stencil entries are fetched with scalar loads
@@ -272,7 +291,8 @@ template <typename Real>
 static hipError_t rho_impl(misa_lattice *h, const StencilEntry<Real> *st, const DevTables<Real> &t) {
     const Geom &g = h->g;
     hipLaunchKernelGGL(k_rho_tile<Real>, dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux, h->S.uy,
-                       h->S.uz, (Real *)h->S.rho, (Real *)h->S.fp, st, h->K, t.f, t.fm, t.emb, t.em, g,
+                       h->S.uz, (Real *)h->S.rho, (Real *)h->S.fp, st, h->K, h->K_in, h->u_cut2, t.f, t.fm, t.emb,
+                       t.em, g,
                        &h->sc.cnt->range_viol);
     return hipGetLastError();
 }
@@ -291,11 +311,12 @@ static hipError_t force_impl(misa_lattice *h, bool energy, const StencilEntry<Re
     if (energy)
         hipLaunchKernelGGL((k_force_tile<Real, true>), dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux,
                            h->S.uy, h->S.uz, (const Real *)h->S.fp, (const Real *)h->S.rho, (Real *)h->S.fx,
-                           (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, T, g, h->sc.part);
+                           (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, h->K_in, h->u_cut2, T, g, h->sc.part);
     else
         hipLaunchKernelGGL((k_force_tile<Real, false>), dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream,
                            h->S.ux, h->S.uy, h->S.uz, (const Real *)h->S.fp, (const Real *)h->S.rho,
-                           (Real *)h->S.fx, (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, T, g, h->sc.part);
+                           (Real *)h->S.fx, (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, h->K_in, h->u_cut2, T, g,
+                           h->sc.part);
     return hipGetLastError();
 }
 

@@ -135,7 +135,10 @@ __device__ __forceinline__ void fetch_tile2(TileRegs &R, const double *__restric
     }
 }
 
-__device__ __forceinline__ void store_tile2(Q4<float> *__restrict__ tile, const TileRegs &R) {
+// Stores this lane's share of the tile; returns the largest |u|^2 among the
+// occupied sites it stored.
+__device__ __forceinline__ float store_tile2(Q4<float> *__restrict__ tile, const TileRegs &R) {
+    float m = 0.0f;
 #pragma unroll
     for (int j = 0; j < TILE2_PER_LANE; ++j) {
         const int e = threadIdx.x + j * TILE2_THREADS;
@@ -146,8 +149,26 @@ __device__ __forceinline__ void store_tile2(Q4<float> *__restrict__ tile, const 
             q.z = (float)R.z[j];
             q.w = R.w[j];
             tile[e] = q;
+            if (q.x < (float)VACANT_TEST) m = fmaxf(m, q.x * q.x + q.y * q.y + q.z * q.z);
         }
     }
+    return m;
+}
+
+// Stencil length for this tile.  The stencil is sorted by |offset|; its first kin
+// entries lie inside rc, the next one at d_next.  A pair (i, i + o) is closer than
+// rc only if |o| < rc + |u_i| + |u_j|, so when every occupied site of the tile and
+// its halo has |u| < u_cut = (d_next - rc) / 2 - margin, entries kin .. K - 1 can
+// hold no pair within rc and are skipped (u_cut < 0 when no entry lies beyond rc).
+// slot: the LDS word of this tile (two words alternate between consecutive tiles).
+__device__ __forceinline__ int tile_stencil_length(float m, unsigned *slot, unsigned *other, int K, int kin,
+                                                   float u_cut2) {
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(m));  // |u|^2 >= 0: integer order = float order
+    __syncthreads();
+    const float umax2 = __uint_as_float(*slot);
+    if (threadIdx.x == 0) *other = 0u;  // cleared for the next tile (read after the next barrier pair)
+    return __builtin_amdgcn_readfirstlane(umax2 < u_cut2 ? kin : K);
 }
 
 // Local segment index and offset t for pp = (q - q0) / hq on the window's q = r^2
@@ -163,11 +184,14 @@ __device__ __forceinline__ int win_seg(float pp, int nwin, float &t) {
 
 template <class Src, bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const StencilEntry<float> *__restrict__ st,
-                                                          int K, const Q4<float> *__restrict__ fwin, float inv_hq,
+                                                          int K, int kin, float u_cut2,
+                                                          const Q4<float> *__restrict__ fwin, float inv_hq,
                                                           float pcq, int nwin, const Q4<float> *__restrict__ etab,
                                                           TabMeta<float> em, float rc2) {
     __shared__ Q4<float> tile[TILE2_SITES];
     __shared__ float4 ftab[LDS_TAB_SEGS];
+    __shared__ unsigned umax_slot[2];
+    if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
     for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) {
         const Q4<float> c = fwin[e];
         ftab[e] = make_float4(c.x, c.y, c.z, c.w);
@@ -192,8 +216,8 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
         PassPtrs P;
         const int tid = src.get(item, G, P);
         __syncthreads();  // previous tile fully consumed (and the table copied)
-        store_tile2(tile, R);
-        __syncthreads();
+        const float m = store_tile2(tile, R);
+        const int Kt = tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2);
         ++it;
         const int nxt = src.next(blockIdx.x, it, gridDim.x);
         if (nxt >= 0) {
@@ -210,7 +234,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
             const Q4<float> ui = tile[me];
             float acc = 0.0f;
 #pragma unroll 4
-            for (int k = 0; k < K; ++k) {
+            for (int k = 0; k < Kt; ++k) {
                 const StencilEntry<float> e = sp[k];
                 const Q4<float> uj = tile[me + e.lds];
                 const float dx = (uj.x - ui.x) + e.ox;
@@ -263,10 +287,13 @@ __device__ __forceinline__ double wave_max_l(double v) {
 // touches (those get their run-away terms, kick and statistics in the fixup pass).
 template <class Src, bool kEnergy, bool kNodeCut, bool kKick>
 __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const StencilEntry<float> *__restrict__ st,
-                                                            int K, const FRec32 *__restrict__ fwin, float inv_hq,
+                                                            int K, int kin, float u_cut2,
+                                                            const FRec32 *__restrict__ fwin, float inv_hq,
                                                             float pcq, int nwin, Tables<float> T, float rc2,
                                                             double kf) {
     __shared__ Q4<float> tile[TILE2_SITES];
+    __shared__ unsigned umax_slot[2];
+    if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
     __shared__ float4 fab[LDS_TAB_SEGS];  // {f'0, f'1, f'2, phi'0} per segment
     __shared__ float2 fcc[LDS_TAB_SEGS];  // {phi'1, phi'2}
     __shared__ double red[4][TILE2_THREADS / 64];
@@ -298,8 +325,8 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
         PassPtrs P;
         const int tid = src.get(item, G, P);
         __syncthreads();
-        store_tile2(tile, R);
-        __syncthreads();
+        const float m = store_tile2(tile, R);
+        const int Kt = tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2);
         ++it;
         const int nxt = src.next(blockIdx.x, it, gridDim.x);
         if (nxt >= 0) {
@@ -328,7 +355,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
             const Q4<float> ui = tile[me];
             float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
 #pragma unroll 4
-            for (int k = 0; k < K; ++k) {
+            for (int k = 0; k < Kt; ++k) {
                 const StencilEntry<float> e = sp[k];
                 const Q4<float> uj = tile[me + e.lds];
                 const float dx = (uj.x - ui.x) + e.ox;
@@ -484,17 +511,18 @@ static Tables<float> t32_tab(const misa_lattice *h) {
 template <class Src>
 static hipError_t rho_lds_src(misa_lattice *h, const Src &src, int grid) {
     auto kern = h->lds32.node_cut ? k_rho_lds<Src, true> : k_rho_lds<Src, false>;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->lds32.f,
-                       h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, h->t32.emb, h->t32.em, (float)h->g.rc2);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->K_in,
+                       h->u_cut2, h->lds32.f, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, h->t32.emb, h->t32.em,
+                       (float)h->g.rc2);
     return hipGetLastError();
 }
 
 template <class Src, bool kEnergy, bool kKick>
 static void force_lds_variant(misa_lattice *h, const Src &src, int grid) {
     auto kern = h->lds32.node_cut ? k_force_lds<Src, kEnergy, true, kKick> : k_force_lds<Src, kEnergy, false, kKick>;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->lds32.force,
-                       h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, t32_tab(h), (float)h->g.rc2,
-                       ACC_UNIT / h->mass);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->K_in,
+                       h->u_cut2, h->lds32.force, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, t32_tab(h),
+                       (float)h->g.rc2, ACC_UNIT / h->mass);
 }
 
 template <class Src>

@@ -243,6 +243,9 @@ struct misa_lattice {
     double mass = 0.0;
     int64_t rcap = 0;
     int K = 0;                                    // stencil entries per parity
+    int K_in = 0;                                 // entries closer than rc (the stencil is sorted by distance)
+    float u_cut2 = -1.f;                          // tiles whose occupied sites all have |u|^2 below this skip
+                                                  // entries K_in .. K - 1 (no pair there can reach rc)
     std::vector<int64_t> stencil_canon;           // [2][K][3] (dX, dY, dZ)
     misa::StencilEntry<double> *st64 = nullptr;   // device [2][KMAX]
     misa::StencilEntry<float> *st32 = nullptr;
