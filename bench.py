@@ -98,8 +98,11 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None)
 
     tabs = w.potential_samples()
     t0 = time.time()
-    lat = Lattice(cfg.n_cells, w.A_FE, w.RC, w.DELTA, w.MASS_FE, form)
+    half = form == "fp32-half"  # the FP32 form with each pair evaluated once (coloured tiles)
+    lat = Lattice(cfg.n_cells, w.A_FE, w.RC, w.DELTA, w.MASS_FE, "fp32" if half else form)
     lat.set_tables(tabs)
+    if half:
+        lat.set_pair_schedule("half")
     if nets is not None:
         lat.set_mlp(nets)
     lat.set_state(x, v)
@@ -311,7 +314,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's step count)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
-    ap.add_argument("--forms", default=None, help="comma list of fp32,fp64,mlp; first is the headline value")
+    ap.add_argument("--forms", default=None,
+                    help="comma list of fp32,fp64,fp32-half,mlp; first is the headline value (fp32 or fp64)")
     ap.add_argument("--mlp-steps", type=int, default=5, help="timed steps of the learned form (it is slower)")
     ap.add_argument("--error-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -360,7 +364,10 @@ def main():
         return
     cfg = w.CONFIGS[args.workload]
     steps = args.steps if args.steps is not None else cfg.steps
-    forms = (args.forms or (cfg.precision + "," + ("fp64" if cfg.precision == "fp32" else "fp32") + ",mlp")).split(",")
+    forms = (args.forms or (cfg.precision + "," + ("fp64" if cfg.precision == "fp32" else "fp32")
+                            + ",fp32-half,mlp")).split(",")
+    if forms[0] not in ("fp32", "fp64"):
+        raise SystemExit("the first form is the headline value: fp32 or fp64")
     torch.cuda.set_device(0)
     t0 = time.time()
     x, v, box, rec = w.make_state(cfg)

@@ -216,6 +216,23 @@ int misa_get_atom_field(misa_lattice *h, int field, double *out, int where);
  * negative error code. */
 int64_t misa_debug_export(misa_lattice *h, int what, int64_t *host_out, int64_t capacity);
 
+/* Pair schedule of the float32 table form (pair_precision MISA_FP32).
+ *
+ * MISA_PAIRS_GATHER (the default): every atom sums its pairs from its own side,
+ * so each pair is evaluated from both ends; no two threads write one atom.
+ * MISA_PAIRS_HALF: Newton's third law (Sec. 4.2): each unordered pair is
+ * evaluated once, by the end whose lattice offset to the other points into the
+ * forward half space, and its terms go to both atoms.  The write conflicts that
+ * creates are resolved by the colouring idea of Sec. 4.2: tiles are 2-coloured
+ * per axis and run one colour at a time, and inside a tile the partner writes
+ * run in phases that no two waves share, so the result is deterministic.  It
+ * needs every axis to be a multiple of 16 cells (MISA_EINVAL otherwise, or for
+ * a handle that is not MISA_FP32).  Forces agree with the gather schedule to
+ * float32 rounding, not bit for bit.  Batched replicas always gather. */
+#define MISA_PAIRS_GATHER 0
+#define MISA_PAIRS_HALF 1
+int misa_set_pair_schedule(misa_lattice *h, int schedule);
+
 /* Wigner-Seitz defect count of the current state (the direct defect analysis
  * the paper names in Sec. 1 and applies to cascades in Sec. 5.1): every atom
  * belongs to the cell of its nearest lattice site (the hash rule); a site whose

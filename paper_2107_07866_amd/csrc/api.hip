@@ -467,6 +467,40 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
             c[1] = o.dY;
             c[2] = o.dZ;
         }
+    // Half stencil: the entries whose lattice offset points into the forward half
+    // space (dZ > 0, or dZ = 0 and dY > 0, or dZ = dY = 0 and dX > 0), grouped by
+    // phase (dZ, partner parity != own) and nearest first inside a phase (the
+    // stable sort keeps the distance order of st).
+    std::vector<StencilEntry<float>> sh(2 * KMAX, StencilEntry<float>{0, 0.f, 0.f, 0.f});
+    std::vector<int32_t> hmeta(2 * HALF_META, 0);
+    for (int p = 0; p < 2; ++p) {
+        std::vector<std::pair<int, int>> fw;  // (phase, k)
+        for (int k = 0; k < h->K; ++k) {
+            const CanonOffset &o = st[p][k];
+            const bool forward = o.dZ > 0 || (o.dZ == 0 && (o.dY > 0 || (o.dY == 0 && o.dX > 0)));
+            if (!forward) continue;
+            const int pn = ((p + o.dX) % 2 + 2) % 2;
+            fw.push_back({2 * (int)o.dZ + (pn != p ? 1 : 0), k});
+        }
+        std::stable_sort(fw.begin(), fw.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+            return x.first < y.first;
+        });
+        int32_t *m = &hmeta[p * HALF_META];
+        for (int q = 0, n = 0; q <= HALF_PHASES; ++q) {
+            while (n < (int)fw.size() && fw[n].first < q) ++n;
+            m[q] = n;
+        }
+        for (size_t i = 0; i < fw.size(); ++i) {
+            const CanonOffset &o = st[p][fw[i].second];
+            const int pn = ((p + o.dX) % 2 + 2) % 2;
+            const int dcx = (p + o.dX - pn) / 2, dcy = o.dY, dcz = o.dZ;
+            const int lds = (pn - p) * HFZ * HFY * HFX + (dcz * HFY + dcy) * HFX + dcx;
+            sh[p * KMAX + i] = StencilEntry<float>{lds, (float)(o.dX * 0.5 * d->a),
+                                                   (float)((o.dY + 0.5 * pn - 0.5 * p) * d->a),
+                                                   (float)((o.dZ + 0.5 * pn - 0.5 * p) * d->a)};
+            if (o.d2 < d->rc * d->rc) ++m[8 + fw[i].first];
+        }
+    }
 
     // scratch
     Scratch &sc = h->sc;
@@ -490,6 +524,8 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(h->st64, 2 * KMAX);
     ALLOC(h->st32, 2 * KMAX);
     ALLOC(h->st32p, 2 * KMAX);
+    ALLOC(h->sth, 2 * KMAX);
+    ALLOC(h->hmeta, 2 * HALF_META);
     ALLOC(sc.cnt, 1);
     ALLOC(sc.scal, 8);
     ALLOC(sc.part, 2 * (int64_t)g.ntiles_pad + 2 * 1024);
@@ -519,6 +555,8 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     if ((e = hipMemcpy(h->st64, s64.data(), sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->st32, s32.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->st32p, s32p.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(h->sth, sh.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(h->hmeta, hmeta.data(), sizeof(int32_t) * 2 * HALF_META, hipMemcpyHostToDevice)) ||
         (e = hipMemset(sc.cnt, 0, sizeof(Counters))) || (e = hipMemset(sc.scal, 0, 8 * sizeof(double))) ||
         (e = hipMemset(sc.hkey, 0xff, sizeof(int32_t) * (size_t)H)) ||
         (e = hipMemset(sc.mark, 0, sizeof(uint32_t) * (size_t)sc.mark_nwords)) ||
@@ -527,6 +565,9 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
         misa_destroy_lattice(h);
         return fail(nullptr, MISA_EHIP, m);
     }
+    h->half.st = h->sth;
+    h->half.meta = h->hmeta;
+    h->half_fits = g.nx % (2 * T2X) == 0 && g.ny % (2 * T2Y) == 0 && g.nz % (2 * T2Z) == 0;
     *out = h;
     return MISA_OK;
 }
@@ -537,7 +578,8 @@ int misa_destroy_lattice(misa_lattice *h) {
         (void)hipStreamSynchronize(h->stream);
     else
         (void)hipDeviceSynchronize();
-    void *ptrs[] = {h->st64, h->st32, h->st32p, h->lds32.f, h->lds32.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t32.f, h->t32.force,
+    void *ptrs[] = {h->st64, h->st32, h->st32p, h->sth, h->hmeta, h->lds32.f, h->lds32.force, h->lds32h.f,
+                    h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
                     h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,
@@ -591,10 +633,11 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
     if (rc) return rc;
     rc = upload_tables<float>(h, h->t32, sf, sp, se, *f, *emb);
     if (rc) return rc;
-    // LDS window for the persistent float32 kernels: two slotted atoms are never
-    // closer than the nearest-neighbour site distance minus 2 delta.
-    {
-        LdsTables &W = h->lds32;
+    // LDS windows for the persistent float32 kernels (gather passes: 4095 segments;
+    // half-stencil passes, which also hold accumulators in LDS: 2879): two slotted
+    // atoms are never closer than the nearest-neighbour site distance minus 2 delta.
+    for (int wi = 0; wi < 2; ++wi) {
+        LdsTables &W = wi == 0 ? h->lds32 : h->lds32h;
         (void)hipFree(W.f);
         (void)hipFree(W.force);
         W = LdsTables{};
@@ -605,7 +648,7 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
         const double x_last = f->x0 + (f->n - 1) * f->dx;
         const double r0 = std::max(f->x0 + k0 * f->dx, 1e-3);
         const double q0 = r0 * r0, q1 = x_last * x_last;
-        const int64_t nwin = LDS_TAB_SEGS - 1;  // + 1: the zero record after the window
+        const int64_t nwin = (wi == 0 ? LDS_TAB_SEGS : HALF_TAB_SEGS) - 1;  // + 1: the zero record after the window
         const double hq = (q1 - q0) / (double)nwin;
         // the float64 spline (value and d/dr) of a source table at r
         auto spline = [&](const std::vector<SegCoef> &S, double r, double &v, double &d) {
@@ -778,6 +821,21 @@ int misa_get_state(misa_lattice *h, double *x, double *v, int where) {
     if (x) HIPCHK(h, hipMemcpyAsync(x, dx, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, h->stream));
     if (v) HIPCHK(h, hipMemcpyAsync(v, dv, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MISA_OK;
+}
+
+int misa_set_pair_schedule(misa_lattice *h, int schedule) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    if (schedule != MISA_PAIRS_GATHER && schedule != MISA_PAIRS_HALF)
+        return fail(h, MISA_EINVAL, "schedule must be MISA_PAIRS_GATHER or MISA_PAIRS_HALF");
+    if (schedule == MISA_PAIRS_HALF) {
+        if (h->precision != MISA_FP32 || h->use_mlp)
+            return fail(h, MISA_EINVAL, "the half-stencil schedule serves the MISA_FP32 table form only");
+        if (!h->half_fits)
+            return fail(h, MISA_EINVAL, "the half-stencil schedule needs every axis a multiple of 16 cells");
+    }
+    if (schedule != h->pair_schedule) h->rho_valid = h->force_valid = false;
+    h->pair_schedule = schedule;
     return MISA_OK;
 }
 
@@ -1004,6 +1062,8 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         if (rc) return bfail(b, rc, "box " + std::to_string(k) + ": " + h->err);
         if (!lds_path(h))
             return bfail(b, MISA_EINVAL, "box " + std::to_string(k) + ": the persistent float32 passes are not usable");
+        if (h->pair_schedule != MISA_PAIRS_GATHER)
+            return bfail(b, MISA_EINVAL, "box " + std::to_string(k) + ": batched replicas use the gather schedule");
         // the same stencil and tables serve every box
         if (h->lds32.nwin != h0->lds32.nwin || h->lds32.k0 != h0->lds32.k0 || h->K != h0->K)
             return bfail(b, MISA_EINVAL, "boxes differ in tables or stencil");

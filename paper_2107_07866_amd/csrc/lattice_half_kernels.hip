@@ -1,0 +1,488 @@
+// Half-stencil float32 lattice passes: every unordered pair is evaluated once.
+//
+// Newton's third law halves the pair work of the rho and force passes (the
+// paper's Sec. 4.2); the price is a write to the partner atom as well, which two
+// threads may share.  The paper avoids those write conflicts by colouring
+// z blocks of the domain red and blue and running one colour after the other.
+// The GPU form here:
+//  * Pair ownership.  The pair (i, j = i + o) belongs to i when the lattice-id
+//    offset o points into the forward half space: dZ > 0, or dZ = 0 and dY > 0,
+//    or dZ = dY = 0 and dX > 0.  The odd-parity stencil is the negated even one,
+//    so exactly one end of every pair owns it.
+//  * Footprint.  An 8 x 8 x 8-cell tile stages the sites its forward pairs reach:
+//    x and y from -2 to +10 cells, z from 0 to +10, both sublattices.  Terms for
+//    footprint sites accumulate in LDS and are added to HBM when the tile ends.
+//  * Colours.  Tiles are 2-coloured per axis (8 colours, one launch each).  Two
+//    tiles of one colour are 16 cells apart, so their footprints never overlap
+//    and the write-back is a plain read-add-write; the colours run in a fixed
+//    order.
+//  * Phases.  Inside a tile a wave serves one z plane of one parity.  The stencil
+//    is split into 6 phases by (dZ, parity change); within a phase every wave
+//    writes a different (plane, parity) of the footprint, so no two waves touch
+//    one LDS word, and barriers separate the phases.  The partner terms are
+//    therefore plain LDS read-add-writes (LDS float atomics measured ~20x slower
+//    than reads).  Within a wave they stay in program order: two stencil
+//    entries' partner addresses may coincide for all the compiler knows, and
+//    the LDS serves one wave's accesses in order.  Every site receives its
+//    terms in a fixed order: results are bit-reproducible run to run.
+// The pair arithmetic (displacement form, q = r^2 table window in LDS, zero
+// record at the cut-off) is that of the full-gather persistent kernels.
+#include "misa_internal.h"
+
+namespace misa {
+
+constexpr int HF_THREADS = TILE2_THREADS;                              // 1024: one lane per interior site
+constexpr int HF_PER_LANE = (HT_SITES + HF_THREADS - 1) / HF_THREADS;  // footprint sites per lane
+
+__device__ __forceinline__ int hf_wrap(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Tile of colour c (bits: x, y, z parity of the tile coordinates) for item it of
+// work-group b, dealt so that every XCD sweeps one contiguous block of items.
+struct ColourTiles {
+    int nt0, nt1, nt2;  // tiles per axis (even)
+    int colour;
+    int nitems, nitems_pad;
+    __device__ __forceinline__ int next(int b, int &it, int grid) const {
+        const int per = nitems_pad >> 3;
+        for (;; ++it) {
+            const int j = (b >> 3) + it * (grid >> 3);
+            if (j >= per) return -1;
+            const int id = (b & 7) * per + j;
+            if (id < nitems) return id;
+        }
+    }
+    // item -> tile coordinates and tile id (the id the energy partials use)
+    __device__ __forceinline__ int tile(int item, int &tx, int &ty, int &tz) const {
+        const int hx = nt0 >> 1, hy = nt1 >> 1;
+        const int ix = item % hx, r = item / hx;
+        const int iy = r % hy, iz = r / hy;
+        tx = 2 * ix + (colour & 1);
+        ty = 2 * iy + ((colour >> 1) & 1);
+        tz = 2 * iz + ((colour >> 2) & 1);
+        return (tz * nt1 + ty) * nt0 + tx;
+    }
+};
+
+// Footprint entry e -> (lx, ly, lz, p) of the staged block and its storage index.
+__device__ __forceinline__ int64_t hf_site(int e, int tx, int ty, int tz, const Geom &g) {
+    const int lx = e % HFX;
+    int r = e / HFX;
+    const int ly = r % HFY;
+    r /= HFY;
+    const int lz = r % HFZ;
+    const int p = r / HFZ;
+    const int gx = hf_wrap(tx * T2X - HALO + lx, g.nx);
+    const int gy = hf_wrap(ty * T2Y - HALO + ly, g.ny);
+    const int gz = hf_wrap(tz * T2Z + lz, g.nz);
+    return (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+}
+
+struct HfRegs {
+    double x[HF_PER_LANE], y[HF_PER_LANE], z[HF_PER_LANE];
+    float w[HF_PER_LANE];
+};
+
+__device__ __forceinline__ void hf_fetch(HfRegs &R, const State &S, bool with_fp, int tx, int ty, int tz,
+                                         const Geom &g) {
+#pragma unroll
+    for (int j = 0; j < HF_PER_LANE; ++j) {
+        const int e = threadIdx.x + j * HF_THREADS;
+        if (e < HT_SITES) {
+            const int64_t idx = hf_site(e, tx, ty, tz, g);
+            R.x[j] = S.ux[idx];
+            R.y[j] = S.uy[idx];
+            R.z[j] = S.uz[idx];
+            R.w[j] = with_fp ? ((const float *)S.fp)[idx] : 0.0f;
+        }
+    }
+}
+
+// Stores the staged displacements, zeroes the accumulators (NACC floats per
+// footprint site), returns max |u|^2 of the occupied sites this lane stored.
+template <int NACC>
+__device__ __forceinline__ float hf_store(Q4<float> *__restrict__ tile, float *__restrict__ acc, const HfRegs &R) {
+    float m = 0.0f;
+#pragma unroll
+    for (int j = 0; j < HF_PER_LANE; ++j) {
+        const int e = threadIdx.x + j * HF_THREADS;
+        if (e < HT_SITES) {
+            Q4<float> q;
+            q.x = (float)R.x[j];
+            q.y = (float)R.y[j];
+            q.z = (float)R.z[j];
+            q.w = R.w[j];
+            tile[e] = q;
+#pragma unroll
+            for (int c = 0; c < NACC; ++c) acc[NACC * e + c] = 0.0f;  // NACC floats per footprint site
+            if (q.x < (float)VACANT_TEST) m = fmaxf(m, q.x * q.x + q.y * q.y + q.z * q.z);
+        }
+    }
+    return m;
+}
+
+// Whether every occupied site of the footprint has |u|^2 below u_cut2 (then the
+// entries beyond rc of each phase cannot hold a pair within rc).  Contains the
+// barrier after which the staged tile is visible.
+__device__ __forceinline__ bool hf_near_sites(float m, unsigned *slot, unsigned *other, float u_cut2) {
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(m));
+    __syncthreads();
+    const float umax2 = __uint_as_float(*slot);
+    if (threadIdx.x == 0) *other = 0u;
+    return __builtin_amdgcn_readfirstlane(umax2 < u_cut2 ? 1 : 0) != 0;
+}
+
+template <bool kNodeCut>
+__device__ __forceinline__ int hf_seg(float pp, int nwin, float &t) {
+    const float top = kNodeCut ? (float)nwin : (float)(nwin - 1);
+    t = __builtin_amdgcn_fractf(pp);
+    return (int)__builtin_amdgcn_fmed3f(pp, 0.0f, top);
+}
+
+// ---------------------------------------------------------------------------
+// rho: rho_i and rho_j += f(r) for every owned pair; one launch per colour.
+template <bool kNodeCut>
+__global__ __launch_bounds__(HF_THREADS) void k_rho_half(ColourTiles ct, State S, Geom g, const StencilEntry<float> *__restrict__ hst,
+                                                         const int32_t *__restrict__ hmeta,
+                                                         const Q4<float> *__restrict__ fwin, float inv_hq,
+                                                         float pcq, int nwin, float rc2, float u_cut2) {
+    __shared__ Q4<float> tile[HT_SITES];
+    __shared__ float acc[HT_SITES];
+    __shared__ float4 ftab[HALF_TAB_SEGS];
+    __shared__ unsigned umax_slot[2];
+    if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
+    for (int e = threadIdx.x; e < nwin; e += HF_THREADS) {
+        const Q4<float> c = fwin[e];
+        ftab[e] = make_float4(c.x, c.y, c.z, c.w);
+    }
+    if (kNodeCut && threadIdx.x == 0) ftab[nwin] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
+    const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
+    // wave-uniform parity: the stencil entries and phase bounds become scalar loads
+    const StencilEntry<float> *sp = hst + p * KMAX;
+    const int32_t *meta = hmeta + p * HALF_META;
+    const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
+    float *rho = (float *)S.rho;
+    int it = 0;
+    int item = ct.next(blockIdx.x, it, gridDim.x);
+    HfRegs R;
+    int tx, ty, tz;
+    if (item >= 0) {
+        ct.tile(item, tx, ty, tz);
+        hf_fetch(R, S, false, tx, ty, tz, g);
+    }
+    while (item >= 0) {
+        ct.tile(item, tx, ty, tz);
+        __syncthreads();  // previous tile written back (and the table copied)
+        const float m = hf_store<1>(tile, acc, R);
+        const bool near = hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2);
+        ++it;
+        const int nxt = ct.next(blockIdx.x, it, gridDim.x);
+        if (nxt >= 0) {
+            int nx_, ny_, nz_;
+            ct.tile(nxt, nx_, ny_, nz_);
+            hf_fetch(R, S, false, nx_, ny_, nz_, g);  // in flight during this tile
+        }
+        const Q4<float> ui = tile[me];
+        float ai = 0.0f;
+        for (int q = 0; q < HALF_PHASES; ++q) {
+            const int k0 = __builtin_amdgcn_readfirstlane(meta[q]);
+            const int k1 = __builtin_amdgcn_readfirstlane(near ? k0 + meta[8 + q] : meta[q + 1]);
+#pragma unroll 2
+            for (int k = k0; k < k1; ++k) {
+                const StencilEntry<float> e = sp[k];
+                const int j = me + e.lds;
+                const Q4<float> uj = tile[j];
+                const float dx = (uj.x - ui.x) + e.ox;
+                const float dy = (uj.y - ui.y) + e.oy;
+                const float dz = (uj.z - ui.z) + e.oz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                float t;
+                const int s = hf_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);
+                const float4 c = ftab[s];
+                float v = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                v = (kNodeCut || r2 < rc2) ? v : 0.0f;
+                ai += v;
+                acc[j] += v;  // no other wave writes this plane in this phase
+            }
+            __syncthreads();  // the next phase's waves write other planes of the footprint
+        }
+        acc[me] += ai;  // the site's own pairs, after every partner term
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < HF_PER_LANE; ++jj) {
+            const int e = threadIdx.x + jj * HF_THREADS;
+            if (e < HT_SITES) {
+                const int64_t idx = hf_site(e, tx, ty, tz, g);
+                rho[idx] += acc[e];
+            }
+        }
+        item = nxt;
+    }
+}
+
+// F'(rho) of every site after the last colour (empty slots: rho = F' = 0).
+__global__ void k_embed_half(State S, Geom g, Tables<float> T, unsigned *range_viol) {
+    float *rho = (float *)S.rho;
+    float *fp = (float *)S.fp;
+    unsigned nb = 0;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const float r = rho[s];
+        float d;
+        if (S.ux[s] > VACANT_TEST) {
+            rho[s] = 0.0f;
+            d = 0.0f;
+        } else if (r > T.em.x_last) {
+            d = T.em.d_last;
+            ++nb;
+        } else {
+            const float q = (r - T.em.x0) * T.em.inv_h;
+            int kk = (int)q;
+            kk = kk < T.em.nseg - 1 ? kk : T.em.nseg - 1;
+            kk = kk > 0 ? kk : 0;
+            const float t = q - (float)kk;
+            const Q4<float> c = T.emb[2 * kk + 1];
+            d = (c.z * t + c.y) * t + c.x;
+        }
+        fp[s] = d;
+    }
+    if (nb) atomicAdd(range_viol, nb);
+}
+
+// ---------------------------------------------------------------------------
+// force: F_i += s d, F_j -= s d for every owned pair (s = (F'_i + F'_j) f'/r + phi'/r);
+// with kEnergy also the per-tile sums of F(rho_i) and of phi over the owned pairs.
+template <bool kEnergy, bool kNodeCut>
+__global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State S, Geom g, const StencilEntry<float> *__restrict__ hst,
+                                                         const int32_t *__restrict__ hmeta,
+                                                           const FRec32 *__restrict__ fwin, float inv_hq,
+                                                           float pcq, int nwin, Tables<float> T, float rc2,
+                                                           float u_cut2, double *__restrict__ part) {
+    __shared__ Q4<float> tile[HT_SITES];
+    __shared__ float4 acc[HT_SITES];       // {F_x, F_y, F_z, -} per footprint site: one 16-byte read-add-write
+    __shared__ float4 fab[HALF_TAB_SEGS];  // {f'0, f'1, f'2, phi'0} per segment
+    __shared__ float2 fcc[HALF_TAB_SEGS];  // {phi'1, phi'2}
+    __shared__ unsigned umax_slot[2];
+    __shared__ double red[2][HF_THREADS / 64];
+    if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
+    for (int e = threadIdx.x; e < nwin; e += HF_THREADS) {
+        const FRec32 c = fwin[e];
+        fab[e] = make_float4(c.a.x, c.a.y, c.b.x, c.b.y);
+        fcc[e] = c.c;
+    }
+    if (kNodeCut && threadIdx.x == 0) {
+        fab[nwin] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        fcc[nwin] = make_float2(0.0f, 0.0f);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
+    const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
+    // wave-uniform parity: the stencil entries and phase bounds become scalar loads
+    const StencilEntry<float> *sp = hst + p * KMAX;
+    const int32_t *meta = hmeta + p * HALF_META;
+    const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
+    const int nlast = T.fm.nseg - 1;
+    float *fx = (float *)S.fx, *fy = (float *)S.fy, *fz = (float *)S.fz;
+    int it = 0;
+    int item = ct.next(blockIdx.x, it, gridDim.x);
+    HfRegs R;
+    int tx, ty, tz;
+    if (item >= 0) {
+        ct.tile(item, tx, ty, tz);
+        hf_fetch(R, S, true, tx, ty, tz, g);
+    }
+    while (item >= 0) {
+        const int tid = ct.tile(item, tx, ty, tz);
+        __syncthreads();
+        const float m = hf_store<4>(tile, (float *)acc, R);
+        const bool near = hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2);
+        ++it;
+        const int nxt = ct.next(blockIdx.x, it, gridDim.x);
+        if (nxt >= 0) {
+            int nx_, ny_, nz_;
+            ct.tile(nxt, nx_, ny_, nz_);
+            hf_fetch(R, S, true, nx_, ny_, nz_, g);
+        }
+        const Q4<float> ui = tile[me];
+        float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
+        for (int q = 0; q < HALF_PHASES; ++q) {
+            const int k0 = __builtin_amdgcn_readfirstlane(meta[q]);
+            const int k1 = __builtin_amdgcn_readfirstlane(near ? k0 + meta[8 + q] : meta[q + 1]);
+#pragma unroll 2
+            for (int k = k0; k < k1; ++k) {
+                const StencilEntry<float> e = sp[k];
+                const int j = me + e.lds;
+                const Q4<float> uj = tile[j];
+                const float dx = (uj.x - ui.x) + e.ox;
+                const float dy = (uj.y - ui.y) + e.oy;
+                const float dz = (uj.z - ui.z) + e.oz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                float t;
+                const int s = hf_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);
+                const float4 a = fab[s];
+                const float2 c = fcc[s];
+                const float gf = (a.z * t + a.y) * t + a.x;  // f'(r) / r
+                const float gp = (c.y * t + c.x) * t + a.w;  // phi'(r) / r
+                float sc = (ui.w + uj.w) * gf + gp;
+                if (!kNodeCut) sc = r2 < rc2 ? sc : 0.0f;
+                const float px = sc * dx, py = sc * dy, pz = sc * dz;
+                ax += px;
+                ay += py;
+                az += pz;
+                float4 aj = acc[j];  // no other wave writes this plane in this phase
+                aj.x -= px;
+                aj.y -= py;
+                aj.z -= pz;
+                acc[j] = aj;
+                if (kEnergy) {
+                    const float pr = (__builtin_amdgcn_sqrtf(r2) - T.fm.x0) * T.fm.inv_h;
+                    const int sg = max(0, min((int)pr, nlast));
+                    const float tr = pr - (float)sg;
+                    const Q4<float> cp = T.phi[sg];
+                    const float v = ((cp.w * tr + cp.z) * tr + cp.y) * tr + cp.x;
+                    ep += (kNodeCut ? s < nwin : r2 < rc2) ? v : 0.0f;
+                }
+            }
+            __syncthreads();
+        }
+        {
+            float4 am = acc[me];
+            am.x += ax;
+            am.y += ay;
+            am.z += az;
+            acc[me] = am;
+        }
+        if (kEnergy) {
+            double e_emb = 0.0, e_pair = 0.0;
+            if (ui.x < (float)VACANT_TEST) {
+                const int gx = tx * T2X + lx, gy = ty * T2Y + ly, gz = tz * T2Z + lz;
+                const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+                const float rr = ((const float *)S.rho)[idx];
+                float Fv;
+                if (rr > T.em.x_last) {
+                    Fv = T.em.y_last + T.em.d_last * (rr - T.em.x_last);
+                } else {
+                    const float qq = (rr - T.em.x0) * T.em.inv_h;
+                    int kk = (int)qq;
+                    kk = kk < T.em.nseg - 1 ? kk : T.em.nseg - 1;
+                    kk = kk > 0 ? kk : 0;
+                    const float tt = qq - (float)kk;
+                    const Q4<float> c = T.emb[2 * kk];
+                    Fv = ((c.w * tt + c.z) * tt + c.y) * tt + c.x;
+                }
+                e_emb = (double)Fv;
+                e_pair = (double)ep;
+            }
+            for (int o = 32; o >= 1; o >>= 1) {
+                e_emb += __shfl_xor(e_emb, o, 64);
+                e_pair += __shfl_xor(e_pair, o, 64);
+            }
+            if (lane == 0) {
+                red[0][w] = e_emb;
+                red[1][w] = e_pair;
+            }
+        }
+        __syncthreads();
+        if (kEnergy && threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int q = 0; q < HF_THREADS / 64; ++q) {
+                s0 += red[0][q];
+                s1 += red[1][q];
+            }
+            part[2 * tid] = s0;
+            part[2 * tid + 1] = s1;
+        }
+#pragma unroll
+        for (int jj = 0; jj < HF_PER_LANE; ++jj) {
+            const int e = threadIdx.x + jj * HF_THREADS;
+            if (e < HT_SITES) {
+                const int64_t idx = hf_site(e, tx, ty, tz, g);
+                const float4 a = acc[e];
+                fx[idx] += a.x;
+                fy[idx] += a.y;
+                fz[idx] += a.z;
+            }
+        }
+        item = nxt;
+    }
+}
+
+__global__ void k_zero_f32(float *__restrict__ a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0f;
+}
+
+bool half_path(const misa_lattice *h) {
+    return h->pair_schedule == MISA_PAIRS_HALF && lds_path(h) && h->lds32h.usable && h->half_fits;
+}
+
+static ColourTiles colour_tiles(const misa_lattice *h, int c) {
+    ColourTiles ct;
+    ct.nt0 = h->g.nt2[0];
+    ct.nt1 = h->g.nt2[1];
+    ct.nt2 = h->g.nt2[2];
+    ct.colour = c;
+    ct.nitems = (ct.nt0 / 2) * (ct.nt1 / 2) * (ct.nt2 / 2);
+    ct.nitems_pad = (ct.nitems + 7) / 8 * 8;
+    return ct;
+}
+
+static Tables<float> half_tables(const misa_lattice *h) {
+    Tables<float> T;
+    T.f = h->t32.f;
+    T.force = h->t32.force;
+    T.phi = h->t32.phi;
+    T.emb = h->t32.emb;
+    T.fm = h->t32.fm;
+    T.em = h->t32.em;
+    return T;
+}
+
+static hipError_t zero_f32(misa_lattice *h, void *a) {
+    const int64_t n = h->g.nsites;
+    const int64_t b = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero_f32, dim3(b > 0 ? b : 1), dim3(256), 0, h->stream, (float *)a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_rho_half(misa_lattice *h) {
+    const LdsTables &W = h->lds32h;
+    hipError_t e = zero_f32(h, h->S.rho);
+    if (e != hipSuccess) return e;
+    auto kern = W.node_cut ? k_rho_half<true> : k_rho_half<false>;
+    for (int c = 0; c < 8; ++c) {
+        const ColourTiles ct = colour_tiles(h, c);
+        const int grid = std::min(h->persistent_grid, ct.nitems_pad);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(HF_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st, h->half.meta,
+                           (const Q4<float> *)W.f, W.inv_hq, W.pcq, W.nwin, (float)h->g.rc2, h->u_cut2);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int64_t b = std::min<int64_t>((h->g.nsites + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_embed_half, dim3(b > 0 ? b : 1), dim3(256), 0, h->stream, h->S, h->g, half_tables(h),
+                       &h->sc.cnt->range_viol);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_half(misa_lattice *h, bool energy) {
+    const LdsTables &W = h->lds32h;
+    hipError_t e;
+    for (void *a : {h->S.fx, h->S.fy, h->S.fz})
+        if ((e = zero_f32(h, a)) != hipSuccess) return e;
+    auto kern = energy ? (W.node_cut ? k_force_half<true, true> : k_force_half<true, false>)
+                       : (W.node_cut ? k_force_half<false, true> : k_force_half<false, false>);
+    for (int c = 0; c < 8; ++c) {
+        const ColourTiles ct = colour_tiles(h, c);
+        const int grid = std::min(h->persistent_grid, ct.nitems_pad);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(HF_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st, h->half.meta, W.force,
+                           W.inv_hq, W.pcq, W.nwin, half_tables(h), (float)h->g.rc2, h->u_cut2, h->sc.part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace misa

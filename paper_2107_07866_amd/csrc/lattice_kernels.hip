@@ -299,6 +299,7 @@ static hipError_t rho_impl(misa_lattice *h, const StencilEntry<Real> *st, const 
 
 hipError_t launch_rho(misa_lattice *h) {
     if (h->use_mlp) return launch_rho_mlp(h);
+    if (half_path(h)) return launch_rho_half(h);
     if (lds_path(h)) return launch_rho_lds(h);
     if (h->precision == MISA_FP32) return rho_impl<float>(h, h->st32, h->t32);
     return rho_impl<double>(h, h->st64, h->t64);
@@ -320,9 +321,10 @@ static hipError_t force_impl(misa_lattice *h, bool energy, const StencilEntry<Re
     return hipGetLastError();
 }
 
-bool fused_kick(const misa_lattice *h) { return lds_path(h); }
+bool fused_kick(const misa_lattice *h) { return lds_path(h) && !half_path(h); }
 
 hipError_t launch_force(misa_lattice *h, bool energy, bool kick) {
+    if (half_path(h)) return kick ? hipErrorInvalidValue : launch_force_half(h, energy);
     if (lds_path(h)) return launch_force_lds(h, energy, kick);
     if (kick) return hipErrorInvalidValue;  // the generic kernels keep the separate final kick
     if (h->use_mlp) return launch_force_mlp(h, energy);

@@ -42,6 +42,15 @@ constexpr int TILE2_SITES = 2 * P2X * P2Y * P2Z;
 constexpr int TILE2_THREADS = 2 * T2X * T2Y * T2Z;  // 1024
 constexpr int LDS_TAB_SEGS = 4096;                  // max table segments held in LDS
 
+// Half-stencil variant (each pair once): the same 8 x 8 x 8-cell tiles staged
+// with their forward footprint (x, y: -2 .. +10 cells, z: 0 .. +10), LDS
+// accumulators for every footprint site, and a smaller table window to make room.
+constexpr int HFX = T2X + 2 * HALO, HFY = T2Y + 2 * HALO, HFZ = T2Z + HALO;
+constexpr int HT_SITES = 2 * HFX * HFY * HFZ;       // 2880
+constexpr int HALF_TAB_SEGS = 2880;                 // LDS: 3 x 46,080 (tile, accumulators, f records) + 23,040 B
+constexpr int HALF_PHASES = 6;                      // (dZ in 0..2) x (partner parity same / other)
+constexpr int HALF_META = 16;                       // ints per parity: phase starts [7], in-rc counts [6]
+
 constexpr double VACANT_U = 1.0e6;             // displacement stored in an empty slot
 constexpr double VACANT_TEST = 0.5e6;          // ux above this means the slot is empty
 constexpr int32_t VACANT_ID = 0x7fffffff;      // atom id stored in an empty slot
@@ -200,6 +209,16 @@ struct LdsTables {
     bool node_cut = false;    // last node at rc: a zero record after the window implements the cut-off
 };
 
+// Forward half of the stencil for the half-stencil passes, per parity: entries
+// grouped by phase (dZ, partner parity != own), nearest first inside a phase,
+// with LDS offsets in the footprint layout.  meta[p * HALF_META + q] is the first
+// entry of phase q (q = 0 .. HALF_PHASES, the last one the end), and
+// meta[p * HALF_META + 8 + q] the number of phase-q entries closer than rc.
+struct HalfStencil {
+    const StencilEntry<float> *st = nullptr;  // device [2][KMAX]
+    const int32_t *meta = nullptr;            // device [2][HALF_META]
+};
+
 // Per-box pointers of the persistent float32 lattice passes.
 struct PassPtrs {
     const double *ux, *uy, *uz;
@@ -256,6 +275,12 @@ struct misa_lattice {
     int n_cu = 0;                                 // compute units of the device
     int persistent_grid = 0;                      // work-groups of the persistent kernels (multiple of 8)
     misa::StencilEntry<float> *st32p = nullptr;   // stencil with LDS offsets of the 8x8x8 tiles
+    int pair_schedule = 0;                        // MISA_PAIRS_GATHER or MISA_PAIRS_HALF
+    bool half_fits = false;                       // every axis a multiple of 16 cells (8 colours of tiles)
+    misa::StencilEntry<float> *sth = nullptr;     // half-stencil entries (device [2][KMAX])
+    int32_t *hmeta = nullptr;                     // half-stencil phases (device [2][HALF_META])
+    misa::HalfStencil half;
+    misa::LdsTables lds32h;                       // smaller window for the half-stencil passes
     bool tables_set = false;
     misa::Scratch sc{};
     void *state_ptr = nullptr;
@@ -295,6 +320,9 @@ hipError_t launch_rho_lds_batch(misa_lattice *h0, const BoxPass *boxes, const in
 hipError_t launch_force_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems,
                                   bool energy, bool kick);
 bool fused_kick(const misa_lattice *h);               // the step fuses the final kick into the force pass
+bool half_path(const misa_lattice *h);                // half-stencil passes serve this handle
+hipError_t launch_rho_half(misa_lattice *h);            // zero, 8 colours, F'(rho)
+hipError_t launch_force_half(misa_lattice *h, bool energy);
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev);
 hipError_t launch_rho_mlp(misa_lattice *h);             // learned form: rho pass with the networks
 hipError_t launch_force_mlp(misa_lattice *h, bool energy);

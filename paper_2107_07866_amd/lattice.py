@@ -95,6 +95,14 @@ class Lattice:
     def defects(self):
         return M.misa_defects(self.h)
 
+    def set_pair_schedule(self, schedule):
+        """"gather" (default: each pair evaluated from both ends) or "half" (Newton's
+        third law: each pair once, coloured tiles; FP32 table form, axes multiple of 16)."""
+        codes = {"gather": M.MISA_PAIRS_GATHER, "half": M.MISA_PAIRS_HALF}
+        if schedule not in codes:
+            raise ValueError(f"unknown pair schedule {schedule!r}")
+        M.misa_set_pair_schedule(self.h, codes[schedule])
+
     def step(self, nsteps, dt_max, dx_max=0.0):
         return M.misa_step(self.h, nsteps, dt_max, dx_max)
 

@@ -23,6 +23,7 @@ MISA_HOST, MISA_DEVICE = 0, 1
 MISA_FIELD_RHO, MISA_FIELD_FPRIME, MISA_FIELD_FORCE = 0, 1, 2
 MISA_EXPORT_STENCIL, MISA_EXPORT_SLOTS = 0, 1
 MISA_MLP = 2
+MISA_PAIRS_GATHER, MISA_PAIRS_HALF = 0, 1
 MISA_FN_F, MISA_FN_PHI, MISA_FN_EMB = 0, 1, 2
 MISA_MLP_HIDDEN, MISA_MLP_PARAMS, MISA_FM_SLOTS = 32, 1153, 96
 
@@ -99,6 +100,7 @@ def _load():
         "misa_get_timing": ([vp, C.POINTER(misa_timing)], C.c_int),
         "misa_debug_export": ([vp, C.c_int, C.POINTER(i64), i64], i64),
         "misa_defects": ([vp, C.POINTER(i64)], C.c_int),
+        "misa_set_pair_schedule": ([vp, C.c_int], C.c_int),
         "misa_set_mlp": ([vp, C.c_int, C.POINTER(misa_mlp_net)], C.c_int),
         "misa_table_eval": ([vp, C.c_int, vp, i64, vp, vp], C.c_int),
         "misa_mlp_trainer_create": ([vp, C.POINTER(vp)], C.c_int),
@@ -277,6 +279,11 @@ def misa_debug_export(h, what):
     out = np.empty(max(n, 1), dtype=np.int64)
     _check(lib.misa_debug_export(h, what, out.ctypes.data_as(C.POINTER(C.c_int64)), out.size), h)
     return out[:n]
+
+
+def misa_set_pair_schedule(h, schedule):
+    """MISA_PAIRS_GATHER (each pair from both ends) or MISA_PAIRS_HALF (each pair once)."""
+    return _check(lib.misa_set_pair_schedule(h, int(schedule)), h)
 
 
 def misa_defects(h):
