@@ -80,13 +80,20 @@ __device__ __forceinline__ int64_t hf_site(int e, int tx, int ty, int tz, const 
     return (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
 }
 
+// One lane's share of a footprint in registers: displacements (and F') to stage,
+// and the values the write-back adds to (NOUT arrays: rho, or F_x, F_y, F_z).
+// Same-colour footprints are disjoint and earlier colours have finished, so those
+// values cannot change during the launch and are fetched a tile ahead.
+template <int NOUT>
 struct HfRegs {
     double x[HF_PER_LANE], y[HF_PER_LANE], z[HF_PER_LANE];
     float w[HF_PER_LANE];
+    float old[NOUT][HF_PER_LANE];
 };
 
-__device__ __forceinline__ void hf_fetch(HfRegs &R, const State &S, bool with_fp, int tx, int ty, int tz,
-                                         const Geom &g) {
+template <int NOUT>
+__device__ __forceinline__ void hf_fetch(HfRegs<NOUT> &R, const State &S, float *const out[NOUT], bool with_fp,
+                                         int tx, int ty, int tz, const Geom &g) {
 #pragma unroll
     for (int j = 0; j < HF_PER_LANE; ++j) {
         const int e = threadIdx.x + j * HF_THREADS;
@@ -96,14 +103,17 @@ __device__ __forceinline__ void hf_fetch(HfRegs &R, const State &S, bool with_fp
             R.y[j] = S.uy[idx];
             R.z[j] = S.uz[idx];
             R.w[j] = with_fp ? ((const float *)S.fp)[idx] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < NOUT; ++c) R.old[c][j] = out[c][idx];
         }
     }
 }
 
 // Stores the staged displacements, zeroes the accumulators (NACC floats per
 // footprint site), returns max |u|^2 of the occupied sites this lane stored.
-template <int NACC>
-__device__ __forceinline__ float hf_store(Q4<float> *__restrict__ tile, float *__restrict__ acc, const HfRegs &R) {
+template <int NACC, int NOUT>
+__device__ __forceinline__ float hf_store(Q4<float> *__restrict__ tile, float *__restrict__ acc,
+                                          const HfRegs<NOUT> &R) {
     float m = 0.0f;
 #pragma unroll
     for (int j = 0; j < HF_PER_LANE; ++j) {
@@ -166,33 +176,36 @@ __global__ __launch_bounds__(HF_THREADS) void k_rho_half(ColourTiles ct, State S
     const StencilEntry<float> *sp = hst + p * KMAX;
     const int32_t *meta = hmeta + p * HALF_META;
     const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
-    float *rho = (float *)S.rho;
+    float *const out[1] = {(float *)S.rho};
     int it = 0;
     int item = ct.next(blockIdx.x, it, gridDim.x);
-    HfRegs R;
+    HfRegs<1> R;
+    float old[1][HF_PER_LANE];
     int tx, ty, tz;
     if (item >= 0) {
         ct.tile(item, tx, ty, tz);
-        hf_fetch(R, S, false, tx, ty, tz, g);
+        hf_fetch<1>(R, S, out, false, tx, ty, tz, g);
     }
     while (item >= 0) {
         ct.tile(item, tx, ty, tz);
         __syncthreads();  // previous tile written back (and the table copied)
         const float m = hf_store<1>(tile, acc, R);
+#pragma unroll
+        for (int jj = 0; jj < HF_PER_LANE; ++jj) old[0][jj] = R.old[0][jj];
         const bool near = hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2);
         ++it;
         const int nxt = ct.next(blockIdx.x, it, gridDim.x);
         if (nxt >= 0) {
             int nx_, ny_, nz_;
             ct.tile(nxt, nx_, ny_, nz_);
-            hf_fetch(R, S, false, nx_, ny_, nz_, g);  // in flight during this tile
+            hf_fetch<1>(R, S, out, false, nx_, ny_, nz_, g);  // in flight during this tile
         }
         const Q4<float> ui = tile[me];
         float ai = 0.0f;
         for (int q = 0; q < HALF_PHASES; ++q) {
             const int k0 = __builtin_amdgcn_readfirstlane(meta[q]);
             const int k1 = __builtin_amdgcn_readfirstlane(near ? k0 + meta[8 + q] : meta[q + 1]);
-#pragma unroll 2
+#pragma unroll 4
             for (int k = k0; k < k1; ++k) {
                 const StencilEntry<float> e = sp[k];
                 const int j = me + e.lds;
@@ -216,10 +229,7 @@ __global__ __launch_bounds__(HF_THREADS) void k_rho_half(ColourTiles ct, State S
 #pragma unroll
         for (int jj = 0; jj < HF_PER_LANE; ++jj) {
             const int e = threadIdx.x + jj * HF_THREADS;
-            if (e < HT_SITES) {
-                const int64_t idx = hf_site(e, tx, ty, tz, g);
-                rho[idx] += acc[e];
-            }
+            if (e < HT_SITES) out[0][hf_site(e, tx, ty, tz, g)] = old[0][jj] + acc[e];
         }
         item = nxt;
     }
@@ -234,7 +244,7 @@ __global__ void k_embed_half(State S, Geom g, Tables<float> T, unsigned *range_v
          s += (int64_t)gridDim.x * blockDim.x) {
         const float r = rho[s];
         float d;
-        if (S.ux[s] > VACANT_TEST) {
+        if (S.atom[s] == VACANT_ID) {
             rho[s] = 0.0f;
             d = 0.0f;
         } else if (r > T.em.x_last) {
@@ -287,33 +297,40 @@ __global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State
     const int32_t *meta = hmeta + p * HALF_META;
     const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
     const int nlast = T.fm.nseg - 1;
-    float *fx = (float *)S.fx, *fy = (float *)S.fy, *fz = (float *)S.fz;
+    float *const out[3] = {(float *)S.fx, (float *)S.fy, (float *)S.fz};
     int it = 0;
     int item = ct.next(blockIdx.x, it, gridDim.x);
-    HfRegs R;
+    HfRegs<3> R;
+    float old[3][HF_PER_LANE];
     int tx, ty, tz;
     if (item >= 0) {
         ct.tile(item, tx, ty, tz);
-        hf_fetch(R, S, true, tx, ty, tz, g);
+        hf_fetch<3>(R, S, out, true, tx, ty, tz, g);
     }
     while (item >= 0) {
         const int tid = ct.tile(item, tx, ty, tz);
         __syncthreads();
         const float m = hf_store<4>(tile, (float *)acc, R);
+#pragma unroll
+        for (int jj = 0; jj < HF_PER_LANE; ++jj) {
+            old[0][jj] = R.old[0][jj];
+            old[1][jj] = R.old[1][jj];
+            old[2][jj] = R.old[2][jj];
+        }
         const bool near = hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2);
         ++it;
         const int nxt = ct.next(blockIdx.x, it, gridDim.x);
         if (nxt >= 0) {
             int nx_, ny_, nz_;
             ct.tile(nxt, nx_, ny_, nz_);
-            hf_fetch(R, S, true, nx_, ny_, nz_, g);
+            hf_fetch<3>(R, S, out, true, nx_, ny_, nz_, g);
         }
         const Q4<float> ui = tile[me];
         float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
         for (int q = 0; q < HALF_PHASES; ++q) {
             const int k0 = __builtin_amdgcn_readfirstlane(meta[q]);
             const int k1 = __builtin_amdgcn_readfirstlane(near ? k0 + meta[8 + q] : meta[q + 1]);
-#pragma unroll 2
+#pragma unroll 4
             for (int k = k0; k < k1; ++k) {
                 const StencilEntry<float> e = sp[k];
                 const int j = me + e.lds;
@@ -403,9 +420,9 @@ __global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State
             if (e < HT_SITES) {
                 const int64_t idx = hf_site(e, tx, ty, tz, g);
                 const float4 a = acc[e];
-                fx[idx] += a.x;
-                fy[idx] += a.y;
-                fz[idx] += a.z;
+                out[0][idx] = old[0][jj] + a.x;
+                out[1][idx] = old[1][jj] + a.y;
+                out[2][idx] = old[2][jj] + a.z;
             }
         }
         item = nxt;
