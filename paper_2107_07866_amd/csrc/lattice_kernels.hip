@@ -145,6 +145,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_tile(
     const Real rc2 = (Real)g.rc2;
     const StencilEntry<Real> *sp = st + p * KMAX;
     Real acc = 0;
+    // Branch-free and unrolled: every candidate gathers its (clamped) record and an
+    // out-of-range pair is dropped by a select, so the L2 gathers of several
+    // candidates are in flight together.
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
         const StencilEntry<Real> e = sp[k];
         const Q4<Real> uj = tile[me + e.lds];
@@ -152,13 +156,13 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_tile(
         const Real dy = (uj.y - ui.y) + e.oy;
         const Real dz = (uj.z - ui.z) + e.oz;
         const Real r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < rc2) {
-            int s;
-            Real t;
-            seg_index(pair_r<Real>(r2), fm, s, t);
-            const Q4<Real> c = ftab[s];
-            acc += ((c.w * t + c.z) * t + c.y) * t + c.x;
-        }
+        const bool in = r2 < rc2;
+        int s;
+        Real t;
+        seg_index(pair_r<Real>(in ? r2 : rc2), fm, s, t);
+        const Q4<Real> c = ftab[s];
+        const Real v = ((c.w * t + c.z) * t + c.y) * t + c.x;
+        acc += in ? v : (Real)0;
     }
     const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
     Real fpv = 0;
@@ -214,6 +218,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
         const Real rc2 = (Real)g.rc2;
         const StencilEntry<Real> *sp = st + p * KMAX;
         Real ax = 0, ay = 0, az = 0, ep = 0;
+        // branch-free and unrolled, as in the rho pass
+#pragma unroll 4
         for (int k = 0; k < K; ++k) {
             const StencilEntry<Real> e = sp[k];
             const Q4<Real> uj = tile[me + e.lds];
@@ -221,24 +227,24 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
             const Real dy = (uj.y - ui.y) + e.oy;
             const Real dz = (uj.z - ui.z) + e.oz;
             const Real r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < rc2) {
-                Real r, rinv;
-                pair_r_rinv<Real>(r2, r, rinv);
-                int s;
-                Real t;
-                seg_index(r, T.fm, s, t);
-                const Q4<Real> a = T.force[2 * s];
-                const Q4<Real> b = T.force[2 * s + 1];
-                const Real dfr = (a.z * t + a.y) * t + a.x;   // f'(r)
-                const Real dph = (b.y * t + b.x) * t + a.w;   // phi'(r)
-                const Real sc = ((ui.w + uj.w) * dfr + dph) * rinv;
-                ax += sc * dx;
-                ay += sc * dy;
-                az += sc * dz;
-                if (kEnergy) {
-                    const Q4<Real> c = T.phi[s];
-                    ep += ((c.w * t + c.z) * t + c.y) * t + c.x;
-                }
+            const bool in = r2 < rc2;
+            Real r, rinv;
+            pair_r_rinv<Real>(in ? r2 : rc2, r, rinv);
+            int s;
+            Real t;
+            seg_index(r, T.fm, s, t);
+            const Q4<Real> a = T.force[2 * s];
+            const Q4<Real> b = T.force[2 * s + 1];
+            const Real dfr = (a.z * t + a.y) * t + a.x;   // f'(r)
+            const Real dph = (b.y * t + b.x) * t + a.w;   // phi'(r)
+            const Real sc = in ? ((ui.w + uj.w) * dfr + dph) * rinv : (Real)0;
+            ax += sc * dx;
+            ay += sc * dy;
+            az += sc * dz;
+            if (kEnergy) {
+                const Q4<Real> c = T.phi[s];
+                const Real v = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                ep += in ? v : (Real)0;
             }
         }
         const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
