@@ -148,9 +148,14 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None)
         ref = oracle.eam_sampled(oracle.Potential(oracle.TABLE, tables=tabs), xg, box, sample)
         scale = float(np.sqrt(np.mean(ref["F"] ** 2)))
         out["force_err_max_rel_rms"] = float(np.max(np.abs(Fg[sample] - ref["F"]))) / max(scale, 1e-3)
+        # embedding energy per sampled atom: |F'| |d rho| to first order, so the density error bounds it
+        rg = lat.rho()[sample]
+        nz = ref["rho"] > 0
+        out["rho_err_max_rel"] = float(np.max(np.abs(rg[nz] - ref["rho"][nz]) / ref["rho"][nz])) if nz.any() else 0.0
+        out["emb_energy_err_max_eV"] = float(np.max(np.abs(ref["fp"] * (rg - ref["rho"]))))
         out["force_err_sample"] = int(len(sample))
         out["mean_pairs_per_atom"] = float(np.mean(ref["npairs"]))
-        _log(f"[bench] {form}: force error {out['force_err_max_rel_rms']:.2e} "
+        _log(f"[bench] {form}: force error {out['force_err_max_rel_rms']:.2e}, rho error {out['rho_err_max_rel']:.2e} "
              f"(oracle sample of {len(sample)} atoms, {time.time() - t3:.1f} s)")
     out["K"] = int(lat.stencil().shape[1])
     lat.close()
@@ -183,6 +188,14 @@ def run_batch(cfg, steps, warmup, err_sample, seq_steps=20):
         batch.boxes[k].set_state(b[1], b[2])
     torch.cuda.synchronize()
     _log(f"[bench] batch: tables and states loaded, {time.time() - t0:.1f} s")
+    # tile shapes: the autotuner times both policies on the initial states, which are
+    # then loaded again so that the warm-up and the timed steps start where they would
+    tune = batch.autotune(max(2, warmup), cfg.dt_max, cfg.dx_max)
+    shapes = [M.MISA_TILE_SHAPES[batch.tile_shape(k)] for k in range(len(boxes))]
+    tune["boxes_off_8x8x8"] = int(sum(1 for s_ in shapes if s_ != (8, 8, 8)))
+    _log(f"[bench] batch: tile autotune {tune}")
+    for k, b in enumerate(boxes):
+        batch.boxes[k].set_state(b[1], b[2])
     if warmup > 0:
         batch.step(warmup, cfg.dt_max, cfg.dx_max, want_stats=False)
     torch.cuda.synchronize()
@@ -203,7 +216,7 @@ def run_batch(cfg, steps, warmup, err_sample, seq_steps=20):
     M.misa_set_timing(batch.boxes[0].h, False)
     out = {"atom_steps_per_s": n_atoms * steps / wall, "ms_per_step": 1e3 * wall / steps,
            "kernel_ms_per_step": {k: ms / steps for k, (ms, cnt) in timing.items()},
-           "boxes": len(boxes), "atoms": n_atoms,
+           "boxes": len(boxes), "atoms": n_atoms, "tile_autotune": tune,
            "n_runaway_total": int(sum(s["n_runaway"] for s in st)),
            "frenkel_pairs_total": int(sum(M.misa_defects(bx.h)["vacancies"] for bx in batch.boxes)),
            "simulated_fs_min": min(s["time"] for s in st), "simulated_fs_max": max(s["time"] for s in st)}

@@ -395,6 +395,28 @@ int misa_batch_set_potential_tables(misa_batch *b, const misa_table *f, const mi
  * misa_set_timing on box 0, the batch's kernel times accumulate on box 0. */
 int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max, misa_step_stats *stats);
 
+/* Tile shapes of the batched rho and force passes.  Every tile has 512 cells (1024
+ * lanes, both sublattices) and is staged in LDS with a 2-cell halo; a box whose
+ * sides are not multiples of 8 wastes less work on a shape that fits it better.
+ * Shapes (x, y, z cells): 0: 8x8x8 (the default and the single-box tiling),
+ * 1: 16x8x4, 2: 8x16x4, 3: 16x4x8, 4: 4x16x8, 5: 8x4x16, 6: 4x8x16.
+ * Per-atom rho, F' and forces do not depend on the shape (every atom sums its
+ * stencil in the same order); the per-tile energy and kinetic sums do, so
+ * energies may differ from misa_step's in the last bits. */
+#define MISA_TILE_SHAPES 7
+int misa_batch_set_tile_shape(misa_batch *b, int32_t k, int32_t shape);
+int misa_batch_get_tile_shape(misa_batch *b, int32_t k, int32_t *shape);
+
+/* Autotuner: times probe_steps batched steps (as misa_batch_step, after one
+ * untimed step) with every box on 8x8x8 tiles (policy 0) and with every box on the
+ * shape that covers it with the fewest cells (policy 1), and keeps the faster
+ * policy.  The boxes advance by *steps_done steps (1 + probe_steps per policy
+ * tried; one policy is tried when both coincide).  Outputs (host, any may be
+ * NULL): *policy, ms_per_step[2] of the two policies, *steps_done.  Synchronises
+ * the stream. */
+int misa_batch_autotune(misa_batch *b, int64_t probe_steps, double dt_max, double dx_max, int32_t *policy,
+                        double *ms_per_step, int64_t *steps_done);
+
 #ifdef __cplusplus
 }
 #endif

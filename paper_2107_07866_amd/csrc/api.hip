@@ -4,6 +4,7 @@
 // Initialization, with the slot tolerance), and the per-step orchestration of
 // the kernels on the caller's stream.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -385,6 +386,11 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     g.nt2[2] = (g.nz + T2Z - 1) / T2Z;
     g.ntiles2 = g.nt2[0] * g.nt2[1] * g.nt2[2];
     g.ntiles2_pad = (g.ntiles2 + 7) / 8 * 8;
+    for (int a = 0; a < 3; ++a) {
+        g.tshape[a] = a == 0 ? T2X : (a == 1 ? T2Y : T2Z);
+        const uint32_t side = (uint32_t)(g.tshape[a] + 2 * HALO);
+        g.tdiv[a] = (uint32_t)((0x100000000ull + side - 1) / side);
+    }
     {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) ncu = 0;
@@ -528,7 +534,14 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(h->hmeta, 2 * HALF_META);
     ALLOC(sc.cnt, 1);
     ALLOC(sc.scal, 8);
-    ALLOC(sc.part, 2 * (int64_t)g.ntiles_pad + 2 * 1024);
+    // per-tile partials of any tiling a batch may choose for this box
+    int64_t max_tiles = std::max<int64_t>(g.ntiles_pad, g.ntiles2_pad);
+    for (int sh = 0; sh < N_TILE_SHAPES; ++sh) {
+        const int *t = TILE_SHAPES[sh];
+        const int64_t n = (int64_t)((g.nx + t[0] - 1) / t[0]) * ((g.ny + t[1] - 1) / t[1]) * ((g.nz + t[2] - 1) / t[2]);
+        max_tiles = std::max<int64_t>(max_tiles, (n + 7) / 8 * 8);
+    }
+    ALLOC(sc.part, 2 * max_tiles + 2 * 1024);
     ALLOC(sc.l_site, rcap);
     ALLOC(sc.l_id, rcap);
     ALLOC(sc.l_x, rcap);
@@ -550,7 +563,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(sc.mark_off, sc.mark_nblk);
     ALLOC(sc.affected, sc.affected_cap);
     ALLOC(sc.aff_v2, sc.affected_cap);
-    ALLOC(sc.part_kick, 2 * (int64_t)std::max(g.ntiles2_pad, 8));
+    ALLOC(sc.part_kick, 2 * std::max<int64_t>(max_tiles, 8));
 #undef ALLOC
     if ((e = hipMemcpy(h->st64, s64.data(), sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->st32, s32.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
@@ -931,6 +944,8 @@ struct misa_batch {
     BoxPass *d_pass = nullptr;
     int2 *d_items = nullptr;
     int64_t cap_boxes = 0, cap_items = 0;
+    std::vector<int32_t> shape;                  // tile shape of each box (index into TILE_SHAPES)
+    StencilEntry<float> *d_st = nullptr;         // [N_TILE_SHAPES][2][KMAX]: stencil per tile shape
 };
 
 namespace {
@@ -958,9 +973,21 @@ int batch_tables(misa_batch *b) {
     b->items.clear();
     for (int k = 0; k < nb; ++k) {
         misa_lattice *h = b->box[k];
-        b->ref[k] = BoxRef{h->S, h->sc, h->g, h->rcap};
-        b->pass[k] = BoxPass{h->g, pass_ptrs(h)};
-        for (int t = 0; t < h->g.ntiles2; ++t) b->items.push_back(int2{k, t});
+        const int sh = b->shape[k];
+        Geom g = h->g;  // the box with the batch's tiling for it
+        for (int a = 0; a < 3; ++a) {
+            g.tshape[a] = TILE_SHAPES[sh][a];
+            const uint32_t side = (uint32_t)(g.tshape[a] + 2 * HALO);
+            g.tdiv[a] = (uint32_t)((0x100000000ull + side - 1) / side);
+        }
+        g.nt2[0] = (g.nx + g.tshape[0] - 1) / g.tshape[0];
+        g.nt2[1] = (g.ny + g.tshape[1] - 1) / g.tshape[1];
+        g.nt2[2] = (g.nz + g.tshape[2] - 1) / g.tshape[2];
+        g.ntiles2 = g.nt2[0] * g.nt2[1] * g.nt2[2];
+        g.ntiles2_pad = (g.ntiles2 + 7) / 8 * 8;
+        b->ref[k] = BoxRef{h->S, h->sc, g, h->rcap};
+        b->pass[k] = BoxPass{g, pass_ptrs(h), sh, 0};
+        for (int t = 0; t < g.ntiles2; ++t) b->items.push_back(int2{k, t});
     }
     if (nb > b->cap_boxes) {
         (void)hipFree(b->d_ref);
@@ -1015,6 +1042,35 @@ int misa_batch_create(const misa_lattice_desc *descs, int32_t n_boxes, void *hip
         }
         b->box.push_back(h);
     }
+    b->shape.assign(n_boxes, 0);
+    // The boxes share one stencil: its LDS offsets for every tile shape, from box 0.
+    {
+        const misa_lattice *h0 = b->box[0];
+        std::vector<StencilEntry<float>> sts((size_t)N_TILE_SHAPES * 2 * KMAX, StencilEntry<float>{0, 0.f, 0.f, 0.f});
+        for (int sh = 0; sh < N_TILE_SHAPES; ++sh) {
+            const int px = TILE_SHAPES[sh][0] + 2 * HALO, py = TILE_SHAPES[sh][1] + 2 * HALO,
+                      pz = TILE_SHAPES[sh][2] + 2 * HALO;
+            for (int p = 0; p < 2; ++p)
+                for (int k = 0; k < h0->K; ++k) {
+                    const int64_t *c = &h0->stencil_canon[(p * h0->K + k) * 3];
+                    const int pn = (int)(((p + c[0]) % 2 + 2) % 2);
+                    const int dcx = (int)((p + c[0] - pn) / 2), dcy = (int)c[1], dcz = (int)c[2];
+                    const int lds = (pn - p) * pz * py * px + (dcz * py + dcy) * px + dcx;
+                    const double a = h0->g.a;
+                    sts[((size_t)sh * 2 + p) * KMAX + k] =
+                        StencilEntry<float>{lds, (float)(c[0] * 0.5 * a), (float)((c[1] + 0.5 * pn - 0.5 * p) * a),
+                                            (float)((c[2] + 0.5 * pn - 0.5 * p) * a)};
+                }
+        }
+        hipError_t e = hipMalloc((void **)&b->d_st, sizeof(StencilEntry<float>) * sts.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_st, sts.data(), sizeof(StencilEntry<float>) * sts.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            const std::string m = std::string("stencil upload: ") + hipGetErrorString(e);
+            misa_batch_destroy(b);
+            return bfail(nullptr, MISA_EHIP, m);
+        }
+    }
     *out = b;
     return MISA_OK;
 }
@@ -1025,6 +1081,7 @@ int misa_batch_destroy(misa_batch *b) {
     (void)hipFree(b->d_ref);
     (void)hipFree(b->d_pass);
     (void)hipFree(b->d_items);
+    (void)hipFree(b->d_st);
     delete b;
     return MISA_OK;
 }
@@ -1086,6 +1143,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
     const double kf = ACC_UNIT / h0->mass;
     const hipStream_t st = b->stream;
     const int nitems = (int)b->items.size();
+    const bool any_shape = std::any_of(b->shape.begin(), b->shape.end(), [](int32_t x) { return x != 0; });
     // kernel timing of the batch, when enabled, accumulates on box 0's timers
     for (int64_t s = 0; s < nsteps; ++s) {
         const bool last = s == nsteps - 1;
@@ -1100,7 +1158,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         }
         {
             GroupTimer t(h0, MISA_TIMER_RHO);
-            BCHK(b, launch_rho_lds_batch(h0, b->d_pass, b->d_items, nitems));
+            BCHK(b, launch_rho_lds_batch(h0, b->d_pass, b->d_items, nitems, b->d_st, any_shape));
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
@@ -1108,7 +1166,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         }
         {
             GroupTimer t(h0, MISA_TIMER_FORCE);
-            BCHK(b, launch_force_lds_batch(h0, b->d_pass, b->d_items, nitems, last, true));
+            BCHK(b, launch_force_lds_batch(h0, b->d_pass, b->d_items, nitems, last, true, b->d_st, any_shape));
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
@@ -1165,6 +1223,69 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         if (cnt[k].overflow) worst = bfail(b, MISA_EOVERFLOW, "box " + std::to_string(k) + ": run-away capacity exceeded");
     }
     return worst;
+}
+
+int misa_batch_set_tile_shape(misa_batch *b, int32_t k, int32_t shape) {
+    if (!b) return MISA_EINVAL;
+    if (k < 0 || k >= (int32_t)b->box.size()) return bfail(b, MISA_EINVAL, "box index out of range");
+    if (shape < 0 || shape >= N_TILE_SHAPES) return bfail(b, MISA_EINVAL, "unknown tile shape");
+    b->shape[k] = shape;
+    return MISA_OK;
+}
+
+int misa_batch_get_tile_shape(misa_batch *b, int32_t k, int32_t *shape) {
+    if (!b || !shape) return MISA_EINVAL;
+    if (k < 0 || k >= (int32_t)b->box.size()) return bfail(b, MISA_EINVAL, "box index out of range");
+    *shape = b->shape[k];
+    return MISA_OK;
+}
+
+int misa_batch_autotune(misa_batch *b, int64_t probe_steps, double dt_max, double dx_max, int32_t *policy,
+                        double *ms_per_step, int64_t *steps_done) {
+    if (!b) return MISA_EINVAL;
+    if (probe_steps < 1) return bfail(b, MISA_EINVAL, "probe_steps >= 1 required");
+    const int nb = (int)b->box.size();
+    // policy 0: every box on 8 x 8 x 8 tiles; policy 1: every box on the shape that
+    // covers it with the fewest cells (8 x 8 x 8 on ties)
+    std::vector<int32_t> cand[2];
+    cand[0].assign(nb, 0);
+    cand[1].assign(nb, 0);
+    for (int k = 0; k < nb; ++k) {
+        const Geom &g = b->box[k]->g;
+        int64_t best = -1;
+        for (int sh = 0; sh < N_TILE_SHAPES; ++sh) {
+            const int *t = TILE_SHAPES[sh];
+            const int64_t cells = (int64_t)((g.nx + t[0] - 1) / t[0] * t[0]) * ((g.ny + t[1] - 1) / t[1] * t[1]) *
+                                  ((g.nz + t[2] - 1) / t[2] * t[2]);
+            if (best < 0 || cells < best) {
+                best = cells;
+                cand[1][k] = sh;
+            }
+        }
+    }
+    const int npol = cand[1] == cand[0] ? 1 : 2;
+    double ms[2] = {0.0, 0.0};
+    int64_t done = 0;
+    for (int pol = 0; pol < npol; ++pol) {
+        b->shape = cand[pol];
+        int rc = misa_batch_step(b, 1, dt_max, dx_max, nullptr);  // untimed: first launches of this tiling
+        if (rc) return rc;
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = misa_batch_step(b, probe_steps, dt_max, dx_max, nullptr);  // synchronises at the end
+        if (rc) return rc;
+        ms[pol] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() /
+                  (double)probe_steps;
+        done += 1 + probe_steps;
+    }
+    const int best = (npol == 2 && ms[1] < ms[0]) ? 1 : 0;
+    b->shape = cand[best];
+    if (policy) *policy = best;
+    if (ms_per_step) {
+        ms_per_step[0] = ms[0];
+        ms_per_step[1] = npol == 2 ? ms[1] : ms[0];
+    }
+    if (steps_done) *steps_done = done;
+    return MISA_OK;
 }
 
 int misa_defects(misa_lattice *h, int64_t *counts) {

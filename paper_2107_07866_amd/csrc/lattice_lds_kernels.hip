@@ -42,41 +42,49 @@ __device__ __forceinline__ int next_item(int b, int &it, int grid, int n, int n_
     }
 }
 
-// What one tile of a lattice pass needs to know about its box.
+// What one tile of a lattice pass needs to know about its box: the box, its tiling
+// (tx x ty x tz interior cells, tx ty tz = 512, so 1024 lanes serve both
+// sublattices) and the stencil with the LDS offsets of that tile shape.
 struct TileGeo {
-    int32_t nx, ny, nz, nt0, nt1, pad;
+    int32_t nx, ny, nz, nt0, nt1;
+    int32_t tx, ty, tz;             // powers of two
+    uint32_t dx, dy, dz;            // ceil(2^32 / (t + 4)) for the staged block's index arithmetic
+    int32_t shape;                  // index of the tiling: its stencil is st + shape 2 KMAX
     int64_t ncell;
 };
 
-__device__ __forceinline__ TileGeo geo_of(const Geom &g) {
-    TileGeo G;
-    G.nx = g.nx;
-    G.ny = g.ny;
-    G.nz = g.nz;
-    G.nt0 = g.nt2[0];
-    G.nt1 = g.nt2[1];
-    G.pad = 0;
-    G.ncell = g.ncell;
-    return G;
-}
-
-// Tiles of one box: item = tile id.
+// Tiles of one box: item = tile id; 8 x 8 x 8 tiles, known at compile time (the
+// shape fields of TileGeo stay unused).
 struct OneBox {
-    TileGeo geo;
+    static constexpr bool kFixed = true;
+    static constexpr int kMaxSites = TILE2_SITES;
+    int32_t nx, ny, nz, nt0, nt1;
+    int64_t ncell;
     PassPtrs P;
     int ntiles, ntiles_pad;
     __device__ __forceinline__ int next(int b, int &it, int grid) const {
         return next_item(b, it, grid, ntiles, ntiles_pad);
     }
     __device__ __forceinline__ int get(int item, TileGeo &G, PassPtrs &Q) const {
-        G = geo;
+        G.nx = nx;
+        G.ny = ny;
+        G.nz = nz;
+        G.nt0 = nt0;
+        G.nt1 = nt1;
+        G.ncell = ncell;
         Q = P;
         return item;
     }
 };
 
-// Tiles of many boxes: item -> (box, tile) from a list built on the host.
-struct ManyBoxes {
+// Tiles of many boxes: item -> (box, tile) from a list built on the host.  With
+// kAnyShape every box has its own tile shape (one of the 1024-lane shapes whose
+// staged block fits in LDS) and the kernel's stencil argument holds the stencils of
+// all shapes; without it every box uses the compile-time 8 x 8 x 8 tiles.
+template <bool kAnyShape>
+struct ManyBoxesT {
+    static constexpr bool kFixed = !kAnyShape;
+    static constexpr int kMaxSites = kAnyShape ? TILE2_SITES_MAX : TILE2_SITES;
     const BoxPass *boxes;
     const int2 *items;
     int nitems, nitems_pad;
@@ -91,14 +99,73 @@ struct ManyBoxes {
         G.nz = B.g.nz;
         G.nt0 = B.g.nt2[0];
         G.nt1 = B.g.nt2[1];
-        G.pad = 0;
+        if (kAnyShape) {
+            G.tx = B.g.tshape[0];
+            G.ty = B.g.tshape[1];
+            G.tz = B.g.tshape[2];
+            G.dx = B.g.tdiv[0];
+            G.dy = B.g.tdiv[1];
+            G.dz = B.g.tdiv[2];
+            G.shape = B.shape;
+        }
         G.ncell = B.g.ncell;
         Q = B.P;
         return bt.y;
     }
 };
 
-constexpr int TILE2_PER_LANE = (TILE2_SITES + TILE2_THREADS - 1) / TILE2_THREADS;
+// Tile shape of a source: compile-time 8 x 8 x 8 for one box, the box's own otherwise.
+// Runtime shapes avoid integer division (tens of instructions on the GPU): the
+// interior sides are powers of two (shifts), and an index e < 2^12 of the staged
+// block divides by a side p + 4 <= 20 exactly as mulhi(e, ceil(2^32 / p)).
+struct Dims {
+    int tx, ty, tz, px, py, pz, sites;
+    int sx, sy;               // log2 tx, log2 ty
+    uint32_t mx, my, mz;      // multiply-high reciprocals of px, py, pz
+};
+template <class Src>
+__device__ __forceinline__ Dims dims_of(const TileGeo &G) {
+    Dims d;
+    d.tx = Src::kFixed ? T2X : G.tx;
+    d.ty = Src::kFixed ? T2Y : G.ty;
+    d.tz = Src::kFixed ? T2Z : G.tz;
+    d.px = d.tx + 2 * HALO;
+    d.py = d.ty + 2 * HALO;
+    d.pz = d.tz + 2 * HALO;
+    d.sites = 2 * d.px * d.py * d.pz;
+    d.sx = __builtin_ctz((unsigned)d.tx);
+    d.sy = __builtin_ctz((unsigned)d.ty);
+    d.mx = Src::kFixed ? 0u : G.dx;
+    d.my = Src::kFixed ? 0u : G.dy;
+    d.mz = Src::kFixed ? 0u : G.dz;
+    return d;
+}
+
+// e / c for a staged-block index e < 2^12 (c one of the block's sides)
+template <class Src>
+__device__ __forceinline__ int div_side(int e, int c, uint32_t m) {
+    return Src::kFixed ? e / c : (int)__umulhi((uint32_t)e, m);
+}
+
+// This lane's site in a tile: wave w serves parity w / 8 and the 64 interior sites
+// (w % 8) 64 .. + 63 of that parity's tx x ty x tz block (x fastest).  For
+// 8 x 8 x 8 tiles that is one z plane per wave.
+struct LaneSite {
+    int lx, ly, lz, me;
+};
+__device__ __forceinline__ LaneSite lane_site(const Dims &d, int p, int w, int lane) {
+    LaneSite L;
+    const int l = (w & 7) * 64 + lane;
+    L.lx = l & (d.tx - 1);
+    L.ly = (l >> d.sx) & (d.ty - 1);
+    L.lz = l >> (d.sx + d.sy);
+    L.me = ((p * d.pz + L.lz + HALO) * d.py + L.ly + HALO) * d.px + L.lx + HALO;
+    return L;
+}
+
+constexpr int TILE2_PER_LANE = (TILE2_SITES_MAX + TILE2_THREADS - 1) / TILE2_THREADS;
+static_assert((TILE2_SITES + TILE2_THREADS - 1) / TILE2_THREADS == TILE2_PER_LANE,
+              "8 x 8 x 8 tiles and the largest shape take the same registers per lane");
 
 // One lane's share of a tile (interior + halo), held in registers between the
 // global fetch and the LDS store.
@@ -107,24 +174,26 @@ struct TileRegs {
     float w[TILE2_PER_LANE];
 };
 
+template <class Src>
 __device__ __forceinline__ void fetch_tile2(TileRegs &R, const double *__restrict__ ux,
                                             const double *__restrict__ uy, const double *__restrict__ uz,
-                                            const float *__restrict__ w_src, const TileGeo &g, int tid) {
+                                            const float *__restrict__ w_src, const TileGeo &g, const Dims &d,
+                                            int tid) {
     const int tx = tid % g.nt0;
     const int tyz = tid / g.nt0;
     const int ty = tyz % g.nt1;
     const int tz = tyz / g.nt1;
-    const int bx = tx * T2X - HALO, by = ty * T2Y - HALO, bz = tz * T2Z - HALO;
+    const int bx = tx * d.tx - HALO, by = ty * d.ty - HALO, bz = tz * d.tz - HALO;
 #pragma unroll
     for (int j = 0; j < TILE2_PER_LANE; ++j) {
         const int e = threadIdx.x + j * TILE2_THREADS;
-        if (e < TILE2_SITES) {
-            const int lx = e % P2X;
-            int r = e / P2X;
-            const int ly = r % P2Y;
-            r /= P2Y;
-            const int lz = r % P2Z;
-            const int p = r / P2Z;
+        if (e < d.sites) {
+            int r = div_side<Src>(e, d.px, d.mx);
+            const int lx = e - r * d.px;
+            const int r2 = div_side<Src>(r, d.py, d.my);
+            const int ly = r - r2 * d.py;
+            const int p = div_side<Src>(r2, d.pz, d.mz);
+            const int lz = r2 - p * d.pz;
             const int gx = wrap2(bx + lx, g.nx), gy = wrap2(by + ly, g.ny), gz = wrap2(bz + lz, g.nz);
             const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
             R.x[j] = ux[idx];
@@ -137,12 +206,12 @@ __device__ __forceinline__ void fetch_tile2(TileRegs &R, const double *__restric
 
 // Stores this lane's share of the tile; returns the largest |u|^2 among the
 // occupied sites it stored.
-__device__ __forceinline__ float store_tile2(Q4<float> *__restrict__ tile, const TileRegs &R) {
+__device__ __forceinline__ float store_tile2(Q4<float> *__restrict__ tile, const TileRegs &R, int sites) {
     float m = 0.0f;
 #pragma unroll
     for (int j = 0; j < TILE2_PER_LANE; ++j) {
         const int e = threadIdx.x + j * TILE2_THREADS;
-        if (e < TILE2_SITES) {
+        if (e < sites) {
             Q4<float> q;
             q.x = (float)R.x[j];
             q.y = (float)R.y[j];
@@ -188,7 +257,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
                                                           const Q4<float> *__restrict__ fwin, float inv_hq,
                                                           float pcq, int nwin, const Q4<float> *__restrict__ etab,
                                                           TabMeta<float> em, float rc2) {
-    __shared__ Q4<float> tile[TILE2_SITES];
+    __shared__ Q4<float> tile[Src::kMaxSites];
     __shared__ float4 ftab[LDS_TAB_SEGS];
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
@@ -198,10 +267,10 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
     }
     if (kNodeCut && threadIdx.x == 0) ftab[nwin] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // wave-uniform: the stencil entries below become scalar loads
-    const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
-    const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
-    const StencilEntry<float> *sp = st + p * KMAX;
+    // wave-uniform parity: the stencil entries below become scalar loads
+    const int p = __builtin_amdgcn_readfirstlane(w >> 3);
+    TileGeo Gf{};  // the fixed shape's lane site and stencil, computed once
+    const LaneSite Lf = lane_site(dims_of<Src>(Gf), p, w, lane);
     int it = 0;
     int item = src.next(blockIdx.x, it, gridDim.x);
     TileRegs R;
@@ -209,14 +278,19 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
         TileGeo G0;
         PassPtrs P0;
         const int t0 = src.get(item, G0, P0);
-        fetch_tile2(R, P0.ux, P0.uy, P0.uz, nullptr, G0, t0);
+        fetch_tile2<Src>(R, P0.ux, P0.uy, P0.uz, nullptr, G0, dims_of<Src>(G0), t0);
     }
     while (item >= 0) {
         TileGeo G;
         PassPtrs P;
         const int tid = src.get(item, G, P);
+        const Dims d = dims_of<Src>(G);
+        const LaneSite L = Src::kFixed ? Lf : lane_site(d, p, w, lane);
+        // wave-uniform shape and parity: the stencil entries are scalar loads from st
+        const int shp = Src::kFixed ? 0 : __builtin_amdgcn_readfirstlane(G.shape);
+        const StencilEntry<float> *sp = st + (shp * 2 + p) * KMAX;
         __syncthreads();  // previous tile fully consumed (and the table copied)
-        const float m = store_tile2(tile, R);
+        const float m = store_tile2(tile, R, d.sites);
         const int Kt = tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2);
         ++it;
         const int nxt = src.next(blockIdx.x, it, gridDim.x);
@@ -224,13 +298,13 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
             TileGeo Gn;
             PassPtrs Pn;
             const int ntid = src.get(nxt, Gn, Pn);
-            fetch_tile2(R, Pn.ux, Pn.uy, Pn.uz, nullptr, Gn, ntid);  // in flight during this tile
+            fetch_tile2<Src>(R, Pn.ux, Pn.uy, Pn.uz, nullptr, Gn, dims_of<Src>(Gn), ntid);  // in flight during this tile
         }
         const int tx = tid % G.nt0;
         const int tyz = tid / G.nt0;
-        const int gx = tx * T2X + lx, gy = (tyz % G.nt1) * T2Y + ly, gz = (tyz / G.nt1) * T2Z + lz;
+        const int gx = tx * d.tx + L.lx, gy = (tyz % G.nt1) * d.ty + L.ly, gz = (tyz / G.nt1) * d.tz + L.lz;
         if (gx < G.nx && gy < G.ny && gz < G.nz) {
-            const int me = ((p * P2Z + lz + HALO) * P2Y + ly + HALO) * P2X + lx + HALO;
+            const int me = L.me;
             const Q4<float> ui = tile[me];
             float acc = 0.0f;
 #pragma unroll 4
@@ -291,7 +365,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
                                                             const FRec32 *__restrict__ fwin, float inv_hq,
                                                             float pcq, int nwin, Tables<float> T, float rc2,
                                                             double kf) {
-    __shared__ Q4<float> tile[TILE2_SITES];
+    __shared__ Q4<float> tile[Src::kMaxSites];
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
     __shared__ float4 fab[LDS_TAB_SEGS];  // {f'0, f'1, f'2, phi'0} per segment
@@ -307,9 +381,9 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
         fcc[nwin] = make_float2(0.0f, 0.0f);
     }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int p = __builtin_amdgcn_readfirstlane(w / T2Z);
-    const int lz = w % T2Z, lx = lane % T2X, ly = lane / T2X;
-    const StencilEntry<float> *sp = st + p * KMAX;
+    const int p = __builtin_amdgcn_readfirstlane(w >> 3);
+    TileGeo Gf{};  // the fixed shape's lane site and stencil, computed once
+    const LaneSite Lf = lane_site(dims_of<Src>(Gf), p, w, lane);
     const int nlast = T.fm.nseg - 1;
     int it = 0;
     int item = src.next(blockIdx.x, it, gridDim.x);
@@ -318,14 +392,19 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
         TileGeo G0;
         PassPtrs P0;
         const int t0 = src.get(item, G0, P0);
-        fetch_tile2(R, P0.ux, P0.uy, P0.uz, P0.fp, G0, t0);
+        fetch_tile2<Src>(R, P0.ux, P0.uy, P0.uz, P0.fp, G0, dims_of<Src>(G0), t0);
     }
     while (item >= 0) {
         TileGeo G;
         PassPtrs P;
         const int tid = src.get(item, G, P);
+        const Dims d = dims_of<Src>(G);
+        const LaneSite L = Src::kFixed ? Lf : lane_site(d, p, w, lane);
+        // wave-uniform shape and parity: the stencil entries are scalar loads from st
+        const int shp = Src::kFixed ? 0 : __builtin_amdgcn_readfirstlane(G.shape);
+        const StencilEntry<float> *sp = st + (shp * 2 + p) * KMAX;
         __syncthreads();
-        const float m = store_tile2(tile, R);
+        const float m = store_tile2(tile, R, d.sites);
         const int Kt = tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2);
         ++it;
         const int nxt = src.next(blockIdx.x, it, gridDim.x);
@@ -333,12 +412,12 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
             TileGeo Gn;
             PassPtrs Pn;
             const int ntid = src.get(nxt, Gn, Pn);
-            fetch_tile2(R, Pn.ux, Pn.uy, Pn.uz, Pn.fp, Gn, ntid);  // in flight during this tile
+            fetch_tile2<Src>(R, Pn.ux, Pn.uy, Pn.uz, Pn.fp, Gn, dims_of<Src>(Gn), ntid);  // in flight during this tile
         }
         const double hk = kKick ? 0.5 * P.scal[0] * kf : 0.0;
         const int tx = tid % G.nt0;
         const int tyz = tid / G.nt0;
-        const int gx = tx * T2X + lx, gy = (tyz % G.nt1) * T2Y + ly, gz = (tyz / G.nt1) * T2Z + lz;
+        const int gx = tx * d.tx + L.lx, gy = (tyz % G.nt1) * d.ty + L.ly, gz = (tyz / G.nt1) * d.tz + L.lz;
         const bool active = gx < G.nx && gy < G.ny && gz < G.nz;
         const int64_t idx = (int64_t)p * G.ncell + ((int64_t)gz * G.ny + gy) * G.nx + gx;
         double e_emb = 0.0, e_pair = 0.0, kvm = 0.0, kvs = 0.0;
@@ -351,7 +430,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
             mw = P.mark[idx >> 5];
         }
         if (active) {
-            const int me = ((p * P2Z + lz + HALO) * P2Y + ly + HALO) * P2X + lx + HALO;
+            const int me = L.me;
             const Q4<float> ui = tile[me];
             float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
 #pragma unroll 4
@@ -483,13 +562,12 @@ PassPtrs pass_ptrs(misa_lattice *h) {
 static OneBox one_box(misa_lattice *h) {
     OneBox o;
     const Geom &g = h->g;
-    o.geo.nx = g.nx;
-    o.geo.ny = g.ny;
-    o.geo.nz = g.nz;
-    o.geo.nt0 = g.nt2[0];
-    o.geo.nt1 = g.nt2[1];
-    o.geo.pad = 0;
-    o.geo.ncell = g.ncell;
+    o.nx = g.nx;
+    o.ny = g.ny;
+    o.nz = g.nz;
+    o.nt0 = g.nt2[0];
+    o.nt1 = g.nt2[1];
+    o.ncell = g.ncell;
     o.P = pass_ptrs(h);
     o.ntiles = g.ntiles2;
     o.ntiles_pad = g.ntiles2_pad;
@@ -509,46 +587,56 @@ static Tables<float> t32_tab(const misa_lattice *h) {
 
 // h: the handle whose stencil and tables serve (every box of a batch shares them).
 template <class Src>
-static hipError_t rho_lds_src(misa_lattice *h, const Src &src, int grid) {
+static hipError_t rho_lds_src(misa_lattice *h, const Src &src, int grid, const StencilEntry<float> *st) {
     auto kern = h->lds32.node_cut ? k_rho_lds<Src, true> : k_rho_lds<Src, false>;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->K_in,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, st, h->K, h->K_in,
                        h->u_cut2, h->lds32.f, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, h->t32.emb, h->t32.em,
                        (float)h->g.rc2);
     return hipGetLastError();
 }
 
 template <class Src, bool kEnergy, bool kKick>
-static void force_lds_variant(misa_lattice *h, const Src &src, int grid) {
+static void force_lds_variant(misa_lattice *h, const Src &src, int grid, const StencilEntry<float> *st) {
     auto kern = h->lds32.node_cut ? k_force_lds<Src, kEnergy, true, kKick> : k_force_lds<Src, kEnergy, false, kKick>;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, h->st32p, h->K, h->K_in,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, st, h->K, h->K_in,
                        h->u_cut2, h->lds32.force, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, t32_tab(h),
                        (float)h->g.rc2, ACC_UNIT / h->mass);
 }
 
 template <class Src>
-static hipError_t force_lds_src(misa_lattice *h, const Src &src, int grid, bool energy, bool kick) {
-    if (energy && kick) force_lds_variant<Src, true, true>(h, src, grid);
-    else if (energy) force_lds_variant<Src, true, false>(h, src, grid);
-    else if (kick) force_lds_variant<Src, false, true>(h, src, grid);
-    else force_lds_variant<Src, false, false>(h, src, grid);
+static hipError_t force_lds_src(misa_lattice *h, const Src &src, int grid, bool energy, bool kick,
+                                const StencilEntry<float> *st) {
+    if (energy && kick) force_lds_variant<Src, true, true>(h, src, grid, st);
+    else if (energy) force_lds_variant<Src, true, false>(h, src, grid, st);
+    else if (kick) force_lds_variant<Src, false, true>(h, src, grid, st);
+    else force_lds_variant<Src, false, false>(h, src, grid, st);
     return hipGetLastError();
 }
 
-hipError_t launch_rho_lds(misa_lattice *h) { return rho_lds_src(h, one_box(h), h->persistent_grid); }
+hipError_t launch_rho_lds(misa_lattice *h) { return rho_lds_src(h, one_box(h), h->persistent_grid, h->st32p); }
 
 hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick) {
-    return force_lds_src(h, one_box(h), h->persistent_grid, energy, kick);
+    return force_lds_src(h, one_box(h), h->persistent_grid, energy, kick, h->st32p);
 }
 
-hipError_t launch_rho_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems) {
-    ManyBoxes m{boxes, items, nitems, (nitems + 7) / 8 * 8};
-    return rho_lds_src(h0, m, h0->persistent_grid);
+hipError_t launch_rho_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems,
+                                const StencilEntry<float> *st_shapes, bool any_shape) {
+    if (any_shape) {
+        ManyBoxesT<true> m{boxes, items, nitems, (nitems + 7) / 8 * 8};
+        return rho_lds_src(h0, m, h0->persistent_grid, st_shapes);
+    }
+    ManyBoxesT<false> m{boxes, items, nitems, (nitems + 7) / 8 * 8};
+    return rho_lds_src(h0, m, h0->persistent_grid, st_shapes);
 }
 
 hipError_t launch_force_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems,
-                                  bool energy, bool kick) {
-    ManyBoxes m{boxes, items, nitems, (nitems + 7) / 8 * 8};
-    return force_lds_src(h0, m, h0->persistent_grid, energy, kick);
+                                  bool energy, bool kick, const StencilEntry<float> *st_shapes, bool any_shape) {
+    if (any_shape) {
+        ManyBoxesT<true> m{boxes, items, nitems, (nitems + 7) / 8 * 8};
+        return force_lds_src(h0, m, h0->persistent_grid, energy, kick, st_shapes);
+    }
+    ManyBoxesT<false> m{boxes, items, nitems, (nitems + 7) / 8 * 8};
+    return force_lds_src(h0, m, h0->persistent_grid, energy, kick, st_shapes);
 }
 
 }  // namespace misa

@@ -42,6 +42,22 @@ constexpr int TILE2_SITES = 2 * P2X * P2Y * P2Z;
 constexpr int TILE2_THREADS = 2 * T2X * T2Y * T2Z;  // 1024
 constexpr int LDS_TAB_SEGS = 4096;                  // max table segments held in LDS
 
+// Tile shapes of the batched persistent passes: tx ty tz = 512 cells (1024 lanes for
+// both sublattices) whose staged block (with halo) fits beside the table window.
+// Shape 0 is the 8 x 8 x 8 tile of the single-box passes.
+constexpr int N_TILE_SHAPES = 7;
+constexpr int TILE_SHAPES[N_TILE_SHAPES][3] = {{8, 8, 8},  {16, 8, 4}, {8, 16, 4}, {16, 4, 8},
+                                               {4, 16, 8}, {8, 4, 16}, {4, 8, 16}};
+constexpr int TILE2_SITES_MAX = 2 * 20 * 12 * 8;    // largest staged block of those shapes
+constexpr bool tile_shapes_fit() {
+    for (int s = 0; s < N_TILE_SHAPES; ++s) {
+        const int *t = TILE_SHAPES[s];
+        if (t[0] * t[1] * t[2] != 512 || 2 * (t[0] + 4) * (t[1] + 4) * (t[2] + 4) > TILE2_SITES_MAX) return false;
+    }
+    return TILE_SHAPES[0][0] == 8 && TILE_SHAPES[0][1] == 8 && TILE_SHAPES[0][2] == 8;
+}
+static_assert(tile_shapes_fit(), "every batch tile shape has 512 cells and fits the staged block");
+
 // Half-stencil variant (each pair once): the same 8 x 8 x 8-cell tiles staged
 // with their forward footprint (x, y: -2 .. +10 cells, z: 0 .. +10), LDS
 // accumulators for every footprint site, and a smaller table window to make room.
@@ -111,8 +127,10 @@ struct Geom {
     int32_t nx, ny, nz;
     int32_t ntx, nty, ntz;  // tiles per axis
     int32_t ntiles, ntiles_pad;
-    int32_t nt2[3];         // 8 x 8 x 8 tiles per axis (persistent float32 kernels)
+    int32_t nt2[3];         // tiles per axis of the persistent float32 kernels
     int32_t ntiles2, ntiles2_pad;
+    int32_t tshape[3];      // their interior cells per axis (8 x 8 x 8 on a handle; a batch may choose others)
+    uint32_t tdiv[3];       // ceil(2^32 / (tshape + 4)): staged-block index division by multiply-high
     int64_t ncell;          // cells per sublattice
     int64_t nsites;
     double a, inv_a;
@@ -232,8 +250,10 @@ struct PassPtrs {
 
 // One box of a batch as the batched kernels read it.
 struct BoxPass {
-    Geom g;
+    Geom g;         // with the tiling the batch chose for this box
     PassPtrs P;
+    int32_t shape;  // index of that tiling in TILE_SHAPES (and of its stencil)
+    int32_t pad;
 };
 struct BoxRef {
     State S;
@@ -316,9 +336,12 @@ hipError_t launch_rho_lds(misa_lattice *h);
 hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick);  // kick: fused second half-kick
 PassPtrs pass_ptrs(misa_lattice *h);
 // batched persistent passes over (box, tile) items; h0 supplies stencil, tables and stream
-hipError_t launch_rho_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems);
+// st_shapes: [N_TILE_SHAPES][2][KMAX] stencils with the LDS offsets of each tile shape;
+// any_shape: some box is not on 8 x 8 x 8 tiles (else the compile-time tiling serves)
+hipError_t launch_rho_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems,
+                                const StencilEntry<float> *st_shapes, bool any_shape);
 hipError_t launch_force_lds_batch(misa_lattice *h0, const BoxPass *boxes, const int2 *items, int nitems,
-                                  bool energy, bool kick);
+                                  bool energy, bool kick, const StencilEntry<float> *st_shapes, bool any_shape);
 bool fused_kick(const misa_lattice *h);               // the step fuses the final kick into the force pass
 bool half_path(const misa_lattice *h);                // half-stencil passes serve this handle
 hipError_t launch_rho_half(misa_lattice *h);            // zero, 8 colours, F'(rho)

@@ -147,6 +147,17 @@ class Batch:
     def step(self, nsteps, dt_max, dx_max=0.0, want_stats=True):
         return M.misa_batch_step(self.b, len(self.boxes), nsteps, dt_max, dx_max, want_stats)
 
+    def set_tile_shape(self, k, shape):
+        """Tile shape of box k in the batched passes: an index into M.MISA_TILE_SHAPES."""
+        M.misa_batch_set_tile_shape(self.b, k, shape)
+
+    def tile_shape(self, k):
+        return M.misa_batch_get_tile_shape(self.b, k)
+
+    def autotune(self, probe_steps, dt_max, dx_max=0.0):
+        """Choose the tile policy by timing (advances every box by the returned steps_done)."""
+        return M.misa_batch_autotune(self.b, probe_steps, dt_max, dx_max)
+
     def close(self):
         if self.b is not None:
             for box in self.boxes:

@@ -24,6 +24,8 @@ MISA_FIELD_RHO, MISA_FIELD_FPRIME, MISA_FIELD_FORCE = 0, 1, 2
 MISA_EXPORT_STENCIL, MISA_EXPORT_SLOTS = 0, 1
 MISA_MLP = 2
 MISA_PAIRS_GATHER, MISA_PAIRS_HALF = 0, 1
+# batch tile shapes (x, y, z cells), in the library's order
+MISA_TILE_SHAPES = ((8, 8, 8), (16, 8, 4), (8, 16, 4), (16, 4, 8), (4, 16, 8), (8, 4, 16), (4, 8, 16))
 MISA_FN_F, MISA_FN_PHI, MISA_FN_EMB = 0, 1, 2
 MISA_MLP_HIDDEN, MISA_MLP_PARAMS, MISA_FM_SLOTS = 32, 1153, 96
 
@@ -121,6 +123,10 @@ def _load():
         "misa_batch_set_potential_tables": ([vp, C.POINTER(misa_table), C.POINTER(misa_table),
                                              C.POINTER(misa_table)], C.c_int),
         "misa_batch_step": ([vp, i64, C.c_double, C.c_double, C.POINTER(misa_step_stats)], C.c_int),
+        "misa_batch_set_tile_shape": ([vp, C.c_int32, C.c_int32], C.c_int),
+        "misa_batch_get_tile_shape": ([vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+        "misa_batch_autotune": ([vp, i64, C.c_double, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                 C.POINTER(i64)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -458,3 +464,24 @@ def misa_batch_step(b, n_boxes, nsteps, dt_max, dx_max=0.0, want_stats=True):
     code = lib.misa_batch_step(b, int(nsteps), float(dt_max), float(dx_max), st if want_stats else None)
     _bcheck(code, b)
     return [st[k].as_dict() for k in range(n_boxes)] if want_stats else None
+
+
+def misa_batch_set_tile_shape(b, k, shape):
+    """shape: index into MISA_TILE_SHAPES."""
+    return _bcheck(lib.misa_batch_set_tile_shape(b, int(k), int(shape)), b)
+
+
+def misa_batch_get_tile_shape(b, k):
+    s = C.c_int32()
+    _bcheck(lib.misa_batch_get_tile_shape(b, int(k), C.byref(s)), b)
+    return s.value
+
+
+def misa_batch_autotune(b, probe_steps, dt_max, dx_max=0.0):
+    """Time both tile policies and keep the faster: dict(policy, ms_per_step, steps_done)."""
+    pol = C.c_int32()
+    ms = (C.c_double * 2)()
+    done = C.c_int64()
+    _bcheck(lib.misa_batch_autotune(b, int(probe_steps), float(dt_max), float(dx_max), C.byref(pol), ms,
+                                    C.byref(done)), b)
+    return {"policy": pol.value, "ms_per_step": [ms[0], ms[1]], "steps_done": done.value}

@@ -94,3 +94,77 @@ def test_batch_energy_matches_oracle(torch_cuda, orc):
         _say(f"box {k}: force {ferr:.2e} energy/atom {eerr:.2e}")
         assert ferr < 1e-3 and eerr < 1e-5
     batch.close()
+
+
+def test_batch_tile_shapes_keep_per_atom_results(torch_cuda):
+    """Boxes on every tile shape (ragged sizes included): positions, velocities,
+    forces and slots equal the single-box run bit for bit (each atom sums its
+    stencil in the same order whatever the tiling); energies agree to rounding."""
+    torch = torch_cuda
+    from paper_2107_07866_amd import Batch, Lattice
+    from paper_2107_07866_amd import misa as M
+    cfg, boxes = _cases()
+    cells = [b[0] for b in boxes]
+    batch = Batch(cells, A, RC, DELTA, MASS)
+    batch.set_tables(TABLES)
+    for k, (_, x, v, _, _, _) in enumerate(boxes):
+        batch.boxes[k].set_state(x, v)
+        batch.set_tile_shape(k, k % len(M.MISA_TILE_SHAPES))
+    _say("shapes " + str([M.MISA_TILE_SHAPES[batch.tile_shape(k)] for k in range(len(cells))]))
+    singles = []
+    for (n, x, v, _, _, _) in boxes:
+        lat = Lattice(n, A, RC, DELTA, MASS, "fp32")
+        lat.set_tables(TABLES)
+        lat.set_state(x, v)
+        singles.append(lat)
+    for rnd, nsteps in enumerate((1, 9)):
+        st_b = batch.step(nsteps, cfg.dt_max, cfg.dx_max)
+        torch.cuda.synchronize()
+        for k, lat in enumerate(singles):
+            st = lat.step(nsteps, cfg.dt_max, cfg.dx_max)
+            xb, vb = batch.boxes[k].get_state()
+            xs, vs = lat.get_state()
+            assert np.array_equal(xb, xs) and np.array_equal(vb, vs), (rnd, k)
+            assert np.array_equal(batch.boxes[k].forces(), lat.forces()), (rnd, k)
+            assert np.array_equal(batch.boxes[k].slots(), lat.slots()), (rnd, k)
+            for key in ("dt", "dt_next", "time", "n_runaway", "vmax"):
+                assert st_b[k][key] == st[key], (rnd, k, key)
+            for key in ("e_kin", "e_emb", "e_pair"):
+                assert abs(st_b[k][key] - st[key]) <= 1e-12 * abs(st[key]), (rnd, k, key, st_b[k][key], st[key])
+        _say(f"round {rnd}: {nsteps} steps equal on every tile shape")
+    for lat in singles:
+        lat.close()
+    batch.close()
+
+
+def test_batch_autotune(torch_cuda):
+    """The autotuner times both policies, keeps one, reports the steps it took, and
+    the batch goes on matching single boxes advanced by the same steps."""
+    torch = torch_cuda
+    from paper_2107_07866_amd import Batch, Lattice
+    cfg, boxes = _cases()
+    boxes = boxes[:4]
+    cells = [b[0] for b in boxes]
+    batch = Batch(cells, A, RC, DELTA, MASS)
+    batch.set_tables(TABLES)
+    for k, (_, x, v, _, _, _) in enumerate(boxes):
+        batch.boxes[k].set_state(x, v)
+    rep = batch.autotune(3, cfg.dt_max, cfg.dx_max)
+    _say(f"autotune: {rep}, shapes {[batch.tile_shape(k) for k in range(len(cells))]}")
+    assert rep["policy"] in (0, 1) and rep["steps_done"] in (4, 8)
+    assert all(m > 0 for m in rep["ms_per_step"])
+    batch.step(4, cfg.dt_max, cfg.dx_max)
+    torch.cuda.synchronize()
+    for k, (n, x, v, _, _, _) in enumerate(boxes):
+        lat = Lattice(n, A, RC, DELTA, MASS, "fp32")
+        lat.set_tables(TABLES)
+        lat.set_state(x, v)
+        for _ in range(rep["steps_done"] // 4):  # per policy tried: 1 untimed step, then 3 timed
+            lat.step(1, cfg.dt_max, cfg.dx_max)
+            lat.step(3, cfg.dt_max, cfg.dx_max)
+        lat.step(4, cfg.dt_max, cfg.dx_max)
+        xb, vb = batch.boxes[k].get_state()
+        xs, vs = lat.get_state()
+        assert np.array_equal(xb, xs) and np.array_equal(vb, vs), k
+        lat.close()
+    batch.close()
