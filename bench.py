@@ -89,7 +89,7 @@ def train_learned_form(seed=11):
     return nets, info
 
 
-def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None):
+def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None, graph=False):
     import numpy as np
     import torch
 
@@ -109,16 +109,18 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None)
     torch.cuda.synchronize()
     _log(f"[bench] {form}: state loaded in {time.time() - t0:.1f} s ({lat.state_bytes / 1e9:.2f} GB)")
     dx_max = cfg.dx_max
+    if graph:  # steps replay a captured HIP graph (per-kernel event timing would disable it)
+        lat.set_graph(True)
     if warmup > 0:
         lat.step(warmup, cfg.dt_max, dx_max)
     torch.cuda.synchronize()
-    lat.set_timing(True)
+    lat.set_timing(not graph)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = lat.step(steps, cfg.dt_max, dx_max)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    timing = lat.timing()
+    timing = lat.timing() if not graph else {}
     lat.set_timing(False)
     wall = t2 - t1
     n = x.shape[0]
@@ -127,6 +129,7 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None)
         "ms_per_step": 1e3 * wall / steps,
         "kernel_ms_per_step": {k: ms / max(steps, 1) for k, (ms, cnt) in timing.items()},
         "kernel_launches": {k: cnt for k, (ms, cnt) in timing.items()},
+        "graph_replay": bool(graph),
         "last_dt_fs": st["dt"],
         "simulated_fs": st["time"],
         "n_runaway": st["n_runaway"],
@@ -281,6 +284,8 @@ def counted_traffic():
 def roofline(form, res, n_atoms):
     """Dominant lattice kernel (by measured time) against the ALU peak of its precision."""
     kms = res["kernel_ms_per_step"]
+    if not kms:  # graph replay: no per-kernel timing
+        return None
     dom = "force" if kms["force"] >= kms["rho"] else "rho"
     pairs = res.get("mean_pairs_per_atom", 58.0)
     if form == "mlp":  # every stencil candidate runs the networks (the whole wave takes part)
@@ -327,6 +332,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's step count)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each step from a captured HIP graph (no per-kernel breakdown then)")
     ap.add_argument("--forms", default=None,
                     help="comma list of fp32,fp64,fp32-half,mlp; first is the headline value (fp32 or fp64)")
     ap.add_argument("--mlp-steps", type=int, default=5, help="timed steps of the learned form (it is slower)")
@@ -395,7 +402,7 @@ def main():
             results[form]["training"] = info
             results[form]["timed_steps"] = k
         else:
-            results[form] = run_form(form, x, v, box, cfg, steps, args.warmup, args.error_sample)
+            results[form] = run_form(form, x, v, box, cfg, steps, args.warmup, args.error_sample, graph=args.graph)
     head = results[forms[0]]
     n = x.shape[0]
     bpa = sum(BYTES_PER_ATOM_STEP[forms[0]].values())

@@ -199,6 +199,15 @@ typedef struct {
     int64_t launches[MISA_TIMER_COUNT]; /* timed launch groups per class */
 } misa_timing;
 
+/* enable != 0: misa_step replays one captured HIP graph of a step for all its
+ * steps but the last, instead of launching the ~20 kernels of each step one by
+ * one (the gain is the launch overhead: large for small boxes, small for big
+ * ones).  Results are bit-identical to the launched steps.  The graph is captured
+ * on first use for the call's (dt_max, dx_max) and captured again when those
+ * change or after misa_set_potential_tables, misa_bind_state,
+ * misa_set_pair_schedule or misa_set_mlp.  Not used while timing is enabled. */
+int misa_set_graph(misa_lattice *h, int enable);
+
 /* enable != 0: record HIP events on the handle's stream around every kernel
  * group of compute/step calls (profiling; a few microseconds per step).
  * Resets the accumulated times. */

@@ -319,10 +319,69 @@ int finish_force(misa_lattice *h) {
     return MISA_OK;
 }
 
+// One MD step (Fig. 1 in kick-drift-kick form): the kernels of the rho and force
+// passes, the run-away path and the integrator, with no host synchronisation.
+int step_body(misa_lattice *h, bool last, bool fused, double dt_max, double dx_max) {
+    int rc;
+    {
+        GroupTimer t(h, MISA_TIMER_KICK);
+        HIPCHK(h, launch_kick_drift(h));
+    }
+    {
+        GroupTimer t(h, MISA_TIMER_RUNAWAY);
+        HIPCHK(h, launch_rehash(h));
+    }
+    if ((rc = do_rho(h))) return rc;
+    if ((rc = do_force(h, last, nullptr, fused))) return rc;
+    {
+        GroupTimer t(h, MISA_TIMER_KICK);
+        HIPCHK(h, launch_final_kick(h));
+    }
+    {
+        GroupTimer t(h, MISA_TIMER_OTHER);
+        HIPCHK(h, launch_dt_update(h, dt_max, dx_max, false));
+    }
+    if ((rc = finish_force(h))) return rc;  // after the step statistics read the affected list
+    if (h->timed.size() > 50000) HIPCHK(h, fold_timing(h));  // bound the event backlog
+    return MISA_OK;
+}
+
+// Capture one regular step into h->graph_exec.  The capture runs on a private
+// stream (the caller's may be the legacy default stream, which cannot capture);
+// the host-side flags a step updates end where they started.
+int capture_step(misa_lattice *h, bool fused, double dt_max, double dx_max) {
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    hipStream_t user = h->stream;
+    h->stream = h->cap_stream;
+    hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+    int rc = MISA_OK;
+    if (e == hipSuccess) rc = step_body(h, false, fused, dt_max, dx_max);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(h->stream, &graph) : e;
+    h->stream = user;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    HIPCHK(h, e2);
+    e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) h->graph_exec = nullptr;
+    HIPCHK(h, e);
+    h->graph_dt = dt_max;
+    h->graph_dx = dx_max;
+    return MISA_OK;
+}
+
 }  // namespace
 
 // k_clear_marks lives here: it only zeroes mark words of listed sites.
 namespace misa {
+void drop_graph(misa_lattice *h) {
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+}
+
 __global__ void k_clear_marks(Scratch sc) {
     int na = sc.cnt->n_affected;
     na = na < sc.affected_cap ? na : (int)sc.affected_cap;
@@ -591,6 +650,8 @@ int misa_destroy_lattice(misa_lattice *h) {
         (void)hipStreamSynchronize(h->stream);
     else
         (void)hipDeviceSynchronize();
+    drop_graph(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     void *ptrs[] = {h->st64, h->st32, h->st32p, h->sth, h->hmeta, h->lds32.f, h->lds32.force, h->lds32h.f,
                     h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
@@ -624,6 +685,7 @@ int misa_bind_state(misa_lattice *h, void *device_ptr, int64_t bytes) {
     h->state_bytes = bytes;
     carve(h, (char *)device_ptr, &h->S);
     h->state_bound = true;
+    drop_graph(h);
     h->state_set = h->rho_valid = h->force_valid = false;
     return MISA_OK;
 }
@@ -720,6 +782,7 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
     }
     h->tables_set = true;
     h->rho_valid = h->force_valid = false;
+    drop_graph(h);
     return MISA_OK;
 }
 
@@ -847,7 +910,10 @@ int misa_set_pair_schedule(misa_lattice *h, int schedule) {
         if (!h->half_fits)
             return fail(h, MISA_EINVAL, "the half-stencil schedule needs every axis a multiple of 16 cells");
     }
-    if (schedule != h->pair_schedule) h->rho_valid = h->force_valid = false;
+    if (schedule != h->pair_schedule) {
+        h->rho_valid = h->force_valid = false;
+        drop_graph(h);
+    }
     h->pair_schedule = schedule;
     return MISA_OK;
 }
@@ -882,29 +948,18 @@ int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, mis
         GroupTimer t(h, MISA_TIMER_OTHER);
         HIPCHK(h, launch_dt_update(h, dt_max, dx_max, true));
     }
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const bool last = s == nsteps - 1;
-        {
-            GroupTimer t(h, MISA_TIMER_KICK);
-            HIPCHK(h, launch_kick_drift(h));
+    int64_t s = 0;
+    if (h->use_graph && !h->timing && nsteps >= 2) {
+        // every step but the last issues the same kernels with the same arguments (dt
+        // lives on the device): replay one captured step
+        if (!h->graph_exec || h->graph_dt != dt_max || h->graph_dx != dx_max) {
+            drop_graph(h);
+            if ((rc = capture_step(h, fused, dt_max, dx_max))) return rc;
         }
-        {
-            GroupTimer t(h, MISA_TIMER_RUNAWAY);
-            HIPCHK(h, launch_rehash(h));
-        }
-        if ((rc = do_rho(h))) return rc;
-        if ((rc = do_force(h, last, nullptr, fused))) return rc;
-        {
-            GroupTimer t(h, MISA_TIMER_KICK);
-            HIPCHK(h, launch_final_kick(h));
-        }
-        {
-            GroupTimer t(h, MISA_TIMER_OTHER);
-            HIPCHK(h, launch_dt_update(h, dt_max, dx_max, false));
-        }
-        if ((rc = finish_force(h))) return rc;  // after the step statistics read the affected list
-        if (h->timed.size() > 50000) HIPCHK(h, fold_timing(h));  // bound the event backlog
+        for (; s < nsteps - 1; ++s) HIPCHK(h, hipGraphLaunch(h->graph_exec, h->stream));
     }
+    for (; s < nsteps; ++s)
+        if ((rc = step_body(h, s == nsteps - 1, fused, dt_max, dx_max))) return rc;
     h->steps_done += nsteps;
     if (!stats) return MISA_OK;
     double scal[8];
@@ -1305,6 +1360,14 @@ int misa_defects(misa_lattice *h, int64_t *counts) {
     counts[1] = (int64_t)c[1];
     counts[2] = n_run;
     counts[3] = (int64_t)c[0];
+    return MISA_OK;
+}
+
+int misa_set_graph(misa_lattice *h, int enable) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    if (enable && !h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    if (!enable) drop_graph(h);
+    h->use_graph = enable != 0;
     return MISA_OK;
 }
 

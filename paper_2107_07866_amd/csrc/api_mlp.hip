@@ -270,6 +270,7 @@ int misa_set_mlp(misa_lattice *h, int fn, const misa_mlp_net *net) {
     A.net[fn] = meta_of(net->x_lo, net->x_hi, net->y_shift, net->y_scale, A.p[fn]);
     A.set[fn] = true;
     h->rho_valid = h->force_valid = false;
+    misa::drop_graph(h);  // the networks' ranges are kernel arguments of the captured step
     return MISA_OK;
 }
 

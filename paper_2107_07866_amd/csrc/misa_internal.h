@@ -312,6 +312,13 @@ struct misa_lattice {
     int64_t steps_done = 0;
     double *staging = nullptr;                    // device staging for host copies
     int64_t staging_bytes = 0;
+    // HIP graph of one regular step (misa_set_graph): captured on a private stream,
+    // replayed on the handle's stream; valid for one (dt_max, dx_max) and dropped
+    // whenever tables, state binding, pair schedule or networks change
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    double graph_dt = 0.0, graph_dx = 0.0;
     // optional event timing of kernel groups
     bool timing = false;
     struct TimedGroup {
@@ -329,6 +336,7 @@ namespace misa {
 
 // ----------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).  All enqueue on h->stream.
+void drop_graph(misa_lattice *h);                      // forget the captured step (its arguments changed)
 hipError_t launch_rho(misa_lattice *h);
 hipError_t launch_force(misa_lattice *h, bool energy, bool kick);
 bool lds_path(const misa_lattice *h);                  // persistent float32 kernels usable

@@ -106,6 +106,10 @@ class Lattice:
     def step(self, nsteps, dt_max, dx_max=0.0):
         return M.misa_step(self.h, nsteps, dt_max, dx_max)
 
+    def set_graph(self, enable=True):
+        """Steps replay a captured HIP graph (launch overhead of small boxes)."""
+        M.misa_set_graph(self.h, enable)
+
     def set_timing(self, enable=True):
         M.misa_set_timing(self.h, enable)
 

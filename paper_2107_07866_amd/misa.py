@@ -99,6 +99,7 @@ def _load():
         "misa_step": ([vp, i64, C.c_double, C.c_double, C.POINTER(misa_step_stats)], C.c_int),
         "misa_get_atom_field": ([vp, C.c_int, vp, C.c_int], C.c_int),
         "misa_set_timing": ([vp, C.c_int], C.c_int),
+        "misa_set_graph": ([vp, C.c_int], C.c_int),
         "misa_get_timing": ([vp, C.POINTER(misa_timing)], C.c_int),
         "misa_debug_export": ([vp, C.c_int, C.POINTER(i64), i64], i64),
         "misa_defects": ([vp, C.POINTER(i64)], C.c_int),
@@ -253,6 +254,11 @@ def misa_step(h, nsteps, dt_max, dx_max=0.0, want_stats=True):
         raise MisaError(code, misa_last_error(h))
     _check(code, h)
     return st.as_dict() if want_stats else None
+
+
+def misa_set_graph(h, enable=True):
+    """Replay a captured HIP graph of one step inside misa_step."""
+    return _check(lib.misa_set_graph(h, int(bool(enable))), h)
 
 
 def misa_set_timing(h, enable=True):
