@@ -167,7 +167,7 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None,
     return out
 
 
-def run_batch(cfg, steps, warmup, err_sample, seq_steps=20):
+def run_batch(cfg, steps, warmup, err_sample, seq_steps=20, graph=False):
     """Batched replicas: every box stepped by misa_batch_step; beside it the same boxes
     stepped one handle at a time (seq_steps steps each) for the gain of batching."""
     import numpy as np
@@ -199,11 +199,13 @@ def run_batch(cfg, steps, warmup, err_sample, seq_steps=20):
     _log(f"[bench] batch: tile autotune {tune}")
     for k, b in enumerate(boxes):
         batch.boxes[k].set_state(b[1], b[2])
+    if graph:  # batched steps replay a captured HIP graph (per-kernel timing would disable it)
+        batch.set_graph(True)
     if warmup > 0:
         batch.step(warmup, cfg.dt_max, cfg.dx_max, want_stats=False)
     torch.cuda.synchronize()
     _log(f"[bench] batch: {warmup} warm-up steps done, {time.time() - t0:.1f} s")
-    M.misa_set_timing(batch.boxes[0].h, True)
+    M.misa_set_timing(batch.boxes[0].h, not graph)
     torch.cuda.synchronize()
     chunk = max(1, min(steps, 200))
     wall, done, st = 0.0, 0, None
@@ -218,7 +220,8 @@ def run_batch(cfg, steps, warmup, err_sample, seq_steps=20):
     timing = M.misa_get_timing(batch.boxes[0].h)
     M.misa_set_timing(batch.boxes[0].h, False)
     out = {"atom_steps_per_s": n_atoms * steps / wall, "ms_per_step": 1e3 * wall / steps,
-           "kernel_ms_per_step": {k: ms / steps for k, (ms, cnt) in timing.items()},
+           "kernel_ms_per_step": {k: ms / steps for k, (ms, cnt) in timing.items()} if not graph else {},
+           "graph_replay": bool(graph),
            "boxes": len(boxes), "atoms": n_atoms, "tile_autotune": tune,
            "n_runaway_total": int(sum(s["n_runaway"] for s in st)),
            "frenkel_pairs_total": int(sum(M.misa_defects(bx.h)["vacancies"] for bx in batch.boxes)),
@@ -369,7 +372,7 @@ def main():
         # so the default times the first 400 steps (about 0.3 ps of dynamics)
         steps = args.steps if args.steps is not None else 400
         torch.cuda.set_device(0)
-        res = run_batch(cfg, steps, args.warmup, args.error_sample)
+        res = run_batch(cfg, steps, args.warmup, args.error_sample, graph=args.graph)
         head = {"kernel_ms_per_step": res["kernel_ms_per_step"], "K": 64, "mean_pairs_per_atom": 58.0}
         line = {"metric": METRIC, "value": res["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1,
                 "steps": steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,

@@ -404,6 +404,12 @@ int misa_batch_set_potential_tables(misa_batch *b, const misa_table *f, const mi
  * misa_set_timing on box 0, the batch's kernel times accumulate on box 0. */
 int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max, misa_step_stats *stats);
 
+/* enable != 0: misa_batch_step replays one captured HIP graph of a batched step
+ * for all its steps but the last (as misa_set_graph does for one box).  The graph
+ * is captured again when the step's arguments change: dt_max, dx_max, tile
+ * shapes, or any box's tables, state binding, schedule or networks. */
+int misa_batch_set_graph(misa_batch *b, int enable);
+
 /* Tile shapes of the batched rho and force passes.  Every tile has 512 cells (1024
  * lanes, both sublattices) and is staged in LDS with a 2-cell halo; a box whose
  * sides are not multiples of 8 wastes less work on a shape that fits it better.

@@ -380,6 +380,7 @@ namespace misa {
 void drop_graph(misa_lattice *h) {
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     h->graph_exec = nullptr;
+    ++h->gen;  // a batch's captured step that holds this box goes stale too
 }
 
 __global__ void k_clear_marks(Scratch sc) {
@@ -1001,6 +1002,11 @@ struct misa_batch {
     int64_t cap_boxes = 0, cap_items = 0;
     std::vector<int32_t> shape;                  // tile shape of each box (index into TILE_SHAPES)
     StencilEntry<float> *d_st = nullptr;         // [N_TILE_SHAPES][2][KMAX]: stencil per tile shape
+    // graph of one regular batched step (misa_batch_set_graph), valid for graph_key
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint64_t> graph_key;
 };
 
 namespace {
@@ -1137,6 +1143,8 @@ int misa_batch_destroy(misa_batch *b) {
     (void)hipFree(b->d_pass);
     (void)hipFree(b->d_items);
     (void)hipFree(b->d_st);
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return MISA_OK;
 }
@@ -1199,9 +1207,12 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
     const hipStream_t st = b->stream;
     const int nitems = (int)b->items.size();
     const bool any_shape = std::any_of(b->shape.begin(), b->shape.end(), [](int32_t x) { return x != 0; });
-    // kernel timing of the batch, when enabled, accumulates on box 0's timers
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const bool last = s == nsteps - 1;
+    // One batched step on stream sq (box 0's stream field follows it, since the
+    // persistent passes launch on h0->stream).  Kernel timing of the batch, when
+    // enabled, accumulates on box 0's timers.
+    auto step_body = [&](bool last, hipStream_t sq) -> int {
+        const hipStream_t st = sq;
+        h0->stream = sq;
         {
             GroupTimer t(h0, MISA_TIMER_KICK);
             BCHK(b, launchb_kick_drift(st, b->d_ref, nb, gx_sites, gx_small, kf));
@@ -1244,7 +1255,46 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
             BCHK(b, launchb_runaway_clear(st, b->d_ref, nb, gx_small));
         }
         if (h0->timed.size() > 50000) BCHK(b, fold_timing(h0));
+        h0->stream = b->stream;
+        return MISA_OK;
+    };
+    int64_t s = 0;
+    if (b->use_graph && !h0->timing && nsteps >= 2) {
+        // the key: everything the captured launches bake in
+        std::vector<uint64_t> key = {(uint64_t)nitems, (uint64_t)any_shape, (uint64_t)gx_sites, (uint64_t)max_mark,
+                                     (uint64_t)(uintptr_t)b->d_ref, (uint64_t)(uintptr_t)b->d_pass,
+                                     (uint64_t)(uintptr_t)b->d_items};
+        uint64_t bits;
+        std::memcpy(&bits, &dt_max, 8);
+        key.push_back(bits);
+        std::memcpy(&bits, &dx_max, 8);
+        key.push_back(bits);
+        for (misa_lattice *h : b->box) key.push_back(h->gen);
+        if (!b->graph_exec || key != b->graph_key) {
+            if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+            b->graph_exec = nullptr;
+            BCHK(b, hipStreamSynchronize(b->stream));
+            hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+            int brc = MISA_OK;
+            if (e == hipSuccess) brc = step_body(false, b->cap_stream);
+            h0->stream = b->stream;
+            hipGraph_t graph = nullptr;
+            const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(b->cap_stream, &graph) : e;
+            if (brc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return brc;
+            }
+            BCHK(b, e2);
+            e = hipGraphInstantiate(&b->graph_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) b->graph_exec = nullptr;
+            BCHK(b, e);
+            b->graph_key = key;
+        }
+        for (; s < nsteps - 1; ++s) BCHK(b, hipGraphLaunch(b->graph_exec, b->stream));
     }
+    for (; s < nsteps; ++s)
+        if ((rc = step_body(s == nsteps - 1, b->stream))) return rc;
     std::vector<double> scal(8 * (size_t)nb);
     std::vector<Counters> cnt(nb);
     for (int k = 0; k < nb; ++k) {
@@ -1278,6 +1328,17 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         if (cnt[k].overflow) worst = bfail(b, MISA_EOVERFLOW, "box " + std::to_string(k) + ": run-away capacity exceeded");
     }
     return worst;
+}
+
+int misa_batch_set_graph(misa_batch *b, int enable) {
+    if (!b) return MISA_EINVAL;
+    if (enable && !b->cap_stream) BCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    if (!enable && b->graph_exec) {
+        (void)hipGraphExecDestroy(b->graph_exec);
+        b->graph_exec = nullptr;
+    }
+    b->use_graph = enable != 0;
+    return MISA_OK;
 }
 
 int misa_batch_set_tile_shape(misa_batch *b, int32_t k, int32_t shape) {

@@ -316,6 +316,7 @@ struct misa_lattice {
     // replayed on the handle's stream; valid for one (dt_max, dx_max) and dropped
     // whenever tables, state binding, pair schedule or networks change
     bool use_graph = false;
+    uint64_t gen = 0;                     // advances whenever captured kernel arguments go stale
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     double graph_dt = 0.0, graph_dx = 0.0;

@@ -151,6 +151,10 @@ class Batch:
     def step(self, nsteps, dt_max, dx_max=0.0, want_stats=True):
         return M.misa_batch_step(self.b, len(self.boxes), nsteps, dt_max, dx_max, want_stats)
 
+    def set_graph(self, enable=True):
+        """Batched steps replay a captured HIP graph."""
+        M.misa_batch_set_graph(self.b, enable)
+
     def set_tile_shape(self, k, shape):
         """Tile shape of box k in the batched passes: an index into M.MISA_TILE_SHAPES."""
         M.misa_batch_set_tile_shape(self.b, k, shape)

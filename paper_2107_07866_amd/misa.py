@@ -125,6 +125,7 @@ def _load():
                                              C.POINTER(misa_table)], C.c_int),
         "misa_batch_step": ([vp, i64, C.c_double, C.c_double, C.POINTER(misa_step_stats)], C.c_int),
         "misa_batch_set_tile_shape": ([vp, C.c_int32, C.c_int32], C.c_int),
+        "misa_batch_set_graph": ([vp, C.c_int], C.c_int),
         "misa_batch_get_tile_shape": ([vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
         "misa_batch_autotune": ([vp, i64, C.c_double, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                  C.POINTER(i64)], C.c_int),
@@ -491,3 +492,8 @@ def misa_batch_autotune(b, probe_steps, dt_max, dx_max=0.0):
     _bcheck(lib.misa_batch_autotune(b, int(probe_steps), float(dt_max), float(dx_max), C.byref(pol), ms,
                                     C.byref(done)), b)
     return {"policy": pol.value, "ms_per_step": [ms[0], ms[1]], "steps_done": done.value}
+
+
+def misa_batch_set_graph(b, enable=True):
+    """Replay a captured HIP graph of one batched step inside misa_batch_step."""
+    return _bcheck(lib.misa_batch_set_graph(b, int(bool(enable))), b)

@@ -67,3 +67,38 @@ def test_graph_replay_equals_launched_steps(torch_cuda, precision, schedule):
     assert st[1]["n_runaway"] >= 1
     for lat in (eager, graph):
         lat.close()
+
+
+def test_batch_graph_replay_equals_launched_steps(torch_cuda):
+    """Batched steps replayed from a graph equal launched batched steps, also after
+    tile shapes change (a new capture) and with eager work between the calls."""
+    torch = torch_cuda
+    from paper_2107_07866_amd import Batch
+    cfg = w.BATCH_CONFIGS["c4"]
+    boxes = w.make_batch(cfg, 5)
+    cells = [b[0] for b in boxes]
+    bats = []
+    for graph in (False, True):
+        bt = Batch(cells, A, RC, DELTA, M)
+        bt.set_tables(TABLES)
+        for k, b in enumerate(boxes):
+            bt.boxes[k].set_state(b[1], b[2])
+        bt.set_graph(graph)
+        bats.append(bt)
+    for rnd, nsteps in enumerate((8, 5, 1, 9)):
+        if rnd == 2:
+            for bt in bats:
+                bt.set_tile_shape(1, 3)
+        st = [bt.step(nsteps, cfg.dt_max, cfg.dx_max) for bt in bats]
+        torch.cuda.synchronize()
+        for k in range(len(cells)):
+            xe, ve = bats[0].boxes[k].get_state()
+            xg, vg = bats[1].boxes[k].get_state()
+            assert np.array_equal(xe, xg) and np.array_equal(ve, vg), (rnd, k)
+            for key in ("dt", "time", "e_kin", "e_emb", "e_pair", "n_runaway"):
+                assert st[0][k][key] == st[1][k][key], (rnd, k, key)
+        for bt in bats:  # eager work between the calls
+            bt.boxes[0].forces()
+        _say(f"batch round {rnd}: {nsteps} steps equal")
+    for bt in bats:
+        bt.close()
