@@ -31,16 +31,18 @@ __device__ __forceinline__ void kick_drift_body(State S, Scratch sc, Geom g, dou
     const Real *fz = (const Real *)S.fz;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites;
          s += (int64_t)gridDim.x * blockDim.x) {
-        double ux = S.ux[s];
-        if (ux > VACANT_TEST) continue;
-        double uy = S.uy[s], uz = S.uz[s];
+        // No branch before the arithmetic, so no load waits on another: an empty slot
+        // (u = VACANT_U, v = 0, F = 0) comes out of the update unchanged and is only
+        // kept out of the leaver test.
+        double ux = S.ux[s], uy = S.uy[s], uz = S.uz[s];
+        const bool vacant = ux > VACANT_TEST;
         const double vx = S.vx[s] + hk * (double)fx[s];
         const double vy = S.vy[s] + hk * (double)fy[s];
         const double vz = S.vz[s] + hk * (double)fz[s];
         ux += dt * vx;
         uy += dt * vy;
         uz += dt * vz;
-        if (ux * ux + uy * uy + uz * uz > g.delta2) {
+        if (!vacant && ux * ux + uy * uy + uz * uz > g.delta2) {
             const int slot = atomicAdd(&sc.cnt->n_leave, 1);
             if (slot < room) {
                 const int p = s >= g.ncell ? 1 : 0;
@@ -116,8 +118,8 @@ __global__ void kb_kick_drift_runaway(const BoxRef *__restrict__ boxes, double k
 
 // Second half-kick (kick = 1) or plain velocity statistics (kick = 0):
 // per-block max |v|^2 and sum |v|^2 over the lattice atoms.
-template <typename Real>
-__global__ __launch_bounds__(KICK_THREADS) void k_final_kick(State S, Scratch sc, Geom g, double kf, int kick,
+template <typename Real, bool kick>
+__global__ __launch_bounds__(KICK_THREADS) void k_final_kick(State S, Scratch sc, Geom g, double kf,
                                                              double *__restrict__ part) {
     __shared__ double red[2][KICK_THREADS / 64];
     const double hk = 0.5 * sc.scal[0] * kf;
@@ -125,9 +127,10 @@ __global__ __launch_bounds__(KICK_THREADS) void k_final_kick(State S, Scratch sc
     const Real *fy = (const Real *)S.fy;
     const Real *fz = (const Real *)S.fz;
     double vm = 0.0, ks = 0.0;
+    // An empty slot holds v = 0 and F = 0 (both cleared when it empties), so it
+    // needs no test: its kick and its |v|^2 are zero.
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites;
          s += (int64_t)gridDim.x * blockDim.x) {
-        if (S.ux[s] > VACANT_TEST) continue;
         double vx = S.vx[s], vy = S.vy[s], vz = S.vz[s];
         if (kick) {
             vx += hk * (double)fx[s];
@@ -351,12 +354,9 @@ hipError_t launch_kick_drift(misa_lattice *h) {
 static hipError_t kick_impl(misa_lattice *h, int kick) {
     const double kf = ACC_UNIT / h->mass;
     double *part = h->sc.part + 2 * (int64_t)h->g.ntiles_pad;  // after the per-tile energy partials
-    if (h->precision == MISA_FP32)
-        hipLaunchKernelGGL(k_final_kick<float>, dim3(KICK_BLOCKS), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc,
-                           h->g, kf, kick, part);
-    else
-        hipLaunchKernelGGL(k_final_kick<double>, dim3(KICK_BLOCKS), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc,
-                           h->g, kf, kick, part);
+    auto kern = h->precision == MISA_FP32 ? (kick ? k_final_kick<float, true> : k_final_kick<float, false>)
+                                          : (kick ? k_final_kick<double, true> : k_final_kick<double, false>);
+    hipLaunchKernelGGL(kern, dim3(KICK_BLOCKS), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc, h->g, kf, part);
     if (kick)
         hipLaunchKernelGGL(k_final_kick_runaway, dim3(SMALL_GRID), dim3(256), 0, h->stream, h->S, h->sc, kf);
     return hipGetLastError();
