@@ -1380,18 +1380,23 @@ int misa_batch_autotune(misa_batch *b, int64_t probe_steps, double dt_max, doubl
         }
     }
     const int npol = cand[1] == cand[0] ? 1 : 2;
+    const std::vector<int32_t> before = b->shape;
     double ms[2] = {0.0, 0.0};
     int64_t done = 0;
     for (int pol = 0; pol < npol; ++pol) {
         b->shape = cand[pol];
         int rc = misa_batch_step(b, 1, dt_max, dx_max, nullptr);  // untimed: first launches of this tiling
-        if (rc) return rc;
+        if (!rc) ++done;
         const auto t0 = std::chrono::steady_clock::now();
-        rc = misa_batch_step(b, probe_steps, dt_max, dx_max, nullptr);  // synchronises at the end
-        if (rc) return rc;
+        if (!rc) rc = misa_batch_step(b, probe_steps, dt_max, dx_max, nullptr);  // synchronises at the end
+        if (rc) {  // the tiling in force when the call began; *steps_done: the steps the boxes did advance
+            b->shape = before;
+            if (steps_done) *steps_done = done;
+            return rc;
+        }
         ms[pol] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() /
                   (double)probe_steps;
-        done += 1 + probe_steps;
+        done += probe_steps;
     }
     const int best = (npol == 2 && ms[1] < ms[0]) ? 1 : 0;
     b->shape = cand[best];

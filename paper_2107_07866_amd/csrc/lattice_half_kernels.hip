@@ -155,7 +155,8 @@ __device__ __forceinline__ int hf_seg(float pp, int nwin, float &t) {
 // ---------------------------------------------------------------------------
 // rho: rho_i and rho_j += f(r) for every owned pair; one launch per colour.
 template <bool kNodeCut>
-__global__ __launch_bounds__(HF_THREADS) void k_rho_half(ColourTiles ct, State S, Geom g, const StencilEntry<float> *__restrict__ hst,
+__global__ __launch_bounds__(HF_THREADS) void k_rho_half(ColourTiles ct, State S, Geom g,
+                                                         const StencilEntry<float> *__restrict__ hst,
                                                          const int32_t *__restrict__ hmeta,
                                                          const Q4<float> *__restrict__ fwin, float inv_hq,
                                                          float pcq, int nwin, float rc2, float u_cut2) {
@@ -268,8 +269,9 @@ __global__ void k_embed_half(State S, Geom g, Tables<float> T, unsigned *range_v
 // force: F_i += s d, F_j -= s d for every owned pair (s = (F'_i + F'_j) f'/r + phi'/r);
 // with kEnergy also the per-tile sums of F(rho_i) and of phi over the owned pairs.
 template <bool kEnergy, bool kNodeCut>
-__global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State S, Geom g, const StencilEntry<float> *__restrict__ hst,
-                                                         const int32_t *__restrict__ hmeta,
+__global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State S, Geom g,
+                                                           const StencilEntry<float> *__restrict__ hst,
+                                                           const int32_t *__restrict__ hmeta,
                                                            const FRec32 *__restrict__ fwin, float inv_hq,
                                                            float pcq, int nwin, Tables<float> T, float rc2,
                                                            float u_cut2, double *__restrict__ part) {
