@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = "atom-steps/s + HBM GB/s: FP64-table vs FP32 vs MLP forms at stated force error"
 
-# Algorithmic cost model (one directed pair i <- j per stencil candidate; see DESIGN.md):
+# Algorithmic cost model (one directed pair i <- j per stencil candidate):
 FLOP_CANDIDATE = 8      # separation (3) and squared distance (5) for every stencil candidate
 FLOP_RHO_PAIR = 10      # sqrt, table index (2), cubic (6), accumulate
 FLOP_FORCE_PAIR = 21    # sqrt, index (2), f' and phi' (8), (F'_i+F'_j) f' + phi' (3), / r, x d and accumulate (6)
@@ -357,7 +357,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs one GPU only (the multi-GPU halo-exchange path is design-only); "
+        print("bench.py: runs on one GPU only (spreading a box over GPUs by halo exchange is not implemented); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
