@@ -73,7 +73,7 @@ typedef struct {
     double delta;             /* slot tolerance: an atom keeps its lattice slot while |x - site| <= delta;
                                  0 < delta < a sqrt(3) / 4 (half the nearest-neighbour distance) */
     double mass;              /* atom mass, > 0 */
-    int64_t runaway_capacity; /* max atoms outside the lattice array; <= 0 picks max(16384, sites / 128) */
+    int64_t runaway_capacity; /* max atoms outside the lattice array; <= 0 picks max(16384, sites / 1024) */
 } misa_lattice_desc;
 
 /* Equidistant samples y[k] = g(x0 + k dx), k = 0 .. n - 1 (host memory; copied, not retained). */
