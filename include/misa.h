@@ -144,8 +144,12 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
  * id = row index) from host or device memory.  Each atom goes to the slot of
  * its nearest site (the hash of Sec. 3) if it lies within delta of it; the
  * lowest atom id wins a contested slot; every other atom becomes a run-away
- * (hash-clash) atom.  Fails with MISA_EOVERFLOW if those exceed the run-away
- * capacity.  Invalidates densities and forces.  Requires a bound state.
+ * (hash-clash) atom, listed in ascending id.  The placement runs on the GPU
+ * (host arrays are uploaded to temporary device memory first; device arrays must
+ * be ready in the handle's stream order); the call synchronises the stream.
+ * Fails with MISA_EINVAL on a non-finite value and with MISA_EOVERFLOW if the
+ * run-away atoms exceed the run-away capacity; after a failure no state is
+ * loaded.  Invalidates densities and forces.  Requires a bound state.
  */
 int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n_atoms, int where);
 

@@ -793,87 +793,65 @@ int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n,
     if (n < 0 || n >= (int64_t)INT32_MAX) return fail(h, MISA_EINVAL, "atom count out of range");
     if (n > 0 && (!x || !v)) return fail(h, MISA_EINVAL, "null positions or velocities");
     if (where != MISA_HOST && where != MISA_DEVICE) return fail(h, MISA_EINVAL, "bad memory kind");
-    const Geom &g = h->g;
-    std::vector<double> hx, hv;
-    const double *X = x, *V = v;
-    if (where == MISA_DEVICE && n > 0) {
-        hx.resize(3 * n);
-        hv.resize(3 * n);
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        HIPCHK(h, hipMemcpy(hx.data(), x, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
-        HIPCHK(h, hipMemcpy(hv.data(), v, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
-        X = hx.data();
-        V = hv.data();
-    }
-    for (int64_t i = 0; i < 3 * n; ++i)
-        if (!std::isfinite(X[i]) || !std::isfinite(V[i])) return fail(h, MISA_EINVAL, "non-finite position or velocity");
-    // placement: ascending atom id, first claimant of a slot is the lowest id
-    const int64_t ns = g.nsites;
-    std::vector<int32_t> atom(ns, VACANT_ID);
-    std::vector<double> u(3 * ns, VACANT_U), vel(3 * ns, 0.0);
-    std::vector<int32_t> rid;
-    std::vector<double> rpos, rvel;
-    for (int64_t i = 0; i < n; ++i) {
-        double uu[3], u2;
-        const int64_t s = hash_site(X + 3 * i, g, uu, &u2);
-        if (u2 <= g.delta2 && atom[s] == VACANT_ID) {
-            atom[s] = (int32_t)i;
-            for (int k = 0; k < 3; ++k) {
-                u[k * ns + s] = uu[k];
-                vel[k * ns + s] = V[3 * i + k];
-            }
-        } else {
-            rid.push_back((int32_t)i);
-            for (int k = 0; k < 3; ++k) {
-                rpos.push_back(wrap_coord(X[3 * i + k], g.L[k]));
-                rvel.push_back(V[3 * i + k]);
-            }
-        }
-    }
-    const int64_t R = (int64_t)rid.size();
-    if (R > h->rcap)
-        return fail(h, MISA_EOVERFLOW, "more atoms off their sites (" + std::to_string(R) +
-                                           ") than the run-away capacity (" + std::to_string(h->rcap) + ")");
+    // Placement runs on the device (launch_place): host arrays are uploaded first.
+    // Temporary device memory: x, v (host input only), the bid of every atom and a flag.
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    State &S = h->S;
-    double *ud[3] = {S.ux, S.uy, S.uz}, *vd[3] = {S.vx, S.vy, S.vz};
-    for (int k = 0; k < 3; ++k) {
-        HIPCHK(h, hipMemcpy(ud[k], u.data() + k * ns, sizeof(double) * ns, hipMemcpyHostToDevice));
-        HIPCHK(h, hipMemcpy(vd[k], vel.data() + k * ns, sizeof(double) * ns, hipMemcpyHostToDevice));
+    h->state_set = false;  // until the new state is complete
+    h->rho_valid = h->force_valid = h->pending_clear = false;
+    const int64_t nn = std::max<int64_t>(n, 1);
+    const size_t xv_bytes = where == MISA_HOST ? 2 * sizeof(double) * 3 * (size_t)nn : 0;
+    const size_t bytes = xv_bytes + sizeof(int32_t) * (size_t)nn + 256;
+    char *tmp = nullptr;
+    HIPCHK(h, hipMalloc((void **)&tmp, bytes));
+    auto done = [&](int rc) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(tmp);
+        return rc;
+    };
+    const double *xd = x, *vd = v;
+    if (where == MISA_HOST && n > 0) {
+        double *xs = (double *)tmp, *vs = xs + 3 * nn;
+        hipError_t e = hipMemcpy(xs, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(vs, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return done(fail(h, MISA_EHIP, std::string("upload: ") + hipGetErrorString(e)));
+        xd = xs;
+        vd = vs;
     }
-    HIPCHK(h, hipMemcpy(S.atom, atom.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice));
-    const int64_t rs = h->precision == MISA_FP32 ? 4 : 8;
-    HIPCHK(h, hipMemset(S.fx, 0, rs * ns));
-    HIPCHK(h, hipMemset(S.fy, 0, rs * ns));
-    HIPCHK(h, hipMemset(S.fz, 0, rs * ns));
-    HIPCHK(h, hipMemset(S.rho, 0, rs * ns));
-    HIPCHK(h, hipMemset(S.fp, 0, rs * ns));
-    if (R > 0) {
-        std::vector<double> col(R);
-        double *rpd[3] = {S.r_x, S.r_y, S.r_z}, *rvd[3] = {S.r_vx, S.r_vy, S.r_vz};
-        for (int k = 0; k < 3; ++k) {
-            for (int64_t r = 0; r < R; ++r) col[r] = rpos[3 * r + k];
-            HIPCHK(h, hipMemcpy(rpd[k], col.data(), sizeof(double) * R, hipMemcpyHostToDevice));
-            for (int64_t r = 0; r < R; ++r) col[r] = rvel[3 * r + k];
-            HIPCHK(h, hipMemcpy(rvd[k], col.data(), sizeof(double) * R, hipMemcpyHostToDevice));
-        }
-        HIPCHK(h, hipMemcpy(S.r_id, rid.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice));
-        HIPCHK(h, hipMemset(S.r_fx, 0, 8 * R));
-        HIPCHK(h, hipMemset(S.r_fy, 0, 8 * R));
-        HIPCHK(h, hipMemset(S.r_fz, 0, 8 * R));
-    }
+    int32_t *cand = (int32_t *)(tmp + xv_bytes);
+    uint32_t *bad = (uint32_t *)(tmp + xv_bytes + sizeof(int32_t) * (size_t)nn);
     Counters c{};
-    c.n_run = (int32_t)R;
-    HIPCHK(h, hipMemcpy(h->sc.cnt, &c, sizeof(c), hipMemcpyHostToDevice));
-    HIPCHK(h, hipMemset(h->sc.scal, 0, 8 * sizeof(double)));
-    HIPCHK(h, hipMemset(h->sc.mark, 0, sizeof(uint32_t) * (size_t)h->sc.mark_nwords));
-    HIPCHK(h, hipMemset(h->sc.hkey, 0xff, sizeof(int32_t) * (size_t)(h->sc.hmask + 1)));
-    HIPCHK(h, hipDeviceSynchronize());
+    hipError_t e = hipMemcpy(h->sc.cnt, &c, sizeof(c), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(bad, 0, sizeof(uint32_t));
+    if (e == hipSuccess) e = launch_place(h, xd, vd, n, cand, bad);
+    uint32_t nbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&c, h->sc.cnt, sizeof(c), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return done(fail(h, MISA_EHIP, std::string("placement: ") + hipGetErrorString(e)));
+    if (nbad) return done(fail(h, MISA_EINVAL, "non-finite position or velocity"));
+    const int64_t R = c.n_leave;
+    if (R > h->rcap)
+        return done(fail(h, MISA_EOVERFLOW, "more atoms off their sites (" + std::to_string(R) +
+                                                ") than the run-away capacity (" + std::to_string(h->rcap) + ")"));
+    // the atoms left without a slot become the run-away list in ascending id (the
+    // leaver sort and compaction; no bid succeeds, every slot they could claim is taken)
+    e = launch_rehash(h);
+    const State &S = h->S;
+    if (e == hipSuccess && R > 0) {
+        e = hipMemsetAsync(S.r_fx, 0, 8 * R, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(S.r_fy, 0, 8 * R, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(S.r_fz, 0, 8 * R, h->stream);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(h->sc.scal, 0, 8 * sizeof(double), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->sc.mark, 0, sizeof(uint32_t) * (size_t)h->sc.mark_nwords, h->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(h->sc.hkey, 0xff, sizeof(int32_t) * (size_t)(h->sc.hmask + 1), h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return done(fail(h, MISA_EHIP, std::string("placement: ") + hipGetErrorString(e)));
     h->n_atoms = n;
     h->steps_done = 0;
     h->state_set = true;
-    h->rho_valid = h->force_valid = h->pending_clear = false;
-    return MISA_OK;
+    return done(MISA_OK);
 }
 
 int misa_atom_count(const misa_lattice *h, int64_t *n_atoms) {

@@ -4,6 +4,8 @@
 // leave the array), the adaptive step length, and the copies out of the store.
 #include "misa_internal.h"
 
+#include <algorithm>
+
 namespace misa {
 
 constexpr int KICK_BLOCKS = 1024;  // fixed grid => fixed reduction order
@@ -250,6 +252,91 @@ __global__ __launch_bounds__(1024) void kb_dt_update(const BoxRef *__restrict__ 
 
 
 // ---------------------------------------------------------------------------
+// placement into the store (misa_set_state): the hash rule of Sec. 3 applied to
+// every atom at once.  An atom takes the slot of its nearest site when it lies
+// within delta of it and no lower atom id claims the same slot; every other atom
+// becomes a run-away atom (listed afterwards in ascending id by the leaver sort
+// and compaction of the hash update).
+
+template <typename Real>
+__global__ void k_place_clear(State S, Geom g) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites; s += stride) {
+        S.atom[s] = VACANT_ID;
+        S.ux[s] = VACANT_U;
+        S.uy[s] = VACANT_U;
+        S.uz[s] = VACANT_U;
+        S.vx[s] = 0.0;
+        S.vy[s] = 0.0;
+        S.vz[s] = 0.0;
+        ((Real *)S.fx)[s] = (Real)0;
+        ((Real *)S.fy)[s] = (Real)0;
+        ((Real *)S.fz)[s] = (Real)0;
+        ((Real *)S.rho)[s] = (Real)0;
+        ((Real *)S.fp)[s] = (Real)0;
+    }
+}
+
+// Bids: atom i within delta of its nearest site bids for that slot with its id.
+// x, v: (n, 3) row-major device arrays; bad counts non-finite inputs.
+__global__ void k_place_claim(const double *__restrict__ x, const double *__restrict__ v, int64_t n, Geom g,
+                              State S, int32_t *__restrict__ cand, uint32_t *__restrict__ bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double X[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+        const double V[3] = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
+        bool finite = true;
+        for (int k = 0; k < 3; ++k) finite = finite && isfinite(X[k]) && isfinite(V[k]);
+        int32_t c = -1;
+        if (!finite) {
+            atomicAdd(bad, 1u);
+        } else {
+            double u[3], u2;
+            const int64_t s = hash_site(X, g, u, &u2);
+            if (u2 <= g.delta2) {
+                c = (int32_t)s;
+                atomicMin(&S.atom[s], (int32_t)i);
+            }
+        }
+        cand[i] = c;
+    }
+}
+
+// The lowest bidder moves into its slot; every other atom joins the leaver list
+// (capacity rcap; the count keeps growing past it so the host can report it).
+__global__ void k_place_settle(const double *__restrict__ x, const double *__restrict__ v, int64_t n, Geom g,
+                               State S, Scratch sc, const int32_t *__restrict__ cand, int64_t rcap) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double X[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+        const double V[3] = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
+        const int32_t s = cand[i];
+        if (s >= 0 && S.atom[s] == (int32_t)i) {
+            double u[3], u2;
+            hash_site(X, g, u, &u2);
+            S.ux[s] = u[0];
+            S.uy[s] = u[1];
+            S.uz[s] = u[2];
+            S.vx[s] = V[0];
+            S.vy[s] = V[1];
+            S.vz[s] = V[2];
+        } else {
+            const int slot = atomicAdd(&sc.cnt->n_leave, 1);
+            if (slot < rcap) {
+                sc.l_site[slot] = -1;
+                sc.l_id[slot] = (int32_t)i;
+                sc.l_x[slot] = wrap_coord(X[0], g.L[0]);
+                sc.l_y[slot] = wrap_coord(X[1], g.L[1]);
+                sc.l_z[slot] = wrap_coord(X[2], g.L[2]);
+                sc.l_vx[slot] = V[0];
+                sc.l_vy[slot] = V[1];
+                sc.l_vz[slot] = V[2];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // copies out of the store, in atom-id order
 
 __global__ void k_gather_state(State S, Scratch sc, Geom g, double *__restrict__ x, double *__restrict__ v) {
@@ -398,6 +485,23 @@ hipError_t launchb_final_kick_runaway(hipStream_t st, const BoxRef *boxes, int n
 hipError_t launchb_dt_update(hipStream_t st, const BoxRef *boxes, int nbox, double mass, double dt_max,
                              double dx_max) {
     hipLaunchKernelGGL(kb_dt_update, dim3(1, nbox), dim3(1024), 0, st, boxes, mass, dt_max, dx_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(misa_lattice *h, const double *x, const double *v, int64_t n, int32_t *cand,
+                        uint32_t *bad) {
+    const int nb = site_blocks(h->g);
+    if (h->precision == MISA_FP32)
+        hipLaunchKernelGGL(k_place_clear<float>, dim3(nb), dim3(KICK_THREADS), 0, h->stream, h->S, h->g);
+    else
+        hipLaunchKernelGGL(k_place_clear<double>, dim3(nb), dim3(KICK_THREADS), 0, h->stream, h->S, h->g);
+    if (n > 0) {
+        const int na = (int)std::min<int64_t>((n + KICK_THREADS - 1) / KICK_THREADS, 65536 * 4);
+        hipLaunchKernelGGL(k_place_claim, dim3(na), dim3(KICK_THREADS), 0, h->stream, x, v, n, h->g, h->S, cand,
+                           bad);
+        hipLaunchKernelGGL(k_place_settle, dim3(na), dim3(KICK_THREADS), 0, h->stream, x, v, n, h->g, h->S, h->sc,
+                           cand, h->rcap);
+    }
     return hipGetLastError();
 }
 

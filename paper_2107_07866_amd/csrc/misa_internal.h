@@ -367,6 +367,9 @@ hipError_t launch_rehash(misa_lattice *h);             // sort leavers, claims, 
 hipError_t launch_final_kick(misa_lattice *h);         // + vmax / KE partials
 hipError_t launch_dt_update(misa_lattice *h, double dt_max, double dx_max, bool first);
 hipError_t launch_gather_state(misa_lattice *h, double *x, double *v);
+// placement of (n, 3) device positions / velocities into cleared slots; the rest to the leaver list
+hipError_t launch_place(misa_lattice *h, const double *x, const double *v, int64_t n, int32_t *cand,
+                        uint32_t *bad);
 // batched replicas: one launch per kernel over every box (blockIdx.y = box)
 hipError_t launchb_kick_drift(hipStream_t st, const BoxRef *boxes, int nbox, int gx_sites, int gx_small, double kf);
 hipError_t launchb_final_kick_runaway(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small, double kf);

@@ -116,6 +116,43 @@ def test_placement_matches_oracle(torch_cuda, orc, n):
     lat.close()
 
 
+def test_placement_from_device_memory_and_failures(torch_cuda, orc):
+    """Device-resident inputs place exactly as host inputs do; a non-finite value and
+    a run-away overflow are refused, and the next valid call loads normally."""
+    import torch
+    from paper_2107_07866_amd import misa as M
+    n = 7
+    states, box = _defect_states(n, seed=5)
+    x, v = states["many_runaways"]
+    _say("placement from device memory, refusals")
+    lat = _lattice(n, cap=4096)
+    lat.set_state(torch.from_numpy(x).cuda(), torch.from_numpy(v).cuda())
+    got = lat.slots()
+    assert np.array_equal(got, orc.place((n, n, n), A, DELTA, x))
+    xg, vg = lat.get_state()
+    L = np.asarray(box)
+    d = xg - x
+    d -= L * np.rint(d / L)
+    assert np.max(np.abs(d)) < 1e-12 and np.array_equal(vg, v)
+    bad = x.copy()
+    bad[17, 1] = np.nan
+    with pytest.raises(M.MisaError) as err:
+        lat.set_state(bad, v)
+    assert err.value.code == M.MISA_EINVAL
+    lat.set_state(x, v)
+    assert np.array_equal(lat.slots(), got)
+    lat.close()
+    lat = _lattice(n, cap=8)  # fewer run-away slots than this state needs
+    assert int(np.sum(got < 0)) > 8
+    with pytest.raises(M.MisaError) as err:
+        lat.set_state(x, v)
+    assert err.value.code == M.MISA_EOVERFLOW
+    xs, vs = states["thermal"]
+    lat.set_state(xs, vs)
+    assert np.array_equal(lat.slots(), orc.place((n, n, n), A, DELTA, xs))
+    lat.close()
+
+
 # ---------------------------------------------------------------------------
 # per-state densities, forces, energies (FP64)
 
