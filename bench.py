@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # bytes each pass must move per atom (each datum once): u, v, F, rho, F' as stored per form.
 # The FP32 form fuses the final half-kick into the force pass (it also reads and writes v).
 BYTES_PER_ATOM_STEP = {
-    "fp64": {"kick_drift": 120, "rho": 40, "force": 56, "final_kick": 72},
+    "fp64": {"kick_drift": 120, "rho": 40, "force": 104, "final_kick": 0},
     "fp32": {"kick_drift": 108, "rho": 32, "force": 88, "final_kick": 0},
     "mlp": {"kick_drift": 108, "rho": 32, "force": 40, "final_kick": 60},
 }

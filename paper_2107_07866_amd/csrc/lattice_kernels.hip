@@ -183,16 +183,27 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// The second half-kick of velocity Verlet fused into the force pass: v += (dt/2) C F / m
+// as soon as F_i is known, plus per-tile {max |v|^2, sum |v|^2} over the atoms no
+// run-away atom touches (those get their run-away terms, kick and statistics later).
+struct KickArgs {
+    double *vx, *vy, *vz;
+    const uint32_t *mark;
+    const double *scal;  // scal[0] = dt of the current step
+    double *part_kick;
+    double kf;           // C / m
+};
+
 // F_i = sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (x_j - x_i) / r   (Eq. eam_force_ij)
 // With kEnergy: per-tile partial sums of F(rho_i) and 1/2 sum_j phi(r_ij).
-template <typename Real, bool kEnergy>
+template <typename Real, bool kEnergy, bool kKick>
 __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
     const Real *__restrict__ fp, const Real *__restrict__ rho, Real *__restrict__ fx, Real *__restrict__ fy,
     Real *__restrict__ fz, const StencilEntry<Real> *__restrict__ st, int K, int kin, float u_cut2, Tables<Real> T,
-    Geom g, double *__restrict__ part) {
+    Geom g, double *__restrict__ part, KickArgs kick) {
     __shared__ Q4<Real> tile[TILE_SITES];
-    __shared__ double red[2][TILE_THREADS / 64];
+    __shared__ double red[4][TILE_THREADS / 64];
     __shared__ unsigned umax;
     const int tid = tile_of_block(blockIdx.x, g);
     if (tid >= g.ntiles) return;
@@ -211,7 +222,16 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
     const int lz = w % TZ, lx = lane % TX, ly = lane / TX;
     const int gx = tx * TX + lx, gy = ty * TY + ly, gz = tz * TZ + lz;
     const bool active = gx < g.nx && gy < g.ny && gz < g.nz;
-    double e_emb = 0.0, e_pair = 0.0;
+    const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+    double e_emb = 0.0, e_pair = 0.0, kvm = 0.0, kvs = 0.0;
+    double v0x = 0.0, v0y = 0.0, v0z = 0.0;
+    uint32_t mw = 0u;
+    if (kKick && active) {  // issued now, consumed after the pair loop
+        v0x = kick.vx[idx];
+        v0y = kick.vy[idx];
+        v0z = kick.vz[idx];
+        mw = kick.mark[idx >> 5];
+    }
     if (active) {
         const int me = ((p * PZ + lz + HALO) * PY + ly + HALO) * PX + lx + HALO;
         const Q4<Real> ui = tile[me];
@@ -247,12 +267,24 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
                 ep += in ? v : (Real)0;
             }
         }
-        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
         const bool vac = ui.x > (Real)VACANT_TEST;
         if (vac) ax = ay = az = 0;
         fx[idx] = ax;
         fy[idx] = ay;
         fz[idx] = az;
+        if (kKick && !vac) {
+            const double hk = 0.5 * kick.scal[0] * kick.kf;
+            const double vx = v0x + hk * (double)ax;
+            const double vy = v0y + hk * (double)ay;
+            const double vz = v0z + hk * (double)az;
+            kick.vx[idx] = vx;
+            kick.vy[idx] = vy;
+            kick.vz[idx] = vz;
+            if (!((mw >> (idx & 31)) & 1u)) {
+                kvm = vx * vx + vy * vy + vz * vz;
+                kvs = kvm;
+            }
+        }
         if (kEnergy && !vac) {
             Real Fv;
             bool beyond = false;
@@ -261,22 +293,38 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
             e_pair = 0.5 * (double)ep;
         }
     }
-    if (kEnergy) {
-        e_emb = wave_sum(e_emb);
-        e_pair = wave_sum(e_pair);
+    if (kEnergy || kKick) {
+        if (kEnergy) {
+            e_emb = wave_sum(e_emb);
+            e_pair = wave_sum(e_pair);
+        }
+        if (kKick) {
+            for (int o = 32; o >= 1; o >>= 1) kvm = fmax(kvm, __shfl_xor(kvm, o, 64));
+            kvs = wave_sum(kvs);
+        }
         if (lane == 0) {
             red[0][w] = e_emb;
             red[1][w] = e_pair;
+            red[2][w] = kvm;
+            red[3][w] = kvs;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double s0 = 0.0, s1 = 0.0;
+            double s0 = 0.0, s1 = 0.0, m2 = 0.0, s3 = 0.0;
             for (int q = 0; q < TILE_THREADS / 64; ++q) {
                 s0 += red[0][q];
                 s1 += red[1][q];
+                m2 = fmax(m2, red[2][q]);
+                s3 += red[3][q];
             }
-            part[2 * tid] = s0;
-            part[2 * tid + 1] = s1;
+            if (kEnergy) {
+                part[2 * tid] = s0;
+                part[2 * tid + 1] = s1;
+            }
+            if (kKick) {
+                kick.part_kick[2 * tid] = m2;
+                kick.part_kick[2 * tid + 1] = s3;
+            }
         }
     }
 }
@@ -311,31 +359,35 @@ hipError_t launch_rho(misa_lattice *h) {
     return rho_impl<double>(h, h->st64, h->t64);
 }
 
-template <typename Real>
-static hipError_t force_impl(misa_lattice *h, bool energy, const StencilEntry<Real> *st, const DevTables<Real> &t) {
+template <typename Real, bool kEnergy, bool kKick>
+static void force_variant(misa_lattice *h, const StencilEntry<Real> *st, const Tables<Real> &T, const KickArgs &ka) {
     const Geom &g = h->g;
-    Tables<Real> T = tables_of(t);
-    if (energy)
-        hipLaunchKernelGGL((k_force_tile<Real, true>), dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux,
-                           h->S.uy, h->S.uz, (const Real *)h->S.fp, (const Real *)h->S.rho, (Real *)h->S.fx,
-                           (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, h->K_in, h->u_cut2, T, g, h->sc.part);
-    else
-        hipLaunchKernelGGL((k_force_tile<Real, false>), dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream,
-                           h->S.ux, h->S.uy, h->S.uz, (const Real *)h->S.fp, (const Real *)h->S.rho,
-                           (Real *)h->S.fx, (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, h->K_in, h->u_cut2, T, g,
-                           h->sc.part);
+    hipLaunchKernelGGL((k_force_tile<Real, kEnergy, kKick>), dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream,
+                       h->S.ux, h->S.uy, h->S.uz, (const Real *)h->S.fp, (const Real *)h->S.rho, (Real *)h->S.fx,
+                       (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, h->K_in, h->u_cut2, T, g, h->sc.part, ka);
+}
+
+template <typename Real>
+static hipError_t force_impl(misa_lattice *h, bool energy, bool kick, const StencilEntry<Real> *st,
+                             const DevTables<Real> &t) {
+    const Tables<Real> T = tables_of(t);
+    const KickArgs ka{h->S.vx, h->S.vy, h->S.vz, h->sc.mark, h->sc.scal, h->sc.part_kick, ACC_UNIT / h->mass};
+    if (energy && kick) force_variant<Real, true, true>(h, st, T, ka);
+    else if (energy) force_variant<Real, true, false>(h, st, T, ka);
+    else if (kick) force_variant<Real, false, true>(h, st, T, ka);
+    else force_variant<Real, false, false>(h, st, T, ka);
     return hipGetLastError();
 }
 
-bool fused_kick(const misa_lattice *h) { return lds_path(h) && !half_path(h); }
+// Every table form but the learned one and the half-stencil schedule kicks inside the force pass.
+bool fused_kick(const misa_lattice *h) { return !h->use_mlp && !half_path(h); }
 
 hipError_t launch_force(misa_lattice *h, bool energy, bool kick) {
     if (half_path(h)) return kick ? hipErrorInvalidValue : launch_force_half(h, energy);
     if (lds_path(h)) return launch_force_lds(h, energy, kick);
-    if (kick) return hipErrorInvalidValue;  // the generic kernels keep the separate final kick
-    if (h->use_mlp) return launch_force_mlp(h, energy);
-    if (h->precision == MISA_FP32) return force_impl<float>(h, energy, h->st32, h->t32);
-    return force_impl<double>(h, energy, h->st64, h->t64);
+    if (h->use_mlp) return kick ? hipErrorInvalidValue : launch_force_mlp(h, energy);
+    if (h->precision == MISA_FP32) return force_impl<float>(h, energy, kick, h->st32, h->t32);
+    return force_impl<double>(h, energy, kick, h->st64, h->t64);
 }
 
 // Final energy sums: per-tile partials and per-run-away terms, fixed order.
