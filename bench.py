@@ -98,8 +98,9 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None,
 
     tabs = w.potential_samples()
     t0 = time.time()
-    half = form == "fp32-half"  # the FP32 form with each pair evaluated once (coloured tiles)
-    lat = Lattice(cfg.n_cells, w.A_FE, w.RC, w.DELTA, w.MASS_FE, "fp32" if half else form)
+    # fp32-half / mlp-half: the form with each pair evaluated once (coloured tiles)
+    half = form in ("fp32-half", "mlp-half")
+    lat = Lattice(cfg.n_cells, w.A_FE, w.RC, w.DELTA, w.MASS_FE, {"fp32-half": "fp32", "mlp-half": "mlp"}.get(form, form))
     lat.set_tables(tabs)
     if half:
         lat.set_pair_schedule("half")
@@ -345,7 +346,7 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="replay each step from a captured HIP graph (no per-kernel breakdown then)")
     ap.add_argument("--forms", default=None,
-                    help="comma list of fp32,fp64,fp32-half,mlp; first is the headline value (fp32 or fp64)")
+                    help="comma list of fp32,fp64,fp32-half,mlp,mlp-half; first is the headline value (fp32 or fp64)")
     ap.add_argument("--mlp-steps", type=int, default=5, help="timed steps of the learned form (it is slower)")
     ap.add_argument("--error-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -395,7 +396,7 @@ def main():
     cfg = w.CONFIGS[args.workload]
     steps = args.steps if args.steps is not None else cfg.steps
     forms = (args.forms or (cfg.precision + "," + ("fp64" if cfg.precision == "fp32" else "fp32")
-                            + ",fp32-half,mlp")).split(",")
+                            + ",fp32-half,mlp,mlp-half")).split(",")
     if forms[0] not in ("fp32", "fp64"):
         raise SystemExit("the first form is the headline value: fp32 or fp64")
     torch.cuda.set_device(0)
@@ -404,9 +405,12 @@ def main():
     _log(f"[bench] {cfg.name}: {x.shape[0]} atoms generated in {time.time() - t0:.1f} s; recoils {rec}")
 
     results = {}
+    trained = None
     for form in forms:
-        if form == "mlp":
-            nets, info = train_learned_form()
+        if form in ("mlp", "mlp-half"):
+            if trained is None:
+                trained = train_learned_form()
+            nets, info = trained
             k = min(steps, args.mlp_steps)
             results[form] = run_form(form, x, v, box, cfg, k, min(args.warmup, 2), args.error_sample, nets=nets)
             results[form]["training"] = info

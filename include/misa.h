@@ -240,8 +240,10 @@ int64_t misa_debug_export(misa_lattice *h, int what, int64_t *host_out, int64_t 
  * per axis and run one colour at a time, and inside a tile the partner writes
  * run in phases that no two waves share, so the result is deterministic.  It
  * needs every axis to be a multiple of 16 cells (MISA_EINVAL otherwise, or for
- * a handle that is not MISA_FP32).  Forces agree with the gather schedule to
- * float32 rounding, not bit for bit.  Batched replicas always gather. */
+ * a MISA_FP64 handle).  It serves the float32 table form and the learned form
+ * (MISA_MLP: each owned pair goes through the networks once instead of twice).
+ * Forces agree with the gather schedule to float32 rounding, not bit for bit.
+ * Batched replicas always gather. */
 #define MISA_PAIRS_GATHER 0
 #define MISA_PAIRS_HALF 1
 int misa_set_pair_schedule(misa_lattice *h, int schedule);

@@ -884,8 +884,8 @@ int misa_set_pair_schedule(misa_lattice *h, int schedule) {
     if (schedule != MISA_PAIRS_GATHER && schedule != MISA_PAIRS_HALF)
         return fail(h, MISA_EINVAL, "schedule must be MISA_PAIRS_GATHER or MISA_PAIRS_HALF");
     if (schedule == MISA_PAIRS_HALF) {
-        if (h->precision != MISA_FP32 || h->use_mlp)
-            return fail(h, MISA_EINVAL, "the half-stencil schedule serves the MISA_FP32 table form only");
+        if (h->precision != MISA_FP32)
+            return fail(h, MISA_EINVAL, "the half-stencil schedule serves the float32 table and learned forms only");
         if (!h->half_fits)
             return fail(h, MISA_EINVAL, "the half-stencil schedule needs every axis a multiple of 16 cells");
     }

@@ -29,6 +29,8 @@
 // record at the cut-off) is that of the full-gather persistent kernels.
 #include "misa_internal.h"
 
+#include "mlp_wave.h"
+
 namespace misa {
 
 constexpr int HF_THREADS = TILE2_THREADS;                              // 1024: one lane per interior site
@@ -84,19 +86,20 @@ __device__ __forceinline__ int64_t hf_site(int e, int tx, int ty, int tz, const 
 // and the values the write-back adds to (NOUT arrays: rho, or F_x, F_y, F_z).
 // Same-colour footprints are disjoint and earlier colours have finished, so those
 // values cannot change during the launch and are fetched a tile ahead.
-template <int NOUT>
+template <int NOUT, int NT = HF_THREADS>
 struct HfRegs {
-    double x[HF_PER_LANE], y[HF_PER_LANE], z[HF_PER_LANE];
-    float w[HF_PER_LANE];
-    float old[NOUT][HF_PER_LANE];
+    static constexpr int PER = (HT_SITES + NT - 1) / NT;  // footprint sites per lane
+    double x[PER], y[PER], z[PER];
+    float w[PER];
+    float old[NOUT > 0 ? NOUT : 1][PER];
 };
 
-template <int NOUT>
-__device__ __forceinline__ void hf_fetch(HfRegs<NOUT> &R, const State &S, float *const out[NOUT], bool with_fp,
+template <int NOUT, int NT = HF_THREADS>
+__device__ __forceinline__ void hf_fetch(HfRegs<NOUT, NT> &R, const State &S, float *const *out, bool with_fp,
                                          int tx, int ty, int tz, const Geom &g) {
 #pragma unroll
-    for (int j = 0; j < HF_PER_LANE; ++j) {
-        const int e = threadIdx.x + j * HF_THREADS;
+    for (int j = 0; j < HfRegs<NOUT, NT>::PER; ++j) {
+        const int e = threadIdx.x + j * NT;
         if (e < HT_SITES) {
             const int64_t idx = hf_site(e, tx, ty, tz, g);
             R.x[j] = S.ux[idx];
@@ -111,13 +114,13 @@ __device__ __forceinline__ void hf_fetch(HfRegs<NOUT> &R, const State &S, float 
 
 // Stores the staged displacements, zeroes the accumulators (NACC floats per
 // footprint site), returns max |u|^2 of the occupied sites this lane stored.
-template <int NACC, int NOUT>
+template <int NACC, int NOUT, int NT = HF_THREADS>
 __device__ __forceinline__ float hf_store(Q4<float> *__restrict__ tile, float *__restrict__ acc,
-                                          const HfRegs<NOUT> &R) {
+                                          const HfRegs<NOUT, NT> &R) {
     float m = 0.0f;
 #pragma unroll
-    for (int j = 0; j < HF_PER_LANE; ++j) {
-        const int e = threadIdx.x + j * HF_THREADS;
+    for (int j = 0; j < HfRegs<NOUT, NT>::PER; ++j) {
+        const int e = threadIdx.x + j * NT;
         if (e < HT_SITES) {
             Q4<float> q;
             q.x = (float)R.x[j];
@@ -431,6 +434,298 @@ __global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State
     }
 }
 
+// ---------------------------------------------------------------------------
+// The learned form on the half stencil: the f and phi networks (matrix cores, whole
+// waves) replace the table window, each owned pair is evaluated once; pairs outside
+// a network's range take the float32 tables from memory, as in the gather form.
+
+struct HalfNets {
+    MlpNet f, phi, emb;
+    const uint16_t *w2f, *w2p, *w2e;  // W2 of each network as bfloat16 bits
+};
+
+// 512 lanes per tile: wave w serves z plane w of both parities, one after the other
+// inside each phase (the 16 (plane, parity) write targets of a phase stay disjoint),
+// which leaves each lane the registers of two networks with their tangents.
+constexpr int HFM_THREADS = 512;
+
+__global__ __launch_bounds__(HFM_THREADS) void k_rho_half_mlp(ColourTiles ct, State S, Geom g,
+                                                              const StencilEntry<float> *__restrict__ hst,
+                                                              const int32_t *__restrict__ hmeta, HalfNets N,
+                                                              Tables<float> T, float rc2, float u_cut2) {
+    __shared__ Q4<float> tile[HT_SITES];
+    __shared__ float acc[HT_SITES];
+    __shared__ MlpLds Lf;
+    __shared__ unsigned umax_slot[2];
+    if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
+    fill_lds(Lf, N.f.p);
+    bf16x4_t Af[4];
+    load_a(Af, N.w2f);
+    const MlpNet nf = N.f;
+    const int lz = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lx = lane % T2X, ly = lane / T2X;
+    float *const out[1] = {(float *)S.rho};
+    int it = 0;
+    int item = ct.next(blockIdx.x, it, gridDim.x);
+    while (item >= 0) {
+        int tx, ty, tz;
+        ct.tile(item, tx, ty, tz);
+        __syncthreads();  // previous tile written back (and the network constants stored)
+        float m;
+        {
+            // fetched when needed: the networks cost ~100x the fetch latency per tile,
+            // and the registers a prefetch would hold go to the networks
+            HfRegs<0, HFM_THREADS> R;
+            hf_fetch<0, HFM_THREADS>(R, S, nullptr, false, tx, ty, tz, g);
+            m = hf_store<1, 0, HFM_THREADS>(tile, acc, R);
+        }
+        const bool near = hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2);
+        ++it;
+        const int nxt = ct.next(blockIdx.x, it, gridDim.x);
+        float ai[2] = {0.0f, 0.0f};
+        for (int q = 0; q < HALF_PHASES; ++q) {
+            for (int p = 0; p < 2; ++p) {
+                const StencilEntry<float> *sp = hst + p * KMAX;
+                const int32_t *meta = hmeta + p * HALF_META;
+                const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
+                const Q4<float> ui = tile[me];
+                const int k0 = __builtin_amdgcn_readfirstlane(meta[q]);
+                const int k1 = __builtin_amdgcn_readfirstlane(near ? k0 + meta[8 + q] : meta[q + 1]);
+                for (int k = k0; k < k1; ++k) {
+                    const StencilEntry<float> e = sp[k];
+                    const int j = me + e.lds;
+                    const Q4<float> uj = tile[j];
+                    const float dx = (uj.x - ui.x) + e.ox;
+                    const float dy = (uj.y - ui.y) + e.oy;
+                    const float dz = (uj.z - ui.z) + e.oz;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float r = __builtin_amdgcn_sqrtf(r2);
+                    float y, unused;
+                    mlp_wave<false>(Lf, Af, net_t(nf, r), y, unused);  // every lane: the whole wave runs it
+                    float v = 0.0f;
+                    if (r2 < rc2) {
+                        v = nf.y_shift + nf.y_scale * y;
+                        if (!mlp_serves(nf, r)) {
+                            int sg;
+                            float t;
+                            seg32(r, T.fm, sg, t);
+                            const Q4<float> c = T.f[sg];
+                            v = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                        }
+                    }
+                    ai[p] += v;
+                    acc[j] += v;  // no other wave writes this (plane, parity) in this phase
+                }
+            }
+            __syncthreads();
+        }
+        for (int p = 0; p < 2; ++p) acc[((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO] += ai[p];
+        __syncthreads();
+        // same-colour footprints are disjoint and earlier colours are done: a plain read-add-write
+        for (int e = threadIdx.x; e < HT_SITES; e += HFM_THREADS) {
+            const int64_t idx = hf_site(e, tx, ty, tz, g);
+            out[0][idx] += acc[e];
+        }
+        item = nxt;
+    }
+}
+
+// F'(rho) from the embedding network after the last colour, 64 sites per wave (the
+// whole wave evaluates; lanes past the end compute on a clamped site and store nothing).
+__global__ __launch_bounds__(256) void k_embed_half_mlp(State S, Geom g, HalfNets N, Tables<float> T,
+                                                        unsigned *range_viol) {
+    __shared__ MlpLds Le;
+    fill_lds(Le, N.emb.p);
+    bf16x4_t Ae[4];
+    load_a(Ae, N.w2e);
+    __syncthreads();
+    const MlpNet ne = N.emb;
+    float *rho = (float *)S.rho;
+    float *fp = (float *)S.fp;
+    unsigned nb = 0;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = wave0; base < g.nsites; base += stride) {
+        const int64_t s = base + (threadIdx.x & 63);
+        const bool valid = s < g.nsites;
+        const int64_t sc = valid ? s : g.nsites - 1;
+        const bool vac = S.atom[sc] == VACANT_ID;
+        const float r = vac ? 0.0f : rho[sc];
+        float ye, de;
+        mlp_wave<true>(Le, Ae, net_t(ne, r), ye, de);
+        float d = ne.y_scale * ne.s * de;
+        bool beyond = false;
+        if (!mlp_serves(ne, r)) {
+            float Fv;
+            d = emb_tab(r, T, Fv, beyond);
+        }
+        if (vac) d = 0.0f;
+        if (valid) {
+            if (vac) rho[s] = 0.0f;
+            fp[s] = d;
+            nb += beyond ? 1u : 0u;
+        }
+    }
+    if (nb) atomicAdd(range_viol, nb);
+}
+
+// F_i += s d, F_j -= s d for every owned pair with s from the f and phi networks;
+// with kEnergy the per-tile sums of F(rho_i) (embedding network) and phi.
+template <bool kEnergy>
+__global__ __launch_bounds__(HFM_THREADS) void k_force_half_mlp(ColourTiles ct, State S, Geom g,
+                                                                const StencilEntry<float> *__restrict__ hst,
+                                                                const int32_t *__restrict__ hmeta, HalfNets N,
+                                                                Tables<float> T, float rc2, float u_cut2,
+                                                                double *__restrict__ part) {
+    __shared__ Q4<float> tile[HT_SITES];
+    __shared__ float4 acc[HT_SITES];
+    __shared__ MlpLds Lf, Lp, Le;
+    __shared__ unsigned umax_slot[2];
+    __shared__ double red[2][HFM_THREADS / 64];
+    if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
+    fill_lds(Lf, N.f.p);
+    fill_lds(Lp, N.phi.p);
+    if (kEnergy) fill_lds(Le, N.emb.p);
+    bf16x4_t Af[4], Ap[4];
+    load_a(Af, N.w2f);
+    load_a(Ap, N.w2p);
+    const MlpNet nf = N.f, np = N.phi;
+    const float kf = nf.y_scale * nf.s, kp = np.y_scale * np.s;
+    const int lz = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lx = lane % T2X, ly = lane / T2X;
+    float *const out[3] = {(float *)S.fx, (float *)S.fy, (float *)S.fz};
+    int it = 0;
+    int item = ct.next(blockIdx.x, it, gridDim.x);
+    while (item >= 0) {
+        int tx, ty, tz;
+        const int tid = ct.tile(item, tx, ty, tz);
+        __syncthreads();
+        float m;
+        {
+            HfRegs<0, HFM_THREADS> R;  // fetched when needed, as in the rho pass
+            hf_fetch<0, HFM_THREADS>(R, S, nullptr, true, tx, ty, tz, g);
+            m = hf_store<4, 0, HFM_THREADS>(tile, (float *)acc, R);
+        }
+        const bool near = hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2);
+        ++it;
+        const int nxt = ct.next(blockIdx.x, it, gridDim.x);
+        // the two parities one after the other: all phases of parity 0, its own sums,
+        // then parity 1 (a phase's (plane, parity) write targets are disjoint either way)
+        float epp[2] = {0.0f, 0.0f};
+#pragma unroll 1
+        for (int p = 0; p < 2; ++p) {
+            const StencilEntry<float> *sp = hst + p * KMAX;
+            const int32_t *meta = hmeta + p * HALF_META;
+            const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
+            const Q4<float> ui = tile[me];
+            float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
+            for (int q = 0; q < HALF_PHASES; ++q) {
+                const int k0 = __builtin_amdgcn_readfirstlane(meta[q]);
+                const int k1 = __builtin_amdgcn_readfirstlane(near ? k0 + meta[8 + q] : meta[q + 1]);
+                for (int k = k0; k < k1; ++k) {
+                    const StencilEntry<float> e = sp[k];
+                    const int j = me + e.lds;
+                    const Q4<float> uj = tile[j];
+                    const float dx = (uj.x - ui.x) + e.ox;
+                    const float dy = (uj.y - ui.y) + e.oy;
+                    const float dz = (uj.z - ui.z) + e.oz;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float rinv = __builtin_amdgcn_rsqf(r2);
+                    const float r = r2 * rinv;
+                    float yf, df, yp, dp;
+                    mlp_wave<true>(Lf, Af, net_t(nf, r), yf, df);  // every lane: the whole wave runs them
+                    mlp_wave<true>(Lp, Ap, net_t(np, r), yp, dp);
+                    float px = 0.0f, py = 0.0f, pz = 0.0f;
+                    if (r2 < rc2) {
+                        float dfr = kf * df, dph = kp * dp, ph = np.y_shift + np.y_scale * yp;
+                        if (!mlp_serves(nf, r) || !mlp_serves(np, r)) {
+                            int sg;
+                            float t;
+                            seg32(r, T.fm, sg, t);
+                            const Q4<float> a = T.force[2 * sg], b = T.force[2 * sg + 1];
+                            if (!mlp_serves(nf, r)) dfr = (a.z * t + a.y) * t + a.x;
+                            if (!mlp_serves(np, r)) {
+                                dph = (b.y * t + b.x) * t + a.w;
+                                const Q4<float> c = T.phi[sg];
+                                ph = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                            }
+                        }
+                        const float sc = ((ui.w + uj.w) * dfr + dph) * rinv;
+                        px = sc * dx;
+                        py = sc * dy;
+                        pz = sc * dz;
+                        if (kEnergy) ep += ph;
+                    }
+                    ax += px;
+                    ay += py;
+                    az += pz;
+                    float4 aj = acc[j];  // no other wave writes this (plane, parity) in this phase
+                    aj.x -= px;
+                    aj.y -= py;
+                    aj.z -= pz;
+                    acc[j] = aj;
+                }
+                __syncthreads();
+            }
+            float4 am = acc[me];
+            am.x += ax;
+            am.y += ay;
+            am.z += az;
+            acc[me] = am;
+            epp[p] = ep;
+            __syncthreads();  // before the other parity's partner writes reach these sites
+        }
+        if (kEnergy) {
+            bf16x4_t Ae[4];
+            load_a(Ae, N.w2e);
+            double e_emb = 0.0, e_pair = 0.0;
+            for (int p = 0; p < 2; ++p) {
+                const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
+                const bool vac = tile[me].x > (float)VACANT_TEST;
+                const int gx = tx * T2X + lx, gy = ty * T2Y + ly, gz = tz * T2Z + lz;
+                const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+                const float rr = vac ? 0.0f : ((const float *)S.rho)[idx];
+                float ye, unused;
+                mlp_wave<false>(Le, Ae, net_t(N.emb, rr), ye, unused);
+                float Fv = N.emb.y_shift + N.emb.y_scale * ye;
+                if (!mlp_serves(N.emb, rr)) {
+                    bool beyond = false;
+                    emb_tab(rr, T, Fv, beyond);
+                }
+                e_emb += vac ? 0.0 : (double)Fv;
+                e_pair += vac ? 0.0 : (double)epp[p];
+            }
+            for (int o = 32; o >= 1; o >>= 1) {
+                e_emb += __shfl_xor(e_emb, o, 64);
+                e_pair += __shfl_xor(e_pair, o, 64);
+            }
+            if (lane == 0) {
+                red[0][lz] = e_emb;
+                red[1][lz] = e_pair;
+            }
+        }
+        __syncthreads();
+        if (kEnergy && threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int w = 0; w < HFM_THREADS / 64; ++w) {
+                s0 += red[0][w];
+                s1 += red[1][w];
+            }
+            part[2 * tid] = s0;
+            part[2 * tid + 1] = s1;
+        }
+        // same-colour footprints are disjoint and earlier colours are done: a plain read-add-write
+        for (int e = threadIdx.x; e < HT_SITES; e += HFM_THREADS) {
+            const int64_t idx = hf_site(e, tx, ty, tz, g);
+            const float4 a = acc[e];
+            out[0][idx] += a.x;
+            out[1][idx] += a.y;
+            out[2][idx] += a.z;
+        }
+        item = nxt;
+    }
+}
+
 __global__ void k_zero_f32(float *__restrict__ a, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         a[i] = 0.0f;
@@ -438,6 +733,10 @@ __global__ void k_zero_f32(float *__restrict__ a, int64_t n) {
 
 bool half_path(const misa_lattice *h) {
     return h->pair_schedule == MISA_PAIRS_HALF && lds_path(h) && h->lds32h.usable && h->half_fits;
+}
+
+bool half_mlp_path(const misa_lattice *h) {
+    return h->pair_schedule == MISA_PAIRS_HALF && h->use_mlp && h->half_fits && h->persistent_grid > 0;
 }
 
 static ColourTiles colour_tiles(const misa_lattice *h, int c) {
@@ -485,6 +784,50 @@ hipError_t launch_rho_half(misa_lattice *h) {
     hipLaunchKernelGGL(k_embed_half, dim3(b > 0 ? b : 1), dim3(256), 0, h->stream, h->S, h->g, half_tables(h),
                        &h->sc.cnt->range_viol);
     return hipGetLastError();
+}
+
+static HalfNets half_nets(const misa_lattice *h) {
+    HalfNets N;
+    N.f = h->mlp.net[0];
+    N.phi = h->mlp.net[1];
+    N.emb = h->mlp.net[2];
+    N.w2f = h->mlp.w2b[0];
+    N.w2p = h->mlp.w2b[1];
+    N.w2e = h->mlp.w2b[2];
+    return N;
+}
+
+hipError_t launch_rho_half_mlp(misa_lattice *h) {
+    hipError_t e = zero_f32(h, h->S.rho);
+    if (e != hipSuccess) return e;
+    const HalfNets N = half_nets(h);
+    for (int c = 0; c < 8; ++c) {
+        const ColourTiles ct = colour_tiles(h, c);
+        const int grid = std::min(h->persistent_grid, ct.nitems_pad);
+        hipLaunchKernelGGL(k_rho_half_mlp, dim3(grid), dim3(HFM_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st,
+                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int64_t b = std::min<int64_t>((h->g.nsites + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_embed_half_mlp, dim3(b > 0 ? b : 1), dim3(256), 0, h->stream, h->S, h->g, N,
+                       half_tables(h), &h->sc.cnt->range_viol);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_half_mlp(misa_lattice *h, bool energy) {
+    hipError_t e;
+    for (void *a : {h->S.fx, h->S.fy, h->S.fz})
+        if ((e = zero_f32(h, a)) != hipSuccess) return e;
+    const HalfNets N = half_nets(h);
+    auto kern = energy ? k_force_half_mlp<true> : k_force_half_mlp<false>;
+    for (int c = 0; c < 8; ++c) {
+        const ColourTiles ct = colour_tiles(h, c);
+        const int grid = std::min(h->persistent_grid, ct.nitems_pad);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(HFM_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st,
+                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2, h->sc.part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_force_half(misa_lattice *h, bool energy) {

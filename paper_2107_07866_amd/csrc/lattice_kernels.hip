@@ -352,7 +352,7 @@ static hipError_t rho_impl(misa_lattice *h, const StencilEntry<Real> *st, const 
 }
 
 hipError_t launch_rho(misa_lattice *h) {
-    if (h->use_mlp) return launch_rho_mlp(h);
+    if (h->use_mlp) return half_mlp_path(h) ? launch_rho_half_mlp(h) : launch_rho_mlp(h);
     if (half_path(h)) return launch_rho_half(h);
     if (lds_path(h)) return launch_rho_lds(h);
     if (h->precision == MISA_FP32) return rho_impl<float>(h, h->st32, h->t32);
@@ -385,7 +385,10 @@ bool fused_kick(const misa_lattice *h) { return !h->use_mlp && !half_path(h); }
 hipError_t launch_force(misa_lattice *h, bool energy, bool kick) {
     if (half_path(h)) return kick ? hipErrorInvalidValue : launch_force_half(h, energy);
     if (lds_path(h)) return launch_force_lds(h, energy, kick);
-    if (h->use_mlp) return kick ? hipErrorInvalidValue : launch_force_mlp(h, energy);
+    if (h->use_mlp) {
+        if (kick) return hipErrorInvalidValue;  // the learned form keeps the separate final kick
+        return half_mlp_path(h) ? launch_force_half_mlp(h, energy) : launch_force_mlp(h, energy);
+    }
     if (h->precision == MISA_FP32) return force_impl<float>(h, energy, kick, h->st32, h->t32);
     return force_impl<double>(h, energy, kick, h->st64, h->t64);
 }
@@ -448,7 +451,8 @@ hipError_t launchb_energy_reduce(hipStream_t st, const BoxRef *boxes, int nbox) 
 }
 
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev) {
-    const int nparts = lds_path(h) ? h->g.ntiles2 : h->g.ntiles;  // per-tile partials of the force pass used
+    // per-tile partials of the force pass used (8 x 8 x 8 tiles or the generic tiles)
+    const int nparts = lds_path(h) || half_mlp_path(h) ? h->g.ntiles2 : h->g.ntiles;
     hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, h->stream, h->sc.part, nparts, h->S.r_e,
                        h->sc.cnt, h->sc.scal, energies_dev);
     return hipGetLastError();

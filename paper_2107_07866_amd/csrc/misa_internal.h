@@ -355,6 +355,9 @@ bool fused_kick(const misa_lattice *h);               // the step fuses the fina
 bool half_path(const misa_lattice *h);                // half-stencil passes serve this handle
 hipError_t launch_rho_half(misa_lattice *h);            // zero, 8 colours, F'(rho)
 hipError_t launch_force_half(misa_lattice *h, bool energy);
+bool half_mlp_path(const misa_lattice *h);            // learned form on the half-stencil passes
+hipError_t launch_rho_half_mlp(misa_lattice *h);        // zero, 8 colours, F'(rho) from the embedding network
+hipError_t launch_force_half_mlp(misa_lattice *h, bool energy);
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev);
 hipError_t launch_rho_mlp(misa_lattice *h);             // learned form: rho pass with the networks
 hipError_t launch_force_mlp(misa_lattice *h, bool energy);

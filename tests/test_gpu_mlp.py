@@ -229,6 +229,66 @@ def test_mlp_form_forces_match_oracle(M, trainer, torch_cuda, orc):
         lat.close()
 
 
+def test_mlp_form_half_schedule(M, trainer, torch_cuda, orc):
+    """The learned form on the half-stencil schedule (each owned pair through the
+    networks once, 8 colours of tiles): forces, densities and energy against the
+    gather schedule (float32 rounding apart) and the oracle's MLP mode, on a thermal
+    box with vacancies (no run-away atoms: their pairs take the tables); then 10
+    steps of both schedules."""
+    torch = torch_cuda
+    lat64 = _lattice(6, "fp64")
+    nets, _, _ = _quick_fit(M, torch, trainer, lat64, iters=8000, seed=33)
+    lat64.close()
+    pot = orc.Potential(orc.MLP, tables=TABLES, mlp={ORC_KEYS[fn]: as_tuple(nets[fn]) for fn in FNS})
+    n = (16, 16, 32)
+    x, v, _ = w.thermal_state(n, seed=5)
+    keep = np.ones(len(x), bool)
+    keep[[7, 900, 4000]] = False
+    x, v = x[keep], v[keep]
+    box = tuple(k * A for k in n)
+    out = {}
+    for sched in ("gather", "half"):
+        _say(f"mlp form box {n}, {sched} schedule")
+        lat = _lattice(n, "mlp")
+        lat.set_mlp(nets)
+        lat.set_pair_schedule(sched)
+        lat.set_state(x, v)
+        e = lat.compute(energies=True)
+        torch.cuda.synchronize()
+        out[sched] = (lat.forces(), lat.rho(), lat.fprime(), float(e.cpu().numpy().sum()))
+        lat.close()
+    ref = orc.eam(pot, x, box, cells=True)
+    scale = float(np.sqrt(np.mean(ref["F"] ** 2)))
+    F, rho, fp, et = out["half"]
+    ferr = np.abs(F - ref["F"]).max() / scale
+    rerr = np.abs(rho - ref["rho"]).max() / np.abs(ref["rho"]).max()
+    eerr = abs(et - (ref["e_emb"] + ref["e_pair"])) / len(x)
+    gf = np.abs(F - out["gather"][0]).max() / scale
+    gr = np.abs(rho - out["gather"][1]).max() / np.abs(ref["rho"]).max()
+    gp = np.abs(fp - out["gather"][2]).max() / np.abs(out["gather"][2]).max()
+    ge = abs(et - out["gather"][3]) / len(x)
+    _say(f"  half vs oracle: force {ferr:.2e} rho {rerr:.2e} energy/atom {eerr:.2e} eV; "
+         f"vs gather: force {gf:.2e} rho {gr:.2e} F' {gp:.2e} energy/atom {ge:.2e}")
+    assert ferr <= 2e-3 and rerr <= 1e-4 and eerr <= 1e-4
+    assert gf <= 1e-4 and gr <= 1e-6 and gp <= 1e-5 and ge <= 1e-6
+    assert np.max(np.abs(F.sum(axis=0))) <= 1e-5 * np.abs(F).sum()  # pair terms cancel in pairs
+    traj = {}
+    for sched in ("gather", "half"):
+        lat = _lattice(n, "mlp")
+        lat.set_mlp(nets)
+        lat.set_pair_schedule(sched)
+        lat.set_state(x, v)
+        st = lat.step(10, 1.0, 0.05)
+        traj[sched] = (lat.get_state()[0], st)
+        lat.close()
+    L = np.asarray(box)
+    d = traj["half"][0] - traj["gather"][0]
+    d -= L * np.rint(d / L)
+    _say(f"  10 steps: max |dx| half vs gather {np.max(np.abs(d)):.2e} A")
+    assert np.max(np.abs(d)) < 1e-5
+    assert abs(traj["half"][1]["dt"] - traj["gather"][1]["dt"]) < 1e-6 * traj["gather"][1]["dt"]
+
+
 def test_collect_matches_oracle(M, torch_cuda, orc):
     """Force-matching data: per sampled atom, the pair list and the reference force
     (the float64 table force; with no run-away atoms it is the atom's whole force)."""
