@@ -289,6 +289,39 @@ def test_mlp_form_half_schedule(M, trainer, torch_cuda, orc):
     assert abs(traj["half"][1]["dt"] - traj["gather"][1]["dt"]) < 1e-6 * traj["gather"][1]["dt"]
 
 
+def test_mlp_half_schedule_recoil(M, trainer, torch_cuda):
+    """A 1 keV recoil in the learned form on both schedules: the recoil leaves its slot
+    (its pairs then take the float64 tables of the run-away path, lattice pairs the
+    networks); trajectories, run-away counts and step lengths agree to float32
+    rounding over 30 adaptive steps."""
+    torch = torch_cuda
+    lat64 = _lattice(6, "fp64")
+    nets, _, _ = _quick_fit(M, torch, trainer, lat64, iters=4000, seed=35)
+    lat64.close()
+    n = (16, 16, 16)
+    x, v, box = w.thermal_state(n, seed=9)
+    w.add_recoils(x, v, box, 1, 1000.0, True, seed=9)
+    out = {}
+    for sched in ("gather", "half"):
+        lat = _lattice(n, "mlp")
+        lat.set_mlp(nets)
+        lat.set_pair_schedule(sched)
+        lat.set_state(x, v)
+        st = lat.step(30, 1.0, 0.05)
+        out[sched] = (lat.get_state()[0], st, lat.slots())
+        lat.close()
+    L = np.asarray(box)
+    d = out["half"][0] - out["gather"][0]
+    d -= L * np.rint(d / L)
+    _say(f"mlp recoil, 30 steps: run-aways {out['half'][1]['n_runaway']} / {out['gather'][1]['n_runaway']}, "
+         f"max |dx| half vs gather {np.max(np.abs(d)):.2e} A")
+    assert out["half"][1]["n_runaway"] >= 1
+    assert out["half"][1]["n_runaway"] == out["gather"][1]["n_runaway"]
+    assert np.array_equal(out["half"][2], out["gather"][2])
+    assert np.max(np.abs(d)) < 1e-5
+    assert abs(out["half"][1]["dt"] - out["gather"][1]["dt"]) < 1e-6 * out["gather"][1]["dt"]
+
+
 def test_collect_matches_oracle(M, torch_cuda, orc):
     """Force-matching data: per sampled atom, the pair list and the reference force
     (the float64 table force; with no run-away atoms it is the atom's whole force)."""
