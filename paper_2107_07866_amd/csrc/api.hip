@@ -566,6 +566,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
                                                    (float)((o.dZ + 0.5 * pn - 0.5 * p) * d->a)};
             if (o.d2 < d->rc * d->rc) ++m[8 + fw[i].first];
         }
+        h->half_entries = std::max(h->half_entries, (int)m[HALF_PHASES]);
     }
 
     // scratch
@@ -659,7 +660,8 @@ int misa_destroy_lattice(misa_lattice *h) {
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
                     h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,
                     h->sc.mark_blk, h->sc.mark_off, h->sc.affected, h->sc.aff_v2, h->sc.part_kick, h->staging,
-                    h->mlp.p[0], h->mlp.p[1], h->mlp.p[2], h->mlp.w2b[0], h->mlp.w2b[1], h->mlp.w2b[2]};
+                    h->mlp.p[0], h->mlp.p[1], h->mlp.p[2], h->mlp.w2b[0], h->mlp.w2b[1], h->mlp.w2b[2],
+                    h->pairbuf};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : h->timed) h->event_pool.push_back({t.start, t.stop});
@@ -888,6 +890,16 @@ int misa_set_pair_schedule(misa_lattice *h, int schedule) {
             return fail(h, MISA_EINVAL, "the half-stencil schedule serves the float32 table and learned forms only");
         if (!h->half_fits)
             return fail(h, MISA_EINVAL, "the half-stencil schedule needs every axis a multiple of 16 cells");
+    }
+    if (schedule == MISA_PAIRS_HALF && h->use_mlp && !h->pairbuf) {
+        // f'(r) of every owned pair, written by the rho pass and read by the force pass
+        const hipError_t e =
+            hipMalloc((void **)&h->pairbuf, sizeof(float) * (size_t)h->half_entries * (size_t)h->g.nsites);
+        if (e != hipSuccess) {
+            h->pairbuf = nullptr;
+            return fail(h, MISA_ENOMEM, std::string("pair buffer of the half-stencil learned form: ") +
+                                            hipGetErrorString(e));
+        }
     }
     if (schedule != h->pair_schedule) {
         h->rho_valid = h->force_valid = false;

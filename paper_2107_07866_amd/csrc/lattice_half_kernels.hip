@@ -449,10 +449,14 @@ struct HalfNets {
 // which leaves each lane the registers of two networks with their tangents.
 constexpr int HFM_THREADS = 512;
 
+// The rho pass evaluates the f network with its tangent and keeps f'(r) of every owned
+// pair in dfbuf (entry k of the site with storage index i at k nsites + i), so that the
+// force pass only runs the phi network.
 __global__ __launch_bounds__(HFM_THREADS) void k_rho_half_mlp(ColourTiles ct, State S, Geom g,
                                                               const StencilEntry<float> *__restrict__ hst,
                                                               const int32_t *__restrict__ hmeta, HalfNets N,
-                                                              Tables<float> T, float rc2, float u_cut2) {
+                                                              Tables<float> T, float rc2, float u_cut2,
+                                                              float *__restrict__ dfbuf) {
     __shared__ Q4<float> tile[HT_SITES];
     __shared__ float acc[HT_SITES];
     __shared__ MlpLds Lf;
@@ -483,11 +487,14 @@ __global__ __launch_bounds__(HFM_THREADS) void k_rho_half_mlp(ColourTiles ct, St
         ++it;
         const int nxt = ct.next(blockIdx.x, it, gridDim.x);
         float ai[2] = {0.0f, 0.0f};
+        const float kfd = nf.y_scale * nf.s;
+        const int64_t cell = ((int64_t)(tz * T2Z + lz) * g.ny + (ty * T2Y + ly)) * g.nx + (tx * T2X + lx);
         for (int q = 0; q < HALF_PHASES; ++q) {
             for (int p = 0; p < 2; ++p) {
                 const StencilEntry<float> *sp = hst + p * KMAX;
                 const int32_t *meta = hmeta + p * HALF_META;
                 const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
+                const int64_t idx = (int64_t)p * g.ncell + cell;
                 const Q4<float> ui = tile[me];
                 const int k0 = __builtin_amdgcn_readfirstlane(meta[q]);
                 const int k1 = __builtin_amdgcn_readfirstlane(near ? k0 + meta[8 + q] : meta[q + 1]);
@@ -500,19 +507,23 @@ __global__ __launch_bounds__(HFM_THREADS) void k_rho_half_mlp(ColourTiles ct, St
                     const float dz = (uj.z - ui.z) + e.oz;
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     const float r = __builtin_amdgcn_sqrtf(r2);
-                    float y, unused;
-                    mlp_wave<false>(Lf, Af, net_t(nf, r), y, unused);  // every lane: the whole wave runs it
-                    float v = 0.0f;
+                    float y, dyt;
+                    mlp_wave<true>(Lf, Af, net_t(nf, r), y, dyt);  // every lane: the whole wave runs it
+                    float v = 0.0f, dfr = 0.0f;
                     if (r2 < rc2) {
                         v = nf.y_shift + nf.y_scale * y;
+                        dfr = kfd * dyt;
                         if (!mlp_serves(nf, r)) {
                             int sg;
                             float t;
                             seg32(r, T.fm, sg, t);
                             const Q4<float> c = T.f[sg];
                             v = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                            const Q4<float> a = T.force[2 * sg];
+                            dfr = (a.z * t + a.y) * t + a.x;
                         }
                     }
+                    dfbuf[(int64_t)k * g.nsites + idx] = dfr;
                     ai[p] += v;
                     acc[j] += v;  // no other wave writes this (plane, parity) in this phase
                 }
@@ -576,21 +587,20 @@ __global__ __launch_bounds__(HFM_THREADS) void k_force_half_mlp(ColourTiles ct, 
                                                                 const StencilEntry<float> *__restrict__ hst,
                                                                 const int32_t *__restrict__ hmeta, HalfNets N,
                                                                 Tables<float> T, float rc2, float u_cut2,
-                                                                double *__restrict__ part) {
+                                                                double *__restrict__ part,
+                                                                const float *__restrict__ dfbuf) {
     __shared__ Q4<float> tile[HT_SITES];
     __shared__ float4 acc[HT_SITES];
-    __shared__ MlpLds Lf, Lp, Le;
+    __shared__ MlpLds Lp, Le;
     __shared__ unsigned umax_slot[2];
     __shared__ double red[2][HFM_THREADS / 64];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
-    fill_lds(Lf, N.f.p);
     fill_lds(Lp, N.phi.p);
     if (kEnergy) fill_lds(Le, N.emb.p);
-    bf16x4_t Af[4], Ap[4];
-    load_a(Af, N.w2f);
+    bf16x4_t Ap[4];
     load_a(Ap, N.w2p);
-    const MlpNet nf = N.f, np = N.phi;
-    const float kf = nf.y_scale * nf.s, kp = np.y_scale * np.s;
+    const MlpNet np = N.phi;
+    const float kp = np.y_scale * np.s;
     const int lz = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lx = lane % T2X, ly = lane / T2X;
     float *const out[3] = {(float *)S.fx, (float *)S.fy, (float *)S.fz};
@@ -612,11 +622,13 @@ __global__ __launch_bounds__(HFM_THREADS) void k_force_half_mlp(ColourTiles ct, 
         // the two parities one after the other: all phases of parity 0, its own sums,
         // then parity 1 (a phase's (plane, parity) write targets are disjoint either way)
         float epp[2] = {0.0f, 0.0f};
+        const int64_t cell = ((int64_t)(tz * T2Z + lz) * g.ny + (ty * T2Y + ly)) * g.nx + (tx * T2X + lx);
 #pragma unroll 1
         for (int p = 0; p < 2; ++p) {
             const StencilEntry<float> *sp = hst + p * KMAX;
             const int32_t *meta = hmeta + p * HALF_META;
             const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
+            const int64_t idx = (int64_t)p * g.ncell + cell;
             const Q4<float> ui = tile[me];
             float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
             for (int q = 0; q < HALF_PHASES; ++q) {
@@ -632,23 +644,20 @@ __global__ __launch_bounds__(HFM_THREADS) void k_force_half_mlp(ColourTiles ct, 
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     const float rinv = __builtin_amdgcn_rsqf(r2);
                     const float r = r2 * rinv;
-                    float yf, df, yp, dp;
-                    mlp_wave<true>(Lf, Af, net_t(nf, r), yf, df);  // every lane: the whole wave runs them
-                    mlp_wave<true>(Lp, Ap, net_t(np, r), yp, dp);
+                    const float dfr = dfbuf[(int64_t)k * g.nsites + idx];  // f'(r) from the rho pass
+                    float yp, dp;
+                    mlp_wave<true>(Lp, Ap, net_t(np, r), yp, dp);  // every lane: the whole wave runs it
                     float px = 0.0f, py = 0.0f, pz = 0.0f;
                     if (r2 < rc2) {
-                        float dfr = kf * df, dph = kp * dp, ph = np.y_shift + np.y_scale * yp;
-                        if (!mlp_serves(nf, r) || !mlp_serves(np, r)) {
+                        float dph = kp * dp, ph = np.y_shift + np.y_scale * yp;
+                        if (!mlp_serves(np, r)) {
                             int sg;
                             float t;
                             seg32(r, T.fm, sg, t);
                             const Q4<float> a = T.force[2 * sg], b = T.force[2 * sg + 1];
-                            if (!mlp_serves(nf, r)) dfr = (a.z * t + a.y) * t + a.x;
-                            if (!mlp_serves(np, r)) {
-                                dph = (b.y * t + b.x) * t + a.w;
-                                const Q4<float> c = T.phi[sg];
-                                ph = ((c.w * t + c.z) * t + c.y) * t + c.x;
-                            }
+                            dph = (b.y * t + b.x) * t + a.w;
+                            const Q4<float> c = T.phi[sg];
+                            ph = ((c.w * t + c.z) * t + c.y) * t + c.x;
                         }
                         const float sc = ((ui.w + uj.w) * dfr + dph) * rinv;
                         px = sc * dx;
@@ -736,7 +745,8 @@ bool half_path(const misa_lattice *h) {
 }
 
 bool half_mlp_path(const misa_lattice *h) {
-    return h->pair_schedule == MISA_PAIRS_HALF && h->use_mlp && h->half_fits && h->persistent_grid > 0;
+    return h->pair_schedule == MISA_PAIRS_HALF && h->use_mlp && h->half_fits && h->persistent_grid > 0 &&
+           h->pairbuf != nullptr;
 }
 
 static ColourTiles colour_tiles(const misa_lattice *h, int c) {
@@ -805,7 +815,7 @@ hipError_t launch_rho_half_mlp(misa_lattice *h) {
         const ColourTiles ct = colour_tiles(h, c);
         const int grid = std::min(h->persistent_grid, ct.nitems_pad);
         hipLaunchKernelGGL(k_rho_half_mlp, dim3(grid), dim3(HFM_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st,
-                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2);
+                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2, h->pairbuf);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int64_t b = std::min<int64_t>((h->g.nsites + 255) / 256, 8192);
@@ -824,7 +834,7 @@ hipError_t launch_force_half_mlp(misa_lattice *h, bool energy) {
         const ColourTiles ct = colour_tiles(h, c);
         const int grid = std::min(h->persistent_grid, ct.nitems_pad);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(HFM_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st,
-                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2, h->sc.part);
+                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2, h->sc.part, h->pairbuf);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
