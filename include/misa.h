@@ -296,7 +296,11 @@ typedef struct {
 /* Attach the network for function fn to a MISA_MLP handle (copied; host memory).
  * MISA_EINVAL if a weight is not a bfloat16 value or the range is empty;
  * MISA_ESTATE on a handle of another pair precision.  The tables of
- * misa_set_potential_tables remain required (fallback outside the range). */
+ * misa_set_potential_tables remain required (fallback outside the range).
+ * The first call also allocates the handle's pair buffer, K x sites floats
+ * (16.8 GB for 320^3 cells): the rho pass keeps f'(r) of every pair there and
+ * the force pass reads it instead of evaluating the f network again
+ * (MISA_ENOMEM if that fails). */
 int misa_set_mlp(misa_lattice *h, int fn, const misa_mlp_net *net);
 
 /* The handle's float64 spline tables evaluated at n device-resident points

@@ -891,16 +891,6 @@ int misa_set_pair_schedule(misa_lattice *h, int schedule) {
         if (!h->half_fits)
             return fail(h, MISA_EINVAL, "the half-stencil schedule needs every axis a multiple of 16 cells");
     }
-    if (schedule == MISA_PAIRS_HALF && h->use_mlp && !h->pairbuf) {
-        // f'(r) of every owned pair, written by the rho pass and read by the force pass
-        const hipError_t e =
-            hipMalloc((void **)&h->pairbuf, sizeof(float) * (size_t)h->half_entries * (size_t)h->g.nsites);
-        if (e != hipSuccess) {
-            h->pairbuf = nullptr;
-            return fail(h, MISA_ENOMEM, std::string("pair buffer of the half-stencil learned form: ") +
-                                            hipGetErrorString(e));
-        }
-    }
     if (schedule != h->pair_schedule) {
         h->rho_valid = h->force_valid = false;
         drop_graph(h);

@@ -262,6 +262,13 @@ int misa_set_mlp(misa_lattice *h, int fn, const misa_mlp_net *net) {
     std::vector<uint16_t> w2(MLP_H * MLP_H);
     for (int j = 0; j < MLP_H * MLP_H; ++j) w2[j] = bf16_of(net->params[OFF_W2 + j]);
     MlpAttached &A = h->mlp;
+    if (!h->pairbuf) {  // f'(r) per pair, kept from the rho pass for the force pass (either schedule)
+        const hipError_t e = hipMalloc((void **)&h->pairbuf, sizeof(float) * (size_t)h->K * (size_t)h->g.nsites);
+        if (e != hipSuccess) {
+            h->pairbuf = nullptr;
+            return hfail(h, MISA_ENOMEM, std::string("pair buffer of the learned form: ") + hipGetErrorString(e));
+        }
+    }
     if (!A.p[fn]) HCHK(h, hipMalloc((void **)&A.p[fn], sizeof(float) * MLP_NP));
     if (!A.w2b[fn]) HCHK(h, hipMalloc((void **)&A.w2b[fn], sizeof(uint16_t) * MLP_H * MLP_H));
     HCHK(h, hipMemcpyAsync(A.p[fn], net->params, sizeof(float) * MLP_NP, hipMemcpyHostToDevice, h->stream));

@@ -301,8 +301,8 @@ struct misa_lattice {
     int32_t *hmeta = nullptr;                     // half-stencil phases (device [2][HALF_META])
     misa::HalfStencil half;
     int half_entries = 0;                         // owned entries of the larger half-stencil parity
-    float *pairbuf = nullptr;                     // learned form, half stencil: f'(r) of every owned pair,
-                                                  // [half_entries][nsites], from the rho pass to the force pass
+    float *pairbuf = nullptr;                     // learned form: f'(r) of every stencil candidate (gather) or
+                                                  // owned pair (half), [K][nsites], rho pass -> force pass
     misa::LdsTables lds32h;                       // smaller window for the half-stencil passes
     bool tables_set = false;
     misa::Scratch sc{};

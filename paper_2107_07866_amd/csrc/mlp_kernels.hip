@@ -56,14 +56,17 @@ struct MlpSet {
 
 // rho_i = sum_j f(r_ij) and F'(rho_i) with the networks.  Every lane of a wave runs
 // the pair loop (the matrix-core evaluation needs the whole wave); lanes outside the
-// box compute on wrapped data and store nothing.
+// box compute on wrapped data and store nothing.  The f network runs with its
+// tangent, and f'(r) of every candidate goes to dfbuf (candidate k of site i at
+// k nsites + i), so that the force pass only runs the phi network.
 __global__ __launch_bounds__(TILE_THREADS) void k_rho_mlp(const double *__restrict__ ux,
                                                           const double *__restrict__ uy,
                                                           const double *__restrict__ uz, float *__restrict__ rho,
                                                           float *__restrict__ fp,
                                                           const StencilEntry<float> *__restrict__ st, int K,
                                                           Tables<float> T, MlpSet M, Geom g,
-                                                          uint32_t *__restrict__ range_viol) {
+                                                          uint32_t *__restrict__ range_viol,
+                                                          float *__restrict__ dfbuf) {
     __shared__ Q4<float> tile[TILE_SITES];
     __shared__ MlpLds Lf, Le;
     const int tid = tile_of_block(blockIdx.x, g);
@@ -90,6 +93,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_mlp(const double *__restri
     const Q4<float> ui = tile[me];
     const float rc2 = (float)g.rc2;
     const StencilEntry<float> *sp = st + p * KMAX;
+    const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+    const float kfd = nf.y_scale * nf.s;
     float acc = 0.0f;
     for (int k = 0; k < K; ++k) {
         const StencilEntry<float> e = sp[k];
@@ -98,20 +103,26 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_mlp(const double *__restri
         const float dy = (uj.y - ui.y) + e.oy;
         const float dz = (uj.z - ui.z) + e.oz;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        const float r = __builtin_amdgcn_sqrtf(r2);
-        float y, unused;
-        mlp_wave<false>(Lf, Af, net_t(nf, r), y, unused);
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float r = r2 * rinv;  // as the force pass forms it, so both passes see the same r
+        float y, dyt;
+        mlp_wave<true>(Lf, Af, net_t(nf, r), y, dyt);
+        float dfr = 0.0f;
         if (r2 < rc2) {
             float v = nf.y_shift + nf.y_scale * y;
+            dfr = kfd * dyt;
             if (!mlp_serves(nf, r)) {
                 int s;
                 float t;
                 seg32(r, T.fm, s, t);
                 const Q4<float> c = T.f[s];
                 v = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                const Q4<float> a = T.force[2 * s];
+                dfr = (a.z * t + a.y) * t + a.x;
             }
             acc += v;
         }
+        if (active) dfbuf[(int64_t)k * g.nsites + idx] = dfr;
     }
     const bool vac = ui.x > (float)VACANT_TEST;
     if (vac) acc = 0.0f;
@@ -125,7 +136,6 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_mlp(const double *__restri
     }
     if (vac) fpv = 0.0f;
     if (active) {
-        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
         rho[idx] = acc;
         fp[idx] = fpv;
         if (beyond) atomicAdd(range_viol, 1u);
@@ -144,9 +154,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_mlp(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
     const float *__restrict__ fp, const float *__restrict__ rho, float *__restrict__ fx, float *__restrict__ fy,
     float *__restrict__ fz, const StencilEntry<float> *__restrict__ st, int K, Tables<float> T, MlpSet M, Geom g,
-    double *__restrict__ part) {
+    double *__restrict__ part, const float *__restrict__ dfbuf) {
     __shared__ Q4<float> tile[TILE_SITES];
-    __shared__ MlpLds Lf, Lp, Le;
+    __shared__ MlpLds Lp, Le;
     __shared__ double red[2][TILE_THREADS / 64];
     const int tid = tile_of_block(blockIdx.x, g);
     if (tid >= g.ntiles) return;
@@ -155,15 +165,13 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_mlp(
     const int ty = tyz % g.nty;
     const int tz = tyz / g.nty;
     load_tile_f(tile, ux, uy, uz, fp, g, tx * TX - HALO, ty * TY - HALO, tz * TZ - HALO);
-    fill_lds(Lf, M.net[0].p);
     fill_lds(Lp, M.net[1].p);
     if (kEnergy) fill_lds(Le, M.net[2].p);
-    bf16x4_t Af[4], Ap[4];
-    load_a(Af, M.w2b[0]);
+    bf16x4_t Ap[4];
     load_a(Ap, M.w2b[1]);
     __syncthreads();
 
-    const MlpNet nf = M.net[0], np = M.net[1];
+    const MlpNet np = M.net[1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(w / TZ);
     const int lz = w % TZ, lx = lane % TX, ly = lane / TX;
@@ -173,7 +181,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_mlp(
     const Q4<float> ui = tile[me];
     const float rc2 = (float)g.rc2;
     const StencilEntry<float> *sp = st + p * KMAX;
-    const float kf = nf.y_scale * nf.s, kp = np.y_scale * np.s;
+    const float kp = np.y_scale * np.s;
+    const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
     float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
     for (int k = 0; k < K; ++k) {
         const StencilEntry<float> e = sp[k];
@@ -184,22 +193,19 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_mlp(
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float rinv = __builtin_amdgcn_rsqf(r2);
         const float r = r2 * rinv;
-        float yf, df, yp, dp;
-        mlp_wave<true>(Lf, Af, net_t(nf, r), yf, df);
+        const float dfr = active ? dfbuf[(int64_t)k * g.nsites + idx] : 0.0f;  // f'(r) from the rho pass
+        float yp, dp;
         mlp_wave<true>(Lp, Ap, net_t(np, r), yp, dp);
         if (r2 < rc2) {
-            float dfr = kf * df, dph = kp * dp, ph = np.y_shift + np.y_scale * yp;
-            if (!mlp_serves(nf, r) || !mlp_serves(np, r)) {
+            float dph = kp * dp, ph = np.y_shift + np.y_scale * yp;
+            if (!mlp_serves(np, r)) {
                 int s;
                 float t;
                 seg32(r, T.fm, s, t);
                 const Q4<float> a = T.force[2 * s], b = T.force[2 * s + 1];
-                if (!mlp_serves(nf, r)) dfr = (a.z * t + a.y) * t + a.x;
-                if (!mlp_serves(np, r)) {
-                    dph = (b.y * t + b.x) * t + a.w;
-                    const Q4<float> c = T.phi[s];
-                    ph = ((c.w * t + c.z) * t + c.y) * t + c.x;
-                }
+                dph = (b.y * t + b.x) * t + a.w;
+                const Q4<float> c = T.phi[s];
+                ph = ((c.w * t + c.z) * t + c.y) * t + c.x;
             }
             const float sc = ((ui.w + uj.w) * dfr + dph) * rinv;
             ax += sc * dx;
@@ -209,7 +215,6 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_mlp(
         }
     }
     const bool vac = ui.x > (float)VACANT_TEST;
-    const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
     if (vac) ax = ay = az = 0.0f;
     if (active) {
         fx[idx] = ax;
@@ -270,19 +275,21 @@ static Tables<float> t32_tables(const misa_lattice *h) {
 }
 
 hipError_t launch_rho_mlp(misa_lattice *h) {
+    if (!h->pairbuf) return hipErrorInvalidValue;  // made by misa_set_mlp
     const Geom &g = h->g;
     hipLaunchKernelGGL(k_rho_mlp, dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
                        (float *)h->S.rho, (float *)h->S.fp, h->st32, h->K, t32_tables(h), mlp_set_of(h), g,
-                       &h->sc.cnt->range_viol);
+                       &h->sc.cnt->range_viol, h->pairbuf);
     return hipGetLastError();
 }
 
 hipError_t launch_force_mlp(misa_lattice *h, bool energy) {
+    if (!h->pairbuf) return hipErrorInvalidValue;
     const Geom &g = h->g;
     auto kern = energy ? k_force_mlp<true> : k_force_mlp<false>;
     hipLaunchKernelGGL(kern, dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
                        (const float *)h->S.fp, (const float *)h->S.rho, (float *)h->S.fx, (float *)h->S.fy,
-                       (float *)h->S.fz, h->st32, h->K, t32_tables(h), mlp_set_of(h), g, h->sc.part);
+                       (float *)h->S.fz, h->st32, h->K, t32_tables(h), mlp_set_of(h), g, h->sc.part, h->pairbuf);
     return hipGetLastError();
 }
 
