@@ -979,6 +979,8 @@ struct misa_batch {
     BoxRef *d_ref = nullptr;
     BoxPass *d_pass = nullptr;
     int2 *d_items = nullptr;
+    int32_t *d_off = nullptr;  // 2 (boxes + 1): offsets of the flattened run-away passes
+    bool flat = false;         // run-away passes over one list of all boxes (int32 item indices)
     int64_t cap_boxes = 0, cap_items = 0;
     std::vector<int32_t> shape;                  // tile shape of each box (index into TILE_SHAPES)
     StencilEntry<float> *d_st = nullptr;         // [N_TILE_SHAPES][2][KMAX]: stencil per tile shape
@@ -1033,12 +1035,23 @@ int batch_tables(misa_batch *b) {
     if (nb > b->cap_boxes) {
         (void)hipFree(b->d_ref);
         (void)hipFree(b->d_pass);
+        (void)hipFree(b->d_off);
         b->d_ref = nullptr;
         b->d_pass = nullptr;
+        b->d_off = nullptr;
         b->cap_boxes = 0;
         BCHK(b, hipMalloc((void **)&b->d_ref, sizeof(BoxRef) * nb));
         BCHK(b, hipMalloc((void **)&b->d_pass, sizeof(BoxPass) * nb));
+        BCHK(b, hipMalloc((void **)&b->d_off, sizeof(int32_t) * 2 * (nb + 1)));
         b->cap_boxes = nb;
+    }
+    {
+        int64_t run = 0, aff = 0;  // largest possible list lengths
+        for (misa_lattice *h : b->box) {
+            run += h->rcap;
+            aff += h->sc.affected_cap;
+        }
+        b->flat = flat_runaway_fits(nb) && run < INT32_MAX && aff < INT32_MAX;
     }
     if ((int64_t)b->items.size() > b->cap_items) {
         (void)hipFree(b->d_items);
@@ -1122,6 +1135,7 @@ int misa_batch_destroy(misa_batch *b) {
     (void)hipFree(b->d_ref);
     (void)hipFree(b->d_pass);
     (void)hipFree(b->d_items);
+    (void)hipFree(b->d_off);
     (void)hipFree(b->d_st);
     if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -1208,7 +1222,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
-            BCHK(b, launchb_runaway_rho(h0, b->d_ref, nb, gx_small, max_mark));
+            BCHK(b, launchb_runaway_rho(h0, b->d_ref, nb, gx_small, max_mark, b->flat ? b->d_off : nullptr));
         }
         {
             GroupTimer t(h0, MISA_TIMER_FORCE);
@@ -1216,7 +1230,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
-            BCHK(b, launchb_runaway_force(h0, b->d_ref, nb, gx_small, last));
+            BCHK(b, launchb_runaway_force(h0, b->d_ref, nb, gx_small, last, b->flat ? b->d_off : nullptr));
         }
         {
             GroupTimer t(h0, MISA_TIMER_OTHER);
@@ -1243,7 +1257,8 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         // the key: everything the captured launches bake in
         std::vector<uint64_t> key = {(uint64_t)nitems, (uint64_t)any_shape, (uint64_t)gx_sites, (uint64_t)max_mark,
                                      (uint64_t)(uintptr_t)b->d_ref, (uint64_t)(uintptr_t)b->d_pass,
-                                     (uint64_t)(uintptr_t)b->d_items};
+                                     (uint64_t)(uintptr_t)b->d_items, (uint64_t)(uintptr_t)b->d_off,
+                                     (uint64_t)b->flat};
         uint64_t bits;
         std::memcpy(&bits, &dt_max, 8);
         key.push_back(bits);

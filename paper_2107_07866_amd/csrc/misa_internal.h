@@ -382,8 +382,11 @@ hipError_t launchb_final_kick_runaway(hipStream_t st, const BoxRef *boxes, int n
 hipError_t launchb_dt_update(hipStream_t st, const BoxRef *boxes, int nbox, double mass, double dt_max, double dx_max);
 hipError_t launchb_rehash(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
 hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
-hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, int mark_blocks);
-hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, bool energy);
+bool flat_runaway_fits(int nbox);
+hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, int mark_blocks,
+                               int32_t *off);
+hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, bool energy,
+                                 const int32_t *off);
 hipError_t launchb_runaway_clear(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
 hipError_t launchb_energy_reduce(hipStream_t st, const BoxRef *boxes, int nbox);
 hipError_t launch_gather_field(misa_lattice *h, int field, double *out);

@@ -14,6 +14,11 @@
 //     scatter, atomics on floats or colouring are needed and results are
 //     deterministic run to run.
 // All arithmetic here is float64 regardless of the lattice pair precision.
+//
+// Multiply-adds are fused only within one source expression: the same item code
+// runs inlined into single-box and batched (flattened) kernels, and fusion across
+// statements would depend on the loop around it, so the two would round differently.
+#pragma clang fp contract(on)
 #include "misa_internal.h"
 
 namespace misa {
@@ -519,14 +524,10 @@ __device__ __forceinline__ bool affected_pair(const double xo[3], const int cj[3
 
 // One wave per run-away atom: rho from lattice sites in its window and from other
 // run-aways; marks every lattice atom it pairs with (they need the reaction term).
-__device__ __forceinline__ void runaway_rho_body(State S, Scratch sc, Geom g,
-                                                                              Tables<double> T) {
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
-    const int n = sc.cnt->n_run;
+__device__ __forceinline__ void runaway_rho_one(const State &S, const Scratch &sc, const Geom &g,
+                                                const Tables<double> &T, int r, int lane) {
     const int win = g.win, win3 = win * win * win;
-    for (int r = wave; r < n; r += nwaves) {
+    {
         const double x[3] = {S.r_x[r], S.r_y[r], S.r_z[r]};
         const int lo[3] = {window_lo(x[0] * g.inv_a, g.reach), window_lo(x[1] * g.inv_a, g.reach),
                            window_lo(x[2] * g.inv_a, g.reach)};
@@ -564,6 +565,14 @@ __device__ __forceinline__ void runaway_rho_body(State S, Scratch sc, Geom g,
     }
 }
 
+__device__ __forceinline__ void runaway_rho_body(State S, Scratch sc, Geom g, Tables<double> T) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
+    const int n = sc.cnt->n_run;
+    for (int r = wave; r < n; r += nwaves) runaway_rho_one(S, sc, g, T, r, lane);
+}
+
 __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(State S, Scratch sc, Geom g,
                                                                               Tables<double> T) {
     runaway_rho_body(S, sc, g, T);
@@ -577,14 +586,12 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kb_runaway_rho(c
 
 // Lattice atoms within rc of run-aways: add the run-away terms to rho, refresh F'.
 // emb: the embedding network of the learned form (an empty range on other handles).
+// q: index into the affected list; cell: this lane's place in its team of AFF_TEAM.
 template <typename Real>
-__device__ __forceinline__ void affected_rho_body(State S, Scratch sc, Geom g, Tables<double> T,
-                                                              Tables<Real> TL, MlpNet emb) {
-    int na = sc.cnt->n_affected;
-    na = na < sc.affected_cap ? na : (int)sc.affected_cap;
-    const int cell = threadIdx.x & (AFF_TEAM - 1);
-    const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
-    for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < na; q += nteams) {
+__device__ __forceinline__ void affected_rho_one(const State &S, const Scratch &sc, const Geom &g,
+                                                 const Tables<double> &T, const Tables<Real> &TL,
+                                                 const MlpNet &emb, int q, int cell) {
+    {
         const int64_t s = sc.affected[q];
         const int p = s >= g.ncell ? 1 : 0;
         const int64_t c = s - p * g.ncell;
@@ -620,6 +627,21 @@ __device__ __forceinline__ void affected_rho_body(State S, Scratch sc, Geom g, T
     }
 }
 
+__device__ __forceinline__ int affected_count(const Scratch &sc) {
+    const int na = sc.cnt->n_affected;
+    return na < sc.affected_cap ? na : (int)sc.affected_cap;
+}
+
+template <typename Real>
+__device__ __forceinline__ void affected_rho_body(State S, Scratch sc, Geom g, Tables<double> T,
+                                                  Tables<Real> TL, MlpNet emb) {
+    const int na = affected_count(sc);
+    const int cell = threadIdx.x & (AFF_TEAM - 1);
+    const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
+    for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < na; q += nteams)
+        affected_rho_one<Real>(S, sc, g, T, TL, emb, q, cell);
+}
+
 template <typename Real>
 __global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch sc, Geom g, Tables<double> T,
                                                               Tables<Real> TL, MlpNet emb) {
@@ -636,15 +658,11 @@ __global__ __launch_bounds__(AFF_THREADS) void kb_affected_rho(const BoxRef *__r
 // ---------------------------------------------------------------------------
 // forces
 
-__device__ __forceinline__ void runaway_force_body(State S, Scratch sc, Geom g,
-                                                                                Tables<double> T, int real_is_f32,
-                                                                                int energy) {
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
-    const int n = sc.cnt->n_run;
+__device__ __forceinline__ void runaway_force_one(const State &S, const Scratch &sc, const Geom &g,
+                                                  const Tables<double> &T, int real_is_f32, int energy, int r,
+                                                  int lane) {
     const int win = g.win, win3 = win * win * win;
-    for (int r = wave; r < n; r += nwaves) {
+    {
         const double x[3] = {S.r_x[r], S.r_y[r], S.r_z[r]};
         const double fpr = S.r_fp[r];
         const int lo[3] = {window_lo(x[0] * g.inv_a, g.reach), window_lo(x[1] * g.inv_a, g.reach),
@@ -698,6 +716,15 @@ __device__ __forceinline__ void runaway_force_body(State S, Scratch sc, Geom g,
     }
 }
 
+__device__ __forceinline__ void runaway_force_body(State S, Scratch sc, Geom g, Tables<double> T, int real_is_f32,
+                                                   int energy) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
+    const int n = sc.cnt->n_run;
+    for (int r = wave; r < n; r += nwaves) runaway_force_one(S, sc, g, T, real_is_f32, energy, r, lane);
+}
+
 __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(State S, Scratch sc, Geom g,
                                                                                 Tables<double> T, int real_is_f32,
                                                                                 int energy) {
@@ -713,14 +740,10 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kb_runaway_force
 // kick != 0: the force pass already applied the second half-kick with the lattice
 // part of F; add the run-away part's kick here and record |v|^2 for the step statistics.
 template <typename Real>
-__device__ __forceinline__ void affected_force_body(State S, Scratch sc, Geom g, Tables<double> T,
-                                                                int kick, double kf) {
-    int na = sc.cnt->n_affected;
-    na = na < sc.affected_cap ? na : (int)sc.affected_cap;
+__device__ __forceinline__ void affected_force_one(const State &S, const Scratch &sc, const Geom &g,
+                                                   const Tables<double> &T, int kick, double kf, int q, int cell) {
     const double hk = kick ? 0.5 * sc.scal[0] * kf : 0.0;
-    const int cell = threadIdx.x & (AFF_TEAM - 1);
-    const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
-    for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < na; q += nteams) {
+    {
         const int64_t s = sc.affected[q];
         const int p = s >= g.ncell ? 1 : 0;
         const int64_t c = s - p * g.ncell;
@@ -767,6 +790,16 @@ __device__ __forceinline__ void affected_force_body(State S, Scratch sc, Geom g,
 }
 
 template <typename Real>
+__device__ __forceinline__ void affected_force_body(State S, Scratch sc, Geom g, Tables<double> T, int kick,
+                                                    double kf) {
+    const int na = affected_count(sc);
+    const int cell = threadIdx.x & (AFF_TEAM - 1);
+    const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
+    for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < na; q += nteams)
+        affected_force_one<Real>(S, sc, g, T, kick, kf, q, cell);
+}
+
+template <typename Real>
 __global__ __launch_bounds__(AFF_THREADS) void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T,
                                                                 int kick, double kf) {
     affected_force_body<Real>(S, sc, g, T, kick, kf);
@@ -778,6 +811,123 @@ __global__ __launch_bounds__(AFF_THREADS) void kb_affected_force(const BoxRef *_
     affected_force_body<Real>(B.S, B.sc, B.g, T, kick, kf);
 }
 
+
+// ---------------------------------------------------------------------------
+// Run-away work of a batch as one list.  Run-aways gather in the few boxes whose
+// cascades melt them, so a fixed share of blocks per box would leave those boxes to a
+// handful of waves.  Instead item q of the list (a run-away, or an affected lattice
+// atom) is item q - off[b] of box b, off[b] <= q < off[b + 1], and every wave of the
+// grid takes items from the whole list.  Each item is computed exactly as in a
+// single-box pass, so results do not depend on how the list is dealt out.
+
+constexpr int FLAT_BLOCKS = 1024;
+constexpr int FLAT_MAX_BOXES = 8192;  // off[] staged in LDS: (FLAT_MAX_BOXES + 1) ints
+
+// off[0] = 0, off[b + 1] = off[b] + items of box b; which = 0: run-aways, 1: affected
+// lattice atoms (capped at the list's capacity, as the passes over it are).
+__global__ __launch_bounds__(1024) void kb_flat_offsets(const BoxRef *__restrict__ boxes, int nbox, int which,
+                                                        int32_t *__restrict__ off) {
+    __shared__ int sw[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) off[0] = 0;
+    int carry = 0;
+    for (int base = 0; base < nbox; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        int v = 0;
+        if (i < nbox) v = which == 0 ? boxes[i].sc.cnt->n_run : affected_count(boxes[i].sc);
+        int incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) sw[w] = incl;
+        __syncthreads();
+        int before = carry, total = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < w) before += sw[k];
+            total += sw[k];
+        }
+        if (i < nbox) off[i + 1] = before + incl;
+        carry += total;
+        __syncthreads();  // sw is rewritten by the next chunk
+    }
+}
+
+// Stages off[0 .. nbox] in LDS; returns the list length.
+__device__ __forceinline__ int stage_offsets(int *s_off, const int32_t *__restrict__ off, int nbox) {
+    for (int i = threadIdx.x; i <= nbox; i += blockDim.x) s_off[i] = off[i];
+    __syncthreads();
+    return s_off[nbox];
+}
+
+// The box b with off[b] <= q < off[b + 1] (0 <= q < off[nbox]; boxes with no items are
+// passed over because their two offsets are equal).
+__device__ __forceinline__ int flat_box(const int *s_off, int nbox, int q) {
+    int lo = 0, hi = nbox;  // off[lo] <= q < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[mid] <= q) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kf_runaway_rho(const BoxRef *__restrict__ boxes,
+                                                                               int nbox, const int32_t *off,
+                                                                               Tables<double> T) {
+    extern __shared__ int s_off[];
+    const int total = stage_offsets(s_off, off, nbox);
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
+    for (int q = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6); q < total; q += nwaves) {
+        const int b = __builtin_amdgcn_readfirstlane(flat_box(s_off, nbox, q));  // one item per wave
+        const BoxRef &B = boxes[b];
+        runaway_rho_one(B.S, B.sc, B.g, T, q - s_off[b], lane);
+    }
+}
+
+__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kf_runaway_force(const BoxRef *__restrict__ boxes,
+                                                                                 int nbox, const int32_t *off,
+                                                                                 Tables<double> T, int energy) {
+    extern __shared__ int s_off[];
+    const int total = stage_offsets(s_off, off, nbox);
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
+    for (int q = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6); q < total; q += nwaves) {
+        const int b = __builtin_amdgcn_readfirstlane(flat_box(s_off, nbox, q));
+        const BoxRef &B = boxes[b];
+        runaway_force_one(B.S, B.sc, B.g, T, 1, energy, q - s_off[b], lane);
+    }
+}
+
+// Affected atoms: one team of AFF_TEAM lanes per item, as in the single-box pass (the
+// two teams of a wave may serve different boxes).
+__global__ __launch_bounds__(AFF_THREADS) void kf_affected_rho(const BoxRef *__restrict__ boxes, int nbox,
+                                                               const int32_t *off, Tables<double> T,
+                                                               Tables<float> TL) {
+    extern __shared__ int s_off[];
+    const int total = stage_offsets(s_off, off, nbox);
+    const int cell = threadIdx.x & (AFF_TEAM - 1);
+    const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
+    for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < total; q += nteams) {
+        const int b = flat_box(s_off, nbox, q);
+        const BoxRef &B = boxes[b];
+        affected_rho_one<float>(B.S, B.sc, B.g, T, TL, MlpNet{}, q - s_off[b], cell);
+    }
+}
+
+__global__ __launch_bounds__(AFF_THREADS) void kf_affected_force(const BoxRef *__restrict__ boxes, int nbox,
+                                                                 const int32_t *off, Tables<double> T, double kf) {
+    extern __shared__ int s_off[];
+    const int total = stage_offsets(s_off, off, nbox);
+    const int cell = threadIdx.x & (AFF_TEAM - 1);
+    const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
+    for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < total; q += nteams) {
+        const int b = flat_box(s_off, nbox, q);
+        const BoxRef &B = boxes[b];
+        affected_force_one<float>(B.S, B.sc, B.g, T, 1, kf, q - s_off[b], cell);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // The affected list: every lattice atom a run-away atom paired with, in ascending
@@ -1002,24 +1152,53 @@ hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, 
     return hipGetLastError();
 }
 
-hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, int mark_blocks) {
+bool flat_runaway_fits(int nbox) { return nbox <= FLAT_MAX_BOXES; }
+
+// off: 2 (nbox + 1) ints of device memory for the run-away and affected-atom offsets
+// of the flattened passes (nullptr: per-box grids of gx_small blocks).  The force half
+// reuses the offsets the density half computed (neither count changes in between).
+hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, int mark_blocks,
+                               int32_t *off) {
     hipStream_t st = h0->stream;
-    hipLaunchKernelGGL(kb_runaway_rho, dim3(gx_small, nbox), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, boxes,
-                       t64_of(h0));
+    const size_t lds = sizeof(int32_t) * (nbox + 1);
+    if (off) {
+        hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 0, off);
+        hipLaunchKernelGGL(kf_runaway_rho, dim3(FLAT_BLOCKS), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes,
+                           nbox, off, t64_of(h0));
+    } else {
+        hipLaunchKernelGGL(kb_runaway_rho, dim3(gx_small, nbox), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, boxes,
+                           t64_of(h0));
+    }
     hipLaunchKernelGGL(kb_mark_count, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
     hipLaunchKernelGGL(kb_mark_scan, dim3(1, nbox), dim3(1024), 0, st, boxes);
     hipLaunchKernelGGL(kb_mark_emit, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
-    hipLaunchKernelGGL(kb_affected_rho<float>, dim3(gx_small, nbox), dim3(AFF_THREADS), 0, st, boxes, t64_of(h0),
-                       t32_of(h0), MlpNet{});
+    if (off) {
+        hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 1, off + nbox + 1);
+        hipLaunchKernelGGL(kf_affected_rho, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox,
+                           off + nbox + 1, t64_of(h0), t32_of(h0));
+    } else {
+        hipLaunchKernelGGL(kb_affected_rho<float>, dim3(gx_small, nbox), dim3(AFF_THREADS), 0, st, boxes,
+                           t64_of(h0), t32_of(h0), MlpNet{});
+    }
     return hipGetLastError();
 }
 
-hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, bool energy) {
+hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, bool energy,
+                                 const int32_t *off) {
     hipStream_t st = h0->stream;
-    hipLaunchKernelGGL(kb_runaway_force, dim3(gx_small, nbox), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, boxes,
-                       t64_of(h0), 1, energy ? 1 : 0);
-    hipLaunchKernelGGL(kb_affected_force<float>, dim3(gx_small, nbox), dim3(AFF_THREADS), 0, st, boxes, t64_of(h0),
-                       1, ACC_UNIT / h0->mass);
+    const size_t lds = sizeof(int32_t) * (nbox + 1);
+    const double kf = ACC_UNIT / h0->mass;
+    if (off) {
+        hipLaunchKernelGGL(kf_runaway_force, dim3(FLAT_BLOCKS), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes,
+                           nbox, off, t64_of(h0), energy ? 1 : 0);
+        hipLaunchKernelGGL(kf_affected_force, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox,
+                           off + nbox + 1, t64_of(h0), kf);
+    } else {
+        hipLaunchKernelGGL(kb_runaway_force, dim3(gx_small, nbox), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, boxes,
+                           t64_of(h0), 1, energy ? 1 : 0);
+        hipLaunchKernelGGL(kb_affected_force<float>, dim3(gx_small, nbox), dim3(AFF_THREADS), 0, st, boxes,
+                           t64_of(h0), 1, kf);
+    }
     return hipGetLastError();
 }
 
