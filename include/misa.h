@@ -389,13 +389,17 @@ int misa_mlp_force_match(misa_mlp_trainer *t, const double *r, const double *dha
  * each keeps its own adaptive time step, run-away atoms, hash and statistics.
  * misa_batch_step advances every box by the same number of steps with one
  * launch per kernel of the step for the whole batch: the rho and force passes
- * are single persistent launches over a list of (box, tile) items, the other
+ * are single persistent launches over a list of (box, tile) items, the passes
+ * over run-away atoms take items from one list of all boxes' run-aways, the other
  * kernels take the box from the grid's second dimension.  Results equal those
  * of misa_step on each box alone, bit for bit.
  */
 typedef struct misa_batch misa_batch;
 
-/* n_boxes descriptors (host); on success *out owns the batch. */
+/* n_boxes descriptors (host), 1 <= n_boxes <= 8192; on success *out owns the batch.
+ * The run-away passes of a batched step run over one work list of all boxes,
+ * indexed with 32-bit integers: MISA_EINVAL when the boxes' run-away capacities
+ * (or the affected-atom capacities derived from them) sum to 2^31 - 1 or more. */
 int misa_batch_create(const misa_lattice_desc *descs, int32_t n_boxes, void *hip_stream, misa_batch **out);
 int misa_batch_destroy(misa_batch *b);
 const char *misa_batch_last_error(const misa_batch *b);

@@ -979,8 +979,7 @@ struct misa_batch {
     BoxRef *d_ref = nullptr;
     BoxPass *d_pass = nullptr;
     int2 *d_items = nullptr;
-    int32_t *d_off = nullptr;  // 2 (boxes + 1): offsets of the flattened run-away passes
-    bool flat = false;         // run-away passes over one list of all boxes (int32 item indices)
+    int32_t *d_off = nullptr;  // 2 (boxes + 1): offsets of the run-away work list
     int64_t cap_boxes = 0, cap_items = 0;
     std::vector<int32_t> shape;                  // tile shape of each box (index into TILE_SHAPES)
     StencilEntry<float> *d_st = nullptr;         // [N_TILE_SHAPES][2][KMAX]: stencil per tile shape
@@ -1045,14 +1044,7 @@ int batch_tables(misa_batch *b) {
         BCHK(b, hipMalloc((void **)&b->d_off, sizeof(int32_t) * 2 * (nb + 1)));
         b->cap_boxes = nb;
     }
-    {
-        int64_t run = 0, aff = 0;  // largest possible list lengths
-        for (misa_lattice *h : b->box) {
-            run += h->rcap;
-            aff += h->sc.affected_cap;
-        }
-        b->flat = flat_runaway_fits(nb) && run < INT32_MAX && aff < INT32_MAX;
-    }
+
     if ((int64_t)b->items.size() > b->cap_items) {
         (void)hipFree(b->d_items);
         b->d_items = nullptr;
@@ -1074,6 +1066,8 @@ extern "C" {
 
 int misa_batch_create(const misa_lattice_desc *descs, int32_t n_boxes, void *hip_stream, misa_batch **out) {
     if (!descs || !out || n_boxes < 1) return bfail(nullptr, MISA_EINVAL, "need descriptors, n_boxes >= 1 and out");
+    if (n_boxes > BATCH_MAX_BOXES)
+        return bfail(nullptr, MISA_EINVAL, "at most " + std::to_string(BATCH_MAX_BOXES) + " boxes per batch");
     *out = nullptr;
     const misa_lattice_desc &d0 = descs[0];
     for (int k = 0; k < n_boxes; ++k) {
@@ -1095,6 +1089,18 @@ int misa_batch_create(const misa_lattice_desc *descs, int32_t n_boxes, void *hip
             return bfail(nullptr, rc, m);
         }
         b->box.push_back(h);
+    }
+    {
+        // the run-away passes index one list over all boxes with 32-bit integers
+        int64_t run = 0, aff = 0;
+        for (const misa_lattice *h : b->box) {
+            run += h->rcap;
+            aff += h->sc.affected_cap;
+        }
+        if (run >= INT32_MAX || aff >= INT32_MAX) {
+            misa_batch_destroy(b);
+            return bfail(nullptr, MISA_EINVAL, "run-away capacities of the batch sum beyond 2^31 - 1");
+        }
     }
     b->shape.assign(n_boxes, 0);
     // The boxes share one stencil: its LDS offsets for every tile shape, from box 0.
@@ -1222,7 +1228,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
-            BCHK(b, launchb_runaway_rho(h0, b->d_ref, nb, gx_small, max_mark, b->flat ? b->d_off : nullptr));
+            BCHK(b, launchb_runaway_rho(h0, b->d_ref, nb, max_mark, b->d_off));
         }
         {
             GroupTimer t(h0, MISA_TIMER_FORCE);
@@ -1230,7 +1236,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
-            BCHK(b, launchb_runaway_force(h0, b->d_ref, nb, gx_small, last, b->flat ? b->d_off : nullptr));
+            BCHK(b, launchb_runaway_force(h0, b->d_ref, nb, last, b->d_off));
         }
         {
             GroupTimer t(h0, MISA_TIMER_OTHER);
@@ -1257,8 +1263,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         // the key: everything the captured launches bake in
         std::vector<uint64_t> key = {(uint64_t)nitems, (uint64_t)any_shape, (uint64_t)gx_sites, (uint64_t)max_mark,
                                      (uint64_t)(uintptr_t)b->d_ref, (uint64_t)(uintptr_t)b->d_pass,
-                                     (uint64_t)(uintptr_t)b->d_items, (uint64_t)(uintptr_t)b->d_off,
-                                     (uint64_t)b->flat};
+                                     (uint64_t)(uintptr_t)b->d_items, (uint64_t)(uintptr_t)b->d_off};
         uint64_t bits;
         std::memcpy(&bits, &dt_max, 8);
         key.push_back(bits);

@@ -74,6 +74,7 @@ constexpr int32_t VACANT_ID = 0x7fffffff;      // atom id stored in an empty slo
 // run-away / hash scratch
 constexpr int SORT_THREADS = 1024;
 constexpr int SORT_LDS_MAX = 16384;            // single-block LDS bitonic sort up to this many keys (128 KB)
+constexpr int BATCH_MAX_BOXES = 8192;         // boxes per batch (run-away list offsets staged in LDS)
 constexpr int RUNAWAY_WAVES_PER_BLOCK = 4;     // one wave per run-away atom
 constexpr int SMALL_GRID = 1024;               // blocks of grid-stride kernels over run-away lists
 constexpr int MARK_THREADS = 256;              // lanes per block of the mark-bitmap compaction
@@ -382,11 +383,9 @@ hipError_t launchb_final_kick_runaway(hipStream_t st, const BoxRef *boxes, int n
 hipError_t launchb_dt_update(hipStream_t st, const BoxRef *boxes, int nbox, double mass, double dt_max, double dx_max);
 hipError_t launchb_rehash(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
 hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
-bool flat_runaway_fits(int nbox);
-hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, int mark_blocks,
-                               int32_t *off);
-hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, bool energy,
-                                 const int32_t *off);
+// off: 2 (nbox + 1) ints of device memory (the offsets of the run-away work list)
+hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int mark_blocks, int32_t *off);
+hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, bool energy, const int32_t *off);
 hipError_t launchb_runaway_clear(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
 hipError_t launchb_energy_reduce(hipStream_t st, const BoxRef *boxes, int nbox);
 hipError_t launch_gather_field(misa_lattice *h, int field, double *out);

@@ -578,11 +578,6 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(St
     runaway_rho_body(S, sc, g, T);
 }
 
-__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kb_runaway_rho(const BoxRef *__restrict__ boxes, Tables<double> T) {
-    const BoxRef &B = boxes[blockIdx.y];
-    runaway_rho_body(B.S, B.sc, B.g, T);
-}
-
 
 // Lattice atoms within rc of run-aways: add the run-away terms to rho, refresh F'.
 // emb: the embedding network of the learned form (an empty range on other handles).
@@ -646,12 +641,6 @@ template <typename Real>
 __global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch sc, Geom g, Tables<double> T,
                                                               Tables<Real> TL, MlpNet emb) {
     affected_rho_body<Real>(S, sc, g, T, TL, emb);
-}
-
-template <typename Real>
-__global__ __launch_bounds__(AFF_THREADS) void kb_affected_rho(const BoxRef *__restrict__ boxes, Tables<double> T, Tables<Real> TL, MlpNet emb) {
-    const BoxRef &B = boxes[blockIdx.y];
-    affected_rho_body<Real>(B.S, B.sc, B.g, T, TL, emb);
 }
 
 
@@ -731,11 +720,6 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(
     runaway_force_body(S, sc, g, T, real_is_f32, energy);
 }
 
-__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kb_runaway_force(const BoxRef *__restrict__ boxes, Tables<double> T, int real_is_f32, int energy) {
-    const BoxRef &B = boxes[blockIdx.y];
-    runaway_force_body(B.S, B.sc, B.g, T, real_is_f32, energy);
-}
-
 
 // kick != 0: the force pass already applied the second half-kick with the lattice
 // part of F; add the run-away part's kick here and record |v|^2 for the step statistics.
@@ -805,12 +789,6 @@ __global__ __launch_bounds__(AFF_THREADS) void k_affected_force(State S, Scratch
     affected_force_body<Real>(S, sc, g, T, kick, kf);
 }
 
-template <typename Real>
-__global__ __launch_bounds__(AFF_THREADS) void kb_affected_force(const BoxRef *__restrict__ boxes, Tables<double> T, int kick, double kf) {
-    const BoxRef &B = boxes[blockIdx.y];
-    affected_force_body<Real>(B.S, B.sc, B.g, T, kick, kf);
-}
-
 
 // ---------------------------------------------------------------------------
 // Run-away work of a batch as one list.  Run-aways gather in the few boxes whose
@@ -820,8 +798,7 @@ __global__ __launch_bounds__(AFF_THREADS) void kb_affected_force(const BoxRef *_
 // grid takes items from the whole list.  Each item is computed exactly as in a
 // single-box pass, so results do not depend on how the list is dealt out.
 
-constexpr int FLAT_BLOCKS = 1024;
-constexpr int FLAT_MAX_BOXES = 8192;  // off[] staged in LDS: (FLAT_MAX_BOXES + 1) ints
+constexpr int FLAT_BLOCKS = 1024;  // off[] (at most BATCH_MAX_BOXES + 1 ints) is staged in LDS
 
 // off[0] = 0, off[b + 1] = off[b] + items of box b; which = 0: run-aways, 1: affected
 // lattice atoms (capped at the list's capacity, as the passes over it are).
@@ -1152,53 +1129,30 @@ hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, 
     return hipGetLastError();
 }
 
-bool flat_runaway_fits(int nbox) { return nbox <= FLAT_MAX_BOXES; }
-
-// off: 2 (nbox + 1) ints of device memory for the run-away and affected-atom offsets
-// of the flattened passes (nullptr: per-box grids of gx_small blocks).  The force half
-// reuses the offsets the density half computed (neither count changes in between).
-hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, int mark_blocks,
-                               int32_t *off) {
+// off: 2 (nbox + 1) ints for the offsets of the run-away and affected-atom lists.  The
+// force half reuses the offsets the density half computed (neither count changes in between).
+hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int mark_blocks, int32_t *off) {
     hipStream_t st = h0->stream;
     const size_t lds = sizeof(int32_t) * (nbox + 1);
-    if (off) {
-        hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 0, off);
-        hipLaunchKernelGGL(kf_runaway_rho, dim3(FLAT_BLOCKS), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes,
-                           nbox, off, t64_of(h0));
-    } else {
-        hipLaunchKernelGGL(kb_runaway_rho, dim3(gx_small, nbox), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, boxes,
-                           t64_of(h0));
-    }
+    hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 0, off);
+    hipLaunchKernelGGL(kf_runaway_rho, dim3(FLAT_BLOCKS), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes, nbox,
+                       off, t64_of(h0));
     hipLaunchKernelGGL(kb_mark_count, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
     hipLaunchKernelGGL(kb_mark_scan, dim3(1, nbox), dim3(1024), 0, st, boxes);
     hipLaunchKernelGGL(kb_mark_emit, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
-    if (off) {
-        hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 1, off + nbox + 1);
-        hipLaunchKernelGGL(kf_affected_rho, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox,
-                           off + nbox + 1, t64_of(h0), t32_of(h0));
-    } else {
-        hipLaunchKernelGGL(kb_affected_rho<float>, dim3(gx_small, nbox), dim3(AFF_THREADS), 0, st, boxes,
-                           t64_of(h0), t32_of(h0), MlpNet{});
-    }
+    hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 1, off + nbox + 1);
+    hipLaunchKernelGGL(kf_affected_rho, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox, off + nbox + 1,
+                       t64_of(h0), t32_of(h0));
     return hipGetLastError();
 }
 
-hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, int gx_small, bool energy,
-                                 const int32_t *off) {
+hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, bool energy, const int32_t *off) {
     hipStream_t st = h0->stream;
     const size_t lds = sizeof(int32_t) * (nbox + 1);
-    const double kf = ACC_UNIT / h0->mass;
-    if (off) {
-        hipLaunchKernelGGL(kf_runaway_force, dim3(FLAT_BLOCKS), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes,
-                           nbox, off, t64_of(h0), energy ? 1 : 0);
-        hipLaunchKernelGGL(kf_affected_force, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox,
-                           off + nbox + 1, t64_of(h0), kf);
-    } else {
-        hipLaunchKernelGGL(kb_runaway_force, dim3(gx_small, nbox), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, boxes,
-                           t64_of(h0), 1, energy ? 1 : 0);
-        hipLaunchKernelGGL(kb_affected_force<float>, dim3(gx_small, nbox), dim3(AFF_THREADS), 0, st, boxes,
-                           t64_of(h0), 1, kf);
-    }
+    hipLaunchKernelGGL(kf_runaway_force, dim3(FLAT_BLOCKS), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes, nbox,
+                       off, t64_of(h0), energy ? 1 : 0);
+    hipLaunchKernelGGL(kf_affected_force, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox, off + nbox + 1,
+                       t64_of(h0), ACC_UNIT / h0->mass);
     return hipGetLastError();
 }
 

@@ -63,6 +63,17 @@ def test_descriptor_validation_without_gpu():
         M.misa_create_lattice((16, 16, 16), 2.855, 5.0, 0.6, 55.845, pair_precision=7)
 
 
+def test_batch_limits_without_gpu():
+    """A batch holds 1 .. 8192 boxes (its run-away work list is indexed through offsets
+    staged in LDS); anything else is rejected before any HIP call."""
+    from paper_2107_07866_amd import misa as M
+    for n in (0, 8193):
+        with pytest.raises(M.MisaError) as ei:
+            M.misa_batch_create([(16, 16, 16)] * n, 2.855, 5.0, 0.6, 55.845)
+        assert ei.value.code == M.MISA_EINVAL
+        assert M.misa_batch_last_error(None)
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_2107_07866_amd import misa as M
     monkeypatch.setattr(M, "LIB_PATH", str(tmp_path / "libmisa.so"))
