@@ -509,7 +509,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
         }
     }
     h->stencil_canon.resize(2 * h->K * 3);
-    std::vector<StencilEntry<double>> s64(2 * KMAX);
+    std::vector<StencilEntry<double>> s64(2 * KMAX), s64p(2 * KMAX);
     std::vector<StencilEntry<float>> s32(2 * KMAX), s32p(2 * KMAX);
     for (int p = 0; p < 2; ++p)
         for (int k = 0; k < h->K; ++k) {
@@ -528,6 +528,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
             s32[p * KMAX + k] = StencilEntry<float>{lds, (float)ox, (float)oy, (float)oz};
             const int lds2 = (pn - p) * P2Z * P2Y * P2X + (dcz * P2Y + dcy) * P2X + dcx;
             s32p[p * KMAX + k] = StencilEntry<float>{lds2, (float)ox, (float)oy, (float)oz};
+            s64p[p * KMAX + k] = StencilEntry<double>{lds2, 0, ox, oy, oz};
             int64_t *c = &h->stencil_canon[(p * h->K + k) * 3];
             c[0] = o.dX;
             c[1] = o.dY;
@@ -591,6 +592,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(h->st64, 2 * KMAX);
     ALLOC(h->st32, 2 * KMAX);
     ALLOC(h->st32p, 2 * KMAX);
+    ALLOC(h->st64p, 2 * KMAX);
     ALLOC(h->sth, 2 * KMAX);
     ALLOC(h->hmeta, 2 * HALF_META);
     ALLOC(sc.cnt, 1);
@@ -629,6 +631,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     if ((e = hipMemcpy(h->st64, s64.data(), sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->st32, s32.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->st32p, s32p.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(h->st64p, s64p.data(), sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->sth, sh.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->hmeta, hmeta.data(), sizeof(int32_t) * 2 * HALF_META, hipMemcpyHostToDevice)) ||
         (e = hipMemset(sc.cnt, 0, sizeof(Counters))) || (e = hipMemset(sc.scal, 0, 8 * sizeof(double))) ||
@@ -654,7 +657,7 @@ int misa_destroy_lattice(misa_lattice *h) {
         (void)hipDeviceSynchronize();
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    void *ptrs[] = {h->st64, h->st32, h->st32p, h->sth, h->hmeta, h->lds32.f, h->lds32.force, h->lds32h.f,
+    void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->lds64.nodes, h->sth, h->hmeta, h->lds32.f, h->lds32.force, h->lds32h.f,
                     h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
@@ -782,6 +785,28 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
         W.pcq = (float)(-q0 / hq);
         W.usable = q1 > q0;
         W.node_cut = std::fabs(x_last - h->g.rc) <= 1e-12 * h->g.rc;
+    }
+    // Node window of f for the persistent float64 density pass: the nodes of every
+    // segment a pair of slotted atoms can reach (the same lower bound as above).
+    {
+        NodeWin64 &W = h->lds64;
+        (void)hipFree(W.nodes);
+        W = NodeWin64{};
+        const double r_lo = h->d_min - 2.0 * std::sqrt(h->g.delta2) - 2.0 * f->dx;
+        int64_t k0 = (int64_t)std::floor((r_lo - f->x0) / f->dx);
+        k0 = std::max<int64_t>(0, std::min<int64_t>(k0, f->n - 2));
+        const int64_t nn = f->n - k0;
+        if (nn <= NODE64_MAX) {
+            std::vector<double> m;
+            node_slopes(f->y, f->n, m);
+            std::vector<double2> nodes(nn);
+            for (int64_t i = 0; i < nn; ++i) nodes[i] = make_double2(f->y[k0 + i], m[k0 + i]);
+            HIPCHK(h, dev_alloc(&W.nodes, nn));
+            HIPCHK(h, hipMemcpy(W.nodes, nodes.data(), sizeof(double2) * nn, hipMemcpyHostToDevice));
+            W.k0 = (int32_t)k0;
+            W.nn = (int32_t)nn;
+            W.usable = true;
+        }
     }
     h->tables_set = true;
     h->rho_valid = h->force_valid = false;

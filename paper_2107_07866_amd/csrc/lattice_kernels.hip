@@ -12,51 +12,6 @@
 
 namespace misa {
 
-template <typename Real>
-__device__ __forceinline__ void seg_index(Real x, const TabMeta<Real> &m, int &k, Real &t) {
-    const Real p = (x - m.x0) * m.inv_h;
-    int kk = (int)p;
-    kk = kk < m.nseg - 1 ? kk : m.nseg - 1;
-    kk = kk > 0 ? kk : 0;  // below the first node: cubic continuation of segment 0
-    k = kk;
-    t = p - (Real)kk;
-}
-
-// F(rho) and F'(rho); linear continuation beyond the last node (flagged).
-template <typename Real>
-__device__ __forceinline__ Real emb_eval(Real rho, const Q4<Real> *__restrict__ emb, const TabMeta<Real> &m,
-                                         Real &Fval, bool &beyond) {
-    if (rho > m.x_last) {
-        beyond = true;
-        Fval = m.y_last + m.d_last * (rho - m.x_last);
-        return m.d_last;
-    }
-    int k;
-    Real t;
-    seg_index(rho, m, k, t);
-    const Q4<Real> c = emb[2 * k];
-    const Q4<Real> d = emb[2 * k + 1];
-    Fval = ((c.w * t + c.z) * t + c.y) * t + c.x;
-    return (d.z * t + d.y) * t + d.x;
-}
-
-// 1/sqrt(x) for x in a normal range (pair distances): hardware estimate refined by
-// two Newton steps y <- y (3 - x y^2) / 2, each squaring the relative error, so the
-// result is within a few ulp of the correctly rounded value.
-__device__ __forceinline__ double rsqrt_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-x * y, y, 1.0);
-    return fma(0.5 * y, e, y);
-}
-
-template <typename Real>
-__device__ __forceinline__ Real pair_r(Real r2);
-template <>
-__device__ __forceinline__ double pair_r<double>(double r2) { return r2 * rsqrt_nr(r2); }
-template <>
-__device__ __forceinline__ float pair_r<float>(float r2) { return __builtin_amdgcn_sqrtf(r2); }
 
 template <typename Real>
 __device__ __forceinline__ void pair_r_rinv(Real r2, Real &r, Real &rinv);
@@ -356,6 +311,7 @@ hipError_t launch_rho(misa_lattice *h) {
     if (half_path(h)) return launch_rho_half(h);
     if (lds_path(h)) return launch_rho_lds(h);
     if (h->precision == MISA_FP32) return rho_impl<float>(h, h->st32, h->t32);
+    if (lds64_path(h)) return launch_rho_lds64(h);
     return rho_impl<double>(h, h->st64, h->t64);
 }
 

@@ -574,6 +574,134 @@ static OneBox one_box(misa_lattice *h) {
     return o;
 }
 
+// ---------------------------------------------------------------------------
+// Float64 density pass on the same persistent scheme.  The float64 spline records
+// (32 bytes per segment) of the window would not fit beside a float64 tile, but its
+// nodes do: node i holds {y_i, m_i}, and segment i is the cubic Hermite through nodes
+// i and i + 1 in t in [0, 1], c2 = 3 dy - 2 m_i - m_{i+1}, c3 = m_i + m_{i+1} - 2 dy
+// (dy = y_{i+1} - y_i), the same coefficients the float64 table records hold.  The
+// window (at most NODE64_MAX nodes, 16 bytes each) sits beside an 8 x 8 x 8 tile of
+// float64 displacements (x and y as one 16-byte word, z apart): 147 KiB of LDS.
+
+// Stores this lane's share of the tile; returns the largest |u|^2 among the occupied
+// sites it stored (in float32, as the stencil-length test takes it).
+__device__ __forceinline__ float store_tile64(double2 *__restrict__ txy, double *__restrict__ tz,
+                                              const TileRegs &R, int sites) {
+    float m = 0.0f;
+#pragma unroll
+    for (int j = 0; j < TILE2_PER_LANE; ++j) {
+        const int e = threadIdx.x + j * TILE2_THREADS;
+        if (e < sites) {
+            txy[e] = make_double2(R.x[j], R.y[j]);
+            tz[e] = R.z[j];
+            if (R.x[j] < VACANT_TEST) m = fmaxf(m, (float)(R.x[j] * R.x[j] + R.y[j] * R.y[j] + R.z[j] * R.z[j]));
+        }
+    }
+    return m;
+}
+
+// rho_i = sum_j f(r_ij) over the stencil, then F'(rho_i) (Sec. 2.2 steps 1-2), float64.
+// nodes: nn nodes of f from source node k0 on; fm: the source table's grid.
+__global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds64(OneBox src, const StencilEntry<double> *__restrict__ st,
+                                                            int K, int kin, float u_cut2,
+                                                            const double2 *__restrict__ nodes, int k0, int nn,
+                                                            TabMeta<double> fm, const Q4<double> *__restrict__ etab,
+                                                            TabMeta<double> em, double rc2) {
+    __shared__ double2 txy[TILE2_SITES];
+    __shared__ double tz[TILE2_SITES];
+    __shared__ double2 nwin[NODE64_MAX];
+    __shared__ unsigned umax_slot[2];
+    if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
+    for (int e = threadIdx.x; e < nn; e += TILE2_THREADS) nwin[e] = nodes[e];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = __builtin_amdgcn_readfirstlane(w >> 3);  // wave-uniform parity: scalar stencil loads
+    TileGeo Gf{};
+    const Dims d = dims_of<OneBox>(Gf);
+    const LaneSite L = lane_site(d, p, w, lane);
+    const StencilEntry<double> *sp = st + p * KMAX;
+    const int lmax = nn - 2;  // last segment of the window
+    int it = 0;
+    int item = src.next(blockIdx.x, it, gridDim.x);
+    TileRegs R;
+    if (item >= 0) {
+        TileGeo G0;
+        PassPtrs P0;
+        const int t0 = src.get(item, G0, P0);
+        fetch_tile2<OneBox>(R, P0.ux, P0.uy, P0.uz, nullptr, G0, d, t0);
+    }
+    while (item >= 0) {
+        TileGeo G;
+        PassPtrs P;
+        const int tid = src.get(item, G, P);
+        __syncthreads();  // previous tile fully consumed (and the window copied)
+        const float m = store_tile64(txy, tz, R, d.sites);
+        const int Kt = tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2);
+        ++it;
+        const int nxt = src.next(blockIdx.x, it, gridDim.x);
+        if (nxt >= 0) {
+            TileGeo Gn;
+            PassPtrs Pn;
+            const int ntid = src.get(nxt, Gn, Pn);
+            fetch_tile2<OneBox>(R, Pn.ux, Pn.uy, Pn.uz, nullptr, Gn, d, ntid);  // in flight during this tile
+        }
+        const int tx = tid % G.nt0;
+        const int tyz = tid / G.nt0;
+        const int gx = tx * d.tx + L.lx, gy = (tyz % G.nt1) * d.ty + L.ly, gz = (tyz / G.nt1) * d.tz + L.lz;
+        if (gx < G.nx && gy < G.ny && gz < G.nz) {
+            const int me = L.me;
+            const double2 pi = txy[me];
+            const double zi = tz[me];
+            double acc = 0.0;
+#pragma unroll 2
+            for (int k = 0; k < Kt; ++k) {
+                const StencilEntry<double> e = sp[k];
+                const double2 pj = txy[me + e.lds];
+                const double dx = (pj.x - pi.x) + e.ox;
+                const double dy = (pj.y - pi.y) + e.oy;
+                const double dz = (tz[me + e.lds] - zi) + e.oz;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const bool in = r2 < rc2;
+                int s;
+                double t;
+                seg_index(pair_r<double>(in ? r2 : rc2), fm, s, t);
+                // inside the window for every pair of slotted atoms; clamped otherwise
+                const int l = min(max(s - k0, 0), lmax);
+                const double2 a = nwin[l], b = nwin[l + 1];
+                const double dyn = b.x - a.x;
+                const double c2 = 3.0 * dyn - 2.0 * a.y - b.y;
+                const double c3 = a.y + b.y - 2.0 * dyn;
+                const double v = ((c3 * t + c2) * t + a.y) * t + a.x;
+                acc += in ? v : 0.0;
+            }
+            const int64_t idx = (int64_t)p * G.ncell + ((int64_t)gz * G.ny + gy) * G.nx + gx;
+            double fpv = 0.0;
+            bool beyond = false;
+            if (pi.x > VACANT_TEST) {
+                acc = 0.0;
+            } else {
+                double Fv;
+                fpv = emb_eval<double>(acc, etab, em, Fv, beyond);
+            }
+            ((double *)P.rho)[idx] = acc;  // float64 arrays on a float64 handle
+            ((double *)P.fp)[idx] = fpv;
+            if (beyond) atomicAdd(P.range_viol, 1u);
+        }
+        item = nxt;
+    }
+}
+
+bool lds64_path(const misa_lattice *h) {
+    return h->precision == MISA_FP64 && !h->use_mlp && h->lds64.usable && h->persistent_grid > 0;
+}
+
+hipError_t launch_rho_lds64(misa_lattice *h) {
+    OneBox o = one_box(h);
+    hipLaunchKernelGGL(k_rho_lds64, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, o, h->st64p, h->K,
+                       h->K_in, h->u_cut2, h->lds64.nodes, h->lds64.k0, h->lds64.nn, h->t64.fm, h->t64.emb,
+                       h->t64.em, h->g.rc2);
+    return hipGetLastError();
+}
+
 static Tables<float> t32_tab(const misa_lattice *h) {
     Tables<float> T;
     T.f = h->t32.f;

@@ -228,6 +228,15 @@ struct LdsTables {
     bool node_cut = false;    // last node at rc: a zero record after the window implements the cut-off
 };
 
+// Window of the f spline's nodes for the persistent float64 density pass: node
+// k0 + i holds {y, m} (value, and slope in units of the sample spacing), i < nn.
+constexpr int NODE64_MAX = 4096;
+struct NodeWin64 {
+    double2 *nodes = nullptr;
+    int32_t k0 = 0, nn = 0;
+    bool usable = false;
+};
+
 // Forward half of the stencil for the half-stencil passes, per parity: entries
 // grouped by phase (dZ, partner parity != own), nearest first inside a phase,
 // with LDS offsets in the footprint layout.  meta[p * HALF_META + q] is the first
@@ -296,6 +305,8 @@ struct misa_lattice {
     int n_cu = 0;                                 // compute units of the device
     int persistent_grid = 0;                      // work-groups of the persistent kernels (multiple of 8)
     misa::StencilEntry<float> *st32p = nullptr;   // stencil with LDS offsets of the 8x8x8 tiles
+    misa::StencilEntry<double> *st64p = nullptr;  // the same offsets, float64 separations
+    misa::NodeWin64 lds64;                        // f nodes for the persistent float64 density pass
     int pair_schedule = 0;                        // MISA_PAIRS_GATHER or MISA_PAIRS_HALF
     bool half_fits = false;                       // every axis a multiple of 16 cells (8 colours of tiles)
     misa::StencilEntry<float> *sth = nullptr;     // half-stencil entries (device [2][KMAX])
@@ -346,6 +357,8 @@ hipError_t launch_rho(misa_lattice *h);
 hipError_t launch_force(misa_lattice *h, bool energy, bool kick);
 bool lds_path(const misa_lattice *h);                  // persistent float32 kernels usable
 hipError_t launch_rho_lds(misa_lattice *h);
+bool lds64_path(const misa_lattice *h);                // persistent float64 density pass usable
+hipError_t launch_rho_lds64(misa_lattice *h);
 hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick);  // kick: fused second half-kick
 PassPtrs pass_ptrs(misa_lattice *h);
 // batched persistent passes over (box, tile) items; h0 supplies stencil, tables and stream
@@ -470,5 +483,54 @@ __host__ __device__ inline int64_t storage_of_lattice_id(int64_t id, const Geom 
                   Z = id / (2 * (int64_t)g.nx * g.ny);
     return (X & 1) * g.ncell + (Z * g.ny + Y) * g.nx + (X >> 1);
 }
+
+// ---------------------------------------------------------------------------
+// Table evaluation shared by the float64 lattice passes.
+
+template <typename Real>
+__device__ __forceinline__ void seg_index(Real x, const TabMeta<Real> &m, int &k, Real &t) {
+    const Real p = (x - m.x0) * m.inv_h;
+    int kk = (int)p;
+    kk = kk < m.nseg - 1 ? kk : m.nseg - 1;
+    kk = kk > 0 ? kk : 0;  // below the first node: cubic continuation of segment 0
+    k = kk;
+    t = p - (Real)kk;
+}
+
+// F(rho) and F'(rho); linear continuation beyond the last node (flagged).
+template <typename Real>
+__device__ __forceinline__ Real emb_eval(Real rho, const Q4<Real> *__restrict__ emb, const TabMeta<Real> &m,
+                                         Real &Fval, bool &beyond) {
+    if (rho > m.x_last) {
+        beyond = true;
+        Fval = m.y_last + m.d_last * (rho - m.x_last);
+        return m.d_last;
+    }
+    int k;
+    Real t;
+    seg_index(rho, m, k, t);
+    const Q4<Real> c = emb[2 * k];
+    const Q4<Real> d = emb[2 * k + 1];
+    Fval = ((c.w * t + c.z) * t + c.y) * t + c.x;
+    return (d.z * t + d.y) * t + d.x;
+}
+
+// 1/sqrt(x) for x in a normal range (pair distances): hardware estimate refined by
+// two Newton steps y <- y (3 - x y^2) / 2, each squaring the relative error, so the
+// result is within a few ulp of the correctly rounded value.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+template <typename Real>
+__device__ __forceinline__ Real pair_r(Real r2);
+template <>
+__device__ __forceinline__ double pair_r<double>(double r2) { return r2 * rsqrt_nr(r2); }
+template <>
+__device__ __forceinline__ float pair_r<float>(float r2) { return __builtin_amdgcn_sqrtf(r2); }
 
 }  // namespace misa
