@@ -140,10 +140,13 @@ int upload_tables(misa_lattice *h, DevTables<Real> &D, const std::vector<SegCoef
                   const misa_table &e) {
     const size_t nf = sf.size(), ne = se.size();
     std::vector<Q4<Real>> F(nf), FO(2 * nf), PH(nf), EM(2 * ne);
+    std::vector<Real> FO6(6 * nf);
     for (size_t k = 0; k < nf; ++k) {
         F[k] = {(Real)sf[k].c0, (Real)sf[k].c1, (Real)sf[k].c2, (Real)sf[k].c3};
         FO[2 * k] = {(Real)sf[k].d0, (Real)sf[k].d1, (Real)sf[k].d2, (Real)sp[k].d0};
         FO[2 * k + 1] = {(Real)sp[k].d1, (Real)sp[k].d2, (Real)0, (Real)0};
+        const double r6[6] = {sf[k].d0, sf[k].d1, sf[k].d2, sp[k].d0, sp[k].d1, sp[k].d2};
+        for (int i = 0; i < 6; ++i) FO6[6 * k + i] = (Real)r6[i];
         PH[k] = {(Real)sp[k].c0, (Real)sp[k].c1, (Real)sp[k].c2, (Real)sp[k].c3};
     }
     for (size_t k = 0; k < ne; ++k) {
@@ -154,11 +157,15 @@ int upload_tables(misa_lattice *h, DevTables<Real> &D, const std::vector<SegCoef
     (void)hipFree(D.force);
     (void)hipFree(D.phi);
     (void)hipFree(D.emb);
+    (void)hipFree(D.force6);
     D.f = D.force = D.phi = D.emb = nullptr;
+    D.force6 = nullptr;
     HIPCHK(h, dev_alloc(&D.f, (int64_t)nf));
     HIPCHK(h, dev_alloc(&D.force, (int64_t)(2 * nf)));
     HIPCHK(h, dev_alloc(&D.phi, (int64_t)nf));
     HIPCHK(h, dev_alloc(&D.emb, (int64_t)(2 * ne)));
+    HIPCHK(h, dev_alloc(&D.force6, (int64_t)(6 * nf)));
+    HIPCHK(h, hipMemcpy(D.force6, FO6.data(), sizeof(Real) * 6 * nf, hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(D.f, F.data(), sizeof(Q4<Real>) * nf, hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(D.force, FO.data(), sizeof(Q4<Real>) * 2 * nf, hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(D.phi, PH.data(), sizeof(Q4<Real>) * nf, hipMemcpyHostToDevice));
@@ -658,7 +665,7 @@ int misa_destroy_lattice(misa_lattice *h) {
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->lds64.nodes, h->sth, h->hmeta, h->lds32.f, h->lds32.force, h->lds32h.f,
-                    h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t32.f, h->t32.force,
+                    h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t64.force6, h->t32.force6, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
                     h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,

@@ -149,6 +149,23 @@ struct KickArgs {
     double kf;           // C / m
 };
 
+// f'(r) and phi'(r) of segment s at t.  Float64 gathers the dense 48-byte record
+// (three 16-byte loads); float32 the two 16-byte records.
+template <typename Real>
+__device__ __forceinline__ void force_rec(const Tables<Real> &T, int s, Real t, Real &dfr, Real &dph) {
+    const Q4<Real> a = T.force[2 * s];
+    const Q4<Real> b = T.force[2 * s + 1];
+    dfr = (a.z * t + a.y) * t + a.x;
+    dph = (b.y * t + b.x) * t + a.w;
+}
+template <>
+__device__ __forceinline__ void force_rec<double>(const Tables<double> &T, int s, double t, double &dfr, double &dph) {
+    const double2 *r = reinterpret_cast<const double2 *>(T.force6) + 3 * s;
+    const double2 q0 = r[0], q1 = r[1], q2 = r[2];  // {f'0, f'1}, {f'2, phi'0}, {phi'1, phi'2}
+    dfr = (q1.x * t + q0.y) * t + q0.x;
+    dph = (q2.y * t + q2.x) * t + q1.y;
+}
+
 // F_i = sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (x_j - x_i) / r   (Eq. eam_force_ij)
 // With kEnergy: per-tile partial sums of F(rho_i) and 1/2 sum_j phi(r_ij).
 template <typename Real, bool kEnergy, bool kKick>
@@ -208,10 +225,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
             int s;
             Real t;
             seg_index(r, T.fm, s, t);
-            const Q4<Real> a = T.force[2 * s];
-            const Q4<Real> b = T.force[2 * s + 1];
-            const Real dfr = (a.z * t + a.y) * t + a.x;   // f'(r)
-            const Real dph = (b.y * t + b.x) * t + a.w;   // phi'(r)
+            Real dfr, dph;  // f'(r), phi'(r)
+            force_rec<Real>(T, s, t, dfr, dph);
             const Real sc = in ? ((ui.w + uj.w) * dfr + dph) * rinv : (Real)0;
             ax += sc * dx;
             ay += sc * dy;
@@ -287,6 +302,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
 template <typename Real>
 static Tables<Real> tables_of(const DevTables<Real> &t) {
     Tables<Real> T;
+    T.force6 = t.force6;
     T.f = t.f;
     T.force = t.force;
     T.phi = t.phi;

@@ -122,6 +122,9 @@ template <typename Real>
 struct Tables {
     const Q4<Real> *f, *force, *phi, *emb;
     TabMeta<Real> fm, em;  // f / phi share one grid; emb has its own
+    // dense force records, 6 per segment: f'0, f'1, f'2, phi'0, phi'1, phi'2 (the
+    // float64 tile force pass; 48 instead of 64 gathered bytes per pair)
+    const Real *force6 = nullptr;
 };
 
 struct Geom {
@@ -203,6 +206,7 @@ struct Scratch {
 template <typename Real>
 struct DevTables {
     Q4<Real> *f = nullptr, *force = nullptr, *phi = nullptr, *emb = nullptr;
+    Real *force6 = nullptr;
     TabMeta<Real> fm{}, em{};
 };
 
