@@ -465,7 +465,7 @@ hipError_t launch_dt_update(misa_lattice *h, double dt_max, double dx_max, bool 
     const bool fused = fused_kick(h) && !first;
     const double *part = fused ? h->sc.part_kick : h->sc.part + 2 * (int64_t)h->g.ntiles_pad;
     // per-tile partials of the force pass that kicked: persistent tiles or generic tiles
-    const int nblk = fused ? (lds_path(h) ? h->g.ntiles2 : h->g.ntiles) : KICK_BLOCKS;
+    const int nblk = fused ? (force_on_tiles2(h) ? h->g.ntiles2 : h->g.ntiles) : KICK_BLOCKS;
     hipLaunchKernelGGL(k_dt_update, dim3(1), dim3(1024), 0, h->stream, h->S, h->sc, part, nblk, fused ? 1 : 0,
                        h->mass, dt_max, dx_max, first ? 1 : 0);
     return hipGetLastError();

@@ -13,19 +13,6 @@
 namespace misa {
 
 
-template <typename Real>
-__device__ __forceinline__ void pair_r_rinv(Real r2, Real &r, Real &rinv);
-template <>
-__device__ __forceinline__ void pair_r_rinv<double>(double r2, double &r, double &rinv) {
-    rinv = rsqrt_nr(r2);
-    r = r2 * rinv;
-}
-template <>
-__device__ __forceinline__ void pair_r_rinv<float>(float r2, float &r, float &rinv) {
-    rinv = __builtin_amdgcn_rsqf(r2);
-    r = r2 * rinv;
-}
-
 __device__ __forceinline__ int wrapg(int i, int n) {
     i %= n;
     return i < 0 ? i + n : i;
@@ -354,6 +341,10 @@ static hipError_t force_impl(misa_lattice *h, bool energy, bool kick, const Sten
 // Every table form but the learned one and the half-stencil schedule kicks inside the force pass.
 bool fused_kick(const misa_lattice *h) { return !h->use_mlp && !half_path(h); }
 
+bool force_on_tiles2(const misa_lattice *h) {
+    return lds_path(h) || half_mlp_path(h) || (h->precision == MISA_FP64 && !h->use_mlp && lds64f_path(h));
+}
+
 hipError_t launch_force(misa_lattice *h, bool energy, bool kick) {
     if (half_path(h)) return kick ? hipErrorInvalidValue : launch_force_half(h, energy);
     if (lds_path(h)) return launch_force_lds(h, energy, kick);
@@ -362,6 +353,7 @@ hipError_t launch_force(misa_lattice *h, bool energy, bool kick) {
         return half_mlp_path(h) ? launch_force_half_mlp(h, energy) : launch_force_mlp(h, energy);
     }
     if (h->precision == MISA_FP32) return force_impl<float>(h, energy, kick, h->st32, h->t32);
+    if (lds64f_path(h)) return launch_force_lds64(h, energy, kick);
     return force_impl<double>(h, energy, kick, h->st64, h->t64);
 }
 
@@ -424,7 +416,7 @@ hipError_t launchb_energy_reduce(hipStream_t st, const BoxRef *boxes, int nbox) 
 
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev) {
     // per-tile partials of the force pass used (8 x 8 x 8 tiles or the generic tiles)
-    const int nparts = lds_path(h) || half_mlp_path(h) ? h->g.ntiles2 : h->g.ntiles;
+    const int nparts = force_on_tiles2(h) ? h->g.ntiles2 : h->g.ntiles;
     hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, h->stream, h->sc.part, nparts, h->S.r_e,
                        h->sc.cnt, h->sc.scal, energies_dev);
     return hipGetLastError();

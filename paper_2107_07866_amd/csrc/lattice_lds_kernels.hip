@@ -690,6 +690,264 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds64(OneBox src, const S
     }
 }
 
+static Tables<double> t64_tab(const misa_lattice *h) {
+    Tables<double> T;
+    T.f = h->t64.f;
+    T.force = h->t64.force;
+    T.phi = h->t64.phi;
+    T.emb = h->t64.emb;
+    T.fm = h->t64.fm;
+    T.em = h->t64.em;
+    T.force6 = h->t64.force6;
+    return T;
+}
+
+// Float64 force pass on the same persistent scheme.  The tile holds {x, y} and
+// {z, F'} per site (32 bytes, 110.6 KiB for 8 x 8 x 8 cells), which leaves room for
+// the top FWIN64_MAX dense force records (48 bytes each: f' and phi' as quadratics
+// in t) of the table.  With 5000-point tables that is r >= rc - 1.08 A: the third to
+// fifth BCC neighbour shells.  Segments below the window (the first two shells) are
+// gathered from global memory; the branch is nearly always uniform across a wave,
+// whose lanes share one stencil offset.  Per-tile partials use the 8 x 8 x 8 tiling.
+constexpr int FWIN64_MAX = 1080;
+
+struct TileRegs64 {
+    double x[TILE2_PER_LANE], y[TILE2_PER_LANE], z[TILE2_PER_LANE], w[TILE2_PER_LANE];
+};
+
+__device__ __forceinline__ void fetch_tile64(TileRegs64 &R, const PassPtrs &P, const TileGeo &g, const Dims &d,
+                                             int tid) {
+    const double *__restrict__ fp = (const double *)P.fp;  // float64 arrays on a float64 handle
+    const int tx = tid % g.nt0;
+    const int tyz = tid / g.nt0;
+    const int ty = tyz % g.nt1;
+    const int tz = tyz / g.nt1;
+    const int bx = tx * d.tx - HALO, by = ty * d.ty - HALO, bz = tz * d.tz - HALO;
+#pragma unroll
+    for (int j = 0; j < TILE2_PER_LANE; ++j) {
+        const int e = threadIdx.x + j * TILE2_THREADS;
+        if (e < d.sites) {
+            const int r = e / d.px;
+            const int lx = e - r * d.px;
+            const int r2 = r / d.py;
+            const int ly = r - r2 * d.py;
+            const int p = r2 / d.pz;
+            const int lz = r2 - p * d.pz;
+            const int gx = wrap2(bx + lx, g.nx), gy = wrap2(by + ly, g.ny), gz = wrap2(bz + lz, g.nz);
+            const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
+            R.x[j] = P.ux[idx];
+            R.y[j] = P.uy[idx];
+            R.z[j] = P.uz[idx];
+            R.w[j] = fp[idx];
+        }
+    }
+}
+
+__device__ __forceinline__ float store_tile64w(double2 *__restrict__ txy, double2 *__restrict__ tzw,
+                                               const TileRegs64 &R, int sites) {
+    float m = 0.0f;
+#pragma unroll
+    for (int j = 0; j < TILE2_PER_LANE; ++j) {
+        const int e = threadIdx.x + j * TILE2_THREADS;
+        if (e < sites) {
+            txy[e] = make_double2(R.x[j], R.y[j]);
+            tzw[e] = make_double2(R.z[j], R.w[j]);
+            if (R.x[j] < VACANT_TEST) m = fmaxf(m, (float)(R.x[j] * R.x[j] + R.y[j] * R.y[j] + R.z[j] * R.z[j]));
+        }
+    }
+    return m;
+}
+
+// F_i = sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (x_j - x_i) / r  (Eq. eam_force_ij), float64,
+// with the fused second half-kick and per-tile partials as in k_force_lds.
+// kw0: first table segment held in LDS; nw: segments held.
+template <bool kEnergy, bool kKick>
+__global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const StencilEntry<double> *__restrict__ st,
+                                                              int K, int kin, float u_cut2, Tables<double> T,
+                                                              int kw0, int nw, double rc2, double kf) {
+    __shared__ double2 txy[TILE2_SITES];
+    __shared__ double2 tzw[TILE2_SITES];
+    __shared__ double2 fw[3 * FWIN64_MAX];
+    __shared__ double red[4][TILE2_THREADS / 64];
+    __shared__ unsigned umax_slot[2];
+    if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
+    const double2 *__restrict__ f6 = reinterpret_cast<const double2 *>(T.force6);
+    for (int e = threadIdx.x; e < 3 * nw; e += TILE2_THREADS) fw[e] = f6[3 * kw0 + e];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = __builtin_amdgcn_readfirstlane(w >> 3);
+    TileGeo Gf{};
+    const Dims d = dims_of<OneBox>(Gf);
+    const LaneSite L = lane_site(d, p, w, lane);
+    const StencilEntry<double> *sp = st + p * KMAX;
+    int it = 0;
+    int item = src.next(blockIdx.x, it, gridDim.x);
+    TileRegs64 R;
+    if (item >= 0) {
+        TileGeo G0;
+        PassPtrs P0;
+        const int t0 = src.get(item, G0, P0);
+        fetch_tile64(R, P0, G0, d, t0);
+    }
+    while (item >= 0) {
+        TileGeo G;
+        PassPtrs P;
+        const int tid = src.get(item, G, P);
+        __syncthreads();  // previous tile fully consumed (and the window copied)
+        const float m = store_tile64w(txy, tzw, R, d.sites);
+        const int Kt = tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2);
+        ++it;
+        const int nxt = src.next(blockIdx.x, it, gridDim.x);
+        if (nxt >= 0) {
+            TileGeo Gn;
+            PassPtrs Pn;
+            const int ntid = src.get(nxt, Gn, Pn);
+            fetch_tile64(R, Pn, Gn, d, ntid);  // in flight during this tile
+        }
+        const double hk = kKick ? 0.5 * P.scal[0] * kf : 0.0;
+        const int tx = tid % G.nt0;
+        const int tyz = tid / G.nt0;
+        const int gx = tx * d.tx + L.lx, gy = (tyz % G.nt1) * d.ty + L.ly, gz = (tyz / G.nt1) * d.tz + L.lz;
+        const bool active = gx < G.nx && gy < G.ny && gz < G.nz;
+        const int64_t idx = (int64_t)p * G.ncell + ((int64_t)gz * G.ny + gy) * G.nx + gx;
+        double e_emb = 0.0, e_pair = 0.0, kvm = 0.0, kvs = 0.0;
+        double v0x = 0.0, v0y = 0.0, v0z = 0.0;
+        uint32_t mw = 0u;
+        if (kKick && active) {  // issued now, consumed after the pair loop
+            v0x = P.vx[idx];
+            v0y = P.vy[idx];
+            v0z = P.vz[idx];
+            mw = P.mark[idx >> 5];
+        }
+        if (active) {
+            const int me = L.me;
+            const double2 pi = txy[me];
+            const double2 zwi = tzw[me];
+            double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
+#pragma unroll 2
+            for (int k = 0; k < Kt; ++k) {
+                const StencilEntry<double> e = sp[k];
+                const double2 pj = txy[me + e.lds];
+                const double2 zwj = tzw[me + e.lds];
+                const double dx = (pj.x - pi.x) + e.ox;
+                const double dy = (pj.y - pi.y) + e.oy;
+                const double dz = (zwj.x - zwi.x) + e.oz;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const bool in = r2 < rc2;
+                double r, rinv;
+                pair_r_rinv<double>(in ? r2 : rc2, r, rinv);
+                int s;
+                double t;
+                seg_index(r, T.fm, s, t);
+                const int l = s - kw0;
+                double2 q0, q1, q2;  // {f'0, f'1}, {f'2, phi'0}, {phi'1, phi'2}
+                if (l >= 0) {
+                    q0 = fw[3 * l];
+                    q1 = fw[3 * l + 1];
+                    q2 = fw[3 * l + 2];
+                } else {
+                    q0 = f6[3 * s];
+                    q1 = f6[3 * s + 1];
+                    q2 = f6[3 * s + 2];
+                }
+                const double dfr = (q1.x * t + q0.y) * t + q0.x;
+                const double dph = (q2.y * t + q2.x) * t + q1.y;
+                const double sc = in ? ((zwi.y + zwj.y) * dfr + dph) * rinv : 0.0;
+                ax += sc * dx;
+                ay += sc * dy;
+                az += sc * dz;
+                if (kEnergy) {
+                    const Q4<double> c = T.phi[s];
+                    const double v = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                    ep += in ? v : 0.0;
+                }
+            }
+            const bool vac = pi.x > VACANT_TEST;
+            if (vac) ax = ay = az = 0.0;
+            double *fxo = (double *)P.fx;  // float64 arrays on a float64 handle
+            double *fyo = (double *)P.fy;
+            double *fzo = (double *)P.fz;
+            fxo[idx] = ax;
+            fyo[idx] = ay;
+            fzo[idx] = az;
+            if (kKick && !vac) {
+                const double vx = v0x + hk * ax;
+                const double vy = v0y + hk * ay;
+                const double vz = v0z + hk * az;
+                P.vx[idx] = vx;
+                P.vy[idx] = vy;
+                P.vz[idx] = vz;
+                if (!((mw >> (idx & 31)) & 1u)) {
+                    kvm = vx * vx + vy * vy + vz * vz;
+                    kvs = kvm;
+                }
+            }
+            if (kEnergy && !vac) {
+                double Fv;
+                bool beyond = false;
+                emb_eval<double>(((const double *)P.rho)[idx], T.emb, T.em, Fv, beyond);
+                e_emb = Fv;
+                e_pair = 0.5 * ep;
+            }
+        }
+        if (kEnergy || kKick) {
+            if (kEnergy) {
+                e_emb = wave_sum_l(e_emb);
+                e_pair = wave_sum_l(e_pair);
+            }
+            if (kKick) {
+                kvm = wave_max_l(kvm);
+                kvs = wave_sum_l(kvs);
+            }
+            if (lane == 0) {
+                red[0][w] = e_emb;
+                red[1][w] = e_pair;
+                red[2][w] = kvm;
+                red[3][w] = kvs;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double s0 = 0.0, s1 = 0.0, m2 = 0.0, s3 = 0.0;
+                for (int q = 0; q < TILE2_THREADS / 64; ++q) {
+                    s0 += red[0][q];
+                    s1 += red[1][q];
+                    m2 = fmax(m2, red[2][q]);
+                    s3 += red[3][q];
+                }
+                if (kEnergy) {
+                    P.part[2 * tid] = s0;
+                    P.part[2 * tid + 1] = s1;
+                }
+                if (kKick) {
+                    P.part_kick[2 * tid] = m2;
+                    P.part_kick[2 * tid + 1] = s3;
+                }
+            }
+        }
+        item = nxt;
+    }
+}
+
+bool lds64f_path(const misa_lattice *h) {
+    return h->precision == MISA_FP64 && !h->use_mlp && h->persistent_grid > 0 && h->g.nsites > 0;
+}
+
+template <bool kEnergy, bool kKick>
+static void force_lds64_variant(misa_lattice *h) {
+    const int nseg = h->t64.fm.nseg;
+    const int nw = nseg < FWIN64_MAX ? nseg : FWIN64_MAX;
+    hipLaunchKernelGGL((k_force_lds64<kEnergy, kKick>), dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream,
+                       one_box(h), h->st64p, h->K, h->K_in, h->u_cut2, t64_tab(h), nseg - nw, nw, h->g.rc2,
+                       ACC_UNIT / h->mass);
+}
+
+hipError_t launch_force_lds64(misa_lattice *h, bool energy, bool kick) {
+    if (energy && kick) force_lds64_variant<true, true>(h);
+    else if (energy) force_lds64_variant<true, false>(h);
+    else if (kick) force_lds64_variant<false, true>(h);
+    else force_lds64_variant<false, false>(h);
+    return hipGetLastError();
+}
+
 bool lds64_path(const misa_lattice *h) {
     return h->precision == MISA_FP64 && !h->use_mlp && h->lds64.usable && h->persistent_grid > 0;
 }

@@ -363,6 +363,10 @@ bool lds_path(const misa_lattice *h);                  // persistent float32 ker
 hipError_t launch_rho_lds(misa_lattice *h);
 bool lds64_path(const misa_lattice *h);                // persistent float64 density pass usable
 hipError_t launch_rho_lds64(misa_lattice *h);
+bool lds64f_path(const misa_lattice *h);               // persistent float64 force pass usable
+hipError_t launch_force_lds64(misa_lattice *h, bool energy, bool kick);
+// per-tile partials of the force pass come from the 8 x 8 x 8 tiling
+bool force_on_tiles2(const misa_lattice *h);
 hipError_t launch_force_lds(misa_lattice *h, bool energy, bool kick);  // kick: fused second half-kick
 PassPtrs pass_ptrs(misa_lattice *h);
 // batched persistent passes over (box, tile) items; h0 supplies stencil, tables and stream
@@ -536,5 +540,18 @@ template <>
 __device__ __forceinline__ double pair_r<double>(double r2) { return r2 * rsqrt_nr(r2); }
 template <>
 __device__ __forceinline__ float pair_r<float>(float r2) { return __builtin_amdgcn_sqrtf(r2); }
+
+template <typename Real>
+__device__ __forceinline__ void pair_r_rinv(Real r2, Real &r, Real &rinv);
+template <>
+__device__ __forceinline__ void pair_r_rinv<double>(double r2, double &r, double &rinv) {
+    rinv = rsqrt_nr(r2);
+    r = r2 * rinv;
+}
+template <>
+__device__ __forceinline__ void pair_r_rinv<float>(float r2, float &r, float &rinv) {
+    rinv = __builtin_amdgcn_rsqf(r2);
+    r = r2 * rinv;
+}
 
 }  // namespace misa
