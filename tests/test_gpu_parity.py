@@ -219,6 +219,24 @@ def test_shifted_force_tables(torch_cuda, orc):
     lat.close()
 
 
+@pytest.mark.parametrize("npts", [1000, 20000])
+def test_fp64_table_resolution(torch_cuda, orc, npts):
+    """Float64 passes with coarse and fine tables.  1000 points: the whole force table
+    sits in the LDS window.  20 000 points: the f node window (r >= nearest-site
+    distance - 2 delta) exceeds 4096 nodes, so the density pass takes the tile kernel
+    with global spline records, and the force pass's LDS window holds only r >= 4.73 A,
+    so the fourth shell straddles its edge (mixed LDS / global reads within a wave)."""
+    _say(f"fp64 tables of {npts} points")
+    tabs = w.potential_samples(n_points=npts)
+    p = orc.Potential(orc.TABLE, tables=tabs)
+    x, v, box = w.thermal_state(7, sigma=0.08, seed=11)
+    lat = _lattice(7, tables=tabs)
+    lat.set_state(x, v)
+    r = _compare_state(orc, p, lat, x, box)
+    _say(f"  {npts}: {r}")
+    lat.close()
+
+
 def test_sum_of_forces_and_determinism(torch_cuda):
     import torch
     _say("newton + determinism")
