@@ -433,7 +433,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
             const int me = L.me;
             const Q4<float> ui = tile[me];
             float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
-#pragma unroll 4
+#pragma unroll 2
             for (int k = 0; k < Kt; ++k) {
                 const StencilEntry<float> e = sp[k];
                 const Q4<float> uj = tile[me + e.lds];
