@@ -342,7 +342,7 @@ static hipError_t force_impl(misa_lattice *h, bool energy, bool kick, const Sten
 bool fused_kick(const misa_lattice *h) { return !h->use_mlp && !half_path(h); }
 
 bool force_on_tiles2(const misa_lattice *h) {
-    return lds_path(h) || half_mlp_path(h) || (h->precision == MISA_FP64 && !h->use_mlp && lds64f_path(h));
+    return lds_path(h) || half_mlp_path(h) || lds64f_path(h);
 }
 
 hipError_t launch_force(misa_lattice *h, bool energy, bool kick) {
