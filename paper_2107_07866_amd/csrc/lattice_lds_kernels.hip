@@ -810,14 +810,6 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const
         const bool active = gx < G.nx && gy < G.ny && gz < G.nz;
         const int64_t idx = (int64_t)p * G.ncell + ((int64_t)gz * G.ny + gy) * G.nx + gx;
         double e_emb = 0.0, e_pair = 0.0, kvm = 0.0, kvs = 0.0;
-        double v0x = 0.0, v0y = 0.0, v0z = 0.0;
-        uint32_t mw = 0u;
-        if (kKick && active) {  // issued now, consumed after the pair loop
-            v0x = P.vx[idx];
-            v0y = P.vy[idx];
-            v0z = P.vz[idx];
-            mw = P.mark[idx >> 5];
-        }
         if (active) {
             const int me = L.me;
             const double2 pi = txy[me];
@@ -870,6 +862,8 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const
             fyo[idx] = ay;
             fzo[idx] = az;
             if (kKick && !vac) {
+                const double v0x = P.vx[idx], v0y = P.vy[idx], v0z = P.vz[idx];
+                const uint32_t mw = P.mark[idx >> 5];
                 const double vx = v0x + hk * ax;
                 const double vy = v0y + hk * ay;
                 const double vz = v0z + hk * az;
