@@ -104,3 +104,28 @@ def test_analytic_derivatives_match_central_differences(orc):
     for g in (P.f, P.phi):
         v, d = g([5.0])
         assert abs(v[0]) < 1e-15 and abs(d[0]) < 1e-15
+
+
+def test_end_segments_closed_form(orc):
+    """The slope rules next to the ends (one-sided at nodes 0 and n-1, second-order
+    central at nodes 1 and n-2) against the Hermite segment they must produce on a
+    polynomial, written out by hand.  With y = s^2 or s^3 sampled at s = x / h = 0..n-1:
+      segment 0,   y = s^2: slopes (1, 2) vs exact (0, 2)       -> S = t^2 + (t^3 - 2t^2 + t)
+      segment 1,   y = s^3: slopes (4, 12) vs exact (3, 12)     -> S = s^3 + (t^3 - 2t^2 + t)
+      segment n-3, y = s^3: slope at n-2 is 3(n-2)^2 + 1        -> S = s^3 + (t^3 - t^2)
+      segment n-2, y = s^2: slopes (2(n-2), 2n-3) vs (.., 2n-2) -> S = s^2 - (t^3 - t^2)
+    (t3 - 2t2 + t and t3 - t2 are the Hermite weights of the left and right slope)."""
+    h, n = 0.5, 12
+    s = np.arange(n, dtype=float)
+    t = np.linspace(0.05, 0.95, 19)
+    h10, h11 = t ** 3 - 2 * t ** 2 + t, t ** 3 - t ** 2
+    dh10, dh11 = 3 * t ** 2 - 4 * t + 1, 3 * t ** 2 - 2 * t
+    cases = [(0, s ** 2, t ** 2 + h10, 2 * t + dh10),
+             (1, s ** 3, (1 + t) ** 3 + h10, 3 * (1 + t) ** 2 + dh10),
+             (n - 3, s ** 3, (n - 3 + t) ** 3 + h11, 3 * (n - 3 + t) ** 2 + dh11),
+             (n - 2, s ** 2, (n - 2 + t) ** 2 - h11, 2 * (n - 2 + t) - dh11)]
+    for k, y, want, dwant in cases:
+        v, d, ext = orc.spline_eval(0.0, h, y, (k + t) * h)
+        assert not ext.any()
+        assert np.max(np.abs(v - want)) < 1e-12, k
+        assert np.max(np.abs(d * h - dwant)) < 1e-11, k  # d/dx = (d/dt) / h
