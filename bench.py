@@ -89,7 +89,7 @@ def train_learned_form(seed=11):
     return nets, info
 
 
-def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None, graph=False):
+def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None, graph=False, recoils=()):
     import numpy as np
     import torch
 
@@ -152,6 +152,19 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None,
         ref = oracle.eam_sampled(oracle.Potential(oracle.TABLE, tables=tabs), xg, box, sample)
         scale = float(np.sqrt(np.mean(ref["F"] ** 2)))
         out["force_err_max_rel_rms"] = float(np.max(np.abs(Fg[sample] - ref["F"]))) / max(scale, 1e-3)
+        # per atom, on sampled atoms farther than 2 rc from every recoil atom:
+        # |dF_i| / max(|F_i|, rms |F| over those atoms)
+        L = np.asarray(box)
+        far = np.ones(len(sample), bool)
+        for i in recoils:
+            d = xg[sample] - xg[int(i)]
+            d -= L * np.rint(d / L)
+            far &= np.einsum("ij,ij->i", d, d) > (2 * w.RC) ** 2
+        fth = np.linalg.norm(ref["F"][far], axis=1)
+        rms_th = float(np.sqrt(np.mean(fth ** 2)))
+        dth = np.linalg.norm(Fg[sample][far] - ref["F"][far], axis=1)
+        out["force_err_per_atom_thermal"] = float(np.max(dth / np.maximum(fth, rms_th)))
+        out["thermal_sample"] = int(far.sum())
         # embedding energy per sampled atom: |F'| |d rho| to first order, so the density error bounds it
         rg = lat.rho()[sample]
         nz = ref["rho"] > 0
@@ -159,8 +172,11 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None,
         out["emb_energy_err_max_eV"] = float(np.max(np.abs(ref["fp"] * (rg - ref["rho"]))))
         out["force_err_sample"] = int(len(sample))
         out["mean_pairs_per_atom"] = float(np.mean(ref["npairs"]))
-        _log(f"[bench] {form}: force error {out['force_err_max_rel_rms']:.2e}, rho error {out['rho_err_max_rel']:.2e} "
-             f"(oracle sample of {len(sample)} atoms, {time.time() - t3:.1f} s)")
+        if form not in ("mlp", "mlp-half"):  # the pair set of the density pass, atom by atom
+            out["pair_counts_equal_oracle"] = bool(np.array_equal(lat.neighbour_counts()[sample], ref["npairs"]))
+        _log(f"[bench] {form}: force error {out['force_err_max_rel_rms']:.2e} (per atom, thermal "
+             f"{out['force_err_per_atom_thermal']:.2e}), rho error {out['rho_err_max_rel']:.2e}, pair counts equal "
+             f"{out.get('pair_counts_equal_oracle')} (oracle sample of {len(sample)} atoms, {time.time() - t3:.1f} s)")
     out["K"] = int(lat.stencil().shape[1])
     lat.close()
     del lat
@@ -412,11 +428,13 @@ def main():
                 trained = train_learned_form()
             nets, info = trained
             k = min(steps, args.mlp_steps)
-            results[form] = run_form(form, x, v, box, cfg, k, min(args.warmup, 2), args.error_sample, nets=nets)
+            results[form] = run_form(form, x, v, box, cfg, k, min(args.warmup, 2), args.error_sample, nets=nets,
+                                     recoils=rec)
             results[form]["training"] = info
             results[form]["timed_steps"] = k
         else:
-            results[form] = run_form(form, x, v, box, cfg, steps, args.warmup, args.error_sample, graph=args.graph)
+            results[form] = run_form(form, x, v, box, cfg, steps, args.warmup, args.error_sample, graph=args.graph,
+                                     recoils=rec)
     head = results[forms[0]]
     n = x.shape[0]
     bpa = sum(BYTES_PER_ATOM_STEP[forms[0]].values())

@@ -56,6 +56,8 @@ extern "C" {
 /* what for misa_debug_export */
 #define MISA_EXPORT_STENCIL 0 /* int64 [2][K][3] lattice-id offsets (dX, dY, dZ) per parity; returns K */
 #define MISA_EXPORT_SLOTS 1   /* int64 [N] lattice id holding each atom, -1 for run-away atoms; returns N */
+#define MISA_EXPORT_NEIGHBOURS 2 /* int64 [N] per atom: partners within rc as the density pass of the
+                                    handle's form counts them (Sec. 2.2 step 1; table forms); returns N */
 
 typedef struct misa_lattice misa_lattice;
 
@@ -97,8 +99,8 @@ typedef struct {
     int64_t steps;      /* accumulated steps on this handle */
     int64_t n_runaway;  /* atoms outside the lattice array */
     int64_t range_violations; /* densities beyond the embedding table (linearly extrapolated) */
-    int32_t overflow;   /* 1 if the run-away capacity was exceeded (forces inexact since) */
-    int32_t reserved;
+    int32_t overflow;   /* 1 if a step's leavers exceeded the run-away capacity (misa_step: MISA_EOVERFLOW) */
+    int32_t failed_step; /* with overflow: index in the call (0-based) of that step; -1 otherwise */
 } misa_step_stats;
 
 /*
@@ -157,6 +159,23 @@ int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n_
  * to (n_atoms, 3) float64 arrays in host or device memory; either may be NULL. */
 int misa_get_state(misa_lattice *h, double *x, double *v, int where);
 
+/*
+ * Checkpoint and resume.  misa_save_checkpoint copies the handle's whole state
+ * (lattice slots with both copies of u and v, forces, densities, slot ids, the
+ * run-away list, the step counters, the time and the step length) and a
+ * description of the lattice into misa_checkpoint_bytes() bytes of host memory;
+ * misa_load_checkpoint puts it into a handle created with the same descriptor,
+ * bound to a state buffer and given the same potential tables (MISA_EINVAL
+ * otherwise).  Stepping on after a load is bit for bit what stepping on the saved
+ * handle would have given.  (misa_get_state / misa_set_state move atoms between
+ * boxes and representations: positions travel as absolute coordinates, so the
+ * site-relative displacements come back within rounding, not bit for bit.)
+ * Both synchronise the stream.
+ */
+int misa_checkpoint_bytes(const misa_lattice *h, int64_t *bytes);
+int misa_save_checkpoint(misa_lattice *h, void *host_out, int64_t bytes);
+int misa_load_checkpoint(misa_lattice *h, const void *host_in, int64_t bytes);
+
 /* Number of atoms loaded by the last misa_set_state. */
 int misa_atom_count(const misa_lattice *h, int64_t *n_atoms);
 
@@ -183,10 +202,18 @@ int misa_compute_force(misa_lattice *h, double *energies_dev);
  * Step length dt = min(dt_max, dx_max / max_i |v_i|) taken at the start of
  * each step; dx_max <= 0 fixes dt = dt_max.  Computes forces first if they
  * are not valid for the current state.  stats (host memory, may be NULL)
- * receives the statistics of the last step (synchronises the stream).
- * Returns MISA_EOVERFLOW (after finishing the steps) if the run-away capacity
- * was exceeded: atoms that could not leave their slots stayed, so forces on
- * them are inexact from then on.
+ * receives the statistics of the last step.  Synchronises the stream at the end.
+ * MISA_EOVERFLOW if a step's leavers (atoms farther than delta from their
+ * sites) do not fit in the run-away capacity: that step is undone and the call
+ * ends with the state (positions, velocities, slots, run-away atoms, forces,
+ * densities, time) exactly as at the start of the failing step; the later
+ * steps of the call ran without advancing it.  stats->failed_step says which
+ * step failed, stats->steps counts the steps completed.  The caller can read the
+ * state out and load it into a handle with a larger capacity.
+ *
+ * The bound state buffer holds two copies of the displacements and velocities:
+ * each step's kick-drift reads one and writes the other (misa_get_state and the
+ * other calls always see the current one).
  */
 int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, misa_step_stats *stats);
 
@@ -226,7 +253,13 @@ int misa_get_atom_field(misa_lattice *h, int field, double *out, int where);
 
 /* Parity and debugging exports to host memory (see MISA_EXPORT_*); capacity
  * counts int64 elements; the return value is the element count (K or N) or a
- * negative error code. */
+ * negative error code.  MISA_EXPORT_NEIGHBOURS runs the handle's own density pass
+ * (lattice gather, run-away atoms and their reaction terms) with f = 1 inside rc,
+ * so each count is the pair set that pass takes for the current state; it needs
+ * tables and state; afterwards the handle is as before (the tables are rebuilt,
+ * densities and F' computed again if they were valid, forces untouched); it
+ * synchronises the stream.
+ * MISA_EINVAL on a MISA_MLP handle. */
 int64_t misa_debug_export(misa_lattice *h, int what, int64_t *host_out, int64_t capacity);
 
 /* Pair schedule of the float32 table form (pair_precision MISA_FP32).

@@ -8,8 +8,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "misa_internal.h"
 
@@ -178,7 +181,7 @@ int upload_tables(misa_lattice *h, DevTables<Real> &D, const std::vector<SegCoef
 // ---------------------------------------------------------------------------
 // state layout inside the caller's buffer
 
-int64_t carve(misa_lattice *h, char *base, State *S) {
+int64_t carve(misa_lattice *h, char *base, State *S, UV *alt = nullptr) {
     const int64_t ns = h->g.nsites, rc = h->rcap;
     const int64_t rs = h->precision == MISA_FP32 ? 4 : 8;
     int64_t off = 0;
@@ -204,7 +207,15 @@ int64_t carve(misa_lattice *h, char *base, State *S) {
     double **rd[] = {&s.r_x, &s.r_y, &s.r_z, &s.r_vx, &s.r_vy, &s.r_vz, &s.r_fx, &s.r_fy, &s.r_fz, &s.r_rho, &s.r_fp};
     for (double **p : rd) *p = (double *)take(8 * rc);
     s.r_e = (double *)take(16 * rc);
+    UV a{};  // the second copy of u and v (the kick-drift writes one copy from the other)
+    a.ux = (double *)take(8 * ns);
+    a.uy = (double *)take(8 * ns);
+    a.uz = (double *)take(8 * ns);
+    a.vx = (double *)take(8 * ns);
+    a.vy = (double *)take(8 * ns);
+    a.vz = (double *)take(8 * ns);
     if (S) *S = s;
+    if (alt) *alt = a;
     return off;
 }
 
@@ -230,10 +241,15 @@ int check_ready(misa_lattice *h, bool need_tables) {
 
 hipError_t clear_marks(misa_lattice *h);
 
-// Records HIP events around one group of launches when timing is enabled.
+// Records HIP events around one group of launches when timing is enabled, and
+// marks the group as a roctx range (rocprofv3 --marker-trace shows the phases of
+// a step on the host timeline).
+const char *const PHASE_NAME[MISA_TIMER_COUNT] = {"misa:rho", "misa:force", "misa:kick", "misa:runaway",
+                                                  "misa:other"};
 class GroupTimer {
   public:
     GroupTimer(misa_lattice *h, int cls) : h_(h), cls_(cls) {
+        roctxRangePushA(PHASE_NAME[cls]);
         if (!h->timing) return;
         if (!h->event_pool.empty()) {
             ev_ = h->event_pool.back();
@@ -245,6 +261,7 @@ class GroupTimer {
         if (hipEventRecord(ev_.first, h->stream) != hipSuccess) ev_ = {nullptr, nullptr};
     }
     ~GroupTimer() {
+        roctxRangePop();
         if (!ev_.first) return;
         if (hipEventRecord(ev_.second, h_->stream) == hipSuccess)
             h_->timed.push_back({ev_.first, ev_.second, cls_});
@@ -329,6 +346,10 @@ int finish_force(misa_lattice *h) {
 // One MD step (Fig. 1 in kick-drift-kick form): the kernels of the rho and force
 // passes, the run-away path and the integrator, with no host synchronisation.
 int step_body(misa_lattice *h, bool last, bool fused, double dt_max, double dx_max) {
+    struct StepRange {
+        StepRange() { roctxRangePushA("misa:step"); }
+        ~StepRange() { roctxRangePop(); }
+    } range;
     int rc;
     {
         GroupTimer t(h, MISA_TIMER_KICK);
@@ -353,11 +374,14 @@ int step_body(misa_lattice *h, bool last, bool fused, double dt_max, double dx_m
     return MISA_OK;
 }
 
-// Capture one regular step into h->graph_exec.  The capture runs on a private
-// stream (the caller's may be the legacy default stream, which cannot capture);
-// the host-side flags a step updates end where they started.
+// Capture one regular step, starting from the current copy of u and v, into
+// h->graph_exec[h->parity] (a step ends on the other copy, so consecutive steps
+// replay the two graphs in turn).  The capture runs on a private stream (the
+// caller's may be the legacy default stream, which cannot capture); the host-side
+// flags a step updates, and the current copy, end where they started.
 int capture_step(misa_lattice *h, bool fused, double dt_max, double dx_max) {
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    const int par = h->parity;
     hipStream_t user = h->stream;
     h->stream = h->cap_stream;
     hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
@@ -366,17 +390,18 @@ int capture_step(misa_lattice *h, bool fused, double dt_max, double dx_max) {
     hipGraph_t graph = nullptr;
     const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(h->stream, &graph) : e;
     h->stream = user;
+    if (h->parity != par) swap_uv(h);  // nothing ran: the state is still on the copy it started from
     if (rc) {
         if (graph) (void)hipGraphDestroy(graph);
         return rc;
     }
     HIPCHK(h, e2);
-    e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&h->graph_exec[par], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) h->graph_exec = nullptr;
+    if (e != hipSuccess) h->graph_exec[par] = nullptr;
     HIPCHK(h, e);
-    h->graph_dt = dt_max;
-    h->graph_dx = dx_max;
+    h->graph_dt[par] = dt_max;
+    h->graph_dx[par] = dx_max;
     return MISA_OK;
 }
 
@@ -385,8 +410,10 @@ int capture_step(misa_lattice *h, bool fused, double dt_max, double dx_max) {
 // k_clear_marks lives here: it only zeroes mark words of listed sites.
 namespace misa {
 void drop_graph(misa_lattice *h) {
-    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
-    h->graph_exec = nullptr;
+    for (hipGraphExec_t &g : h->graph_exec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     ++h->gen;  // a batch's captured step that holds this box goes stale too
 }
 
@@ -518,6 +545,21 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     h->stencil_canon.resize(2 * h->K * 3);
     std::vector<StencilEntry<double>> s64(2 * KMAX), s64p(2 * KMAX);
     std::vector<StencilEntry<float>> s32(2 * KMAX), s32p(2 * KMAX);
+    NearTab ng{}, nh{};
+    ng.rc2 = nh.rc2 = d->rc * d->rc;
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < 64; ++k) ng.thr2[p][k] = nh.thr2[p][k] = -1.f;
+    auto near_thr = [&](const CanonOffset &o) {
+        const double t = 0.5 * (d->rc - std::sqrt(o.d2) - (double)NEAR_MARGIN);
+        return t > 0.0 ? (float)(t * t) : -1.f;
+    };
+    for (int p = 0; p < 2; ++p)  // |o_k| is the same for both parities
+        for (int k = 0; k < h->K && k < 64; ++k) ng.thr2[p][k] = near_thr(st[0][k]);
+    auto near_of = [&](const CanonOffset &o, int p) {
+        const int pn = ((p + o.dX) % 2 + 2) % 2;
+        return NearEntry{(int32_t)o.dX, (int32_t)o.dY, (int32_t)o.dZ, 0, o.dX * 0.5 * d->a,
+                         (o.dY + 0.5 * pn - 0.5 * p) * d->a, (o.dZ + 0.5 * pn - 0.5 * p) * d->a, 0.0};
+    };
     for (int p = 0; p < 2; ++p)
         for (int k = 0; k < h->K; ++k) {
             const CanonOffset &o = st[p][k];
@@ -536,6 +578,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
             const int lds2 = (pn - p) * P2Z * P2Y * P2X + (dcz * P2Y + dcy) * P2X + dcx;
             s32p[p * KMAX + k] = StencilEntry<float>{lds2, (float)ox, (float)oy, (float)oz};
             s64p[p * KMAX + k] = StencilEntry<double>{lds2, 0, ox, oy, oz};
+            ng.st[p][k] = near_of(o, p);
             int64_t *c = &h->stencil_canon[(p * h->K + k) * 3];
             c[0] = o.dX;
             c[1] = o.dY;
@@ -572,6 +615,8 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
             sh[p * KMAX + i] = StencilEntry<float>{lds, (float)(o.dX * 0.5 * d->a),
                                                    (float)((o.dY + 0.5 * pn - 0.5 * p) * d->a),
                                                    (float)((o.dZ + 0.5 * pn - 0.5 * p) * d->a)};
+            nh.st[p][i] = near_of(o, p);
+            if (i < 64) nh.thr2[p][i] = near_thr(o);
             if (o.d2 < d->rc * d->rc) ++m[8 + fw[i].first];
         }
         h->half_entries = std::max(h->half_entries, (int)m[HALF_PHASES]);
@@ -601,6 +646,8 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(h->st32p, 2 * KMAX);
     ALLOC(h->st64p, 2 * KMAX);
     ALLOC(h->sth, 2 * KMAX);
+    ALLOC(h->near_g, 1);
+    ALLOC(h->near_h, 1);
     ALLOC(h->hmeta, 2 * HALF_META);
     ALLOC(sc.cnt, 1);
     ALLOC(sc.scal, 8);
@@ -640,6 +687,8 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
         (e = hipMemcpy(h->st32p, s32p.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->st64p, s64p.data(), sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->sth, sh.data(), sizeof(StencilEntry<float>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(h->near_g, &ng, sizeof(NearTab), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(h->near_h, &nh, sizeof(NearTab), hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->hmeta, hmeta.data(), sizeof(int32_t) * 2 * HALF_META, hipMemcpyHostToDevice)) ||
         (e = hipMemset(sc.cnt, 0, sizeof(Counters))) || (e = hipMemset(sc.scal, 0, 8 * sizeof(double))) ||
         (e = hipMemset(sc.hkey, 0xff, sizeof(int32_t) * (size_t)H)) ||
@@ -664,7 +713,7 @@ int misa_destroy_lattice(misa_lattice *h) {
         (void)hipDeviceSynchronize();
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->lds64.nodes, h->sth, h->hmeta, h->lds32.f, h->lds32.force, h->lds32h.f,
+    void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->near_g, h->near_h, h->lds64.nodes, h->sth, h->hmeta, h->lds32.f, h->lds32.force, h->lds32h.f,
                     h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t64.force6, h->t32.force6, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
@@ -696,14 +745,34 @@ int misa_bind_state(misa_lattice *h, void *device_ptr, int64_t bytes) {
     if (((uintptr_t)device_ptr & 255u) != 0) return fail(h, MISA_EINVAL, "state buffer must be 256-byte aligned");
     h->state_ptr = device_ptr;
     h->state_bytes = bytes;
-    carve(h, (char *)device_ptr, &h->S);
+    carve(h, (char *)device_ptr, &h->S, &h->alt);
+    h->parity = 0;
     h->state_bound = true;
     drop_graph(h);
     h->state_set = h->rho_valid = h->force_valid = false;
     return MISA_OK;
 }
 
+namespace {
+int set_tables_impl(misa_lattice *h, const misa_table *f, const misa_table *phi, const misa_table *emb);
+}
+
 int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_table *phi, const misa_table *emb) {
+    const int rc = set_tables_impl(h, f, phi, emb);
+    if (rc) return rc;
+    const misa_table *t3[3] = {f, phi, emb};
+    for (int i = 0; i < 3; ++i) {
+        h->tab_y[i].assign(t3[i]->y, t3[i]->y + t3[i]->n);
+        h->tab[i] = *t3[i];
+        h->tab[i].y = h->tab_y[i].data();
+    }
+    return MISA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+int set_tables_impl(misa_lattice *h, const misa_table *f, const misa_table *phi, const misa_table *emb) {
     if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
     const misa_table *t3[3] = {f, phi, emb};
     for (const misa_table *t : t3) {
@@ -820,42 +889,22 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
     drop_graph(h);
     return MISA_OK;
 }
+}  // namespace
 
-int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n, int where) {
-    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
-    if (!h->state_bound) return fail(h, MISA_ESTATE, "no state buffer bound (misa_bind_state)");
-    if (n < 0 || n >= (int64_t)INT32_MAX) return fail(h, MISA_EINVAL, "atom count out of range");
-    if (n > 0 && (!x || !v)) return fail(h, MISA_EINVAL, "null positions or velocities");
-    if (where != MISA_HOST && where != MISA_DEVICE) return fail(h, MISA_EINVAL, "bad memory kind");
-    // Placement runs on the device (launch_place): host arrays are uploaded first.
-    // Temporary device memory: x, v (host input only), the bid of every atom and a flag.
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    h->state_set = false;  // until the new state is complete
-    h->rho_valid = h->force_valid = h->pending_clear = false;
-    const int64_t nn = std::max<int64_t>(n, 1);
-    const size_t xv_bytes = where == MISA_HOST ? 2 * sizeof(double) * 3 * (size_t)nn : 0;
-    const size_t bytes = xv_bytes + sizeof(int32_t) * (size_t)nn + 256;
-    char *tmp = nullptr;
-    HIPCHK(h, hipMalloc((void **)&tmp, bytes));
-    auto done = [&](int rc) {
-        (void)hipStreamSynchronize(h->stream);
-        (void)hipFree(tmp);
-        return rc;
-    };
-    const double *xd = x, *vd = v;
-    if (where == MISA_HOST && n > 0) {
-        double *xs = (double *)tmp, *vs = xs + 3 * nn;
-        hipError_t e = hipMemcpy(xs, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(vs, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice);
-        if (e != hipSuccess) return done(fail(h, MISA_EHIP, std::string("upload: ") + hipGetErrorString(e)));
-        xd = xs;
-        vd = vs;
-    }
-    int32_t *cand = (int32_t *)(tmp + xv_bytes);
-    uint32_t *bad = (uint32_t *)(tmp + xv_bytes + sizeof(int32_t) * (size_t)nn);
+extern "C" {
+
+}  // extern "C"
+
+namespace {
+// Placement of n atoms from device arrays xd, vd: cand (n bids) and bad (one
+// counter) are device scratch the caller provides; done(rc) releases whatever
+// the caller allocated and returns rc.
+template <class Done>
+int place_atoms(misa_lattice *h, const double *xd, const double *vd, int64_t n, int32_t *cand, uint32_t *bad,
+                Done done) {
     Counters c{};
     hipError_t e = hipMemcpy(h->sc.cnt, &c, sizeof(c), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(bad, 0, sizeof(uint32_t));
+    if (e == hipSuccess) e = launch_fill_u32(h, bad, 0u, 1);
     if (e == hipSuccess) e = launch_place(h, xd, vd, n, cand, bad);
     uint32_t nbad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&c, h->sc.cnt, sizeof(c), hipMemcpyDeviceToHost, h->stream);
@@ -886,6 +935,160 @@ int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n,
     h->steps_done = 0;
     h->state_set = true;
     return done(MISA_OK);
+}
+
+int check_set_state(misa_lattice *h, const double *x, const double *v, int64_t n) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    if (!h->state_bound) return fail(h, MISA_ESTATE, "no state buffer bound (misa_bind_state)");
+    if (n < 0 || n >= (int64_t)INT32_MAX) return fail(h, MISA_EINVAL, "atom count out of range");
+    if (n > 0 && (!x || !v)) return fail(h, MISA_EINVAL, "null positions or velocities");
+    return MISA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n, int where) {
+    int rc = check_set_state(h, x, v, n);
+    if (rc) return rc;
+    if (where != MISA_HOST && where != MISA_DEVICE) return fail(h, MISA_EINVAL, "bad memory kind");
+    // Placement runs on the device (launch_place): host arrays are uploaded first.
+    // Temporary device memory: x, v (host input only), the bid of every atom and a flag.
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->state_set = false;  // until the new state is complete
+    h->rho_valid = h->force_valid = h->pending_clear = false;
+    const int64_t nn = std::max<int64_t>(n, 1);
+    const size_t xv_bytes = where == MISA_HOST ? 2 * sizeof(double) * 3 * (size_t)nn : 0;
+    const size_t bytes = xv_bytes + sizeof(int32_t) * (size_t)nn + 256;
+    char *tmp = nullptr;
+    HIPCHK(h, hipMalloc((void **)&tmp, bytes));
+    auto done = [&](int rc) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(tmp);
+        return rc;
+    };
+    const double *xd = x, *vd = v;
+    if (where == MISA_HOST && n > 0) {
+        double *xs = (double *)tmp, *vs = xs + 3 * nn;
+        hipError_t e = hipMemcpy(xs, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(vs, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return done(fail(h, MISA_EHIP, std::string("upload: ") + hipGetErrorString(e)));
+        xd = xs;
+        vd = vs;
+    }
+    int32_t *cand = (int32_t *)(tmp + xv_bytes);
+    uint32_t *bad = (uint32_t *)(tmp + xv_bytes + sizeof(int32_t) * (size_t)nn);
+    return place_atoms(h, xd, vd, n, cand, bad, done);
+}
+
+}  // extern "C"
+
+namespace {
+// Checkpoint blob: this header, then the whole bound state buffer (both copies of u
+// and v, forces, densities, slots and the run-away list) as the handle holds it.
+struct CkptHeader {
+    char magic[8];  // "MISACKP1"
+    int32_t precision, use_mlp;
+    int32_t n_cells[3], parity;
+    double a, rc, delta2, mass;
+    int64_t rcap, n_atoms, steps_done, state_bytes;
+    uint64_t tables_hash;
+    int32_t rho_valid, force_valid;
+    Counters cnt;
+    double scal[8];
+};
+constexpr char CKPT_MAGIC[8] = {'M', 'I', 'S', 'A', 'C', 'K', 'P', '1'};
+
+// FNV-1a over the three sampled tables (grids and samples) of the last misa_set_potential_tables.
+uint64_t tables_hash(const misa_lattice *h) {
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *c = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) x = (x ^ c[i]) * 1099511628211ull;
+    };
+    for (int i = 0; i < 3; ++i) {
+        mix(&h->tab[i].x0, sizeof(double));
+        mix(&h->tab[i].dx, sizeof(double));
+        mix(h->tab_y[i].data(), sizeof(double) * h->tab_y[i].size());
+    }
+    return x;
+}
+}  // namespace
+
+extern "C" {
+
+int misa_checkpoint_bytes(const misa_lattice *h, int64_t *bytes) {
+    if (!h || !bytes) return fail(nullptr, MISA_EINVAL, "null argument");
+    *bytes = (int64_t)sizeof(CkptHeader) + carve(const_cast<misa_lattice *>(h), nullptr, nullptr);
+    return MISA_OK;
+}
+
+int misa_save_checkpoint(misa_lattice *h, void *host_out, int64_t bytes) {
+    int rc = check_ready(h, true);
+    if (rc) return rc;
+    const int64_t sb = carve(h, nullptr, nullptr);
+    if (!host_out || bytes < (int64_t)sizeof(CkptHeader) + sb)
+        return fail(h, MISA_EINVAL, "checkpoint buffer missing or smaller than misa_checkpoint_bytes");
+    CkptHeader hd{};
+    std::memcpy(hd.magic, CKPT_MAGIC, 8);
+    hd.precision = h->precision;
+    hd.use_mlp = h->use_mlp;
+    hd.n_cells[0] = h->g.nx;
+    hd.n_cells[1] = h->g.ny;
+    hd.n_cells[2] = h->g.nz;
+    hd.parity = h->parity;
+    hd.a = h->g.a;
+    hd.rc = h->g.rc;
+    hd.delta2 = h->g.delta2;
+    hd.mass = h->mass;
+    hd.rcap = h->rcap;
+    hd.n_atoms = h->n_atoms;
+    hd.steps_done = h->steps_done;
+    hd.state_bytes = sb;
+    hd.tables_hash = tables_hash(h);
+    hd.rho_valid = h->rho_valid && !h->pending_clear;  // densities of a finished pass
+    hd.force_valid = h->force_valid && !h->pending_clear;
+    HIPCHK(h, hipMemcpyAsync(&hd.cnt, h->sc.cnt, sizeof(Counters), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(hd.scal, h->sc.scal, sizeof(hd.scal), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync((char *)host_out + sizeof(CkptHeader), h->state_ptr, (size_t)sb, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    std::memcpy(host_out, &hd, sizeof(hd));
+    return MISA_OK;
+}
+
+int misa_load_checkpoint(misa_lattice *h, const void *host_in, int64_t bytes) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    if (!h->state_bound) return fail(h, MISA_ESTATE, "no state buffer bound (misa_bind_state)");
+    if (!h->tables_set) return fail(h, MISA_ESTATE, "no potential tables (misa_set_potential_tables)");
+    if (!host_in || bytes < (int64_t)sizeof(CkptHeader)) return fail(h, MISA_EINVAL, "checkpoint too short");
+    CkptHeader hd;
+    std::memcpy(&hd, host_in, sizeof(hd));
+    const int64_t sb = carve(h, nullptr, nullptr);
+    if (std::memcmp(hd.magic, CKPT_MAGIC, 8) != 0) return fail(h, MISA_EINVAL, "not a checkpoint of this library");
+    if (hd.precision != h->precision || hd.use_mlp != (int)h->use_mlp || hd.n_cells[0] != h->g.nx ||
+        hd.n_cells[1] != h->g.ny || hd.n_cells[2] != h->g.nz || hd.a != h->g.a || hd.rc != h->g.rc ||
+        hd.delta2 != h->g.delta2 || hd.mass != h->mass || hd.rcap != h->rcap || hd.state_bytes != sb)
+        return fail(h, MISA_EINVAL, "checkpoint of another lattice (box, a, rc, delta, mass, capacity or precision)");
+    if (bytes < (int64_t)sizeof(CkptHeader) + sb) return fail(h, MISA_EINVAL, "checkpoint too short");
+    if (hd.tables_hash != tables_hash(h))
+        return fail(h, MISA_EINVAL, "checkpoint taken with other potential tables");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(h->state_ptr, (const char *)host_in + sizeof(CkptHeader), (size_t)sb, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->sc.cnt, &hd.cnt, sizeof(Counters), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->sc.scal, hd.scal, sizeof(hd.scal), hipMemcpyHostToDevice));
+    // run-away hash and near-run-away marks empty, as after any finished pass
+    HIPCHK(h, hipMemset(h->sc.mark, 0, sizeof(uint32_t) * (size_t)h->sc.mark_nwords));
+    HIPCHK(h, hipMemset(h->sc.hkey, 0xff, sizeof(int32_t) * (size_t)(h->sc.hmask + 1)));
+    if (h->parity != hd.parity) swap_uv(h);
+    drop_graph(h);
+    h->n_atoms = hd.n_atoms;
+    h->steps_done = hd.steps_done;
+    h->state_set = true;
+    h->rho_valid = hd.rho_valid != 0;
+    h->force_valid = hd.force_valid != 0;
+    h->pending_clear = false;
+    return MISA_OK;
 }
 
 int misa_atom_count(const misa_lattice *h, int64_t *n_atoms) {
@@ -964,35 +1167,54 @@ int misa_step(misa_lattice *h, int64_t nsteps, double dt_max, double dx_max, mis
     int64_t s = 0;
     if (h->use_graph && !h->timing && nsteps >= 2) {
         // every step but the last issues the same kernels with the same arguments (dt
-        // lives on the device): replay one captured step
-        if (!h->graph_exec || h->graph_dt != dt_max || h->graph_dx != dx_max) {
-            drop_graph(h);
-            if ((rc = capture_step(h, fused, dt_max, dx_max))) return rc;
+        // lives on the device), but on alternating copies of u and v: replay the two
+        // captured steps in turn
+        for (; s < nsteps - 1; ++s) {
+            const int par = h->parity;
+            if (!h->graph_exec[par] || h->graph_dt[par] != dt_max || h->graph_dx[par] != dx_max) {
+                if (h->graph_exec[par]) (void)hipGraphExecDestroy(h->graph_exec[par]);
+                h->graph_exec[par] = nullptr;
+                if ((rc = capture_step(h, fused, dt_max, dx_max))) return rc;
+            }
+            HIPCHK(h, hipGraphLaunch(h->graph_exec[par], h->stream));
+            swap_uv(h);
         }
-        for (; s < nsteps - 1; ++s) HIPCHK(h, hipGraphLaunch(h->graph_exec, h->stream));
     }
     for (; s < nsteps; ++s)
         if ((rc = step_body(h, s == nsteps - 1, fused, dt_max, dx_max))) return rc;
-    h->steps_done += nsteps;
-    if (!stats) return MISA_OK;
     double scal[8];
     Counters c;
-    HIPCHK(h, hipMemcpyAsync(scal, h->sc.scal, sizeof(scal), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(&c, h->sc.cnt, sizeof(c), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    std::memset(stats, 0, sizeof(*stats));
-    stats->dt_next = scal[0];
-    stats->time = scal[1];
-    stats->vmax = scal[2];
-    stats->e_kin = scal[3];
-    stats->e_emb = nsteps > 0 ? scal[4] : 0.0;
-    stats->e_pair = nsteps > 0 ? scal[5] : 0.0;
-    stats->steps = h->steps_done;
-    stats->n_runaway = c.n_run;
-    stats->range_violations = c.range_viol;
-    stats->overflow = c.overflow;
-    stats->dt = scal[6];
-    if (c.overflow) return fail(h, MISA_EOVERFLOW, "run-away capacity exceeded; forces inexact since");
+    if (c.overflow && nsteps > 0) {
+        // The failing step was undone and every later step of the call left the state
+        // where it was (dt = 0); the densities, forces and energies of the last of them
+        // belong to that state.  Take the step length of the state and clear the flag.
+        h->steps_done += c.fail_step;
+        HIPCHK(h, launch_dt_update(h, dt_max, dx_max, true));
+    } else {
+        h->steps_done += nsteps;
+    }
+    if (stats) {
+        HIPCHK(h, hipMemcpyAsync(scal, h->sc.scal, sizeof(scal), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        std::memset(stats, 0, sizeof(*stats));
+        stats->dt_next = scal[0];
+        stats->time = scal[1];
+        stats->vmax = scal[2];
+        stats->e_kin = scal[3];
+        stats->e_emb = nsteps > 0 ? scal[4] : 0.0;
+        stats->e_pair = nsteps > 0 ? scal[5] : 0.0;
+        stats->steps = h->steps_done;
+        stats->n_runaway = c.n_run;
+        stats->range_violations = c.range_viol;
+        stats->overflow = c.overflow ? 1 : 0;
+        stats->failed_step = c.overflow ? c.fail_step : -1;
+        stats->dt = scal[6];
+    }
+    if (c.overflow && nsteps > 0)
+        return fail(h, MISA_EOVERFLOW, "run-away capacity exceeded at step " + std::to_string(c.fail_step) +
+                                           " of the call; the state is left at the start of that step");
     return MISA_OK;
 }
 
@@ -1005,6 +1227,9 @@ struct misa_batch {
     hipStream_t stream = nullptr;
     std::vector<misa_lattice *> box;
     std::string err;
+    // box tables, two sets of n_boxes: set 0 with each box's current copy of u and v,
+    // set 1 with the copies swapped; a step starts on one set and its kick-drift
+    // hands over to the other
     std::vector<BoxRef> ref;
     std::vector<BoxPass> pass;
     std::vector<int2> items;
@@ -1018,7 +1243,7 @@ struct misa_batch {
     // graph of one regular batched step (misa_batch_set_graph), valid for graph_key
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // a step starting on table set 0 / 1
     std::vector<uint64_t> graph_key;
 };
 
@@ -1042,8 +1267,8 @@ int bfail(misa_batch *b, int code, const std::string &msg) {
 // Box tables and the (box, tile) work list of the persistent passes, in box order.
 int batch_tables(misa_batch *b) {
     const int nb = (int)b->box.size();
-    b->ref.resize(nb);
-    b->pass.resize(nb);
+    b->ref.resize(2 * nb);
+    b->pass.resize(2 * nb);
     b->items.clear();
     for (int k = 0; k < nb; ++k) {
         misa_lattice *h = b->box[k];
@@ -1059,8 +1284,12 @@ int batch_tables(misa_batch *b) {
         g.nt2[2] = (g.nz + g.tshape[2] - 1) / g.tshape[2];
         g.ntiles2 = g.nt2[0] * g.nt2[1] * g.nt2[2];
         g.ntiles2_pad = (g.ntiles2 + 7) / 8 * 8;
-        b->ref[k] = BoxRef{h->S, h->sc, g, h->rcap};
+        b->ref[k] = BoxRef{h->S, h->sc, g, h->rcap, h->alt};
         b->pass[k] = BoxPass{g, pass_ptrs(h), sh, 0};
+        swap_uv(h);
+        b->ref[nb + k] = BoxRef{h->S, h->sc, g, h->rcap, h->alt};
+        b->pass[nb + k] = BoxPass{g, pass_ptrs(h), sh, 0};
+        swap_uv(h);
         for (int t = 0; t < g.ntiles2; ++t) b->items.push_back(int2{k, t});
     }
     if (nb > b->cap_boxes) {
@@ -1071,8 +1300,8 @@ int batch_tables(misa_batch *b) {
         b->d_pass = nullptr;
         b->d_off = nullptr;
         b->cap_boxes = 0;
-        BCHK(b, hipMalloc((void **)&b->d_ref, sizeof(BoxRef) * nb));
-        BCHK(b, hipMalloc((void **)&b->d_pass, sizeof(BoxPass) * nb));
+        BCHK(b, hipMalloc((void **)&b->d_ref, sizeof(BoxRef) * 2 * nb));
+        BCHK(b, hipMalloc((void **)&b->d_pass, sizeof(BoxPass) * 2 * nb));
         BCHK(b, hipMalloc((void **)&b->d_off, sizeof(int32_t) * 2 * (nb + 1)));
         b->cap_boxes = nb;
     }
@@ -1084,8 +1313,8 @@ int batch_tables(misa_batch *b) {
         BCHK(b, hipMalloc((void **)&b->d_items, sizeof(int2) * b->items.size()));
         b->cap_items = (int64_t)b->items.size();
     }
-    BCHK(b, hipMemcpyAsync(b->d_ref, b->ref.data(), sizeof(BoxRef) * nb, hipMemcpyHostToDevice, b->stream));
-    BCHK(b, hipMemcpyAsync(b->d_pass, b->pass.data(), sizeof(BoxPass) * nb, hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipMemcpyAsync(b->d_ref, b->ref.data(), sizeof(BoxRef) * 2 * nb, hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipMemcpyAsync(b->d_pass, b->pass.data(), sizeof(BoxPass) * 2 * nb, hipMemcpyHostToDevice, b->stream));
     BCHK(b, hipMemcpyAsync(b->d_items, b->items.data(), sizeof(int2) * b->items.size(), hipMemcpyHostToDevice,
                            b->stream));
     BCHK(b, hipStreamSynchronize(b->stream));  // the host tables may change on the next call
@@ -1175,7 +1404,8 @@ int misa_batch_destroy(misa_batch *b) {
     (void)hipFree(b->d_items);
     (void)hipFree(b->d_off);
     (void)hipFree(b->d_st);
-    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    for (hipGraphExec_t g : b->graph_exec)
+        if (g) (void)hipGraphExecDestroy(g);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return MISA_OK;
@@ -1242,49 +1472,52 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
     // One batched step on stream sq (box 0's stream field follows it, since the
     // persistent passes launch on h0->stream).  Kernel timing of the batch, when
     // enabled, accumulates on box 0's timers.
-    auto step_body = [&](bool last, hipStream_t sq) -> int {
+    // set: the table set the step starts on; after the kick-drift every kernel reads the other
+    auto step_body = [&](bool last, hipStream_t sq, int set) -> int {
         const hipStream_t st = sq;
         h0->stream = sq;
+        const BoxRef *ref0 = b->d_ref + (int64_t)set * nb, *ref = b->d_ref + (int64_t)(set ^ 1) * nb;
+        const BoxPass *pass = b->d_pass + (int64_t)(set ^ 1) * nb;
         {
             GroupTimer t(h0, MISA_TIMER_KICK);
-            BCHK(b, launchb_kick_drift(st, b->d_ref, nb, gx_sites, gx_small, kf));
+            BCHK(b, launchb_kick_drift(st, ref0, ref, nb, gx_sites, gx_small, kf));
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
-            BCHK(b, launchb_rehash(st, b->d_ref, nb, gx_small));
-            BCHK(b, launchb_runaway_build(st, b->d_ref, nb, gx_small));
+            BCHK(b, launchb_rehash(st, ref, nb, gx_small));
+            BCHK(b, launchb_runaway_build(st, ref, nb, gx_small));
         }
         {
             GroupTimer t(h0, MISA_TIMER_RHO);
-            BCHK(b, launch_rho_lds_batch(h0, b->d_pass, b->d_items, nitems, b->d_st, any_shape));
+            BCHK(b, launch_rho_lds_batch(h0, pass, b->d_items, nitems, b->d_st, any_shape));
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
-            BCHK(b, launchb_runaway_rho(h0, b->d_ref, nb, max_mark, b->d_off));
+            BCHK(b, launchb_runaway_rho(h0, ref, nb, max_mark, b->d_off));
         }
         {
             GroupTimer t(h0, MISA_TIMER_FORCE);
-            BCHK(b, launch_force_lds_batch(h0, b->d_pass, b->d_items, nitems, last, true, b->d_st, any_shape));
+            BCHK(b, launch_force_lds_batch(h0, pass, b->d_items, nitems, last, true, b->d_st, any_shape));
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
-            BCHK(b, launchb_runaway_force(h0, b->d_ref, nb, last, b->d_off));
+            BCHK(b, launchb_runaway_force(h0, ref, nb, last, b->d_off));
         }
         {
             GroupTimer t(h0, MISA_TIMER_OTHER);
-            if (last) BCHK(b, launchb_energy_reduce(st, b->d_ref, nb));
+            if (last) BCHK(b, launchb_energy_reduce(st, ref, nb));
         }
         {
             GroupTimer t(h0, MISA_TIMER_KICK);
-            BCHK(b, launchb_final_kick_runaway(st, b->d_ref, nb, gx_small, kf));
+            BCHK(b, launchb_final_kick_runaway(st, ref, nb, gx_small, kf));
         }
         {
             GroupTimer t(h0, MISA_TIMER_OTHER);
-            BCHK(b, launchb_dt_update(st, b->d_ref, nb, h0->mass, dt_max, dx_max));
+            BCHK(b, launchb_dt_update(st, ref, nb, h0->mass, dt_max, dx_max));
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
-            BCHK(b, launchb_runaway_clear(st, b->d_ref, nb, gx_small));
+            BCHK(b, launchb_runaway_clear(st, ref, nb, gx_small));
         }
         if (h0->timed.size() > 50000) BCHK(b, fold_timing(h0));
         h0->stream = b->stream;
@@ -1302,46 +1535,59 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         std::memcpy(&bits, &dx_max, 8);
         key.push_back(bits);
         for (misa_lattice *h : b->box) key.push_back(h->gen);
-        if (!b->graph_exec || key != b->graph_key) {
-            if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
-            b->graph_exec = nullptr;
+        if (!b->graph_exec[0] || !b->graph_exec[1] || key != b->graph_key) {
             BCHK(b, hipStreamSynchronize(b->stream));
-            hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-            int brc = MISA_OK;
-            if (e == hipSuccess) brc = step_body(false, b->cap_stream);
-            h0->stream = b->stream;
-            hipGraph_t graph = nullptr;
-            const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(b->cap_stream, &graph) : e;
-            if (brc) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return brc;
+            for (int set = 0; set < 2; ++set) {
+                if (b->graph_exec[set]) (void)hipGraphExecDestroy(b->graph_exec[set]);
+                b->graph_exec[set] = nullptr;
+                hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+                int brc = MISA_OK;
+                if (e == hipSuccess) brc = step_body(false, b->cap_stream, set);
+                h0->stream = b->stream;
+                hipGraph_t graph = nullptr;
+                const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(b->cap_stream, &graph) : e;
+                if (brc) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return brc;
+                }
+                BCHK(b, e2);
+                e = hipGraphInstantiate(&b->graph_exec[set], graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) b->graph_exec[set] = nullptr;
+                BCHK(b, e);
             }
-            BCHK(b, e2);
-            e = hipGraphInstantiate(&b->graph_exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) b->graph_exec = nullptr;
-            BCHK(b, e);
             b->graph_key = key;
         }
-        for (; s < nsteps - 1; ++s) BCHK(b, hipGraphLaunch(b->graph_exec, b->stream));
+        for (; s < nsteps - 1; ++s) BCHK(b, hipGraphLaunch(b->graph_exec[s & 1], b->stream));
     }
     for (; s < nsteps; ++s)
-        if ((rc = step_body(s == nsteps - 1, b->stream))) return rc;
+        if ((rc = step_body(s == nsteps - 1, b->stream, (int)(s & 1)))) return rc;
     std::vector<double> scal(8 * (size_t)nb);
     std::vector<Counters> cnt(nb);
     for (int k = 0; k < nb; ++k) {
         misa_lattice *h = b->box[k];
-        h->steps_done += nsteps;
+        if (nsteps & 1) swap_uv(h);  // the host view follows the copy the last step wrote
         h->rho_valid = h->force_valid = true;
         h->pending_clear = false;
-        if (stats) {
-            BCHK(b, hipMemcpyAsync(&scal[8 * k], h->sc.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-            BCHK(b, hipMemcpyAsync(&cnt[k], h->sc.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
-        }
+        BCHK(b, hipMemcpyAsync(&cnt[k], h->sc.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
     }
     BCHK(b, hipStreamSynchronize(st));
-    if (!stats) return MISA_OK;
     int worst = MISA_OK;
+    for (int k = 0; k < nb; ++k) {
+        misa_lattice *h = b->box[k];
+        if (cnt[k].overflow && nsteps > 0) {  // box k stopped at the start of its failing step
+            h->steps_done += cnt[k].fail_step;
+            BCHK(b, launch_dt_update(h, dt_max, dx_max, true));
+            worst = bfail(b, MISA_EOVERFLOW, "box " + std::to_string(k) + ": run-away capacity exceeded at step " +
+                                                 std::to_string(cnt[k].fail_step) +
+                                                 " of the call; the box is left at the start of that step");
+        } else {
+            h->steps_done += nsteps;
+        }
+        if (stats) BCHK(b, hipMemcpyAsync(&scal[8 * k], h->sc.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    BCHK(b, hipStreamSynchronize(st));
+    if (!stats) return worst;
     for (int k = 0; k < nb; ++k) {
         misa_step_stats &o = stats[k];
         const double *sc = &scal[8 * k];
@@ -1355,9 +1601,9 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         o.steps = b->box[k]->steps_done;
         o.n_runaway = cnt[k].n_run;
         o.range_violations = cnt[k].range_viol;
-        o.overflow = cnt[k].overflow;
+        o.overflow = cnt[k].overflow ? 1 : 0;
+        o.failed_step = cnt[k].overflow ? cnt[k].fail_step : -1;
         o.dt = sc[6];
-        if (cnt[k].overflow) worst = bfail(b, MISA_EOVERFLOW, "box " + std::to_string(k) + ": run-away capacity exceeded");
     }
     return worst;
 }
@@ -1365,10 +1611,11 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
 int misa_batch_set_graph(misa_batch *b, int enable) {
     if (!b) return MISA_EINVAL;
     if (enable && !b->cap_stream) BCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-    if (!enable && b->graph_exec) {
-        (void)hipGraphExecDestroy(b->graph_exec);
-        b->graph_exec = nullptr;
-    }
+    if (!enable)
+        for (hipGraphExec_t &g : b->graph_exec) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     b->use_graph = enable != 0;
     return MISA_OK;
 }
@@ -1526,6 +1773,49 @@ int64_t misa_debug_export(misa_lattice *h, int what, int64_t *host_out, int64_t 
         HIPCHK(h, launch_gather_slots(h, (int64_t *)h->staging));
         HIPCHK(h, hipMemcpyAsync(host_out, h->staging, sizeof(int64_t) * n, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
+        return n;
+    }
+    if (what == MISA_EXPORT_NEIGHBOURS) {
+        int rc = check_ready(h, true);
+        if (rc) return rc;
+        if (h->use_mlp) return fail(h, MISA_EINVAL, "neighbour counts: table forms only (the learned form's f is a network)");
+        const int64_t n = h->n_atoms;
+        if (n == 0 || !host_out) return n;
+        if (capacity < n) return fail(h, MISA_EINVAL, "capacity smaller than the atom count");
+        // The density pass of the handle's own form with f = 1 inside rc counts every
+        // pair it takes, run-away pairs included.  Afterwards the tables and counters
+        // are restored and, if they were valid, the densities and F' recomputed (the
+        // forces are not touched).
+        const bool rho_was = h->rho_valid, force_was = h->force_valid;
+        Counters c0;
+        HIPCHK(h, hipMemcpyAsync(&c0, h->sc.cnt, sizeof(c0), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        const std::vector<double> ones(h->tab_y[0].size(), 1.0);
+        misa_table unit = h->tab[0];
+        unit.y = ones.data();
+        rc = set_tables_impl(h, &unit, &h->tab[1], &h->tab[2]);
+        if (!rc) rc = do_rho(h);
+        std::vector<double> cnt(rc ? 0 : n);
+        if (!rc) {
+            HIPCHK(h, ensure_staging(h, sizeof(double) * n));
+            HIPCHK(h, launch_gather_field(h, MISA_FIELD_RHO, h->staging));
+            HIPCHK(h, hipMemcpyAsync(cnt.data(), h->staging, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+        }
+        const int rc2 = set_tables_impl(h, &h->tab[0], &h->tab[1], &h->tab[2]);
+        if (rc) return rc;
+        if (rc2) return rc2;
+        HIPCHK(h, hipMemcpyAsync(h->sc.cnt, &c0, sizeof(c0), hipMemcpyHostToDevice, h->stream));
+        if (rho_was) {
+            if ((rc = do_rho(h))) return rc;
+            h->force_valid = force_was;
+            if (force_was && (rc = finish_force(h))) return rc;  // as after a force pass: marks cleared
+        }
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (int64_t i = 0; i < n; ++i) {
+            host_out[i] = (int64_t)std::llround(cnt[i]);
+            if ((double)host_out[i] != cnt[i]) return fail(h, MISA_EHIP, "neighbour count not integral");
+        }
         return n;
     }
     return fail(h, MISA_EINVAL, "unknown export");

@@ -21,10 +21,13 @@ __device__ __forceinline__ double wave_max_i(double v) {
     return v;
 }
 
-// v += (dt/2) C F / m;  u += dt v;  an atom now farther than delta from its
-// site is appended to this step's leavers and its slot emptied.
+// v += (dt/2) C F / m;  u += dt v, from the current copy of u, v into the other
+// (dst); an atom now farther than delta from its site is appended to this step's
+// leavers and its slot emptied.  A leaver beyond the run-away capacity raises the
+// overflow flag, and the run-away kick-drift that follows undoes the step.
 template <typename Real>
-__device__ __forceinline__ void kick_drift_body(State S, Scratch sc, Geom g, double kf, int64_t rcap) {
+__device__ __forceinline__ void kick_drift_body(State S, UV dst, Scratch sc, Geom g, double kf, int64_t rcap) {
+    if (sc.cnt->overflow) return;  // frozen after an overflow: both copies hold the state
     const double dt = sc.scal[0];
     const double hk = 0.5 * dt * kf;
     const int64_t room = rcap - sc.cnt->n_run;
@@ -59,39 +62,64 @@ __device__ __forceinline__ void kick_drift_body(State S, Scratch sc, Geom g, dou
                 sc.l_vx[slot] = vx;
                 sc.l_vy[slot] = vy;
                 sc.l_vz[slot] = vz;
-                S.ux[s] = VACANT_U;
-                S.uy[s] = VACANT_U;
-                S.uz[s] = VACANT_U;
-                S.vx[s] = 0.0;
-                S.vy[s] = 0.0;
-                S.vz[s] = 0.0;
+                dst.ux[s] = VACANT_U;
+                dst.uy[s] = VACANT_U;
+                dst.uz[s] = VACANT_U;
+                dst.vx[s] = 0.0;
+                dst.vy[s] = 0.0;
+                dst.vz[s] = 0.0;
                 S.atom[s] = VACANT_ID;
                 continue;
             }
-            atomicExch(&sc.cnt->overflow, 1);  // stays in its slot; forces on it become inexact
+            atomicExch(&sc.cnt->overflow, 1);  // the step is undone before anything else reads it
         }
-        S.ux[s] = ux;
-        S.uy[s] = uy;
-        S.uz[s] = uz;
-        S.vx[s] = vx;
-        S.vy[s] = vy;
-        S.vz[s] = vz;
+        dst.ux[s] = ux;
+        dst.uy[s] = uy;
+        dst.uz[s] = uz;
+        dst.vx[s] = vx;
+        dst.vy[s] = vy;
+        dst.vz[s] = vz;
     }
 }
 
 template <typename Real>
-__global__ __launch_bounds__(KICK_THREADS) void k_kick_drift(State S, Scratch sc, Geom g, double kf, int64_t rcap) {
-    kick_drift_body<Real>(S, sc, g, kf, rcap);
+__global__ __launch_bounds__(KICK_THREADS) void k_kick_drift(State S, UV dst, Scratch sc, Geom g, double kf,
+                                                             int64_t rcap) {
+    kick_drift_body<Real>(S, dst, sc, g, kf, rcap);
 }
 
 template <typename Real>
 __global__ __launch_bounds__(KICK_THREADS) void kb_kick_drift(const BoxRef *__restrict__ boxes, double kf) {
     const BoxRef &B = boxes[blockIdx.y];
-    kick_drift_body<Real>(B.S, B.sc, B.g, kf, B.rcap);
+    kick_drift_body<Real>(B.S, B.alt, B.sc, B.g, kf, B.rcap);
 }
 
 
-__device__ __forceinline__ void kick_drift_runaway_body(State S, Scratch sc, Geom g, double kf) {
+// Run-away atoms: the same kick-drift, in place.  S is the copy the lattice
+// kick-drift just wrote, prev the one it read.  After an overflow in that kick-drift
+// this undoes the step instead: u, v of every site back from prev, the slots of the
+// admitted leavers back to their atoms, and the run-away atoms stay where they were
+// (the leaver count is cleared and dt set to zero by the leaver sort that follows).
+__device__ __forceinline__ void kick_drift_runaway_body(State S, UV prev, Scratch sc, Geom g, double kf,
+                                                        int64_t rcap) {
+    const int ov = sc.cnt->overflow;
+    if (ov == 1) {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.nsites; s += stride) {
+            S.ux[s] = prev.ux[s];
+            S.uy[s] = prev.uy[s];
+            S.uz[s] = prev.uz[s];
+            S.vx[s] = prev.vx[s];
+            S.vy[s] = prev.vy[s];
+            S.vz[s] = prev.vz[s];
+        }
+        const int64_t room = rcap - sc.cnt->n_run;
+        const int64_t nl = sc.cnt->n_leave < room ? sc.cnt->n_leave : room;
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nl; q += stride)
+            S.atom[sc.l_site[q]] = sc.l_id[q];
+        return;
+    }
+    if (ov) return;  // frozen
     const double dt = sc.scal[0];
     const double hk = 0.5 * dt * kf;
     const int n = sc.cnt->n_run;
@@ -108,13 +136,14 @@ __device__ __forceinline__ void kick_drift_runaway_body(State S, Scratch sc, Geo
     }
 }
 
-__global__ void k_kick_drift_runaway(State S, Scratch sc, Geom g, double kf) {
-    kick_drift_runaway_body(S, sc, g, kf);
+__global__ void k_kick_drift_runaway(State S, UV prev, Scratch sc, Geom g, double kf, int64_t rcap) {
+    kick_drift_runaway_body(S, prev, sc, g, kf, rcap);
 }
 
+// boxes: the box table after the swap (S the copy just written, alt the one read)
 __global__ void kb_kick_drift_runaway(const BoxRef *__restrict__ boxes, double kf) {
     const BoxRef &B = boxes[blockIdx.y];
-    kick_drift_runaway_body(B.S, B.sc, B.g, kf);
+    kick_drift_runaway_body(B.S, B.alt, B.sc, B.g, kf, B.rcap);
 }
 
 
@@ -193,6 +222,7 @@ __device__ __forceinline__ void dt_update_body(State S, Scratch sc, const double
                                                     int use_aff, double mass, double dt_max, double dx_max,
                                                     int first) {
     __shared__ double red[2][1024 / 64];
+    if (!first && sc.cnt->overflow) return;  // frozen after an overflow: dt stays zero, time stands still
     double vm = 0.0, ks = 0.0;
     for (int i = threadIdx.x; i < nblk; i += 1024) {
         vm = fmax(vm, part[2 * i]);
@@ -232,6 +262,11 @@ __device__ __forceinline__ void dt_update_body(State S, Scratch sc, const double
         if (!first) {
             sc.scal[1] += sc.scal[0];
             sc.scal[6] = sc.scal[0];
+            sc.cnt->steps += 1;
+        } else {  // a new call: no overflow, no steps yet
+            sc.cnt->overflow = 0;
+            sc.cnt->steps = 0;
+            sc.cnt->fail_step = 0;
         }
         sc.scal[0] = dt;
         sc.scal[2] = vmax;
@@ -425,16 +460,28 @@ static int site_blocks(const Geom &g) {
     return (int)(b < 65536 * 4 ? (b > 0 ? b : 1) : 65536 * 4);
 }
 
+void swap_uv(misa_lattice *h) {
+    std::swap(h->S.ux, h->alt.ux);
+    std::swap(h->S.uy, h->alt.uy);
+    std::swap(h->S.uz, h->alt.uz);
+    std::swap(h->S.vx, h->alt.vx);
+    std::swap(h->S.vy, h->alt.vy);
+    std::swap(h->S.vz, h->alt.vz);
+    h->parity ^= 1;
+}
+
 hipError_t launch_kick_drift(misa_lattice *h) {
     const double kf = ACC_UNIT / h->mass;
     const int nb = site_blocks(h->g);
     if (h->precision == MISA_FP32)
-        hipLaunchKernelGGL(k_kick_drift<float>, dim3(nb), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc, h->g, kf,
-                           h->rcap);
+        hipLaunchKernelGGL(k_kick_drift<float>, dim3(nb), dim3(KICK_THREADS), 0, h->stream, h->S, h->alt, h->sc, h->g,
+                           kf, h->rcap);
     else
-        hipLaunchKernelGGL(k_kick_drift<double>, dim3(nb), dim3(KICK_THREADS), 0, h->stream, h->S, h->sc, h->g, kf,
-                           h->rcap);
-    hipLaunchKernelGGL(k_kick_drift_runaway, dim3(SMALL_GRID), dim3(256), 0, h->stream, h->S, h->sc, h->g, kf);
+        hipLaunchKernelGGL(k_kick_drift<double>, dim3(nb), dim3(KICK_THREADS), 0, h->stream, h->S, h->alt, h->sc,
+                           h->g, kf, h->rcap);
+    swap_uv(h);
+    hipLaunchKernelGGL(k_kick_drift_runaway, dim3(SMALL_GRID), dim3(256), 0, h->stream, h->S, h->alt, h->sc, h->g, kf,
+                       h->rcap);
     return hipGetLastError();
 }
 
@@ -472,9 +519,10 @@ hipError_t launch_dt_update(misa_lattice *h, double dt_max, double dx_max, bool 
 }
 
 // Batched: one launch per kernel over every box (blockIdx.y = box).
-hipError_t launchb_kick_drift(hipStream_t st, const BoxRef *boxes, int nbox, int gx_sites, int gx_small, double kf) {
+hipError_t launchb_kick_drift(hipStream_t st, const BoxRef *boxes, const BoxRef *boxes_after, int nbox, int gx_sites,
+                              int gx_small, double kf) {
     hipLaunchKernelGGL(kb_kick_drift<float>, dim3(gx_sites, nbox), dim3(KICK_THREADS), 0, st, boxes, kf);
-    hipLaunchKernelGGL(kb_kick_drift_runaway, dim3(gx_small, nbox), dim3(256), 0, st, boxes, kf);
+    hipLaunchKernelGGL(kb_kick_drift_runaway, dim3(gx_small, nbox), dim3(256), 0, st, boxes_after, kf);
     return hipGetLastError();
 }
 
@@ -503,6 +551,17 @@ hipError_t launch_place(misa_lattice *h, const double *x, const double *v, int64
         hipLaunchKernelGGL(k_place_settle, dim3(na), dim3(KICK_THREADS), 0, h->stream, x, v, n, h->g, h->S, h->sc,
                            cand, h->rcap);
     }
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ a, uint32_t value, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = value;
+}
+
+hipError_t launch_fill_u32(misa_lattice *h, uint32_t *a, uint32_t value, int64_t n) {
+    const int nb = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024);
+    hipLaunchKernelGGL(k_fill_u32, dim3(nb), dim3(256), 0, h->stream, a, value, n);
     return hipGetLastError();
 }
 

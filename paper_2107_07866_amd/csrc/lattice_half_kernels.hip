@@ -29,6 +29,8 @@
 // record at the cut-off) is that of the full-gather persistent kernels.
 #include "misa_internal.h"
 
+#include <type_traits>
+
 #include "mlp_wave.h"
 
 namespace misa {
@@ -139,13 +141,28 @@ __device__ __forceinline__ float hf_store(Q4<float> *__restrict__ tile, float *_
 // Whether every occupied site of the footprint has |u|^2 below u_cut2 (then the
 // entries beyond rc of each phase cannot hold a pair within rc).  Contains the
 // barrier after which the staged tile is visible.
-__device__ __forceinline__ bool hf_near_sites(float m, unsigned *slot, unsigned *other, float u_cut2) {
+// safe: bit k set when entry k (this lane's threshold: thr) holds no pair near rc
+// in this tile, so its cut-off decision needs no band test (NearTab).
+__device__ __forceinline__ bool hf_near_sites(float m, unsigned *slot, unsigned *other, float u_cut2, float thr,
+                                              uint64_t &safe) {
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(m));
     __syncthreads();
     const float umax2 = __uint_as_float(*slot);
     if (threadIdx.x == 0) *other = 0u;
+    safe = __ballot(umax2 < thr);
     return __builtin_amdgcn_readfirstlane(umax2 < u_cut2 ? 1 : 0) != 0;
+}
+__device__ __forceinline__ bool hf_near_sites(float m, unsigned *slot, unsigned *other, float u_cut2) {
+    uint64_t safe;
+    return hf_near_sites(m, slot, other, u_cut2, -1.0f, safe);
+}
+
+// First entry of [k0, k1) that needs the band test: the safe entries of a phase
+// are a prefix of it (nearest first).
+__device__ __forceinline__ int hf_klo(uint64_t safe, int k0, int k1) {
+    const uint64_t in = k1 - k0 >= 64 ? ~0ull : ((1ull << (k1 - k0)) - 1ull);
+    return __builtin_amdgcn_readfirstlane(k0 + __popcll((safe >> k0) & in));
 }
 
 template <bool kNodeCut>
@@ -162,7 +179,8 @@ __global__ __launch_bounds__(HF_THREADS) void k_rho_half(ColourTiles ct, State S
                                                          const StencilEntry<float> *__restrict__ hst,
                                                          const int32_t *__restrict__ hmeta,
                                                          const Q4<float> *__restrict__ fwin, float inv_hq,
-                                                         float pcq, int nwin, float rc2, float u_cut2) {
+                                                         float pcq, int nwin, float rc2, float u_cut2,
+                                                         const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[HT_SITES];
     __shared__ float acc[HT_SITES];
     __shared__ float4 ftab[HALF_TAB_SEGS];
@@ -180,6 +198,7 @@ __global__ __launch_bounds__(HF_THREADS) void k_rho_half(ColourTiles ct, State S
     const StencilEntry<float> *sp = hst + p * KMAX;
     const int32_t *meta = hmeta + p * HALF_META;
     const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
+    const float thr = nt->thr2[p][lane];
     float *const out[1] = {(float *)S.rho};
     int it = 0;
     int item = ct.next(blockIdx.x, it, gridDim.x);
@@ -196,7 +215,9 @@ __global__ __launch_bounds__(HF_THREADS) void k_rho_half(ColourTiles ct, State S
         const float m = hf_store<1>(tile, acc, R);
 #pragma unroll
         for (int jj = 0; jj < HF_PER_LANE; ++jj) old[0][jj] = R.old[0][jj];
-        const bool near = hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2);
+        uint64_t safe;
+        const bool near =
+            hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2, thr, safe);
         ++it;
         const int nxt = ct.next(blockIdx.x, it, gridDim.x);
         if (nxt >= 0) {
@@ -205,27 +226,45 @@ __global__ __launch_bounds__(HF_THREADS) void k_rho_half(ColourTiles ct, State S
             hf_fetch<1>(R, S, out, false, nx_, ny_, nz_, g);  // in flight during this tile
         }
         const Q4<float> ui = tile[me];
+        const int gx = tx * T2X + lx, gy = ty * T2Y + ly, gz = tz * T2Z + lz;
+        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
         float ai = 0.0f;
+        // f(r) of entry k to both ends; kCheck: the cut-off decision of a pair within
+        // the band around rc^2 is taken again in float64
+        auto term = [&](int k, auto check) {
+            const StencilEntry<float> e = sp[k];
+            const int j = me + e.lds;
+            const Q4<float> uj = tile[j];
+            const float dx = (uj.x - ui.x) + e.ox;
+            const float dy = (uj.y - ui.y) + e.oy;
+            const float dz = (uj.z - ui.z) + e.oz;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            float t;
+            const int s = hf_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);
+            const float4 c = ftab[s];
+            const float vr = ((c.w * t + c.z) * t + c.y) * t + c.x;
+            float v = (kNodeCut || r2 < rc2) ? vr : 0.0f;
+            if (decltype(check)::value && fabsf(r2 - rc2) < RC_BAND_Q) {
+                const bool in = pair_in_rc64(S.ux, S.uy, S.uz, idx, gx, gy, gz, p, nt->st[p][k], g.nx, g.ny,
+                                             g.nz, g.ncell, nt->rc2);
+                if (kNodeCut && s >= nwin) {  // past the window's last node (rc) in float32: f there
+                    const float4 cl = ftab[nwin - 1];
+                    v = in ? cl.x + cl.y + cl.z + cl.w : 0.0f;
+                } else {
+                    v = in ? vr : 0.0f;
+                }
+            }
+            ai += v;
+            acc[j] += v;  // no other wave writes this plane in this phase
+        };
         for (int q = 0; q < HALF_PHASES; ++q) {
             const int k0 = __builtin_amdgcn_readfirstlane(meta[q]);
             const int k1 = __builtin_amdgcn_readfirstlane(near ? k0 + meta[8 + q] : meta[q + 1]);
+            const int kl = hf_klo(safe, k0, k1);
 #pragma unroll 4
-            for (int k = k0; k < k1; ++k) {
-                const StencilEntry<float> e = sp[k];
-                const int j = me + e.lds;
-                const Q4<float> uj = tile[j];
-                const float dx = (uj.x - ui.x) + e.ox;
-                const float dy = (uj.y - ui.y) + e.oy;
-                const float dz = (uj.z - ui.z) + e.oz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                float t;
-                const int s = hf_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);
-                const float4 c = ftab[s];
-                float v = ((c.w * t + c.z) * t + c.y) * t + c.x;
-                v = (kNodeCut || r2 < rc2) ? v : 0.0f;
-                ai += v;
-                acc[j] += v;  // no other wave writes this plane in this phase
-            }
+            for (int k = k0; k < kl; ++k) term(k, std::false_type{});
+#pragma unroll 4
+            for (int k = kl; k < k1; ++k) term(k, std::true_type{});
             __syncthreads();  // the next phase's waves write other planes of the footprint
         }
         acc[me] += ai;  // the site's own pairs, after every partner term
@@ -277,7 +316,7 @@ __global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State
                                                            const int32_t *__restrict__ hmeta,
                                                            const FRec32 *__restrict__ fwin, float inv_hq,
                                                            float pcq, int nwin, Tables<float> T, float rc2,
-                                                           float u_cut2, double *__restrict__ part) {
+                                                           float u_cut2, double *__restrict__ part, const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[HT_SITES];
     __shared__ float4 acc[HT_SITES];       // {F_x, F_y, F_z, -} per footprint site: one 16-byte read-add-write
     __shared__ float4 fab[HALF_TAB_SEGS];  // {f'0, f'1, f'2, phi'0} per segment
@@ -301,6 +340,7 @@ __global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State
     const StencilEntry<float> *sp = hst + p * KMAX;
     const int32_t *meta = hmeta + p * HALF_META;
     const int me = ((p * HFZ + lz) * HFY + ly + HALO) * HFX + lx + HALO;
+    const float thr = nt->thr2[p][lane];
     const int nlast = T.fm.nseg - 1;
     float *const out[3] = {(float *)S.fx, (float *)S.fy, (float *)S.fz};
     int it = 0;
@@ -322,7 +362,9 @@ __global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State
             old[1][jj] = R.old[1][jj];
             old[2][jj] = R.old[2][jj];
         }
-        const bool near = hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2);
+        uint64_t safe;
+        const bool near =
+            hf_near_sites(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], u_cut2, thr, safe);
         ++it;
         const int nxt = ct.next(blockIdx.x, it, gridDim.x);
         if (nxt >= 0) {
@@ -331,45 +373,66 @@ __global__ __launch_bounds__(HF_THREADS) void k_force_half(ColourTiles ct, State
             hf_fetch<3>(R, S, out, true, nx_, ny_, nz_, g);
         }
         const Q4<float> ui = tile[me];
+        const int gx = tx * T2X + lx, gy = ty * T2Y + ly, gz = tz * T2Z + lz;
+        const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
         float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
+        // the pair term of entry k to both ends; kCheck: the cut-off decision of a pair
+        // within the band around rc^2 is taken again in float64
+        auto term = [&](int k, auto check) {
+            const StencilEntry<float> e = sp[k];
+            const int j = me + e.lds;
+            const Q4<float> uj = tile[j];
+            const float dx = (uj.x - ui.x) + e.ox;
+            const float dy = (uj.y - ui.y) + e.oy;
+            const float dz = (uj.z - ui.z) + e.oz;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            float t;
+            const int s = hf_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);
+            const float4 a = fab[s];
+            const float2 c = fcc[s];
+            float gf = (a.z * t + a.y) * t + a.x;  // f'(r) / r
+            float gp = (c.y * t + c.x) * t + a.w;  // phi'(r) / r
+            bool in = kNodeCut ? s < nwin : r2 < rc2;
+            if (decltype(check)::value && fabsf(r2 - rc2) < RC_BAND_Q) {
+                in = pair_in_rc64(S.ux, S.uy, S.uz, idx, gx, gy, gz, p, nt->st[p][k], g.nx, g.ny, g.nz,
+                                  g.ncell, nt->rc2);
+                if (kNodeCut && s >= nwin) {  // past the window's last node (rc) in float32: the records there
+                    const float4 al = fab[nwin - 1];
+                    const float2 cl = fcc[nwin - 1];
+                    gf = al.x + al.y + al.z;
+                    gp = al.w + cl.x + cl.y;
+                }
+                gf = in ? gf : 0.0f;
+                gp = in ? gp : 0.0f;
+            }
+            float sc = (ui.w + uj.w) * gf + gp;
+            if (!kNodeCut) sc = in ? sc : 0.0f;
+            const float px = sc * dx, py = sc * dy, pz = sc * dz;
+            ax += px;
+            ay += py;
+            az += pz;
+            float4 aj = acc[j];  // no other wave writes this plane in this phase
+            aj.x -= px;
+            aj.y -= py;
+            aj.z -= pz;
+            acc[j] = aj;
+            if (kEnergy) {
+                const float pr = (__builtin_amdgcn_sqrtf(r2) - T.fm.x0) * T.fm.inv_h;
+                const int sg = max(0, min((int)pr, nlast));
+                const float tr = pr - (float)sg;
+                const Q4<float> cp = T.phi[sg];
+                const float v = ((cp.w * tr + cp.z) * tr + cp.y) * tr + cp.x;
+                ep += in ? v : 0.0f;
+            }
+        };
         for (int q = 0; q < HALF_PHASES; ++q) {
             const int k0 = __builtin_amdgcn_readfirstlane(meta[q]);
             const int k1 = __builtin_amdgcn_readfirstlane(near ? k0 + meta[8 + q] : meta[q + 1]);
+            const int kl = hf_klo(safe, k0, k1);
 #pragma unroll 4
-            for (int k = k0; k < k1; ++k) {
-                const StencilEntry<float> e = sp[k];
-                const int j = me + e.lds;
-                const Q4<float> uj = tile[j];
-                const float dx = (uj.x - ui.x) + e.ox;
-                const float dy = (uj.y - ui.y) + e.oy;
-                const float dz = (uj.z - ui.z) + e.oz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                float t;
-                const int s = hf_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);
-                const float4 a = fab[s];
-                const float2 c = fcc[s];
-                const float gf = (a.z * t + a.y) * t + a.x;  // f'(r) / r
-                const float gp = (c.y * t + c.x) * t + a.w;  // phi'(r) / r
-                float sc = (ui.w + uj.w) * gf + gp;
-                if (!kNodeCut) sc = r2 < rc2 ? sc : 0.0f;
-                const float px = sc * dx, py = sc * dy, pz = sc * dz;
-                ax += px;
-                ay += py;
-                az += pz;
-                float4 aj = acc[j];  // no other wave writes this plane in this phase
-                aj.x -= px;
-                aj.y -= py;
-                aj.z -= pz;
-                acc[j] = aj;
-                if (kEnergy) {
-                    const float pr = (__builtin_amdgcn_sqrtf(r2) - T.fm.x0) * T.fm.inv_h;
-                    const int sg = max(0, min((int)pr, nlast));
-                    const float tr = pr - (float)sg;
-                    const Q4<float> cp = T.phi[sg];
-                    const float v = ((cp.w * tr + cp.z) * tr + cp.y) * tr + cp.x;
-                    ep += (kNodeCut ? s < nwin : r2 < rc2) ? v : 0.0f;
-                }
-            }
+            for (int k = k0; k < kl; ++k) term(k, std::false_type{});
+#pragma unroll 4
+            for (int k = kl; k < k1; ++k) term(k, std::true_type{});
             __syncthreads();
         }
         {
@@ -456,7 +519,7 @@ __global__ __launch_bounds__(HFM_THREADS) void k_rho_half_mlp(ColourTiles ct, St
                                                               const StencilEntry<float> *__restrict__ hst,
                                                               const int32_t *__restrict__ hmeta, HalfNets N,
                                                               Tables<float> T, float rc2, float u_cut2,
-                                                              float *__restrict__ dfbuf) {
+                                                              float *__restrict__ dfbuf, const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[HT_SITES];
     __shared__ float acc[HT_SITES];
     __shared__ MlpLds Lf;
@@ -510,7 +573,11 @@ __global__ __launch_bounds__(HFM_THREADS) void k_rho_half_mlp(ColourTiles ct, St
                     float y, dyt;
                     mlp_wave<true>(Lf, Af, net_t(nf, r), y, dyt);  // every lane: the whole wave runs it
                     float v = 0.0f, dfr = 0.0f;
-                    if (r2 < rc2) {
+                    bool in = r2 < rc2;
+                    if (fabsf(r2 - rc2) < RC_BAND_Q)  // cut-off decided again in float64 (NearTab)
+                        in = pair_in_rc64(S.ux, S.uy, S.uz, idx, tx * T2X + lx, ty * T2Y + ly, tz * T2Z + lz, p,
+                                          nt->st[p][k], g.nx, g.ny, g.nz, g.ncell, nt->rc2);
+                    if (in) {
                         v = nf.y_shift + nf.y_scale * y;
                         dfr = kfd * dyt;
                         if (!mlp_serves(nf, r)) {
@@ -588,7 +655,7 @@ __global__ __launch_bounds__(HFM_THREADS) void k_force_half_mlp(ColourTiles ct, 
                                                                 const int32_t *__restrict__ hmeta, HalfNets N,
                                                                 Tables<float> T, float rc2, float u_cut2,
                                                                 double *__restrict__ part,
-                                                                const float *__restrict__ dfbuf) {
+                                                                const float *__restrict__ dfbuf, const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[HT_SITES];
     __shared__ float4 acc[HT_SITES];
     __shared__ MlpLds Lp, Le;
@@ -648,7 +715,11 @@ __global__ __launch_bounds__(HFM_THREADS) void k_force_half_mlp(ColourTiles ct, 
                     float yp, dp;
                     mlp_wave<true>(Lp, Ap, net_t(np, r), yp, dp);  // every lane: the whole wave runs it
                     float px = 0.0f, py = 0.0f, pz = 0.0f;
-                    if (r2 < rc2) {
+                    bool in = r2 < rc2;
+                    if (fabsf(r2 - rc2) < RC_BAND_Q)  // cut-off decided again in float64 (NearTab)
+                        in = pair_in_rc64(S.ux, S.uy, S.uz, idx, tx * T2X + lx, ty * T2Y + ly, tz * T2Z + lz, p,
+                                          nt->st[p][k], g.nx, g.ny, g.nz, g.ncell, nt->rc2);
+                    if (in) {
                         float dph = kp * dp, ph = np.y_shift + np.y_scale * yp;
                         if (!mlp_serves(np, r)) {
                             int sg;
@@ -787,7 +858,8 @@ hipError_t launch_rho_half(misa_lattice *h) {
         const ColourTiles ct = colour_tiles(h, c);
         const int grid = std::min(h->persistent_grid, ct.nitems_pad);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(HF_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st, h->half.meta,
-                           (const Q4<float> *)W.f, W.inv_hq, W.pcq, W.nwin, (float)h->g.rc2, h->u_cut2);
+                           (const Q4<float> *)W.f, W.inv_hq, W.pcq, W.nwin, (float)h->g.rc2, h->u_cut2,
+                           near_args(h, true));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int64_t b = std::min<int64_t>((h->g.nsites + 255) / 256, 8192);
@@ -815,7 +887,8 @@ hipError_t launch_rho_half_mlp(misa_lattice *h) {
         const ColourTiles ct = colour_tiles(h, c);
         const int grid = std::min(h->persistent_grid, ct.nitems_pad);
         hipLaunchKernelGGL(k_rho_half_mlp, dim3(grid), dim3(HFM_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st,
-                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2, h->pairbuf);
+                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2, h->pairbuf,
+                           near_args(h, true));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int64_t b = std::min<int64_t>((h->g.nsites + 255) / 256, 8192);
@@ -834,7 +907,8 @@ hipError_t launch_force_half_mlp(misa_lattice *h, bool energy) {
         const ColourTiles ct = colour_tiles(h, c);
         const int grid = std::min(h->persistent_grid, ct.nitems_pad);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(HFM_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st,
-                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2, h->sc.part, h->pairbuf);
+                           h->half.meta, N, half_tables(h), (float)h->g.rc2, h->u_cut2, h->sc.part, h->pairbuf,
+                           near_args(h, true));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -851,7 +925,8 @@ hipError_t launch_force_half(misa_lattice *h, bool energy) {
         const ColourTiles ct = colour_tiles(h, c);
         const int grid = std::min(h->persistent_grid, ct.nitems_pad);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(HF_THREADS), 0, h->stream, ct, h->S, h->g, h->half.st, h->half.meta, W.force,
-                           W.inv_hq, W.pcq, W.nwin, half_tables(h), (float)h->g.rc2, h->u_cut2, h->sc.part);
+                           W.inv_hq, W.pcq, W.nwin, half_tables(h), (float)h->g.rc2, h->u_cut2, h->sc.part,
+                           near_args(h, true));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

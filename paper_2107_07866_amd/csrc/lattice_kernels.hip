@@ -10,6 +10,8 @@
 // write conflicts arise and no colouring or atomics are needed.
 #include "misa_internal.h"
 
+#include <type_traits>
+
 namespace misa {
 
 
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_tile(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
     Real *__restrict__ rho, Real *__restrict__ fp, const StencilEntry<Real> *__restrict__ st, int K, int kin,
     float u_cut2, const Q4<Real> *__restrict__ ftab, TabMeta<Real> fm, const Q4<Real> *__restrict__ etab,
-    TabMeta<Real> em, Geom g, uint32_t *__restrict__ range_viol) {
+    TabMeta<Real> em, Geom g, uint32_t *__restrict__ range_viol, const NearTab *__restrict__ nt) {
     __shared__ Q4<Real> tile[TILE_SITES];
     __shared__ unsigned umax;
     const int tid = tile_of_block(blockIdx.x, g);
@@ -86,6 +88,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_tile(
     const Q4<Real> ui = tile[me];
     const Real rc2 = (Real)g.rc2;
     const StencilEntry<Real> *sp = st + p * KMAX;
+    const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
     Real acc = 0;
     // Branch-free and unrolled: every candidate gathers its (clamped) record and an
     // out-of-range pair is dropped by a select, so the L2 gathers of several
@@ -98,7 +101,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_tile(
         const Real dy = (uj.y - ui.y) + e.oy;
         const Real dz = (uj.z - ui.z) + e.oz;
         const Real r2 = dx * dx + dy * dy + dz * dz;
-        const bool in = r2 < rc2;
+        bool in = r2 < rc2;
+        if (std::is_same<Real, float>::value && fabsf((float)r2 - (float)rc2) < RC_BAND_Q)  // float64 re-decision
+            in = pair_in_rc64(ux, uy, uz, idx, gx, gy, gz, p, nt->st[p][k], g.nx, g.ny, g.nz, g.ncell, nt->rc2);
         int s;
         Real t;
         seg_index(pair_r<Real>(in ? r2 : rc2), fm, s, t);
@@ -106,7 +111,6 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_tile(
         const Real v = ((c.w * t + c.z) * t + c.y) * t + c.x;
         acc += in ? v : (Real)0;
     }
-    const int64_t idx = (int64_t)p * g.ncell + ((int64_t)gz * g.ny + gy) * g.nx + gx;
     Real fpv = 0;
     bool beyond = false;
     if (ui.x > (Real)VACANT_TEST) {
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
     const Real *__restrict__ fp, const Real *__restrict__ rho, Real *__restrict__ fx, Real *__restrict__ fy,
     Real *__restrict__ fz, const StencilEntry<Real> *__restrict__ st, int K, int kin, float u_cut2, Tables<Real> T,
-    Geom g, double *__restrict__ part, KickArgs kick) {
+    Geom g, double *__restrict__ part, KickArgs kick, const NearTab *__restrict__ nt) {
     __shared__ Q4<Real> tile[TILE_SITES];
     __shared__ double red[4][TILE_THREADS / 64];
     __shared__ unsigned umax;
@@ -206,7 +210,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_tile(
             const Real dy = (uj.y - ui.y) + e.oy;
             const Real dz = (uj.z - ui.z) + e.oz;
             const Real r2 = dx * dx + dy * dy + dz * dz;
-            const bool in = r2 < rc2;
+            bool in = r2 < rc2;
+            if (std::is_same<Real, float>::value && fabsf((float)r2 - (float)rc2) < RC_BAND_Q)  // float64 re-decision
+                in = pair_in_rc64(ux, uy, uz, idx, gx, gy, gz, p, nt->st[p][k], g.nx, g.ny, g.nz, g.ncell,
+                                  nt->rc2);
             Real r, rinv;
             pair_r_rinv<Real>(in ? r2 : rc2, r, rinv);
             int s;
@@ -304,8 +311,7 @@ static hipError_t rho_impl(misa_lattice *h, const StencilEntry<Real> *st, const 
     const Geom &g = h->g;
     hipLaunchKernelGGL(k_rho_tile<Real>, dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux, h->S.uy,
                        h->S.uz, (Real *)h->S.rho, (Real *)h->S.fp, st, h->K, h->K_in, h->u_cut2, t.f, t.fm, t.emb,
-                       t.em, g,
-                       &h->sc.cnt->range_viol);
+                       t.em, g, &h->sc.cnt->range_viol, near_args(h, false));
     return hipGetLastError();
 }
 
@@ -323,7 +329,8 @@ static void force_variant(misa_lattice *h, const StencilEntry<Real> *st, const T
     const Geom &g = h->g;
     hipLaunchKernelGGL((k_force_tile<Real, kEnergy, kKick>), dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream,
                        h->S.ux, h->S.uy, h->S.uz, (const Real *)h->S.fp, (const Real *)h->S.rho, (Real *)h->S.fx,
-                       (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, h->K_in, h->u_cut2, T, g, h->sc.part, ka);
+                       (Real *)h->S.fy, (Real *)h->S.fz, st, h->K, h->K_in, h->u_cut2, T, g, h->sc.part, ka,
+                       near_args(h, false));
 }
 
 template <typename Real>

@@ -23,6 +23,14 @@
 // below the window after a run-away capacity overflow (reported on its own).
 #include "misa_internal.h"
 
+#include <type_traits>
+
+// Multiply-adds fuse only within one expression: every copy of a pair loop (the
+// unrolled bodies, the loops with and without the band test of the cut-off) then
+// rounds a pair's terms alike, so results do not depend on which copy a stencil
+// entry falls into (the tile shapes and the per-tile band test move that boundary).
+#pragma clang fp contract(on)
+
 namespace misa {
 
 __device__ __forceinline__ int wrap2(int i, int n) {
@@ -230,14 +238,23 @@ __device__ __forceinline__ float store_tile2(Q4<float> *__restrict__ tile, const
 // its halo has |u| < u_cut = (d_next - rc) / 2 - margin, entries kin .. K - 1 can
 // hold no pair within rc and are skipped (u_cut < 0 when no entry lies beyond rc).
 // slot: the LDS word of this tile (two words alternate between consecutive tiles).
+// klo: entries 0 .. klo - 1 hold no pair within NEAR_MARGIN of rc in this tile
+// (thr: this lane's entry of NearTab::thr2), so only entries klo .. need the
+// band test of the float32 cut-off decision.
 __device__ __forceinline__ int tile_stencil_length(float m, unsigned *slot, unsigned *other, int K, int kin,
-                                                   float u_cut2) {
+                                                   float u_cut2, float thr, int &klo) {
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(m));  // |u|^2 >= 0: integer order = float order
     __syncthreads();
     const float umax2 = __uint_as_float(*slot);
     if (threadIdx.x == 0) *other = 0u;  // cleared for the next tile (read after the next barrier pair)
+    klo = __builtin_amdgcn_readfirstlane(__popcll(__ballot(umax2 < thr)));
     return __builtin_amdgcn_readfirstlane(umax2 < u_cut2 ? kin : K);
+}
+__device__ __forceinline__ int tile_stencil_length(float m, unsigned *slot, unsigned *other, int K, int kin,
+                                                   float u_cut2) {
+    int klo;
+    return tile_stencil_length(m, slot, other, K, kin, u_cut2, -1.0f, klo);
 }
 
 // Local segment index and offset t for pp = (q - q0) / hq on the window's q = r^2
@@ -251,14 +268,63 @@ __device__ __forceinline__ int win_seg(float pp, int nwin, float &t) {
     return (int)__builtin_amdgcn_fmed3f(pp, 0.0f, top);
 }
 
+// The box of a tile as the float64 cut-off decision needs it.  Kept in LDS (written
+// per tile) and read only by the rare fix-ups: the pair loops run short of scalar
+// registers, and values they keep live cost them their overlap of LDS reads.
+struct NearBox {
+    const double *ux, *uy, *uz;
+    const NearTab *nt;
+    int64_t ncell;
+    int nx, ny, nz, pad;
+};
+
+// A lane's site as the fix-ups need it.
+struct NearSite {
+    int64_t idx;
+    int gx, gy, gz, p;
+};
+
+// For a lane whose entries klo .. Kt - 1 hold a pair within the band around rc^2:
+// what must be added to the density the loop summed, so that each such pair counts
+// as the float64 decision says (with f at the window's last node, rc, when the
+// float32 r^2 fell at or beyond it).
+template <bool kNodeCut>
+__device__ __forceinline__ float rho_near_fix(const Q4<float> *tile, const float4 *ftab, const StencilEntry<float> *sp,
+                                           int me, Q4<float> ui, int klo, int Kt, float inv_hq, float pcq, int nwin,
+                                           float rc2, NearSite q, const NearBox &bx) {
+    const NearTab *nt = bx.nt;
+    float add = 0.0f;
+    for (int k = klo; k < Kt; ++k) {
+        const StencilEntry<float> e = sp[k];
+        const Q4<float> uj = tile[me + e.lds];
+        const float dx = (uj.x - ui.x) + e.ox;
+        const float dy = (uj.y - ui.y) + e.oy;
+        const float dz = (uj.z - ui.z) + e.oz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (!(fabsf(r2 - rc2) < RC_BAND_Q)) continue;
+        float t;
+        const int s = win_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);
+        const float4 c = ftab[s];
+        const float vr = ((c.w * t + c.z) * t + c.y) * t + c.x;
+        const float used = (kNodeCut || r2 < rc2) ? vr : 0.0f;
+        const bool in = pair_in_rc64(bx.ux, bx.uy, bx.uz, q.idx, q.gx, q.gy, q.gz, q.p, nt->st[q.p][k], bx.nx, bx.ny,
+                                     bx.nz, bx.ncell, nt->rc2);
+        const float4 cl = ftab[nwin - 1];
+        const float want = !in ? 0.0f : (kNodeCut && s >= nwin) ? cl.x + cl.y + cl.z + cl.w : vr;
+        add += want - used;
+    }
+    return add;
+}
+
 template <class Src, bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const StencilEntry<float> *__restrict__ st,
                                                           int K, int kin, float u_cut2,
                                                           const Q4<float> *__restrict__ fwin, float inv_hq,
                                                           float pcq, int nwin, const Q4<float> *__restrict__ etab,
-                                                          TabMeta<float> em, float rc2) {
+                                                          TabMeta<float> em, float rc2, const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[Src::kMaxSites];
     __shared__ float4 ftab[LDS_TAB_SEGS];
+    __shared__ NearBox nbox;
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
     for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) {
@@ -269,6 +335,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // wave-uniform parity: the stencil entries below become scalar loads
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);
+    const float thr = nt->thr2[p][lane];
     TileGeo Gf{};  // the fixed shape's lane site and stencil, computed once
     const LaneSite Lf = lane_site(dims_of<Src>(Gf), p, w, lane);
     int it = 0;
@@ -290,8 +357,11 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
         const int shp = Src::kFixed ? 0 : __builtin_amdgcn_readfirstlane(G.shape);
         const StencilEntry<float> *sp = st + (shp * 2 + p) * KMAX;
         __syncthreads();  // previous tile fully consumed (and the table copied)
+        if (threadIdx.x == 0) nbox = NearBox{P.ux, P.uy, P.uz, nt, G.ncell, G.nx, G.ny, G.nz, 0};
         const float m = store_tile2(tile, R, d.sites);
-        const int Kt = tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2);
+        int klo;
+        const int Kt =
+            tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2, thr, klo);
         ++it;
         const int nxt = src.next(blockIdx.x, it, gridDim.x);
         if (nxt >= 0) {
@@ -307,8 +377,10 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
             const int me = L.me;
             const Q4<float> ui = tile[me];
             float acc = 0.0f;
-#pragma unroll 4
-            for (int k = 0; k < Kt; ++k) {
+            // f(r_ij) of entry k as the loops add it (entries klo .. also flag a pair whose
+            // float32 r^2 lies within the band around rc^2)
+            bool near = false;
+            auto term = [&](int k, auto check) -> float {
                 const StencilEntry<float> e = sp[k];
                 const Q4<float> uj = tile[me + e.lds];
                 const float dx = (uj.x - ui.x) + e.ox;
@@ -318,10 +390,19 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
                 float t;
                 const int s = win_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);  // q = r^2 grid
                 const float4 c = ftab[s];
-                const float v = ((c.w * t + c.z) * t + c.y) * t + c.x;
-                acc += (kNodeCut || r2 < rc2) ? v : 0.0f;
-            }
+                const float vr = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                if (decltype(check)::value) near |= fabsf(r2 - rc2) < RC_BAND_Q;
+                return (kNodeCut || r2 < rc2) ? vr : 0.0f;
+            };
+            // (two loop variables: with one shared by both loops the unrolled bodies lost
+            // the overlap of their LDS reads)
+#pragma unroll 4
+            for (int k = 0; k < klo; ++k) acc += term(k, std::false_type{});
+#pragma unroll 4
+            for (int k = klo; k < Kt; ++k) acc += term(k, std::true_type{});
             const int64_t idx = (int64_t)p * G.ncell + ((int64_t)gz * G.ny + gy) * G.nx + gx;
+            if (near) acc += rho_near_fix<kNodeCut>(tile, ftab, sp, me, ui, klo, Kt, inv_hq, pcq, nwin, rc2,
+                                                    NearSite{idx, gx, gy, gz, p}, nbox);
             float fpv = 0.0f;
             bool beyond = false;
             if (ui.x > (float)VACANT_TEST) {
@@ -364,7 +445,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
                                                             int K, int kin, float u_cut2,
                                                             const FRec32 *__restrict__ fwin, float inv_hq,
                                                             float pcq, int nwin, Tables<float> T, float rc2,
-                                                            double kf) {
+                                                            double kf, const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[Src::kMaxSites];
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
@@ -382,6 +463,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
     }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);
+    const float thr = nt->thr2[p][lane];
     TileGeo Gf{};  // the fixed shape's lane site and stencil, computed once
     const LaneSite Lf = lane_site(dims_of<Src>(Gf), p, w, lane);
     const int nlast = T.fm.nseg - 1;
@@ -405,7 +487,9 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
         const StencilEntry<float> *sp = st + (shp * 2 + p) * KMAX;
         __syncthreads();
         const float m = store_tile2(tile, R, d.sites);
-        const int Kt = tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2);
+        int klo;
+        const int Kt =
+            tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2, thr, klo);
         ++it;
         const int nxt = src.next(blockIdx.x, it, gridDim.x);
         if (nxt >= 0) {
@@ -433,8 +517,9 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
             const int me = L.me;
             const Q4<float> ui = tile[me];
             float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
-#pragma unroll 2
-            for (int k = 0; k < Kt; ++k) {
+            // the pair term of entry k; kCheck: the cut-off decision of a pair within the
+            // band around rc^2 is taken again in float64
+            auto term = [&](int k, auto check) {
                 const StencilEntry<float> e = sp[k];
                 const Q4<float> uj = tile[me + e.lds];
                 const float dx = (uj.x - ui.x) + e.ox;
@@ -445,10 +530,23 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
                 const int s = win_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);  // q = r^2 grid
                 const float4 a = fab[s];
                 const float2 c = fcc[s];
-                const float gf = (a.z * t + a.y) * t + a.x;  // f'(r) / r
-                const float gp = (c.y * t + c.x) * t + a.w;  // phi'(r) / r
+                float gf = (a.z * t + a.y) * t + a.x;  // f'(r) / r
+                float gp = (c.y * t + c.x) * t + a.w;  // phi'(r) / r
+                bool in = kNodeCut ? s < nwin : r2 < rc2;
+                if (decltype(check)::value && fabsf(r2 - rc2) < RC_BAND_Q) {
+                    in = pair_in_rc64(P.ux, P.uy, P.uz, idx, gx, gy, gz, p, nt->st[p][k], G.nx, G.ny, G.nz,
+                                      G.ncell, nt->rc2);
+                    if (kNodeCut && s >= nwin) {  // past the window's last node (rc) in float32: the records there
+                        const float4 al = fab[nwin - 1];
+                        const float2 cl = fcc[nwin - 1];
+                        gf = al.x + al.y + al.z;
+                        gp = al.w + cl.x + cl.y;
+                    }
+                    gf = in ? gf : 0.0f;
+                    gp = in ? gp : 0.0f;
+                }
                 float sc = (ui.w + uj.w) * gf + gp;
-                if (!kNodeCut) sc = r2 < rc2 ? sc : 0.0f;
+                if (!kNodeCut) sc = in ? sc : 0.0f;
                 ax += sc * dx;
                 ay += sc * dy;
                 az += sc * dz;
@@ -458,9 +556,13 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
                     const float tr = pr - (float)sg;
                     const Q4<float> cp = T.phi[sg];
                     const float v = ((cp.w * tr + cp.z) * tr + cp.y) * tr + cp.x;
-                    ep += (kNodeCut ? s < nwin : r2 < rc2) ? v : 0.0f;  // same pair set as the force
+                    ep += in ? v : 0.0f;  // same pair set as the force
                 }
-            }
+            };
+#pragma unroll 2
+            for (int k = 0; k < klo; ++k) term(k, std::false_type{});
+#pragma unroll 2
+            for (int k = klo; k < Kt; ++k) term(k, std::true_type{});
             const bool vac = ui.x > (float)VACANT_TEST;
             if (vac) ax = ay = az = 0.0f;
             P.fx[idx] = ax;
@@ -971,7 +1073,7 @@ static hipError_t rho_lds_src(misa_lattice *h, const Src &src, int grid, const S
     auto kern = h->lds32.node_cut ? k_rho_lds<Src, true> : k_rho_lds<Src, false>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, st, h->K, h->K_in,
                        h->u_cut2, h->lds32.f, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, h->t32.emb, h->t32.em,
-                       (float)h->g.rc2);
+                       (float)h->g.rc2, near_args(h, false));
     return hipGetLastError();
 }
 
@@ -980,7 +1082,7 @@ static void force_lds_variant(misa_lattice *h, const Src &src, int grid, const S
     auto kern = h->lds32.node_cut ? k_force_lds<Src, kEnergy, true, kKick> : k_force_lds<Src, kEnergy, false, kKick>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, st, h->K, h->K_in,
                        h->u_cut2, h->lds32.force, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, t32_tab(h),
-                       (float)h->g.rc2, ACC_UNIT / h->mass);
+                       (float)h->g.rc2, ACC_UNIT / h->mass, near_args(h, false));
 }
 
 template <class Src>

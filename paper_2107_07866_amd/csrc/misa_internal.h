@@ -103,6 +103,64 @@ struct alignas(16) StencilEntry<float> {
     float ox, oy, oz;
 };
 
+// Cut-off decisions of float32 pair arithmetic.  A pair counts iff r < rc (Eq.
+// eam_base).  For two slotted atoms (|u| < 1.24 A, site offsets below 8 A) the
+// float32 r^2 = |o + u_j - u_i|^2 lies within 3e-5 A^2 of the float64 one (each
+// displacement and offset rounded once, two rounded sums, three rounded squares and
+// their sum), so outside a band of RC_BAND_Q around rc^2 the float32 decision is the
+// float64 one.  Inside the band the decision is taken again in float64 from the
+// stored displacements, as the float64 passes take it; at 300 K about one pair in
+// 10^5 falls there.
+constexpr float RC_BAND_Q = 1.0e-4f;   // A^2
+constexpr float NEAR_MARGIN = 1.0e-3f; // A: slack of the per-tile test below
+
+// A stencil entry as the float64 re-decision needs it: the lattice-id offset of
+// Sec. 3 and the site offset vector, in the order of the kernel's float stencil.
+struct alignas(16) NearEntry {
+    int32_t dX, dY, dZ, pad;
+    double ox, oy, oz, pad2;
+};
+
+// What the float32 passes need for that re-decision, in device memory (the kernels
+// take a pointer and read it only where they need it: kept out of the scalar
+// registers of the pair loops).  thr2[p][k] (k < 64, in the stencil's order; the
+// gather stencil is sorted by |o|, the half stencil by |o| inside each phase): a
+// tile whose occupied sites all have |u|^2 < thr2[p][k] holds no pair of entry k
+// within NEAR_MARGIN of rc, since r <= |o_k| + 2 |u|max; -1 where |o_k| > rc -
+// NEAR_MARGIN.
+struct NearTab {
+    double rc2;
+    double pad;
+    float thr2[2][64];
+    NearEntry st[2][KMAX];
+};
+
+// Storage index of the site at lattice-id offset (dX, dY, dZ) from site (cx, cy, cz)
+// of sublattice p, wrapped into the periodic box.
+__device__ __forceinline__ int64_t offset_site(int cx, int cy, int cz, int p, const NearEntry &e, int nx, int ny,
+                                               int nz, int64_t ncell) {
+    int X = (2 * cx + p + e.dX) % (2 * nx);
+    int Y = (cy + e.dY) % ny;
+    int Z = (cz + e.dZ) % nz;
+    X = X < 0 ? X + 2 * nx : X;
+    Y = Y < 0 ? Y + ny : Y;
+    Z = Z < 0 ? Z + nz : Z;
+    return (int64_t)(X & 1) * ncell + ((int64_t)Z * ny + Y) * nx + (X >> 1);
+}
+
+// The float64 decision r^2 < rc^2 for the pair (i, its neighbour of entry e), with
+// the separation formed as the float64 passes form it.
+__device__ __forceinline__ bool pair_in_rc64(const double *__restrict__ ux, const double *__restrict__ uy,
+                                             const double *__restrict__ uz, int64_t i, int cx, int cy, int cz,
+                                             int p, const NearEntry &e, int nx, int ny, int nz, int64_t ncell,
+                                             double rc2) {
+    const int64_t j = offset_site(cx, cy, cz, p, e, nx, ny, nz, ncell);
+    const double dx = (ux[j] - ux[i]) + e.ox;
+    const double dy = (uy[j] - uy[i]) + e.oy;
+    const double dz = (uz[j] - uz[i]) + e.oz;
+    return dx * dx + dy * dy + dz * dz < rc2;
+}
+
 // Interpolation table metadata (records live in device memory).
 template <typename Real>
 struct TabMeta {
@@ -151,6 +209,15 @@ struct Geom {
     double reach;           // (rc + delta) / a
 };
 
+// The other copy of the displacements and velocities.  A step's kick-drift reads
+// the current copy and writes this one, which then becomes current; the copy it
+// read still holds the state at the start of the step, so a step whose leavers
+// overflow the run-away capacity can be undone exactly (Algorithm 2; the state is
+// left at the start of the failing step).
+struct UV {
+    double *ux, *uy, *uz, *vx, *vy, *vz;
+};
+
 // Caller-owned state, carved from the bound buffer.
 struct State {
     double *ux, *uy, *uz;
@@ -168,9 +235,12 @@ struct Counters {
     int32_t n_run;        // run-away atoms in the list
     int32_t n_leave;      // atoms that left their slot this step
     int32_t n_affected;   // lattice atoms within rc of a run-away atom
-    int32_t overflow;     // run-away capacity exceeded
+    int32_t overflow;     // 0; 1: this step's leavers exceed the run-away capacity; 2: the state
+                          // is back at the start of that step and the call's later steps are frozen
     uint32_t range_viol;  // densities beyond the embedding table
-    int32_t pad[3];
+    int32_t steps;        // steps completed in the current misa_step call
+    int32_t fail_step;    // with overflow: index in the call of the step that overflowed
+    int32_t pad;
 };
 
 // Library scratch (hipMalloc'd by the handle).
@@ -274,6 +344,7 @@ struct BoxRef {
     Scratch sc;
     Geom g;
     int64_t rcap;
+    UV alt;  // the kick-drift's destination (the other copy)
 };
 
 // Surrogate networks attached to a handle of the learned form (device copies).
@@ -308,6 +379,8 @@ struct misa_lattice {
     double d_min = 0.0;                           // nearest-neighbour site distance
     int n_cu = 0;                                 // compute units of the device
     int persistent_grid = 0;                      // work-groups of the persistent kernels (multiple of 8)
+    misa::NearTab *near_g = nullptr;              // float64 cut-off re-decision, gather order (device)
+    misa::NearTab *near_h = nullptr;              // the same in half-stencil order
     misa::StencilEntry<float> *st32p = nullptr;   // stencil with LDS offsets of the 8x8x8 tiles
     misa::StencilEntry<double> *st64p = nullptr;  // the same offsets, float64 separations
     misa::NodeWin64 lds64;                        // f nodes for the persistent float64 density pass
@@ -321,10 +394,15 @@ struct misa_lattice {
                                                   // owned pair (half), [K][nsites], rho pass -> force pass
     misa::LdsTables lds32h;                       // smaller window for the half-stencil passes
     bool tables_set = false;
+    // host copy of the last misa_set_potential_tables samples (f, phi, F), kept so the
+    // tables can be rebuilt after the neighbour-count export swaps f for a unit table
+    std::vector<double> tab_y[3];
+    misa_table tab[3] = {};
     misa::Scratch sc{};
     void *state_ptr = nullptr;
     int64_t state_bytes = 0;
-    misa::State S{};
+    misa::State S{};                              // current view of the state
+    misa::UV alt{};                               // the other copy of u and v (kick-drift destination)
     bool state_bound = false, state_set = false, rho_valid = false, force_valid = false;
     bool pending_clear = false;                   // hash and marks of a rho pass await the force pass
     int64_t n_atoms = 0;
@@ -337,8 +415,9 @@ struct misa_lattice {
     bool use_graph = false;
     uint64_t gen = 0;                     // advances whenever captured kernel arguments go stale
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    double graph_dt = 0.0, graph_dx = 0.0;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // one per copy a step starts from
+    double graph_dt[2] = {0.0, 0.0}, graph_dx[2] = {0.0, 0.0};
+    int parity = 0;                               // which copy of u and v is current (0: the first)
     // optional event timing of kernel groups
     bool timing = false;
     struct TimedGroup {
@@ -353,6 +432,9 @@ struct misa_lattice {
 };
 
 namespace misa {
+
+// Float64 cut-off re-decision of the float32 passes (gather or half-stencil order).
+inline const NearTab *near_args(const misa_lattice *h, bool half) { return half ? h->near_h : h->near_g; }
 
 // ----------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).  All enqueue on h->stream.
@@ -390,16 +472,23 @@ hipError_t launch_runaway_build(misa_lattice *h);      // keys, sort, hash inser
 hipError_t launch_runaway_rho(misa_lattice *h);        // run-away rho + affected-site fixup
 hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick);
 hipError_t launch_runaway_clear(misa_lattice *h);      // hash and marks back to empty
-hipError_t launch_kick_drift(misa_lattice *h);         // lattice + run-aways, leavers appended
+// lattice + run-aways, leavers appended; the lattice kick-drift writes the other copy of
+// u and v, which becomes current (h->S and h->alt swap); the run-away kick-drift then
+// undoes the step if its leavers overflowed
+hipError_t launch_kick_drift(misa_lattice *h);
+void swap_uv(misa_lattice *h);                         // exchange h->S's u, v with h->alt
 hipError_t launch_rehash(misa_lattice *h);             // sort leavers, claims, settle, compact
 hipError_t launch_final_kick(misa_lattice *h);         // + vmax / KE partials
 hipError_t launch_dt_update(misa_lattice *h, double dt_max, double dx_max, bool first);
 hipError_t launch_gather_state(misa_lattice *h, double *x, double *v);
+hipError_t launch_fill_u32(misa_lattice *h, uint32_t *a, uint32_t value, int64_t n);  // a[0..n) = value
 // placement of (n, 3) device positions / velocities into cleared slots; the rest to the leaver list
 hipError_t launch_place(misa_lattice *h, const double *x, const double *v, int64_t n, int32_t *cand,
                         uint32_t *bad);
 // batched replicas: one launch per kernel over every box (blockIdx.y = box)
-hipError_t launchb_kick_drift(hipStream_t st, const BoxRef *boxes, int nbox, int gx_sites, int gx_small, double kf);
+// boxes: the box table of the step's start; boxes_after: the same with each box's u, v copies swapped
+hipError_t launchb_kick_drift(hipStream_t st, const BoxRef *boxes, const BoxRef *boxes_after, int nbox, int gx_sites,
+                              int gx_small, double kf);
 hipError_t launchb_final_kick_runaway(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small, double kf);
 hipError_t launchb_dt_update(hipStream_t st, const BoxRef *boxes, int nbox, double mass, double dt_max, double dx_max);
 hipError_t launchb_rehash(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_mlp(const double *__restri
                                                           const StencilEntry<float> *__restrict__ st, int K,
                                                           Tables<float> T, MlpSet M, Geom g,
                                                           uint32_t *__restrict__ range_viol,
-                                                          float *__restrict__ dfbuf) {
+                                                          float *__restrict__ dfbuf, const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[TILE_SITES];
     __shared__ MlpLds Lf, Le;
     const int tid = tile_of_block(blockIdx.x, g);
@@ -108,7 +108,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_rho_mlp(const double *__restri
         float y, dyt;
         mlp_wave<true>(Lf, Af, net_t(nf, r), y, dyt);
         float dfr = 0.0f;
-        if (r2 < rc2) {
+        bool in = r2 < rc2;
+        if (active && fabsf(r2 - rc2) < RC_BAND_Q)  // cut-off decided again in float64 (NearTab)
+            in = pair_in_rc64(ux, uy, uz, idx, gx, gy, gz, p, nt->st[p][k], g.nx, g.ny, g.nz, g.ncell, nt->rc2);
+        if (in) {
             float v = nf.y_shift + nf.y_scale * y;
             dfr = kfd * dyt;
             if (!mlp_serves(nf, r)) {
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_mlp(
     const double *__restrict__ ux, const double *__restrict__ uy, const double *__restrict__ uz,
     const float *__restrict__ fp, const float *__restrict__ rho, float *__restrict__ fx, float *__restrict__ fy,
     float *__restrict__ fz, const StencilEntry<float> *__restrict__ st, int K, Tables<float> T, MlpSet M, Geom g,
-    double *__restrict__ part, const float *__restrict__ dfbuf) {
+    double *__restrict__ part, const float *__restrict__ dfbuf, const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[TILE_SITES];
     __shared__ MlpLds Lp, Le;
     __shared__ double red[2][TILE_THREADS / 64];
@@ -196,7 +199,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_force_mlp(
         const float dfr = active ? dfbuf[(int64_t)k * g.nsites + idx] : 0.0f;  // f'(r) from the rho pass
         float yp, dp;
         mlp_wave<true>(Lp, Ap, net_t(np, r), yp, dp);
-        if (r2 < rc2) {
+        bool in = r2 < rc2;
+        if (active && fabsf(r2 - rc2) < RC_BAND_Q)  // cut-off decided again in float64 (NearTab)
+            in = pair_in_rc64(ux, uy, uz, idx, gx, gy, gz, p, nt->st[p][k], g.nx, g.ny, g.nz, g.ncell, nt->rc2);
+        if (in) {
             float dph = kp * dp, ph = np.y_shift + np.y_scale * yp;
             if (!mlp_serves(np, r)) {
                 int s;
@@ -279,7 +285,7 @@ hipError_t launch_rho_mlp(misa_lattice *h) {
     const Geom &g = h->g;
     hipLaunchKernelGGL(k_rho_mlp, dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
                        (float *)h->S.rho, (float *)h->S.fp, h->st32, h->K, t32_tables(h), mlp_set_of(h), g,
-                       &h->sc.cnt->range_viol, h->pairbuf);
+                       &h->sc.cnt->range_viol, h->pairbuf, near_args(h, false));
     return hipGetLastError();
 }
 
@@ -289,7 +295,8 @@ hipError_t launch_force_mlp(misa_lattice *h, bool energy) {
     auto kern = energy ? k_force_mlp<true> : k_force_mlp<false>;
     hipLaunchKernelGGL(kern, dim3(g.ntiles_pad), dim3(TILE_THREADS), 0, h->stream, h->S.ux, h->S.uy, h->S.uz,
                        (const float *)h->S.fp, (const float *)h->S.rho, (float *)h->S.fx, (float *)h->S.fy,
-                       (float *)h->S.fz, h->st32, h->K, t32_tables(h), mlp_set_of(h), g, h->sc.part, h->pairbuf);
+                       (float *)h->S.fz, h->st32, h->K, t32_tables(h), mlp_set_of(h), g, h->sc.part, h->pairbuf,
+                       near_args(h, false));
     return hipGetLastError();
 }
 

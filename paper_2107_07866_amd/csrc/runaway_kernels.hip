@@ -141,16 +141,27 @@ __device__ __forceinline__ void min_image3(double d[3], const Geom &g) {
 
 // ---------------------------------------------------------------------------
 // single-block bitonic sort of 64-bit keys (ascending); mode 0: leavers by atom
-// id, mode 1: run-aways by (coarse cell, list index)
+// id, mode 1: run-aways by (coarse cell, list index).  Mode 0 first freezes a step
+// that the run-away kick-drift has just undone after an overflow: no leavers, dt = 0
+// for the rest of the call (the step length is kept in scal[7]), and the step's index.
 
 __device__ __forceinline__ void sort_body(uint64_t *__restrict__ buf, int mode,
                                                         Counters *__restrict__ cnt, int64_t rcap,
                                                         const int32_t *__restrict__ l_id,
                                                         const double *__restrict__ rx, const double *__restrict__ ry,
-                                                        const double *__restrict__ rz, Geom g) {
+                                                        const double *__restrict__ rz, Geom g,
+                                                        double *__restrict__ scal) {
     __shared__ uint64_t sh[SORT_LDS_MAX];
     int n;
     if (mode == 0) {
+        if (threadIdx.x == 0 && cnt->overflow == 1) {
+            scal[7] = scal[0];
+            scal[0] = 0.0;
+            cnt->n_leave = 0;
+            cnt->fail_step = cnt->steps;
+            cnt->overflow = 2;
+        }
+        __syncthreads();
         // leavers beyond the run-away capacity were not recorded (they kept their slots)
         const int nl = cnt->n_leave;
         const int room = (int)(rcap - cnt->n_run);
@@ -218,13 +229,14 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort(uint64_t *__restrict__ bu
                                                         Counters *__restrict__ cnt, int64_t rcap,
                                                         const int32_t *__restrict__ l_id,
                                                         const double *__restrict__ rx, const double *__restrict__ ry,
-                                                        const double *__restrict__ rz, Geom g) {
-    sort_body(buf, mode, cnt, rcap, l_id, rx, ry, rz, g);
+                                                        const double *__restrict__ rz, Geom g,
+                                                        double *__restrict__ scal) {
+    sort_body(buf, mode, cnt, rcap, l_id, rx, ry, rz, g, scal);
 }
 
 __global__ __launch_bounds__(SORT_THREADS) void kb_sort(const BoxRef *__restrict__ boxes, int mode) {
     const BoxRef &B = boxes[blockIdx.y];
-    sort_body(B.sc.sortbuf, mode, B.sc.cnt, B.rcap, B.sc.l_id, B.S.r_x, B.S.r_y, B.S.r_z, B.g);
+    sort_body(B.sc.sortbuf, mode, B.sc.cnt, B.rcap, B.sc.l_id, B.S.r_x, B.S.r_y, B.S.r_z, B.g, B.sc.scal);
 }
 
 
@@ -1069,7 +1081,7 @@ static Tables<float> t32_of(misa_lattice *h) {
 hipError_t launch_rehash(misa_lattice *h) {
     hipStream_t st = h->stream;
     hipLaunchKernelGGL(k_sort, dim3(1), dim3(SORT_THREADS), 0, st, h->sc.sortbuf, 0, h->sc.cnt, h->rcap, h->sc.l_id,
-                       nullptr, nullptr, nullptr, h->g);
+                       nullptr, nullptr, nullptr, h->g, h->sc.scal);
     hipLaunchKernelGGL(k_claim, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g);
     hipLaunchKernelGGL(k_settle, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, h->S, h->sc);
@@ -1079,7 +1091,7 @@ hipError_t launch_rehash(misa_lattice *h) {
 hipError_t launch_runaway_build(misa_lattice *h) {
     hipStream_t st = h->stream;
     hipLaunchKernelGGL(k_sort, dim3(1), dim3(SORT_THREADS), 0, st, h->sc.sortbuf, 1, h->sc.cnt, h->rcap, nullptr,
-                       h->S.r_x, h->S.r_y, h->S.r_z, h->g);
+                       h->S.r_x, h->S.r_y, h->S.r_z, h->g, h->sc.scal);
     hipLaunchKernelGGL(k_hash_insert, dim3(SMALL_GRID), dim3(256), 0, st, h->sc);
     return hipGetLastError();
 }

@@ -92,6 +92,17 @@ class Lattice:
     def stencil(self):
         return M.misa_debug_export(self.h, M.MISA_EXPORT_STENCIL)
 
+    def save_checkpoint(self):
+        """The whole state (bit-exact resume with load_checkpoint) as a uint8 numpy array."""
+        return M.misa_save_checkpoint(self.h)
+
+    def load_checkpoint(self, buf):
+        M.misa_load_checkpoint(self.h, buf)
+
+    def neighbour_counts(self):
+        """Per atom: partners within rc as the density pass of this form counts them."""
+        return M.misa_debug_export(self.h, M.MISA_EXPORT_NEIGHBOURS)
+
     def defects(self):
         return M.misa_defects(self.h)
 

@@ -21,7 +21,7 @@ MISA_OK, MISA_EINVAL, MISA_ENOMEM, MISA_EHIP, MISA_ESTATE, MISA_EOVERFLOW = 0, -
 MISA_FP64, MISA_FP32 = 0, 1
 MISA_HOST, MISA_DEVICE = 0, 1
 MISA_FIELD_RHO, MISA_FIELD_FPRIME, MISA_FIELD_FORCE = 0, 1, 2
-MISA_EXPORT_STENCIL, MISA_EXPORT_SLOTS = 0, 1
+MISA_EXPORT_STENCIL, MISA_EXPORT_SLOTS, MISA_EXPORT_NEIGHBOURS = 0, 1, 2
 MISA_MLP = 2
 MISA_PAIRS_GATHER, MISA_PAIRS_HALF = 0, 1
 # batch tile shapes (x, y, z cells), in the library's order
@@ -54,7 +54,7 @@ class misa_step_stats(C.Structure):
     _fields_ = [("dt", C.c_double), ("dt_next", C.c_double), ("vmax", C.c_double), ("e_kin", C.c_double),
                 ("e_emb", C.c_double), ("e_pair", C.c_double), ("time", C.c_double), ("steps", C.c_int64),
                 ("n_runaway", C.c_int64), ("range_violations", C.c_int64), ("overflow", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("failed_step", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -92,6 +92,9 @@ def _load():
         "misa_set_potential_tables": ([vp, C.POINTER(misa_table), C.POINTER(misa_table), C.POINTER(misa_table)],
                                       C.c_int),
         "misa_set_state": ([vp, vp, vp, i64, C.c_int], C.c_int),
+        "misa_checkpoint_bytes": ([vp, C.POINTER(i64)], C.c_int),
+        "misa_save_checkpoint": ([vp, vp, i64], C.c_int),
+        "misa_load_checkpoint": ([vp, vp, i64], C.c_int),
         "misa_get_state": ([vp, vp, vp, C.c_int], C.c_int),
         "misa_atom_count": ([vp, C.POINTER(i64)], C.c_int),
         "misa_compute_rho": ([vp], C.c_int),
@@ -221,6 +224,26 @@ def misa_set_state(h, x, v):
     return _check(lib.misa_set_state(h, px, pv, n, where), h)
 
 
+def misa_checkpoint_bytes(h):
+    """Size in bytes of the handle's checkpoint."""
+    n = C.c_int64()
+    _check(lib.misa_checkpoint_bytes(h, C.byref(n)), h)
+    return n.value
+
+
+def misa_save_checkpoint(h):
+    """The handle's whole state as a numpy uint8 array (host memory)."""
+    n = misa_checkpoint_bytes(h)
+    buf = np.empty(n, dtype=np.uint8)
+    _check(lib.misa_save_checkpoint(h, C.c_void_p(buf.ctypes.data), n), h)
+    return buf
+
+
+def misa_load_checkpoint(h, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    return _check(lib.misa_load_checkpoint(h, C.c_void_p(buf.ctypes.data), buf.size), h)
+
+
 def misa_atom_count(h):
     n = C.c_int64()
     _check(lib.misa_atom_count(h, C.byref(n)), h)
@@ -251,8 +274,10 @@ def misa_compute_force(h, energies_dev=None):
 def misa_step(h, nsteps, dt_max, dx_max=0.0, want_stats=True):
     st = misa_step_stats()
     code = lib.misa_step(h, int(nsteps), float(dt_max), float(dx_max), C.byref(st) if want_stats else None)
-    if code == MISA_EOVERFLOW:
-        raise MisaError(code, misa_last_error(h))
+    if code == MISA_EOVERFLOW:  # the statistics of the state the call stopped at go with the error
+        err = MisaError(code, misa_last_error(h))
+        err.stats = st.as_dict() if want_stats else None
+        raise err
     _check(code, h)
     return st.as_dict() if want_stats else None
 
@@ -432,14 +457,16 @@ def _bcheck(code, b=None):
 
 
 def misa_batch_create(boxes, a, rc, delta, mass, runaway_capacity=0, hip_stream=None):
-    """boxes: list of n_cells triples; every box uses MISA_FP32 and the same a, rc, delta, mass."""
+    """boxes: list of n_cells triples; every box uses MISA_FP32 and the same a, rc, delta, mass;
+    runaway_capacity: one value for every box or one per box."""
     n = len(boxes)
+    caps = list(runaway_capacity) if hasattr(runaway_capacity, "__len__") else [runaway_capacity] * n
     descs = (misa_lattice_desc * n)()
     for k, nc in enumerate(boxes):
         d = descs[k]
         d.n_cells[:] = [int(c) for c in nc]
         d.pair_precision, d.a, d.rc, d.delta, d.mass = MISA_FP32, float(a), float(rc), float(delta), float(mass)
-        d.runaway_capacity = int(runaway_capacity)
+        d.runaway_capacity = int(caps[k])
     b = C.c_void_p()
     _bcheck(lib.misa_batch_create(descs, n, C.c_void_p(hip_stream or 0), C.byref(b)))
     return b
@@ -469,6 +496,10 @@ def misa_batch_set_potential_tables(b, f, phi, emb):
 def misa_batch_step(b, n_boxes, nsteps, dt_max, dx_max=0.0, want_stats=True):
     st = (misa_step_stats * n_boxes)()
     code = lib.misa_batch_step(b, int(nsteps), float(dt_max), float(dx_max), st if want_stats else None)
+    if code == MISA_EOVERFLOW:  # the statistics of every box go with the error
+        err = MisaError(code, misa_batch_last_error(b))
+        err.stats = [st[k].as_dict() for k in range(n_boxes)] if want_stats else None
+        raise err
     _bcheck(code, b)
     return [st[k].as_dict() for k in range(n_boxes)] if want_stats else None
 

@@ -13,7 +13,11 @@ rule, the whole-box energy (4.2 M atoms) and a 10-step trajectory (4.2 M atoms).
 
 Bars: FP64 forces within 1e-6 of the rms force (max |dF| / rms |F|), densities
 and F' within 1e-12 relative; FP32 pair arithmetic within the loose bounds
-derived for float32 sums (force 1e-3, density 1e-5 relative).
+derived for float32 sums (force 1e-3, density 1e-5 relative).  Beside the rms
+measure, which the 25-50 eV/A forces next to the recoils inflate, every sampled
+atom farther than 2 rc from all recoil atoms is held to a per-atom bound,
+|dF_i| / max(|F_i|, rms over those atoms): 1e-9 (FP64), 1e-4 (FP32).  The
+per-atom neighbour counts of the density pass equal the oracle's on the sample.
 """
 import numpy as np
 import pytest
@@ -24,8 +28,8 @@ pytestmark = pytest.mark.gpu
 
 A, RC, DELTA, M = w.A_FE, w.RC, w.DELTA, w.MASS_FE
 TABLES = w.potential_samples()
-BARS = {"fp64": dict(F=1e-6, rho=1e-12, fp=1e-11, sumF=1e-9),
-        "fp32": dict(F=1e-3, rho=1e-5, fp=1e-5, sumF=1e-5)}
+BARS = {"fp64": dict(F=1e-6, rho=1e-12, fp=1e-11, sumF=1e-9, Fth=1e-9),
+        "fp32": dict(F=1e-3, rho=1e-5, fp=1e-5, sumF=1e-5, Fth=1e-4)}
 
 
 @pytest.fixture(scope="module")
@@ -55,8 +59,21 @@ def _sample(orc, x, box, rec, n_random, seed):
     return np.unique(np.concatenate(picks))
 
 
-def _check_sampled(orc, pot, lat, box, sample, form, what):
-    """Per-atom rho, F' and forces of the lattice's current state on the sample."""
+def thermal_mask(x, box, sample, hot):
+    """Sampled atoms farther than 2 rc from every atom of `hot` (minimum image)."""
+    L = np.asarray(box)
+    far = np.ones(len(sample), bool)
+    for i in hot:
+        d = x[sample] - x[int(i)]
+        d -= L * np.rint(d / L)
+        far &= np.einsum("ij,ij->i", d, d) > (2 * RC) ** 2
+    return far
+
+
+def _check_sampled(orc, pot, lat, box, sample, form, what, hot=()):
+    """Per-atom rho, F', forces and neighbour counts of the lattice's current state on
+    the sample; hot: the recoil atoms (their surroundings are excluded from the
+    per-atom thermal measure)."""
     xg, vg = lat.get_state()
     F, rho, fp = lat.forces(), lat.rho(), lat.fprime()
     ref = orc.eam_sampled(pot, xg, box, sample)
@@ -65,9 +82,19 @@ def _check_sampled(orc, pot, lat, box, sample, form, what):
     nz = ref["rho"] > 0
     rerr = float(np.max(np.abs(rho[sample][nz] - ref["rho"][nz]) / ref["rho"][nz]))
     fperr = float(np.max(np.abs(fp[sample][nz] - ref["fp"][nz]) / np.abs(ref["fp"][nz])))
-    _say(f"  {form} {what}: {len(sample)} sampled atoms, force {ferr:.2e} rho {rerr:.2e} F' {fperr:.2e}")
+    th = thermal_mask(xg, box, sample, hot)
+    fth = np.linalg.norm(ref["F"][th], axis=1)
+    rms_th = float(np.sqrt(np.mean(fth ** 2)))
+    dth = np.linalg.norm(F[sample][th] - ref["F"][th], axis=1)
+    therr = float(np.max(dth / np.maximum(fth, rms_th)))
+    _say(f"  {form} {what}: {len(sample)} sampled atoms, force {ferr:.2e} rho {rerr:.2e} F' {fperr:.2e}; "
+         f"{int(th.sum())} thermal atoms, per-atom force {therr:.2e}")
     b = BARS[form]
     assert ferr <= b["F"] and rerr <= b["rho"] and fperr <= b["fp"], (form, what, ferr, rerr, fperr)
+    assert therr <= b["Fth"], (form, what, therr)
+    cnt = lat.neighbour_counts()[sample]
+    assert np.array_equal(cnt, ref["npairs"]), (form, what, np.nonzero(cnt != ref["npairs"])[0][:8])
+    lat.compute()  # the count export rebuilt the tables: densities and forces of this state again
     assert np.all(rho[sample][~nz] == 0.0)
     # Newton's third law over the whole box
     assert np.max(np.abs(F.sum(axis=0))) <= b["sumF"] * float(np.abs(F).sum()), (form, what)
@@ -101,10 +128,10 @@ def test_c3_full_box_sampled_parity(torch_cuda, orc, pot, form):
     lat.set_state(x, v)
     lat.compute()
     torch.cuda.synchronize()
-    _check_sampled(orc, pot, lat, box, sample, form, "placed state")
+    _check_sampled(orc, pot, lat, box, sample, form, "placed state", rec)
     st = lat.step(20, cfg.dt_max, cfg.dx_max)
     torch.cuda.synchronize()
-    _, vg = _check_sampled(orc, pot, lat, box, sample, form, "after 20 steps")
+    _, vg = _check_sampled(orc, pot, lat, box, sample, form, "after 20 steps", rec)
     _check_stats(st, vg, cfg.dt_max, cfg.dx_max, f"{form} 20 steps")
     assert st["n_runaway"] >= len(rec)
     d = lat.defects()
@@ -155,7 +182,7 @@ def test_c2_full_box_trajectory_and_energy(torch_cuda, orc, pot):
         lat.set_state(x, v)
         st = lat.step(40, cfg.dt_max, cfg.dx_max)
         torch.cuda.synchronize()
-        xg, vg = _check_sampled(orc, pot, lat, box, sample, form, "after 40 steps")
+        xg, vg = _check_sampled(orc, pot, lat, box, sample, form, "after 40 steps", rec)
         _check_stats(st, vg, cfg.dt_max, cfg.dx_max, f"{form} 40 steps")
         assert st["n_runaway"] >= 1
         ref = orc.eam(pot, xg, box, cells=True)
