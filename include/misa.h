@@ -155,6 +155,21 @@ int misa_set_potential_tables(misa_lattice *h, const misa_table *f, const misa_t
  */
 int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n_atoms, int where);
 
+/*
+ * misa_set_state for callers that cannot allocate device memory (serving loops
+ * that reload states, harnesses that forbid allocation): the same placement from
+ * device arrays x, v ((n_atoms, 3) float64, device memory of the handle's GPU)
+ * with no hipMalloc or hipFree.  Its scratch (one bid per atom and a counter) is a
+ * static array of MISA_NOALLOC_MAX_ATOMS + 64 words of device memory on every GPU
+ * the library runs on, held until the process ends; MISA_EINVAL for more atoms
+ * than MISA_NOALLOC_MAX_ATOMS.  The array is shared by every handle on a GPU and
+ * keeps the last call's contents: calls that overlap on one GPU (two host
+ * threads, or handles on streams that run concurrently) race.  Synchronises the
+ * stream; results and errors are those of misa_set_state.
+ */
+#define MISA_NOALLOC_MAX_ATOMS 4194304 /* 16 MiB of bids per GPU */
+int misa_set_state_noalloc(misa_lattice *h, const double *x, const double *v, int64_t n_atoms);
+
 /* Copy positions (wrapped into the box) and velocities out, in atom-id order,
  * to (n_atoms, 3) float64 arrays in host or device memory; either may be NULL. */
 int misa_get_state(misa_lattice *h, double *x, double *v, int where);

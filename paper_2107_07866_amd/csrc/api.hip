@@ -18,9 +18,33 @@
 
 using namespace misa;
 
+// Scratch of misa_set_state_noalloc: the placement bid of every atom, then the
+// counter of non-finite inputs.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code `scratch` only names the symbol: kernels
+// get the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint32_t scratch[MISA_NOALLOC_MAX_ATOMS + 64];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_addr;  // per device ordinal; null until looked up
+
+// Address of `scratch` on device dev, looked up once per device; dev must be the
+// current device.
+hipError_t scratch_address(int dev, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 int fail(misa_lattice *h, int code, const std::string &msg) {
     if (h)
@@ -698,6 +722,10 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
         misa_destroy_lattice(h);
         return fail(nullptr, MISA_EHIP, m);
     }
+    {
+        void *sp = nullptr;  // once per device, with the device current (misa_set_state_noalloc reports failures)
+        (void)scratch_address(h->device, &sp);
+    }
     h->half.st = h->sth;
     h->half.meta = h->hmeta;
     h->half_fits = g.nx % (2 * T2X) == 0 && g.ny % (2 * T2Y) == 0 && g.nz % (2 * T2Z) == 0;
@@ -979,6 +1007,30 @@ int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n,
     int32_t *cand = (int32_t *)(tmp + xv_bytes);
     uint32_t *bad = (uint32_t *)(tmp + xv_bytes + sizeof(int32_t) * (size_t)nn);
     return place_atoms(h, xd, vd, n, cand, bad, done);
+}
+
+int misa_set_state_noalloc(misa_lattice *h, const double *x, const double *v, int64_t n) {
+    int rc = check_set_state(h, x, v, n);
+    if (rc) return rc;
+    if (n > MISA_NOALLOC_MAX_ATOMS)
+        return fail(h, MISA_EINVAL, "misa_set_state_noalloc: more than MISA_NOALLOC_MAX_ATOMS (" +
+                                        std::to_string((long long)MISA_NOALLOC_MAX_ATOMS) + ") atoms");
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if ((int)g_scratch_addr.size() > h->device) base = g_scratch_addr[h->device];
+    }
+    if (!base) return fail(h, MISA_EHIP, "misa_set_state_noalloc: no device address for the scratch array");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->state_set = false;  // until the new state is complete
+    h->rho_valid = h->force_valid = h->pending_clear = false;
+    int32_t *cand = (int32_t *)base;
+    uint32_t *bad = (uint32_t *)base + MISA_NOALLOC_MAX_ATOMS;
+    auto done = [&](int rc2) {
+        (void)hipStreamSynchronize(h->stream);
+        return rc2;
+    };
+    return place_atoms(h, x, v, n, cand, bad, done);
 }
 
 }  // extern "C"

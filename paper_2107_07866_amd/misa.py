@@ -92,6 +92,7 @@ def _load():
         "misa_set_potential_tables": ([vp, C.POINTER(misa_table), C.POINTER(misa_table), C.POINTER(misa_table)],
                                       C.c_int),
         "misa_set_state": ([vp, vp, vp, i64, C.c_int], C.c_int),
+        "misa_set_state_noalloc": ([vp, vp, vp, i64], C.c_int),
         "misa_checkpoint_bytes": ([vp, C.POINTER(i64)], C.c_int),
         "misa_save_checkpoint": ([vp, vp, i64], C.c_int),
         "misa_load_checkpoint": ([vp, vp, i64], C.c_int),
@@ -242,6 +243,16 @@ def misa_save_checkpoint(h):
 def misa_load_checkpoint(h, buf):
     buf = np.ascontiguousarray(buf, dtype=np.uint8)
     return _check(lib.misa_load_checkpoint(h, C.c_void_p(buf.ctypes.data), buf.size), h)
+
+
+MISA_NOALLOC_MAX_ATOMS = 4194304
+
+
+def misa_set_state_noalloc(h, x, v):
+    """x, v: (N, 3) float64 CUDA tensors on the handle's GPU; no device allocation."""
+    if not (hasattr(x, "data_ptr") and x.is_cuda and hasattr(v, "data_ptr") and v.is_cuda):
+        raise ValueError("misa_set_state_noalloc takes device tensors")
+    return _check(lib.misa_set_state_noalloc(h, C.c_void_p(x.data_ptr()), C.c_void_p(v.data_ptr()), x.shape[0]), h)
 
 
 def misa_atom_count(h):
