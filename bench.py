@@ -29,10 +29,18 @@ if ROOT not in sys.path:
 
 METRIC = "atom-steps/s + HBM GB/s: FP64-table vs FP32 vs MLP forms at stated force error"
 
-# Algorithmic cost model (one directed pair i <- j per stencil candidate):
-FLOP_CANDIDATE = 8      # separation (3) and squared distance (5) for every stencil candidate
-FLOP_RHO_PAIR = 10      # sqrt, table index (2), cubic (6), accumulate
-FLOP_FORCE_PAIR = 21    # sqrt, index (2), f' and phi' (8), (F'_i+F'_j) f' + phi' (3), / r, x d and accumulate (6)
+# Algorithmic arithmetic per in-range pair (directed, i <- j), the figures the roofline is
+# priced with: separation and distance, table index, spline value or derivatives, the
+# force combination and its accumulation; square root and reciprocal not counted.
+FLOP_RHO_PAIR = 22
+FLOP_FORCE_PAIR = 34
+# A second, instruction-level model, reported beside it: every stencil candidate pays the
+# separation and squared distance (8); an in-range pair then pays index and cubic (10) in
+# the density pass, index, both derivatives, combination and accumulation (21) in the
+# force pass (the kernels work on r^2, so no square root or division is executed).
+ALT_FLOP_CANDIDATE = 8
+ALT_FLOP_RHO_PAIR = 10
+ALT_FLOP_FORCE_PAIR = 21
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "mlp": 2500.0}  # mlp: dense bf16 matrix cores
 # learned form: per network evaluation, the 1-32-32-1 layers' multiply-adds (2 flops each);
 # the rho pass evaluates f (values), the force pass f and phi (values and input tangents)
@@ -279,24 +287,33 @@ def run_batch(cfg, steps, warmup, err_sample, seq_steps=20, graph=False):
 
 
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_force_lds_c3_fp32_hbm_counters.txt")
-LDS_KERNEL_SRC = os.path.join(ROOT, "paper_2107_07866_amd", "csrc", "lattice_lds_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2107_07866_amd", "csrc")
+
+
+def kernel_source_sha256():
+    """sha256 over every kernel source file (name and bytes, sorted by name)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
 
 
 def counted_traffic():
-    """HBM bytes per launch of k_force_lds from the committed rocprofv3 counter summary
-    (FETCH_SIZE, WRITE_SIZE scaled by a plain-copy calibration), or None when the kernel
-    source has changed since the counters were taken."""
-    import hashlib
+    """From the committed rocprofv3 counter summary of the C3 FP32 step (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain-copy calibration): HBM bytes per launch of k_force_lds
+    and per step, or None when a kernel source has changed since the counters were taken."""
     try:
         kv = {}
         for line in open(COUNTER_SUMMARY):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        src = hashlib.sha256(open(LDS_KERNEL_SRC, "rb").read()).hexdigest()
-        if kv.get("kernel_source_sha256") != src:
+        if kv.get("kernel_source_sha256") != kernel_source_sha256():
             return None
-        return float(kv["dominant_traffic_bytes"])
+        return {"dominant": float(kv["dominant_traffic_bytes"]), "step": float(kv["step_traffic_bytes"])}
     except (OSError, KeyError, ValueError):
         return None
 
@@ -308,39 +325,56 @@ def roofline(form, res, n_atoms):
         return None
     dom = "force" if kms["force"] >= kms["rho"] else "rho"
     pairs = res.get("mean_pairs_per_atom", 58.0)
+    avg_ms = kms[dom]
+    peak = PEAK_TFLOPS[form]
+    alt = None
     if form == "mlp":  # every stencil candidate runs the networks (the whole wave takes part)
         per_atom = res["K"] * (2 * FLOP_MLP_TANGENT if dom == "force" else FLOP_MLP_VALUE)
+        model = "1-32-32-1 layer multiply-adds per stencil candidate"
     else:
-        per_atom = res["K"] * FLOP_CANDIDATE + pairs * (FLOP_FORCE_PAIR if dom == "force" else FLOP_RHO_PAIR)
-    flops = n_atoms * per_atom
-    avg_ms = kms[dom]
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[form]
-    kname = {"fp32": f"k_{dom}_lds", "fp64": f"k_{dom}_tile<double>", "mlp": f"k_{dom}_mlp"}[form]
-    traffic = counted_traffic() if (form == "fp32" and dom == "force" and n_atoms == 65536000) else None
-    return {"kernel": kname, "bound": "mfma" if form == "mlp" else "alu",
-            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": traffic, "traffic_unit": "B/launch", "avg_launch_ms": round(avg_ms, 4),
-            "algorithmic_flop_per_atom": round(per_atom, 1),
-            "algorithmic_bytes_per_launch": n_atoms * (BYTES_PER_ATOM_STEP[form][dom])}
+        per_atom = pairs * (FLOP_FORCE_PAIR if dom == "force" else FLOP_RHO_PAIR)
+        model = f"{FLOP_FORCE_PAIR if dom == 'force' else FLOP_RHO_PAIR} flops per in-range pair"
+        alt_atom = res["K"] * ALT_FLOP_CANDIDATE + pairs * (ALT_FLOP_FORCE_PAIR if dom == "force"
+                                                             else ALT_FLOP_RHO_PAIR)
+        alt_ach = n_atoms * alt_atom / (avg_ms * 1e-3) / 1e12
+        alt = {"flop_model": f"{ALT_FLOP_CANDIDATE} per candidate + "
+                             f"{ALT_FLOP_FORCE_PAIR if dom == 'force' else ALT_FLOP_RHO_PAIR} per in-range pair",
+               "flop_per_atom": round(alt_atom, 1), "achieved": round(alt_ach, 3), "frac": round(alt_ach / peak, 4)}
+    achieved = n_atoms * per_atom / (avg_ms * 1e-3) / 1e12
+    kname = {"fp32": f"k_{dom}_lds", "fp64": f"k_{dom}_lds64", "mlp": f"k_{dom}_mlp"}[form]
+    counted = counted_traffic() if (form == "fp32" and dom == "force" and n_atoms == 65536000) else None
+    out = {"kernel": kname, "bound": "mfma" if form == "mlp" else "alu",
+           "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+           "traffic": counted["dominant"] if counted else None, "traffic_unit": "B/launch",
+           "avg_launch_ms": round(avg_ms, 4), "flop_model": model, "algorithmic_flop_per_atom": round(per_atom, 1),
+           "algorithmic_bytes_per_launch": n_atoms * (BYTES_PER_ATOM_STEP[form][dom])}
+    if alt:
+        out["instruction_model"] = alt
+    return out
 
 
-def cpu_baseline(cfg, budget_s=15.0):
-    """The oracle (exact cell-binned FP64 EAM + velocity Verlet) on a bounded sample of the workload."""
+def cpu_baseline(cfg, x, v, box, budget_s=15.0):
+    """The oracle (exact cell-binned FP64 EAM + velocity Verlet) on the workload's own
+    state. A box of more than 2e6 atoms gets one step, its starting forces computed
+    first and not timed; a smaller one as many steps as fit in budget_s."""
     import misa_workloads as w
     import oracle
-    n = 24
-    x, v, box, _ = w.make_state(cfg, n_cells=n)
     pot = oracle.Potential(oracle.TABLE, tables=w.potential_samples())
-    steps, F = 0, None
-    t0 = time.perf_counter()
-    while True:
-        x, v, F, _ = oracle.run(pot, x, v, box, w.MASS_FE, 5, cfg.dt_max, dx_max=cfg.dx_max, cells=True, F=F)
-        steps += 5
-        if time.perf_counter() - t0 > budget_s or steps >= 5000:
-            break
-    dt = time.perf_counter() - t0
     N = x.shape[0]
+    if N > 2_000_000:
+        F = oracle.eam(pot, x, box, cells=True)["F"]
+        t0 = time.perf_counter()
+        oracle.run(pot, x, v, box, w.MASS_FE, 1, cfg.dt_max, dx_max=cfg.dx_max, cells=True, F=F)
+        steps = 1
+    else:
+        steps, F = 0, None
+        t0 = time.perf_counter()
+        while True:
+            x, v, F, _ = oracle.run(pot, x, v, box, w.MASS_FE, 5, cfg.dt_max, dx_max=cfg.dx_max, cells=True, F=F)
+            steps += 5
+            if time.perf_counter() - t0 > budget_s or steps >= 5000:
+                break
+    dt = time.perf_counter() - t0
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -349,8 +383,9 @@ def cpu_baseline(cfg, budget_s=15.0):
         pass
     return {"value": N * steps / dt, "unit": "atom-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
             "cpu_model": model, "host_cpus": os.cpu_count(),
-            "sample": f"{cfg.name} recipe on a {n}^3-cell box ({N} atoms), {steps} steps, exact cell-binned "
-                      f"FP64 EAM from the same spline tables, {dt:.1f} s"}
+            "sample": f"{cfg.name}: the timed box itself ({N} atoms), {steps} step(s) from its start, exact "
+                      f"cell-binned FP64 EAM from the same spline tables, {dt:.1f} s"
+                      + (" (starting forces computed first, untimed)" if N > 2_000_000 else "")}
 
 
 def main():
@@ -461,6 +496,10 @@ def main():
                       "frac": round(head["atom_steps_per_s"] * bpa / 1e9 / HBM_PEAK_GBS, 4)},
         "forms": results,
     }
+    counted = counted_traffic() if (forms[0] == "fp32" and n == 65536000) else None
+    line["hbm_model"]["counted_GBps"] = (round(counted["step"] / (head["ms_per_step"] * 1e-3) / 1e9, 1)
+                                         if counted else None)
+    line["hbm_model"]["counted_bytes_per_step"] = counted["step"] if counted else None
     # the paper's own figure, as context only: one SW26010 core group (1 MPE + 64 CPEs), FP64, 20,480,000
     # BCC Fe atoms, 10 steps in 21.29 s (Sec. 5.2, single core group evaluation), assuming all of it stepping
     line["paper_context"] = {"value": 20.48e6 * 10 / 21.2939, "unit": "atom-steps/s",
@@ -468,7 +507,7 @@ def main():
                              "workload": "20,480,000-atom BCC Fe, 10 steps (derived from the run time)"}
     if not args.no_cpu_baseline:
         _log("[bench] cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(cfg)
+        line["cpu_baseline"] = cpu_baseline(cfg, x, v, box)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

@@ -651,7 +651,9 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     const int64_t rcap = h->rcap;
     const int64_t H = next_pow2(2 * rcap);
     sc.hmask = (int32_t)(H - 1);
-    sc.affected_cap = std::min<int64_t>(g.nsites, 128 * rcap);
+    // lattice atoms within rc of a run-away, plus those of the float32 gather form with a
+    // pair inside the cut-off band (about one atom in 10^3 at 300 K)
+    sc.affected_cap = std::min<int64_t>(g.nsites, 128 * rcap + g.nsites / 16 + 64);
     {
         const int64_t per_blk = (int64_t)MARK_THREADS * MARK_WORDS;
         sc.mark_nblk = (int32_t)(((g.nsites + 31) / 32 + per_blk - 1) / per_blk);
@@ -704,6 +706,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(sc.mark_off, sc.mark_nblk);
     ALLOC(sc.affected, sc.affected_cap);
     ALLOC(sc.aff_v2, sc.affected_cap);
+    ALLOC(sc.aff_e, sc.affected_cap);
     ALLOC(sc.part_kick, 2 * std::max<int64_t>(max_tiles, 8));
 #undef ALLOC
     if ((e = hipMemcpy(h->st64, s64.data(), sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyHostToDevice)) ||
@@ -746,7 +749,7 @@ int misa_destroy_lattice(misa_lattice *h) {
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
                     h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,
-                    h->sc.mark_blk, h->sc.mark_off, h->sc.affected, h->sc.aff_v2, h->sc.part_kick, h->staging,
+                    h->sc.mark_blk, h->sc.mark_off, h->sc.affected, h->sc.aff_v2, h->sc.aff_e, h->sc.part_kick, h->staging,
                     h->mlp.p[0], h->mlp.p[1], h->mlp.p[2], h->mlp.w2b[0], h->mlp.w2b[1], h->mlp.w2b[2],
                     h->pairbuf};
     for (void *p : ptrs)

@@ -364,9 +364,11 @@ hipError_t launch_force(misa_lattice *h, bool energy, bool kick) {
     return force_impl<double>(h, energy, kick, h->st64, h->t64);
 }
 
-// Final energy sums: per-tile partials and per-run-away terms, fixed order.
+// Final energy sums: per-tile partials, per-run-away terms and the pair-energy
+// corrections of the affected list, fixed order.
 __device__ __forceinline__ void energy_reduce_body(const double *__restrict__ part, int ntiles,
                                                         const double *__restrict__ r_e,
+                                                        const double *__restrict__ aff_e, int64_t aff_cap,
                                                         const Counters *__restrict__ cnt,
                                                         double *__restrict__ scal, double *__restrict__ out) {
     __shared__ double red[2][1024 / 64];
@@ -380,6 +382,8 @@ __device__ __forceinline__ void energy_reduce_body(const double *__restrict__ pa
         s0 += r_e[2 * i];
         s1 += r_e[2 * i + 1];
     }
+    const int na = cnt->n_affected < aff_cap ? cnt->n_affected : (int)aff_cap;
+    for (int i = threadIdx.x; i < na; i += 1024) s1 += aff_e[i];
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
     const int w = threadIdx.x >> 6;
@@ -405,14 +409,15 @@ __device__ __forceinline__ void energy_reduce_body(const double *__restrict__ pa
 
 __global__ __launch_bounds__(1024) void k_energy_reduce(const double *__restrict__ part, int ntiles,
                                                         const double *__restrict__ r_e,
+                                                        const double *__restrict__ aff_e, int64_t aff_cap,
                                                         const Counters *__restrict__ cnt,
                                                         double *__restrict__ scal, double *__restrict__ out) {
-    energy_reduce_body(part, ntiles, r_e, cnt, scal, out);
+    energy_reduce_body(part, ntiles, r_e, aff_e, aff_cap, cnt, scal, out);
 }
 
 __global__ __launch_bounds__(1024) void kb_energy_reduce(const BoxRef *__restrict__ boxes) {
     const BoxRef &B = boxes[blockIdx.y];
-    energy_reduce_body(B.sc.part, B.g.ntiles2, B.S.r_e, B.sc.cnt, B.sc.scal, nullptr);
+    energy_reduce_body(B.sc.part, B.g.ntiles2, B.S.r_e, B.sc.aff_e, B.sc.affected_cap, B.sc.cnt, B.sc.scal, nullptr);
 }
 
 
@@ -425,7 +430,7 @@ hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev) {
     // per-tile partials of the force pass used (8 x 8 x 8 tiles or the generic tiles)
     const int nparts = force_on_tiles2(h) ? h->g.ntiles2 : h->g.ntiles;
     hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, h->stream, h->sc.part, nparts, h->S.r_e,
-                       h->sc.cnt, h->sc.scal, energies_dev);
+                       h->sc.aff_e, h->sc.affected_cap, h->sc.cnt, h->sc.scal, energies_dev);
     return hipGetLastError();
 }
 

@@ -257,65 +257,6 @@ __device__ __forceinline__ int tile_stencil_length(float m, unsigned *slot, unsi
     return tile_stencil_length(m, slot, other, K, kin, u_cut2, -1.0f, klo);
 }
 
-// Local segment index and offset t for pp = (q - q0) / hq on the window's q = r^2
-// grid.  With kNodeCut the last node sits at the cut-off and the window ends with
-// a zero record at local index nwin: pairs at or beyond the cut-off read zeros, so
-// no separate cut-off select is needed.
-template <bool kNodeCut>
-__device__ __forceinline__ int win_seg(float pp, int nwin, float &t) {
-    const float top = kNodeCut ? (float)nwin : (float)(nwin - 1);
-    t = __builtin_amdgcn_fractf(pp);
-    return (int)__builtin_amdgcn_fmed3f(pp, 0.0f, top);
-}
-
-// The box of a tile as the float64 cut-off decision needs it.  Kept in LDS (written
-// per tile) and read only by the rare fix-ups: the pair loops run short of scalar
-// registers, and values they keep live cost them their overlap of LDS reads.
-struct NearBox {
-    const double *ux, *uy, *uz;
-    const NearTab *nt;
-    int64_t ncell;
-    int nx, ny, nz, pad;
-};
-
-// A lane's site as the fix-ups need it.
-struct NearSite {
-    int64_t idx;
-    int gx, gy, gz, p;
-};
-
-// For a lane whose entries klo .. Kt - 1 hold a pair within the band around rc^2:
-// what must be added to the density the loop summed, so that each such pair counts
-// as the float64 decision says (with f at the window's last node, rc, when the
-// float32 r^2 fell at or beyond it).
-template <bool kNodeCut>
-__device__ __forceinline__ float rho_near_fix(const Q4<float> *tile, const float4 *ftab, const StencilEntry<float> *sp,
-                                           int me, Q4<float> ui, int klo, int Kt, float inv_hq, float pcq, int nwin,
-                                           float rc2, NearSite q, const NearBox &bx) {
-    const NearTab *nt = bx.nt;
-    float add = 0.0f;
-    for (int k = klo; k < Kt; ++k) {
-        const StencilEntry<float> e = sp[k];
-        const Q4<float> uj = tile[me + e.lds];
-        const float dx = (uj.x - ui.x) + e.ox;
-        const float dy = (uj.y - ui.y) + e.oy;
-        const float dz = (uj.z - ui.z) + e.oz;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (!(fabsf(r2 - rc2) < RC_BAND_Q)) continue;
-        float t;
-        const int s = win_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);
-        const float4 c = ftab[s];
-        const float vr = ((c.w * t + c.z) * t + c.y) * t + c.x;
-        const float used = (kNodeCut || r2 < rc2) ? vr : 0.0f;
-        const bool in = pair_in_rc64(bx.ux, bx.uy, bx.uz, q.idx, q.gx, q.gy, q.gz, q.p, nt->st[q.p][k], bx.nx, bx.ny,
-                                     bx.nz, bx.ncell, nt->rc2);
-        const float4 cl = ftab[nwin - 1];
-        const float want = !in ? 0.0f : (kNodeCut && s >= nwin) ? cl.x + cl.y + cl.z + cl.w : vr;
-        add += want - used;
-    }
-    return add;
-}
-
 template <class Src, bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const StencilEntry<float> *__restrict__ st,
                                                           int K, int kin, float u_cut2,
@@ -324,7 +265,6 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
                                                           TabMeta<float> em, float rc2, const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[Src::kMaxSites];
     __shared__ float4 ftab[LDS_TAB_SEGS];
-    __shared__ NearBox nbox;
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
     for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) {
@@ -357,7 +297,6 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
         const int shp = Src::kFixed ? 0 : __builtin_amdgcn_readfirstlane(G.shape);
         const StencilEntry<float> *sp = st + (shp * 2 + p) * KMAX;
         __syncthreads();  // previous tile fully consumed (and the table copied)
-        if (threadIdx.x == 0) nbox = NearBox{P.ux, P.uy, P.uz, nt, G.ncell, G.nx, G.ny, G.nz, 0};
         const float m = store_tile2(tile, R, d.sites);
         int klo;
         const int Kt =
@@ -377,32 +316,34 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
             const int me = L.me;
             const Q4<float> ui = tile[me];
             float acc = 0.0f;
-            // f(r_ij) of entry k as the loops add it (entries klo .. also flag a pair whose
-            // float32 r^2 lies within the band around rc^2)
-            bool near = false;
-            auto term = [&](int k, auto check) -> float {
+            // f(r_ij) of entry k added to acc; returns r^2 - rc^2
+            auto term = [&](int k) -> float {
                 const StencilEntry<float> e = sp[k];
                 const Q4<float> uj = tile[me + e.lds];
                 const float dx = (uj.x - ui.x) + e.ox;
                 const float dy = (uj.y - ui.y) + e.oy;
                 const float dz = (uj.z - ui.z) + e.oz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float r2 = pair_r2_f32(dx, dy, dz);
                 float t;
-                const int s = win_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);  // q = r^2 grid
+                const int s = win_seg<kNodeCut>(win_pos(r2, inv_hq, pcq), nwin, t);  // q = r^2 grid
                 const float4 c = ftab[s];
                 const float vr = ((c.w * t + c.z) * t + c.y) * t + c.x;
-                if (decltype(check)::value) near |= fabsf(r2 - rc2) < RC_BAND_Q;
-                return (kNodeCut || r2 < rc2) ? vr : 0.0f;
+                acc += (kNodeCut || r2 < rc2) ? vr : 0.0f;
+                return r2 - rc2;
             };
-            // (two loop variables: with one shared by both loops the unrolled bodies lost
-            // the overlap of their LDS reads)
+            // Entries klo .. also track the pair closest to rc^2.  A pair whose float32
+            // r^2 lies within RC_BAND_Q of rc^2 may fall on the other side of rc than in
+            // float64: such an atom joins the list of atoms that run-aways touch, whose
+            // fix-ups correct its density and force.  (Two loop variables, and the band
+            // test as a running minimum in a vector register: with a shared variable or
+            // a lane-mask flag the unrolled loops lost the overlap of their LDS reads.)
+            float dmin = 1.0f;
 #pragma unroll 4
-            for (int k = 0; k < klo; ++k) acc += term(k, std::false_type{});
+            for (int k = 0; k < klo; ++k) (void)term(k);
 #pragma unroll 4
-            for (int k = klo; k < Kt; ++k) acc += term(k, std::true_type{});
+            for (int k2 = klo; k2 < Kt; ++k2) dmin = fminf(dmin, fabsf(term(k2)));
             const int64_t idx = (int64_t)p * G.ncell + ((int64_t)gz * G.ny + gy) * G.nx + gx;
-            if (near) acc += rho_near_fix<kNodeCut>(tile, ftab, sp, me, ui, klo, Kt, inv_hq, pcq, nwin, rc2,
-                                                    NearSite{idx, gx, gy, gz, p}, nbox);
+            if (dmin < RC_BAND_Q) atomicOr(&P.mark[idx >> 5], 1u << (idx & 31));
             float fpv = 0.0f;
             bool beyond = false;
             if (ui.x > (float)VACANT_TEST) {
@@ -445,7 +386,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
                                                             int K, int kin, float u_cut2,
                                                             const FRec32 *__restrict__ fwin, float inv_hq,
                                                             float pcq, int nwin, Tables<float> T, float rc2,
-                                                            double kf, const NearTab *__restrict__ nt) {
+                                                            double kf) {
     __shared__ Q4<float> tile[Src::kMaxSites];
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
@@ -463,7 +404,6 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
     }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);
-    const float thr = nt->thr2[p][lane];
     TileGeo Gf{};  // the fixed shape's lane site and stencil, computed once
     const LaneSite Lf = lane_site(dims_of<Src>(Gf), p, w, lane);
     const int nlast = T.fm.nseg - 1;
@@ -487,9 +427,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
         const StencilEntry<float> *sp = st + (shp * 2 + p) * KMAX;
         __syncthreads();
         const float m = store_tile2(tile, R, d.sites);
-        int klo;
-        const int Kt =
-            tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2, thr, klo);
+        const int Kt = tile_stencil_length(m, &umax_slot[it & 1], &umax_slot[(it + 1) & 1], K, kin, u_cut2);
         ++it;
         const int nxt = src.next(blockIdx.x, it, gridDim.x);
         if (nxt >= 0) {
@@ -517,36 +455,25 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
             const int me = L.me;
             const Q4<float> ui = tile[me];
             float ax = 0.0f, ay = 0.0f, az = 0.0f, ep = 0.0f;
-            // the pair term of entry k; kCheck: the cut-off decision of a pair within the
-            // band around rc^2 is taken again in float64
-            auto term = [&](int k, auto check) {
+            // A pair whose float32 r^2 lies within RC_BAND_Q of rc^2 may fall on the other
+            // side of rc than in float64: the density pass lists such atoms with the atoms
+            // run-aways touch, and the fix-up of that list corrects their forces.
+#pragma unroll 2
+            for (int k = 0; k < Kt; ++k) {
                 const StencilEntry<float> e = sp[k];
                 const Q4<float> uj = tile[me + e.lds];
                 const float dx = (uj.x - ui.x) + e.ox;
                 const float dy = (uj.y - ui.y) + e.oy;
                 const float dz = (uj.z - ui.z) + e.oz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float r2 = pair_r2_f32(dx, dy, dz);
                 float t;
-                const int s = win_seg<kNodeCut>(r2 * inv_hq + pcq, nwin, t);  // q = r^2 grid
+                const int s = win_seg<kNodeCut>(win_pos(r2, inv_hq, pcq), nwin, t);  // q = r^2 grid
                 const float4 a = fab[s];
                 const float2 c = fcc[s];
-                float gf = (a.z * t + a.y) * t + a.x;  // f'(r) / r
-                float gp = (c.y * t + c.x) * t + a.w;  // phi'(r) / r
-                bool in = kNodeCut ? s < nwin : r2 < rc2;
-                if (decltype(check)::value && fabsf(r2 - rc2) < RC_BAND_Q) {
-                    in = pair_in_rc64(P.ux, P.uy, P.uz, idx, gx, gy, gz, p, nt->st[p][k], G.nx, G.ny, G.nz,
-                                      G.ncell, nt->rc2);
-                    if (kNodeCut && s >= nwin) {  // past the window's last node (rc) in float32: the records there
-                        const float4 al = fab[nwin - 1];
-                        const float2 cl = fcc[nwin - 1];
-                        gf = al.x + al.y + al.z;
-                        gp = al.w + cl.x + cl.y;
-                    }
-                    gf = in ? gf : 0.0f;
-                    gp = in ? gp : 0.0f;
-                }
+                const float gf = (a.z * t + a.y) * t + a.x;  // f'(r) / r
+                const float gp = (c.y * t + c.x) * t + a.w;  // phi'(r) / r
                 float sc = (ui.w + uj.w) * gf + gp;
-                if (!kNodeCut) sc = in ? sc : 0.0f;
+                if (!kNodeCut) sc = r2 < rc2 ? sc : 0.0f;
                 ax += sc * dx;
                 ay += sc * dy;
                 az += sc * dz;
@@ -556,13 +483,9 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
                     const float tr = pr - (float)sg;
                     const Q4<float> cp = T.phi[sg];
                     const float v = ((cp.w * tr + cp.z) * tr + cp.y) * tr + cp.x;
-                    ep += in ? v : 0.0f;  // same pair set as the force
+                    ep += (kNodeCut ? s < nwin : r2 < rc2) ? v : 0.0f;  // same pair set as the force
                 }
-            };
-#pragma unroll 2
-            for (int k = 0; k < klo; ++k) term(k, std::false_type{});
-#pragma unroll 2
-            for (int k = klo; k < Kt; ++k) term(k, std::true_type{});
+            }
             const bool vac = ui.x > (float)VACANT_TEST;
             if (vac) ax = ay = az = 0.0f;
             P.fx[idx] = ax;
@@ -638,6 +561,23 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
 
 bool lds_path(const misa_lattice *h) {
     return h->precision == MISA_FP32 && !h->use_mlp && h->lds32.usable && h->persistent_grid > 0;
+}
+
+NearFix32 near_fix_of(const misa_lattice *h) {
+    NearFix32 nf;
+    if (!lds_path(h) || half_path(h)) return nf;  // the half-stencil passes decide in float64 themselves
+    nf.frec = h->lds32.f;
+    nf.rec = h->lds32.force;
+    nf.nt = h->near_g;
+    nf.phi = h->t32.phi;
+    nf.fm = h->t32.fm;
+    nf.inv_hq = h->lds32.inv_hq;
+    nf.pcq = h->lds32.pcq;
+    nf.rc2 = (float)h->g.rc2;
+    nf.nwin = h->lds32.nwin;
+    nf.node_cut = h->lds32.node_cut ? 1 : 0;
+    nf.K = h->K;
+    return nf;
 }
 
 PassPtrs pass_ptrs(misa_lattice *h) {
@@ -1082,7 +1022,7 @@ static void force_lds_variant(misa_lattice *h, const Src &src, int grid, const S
     auto kern = h->lds32.node_cut ? k_force_lds<Src, kEnergy, true, kKick> : k_force_lds<Src, kEnergy, false, kKick>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, st, h->K, h->K_in,
                        h->u_cut2, h->lds32.force, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, t32_tab(h),
-                       (float)h->g.rc2, ACC_UNIT / h->mass, near_args(h, false));
+                       (float)h->g.rc2, ACC_UNIT / h->mass);
 }
 
 template <class Src>

@@ -114,6 +114,28 @@ struct alignas(16) StencilEntry<float> {
 constexpr float RC_BAND_Q = 1.0e-4f;   // A^2
 constexpr float NEAR_MARGIN = 1.0e-3f; // A: slack of the per-tile test below
 
+// float32 r^2 of a separation, in the one order every float32 pass and the fix-ups
+// use, so that all of them see the same bits for the same pair.
+__device__ __forceinline__ float pair_r2_f32(float dx, float dy, float dz) {
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dx, dx, dy * dy));
+}
+
+// Position (q - q0) / hq of q = r^2 on the q grid of the float32 table window.
+__device__ __forceinline__ float win_pos(float r2, float inv_hq, float pcq) {
+    return __builtin_fmaf(r2, inv_hq, pcq);
+}
+
+// Local segment index and offset t for pp = (q - q0) / hq on the window's q = r^2
+// grid.  With kNodeCut the last node sits at the cut-off and the window ends with
+// a zero record at local index nwin: pairs at or beyond the cut-off read zeros, so
+// no separate cut-off select is needed.
+template <bool kNodeCut>
+__device__ __forceinline__ int win_seg(float pp, int nwin, float &t) {
+    const float top = kNodeCut ? (float)nwin : (float)(nwin - 1);
+    t = __builtin_amdgcn_fractf(pp);
+    return (int)__builtin_amdgcn_fmed3f(pp, 0.0f, top);
+}
+
 // A stencil entry as the float64 re-decision needs it: the lattice-id offset of
 // Sec. 3 and the site offset vector, in the order of the kernel's float stencil.
 struct alignas(16) NearEntry {
@@ -270,6 +292,7 @@ struct Scratch {
     int32_t *affected;    // ascending site indices, capacity affected_cap
     int64_t affected_cap;
     double *aff_v2;       // |v|^2 of each affected lattice atom after the fused final kick
+    double *aff_e;        // pair-energy correction of each affected lattice atom (energy passes)
     double *part_kick;    // per-tile {max |v|^2, sum |v|^2} of the fused final kick
 };
 
@@ -302,6 +325,20 @@ struct LdsTables {
     bool node_cut = false;    // last node at rc: a zero record after the window implements the cut-off
 };
 
+// What the fix-up of the affected list needs to correct the float32 gather pass for
+// atoms with a pair inside the cut-off band (that pass's window of force records,
+// the float64 stencil, the r-grid records of phi for the pair energy).  rec null:
+// the force pass used takes that decision itself, or computes in float64.
+struct NearFix32 {
+    const Q4<float> *frec = nullptr;  // value records of f (density)
+    const FRec32 *rec = nullptr;      // force records
+    const NearTab *nt = nullptr;
+    const Q4<float> *phi = nullptr;
+    TabMeta<float> fm{};
+    float inv_hq = 0.f, pcq = 0.f, rc2 = 0.f;
+    int32_t nwin = 0, node_cut = 0, K = 0;
+};
+
 // Window of the f spline's nodes for the persistent float64 density pass: node
 // k0 + i holds {y, m} (value, and slope in units of the sample spacing), i < nn.
 constexpr int NODE64_MAX = 4096;
@@ -326,7 +363,7 @@ struct PassPtrs {
     const double *ux, *uy, *uz;
     float *rho, *fp, *fx, *fy, *fz;
     double *vx, *vy, *vz;
-    const uint32_t *mark;
+    uint32_t *mark;
     const double *scal;  // scal[0] = dt of the current step
     double *part, *part_kick;
     uint32_t *range_viol;
@@ -442,6 +479,7 @@ void drop_graph(misa_lattice *h);                      // forget the captured st
 hipError_t launch_rho(misa_lattice *h);
 hipError_t launch_force(misa_lattice *h, bool energy, bool kick);
 bool lds_path(const misa_lattice *h);                  // persistent float32 kernels usable
+NearFix32 near_fix_of(const misa_lattice *h);          // the affected-list correction of the gather pass
 hipError_t launch_rho_lds(misa_lattice *h);
 bool lds64_path(const misa_lattice *h);                // persistent float64 density pass usable
 hipError_t launch_rho_lds64(misa_lattice *h);

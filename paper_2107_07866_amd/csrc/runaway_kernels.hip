@@ -591,13 +591,60 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(St
 }
 
 
+// The float32 band pairs of lattice atom s, one team lane per stencil entry (entries
+// cell, cell + AFF_TEAM, ...): for each pair whose float32 r^2 fell within RC_BAND_Q of
+// rc^2 and on the other side of rc than in float64, iterate f (the float32 window form
+// the density pass used, at the window's last node where float32 put r past it).
+// Returns this lane's correction of the density (Eq. eam_base: a pair counts iff r < rc).
+// The force-pass counterpart, near_pair_fix, follows the same steps.
+template <class Body>
+__device__ __forceinline__ void for_band_flips(const State &S, const Geom &g, const NearFix32 &nf, int64_t s,
+                                               const int c[3], int p, int cell, Body body) {
+    const float uix = (float)S.ux[s], uiy = (float)S.uy[s], uiz = (float)S.uz[s];
+    for (int k = cell; k < nf.K; k += AFF_TEAM) {
+        const NearEntry &e = nf.nt->st[p][k];
+        const int64_t j = offset_site(c[0], c[1], c[2], p, e, g.nx, g.ny, g.nz, g.ncell);
+        const float dx = ((float)S.ux[j] - uix) + (float)e.ox;
+        const float dy = ((float)S.uy[j] - uiy) + (float)e.oy;
+        const float dz = ((float)S.uz[j] - uiz) + (float)e.oz;
+        const float r2 = pair_r2_f32(dx, dy, dz);
+        if (!(fabsf(r2 - nf.rc2) < RC_BAND_Q)) continue;
+        float t;
+        int sg;
+        bool in32;
+        if (nf.node_cut) {
+            sg = win_seg<true>(win_pos(r2, nf.inv_hq, nf.pcq), nf.nwin, t);
+            in32 = sg < nf.nwin;
+        } else {
+            sg = win_seg<false>(win_pos(r2, nf.inv_hq, nf.pcq), nf.nwin, t);
+            in32 = r2 < nf.rc2;
+        }
+        const bool in64 = pair_in_rc64(S.ux, S.uy, S.uz, s, c[0], c[1], c[2], p, e, g.nx, g.ny, g.nz, g.ncell,
+                                       nf.nt->rc2);
+        if (in32 == in64) continue;
+        const bool past = sg >= nf.nwin;  // float32 r at or past the last node: the node's record at t = 1
+        body(j, past ? nf.nwin - 1 : sg, past ? 1.0f : t, in64 ? 1.0 : -1.0, dx, dy, dz, r2);
+    }
+}
+
+__device__ __forceinline__ double near_rho_fix(const State &S, const Geom &g, const NearFix32 &nf, int64_t s,
+                                               const int c[3], int p, int cell) {
+    double acc = 0.0;
+    for_band_flips(S, g, nf, s, c, p, cell,
+                   [&](int64_t, int sg, float t, double sgn, float, float, float, float) {
+                       const Q4<float> cf = nf.frec[sg];
+                       acc += sgn * (double)(((cf.w * t + cf.z) * t + cf.y) * t + cf.x);
+                   });
+    return acc;
+}
+
 // Lattice atoms within rc of run-aways: add the run-away terms to rho, refresh F'.
 // emb: the embedding network of the learned form (an empty range on other handles).
 // q: index into the affected list; cell: this lane's place in its team of AFF_TEAM.
 template <typename Real>
 __device__ __forceinline__ void affected_rho_one(const State &S, const Scratch &sc, const Geom &g,
                                                  const Tables<double> &T, const Tables<Real> &TL,
-                                                 const MlpNet &emb, int q, int cell) {
+                                                 const MlpNet &emb, const NearFix32 &nf, int q, int cell) {
     {
         const int64_t s = sc.affected[q];
         const int p = s >= g.ncell ? 1 : 0;
@@ -614,6 +661,7 @@ __device__ __forceinline__ void affected_rho_one(const State &S, const Scratch &
                 double d[3], r2;
                 if (affected_pair(xo, cj, p, u, g, d, r2)) acc += f_val(sqrt(r2), T);
             });
+        if (nf.frec) acc += near_rho_fix(S, g, nf, s, cj, p, cell);
         acc = team_sum32(acc);
         if (cell == 0) {
             Real *rho = (Real *)S.rho;
@@ -641,18 +689,18 @@ __device__ __forceinline__ int affected_count(const Scratch &sc) {
 
 template <typename Real>
 __device__ __forceinline__ void affected_rho_body(State S, Scratch sc, Geom g, Tables<double> T,
-                                                  Tables<Real> TL, MlpNet emb) {
+                                                  Tables<Real> TL, MlpNet emb, const NearFix32 &nf) {
     const int na = affected_count(sc);
     const int cell = threadIdx.x & (AFF_TEAM - 1);
     const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
     for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < na; q += nteams)
-        affected_rho_one<Real>(S, sc, g, T, TL, emb, q, cell);
+        affected_rho_one<Real>(S, sc, g, T, TL, emb, nf, q, cell);
 }
 
 template <typename Real>
 __global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch sc, Geom g, Tables<double> T,
-                                                              Tables<Real> TL, MlpNet emb) {
-    affected_rho_body<Real>(S, sc, g, T, TL, emb);
+                                                              Tables<Real> TL, MlpNet emb, NearFix32 nf) {
+    affected_rho_body<Real>(S, sc, g, T, TL, emb, nf);
 }
 
 
@@ -733,11 +781,38 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(
 }
 
 
+// The force-pass counterpart of near_rho_fix: this lane's corrections of the force and
+// of the pair energy (phi from the r-grid records, as the pass takes it).
+__device__ __forceinline__ void near_pair_fix(const State &S, const Geom &g, const NearFix32 &nf, int64_t s,
+                                              const int c[3], int p, int cell, double &ax, double &ay,
+                                              double &az, double &ae) {
+    const float *fpa = (const float *)S.fp;
+    const float fpi = fpa[s];
+    for_band_flips(S, g, nf, s, c, p, cell,
+                   [&](int64_t j, int sg, float t, double sgn, float dx, float dy, float dz, float r2) {
+                       const FRec32 rc_ = nf.rec[sg];
+                       const float gf = (rc_.b.x * t + rc_.a.y) * t + rc_.a.x;  // f'(r) / r
+                       const float gp = (rc_.c.y * t + rc_.c.x) * t + rc_.b.y;  // phi'(r) / r
+                       const float sc_ = (fpi + fpa[j]) * gf + gp;
+                       ax += sgn * (double)(sc_ * dx);
+                       ay += sgn * (double)(sc_ * dy);
+                       az += sgn * (double)(sc_ * dz);
+                       const float pr = (__builtin_amdgcn_sqrtf(r2) - nf.fm.x0) * nf.fm.inv_h;
+                       const int sr = max(0, min((int)pr, nf.fm.nseg - 1));
+                       const float tr = pr - (float)sr;
+                       const Q4<float> cp = nf.phi[sr];
+                       ae += sgn * 0.5 * (double)(((cp.w * tr + cp.z) * tr + cp.y) * tr + cp.x);
+                   });
+}
+
 // kick != 0: the force pass already applied the second half-kick with the lattice
 // part of F; add the run-away part's kick here and record |v|^2 for the step statistics.
+// nf.rec: also correct the float32 gather pass's cut-off decisions (near_pair_fix);
+// energy: record the pair-energy correction in aff_e.
 template <typename Real>
 __device__ __forceinline__ void affected_force_one(const State &S, const Scratch &sc, const Geom &g,
-                                                   const Tables<double> &T, int kick, double kf, int q, int cell) {
+                                                   const Tables<double> &T, int kick, double kf,
+                                                   const NearFix32 &nf, int energy, int q, int cell) {
     const double hk = kick ? 0.5 * sc.scal[0] * kf : 0.0;
     {
         const int64_t s = sc.affected[q];
@@ -763,10 +838,14 @@ __device__ __forceinline__ void affected_force_one(const State &S, const Scratch
                 ay -= sc_ * d[1];
                 az -= sc_ * d[2];
             });
+        double ae = 0.0;
+        if (nf.rec) near_pair_fix(S, g, nf, s, cj, p, cell, ax, ay, az, ae);
         ax = team_sum32(ax);
         ay = team_sum32(ay);
         az = team_sum32(az);
+        if (energy) ae = team_sum32(ae);
         if (cell == 0) {
+            if (energy) sc.aff_e[q] = ae;
             Real *fxa = (Real *)S.fx;
             Real *fya = (Real *)S.fy;
             Real *fza = (Real *)S.fz;
@@ -787,18 +866,18 @@ __device__ __forceinline__ void affected_force_one(const State &S, const Scratch
 
 template <typename Real>
 __device__ __forceinline__ void affected_force_body(State S, Scratch sc, Geom g, Tables<double> T, int kick,
-                                                    double kf) {
+                                                    double kf, const NearFix32 &nf, int energy) {
     const int na = affected_count(sc);
     const int cell = threadIdx.x & (AFF_TEAM - 1);
     const int nteams = gridDim.x * (AFF_THREADS / AFF_TEAM);
     for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < na; q += nteams)
-        affected_force_one<Real>(S, sc, g, T, kick, kf, q, cell);
+        affected_force_one<Real>(S, sc, g, T, kick, kf, nf, energy, q, cell);
 }
 
 template <typename Real>
 __global__ __launch_bounds__(AFF_THREADS) void k_affected_force(State S, Scratch sc, Geom g, Tables<double> T,
-                                                                int kick, double kf) {
-    affected_force_body<Real>(S, sc, g, T, kick, kf);
+                                                                int kick, double kf, NearFix32 nf, int energy) {
+    affected_force_body<Real>(S, sc, g, T, kick, kf, nf, energy);
 }
 
 
@@ -893,7 +972,7 @@ __global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kf_runaway_force
 // two teams of a wave may serve different boxes).
 __global__ __launch_bounds__(AFF_THREADS) void kf_affected_rho(const BoxRef *__restrict__ boxes, int nbox,
                                                                const int32_t *off, Tables<double> T,
-                                                               Tables<float> TL) {
+                                                               Tables<float> TL, NearFix32 nf) {
     extern __shared__ int s_off[];
     const int total = stage_offsets(s_off, off, nbox);
     const int cell = threadIdx.x & (AFF_TEAM - 1);
@@ -901,12 +980,13 @@ __global__ __launch_bounds__(AFF_THREADS) void kf_affected_rho(const BoxRef *__r
     for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < total; q += nteams) {
         const int b = flat_box(s_off, nbox, q);
         const BoxRef &B = boxes[b];
-        affected_rho_one<float>(B.S, B.sc, B.g, T, TL, MlpNet{}, q - s_off[b], cell);
+        affected_rho_one<float>(B.S, B.sc, B.g, T, TL, MlpNet{}, nf, q - s_off[b], cell);
     }
 }
 
 __global__ __launch_bounds__(AFF_THREADS) void kf_affected_force(const BoxRef *__restrict__ boxes, int nbox,
-                                                                 const int32_t *off, Tables<double> T, double kf) {
+                                                                 const int32_t *off, Tables<double> T, double kf,
+                                                                 NearFix32 nf, int energy) {
     extern __shared__ int s_off[];
     const int total = stage_offsets(s_off, off, nbox);
     const int cell = threadIdx.x & (AFF_TEAM - 1);
@@ -914,7 +994,7 @@ __global__ __launch_bounds__(AFF_THREADS) void kf_affected_force(const BoxRef *_
     for (int q = (blockIdx.x * AFF_THREADS + threadIdx.x) / AFF_TEAM; q < total; q += nteams) {
         const int b = flat_box(s_off, nbox, q);
         const BoxRef &B = boxes[b];
-        affected_force_one<float>(B.S, B.sc, B.g, T, 1, kf, q - s_off[b], cell);
+        affected_force_one<float>(B.S, B.sc, B.g, T, 1, kf, nf, energy, q - s_off[b], cell);
     }
 }
 
@@ -956,8 +1036,9 @@ __device__ __forceinline__ void load_mark_words(const Scratch &sc, uint32_t (&m)
 
 __device__ __forceinline__ void mark_count_body(Scratch sc) {
     __shared__ int shw[MARK_THREADS / 64];
-    // nothing marked; or a batched grid sized for a larger box
-    if (sc.cnt->n_run == 0 || (int)blockIdx.x >= sc.mark_nblk) return;
+    // a batched grid sized for a larger box (marks come from run-aways and, in the
+    // float32 gather form, from the density pass's cut-off band: no early exit on n_run)
+    if ((int)blockIdx.x >= sc.mark_nblk) return;
     uint32_t m[MARK_WORDS];
     int c, total;
     load_mark_words(sc, m, c);
@@ -978,10 +1059,6 @@ __global__ __launch_bounds__(MARK_THREADS) void kb_mark_count(const BoxRef *__re
 __device__ __forceinline__ void mark_scan_body(Scratch sc, int nblk) {
     __shared__ int64_t base_sh;
     __shared__ int wsum[1024 / 64];
-    if (sc.cnt->n_run == 0) {
-        if (threadIdx.x == 0) sc.cnt->n_affected = 0;
-        return;
-    }
     if (threadIdx.x == 0) base_sh = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1025,7 +1102,7 @@ __global__ __launch_bounds__(1024) void kb_mark_scan(const BoxRef *__restrict__ 
 
 __device__ __forceinline__ void mark_emit_body(Scratch sc) {
     __shared__ int shw[MARK_THREADS / 64];
-    if (sc.cnt->n_run == 0 || (int)blockIdx.x >= sc.mark_nblk) return;
+    if ((int)blockIdx.x >= sc.mark_nblk) return;
     uint32_t m[MARK_WORDS];
     int c, total;
     load_mark_words(sc, m, c);
@@ -1105,10 +1182,10 @@ hipError_t launch_runaway_rho(misa_lattice *h) {
     hipLaunchKernelGGL(k_mark_emit, dim3(h->sc.mark_nblk), dim3(MARK_THREADS), 0, st, h->sc);
     if (h->precision == MISA_FP32)
         hipLaunchKernelGGL(k_affected_rho<float>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g, t64_of(h),
-                           t32_of(h), h->use_mlp ? h->mlp.net[2] : MlpNet{});
+                           t32_of(h), h->use_mlp ? h->mlp.net[2] : MlpNet{}, near_fix_of(h));
     else
         hipLaunchKernelGGL(k_affected_rho<double>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g,
-                           t64_of(h), t64_of(h), MlpNet{});
+                           t64_of(h), t64_of(h), MlpNet{}, NearFix32{});
     return hipGetLastError();
 }
 
@@ -1119,10 +1196,10 @@ hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick) {
     const double kf = ACC_UNIT / h->mass;
     if (h->precision == MISA_FP32)
         hipLaunchKernelGGL(k_affected_force<float>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g,
-                           t64_of(h), kick ? 1 : 0, kf);
+                           t64_of(h), kick ? 1 : 0, kf, near_fix_of(h), energy ? 1 : 0);
     else
         hipLaunchKernelGGL(k_affected_force<double>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g,
-                           t64_of(h), kick ? 1 : 0, kf);
+                           t64_of(h), kick ? 1 : 0, kf, NearFix32{}, energy ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1154,7 +1231,7 @@ hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, 
     hipLaunchKernelGGL(kb_mark_emit, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
     hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 1, off + nbox + 1);
     hipLaunchKernelGGL(kf_affected_rho, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox, off + nbox + 1,
-                       t64_of(h0), t32_of(h0));
+                       t64_of(h0), t32_of(h0), near_fix_of(h0));
     return hipGetLastError();
 }
 
@@ -1164,7 +1241,7 @@ hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox
     hipLaunchKernelGGL(kf_runaway_force, dim3(FLAT_BLOCKS), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes, nbox,
                        off, t64_of(h0), energy ? 1 : 0);
     hipLaunchKernelGGL(kf_affected_force, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox, off + nbox + 1,
-                       t64_of(h0), ACC_UNIT / h0->mass);
+                       t64_of(h0), ACC_UNIT / h0->mass, near_fix_of(h0), energy ? 1 : 0);
     return hipGetLastError();
 }
 
