@@ -2,8 +2,11 @@
 """Benchmark of the EAM lattice MD step (the MISA-MD hot path) on one MI355X.
 
 Prints ONE JSON line.  `value` is atom-steps/s of the headline form (the first
-of --forms) on the chosen workload; every form's atom-steps/s, sampled force
-error against the FP64 oracle and per-kernel times go under "forms".
+of --forms) on the chosen workload; every form's atom-steps/s, per-kernel times
+and errors go under "forms".  The errors are those of the initial state (the state
+the run starts from) against a stored sample of FP64 oracle values
+(tests/golden/bench_reference.json, written by make_bench_reference.py beside it):
+the benchmark itself runs the oracle only for the cpu_baseline figure.
 
 Workloads (synthetic, seeded; the recipe lives in misa_workloads.synth):
   c3: 320^3 BCC cells = 65,536,000 atoms, 300 K + 5 recoils at 2 keV, adaptive dt
@@ -97,7 +100,54 @@ def train_learned_form(seed=11):
     return nets, info
 
 
-def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None, graph=False, recoils=()):
+REFERENCE = os.path.join(ROOT, "tests", "golden", "bench_reference.json")
+
+
+def bench_reference(key):
+    """Oracle values on the initial state of workload key (tests/golden/make_bench_reference.py
+    writes them), or None."""
+    try:
+        with open(REFERENCE) as fh:
+            return json.load(fh).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def initial_state_errors(lat, ref, table_form):
+    """Errors of the handle's rho, F' and forces on the stored oracle sample of its
+    initial state (call right after set_state)."""
+    import numpy as np
+    import torch
+    lat.compute()
+    torch.cuda.synchronize()
+    sample = np.asarray(ref["sample"], dtype=np.int64)
+    Fr, rr, fpr = np.asarray(ref["F"]), np.asarray(ref["rho"]), np.asarray(ref["fp"])
+    Fg, rg = lat.forces()[sample], lat.rho()[sample]
+    out = {}
+    scale = float(np.sqrt(np.mean(Fr ** 2)))
+    out["force_err_max_rel_rms"] = float(np.max(np.abs(Fg - Fr))) / max(scale, 1e-3)
+    # per atom, on sampled atoms farther than 2 rc from every recoil atom:
+    # |dF_i| / max(|F_i|, rms |F| over those atoms)
+    far = np.asarray(ref["far"], dtype=bool)
+    if far.any():
+        fth = np.linalg.norm(Fr[far], axis=1)
+        rms_th = float(np.sqrt(np.mean(fth ** 2)))
+        dth = np.linalg.norm(Fg[far] - Fr[far], axis=1)
+        out["force_err_per_atom_thermal"] = float(np.max(dth / np.maximum(fth, rms_th)))
+    out["thermal_sample"] = int(far.sum())
+    nz = rr > 0
+    out["rho_err_max_rel"] = float(np.max(np.abs(rg[nz] - rr[nz]) / rr[nz])) if nz.any() else 0.0
+    # embedding energy per sampled atom: |F'| |d rho| to first order, so the density error bounds it
+    out["emb_energy_err_max_eV"] = float(np.max(np.abs(fpr * (rg - rr))))
+    out["force_err_sample"] = int(len(sample))
+    out["mean_pairs_per_atom"] = float(np.mean(ref["npairs"]))
+    if table_form:  # the pair set of the density pass, atom by atom
+        out["pair_counts_equal_oracle"] = bool(np.array_equal(lat.neighbour_counts()[sample],
+                                                              np.asarray(ref["npairs"])))
+    return out
+
+
+def run_form(form, x, v, box, cfg, steps, warmup, ref, nets=None, graph=False):
     import numpy as np
     import torch
 
@@ -117,6 +167,12 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None,
     lat.set_state(x, v)
     torch.cuda.synchronize()
     _log(f"[bench] {form}: state loaded in {time.time() - t0:.1f} s ({lat.state_bytes / 1e9:.2f} GB)")
+    errs = {}
+    if ref is not None:  # the initial state against the stored oracle sample (outside the timed region)
+        errs = initial_state_errors(lat, ref, form not in ("mlp", "mlp-half"))
+        _log(f"[bench] {form}: initial state: force error {errs['force_err_max_rel_rms']:.2e} (per atom, thermal "
+             f"{errs.get('force_err_per_atom_thermal', float('nan')):.2e}), rho error {errs['rho_err_max_rel']:.2e}, "
+             f"pair counts equal {errs.get('pair_counts_equal_oracle')} (oracle sample of {errs['force_err_sample']})")
     dx_max = cfg.dx_max
     if graph:  # steps replay a captured HIP graph (per-kernel event timing would disable it)
         lat.set_graph(True)
@@ -149,42 +205,7 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None,
     }
     _log(f"[bench] {form}: {out['atom_steps_per_s']:.3e} atom-steps/s, {out['ms_per_step']:.3f} ms/step, "
          f"run-aways {st['n_runaway']}")
-    # sampled force error of the final state against the FP64 oracle (outside the timed region)
-    if err_sample > 0:
-        import oracle
-        xg, _ = lat.get_state()
-        Fg = lat.forces()
-        rng = np.random.default_rng(seed)
-        sample = rng.choice(n, size=min(err_sample, n), replace=False)
-        t3 = time.time()
-        ref = oracle.eam_sampled(oracle.Potential(oracle.TABLE, tables=tabs), xg, box, sample)
-        scale = float(np.sqrt(np.mean(ref["F"] ** 2)))
-        out["force_err_max_rel_rms"] = float(np.max(np.abs(Fg[sample] - ref["F"]))) / max(scale, 1e-3)
-        # per atom, on sampled atoms farther than 2 rc from every recoil atom:
-        # |dF_i| / max(|F_i|, rms |F| over those atoms)
-        L = np.asarray(box)
-        far = np.ones(len(sample), bool)
-        for i in recoils:
-            d = xg[sample] - xg[int(i)]
-            d -= L * np.rint(d / L)
-            far &= np.einsum("ij,ij->i", d, d) > (2 * w.RC) ** 2
-        fth = np.linalg.norm(ref["F"][far], axis=1)
-        rms_th = float(np.sqrt(np.mean(fth ** 2)))
-        dth = np.linalg.norm(Fg[sample][far] - ref["F"][far], axis=1)
-        out["force_err_per_atom_thermal"] = float(np.max(dth / np.maximum(fth, rms_th)))
-        out["thermal_sample"] = int(far.sum())
-        # embedding energy per sampled atom: |F'| |d rho| to first order, so the density error bounds it
-        rg = lat.rho()[sample]
-        nz = ref["rho"] > 0
-        out["rho_err_max_rel"] = float(np.max(np.abs(rg[nz] - ref["rho"][nz]) / ref["rho"][nz])) if nz.any() else 0.0
-        out["emb_energy_err_max_eV"] = float(np.max(np.abs(ref["fp"] * (rg - ref["rho"]))))
-        out["force_err_sample"] = int(len(sample))
-        out["mean_pairs_per_atom"] = float(np.mean(ref["npairs"]))
-        if form not in ("mlp", "mlp-half"):  # the pair set of the density pass, atom by atom
-            out["pair_counts_equal_oracle"] = bool(np.array_equal(lat.neighbour_counts()[sample], ref["npairs"]))
-        _log(f"[bench] {form}: force error {out['force_err_max_rel_rms']:.2e} (per atom, thermal "
-             f"{out['force_err_per_atom_thermal']:.2e}), rho error {out['rho_err_max_rel']:.2e}, pair counts equal "
-             f"{out.get('pair_counts_equal_oracle')} (oracle sample of {len(sample)} atoms, {time.time() - t3:.1f} s)")
+    out.update(errs)
     out["K"] = int(lat.stencil().shape[1])
     lat.close()
     del lat
@@ -192,7 +213,7 @@ def run_form(form, x, v, box, cfg, steps, warmup, err_sample, seed=7, nets=None,
     return out
 
 
-def run_batch(cfg, steps, warmup, err_sample, seq_steps=20, graph=False):
+def run_batch(cfg, steps, warmup, ref, seq_steps=20, graph=False):
     """Batched replicas: every box stepped by misa_batch_step; beside it the same boxes
     stepped one handle at a time (seq_steps steps each) for the gain of batching."""
     import numpy as np
@@ -216,6 +237,17 @@ def run_batch(cfg, steps, warmup, err_sample, seq_steps=20, graph=False):
         batch.boxes[k].set_state(b[1], b[2])
     torch.cuda.synchronize()
     _log(f"[bench] batch: tables and states loaded, {time.time() - t0:.1f} s")
+    errs = []
+    for e in (ref or []):  # stored oracle samples of the first boxes' initial states
+        r = initial_state_errors(batch.boxes[e["box"]], e, True)
+        errs.append(r)
+    batch_err = {}
+    if errs:
+        batch_err["force_err_max_rel_rms"] = max(r["force_err_max_rel_rms"] for r in errs)
+        batch_err["pair_counts_equal_oracle"] = all(r["pair_counts_equal_oracle"] for r in errs)
+        batch_err["force_err_boxes"] = len(errs)
+        _log(f"[bench] batch: initial states of {len(errs)} boxes: force error "
+             f"{batch_err['force_err_max_rel_rms']:.2e}, pair counts equal {batch_err['pair_counts_equal_oracle']}")
     # tile shapes: the autotuner times both policies on the initial states, which are
     # then loaded again so that the warm-up and the timed steps start where they would
     tune = batch.autotune(max(2, warmup), cfg.dt_max, cfg.dx_max)
@@ -250,21 +282,10 @@ def run_batch(cfg, steps, warmup, err_sample, seq_steps=20, graph=False):
            "boxes": len(boxes), "atoms": n_atoms, "tile_autotune": tune,
            "n_runaway_total": int(sum(s["n_runaway"] for s in st)),
            "frenkel_pairs_total": int(sum(M.misa_defects(bx.h)["vacancies"] for bx in batch.boxes)),
-           "simulated_fs_min": min(s["time"] for s in st), "simulated_fs_max": max(s["time"] for s in st)}
+           "simulated_fs_min": min(s["time"] for s in st), "simulated_fs_max": max(s["time"] for s in st),
+           **batch_err}
     _log(f"[bench] batch: {out['atom_steps_per_s']:.3e} atom-steps/s, {out['ms_per_step']:.3f} ms/step, "
          f"run-aways {out['n_runaway_total']}")
-    if err_sample > 0:
-        import oracle
-        pot = oracle.Potential(oracle.TABLE, tables=tabs)
-        errs = []
-        for k in range(3):
-            xg, _ = batch.boxes[k].get_state()
-            F = batch.boxes[k].forces()
-            sample = np.random.default_rng(k).choice(len(xg), size=min(err_sample // 3, len(xg)), replace=False)
-            ref = oracle.eam_sampled(pot, xg, boxes[k][3], sample)
-            errs.append(float(np.max(np.abs(F[sample] - ref["F"]))) / float(np.sqrt(np.mean(ref["F"] ** 2))))
-        out["force_err_max_rel_rms"] = max(errs)
-        _log(f"[bench] batch: force error {out['force_err_max_rel_rms']:.2e} (three boxes against the oracle)")
     batch.close()
     del batch
     torch.cuda.empty_cache()
@@ -399,11 +420,15 @@ def main():
     ap.add_argument("--forms", default=None,
                     help="comma list of fp32,fp64,fp32-half,mlp,mlp-half; first is the headline value (fp32 or fp64)")
     ap.add_argument("--mlp-steps", type=int, default=5, help="timed steps of the learned form (it is slower)")
-    ap.add_argument("--error-sample", type=int, default=1000)
+    ap.add_argument("--no-error-check", dest="error_check", action="store_false",
+                    help="skip the error report against the stored oracle sample of the initial state")
+    ap.add_argument("--error-sample", type=int, default=None, help="0: the same as --no-error-check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scale for HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.error_sample == 0:
+        args.error_check = False
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
@@ -431,7 +456,8 @@ def main():
         # so the default times the first 400 steps (about 0.3 ps of dynamics)
         steps = args.steps if args.steps is not None else 400
         torch.cuda.set_device(0)
-        res = run_batch(cfg, steps, args.warmup, args.error_sample, graph=args.graph)
+        res = run_batch(cfg, steps, args.warmup, bench_reference("c4") if args.error_check else None,
+                        graph=args.graph)
         head = {"kernel_ms_per_step": res["kernel_ms_per_step"], "K": 64, "mean_pairs_per_atom": 58.0}
         line = {"metric": METRIC, "value": res["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1,
                 "steps": steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
@@ -454,6 +480,9 @@ def main():
     t0 = time.time()
     x, v, box, rec = w.make_state(cfg)
     _log(f"[bench] {cfg.name}: {x.shape[0]} atoms generated in {time.time() - t0:.1f} s; recoils {rec}")
+    ref = bench_reference(args.workload) if args.error_check else None
+    if ref is not None and ref.get("atoms") != x.shape[0]:
+        raise SystemExit("stored oracle sample does not match the workload; rerun tests/golden/make_bench_reference.py")
 
     results = {}
     trained = None
@@ -463,13 +492,11 @@ def main():
                 trained = train_learned_form()
             nets, info = trained
             k = min(steps, args.mlp_steps)
-            results[form] = run_form(form, x, v, box, cfg, k, min(args.warmup, 2), args.error_sample, nets=nets,
-                                     recoils=rec)
+            results[form] = run_form(form, x, v, box, cfg, k, min(args.warmup, 2), ref, nets=nets)
             results[form]["training"] = info
             results[form]["timed_steps"] = k
         else:
-            results[form] = run_form(form, x, v, box, cfg, steps, args.warmup, args.error_sample, graph=args.graph,
-                                     recoils=rec)
+            results[form] = run_form(form, x, v, box, cfg, steps, args.warmup, ref, graph=args.graph)
     head = results[forms[0]]
     n = x.shape[0]
     bpa = sum(BYTES_PER_ATOM_STEP[forms[0]].values())
@@ -496,6 +523,22 @@ def main():
                       "frac": round(head["atom_steps_per_s"] * bpa / 1e9 / HBM_PEAK_GBS, 4)},
         "forms": results,
     }
+    learned = [f for f in ("mlp-half", "mlp") if f in results]
+    table = [f for f in ("fp32", "fp32-half", "fp64") if f in results]
+    if learned and table:
+        # what the learned form gains over the tables: bytes holding f, phi, F; force error; rate
+        tabs = w.potential_samples()
+        sample_bytes = 8 * sum(len(tabs[k][2]) for k in ("f", "phi", "F"))
+        from paper_2107_07866_amd import misa as M
+        weight_bytes = 3 * M.MISA_MLP_PARAMS * 2
+        line["learned_vs_table"] = {
+            "table": {"form": table[0], "bytes": sample_bytes, "bytes_of": "float64 samples of f, phi, F",
+                      "atom_steps_per_s": results[table[0]]["atom_steps_per_s"],
+                      "force_err_max_rel_rms": results[table[0]].get("force_err_max_rel_rms")},
+            "learned": {"form": learned[0], "bytes": weight_bytes, "bytes_of": "bfloat16 weights of 3 networks",
+                        "atom_steps_per_s": results[learned[0]]["atom_steps_per_s"],
+                        "force_err_max_rel_rms": results[learned[0]].get("force_err_max_rel_rms")},
+        }
     counted = counted_traffic() if (forms[0] == "fp32" and n == 65536000) else None
     line["hbm_model"]["counted_GBps"] = (round(counted["step"] / (head["ms_per_step"] * 1e-3) / 1e9, 1)
                                          if counted else None)

@@ -413,3 +413,51 @@ def test_mlp_form_runaway_pairs_use_the_tables(M, trainer, torch_cuda, orc):
     err = np.abs(F_mlp[run] - F_tab[run]).max() / np.abs(F_tab[run]).max()
     print(f"run-away forces, learned vs table form: {err:.2e} ({len(run)} run-away atoms)", flush=True)
     assert err < 1e-3
+
+
+def test_learned_vs_table_side_by_side(M, trainer, torch_cuda, orc):
+    """What the learned form gains over the method without it (the spline tables of
+    Sec. 4.1), on one thermal state: the bytes that hold f, phi and F, the force error
+    against the oracle's table potential, and the stepping rate, side by side.  The
+    networks hold the three functions in ~1/17 of the bytes of the tables' float64
+    samples (and ~1/60 of the float32 records the table form reads), at a force error
+    near 1e-3 against ~1e-5; they step slower (their SiLU evaluations cost more than
+    the table look-ups they replace)."""
+    import time
+    torch = torch_cuda
+    lat64 = _lattice(6, "fp64")
+    nets, _, _ = _quick_fit(M, torch, trainer, lat64, iters=8000, seed=41)
+    lat64.close()
+    n = 24
+    x, v, box = w.thermal_state(n, seed=5)
+    pot = orc.Potential(orc.TABLE, tables=TABLES)
+    ref = orc.eam(pot, x, box)
+    rms = np.sqrt(np.mean(np.sum(ref["F"] ** 2, axis=1)))
+    rows = {}
+    for form in ("fp32", "mlp"):
+        lat = _lattice(n, form)
+        if form == "mlp":
+            lat.set_mlp(nets)
+        lat.set_state(x, v)
+        lat.compute()
+        torch.cuda.synchronize()
+        err = float(np.max(np.linalg.norm(lat.forces() - ref["F"], axis=1)) / rms)
+        lat.step(3, 1.0, 0.05)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(20, 1.0, 0.05)
+        torch.cuda.synchronize()
+        rate = len(x) * 20 / (time.perf_counter() - t0)
+        lat.close()
+        rows[form] = (err, rate)
+    n_tab = sum(len(TABLES[k][2]) for k in ("f", "phi", "F"))
+    table_bytes = 8 * n_tab                                  # float64 samples of the three tables
+    records = 3 * (n_tab // 3 - 1) * 16 + 4095 * (16 + 24)    # float32 cubic records + the q-window
+    weight_bytes = 3 * O.MLP_PARAMS * 2                      # bfloat16 weights of three networks
+    _say(f"table form:   {table_bytes} B of samples ({records} B of float32 records), force error "
+         f"{rows['fp32'][0]:.2e}, {rows['fp32'][1]:.3e} atom-steps/s")
+    _say(f"learned form: {weight_bytes} B of weights, force error {rows['mlp'][0]:.2e}, "
+         f"{rows['mlp'][1]:.3e} atom-steps/s")
+    assert weight_bytes * 15 < table_bytes
+    assert rows["fp32"][0] < 1e-4
+    assert rows["mlp"][0] < 2e-2
