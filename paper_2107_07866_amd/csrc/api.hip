@@ -701,6 +701,10 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(sc.hslot, rcap);
     ALLOC(sc.hkey, H);
     ALLOC(sc.hval, H);
+    ALLOC(sc.hcnt, H);
+    ALLOC(sc.srx, rcap);
+    ALLOC(sc.sry, rcap);
+    ALLOC(sc.srz, rcap);
     ALLOC(sc.mark, sc.mark_nwords);
     ALLOC(sc.mark_blk, sc.mark_nblk);
     ALLOC(sc.mark_off, sc.mark_nblk);
@@ -748,7 +752,8 @@ int misa_destroy_lattice(misa_lattice *h) {
                     h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t64.force6, h->t32.force6, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
-                    h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.mark,
+                    h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.hcnt,
+                    h->sc.srx, h->sc.sry, h->sc.srz, h->sc.mark,
                     h->sc.mark_blk, h->sc.mark_off, h->sc.affected, h->sc.aff_v2, h->sc.aff_e, h->sc.part_kick, h->staging,
                     h->mlp.p[0], h->mlp.p[1], h->mlp.p[2], h->mlp.w2b[0], h->mlp.w2b[1], h->mlp.w2b[2],
                     h->pairbuf};

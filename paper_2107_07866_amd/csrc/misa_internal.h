@@ -282,6 +282,8 @@ struct Scratch {
     // device hash of run-away atoms: sorted (coarse key, index), key -> first position
     int32_t *skey, *sidx;
     int32_t *hkey, *hval, *hslot;
+    int32_t *hcnt;                 // run-aways in the cell of each hash slot
+    double *srx, *sry, *srz;       // run-away positions in the sorted (cell, list index) order
     int32_t hmask;
     // lattice atoms near run-away atoms
     uint32_t *mark;       // 1 bit per site, padded with zero words to mark_nblk blocks

@@ -86,12 +86,12 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t key, int32_t mask) {
     return (h ^ (h >> 16)) & (uint32_t)mask;
 }
 
-__device__ __forceinline__ int32_t hash_find(int32_t key, const int32_t *__restrict__ hkey,
-                                             const int32_t *__restrict__ hval, int32_t mask) {
+// Slot of key in the hash, or -1.
+__device__ __forceinline__ int32_t hash_find(int32_t key, const int32_t *__restrict__ hkey, int32_t mask) {
     uint32_t h = hash_slot(key, mask);
     for (int probe = 0; probe <= mask; ++probe) {
         const int32_t k = hkey[h];
-        if (k == key) return hval[h];
+        if (k == key) return (int32_t)h;
         if (k == -1) return -1;
         h = (h + 1) & (uint32_t)mask;
     }
@@ -415,19 +415,28 @@ __global__ __launch_bounds__(1024) void kb_compact(const BoxRef *__restrict__ bo
 // ---------------------------------------------------------------------------
 // device hash of run-away atoms
 
-__device__ __forceinline__ void hash_insert_body(Scratch sc) {
+// The sorted run-aways: keys, list indices and positions in sorted order; the first
+// entry of each cell enters the cell's key with its start and length.
+__device__ __forceinline__ void hash_insert_body(const State &S, Scratch sc) {
     const int n = sc.cnt->n_run;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
         const uint64_t v = sc.sortbuf[q];
         const int32_t key = (int32_t)(v >> 32);
+        const int32_t o = (int32_t)(v & 0xffffffffu);
         sc.skey[q] = key;
-        sc.sidx[q] = (int32_t)(v & 0xffffffffu);
+        sc.sidx[q] = o;
+        sc.srx[q] = S.r_x[o];
+        sc.sry[q] = S.r_y[o];
+        sc.srz[q] = S.r_z[o];
         const bool start = q == 0 || (int32_t)(sc.sortbuf[q - 1] >> 32) != key;
         if (start) {
+            int end = q + 1;  // a cell holds a few dozen atoms at most (its edge is about rc)
+            while (end < n && (int32_t)(sc.sortbuf[end] >> 32) == key) ++end;
             uint32_t h = hash_slot(key, sc.hmask);
             for (int probe = 0; probe <= sc.hmask; ++probe) {
                 if (atomicCAS(&sc.hkey[h], -1, key) == -1) {
                     sc.hval[h] = q;
+                    sc.hcnt[h] = end - q;
                     sc.hslot[q] = (int32_t)h;
                     break;
                 }
@@ -437,13 +446,13 @@ __device__ __forceinline__ void hash_insert_body(Scratch sc) {
     }
 }
 
-__global__ void k_hash_insert(Scratch sc) {
-    hash_insert_body(sc);
+__global__ void k_hash_insert(State S, Scratch sc) {
+    hash_insert_body(S, sc);
 }
 
 __global__ void kb_hash_insert(const BoxRef *__restrict__ boxes) {
     const BoxRef &B = boxes[blockIdx.y];
-    hash_insert_body(B.sc);
+    hash_insert_body(B.S, B.sc);
 }
 
 
@@ -467,8 +476,8 @@ __global__ void kb_hash_clear(const BoxRef *__restrict__ boxes) {
 
 
 // Run-away atoms in one of the (up to) 27 coarse cells around x, cell = ax + 3 (ay + 3 az);
-// cells beyond the box's distinct neighbours are empty.  fn(o) for entries first,
-// first + stride, ... of the cell's stretch of the sorted list.
+// cells beyond the box's distinct neighbours are empty.  fn(o, xo) for entries first,
+// first + stride, ... of the cell's stretch of the sorted list (o: list index, xo: position).
 template <typename Fn>
 __device__ __forceinline__ void for_runaways_in_cell(const double x[3], int cell, int first, int stride,
                                                      const Scratch &sc, const Geom &g, Fn fn) {
@@ -478,10 +487,14 @@ __device__ __forceinline__ void for_runaways_in_cell(const double x[3], int cell
     if (ay >= axis_cells(coarse_of(x[1], g.nc[1], g.inv_cs[1]), g.nc[1], cy)) return;
     if (az >= axis_cells(coarse_of(x[2], g.nc[2], g.inv_cs[2]), g.nc[2], cz)) return;
     const int32_t key = (cz[az] * g.nc[1] + cy[ay]) * g.nc[0] + cx[ax];
-    const int32_t start = hash_find(key, sc.hkey, sc.hval, sc.hmask);
-    if (start < 0) return;
-    const int n = sc.cnt->n_run;
-    for (int q = start + first; q < n && sc.skey[q] == key; q += stride) fn(sc.sidx[q]);
+    const int32_t slot = hash_find(key, sc.hkey, sc.hmask);
+    if (slot < 0) return;
+    const int start = sc.hval[slot], end = start + sc.hcnt[slot];
+#pragma unroll 2
+    for (int q = start + first; q < end; q += stride) {
+        const double xo[3] = {sc.srx[q], sc.sry[q], sc.srz[q]};
+        fn(sc.sidx[q], xo);
+    }
 }
 
 // Run-away atoms other than self closer than sqrt(cut2) to x, searched by a whole wave:
@@ -493,9 +506,9 @@ __device__ __forceinline__ void for_runaway_neighbours(const double x[3], int se
                                                        Fn fn) {
     const int cell = lane & 31;
     if (cell >= 27) return;
-    for_runaways_in_cell(x, cell, lane >> 5, 2, sc, g, [&](int o) {
+    for_runaways_in_cell(x, cell, lane >> 5, 2, sc, g, [&](int o, const double *xo) {
         if (o == self) return;
-        double d[3] = {S.r_x[o] - x[0], S.r_y[o] - x[1], S.r_z[o] - x[2]};
+        double d[3] = {xo[0] - x[0], xo[1] - x[1], xo[2] - x[2]};
         min_image3(d, g);
         const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         if (r2 < cut2) fn(o, d, r2);
@@ -656,8 +669,7 @@ __device__ __forceinline__ void affected_rho_one(const State &S, const Scratch &
         for (int k = 0; k < 3; ++k) xj[k] = wrap_coord(xj[k] + u[k], g.L[k]);
         double acc = 0.0;
         if (cell < 27)
-            for_runaways_in_cell(xj, cell, 0, 1, sc, g, [&](int o) {
-                const double xo[3] = {S.r_x[o], S.r_y[o], S.r_z[o]};
+            for_runaways_in_cell(xj, cell, 0, 1, sc, g, [&](int, const double *xo) {
                 double d[3], r2;
                 if (affected_pair(xo, cj, p, u, g, d, r2)) acc += f_val(sqrt(r2), T);
             });
@@ -826,8 +838,7 @@ __device__ __forceinline__ void affected_force_one(const State &S, const Scratch
         for (int k = 0; k < 3; ++k) xj[k] = wrap_coord(xj[k] + u[k], g.L[k]);
         double ax = 0.0, ay = 0.0, az = 0.0;
         if (cell < 27)
-            for_runaways_in_cell(xj, cell, 0, 1, sc, g, [&](int o) {
-                const double xo[3] = {S.r_x[o], S.r_y[o], S.r_z[o]};
+            for_runaways_in_cell(xj, cell, 0, 1, sc, g, [&](int o, const double *xo) {
                 double d[3], r2;  // d = x_j - x_o
                 if (!affected_pair(xo, cj, p, u, g, d, r2)) return;
                 const double rr = sqrt(r2);
@@ -1169,7 +1180,7 @@ hipError_t launch_runaway_build(misa_lattice *h) {
     hipStream_t st = h->stream;
     hipLaunchKernelGGL(k_sort, dim3(1), dim3(SORT_THREADS), 0, st, h->sc.sortbuf, 1, h->sc.cnt, h->rcap, nullptr,
                        h->S.r_x, h->S.r_y, h->S.r_z, h->g, h->sc.scal);
-    hipLaunchKernelGGL(k_hash_insert, dim3(SMALL_GRID), dim3(256), 0, st, h->sc);
+    hipLaunchKernelGGL(k_hash_insert, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc);
     return hipGetLastError();
 }
 
@@ -1218,30 +1229,41 @@ hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, 
     return hipGetLastError();
 }
 
+// Blocks of a grid-stride kernel over the flattened lists that keep every compute unit
+// at the kernel's occupancy (its waves are latency-bound chains of scattered loads, so
+// the more resident, the better), and at least FLAT_BLOCKS.
+template <typename Kernel>
+static int fill_grid(const misa_lattice *h0, Kernel k, int threads, size_t lds) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds) != hipSuccess) per_cu = 0;
+    return std::max(FLAT_BLOCKS, per_cu * h0->n_cu);
+}
+
 // off: 2 (nbox + 1) ints for the offsets of the run-away and affected-atom lists.  The
 // force half reuses the offsets the density half computed (neither count changes in between).
 hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int mark_blocks, int32_t *off) {
     hipStream_t st = h0->stream;
     const size_t lds = sizeof(int32_t) * (nbox + 1);
     hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 0, off);
-    hipLaunchKernelGGL(kf_runaway_rho, dim3(FLAT_BLOCKS), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes, nbox,
-                       off, t64_of(h0));
+    hipLaunchKernelGGL(kf_runaway_rho, dim3(fill_grid(h0, kf_runaway_rho, 64 * RUNAWAY_WAVES_PER_BLOCK, lds)),
+                       dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes, nbox, off, t64_of(h0));
     hipLaunchKernelGGL(kb_mark_count, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
     hipLaunchKernelGGL(kb_mark_scan, dim3(1, nbox), dim3(1024), 0, st, boxes);
     hipLaunchKernelGGL(kb_mark_emit, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
     hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 1, off + nbox + 1);
-    hipLaunchKernelGGL(kf_affected_rho, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox, off + nbox + 1,
-                       t64_of(h0), t32_of(h0), near_fix_of(h0));
+    hipLaunchKernelGGL(kf_affected_rho, dim3(fill_grid(h0, kf_affected_rho, AFF_THREADS, lds)), dim3(AFF_THREADS),
+                       lds, st, boxes, nbox, off + nbox + 1, t64_of(h0), t32_of(h0), near_fix_of(h0));
     return hipGetLastError();
 }
 
 hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, bool energy, const int32_t *off) {
     hipStream_t st = h0->stream;
     const size_t lds = sizeof(int32_t) * (nbox + 1);
-    hipLaunchKernelGGL(kf_runaway_force, dim3(FLAT_BLOCKS), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes, nbox,
-                       off, t64_of(h0), energy ? 1 : 0);
-    hipLaunchKernelGGL(kf_affected_force, dim3(FLAT_BLOCKS), dim3(AFF_THREADS), lds, st, boxes, nbox, off + nbox + 1,
-                       t64_of(h0), ACC_UNIT / h0->mass, near_fix_of(h0), energy ? 1 : 0);
+    hipLaunchKernelGGL(kf_runaway_force, dim3(fill_grid(h0, kf_runaway_force, 64 * RUNAWAY_WAVES_PER_BLOCK, lds)),
+                       dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes, nbox, off, t64_of(h0), energy ? 1 : 0);
+    hipLaunchKernelGGL(kf_affected_force, dim3(fill_grid(h0, kf_affected_force, AFF_THREADS, lds)),
+                       dim3(AFF_THREADS), lds, st, boxes, nbox, off + nbox + 1, t64_of(h0), ACC_UNIT / h0->mass,
+                       near_fix_of(h0), energy ? 1 : 0);
     return hipGetLastError();
 }
 
