@@ -405,6 +405,18 @@ int misa_mlp_adam(misa_mlp_trainer *t, int fn, const double *grad, double lr);
 int misa_mlp_fit(misa_mlp_trainer *t, int fn, const double *x, const double *y, const double *dy, int64_t n,
                  const misa_fit_opts *o, double *loss);
 
+/* misa_mlp_fit of nnet (1 to 3) different networks fns[k] together, with the same
+ * options: network k fits its own samples x[k], y[k], dy[k] (n[k] each, device
+ * memory) and draws its own mini-batches exactly as misa_mlp_fit alone would with
+ * seed o->seed + fns[k], so the weights are bit for bit those of nnet separate
+ * calls with those seeds; one kernel launch per
+ * step serves all of them (each step's partial gradients, their sum and the Adam
+ * update in that one launch).  loss[k] (host, may be NULL): as misa_mlp_fit's.
+ * MISA_EINVAL for a network listed twice or a batch above 65535 * 64. */
+int misa_mlp_fit_many(misa_mlp_trainer *t, int nnet, const int *fns, const double *const *x,
+                      const double *const *y, const double *const *dy, const int64_t *n, const misa_fit_opts *o,
+                      double *loss);
+
 /* Force-matching data from the current state of a lattice handle after
  * misa_compute_rho: for each of the n lattice sites sites[] (lattice ids of
  * Sec. 3, host memory), the pairs of the atom it holds with slotted

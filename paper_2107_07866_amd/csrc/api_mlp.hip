@@ -37,6 +37,7 @@ struct misa_mlp_trainer {
     double *fm_x = nullptr, *fm_cf = nullptr, *fm_cp = nullptr, *fm_zero = nullptr, *fm_loss = nullptr;
     int64_t fm_cap = 0;
     double *scalar = nullptr;
+    int32_t *tickets = nullptr;  // [3] finished blocks of a fused fit iteration, zero between launches
 };
 
 namespace {
@@ -355,6 +356,8 @@ int misa_mlp_trainer_create(void *hip_stream, misa_mlp_trainer **out) {
     t->stream = (hipStream_t)hip_stream;
     hipError_t e = hipMalloc((void **)&t->grad, sizeof(double) * MLP_NP);
     if (e == hipSuccess) e = hipMalloc((void **)&t->scalar, sizeof(double) * 8);
+    if (e == hipSuccess) e = hipMalloc((void **)&t->tickets, sizeof(int32_t) * 3);
+    if (e == hipSuccess) e = hipMemset(t->tickets, 0, sizeof(int32_t) * 3);
     for (int f = 0; f < 3 && e == hipSuccess; ++f) {
         auto &N = t->net[f];
         float **bufs[] = {&N.w, &N.m, &N.v, &N.q};
@@ -374,7 +377,7 @@ int misa_mlp_trainer_destroy(misa_mlp_trainer *t) {
     if (!t) return MISA_OK;
     (void)hipStreamSynchronize(t->stream);
     void *ptrs[] = {t->part, t->grad, t->loss_part, t->loss_hist, t->envs, t->fm_x, t->fm_cf,
-                    t->fm_cp, t->fm_zero, t->fm_loss, t->scalar};
+                    t->fm_cp, t->fm_zero, t->fm_loss, t->scalar, t->tickets};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &N : t->net) {
@@ -476,43 +479,93 @@ int misa_mlp_adam(misa_mlp_trainer *t, int fn, const double *grad, double lr) {
     return MISA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Fit networks fns[0 .. nnet - 1] together: one launch of k_fit_step per iteration
+// for all of them (each draws its own mini-batches, as when fitted alone, so the
+// result does not depend on which networks share the launches).
+// Network fns[k] draws with seed o->seed + seed_step fns[k].
+int fit_fused(misa_mlp_trainer *t, int nnet, const int *fns, const double *const *x, const double *const *y,
+              const double *const *dy, const int64_t *n, const misa_fit_opts *o, uint64_t seed_step,
+              double *loss) {
+    int rc = check_opts(t, o);
+    if (rc) return rc;
+    if (nnet < 1 || nnet > 3 || !fns || !x || !y || !dy || !n) return tfail(t, MISA_EINVAL, "bad arguments");
+    for (int k = 0; k < nnet; ++k) {
+        if (fns[k] < 0 || fns[k] > 2 || n[k] < 1 || !x[k] || !y[k] || !dy[k])
+            return tfail(t, MISA_EINVAL, "bad arguments");
+        for (int l = 0; l < k; ++l)
+            if (fns[l] == fns[k]) return tfail(t, MISA_EINVAL, "a network listed twice");
+        if (!t->net[fns[k]].set) return tfail(t, MISA_ESTATE, "network not set (misa_mlp_trainer_set)");
+    }
+    const int64_t nblk = (o->batch + GRAD_SAMPLES - 1) / GRAD_SAMPLES;
+    if (nblk > 65535) return tfail(t, MISA_EINVAL, "batch too large");
+    const int64_t tail = std::max<int64_t>(1, o->iters / 100);
+    rc = ensure_scratch(t, nnet * nblk, nnet * nblk, nnet * tail);
+    if (rc) return rc;
+    for (int k = 0; k < nnet; ++k) {
+        auto &N = t->net[fns[k]];
+        N.sx = x[k];
+        N.sy = y[k];
+        N.sdy = dy[k];
+        N.sn = n[k];
+        N.lam = o->lambda;
+    }
+    for (int64_t i = 0; i < o->iters; ++i) {
+        FitSteps F{};
+        F.nnet = nnet;
+        F.lr = lr_at(o, i);
+        for (int k = 0; k < nnet; ++k) {
+            auto &N = t->net[fns[k]];
+            const float *pw = o->quantize ? N.q : N.w;
+            FitStep &S = F.s[k];
+            S.J = fit_job(t, fns[k], pw, o->batch, o->seed + seed_step * (uint64_t)fns[k], t->loss_part + k * nblk,
+                          t->part + k * nblk * MLP_NP);
+            N.step += 1;
+            S.w = N.w;
+            S.m = N.m;
+            S.v = N.v;
+            S.q = N.q;
+            S.bc1 = 1.0 - std::pow(0.9, (double)N.step);
+            S.bc2 = 1.0 - std::pow(0.999, (double)N.step);
+            S.ticket = t->tickets + k;
+            S.loss_hist = t->loss_hist + k * tail;
+            S.slot = i >= o->iters - tail ? (int)(i - (o->iters - tail)) : -1;
+        }
+        TCHK(t, launch_fit_step(t->stream, F, (int)nblk));
+    }
+    for (int k = 0; k < nnet; ++k) {
+        auto &N = t->net[fns[k]];
+        TCHK(t, launch_round_weights(t->stream, N.w, N.q, N.w2b));
+    }
+    std::vector<double> h(nnet * tail);
+    TCHK(t, hipMemcpyAsync(h.data(), t->loss_hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, t->stream));
+    TCHK(t, hipStreamSynchronize(t->stream));
+    if (loss)
+        for (int k = 0; k < nnet; ++k) {
+            double s = 0.0;
+            for (int64_t j = 0; j < tail; ++j) s += h[k * tail + j];
+            loss[k] = s / (double)tail / (double)o->batch;
+        }
+    return MISA_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int misa_mlp_fit(misa_mlp_trainer *t, int fn, const double *x, const double *y, const double *dy, int64_t n,
                  const misa_fit_opts *o, double *loss) {
     if (!t) return MISA_EINVAL;
     if (fn < 0 || fn > 2 || n < 1 || !x || !y || !dy) return tfail(t, MISA_EINVAL, "bad arguments");
-    int rc = check_opts(t, o);
-    if (rc) return rc;
-    auto &N = t->net[fn];
-    if (!N.set) return tfail(t, MISA_ESTATE, "network not set (misa_mlp_trainer_set)");
-    N.sx = x;
-    N.sy = y;
-    N.sdy = dy;
-    N.sn = n;
-    N.lam = o->lambda;
-    const int64_t nblk = (o->batch + GRAD_SAMPLES - 1) / GRAD_SAMPLES;
-    const int64_t tail = std::max<int64_t>(1, o->iters / 100);
-    rc = ensure_scratch(t, nblk, nblk, tail);
-    if (rc) return rc;
-    for (int64_t i = 0; i < o->iters; ++i) {
-        const float *pw = o->quantize ? N.q : N.w;
-        GradJob J = fit_job(t, fn, pw, o->batch, o->seed, t->loss_part, t->part);
-        TCHK(t, launch_grad(t->stream, J, (int)nblk));
-        TCHK(t, launch_grad_sum(t->stream, t->part, (int)nblk, t->grad));
-        if (i >= o->iters - tail)
-            TCHK(t, launch_sum_into(t->stream, t->loss_part, (int)nblk, t->loss_hist, (int)(i - (o->iters - tail))));
-        N.step += 1;
-        TCHK(t, launch_adam(t->stream, N.w, N.m, N.v, t->grad, N.q, lr_at(o, i), N.step));
-    }
-    TCHK(t, launch_round_weights(t->stream, N.w, N.q, N.w2b));
-    std::vector<double> h(tail);
-    TCHK(t, hipMemcpyAsync(h.data(), t->loss_hist, sizeof(double) * tail, hipMemcpyDeviceToHost, t->stream));
-    TCHK(t, hipStreamSynchronize(t->stream));
-    if (loss) {
-        double s = 0.0;
-        for (double v : h) s += v;
-        *loss = s / (double)tail / (double)o->batch;
-    }
-    return MISA_OK;
+    return fit_fused(t, 1, &fn, &x, &y, &dy, &n, o, 0, loss);
+}
+
+int misa_mlp_fit_many(misa_mlp_trainer *t, int nnet, const int *fns, const double *const *x,
+                      const double *const *y, const double *const *dy, const int64_t *n, const misa_fit_opts *o,
+                      double *loss) {
+    if (!t) return MISA_EINVAL;
+    return fit_fused(t, nnet, fns, x, y, dy, n, o, 1, loss);
 }
 
 int misa_mlp_force_match(misa_mlp_trainer *t, const double *r, const double *dhat, const double *fp_j,

@@ -71,6 +71,9 @@ __device__ __forceinline__ void mlp_eval_lane(const MlpNet &m, float x, float &g
 // Training jobs (filled on the host, read by the kernels).
 
 constexpr int GRAD_SAMPLES = 64;  // samples per block of the gradient kernel
+constexpr int GRAD_SPLIT = 4;                           // lanes per sample
+constexpr int GRAD_THREADS = GRAD_SAMPLES * GRAD_SPLIT;  // threads per block of the gradient kernel
+constexpr int GRAD_UNITS = MLP_H / GRAD_SPLIT;           // hidden units per lane
 
 struct GradJob {
     const float *p;        // weights used by the forward pass
@@ -89,6 +92,22 @@ struct GradJob {
     double *loss_part;     // [blocks] (Sobolev mode)
 };
 
+// One network's share of a fused fit iteration (k_fit_step).
+struct FitStep {
+    GradJob J;                     // the gradient job; J.part holds gridDim.x partials
+    float *w, *m, *v, *q;          // float32 master weights, Adam moments, bfloat16 copy
+    double bc1, bc2;               // Adam bias corrections of this step
+    int32_t *ticket;               // blocks finished in this launch (zero between launches)
+    double *loss_hist;             // the iteration's summed loss goes to loss_hist[slot] if slot >= 0
+    int slot;
+};
+
+struct FitSteps {
+    FitStep s[3];
+    int nnet;
+    double lr;
+};
+
 struct FmJob {
     MlpNet nf, np;              // forward weights (training copies)
     const double *r, *dhat, *fpj, *fpi, *fref;
@@ -104,6 +123,7 @@ struct FmJob {
 hipError_t launch_mlp_eval(hipStream_t st, int path, const MlpNet &m, const uint16_t *w2b, const double *x,
                            int64_t n, double *y, double *dy);
 hipError_t launch_grad(hipStream_t st, const GradJob &J, int nblk);
+hipError_t launch_fit_step(hipStream_t st, const FitSteps &F, int nblk);
 hipError_t launch_grad_sum(hipStream_t st, const float *part, int nblk, double *grad);
 hipError_t launch_adam(hipStream_t st, float *w, float *m, float *v, const double *grad, float *q, double lr,
                        int64_t step);

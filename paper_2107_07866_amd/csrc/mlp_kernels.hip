@@ -360,7 +360,16 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(GRAD_SAMPLES) void k_grad(GradJob J) {
+// Partial gradient of block blk (samples blk GRAD_SAMPLES ..) into J.part[blk], and
+// its Sobolev loss into J.loss_part[blk].  GRAD_SPLIT consecutive lanes serve one
+// sample, each taking GRAD_UNITS of the hidden units of both layers (sums over a
+// sample's units: a fixed butterfly over its lanes).
+__device__ __forceinline__ float split_sum(float v) {
+    for (int o = 1; o < GRAD_SPLIT; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void grad_block(const GradJob &J, int blk) {
     // weights and per-sample vectors in LDS (rows padded against bank conflicts)
     __shared__ float P[MLP_NP];
     __shared__ float sh1[GRAD_SAMPLES][GS], sd1[GRAD_SAMPLES][GS], sa1[GRAD_SAMPLES][GS];
@@ -368,9 +377,10 @@ __global__ __launch_bounds__(GRAD_SAMPLES) void k_grad(GradJob J) {
     __shared__ float sp1[GRAD_SAMPLES][GS], sz1[GRAD_SAMPLES][GS];
     __shared__ float scv[GRAD_SAMPLES];
     __shared__ double sloss[GRAD_SAMPLES];
-    const int b = threadIdx.x;
-    for (int j = b; j < MLP_NP; j += GRAD_SAMPLES) P[j] = J.p[j];
-    const int64_t i = (int64_t)blockIdx.x * GRAD_SAMPLES + b;
+    const int tid = threadIdx.x;
+    const int b = tid / GRAD_SPLIT, u0 = (tid % GRAD_SPLIT) * GRAD_UNITS;  // sample, first unit of this lane
+    for (int j = tid; j < MLP_NP; j += GRAD_THREADS) P[j] = J.p[j];
+    const int64_t i = (int64_t)blk * GRAD_SAMPLES + b;
     const bool sob = J.cval == nullptr;
     const int64_t count = sob ? J.batch : J.n;
     const bool live = i < count;
@@ -383,8 +393,9 @@ __global__ __launch_bounds__(GRAD_SAMPLES) void k_grad(GradJob J) {
         idx = 0;
     const float t = ((float)J.x[idx] - J.c) * J.s;
     __syncthreads();
-    // forward with tangents
-    for (int k = 0; k < MLP_H; ++k) {
+    // forward with tangents: layer 1
+    for (int kk = 0; kk < GRAD_UNITS; ++kk) {
+        const int k = u0 + kk;
         const float w = P[OFF_W1 + k];
         const float z = w * t + P[OFF_B1 + k];
         const float sg = sigm(z);
@@ -394,8 +405,11 @@ __global__ __launch_bounds__(GRAD_SAMPLES) void k_grad(GradJob J) {
         sa1[b][k] = a;
         sd1[b][k] = a * w;
     }
-    float y = P[OFF_B3], dyt = 0.0f;
-    for (int n = 0; n < MLP_H; ++n) {
+    __syncthreads();
+    // layer 2 and the output
+    float y = 0.0f, dyt = 0.0f;
+    for (int nn = 0; nn < GRAD_UNITS; ++nn) {
+        const int n = u0 + nn;
         const float *w2 = P + OFF_W2 + n * MLP_H;
         float z = P[OFF_B2 + n], dz = 0.0f;
 #pragma unroll 8
@@ -411,6 +425,8 @@ __global__ __launch_bounds__(GRAD_SAMPLES) void k_grad(GradJob J) {
         su[b][n] = z;   // z2 until the reverse pass
         sv[b][n] = dz;  // dz2 until the reverse pass
     }
+    y = split_sum(y) + P[OFF_B3];
+    dyt = split_sum(dyt);
     float cv, cd;
     double loss = 0.0;
     if (sob) {
@@ -425,8 +441,9 @@ __global__ __launch_bounds__(GRAD_SAMPLES) void k_grad(GradJob J) {
         cv = live ? (float)J.cval[idx] : 0.0f;
         cd = live ? (float)J.cder[idx] : 0.0f;
     }
-    // reverse through layer 2
-    for (int n = 0; n < MLP_H; ++n) {
+    // reverse through layer 2 (this lane's output units)
+    for (int nn = 0; nn < GRAD_UNITS; ++nn) {
+        const int n = u0 + nn;
         const float z = su[b][n], dz = sv[b][n];
         const float sg = sigm(z);
         const float h2 = z * sg;
@@ -437,8 +454,10 @@ __global__ __launch_bounds__(GRAD_SAMPLES) void k_grad(GradJob J) {
         su[b][n] = cv * w3 * a2 + cd * w3 * dz * s2;  // d/dz2
         sv[b][n] = cd * w3 * a2;                   // d/d(dz2)
     }
-    // reverse through layer 1
-    for (int k = 0; k < MLP_H; ++k) {
+    __syncthreads();
+    // reverse through layer 1 (this lane's hidden units)
+    for (int kk = 0; kk < GRAD_UNITS; ++kk) {
+        const int k = u0 + kk;
         float gh = 0.0f, gd = 0.0f;
 #pragma unroll 8
         for (int n = 0; n < MLP_H; ++n) {
@@ -455,41 +474,99 @@ __global__ __launch_bounds__(GRAD_SAMPLES) void k_grad(GradJob J) {
         sp1[b][k] = gd * a1 + gz1 * t;  // d/dW1
         sz1[b][k] = gz1;                // d/db1
     }
-    scv[b] = cv;
-    sloss[b] = loss;
+    if (u0 == 0) {
+        scv[b] = cv;
+        sloss[b] = loss;
+    }
     __syncthreads();
     // block sums in a fixed order
-    float *out = J.part + (int64_t)blockIdx.x * MLP_NP;
-    const int n = b >> 1, k0 = (b & 1) * 16;
-    for (int j = 0; j < 16; ++j) {
-        const int k = k0 + j;
-        float s = 0.0f;
+    float *out = J.part + (int64_t)blk * MLP_NP;
+    {
+        constexpr int PER = MLP_H * MLP_H / GRAD_THREADS;  // entries of W2 per thread
+        const int n = tid / (MLP_H / PER), k0 = (tid % (MLP_H / PER)) * PER;
+        for (int j = 0; j < PER; ++j) {
+            const int k = k0 + j;
+            float s = 0.0f;
 #pragma unroll 8
-        for (int q = 0; q < GRAD_SAMPLES; ++q) s += su[q][n] * sh1[q][k] + sv[q][n] * sd1[q][k];
-        out[OFF_W2 + n * MLP_H + k] = s;
+            for (int q = 0; q < GRAD_SAMPLES; ++q) s += su[q][n] * sh1[q][k] + sv[q][n] * sd1[q][k];
+            out[OFF_W2 + n * MLP_H + k] = s;
+        }
     }
-    if (b < MLP_H) {
+    if (tid < MLP_H) {
         float g1 = 0.0f, gb1 = 0.0f, gb2 = 0.0f, gw3 = 0.0f;
         for (int q = 0; q < GRAD_SAMPLES; ++q) {
-            g1 += sp1[q][b];
-            gb1 += sz1[q][b];
-            gb2 += su[q][b];
-            gw3 += sq[q][b];
+            g1 += sp1[q][tid];
+            gb1 += sz1[q][tid];
+            gb2 += su[q][tid];
+            gw3 += sq[q][tid];
         }
-        out[OFF_W1 + b] = g1;
-        out[OFF_B1 + b] = gb1;
-        out[OFF_B2 + b] = gb2;
-        out[OFF_W3 + b] = gw3;
+        out[OFF_W1 + tid] = g1;
+        out[OFF_B1 + tid] = gb1;
+        out[OFF_B2 + tid] = gb2;
+        out[OFF_W3 + tid] = gw3;
     }
-    if (b == MLP_H) {
+    if (tid == MLP_H) {
         float g3 = 0.0f;
         for (int q = 0; q < GRAD_SAMPLES; ++q) g3 += scv[q];
         out[OFF_B3] = g3;
     }
-    if (b == MLP_H + 1 && J.loss_part) {
+    if (tid == MLP_H + 1 && J.loss_part) {
         double l = 0.0;
         for (int q = 0; q < GRAD_SAMPLES; ++q) l += sloss[q];
-        J.loss_part[blockIdx.x] = l;
+        J.loss_part[blk] = l;
+    }
+}
+
+__global__ __launch_bounds__(GRAD_THREADS) void k_grad(GradJob J) { grad_block(J, blockIdx.x); }
+
+// Adam on element j of a network's float32 master weights (q: the bfloat16 rounding).
+__device__ __forceinline__ void adam_one(int j, double g, float *__restrict__ w, float *__restrict__ m,
+                                         float *__restrict__ v, float *__restrict__ q, double lr, double bc1,
+                                         double bc2) {
+    const double mj = 0.9 * (double)m[j] + 0.1 * g;
+    const double vj = 0.999 * (double)v[j] + 0.001 * g * g;
+    m[j] = (float)mj;
+    v[j] = (float)vj;
+    const double step = lr * (mj / bc1) / (sqrt(vj / bc2) + 1e-8);
+    const float wj = (float)((double)w[j] - step);
+    w[j] = wj;
+    q[j] = bf16_float(bf16_bits(wj));
+}
+
+// One fit iteration of up to three networks in one launch (blockIdx.y = network):
+// every block writes its partial gradient; the block that finishes last for its
+// network sums the partials in block order (float64, as k_grad_sum) and takes the
+// Adam step (as k_adam), so an iteration is one launch and the GPU never waits on
+// the host between the gradient and the update.  Counting the finished blocks is
+// the only cross-block step; nothing waits on another block.
+__global__ __launch_bounds__(GRAD_THREADS) void k_fit_step(FitSteps F) {
+    const FitStep &S = F.s[blockIdx.y];
+    grad_block(S.J, blockIdx.x);
+    __shared__ int last;
+    __threadfence();  // this block's partial gradient and loss, before the count
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(S.ticket, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    // agent-scope acquire: the other blocks' partials are read from L2 (this block has
+    // not read them before, and the fence invalidates its L1)
+    __threadfence();
+    const float *part = S.J.part;
+    for (int j = threadIdx.x; j < MLP_NP; j += GRAD_THREADS) {
+        double g = 0.0;
+        // all partials of element j in flight at once; summed in block order
+#pragma unroll 64
+        for (int q = 0; q < (int)gridDim.x; ++q) g += (double)part[(int64_t)q * MLP_NP + j];
+        adam_one(j, g, S.w, S.m, S.v, S.q, F.lr, S.bc1, S.bc2);
+    }
+    if (threadIdx.x == 0) {
+        if (S.slot >= 0) {
+            const double *lp = S.J.loss_part;
+            double l = 0.0;
+            for (int q = 0; q < (int)gridDim.x; ++q) l += lp[q];
+            S.loss_hist[S.slot] = l;
+        }
+        *S.ticket = 0;  // for the next iteration (a later launch on the same stream)
     }
 }
 
@@ -505,17 +582,8 @@ __global__ void k_grad_sum(const float *__restrict__ part, int nblk, double *__r
 // Adam on the float32 master weights; q receives them rounded to bfloat16.
 __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
                        const double *__restrict__ grad, float *__restrict__ q, double lr, double bc1, double bc2) {
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < MLP_NP; j += gridDim.x * blockDim.x) {
-        const double g = grad[j];
-        const double mj = 0.9 * (double)m[j] + 0.1 * g;
-        const double vj = 0.999 * (double)v[j] + 0.001 * g * g;
-        m[j] = (float)mj;
-        v[j] = (float)vj;
-        const double step = lr * (mj / bc1) / (sqrt(vj / bc2) + 1e-8);
-        const float wj = (float)((double)w[j] - step);
-        w[j] = wj;
-        q[j] = bf16_float(bf16_bits(wj));
-    }
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < MLP_NP; j += gridDim.x * blockDim.x)
+        adam_one(j, grad[j], w, m, v, q, lr, bc1, bc2);
 }
 
 __global__ void k_round_weights(const float *__restrict__ w, float *__restrict__ q, uint16_t *__restrict__ w2b) {
@@ -526,8 +594,13 @@ __global__ void k_round_weights(const float *__restrict__ w, float *__restrict__
     }
 }
 
+hipError_t launch_fit_step(hipStream_t st, const FitSteps &F, int nblk) {
+    hipLaunchKernelGGL(k_fit_step, dim3(nblk, F.nnet), dim3(GRAD_THREADS), 0, st, F);
+    return hipGetLastError();
+}
+
 hipError_t launch_grad(hipStream_t st, const GradJob &J, int nblk) {
-    hipLaunchKernelGGL(k_grad, dim3(nblk), dim3(GRAD_SAMPLES), 0, st, J);
+    hipLaunchKernelGGL(k_grad, dim3(nblk), dim3(GRAD_THREADS), 0, st, J);
     return hipGetLastError();
 }
 

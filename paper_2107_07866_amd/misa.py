@@ -119,6 +119,7 @@ def _load():
         "misa_mlp_grad": ([vp, C.c_int, vp, vp, vp, i64, vp], C.c_int),
         "misa_mlp_adam": ([vp, C.c_int, vp, C.c_double], C.c_int),
         "misa_mlp_fit": ([vp, C.c_int, vp, vp, vp, i64, C.POINTER(misa_fit_opts), dp], C.c_int),
+        "misa_mlp_fit_many": ([vp, C.c_int, vp, vp, vp, vp, vp, C.POINTER(misa_fit_opts), vp], C.c_int),
         "misa_mlp_collect": ([vp, vp, i64, vp, vp, vp, vp, vp], C.c_int),
         "misa_mlp_force_match": ([vp, vp, vp, vp, vp, vp, i64, C.POINTER(misa_fit_opts), dp], C.c_int),
         "misa_batch_create": ([C.POINTER(misa_lattice_desc), C.c_int32, vp, C.POINTER(vp)], C.c_int),
@@ -439,6 +440,18 @@ def misa_mlp_fit(t, fn, x, y, dy, opts):
     o = _opts(opts)
     _tcheck(lib.misa_mlp_fit(t, int(fn), _dev(x), _dev(y), _dev(dy), x.numel(), C.byref(o), C.byref(loss)), t)
     return loss.value
+
+
+def misa_mlp_fit_many(t, fns, xs, ys, dys, opts):
+    """Fit networks fns together; xs, ys, dys: lists of CUDA float64 tensors. Returns the losses."""
+    k = len(fns)
+    f = (C.c_int * k)(*[int(v) for v in fns])
+    ptr = lambda ts: (C.c_void_p * k)(*[_dev(v) for v in ts])
+    n = (C.c_int64 * k)(*[int(v.numel()) for v in xs])
+    loss = (C.c_double * k)()
+    o = _opts(opts)
+    _tcheck(lib.misa_mlp_fit_many(t, k, f, ptr(xs), ptr(ys), ptr(dys), n, C.byref(o), loss), t)
+    return list(loss)
 
 
 def misa_mlp_collect(h, sites, r, dhat, fp_j, fp_i, f_ref):

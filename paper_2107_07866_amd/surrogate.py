@@ -41,7 +41,7 @@ def table_samples(h, fn, lo, hi, n, rng, device="cuda"):
     return x, y, dy
 
 
-DEFAULT_FIT = dict(iters=60000, batch=4096, quantize=1, lr=1e-2, lr_final=1e-6, seed=7)
+DEFAULT_FIT = dict(iters=120000, batch=4096, quantize=1, lr=5e-3, lr_final=1e-6, seed=7)
 
 
 def fit_surrogates(h, rc, n_samples=1_000_000, seed=11, fit=None, ranges=None, trainer=None, device="cuda"):
@@ -54,16 +54,22 @@ def fit_surrogates(h, rc, n_samples=1_000_000, seed=11, fit=None, ranges=None, t
     rng = np.random.default_rng(seed)
     t = trainer or M.misa_mlp_trainer_create(torch.cuda.current_stream().cuda_stream)
     nets, losses, samples = {}, {}, {}
-    for fn in (M.MISA_FN_F, M.MISA_FN_PHI, M.MISA_FN_EMB):
+    fns = (M.MISA_FN_F, M.MISA_FN_PHI, M.MISA_FN_EMB)
+    for fn in fns:
         lo, hi = ranges[fn]
         x, y, dy = table_samples(h, fn, lo, hi, n_samples, rng, device)
         ys = y.double()
         net = {"x_lo": lo, "x_hi": hi, "y_shift": float(ys.mean()), "y_scale": float(ys.std()),
                "params": init_params(rng)}
         M.misa_mlp_trainer_set(t, fn, net)
-        losses[fn] = M.misa_mlp_fit(t, fn, x, y, dy, dict(fit, seed=fit["seed"] + fn))
-        nets[fn], _ = M.misa_mlp_trainer_get(t, fn)
         samples[fn] = (x, y, dy)
+    # the three networks step together (one launch per optimiser step for all of them);
+    # network fn draws its mini-batches with seed fit["seed"] + fn
+    fitted = M.misa_mlp_fit_many(t, fns, [samples[f][0] for f in fns], [samples[f][1] for f in fns],
+                                 [samples[f][2] for f in fns], fit)
+    for fn, loss in zip(fns, fitted):
+        losses[fn] = loss
+        nets[fn], _ = M.misa_mlp_trainer_get(t, fn)
     return t, nets, losses, samples
 
 

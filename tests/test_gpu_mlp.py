@@ -461,3 +461,76 @@ def test_learned_vs_table_side_by_side(M, trainer, torch_cuda, orc):
     assert weight_bytes * 15 < table_bytes
     assert rows["fp32"][0] < 1e-4
     assert rows["mlp"][0] < 2e-2
+
+
+def _splitmix64(z):
+    z = (z + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    return z ^ (z >> 31)
+
+
+def test_fused_fit_step_matches_oracle(M, trainer, torch_cuda, orc):
+    """Two steps of misa_mlp_fit (the fused launch: partial gradients, their sum and
+    the Adam update) against the oracle: the same SplitMix64 mini-batches, the
+    Sobolev loss coefficients, the parameter gradient and two Adam updates."""
+    torch = torch_cuda
+    fn, n, batch, lr, lam, seed = 1, 3000, 200, 2e-3, 1.0, 77
+    lo, hi = RANGES[fn]
+    net = rand_net(500, fn)
+    M.misa_mlp_trainer_set(trainer, fn, net)
+    rng = np.random.default_rng(501)
+    x = rng.uniform(lo, hi, n)
+    y, dy, _ = orc.spline_eval(*TABLES[ORC_KEYS[fn]], x)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    M.misa_mlp_fit(trainer, fn, dev(x), dev(y), dev(dy),
+                   dict(iters=2, batch=batch, quantize=0, lr=lr, lr_final=lr, seed=seed, **{"lambda": lam}))
+    _, master = M.misa_mlp_trainer_get(trainer, fn)
+    c, s = O.scaling(lo, hi)
+    p = np.asarray(net["params"], dtype=np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for step in range(2):
+        idx = np.array([_splitmix64(seed ^ _splitmix64((step * 0x100000001B3 + i) & 0xFFFFFFFFFFFFFFFF)) % n
+                        for i in range(batch)])
+        t = (x[idx] - c) * s
+        yn, dyn = O.forward_t(p.astype(np.float32).astype(np.float64), t)
+        cv, cd, _ = O.sobolev_coefs(yn, dyn, (y[idx] - net["y_shift"]) / net["y_scale"],
+                                    dy[idx] / (net["y_scale"] * s), lam)
+        g = O.param_grad(p.astype(np.float32).astype(np.float64), t, cv, cd)
+        p, m, v = O.adam_step(p, g, m, v, step + 1, lr)
+        p = p.astype(np.float32).astype(np.float64)  # float32 master weights
+    err = np.abs(master - p)
+    _say(f"fused fit, two steps: max |w - w_oracle| {err.max():.2e} (steps of size {lr})")
+    # Adam's first steps move each weight by about lr whatever the gradient's size, so a
+    # weight agrees to float32 rounding unless its gradient is too small to fix a sign
+    assert np.sum(err > 1e-6 * np.abs(p).max()) <= 3
+    assert err.max() <= 2.5 * lr
+
+
+def test_fit_many_equals_separate_fits(M, torch_cuda):
+    """misa_mlp_fit_many of three networks gives network fn bit for bit the weights of
+    a misa_mlp_fit call of its own with the seed raised by fn."""
+    torch = torch_cuda
+    opts = dict(iters=40, batch=512, quantize=1, lr=5e-3, lr_final=1e-4, seed=3)
+    rng = np.random.default_rng(602)
+    data = {}
+    for fn in FNS:
+        lo, hi = RANGES[fn]
+        x = rng.uniform(lo, hi, 5000)
+        y, dy = np.sin(x), np.cos(x)
+        data[fn] = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (x, y, dy)]
+    got = {}
+    for together in (True, False):
+        t = M.misa_mlp_trainer_create(torch.cuda.current_stream().cuda_stream)
+        for fn in FNS:
+            M.misa_mlp_trainer_set(t, fn, rand_net(610 + fn, fn))
+        if together:
+            losses = M.misa_mlp_fit_many(t, FNS, *[[data[f][k] for f in FNS] for k in range(3)], opts)
+        else:
+            losses = [M.misa_mlp_fit(t, fn, *data[fn], dict(opts, seed=opts["seed"] + fn)) for fn in FNS]
+        got[together] = ([M.misa_mlp_trainer_get(t, fn)[1] for fn in FNS], losses)
+        M.misa_mlp_trainer_destroy(t)
+    for fn in FNS:
+        assert np.array_equal(got[True][0][fn], got[False][0][fn]), fn
+    assert np.allclose(got[True][1], got[False][1], rtol=1e-12)
