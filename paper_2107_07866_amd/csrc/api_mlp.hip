@@ -584,8 +584,9 @@ int misa_mlp_force_match(misa_mlp_trainer *t, const double *r, const double *dha
     const int64_t nblk_fm = (npair + GRAD_SAMPLES - 1) / GRAD_SAMPLES;
     const int64_t sob_batch = 4096;
     const int64_t nblk_sob = sob_batch / GRAD_SAMPLES;
+    if (nblk_fm + nblk_sob > 65535) return tfail(t, MISA_EINVAL, "batch too large");
     const int64_t tail = std::max<int64_t>(1, o->iters / 100);
-    rc = ensure_scratch(t, nblk_fm + nblk_sob, std::max<int64_t>(nb, nblk_sob), tail);
+    rc = ensure_scratch(t, 2 * (nblk_fm + nblk_sob), std::max<int64_t>(nb, nblk_sob), tail);
     if (rc) return rc;
     if (npair > t->fm_cap) {
         void *old[] = {t->envs, t->fm_x, t->fm_cf, t->fm_cp, t->fm_zero, t->fm_loss};
@@ -631,10 +632,15 @@ int misa_mlp_force_match(misa_mlp_trainer *t, const double *r, const double *dha
         TCHK(t, launch_fm(t->stream, F, o->seed, (uint64_t)i, t->envs));
         if (i >= o->iters - tail)
             TCHK(t, launch_sum_into(t->stream, t->fm_loss, nb, t->loss_hist, (int)(i - (o->iters - tail))));
-        const double lr = lr_at(o, i);
+        // both networks' gradients (force-matching pairs, then the Sobolev term on the
+        // function's own samples), their sums and Adam steps: one launch
+        FitSteps FS{};
+        FS.nnet = 2;
+        FS.lr = lr_at(o, i);
         for (int f = 0; f < 2; ++f) {
             auto &N = t->net[f];
             const float *pw = f == 0 ? pf : pp;
+            float *part = t->part + (int64_t)f * (nblk_fm + nblk_sob) * MLP_NP;
             GradJob J{};
             const MlpNet m = trainer_net(N, pw);
             J.p = pw;
@@ -646,15 +652,24 @@ int misa_mlp_force_match(misa_mlp_trainer *t, const double *r, const double *dha
             J.n = npair;
             J.cval = t->fm_zero;
             J.cder = f == 0 ? t->fm_cf : t->fm_cp;
-            J.part = t->part;
+            J.part = part;
             J.loss_part = nullptr;
-            TCHK(t, launch_grad(t->stream, J, (int)nblk_fm));
-            GradJob S = fit_job(t, f, pw, sob_batch, o->seed ^ 0x5eedull, nullptr, t->part + nblk_fm * MLP_NP);
-            TCHK(t, launch_grad(t->stream, S, (int)nblk_sob));
-            TCHK(t, launch_grad_sum(t->stream, t->part, (int)(nblk_fm + nblk_sob), t->grad));
+            FitStep &S = FS.s[f];
+            S.J = J;
+            S.J2 = fit_job(t, f, pw, sob_batch, o->seed ^ 0x5eedull, nullptr, part + nblk_fm * MLP_NP);
+            S.nblk1 = (int)nblk_fm;
             N.step += 1;
-            TCHK(t, launch_adam(t->stream, N.w, N.m, N.v, t->grad, N.q, lr, N.step));
+            S.w = N.w;
+            S.m = N.m;
+            S.v = N.v;
+            S.q = N.q;
+            S.bc1 = 1.0 - std::pow(0.9, (double)N.step);
+            S.bc2 = 1.0 - std::pow(0.999, (double)N.step);
+            S.ticket = t->tickets + f;
+            S.loss_hist = nullptr;
+            S.slot = -1;
         }
+        TCHK(t, launch_fit_step(t->stream, FS, (int)(nblk_fm + nblk_sob)));
     }
     for (int f = 0; f < 2; ++f)
         TCHK(t, launch_round_weights(t->stream, t->net[f].w, t->net[f].q, t->net[f].w2b));

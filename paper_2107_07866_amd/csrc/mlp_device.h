@@ -94,11 +94,13 @@ struct GradJob {
 
 // One network's share of a fused fit iteration (k_fit_step).
 struct FitStep {
-    GradJob J;                     // the gradient job; J.part holds gridDim.x partials
+    GradJob J;                     // the gradient job of blocks 0 .. nblk1 - 1 (all of them if nblk1 = 0)
+    GradJob J2;                    // blocks nblk1 ..: a second job whose partials follow J's
+    int nblk1;
     float *w, *m, *v, *q;          // float32 master weights, Adam moments, bfloat16 copy
     double bc1, bc2;               // Adam bias corrections of this step
     int32_t *ticket;               // blocks finished in this launch (zero between launches)
-    double *loss_hist;             // the iteration's summed loss goes to loss_hist[slot] if slot >= 0
+    double *loss_hist;             // the iteration's summed loss (J.loss_part) goes to loss_hist[slot] if slot >= 0
     int slot;
 };
 

@@ -541,7 +541,10 @@ __device__ __forceinline__ void adam_one(int j, double g, float *__restrict__ w,
 // the only cross-block step; nothing waits on another block.
 __global__ __launch_bounds__(GRAD_THREADS) void k_fit_step(FitSteps F) {
     const FitStep &S = F.s[blockIdx.y];
-    grad_block(S.J, blockIdx.x);
+    if (S.nblk1 == 0 || (int)blockIdx.x < S.nblk1)
+        grad_block(S.J, blockIdx.x);
+    else
+        grad_block(S.J2, blockIdx.x - S.nblk1);  // its partials follow J's: J2.part = J.part + nblk1 MLP_NP
     __shared__ int last;
     __threadfence();  // this block's partial gradient and loss, before the count
     __syncthreads();
