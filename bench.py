@@ -311,14 +311,17 @@ COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_force_lds_c3_fp32_hbm_counte
 CSRC = os.path.join(ROOT, "paper_2107_07866_amd", "csrc")
 
 
+STEP_SOURCES = ("integrate_kernels.hip", "lattice_lds_kernels.hip", "misa_internal.h")
+
+
 def kernel_source_sha256():
-    """sha256 over every kernel source file (name and bytes, sorted by name)."""
+    """sha256 over the sources of the kernels that move the C3 FP32 step's bytes (the
+    persistent pair passes and the kick-drift; name and bytes, in this order)."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h")):
-            h.update(name.encode())
-            h.update(open(os.path.join(CSRC, name), "rb").read())
+    for name in STEP_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()
 
 
