@@ -341,7 +341,7 @@ int do_rho(misa_lattice *h) {
     return MISA_OK;
 }
 
-// Force pass (kick: with the fused second half-kick).  The hash and the affected
+// Force pass (kick: with the fused second half-kick).  The cell lists and the affected
 // list stay alive for the step statistics until finish_force.
 int do_force(misa_lattice *h, bool energy, double *energies_dev, bool kick) {
     {
@@ -521,7 +521,10 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     g.a = d->a;
     g.inv_a = 1.0 / d->a;
     const int32_t n3[3] = {g.nx, g.ny, g.nz};
-    for (int k = 0; k < 3; ++k) g.L[k] = (double)n3[k] * d->a;
+    for (int k = 0; k < 3; ++k) {
+        g.L[k] = (double)n3[k] * d->a;
+        g.inv_L[k] = 1.0 / g.L[k];
+    }
     g.rc = d->rc;
     g.rc2 = d->rc * d->rc;
     g.delta2 = d->delta * d->delta;
@@ -649,8 +652,9 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     // scratch
     Scratch &sc = h->sc;
     const int64_t rcap = h->rcap;
-    const int64_t H = next_pow2(2 * rcap);
-    sc.hmask = (int32_t)(H - 1);
+    const int64_t ncc = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+    sc.cs_nblk = (int32_t)((ncc + CS_CHUNK - 1) / CS_CHUNK);
+    const int64_t ncc_pad = (int64_t)sc.cs_nblk * CS_CHUNK;
     // lattice atoms within rc of a run-away, plus those of the float32 gather form with a
     // pair inside the cut-off band (about one atom in 10^3 at 300 K)
     sc.affected_cap = std::min<int64_t>(g.nsites, 128 * rcap + g.nsites / 16 + 64);
@@ -698,13 +702,15 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(sc.sortbuf, next_pow2(rcap));
     ALLOC(sc.skey, rcap);
     ALLOC(sc.sidx, rcap);
-    ALLOC(sc.hslot, rcap);
-    ALLOC(sc.hkey, H);
-    ALLOC(sc.hval, H);
-    ALLOC(sc.hcnt, H);
+    ALLOC(sc.cell_n, ncc_pad);
+    ALLOC(sc.cell_s, ncc_pad + 1);
+    ALLOC(sc.cs_blk, sc.cs_nblk);
     ALLOC(sc.srx, rcap);
     ALLOC(sc.sry, rcap);
     ALLOC(sc.srz, rcap);
+    ALLOC(sc.cellq, rcap);
+    ALLOC(sc.sfp, rcap);
+    ALLOC(sc.loneq, rcap);
     ALLOC(sc.mark, sc.mark_nwords);
     ALLOC(sc.mark_blk, sc.mark_nblk);
     ALLOC(sc.mark_off, sc.mark_nblk);
@@ -722,7 +728,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
         (e = hipMemcpy(h->near_h, &nh, sizeof(NearTab), hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(h->hmeta, hmeta.data(), sizeof(int32_t) * 2 * HALF_META, hipMemcpyHostToDevice)) ||
         (e = hipMemset(sc.cnt, 0, sizeof(Counters))) || (e = hipMemset(sc.scal, 0, 8 * sizeof(double))) ||
-        (e = hipMemset(sc.hkey, 0xff, sizeof(int32_t) * (size_t)H)) ||
+        (e = hipMemset(sc.cell_n, 0, sizeof(int32_t) * (size_t)ncc_pad)) ||
         (e = hipMemset(sc.mark, 0, sizeof(uint32_t) * (size_t)sc.mark_nwords)) ||
         (e = hipDeviceSynchronize())) {
         std::string m = std::string("device initialisation failed: ") + hipGetErrorString(e);
@@ -752,8 +758,8 @@ int misa_destroy_lattice(misa_lattice *h) {
                     h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t64.force6, h->t32.force6, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
-                    h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.hslot, h->sc.hkey, h->sc.hval, h->sc.hcnt,
-                    h->sc.srx, h->sc.sry, h->sc.srz, h->sc.mark,
+                    h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.cell_n, h->sc.cell_s, h->sc.cs_blk,
+                    h->sc.srx, h->sc.sry, h->sc.srz, h->sc.cellq, h->sc.loneq, h->sc.sfp, h->sc.mark,
                     h->sc.mark_blk, h->sc.mark_off, h->sc.affected, h->sc.aff_v2, h->sc.aff_e, h->sc.part_kick, h->staging,
                     h->mlp.p[0], h->mlp.p[1], h->mlp.p[2], h->mlp.w2b[0], h->mlp.w2b[1], h->mlp.w2b[2],
                     h->pairbuf};
@@ -964,7 +970,7 @@ int place_atoms(misa_lattice *h, const double *xd, const double *vd, int64_t n, 
     if (e == hipSuccess) e = hipMemsetAsync(h->sc.scal, 0, 8 * sizeof(double), h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->sc.mark, 0, sizeof(uint32_t) * (size_t)h->sc.mark_nwords, h->stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(h->sc.hkey, 0xff, sizeof(int32_t) * (size_t)(h->sc.hmask + 1), h->stream);
+        e = hipMemsetAsync(h->sc.cell_n, 0, sizeof(int32_t) * (size_t)h->sc.cs_nblk * CS_CHUNK, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return done(fail(h, MISA_EHIP, std::string("placement: ") + hipGetErrorString(e)));
     h->n_atoms = n;
@@ -1137,9 +1143,9 @@ int misa_load_checkpoint(misa_lattice *h, const void *host_in, int64_t bytes) {
     HIPCHK(h, hipMemcpy(h->state_ptr, (const char *)host_in + sizeof(CkptHeader), (size_t)sb, hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->sc.cnt, &hd.cnt, sizeof(Counters), hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->sc.scal, hd.scal, sizeof(hd.scal), hipMemcpyHostToDevice));
-    // run-away hash and near-run-away marks empty, as after any finished pass
+    // cell grid and near-run-away marks empty, as after any finished pass
     HIPCHK(h, hipMemset(h->sc.mark, 0, sizeof(uint32_t) * (size_t)h->sc.mark_nwords));
-    HIPCHK(h, hipMemset(h->sc.hkey, 0xff, sizeof(int32_t) * (size_t)(h->sc.hmask + 1)));
+    HIPCHK(h, hipMemset(h->sc.cell_n, 0, sizeof(int32_t) * (size_t)h->sc.cs_nblk * CS_CHUNK));
     if (h->parity != hd.parity) swap_uv(h);
     drop_graph(h);
     h->n_atoms = hd.n_atoms;
@@ -1296,7 +1302,7 @@ struct misa_batch {
     BoxRef *d_ref = nullptr;
     BoxPass *d_pass = nullptr;
     int2 *d_items = nullptr;
-    int32_t *d_off = nullptr;  // 2 (boxes + 1): offsets of the run-away work list
+    int32_t *d_off = nullptr;  // 3 (boxes + 1): offsets of the run-away work lists
     int64_t cap_boxes = 0, cap_items = 0;
     std::vector<int32_t> shape;                  // tile shape of each box (index into TILE_SHAPES)
     StencilEntry<float> *d_st = nullptr;         // [N_TILE_SHAPES][2][KMAX]: stencil per tile shape
@@ -1362,7 +1368,7 @@ int batch_tables(misa_batch *b) {
         b->cap_boxes = 0;
         BCHK(b, hipMalloc((void **)&b->d_ref, sizeof(BoxRef) * 2 * nb));
         BCHK(b, hipMalloc((void **)&b->d_pass, sizeof(BoxPass) * 2 * nb));
-        BCHK(b, hipMalloc((void **)&b->d_off, sizeof(int32_t) * 2 * (nb + 1)));
+        BCHK(b, hipMalloc((void **)&b->d_off, sizeof(int32_t) * 3 * (nb + 1)));
         b->cap_boxes = nb;
     }
 
@@ -1497,7 +1503,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
     const int nb = (int)b->box.size();
     misa_lattice *h0 = b->box[0];
     int64_t max_sites = 0;
-    int max_mark = 1;
+    int max_mark = 1, max_cells = 1;
     for (int k = 0; k < nb; ++k) {
         misa_lattice *h = b->box[k];
         int rc = check_ready(h, true);
@@ -1520,6 +1526,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
             return bfail(b, rc, h->err);
         max_sites = std::max<int64_t>(max_sites, h->g.nsites);
         max_mark = std::max(max_mark, (int)h->sc.mark_nblk);
+        max_cells = std::max(max_cells, (int)h->sc.cs_nblk);
     }
     int rc = batch_tables(b);
     if (rc) return rc;
@@ -1545,7 +1552,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
             BCHK(b, launchb_rehash(st, ref, nb, gx_small));
-            BCHK(b, launchb_runaway_build(st, ref, nb, gx_small));
+            BCHK(b, launchb_runaway_build(st, ref, nb, gx_small, max_cells));
         }
         {
             GroupTimer t(h0, MISA_TIMER_RHO);
@@ -1577,7 +1584,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
         }
         {
             GroupTimer t(h0, MISA_TIMER_RUNAWAY);
-            BCHK(b, launchb_runaway_clear(st, ref, nb, gx_small));
+            BCHK(b, launchb_runaway_clear(st, ref, nb));
         }
         if (h0->timed.size() > 50000) BCHK(b, fold_timing(h0));
         h0->stream = b->stream;
@@ -1587,6 +1594,7 @@ int misa_batch_step(misa_batch *b, int64_t nsteps, double dt_max, double dx_max,
     if (b->use_graph && !h0->timing && nsteps >= 2) {
         // the key: everything the captured launches bake in
         std::vector<uint64_t> key = {(uint64_t)nitems, (uint64_t)any_shape, (uint64_t)gx_sites, (uint64_t)max_mark,
+                                     (uint64_t)max_cells,
                                      (uint64_t)(uintptr_t)b->d_ref, (uint64_t)(uintptr_t)b->d_pass,
                                      (uint64_t)(uintptr_t)b->d_items, (uint64_t)(uintptr_t)b->d_off};
         uint64_t bits;

@@ -71,14 +71,16 @@ constexpr double VACANT_U = 1.0e6;             // displacement stored in an empt
 constexpr double VACANT_TEST = 0.5e6;          // ux above this means the slot is empty
 constexpr int32_t VACANT_ID = 0x7fffffff;      // atom id stored in an empty slot
 
-// run-away / hash scratch
+// run-away scratch
 constexpr int SORT_THREADS = 1024;
 constexpr int SORT_LDS_MAX = 16384;            // single-block LDS bitonic sort up to this many keys (128 KB)
 constexpr int BATCH_MAX_BOXES = 8192;         // boxes per batch (run-away list offsets staged in LDS)
-constexpr int RUNAWAY_WAVES_PER_BLOCK = 4;     // one wave per run-away atom
 constexpr int SMALL_GRID = 1024;               // blocks of grid-stride kernels over run-away lists
 constexpr int MARK_THREADS = 256;              // lanes per block of the mark-bitmap compaction
 constexpr int MARK_WORDS = 8;                  // bitmap words per lane (two 16-byte loads)
+constexpr int CS_THREADS = 256;                // lanes per block of the coarse-cell scan
+constexpr int CS_ITEMS = 16;                   // cells per lane (four 16-byte loads)
+constexpr int CS_CHUNK = CS_THREADS * CS_ITEMS;
 
 // 1 eV/(Angstrom amu) in Angstrom/fs^2 (exact SI e, CODATA-2018 amu)
 constexpr double ACC_UNIT = (1.602176634e-19 / 1.66053906660e-27) * 1e-10;
@@ -221,7 +223,7 @@ struct Geom {
     double L[3];
     double rc, rc2, delta2;
     double pre2;            // slightly generous rc^2 for candidate searches followed by an exact test
-    // coarse cells (edge >= rc) that bucket run-away atoms in the device hash
+    // coarse cells (edge >= rc) that bucket run-away atoms (the cell grid of the run-away passes)
     int32_t nc[3];
     int32_t pad;
     double inv_cs[3];
@@ -229,6 +231,7 @@ struct Geom {
     int32_t win;
     int32_t pad2;
     double reach;           // (rc + delta) / a
+    double inv_L[3];        // 1 / L: the minimum image of a run-away pair
 };
 
 // The other copy of the displacements and velocities.  A step's kick-drift reads
@@ -262,6 +265,8 @@ struct Counters {
     uint32_t range_viol;  // densities beyond the embedding table
     int32_t steps;        // steps completed in the current misa_step call
     int32_t fail_step;    // with overflow: index in the call of the step that overflowed
+    int32_t n_cells;      // coarse cells whose run-aways are summed by cell (entries of Scratch::cellq)
+    int32_t n_lone;       // run-aways of the other occupied cells, summed one by one (Scratch::loneq)
     int32_t pad;
 };
 
@@ -277,14 +282,19 @@ struct Scratch {
     // claims / settling
     int32_t *cand;        // candidate site per (run-away or leaver) entry, -1 if none
     uint8_t *settled;
-    // sort buffers
+    // sort buffer (the leaver sort, the defect count's sort)
     uint64_t *sortbuf;
-    // device hash of run-away atoms: sorted (coarse key, index), key -> first position
-    int32_t *skey, *sidx;
-    int32_t *hkey, *hval, *hslot;
-    int32_t *hcnt;                 // run-aways in the cell of each hash slot
+    // run-away atoms by coarse cell: the dense cell grid (padded to cs_nblk * CS_CHUNK
+    // cells) and the run-aways sorted by (cell, list index)
+    int32_t *cell_n;               // run-aways per cell while the grid is built; zero between builds
+    int32_t *cell_s;               // first sorted place of each cell (cs_nblk * CS_CHUNK + 1 entries)
+    int32_t *cs_blk;               // per-block totals of the cell scan
+    int32_t cs_nblk;
+    int32_t *skey, *sidx;          // cell and list index of each sorted place
     double *srx, *sry, *srz;       // run-away positions in the sorted (cell, list index) order
-    int32_t hmask;
+    double *sfp;                   // run-away F' in that order (written by the density pass)
+    int32_t *cellq;                // sorted position of the first run-away of each crowded cell (any order)
+    int32_t *loneq;                // sorted positions of the run-aways of the other cells (any order)
     // lattice atoms near run-away atoms
     uint32_t *mark;       // 1 bit per site, padded with zero words to mark_nblk blocks
     int64_t mark_nwords;  // padded length: mark_nblk * MARK_THREADS * MARK_WORDS
@@ -443,7 +453,7 @@ struct misa_lattice {
     misa::State S{};                              // current view of the state
     misa::UV alt{};                               // the other copy of u and v (kick-drift destination)
     bool state_bound = false, state_set = false, rho_valid = false, force_valid = false;
-    bool pending_clear = false;                   // hash and marks of a rho pass await the force pass
+    bool pending_clear = false;                   // cell lists and marks of a rho pass await the force pass
     int64_t n_atoms = 0;
     int64_t steps_done = 0;
     double *staging = nullptr;                    // device staging for host copies
@@ -508,10 +518,10 @@ hipError_t launch_force_half_mlp(misa_lattice *h, bool energy);
 hipError_t launch_energy_reduce(misa_lattice *h, double *energies_dev);
 hipError_t launch_rho_mlp(misa_lattice *h);             // learned form: rho pass with the networks
 hipError_t launch_force_mlp(misa_lattice *h, bool energy);
-hipError_t launch_runaway_build(misa_lattice *h);      // keys, sort, hash insert
+hipError_t launch_runaway_build(misa_lattice *h);      // run-aways sorted into the coarse-cell grid
 hipError_t launch_runaway_rho(misa_lattice *h);        // run-away rho + affected-site fixup
 hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick);
-hipError_t launch_runaway_clear(misa_lattice *h);      // hash and marks back to empty
+hipError_t launch_runaway_clear(misa_lattice *h);      // the pass's affected list spent
 // lattice + run-aways, leavers appended; the lattice kick-drift writes the other copy of
 // u and v, which becomes current (h->S and h->alt swap); the run-away kick-drift then
 // undoes the step if its leavers overflowed
@@ -532,11 +542,11 @@ hipError_t launchb_kick_drift(hipStream_t st, const BoxRef *boxes, const BoxRef 
 hipError_t launchb_final_kick_runaway(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small, double kf);
 hipError_t launchb_dt_update(hipStream_t st, const BoxRef *boxes, int nbox, double mass, double dt_max, double dx_max);
 hipError_t launchb_rehash(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
-hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
+hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small, int gx_cells);
 // off: 2 (nbox + 1) ints of device memory (the offsets of the run-away work list)
 hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int mark_blocks, int32_t *off);
 hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, bool energy, const int32_t *off);
-hipError_t launchb_runaway_clear(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small);
+hipError_t launchb_runaway_clear(hipStream_t st, const BoxRef *boxes, int nbox);
 hipError_t launchb_energy_reduce(hipStream_t st, const BoxRef *boxes, int nbox);
 hipError_t launch_gather_field(misa_lattice *h, int field, double *out);
 hipError_t launch_gather_slots(misa_lattice *h, int64_t *out);

@@ -81,26 +81,17 @@ __device__ __forceinline__ Real emb_any(Real rho, const Q4<Real> *__restrict__ e
     return (d.z * t + d.y) * t + d.x;
 }
 
-__device__ __forceinline__ uint32_t hash_slot(int32_t key, int32_t mask) {
-    uint32_t h = (uint32_t)key * 2654435761u;
-    return (h ^ (h >> 16)) & (uint32_t)mask;
-}
-
-// Slot of key in the hash, or -1.
-__device__ __forceinline__ int32_t hash_find(int32_t key, const int32_t *__restrict__ hkey, int32_t mask) {
-    uint32_t h = hash_slot(key, mask);
-    for (int probe = 0; probe <= mask; ++probe) {
-        const int32_t k = hkey[h];
-        if (k == key) return (int32_t)h;
-        if (k == -1) return -1;
-        h = (h + 1) & (uint32_t)mask;
-    }
-    return -1;
-}
-
 __device__ __forceinline__ int coarse_of(double xw, int nc, double inv_cs) {
     int c = (int)(xw * inv_cs);
     return c >= nc ? nc - 1 : (c < 0 ? 0 : c);
+}
+
+// Coarse cell of run-away r (the key the cell grid is indexed by).
+__device__ __forceinline__ int32_t run_key(const State &S, const Geom &g, int r) {
+    const int kx = coarse_of(S.r_x[r], g.nc[0], g.inv_cs[0]);
+    const int ky = coarse_of(S.r_y[r], g.nc[1], g.inv_cs[1]);
+    const int kz = coarse_of(S.r_z[r], g.nc[2], g.inv_cs[2]);
+    return (kz * g.nc[1] + ky) * g.nc[0] + kx;
 }
 
 __device__ __forceinline__ int axis_cells(int c, int n, int out[3]) {
@@ -135,75 +126,47 @@ __device__ __forceinline__ void lat_sep(int cx, int cy, int cz, int p, const dou
     d[2] = (sp[2] - x[2]) + u[2];
 }
 
+// Nearest periodic image of a separation of two wrapped positions (|d| <= L per axis).
+// The image shift rint(d / L) is taken as rint(d * (1 / L)): the two differ only where
+// |d| is within rounding of L / 2 on some axis, and such a pair lies beyond rc (the box
+// exceeds 2 rc), so every pair within rc gets the same separation either way.
 __device__ __forceinline__ void min_image3(double d[3], const Geom &g) {
-    for (int k = 0; k < 3; ++k) d[k] -= g.L[k] * rint(d[k] / g.L[k]);
+    for (int k = 0; k < 3; ++k) d[k] -= g.L[k] * rint(d[k] * g.inv_L[k]);
 }
 
 // ---------------------------------------------------------------------------
-// single-block bitonic sort of 64-bit keys (ascending); mode 0: leavers by atom
-// id, mode 1: run-aways by (coarse cell, list index).  Mode 0 first freezes a step
-// that the run-away kick-drift has just undone after an overflow: no leavers, dt = 0
-// for the rest of the call (the step length is kept in scal[7]), and the step's index.
+// single-block bitonic sort of 64-bit keys (ascending): this step's leavers by atom
+// id.  It first freezes a step that the run-away kick-drift has just undone after an
+// overflow: no leavers, dt = 0 for the rest of the call (the step length is kept in
+// scal[7]), and the step's index.
 
-__device__ __forceinline__ void sort_body(uint64_t *__restrict__ buf, int mode,
-                                                        Counters *__restrict__ cnt, int64_t rcap,
-                                                        const int32_t *__restrict__ l_id,
-                                                        const double *__restrict__ rx, const double *__restrict__ ry,
-                                                        const double *__restrict__ rz, Geom g,
-                                                        double *__restrict__ scal) {
+__device__ __forceinline__ void sort_body(uint64_t *__restrict__ buf, Counters *__restrict__ cnt, int64_t rcap,
+                                          const int32_t *__restrict__ l_id, double *__restrict__ scal) {
     __shared__ uint64_t sh[SORT_LDS_MAX];
-    int n;
-    if (mode == 0) {
-        if (threadIdx.x == 0 && cnt->overflow == 1) {
-            scal[7] = scal[0];
-            scal[0] = 0.0;
-            cnt->n_leave = 0;
-            cnt->fail_step = cnt->steps;
-            cnt->overflow = 2;
-        }
-        __syncthreads();
-        // leavers beyond the run-away capacity were not recorded (they kept their slots)
-        const int nl = cnt->n_leave;
-        const int room = (int)(rcap - cnt->n_run);
-        n = nl < room ? nl : room;
-    } else {
-        n = cnt->n_run;
+    if (threadIdx.x == 0 && cnt->overflow == 1) {
+        scal[7] = scal[0];
+        scal[0] = 0.0;
+        cnt->n_leave = 0;
+        cnt->fail_step = cnt->steps;
+        cnt->overflow = 2;
     }
     __syncthreads();
-    if (mode == 0 && threadIdx.x == 0) cnt->n_leave = n;
+    // leavers beyond the run-away capacity were not recorded (they kept their slots)
+    const int nl = cnt->n_leave;
+    const int room = (int)(rcap - cnt->n_run);
+    const int n = nl < room ? nl : room;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt->n_leave = n;
     if (n <= 1) {
-        if (n == 1 && threadIdx.x == 0) {
-            if (mode == 0) {
-                buf[0] = ((uint64_t)(uint32_t)l_id[0] << 32) | 0u;
-            } else {
-                int kx = coarse_of(rx[0], g.nc[0], g.inv_cs[0]);
-                int ky = coarse_of(ry[0], g.nc[1], g.inv_cs[1]);
-                int kz = coarse_of(rz[0], g.nc[2], g.inv_cs[2]);
-                int32_t key = (kz * g.nc[1] + ky) * g.nc[0] + kx;
-                buf[0] = ((uint64_t)(uint32_t)key << 32) | 0u;
-            }
-        }
+        if (n == 1 && threadIdx.x == 0) buf[0] = ((uint64_t)(uint32_t)l_id[0] << 32) | 0u;
         return;
     }
     int P = 1;
     while (P < n) P <<= 1;
     const bool in_lds = P <= SORT_LDS_MAX;
     uint64_t *A = in_lds ? sh : buf;
-    for (int i = threadIdx.x; i < P; i += SORT_THREADS) {
-        uint64_t v = ~0ull;
-        if (i < n) {
-            if (mode == 0) {
-                v = ((uint64_t)(uint32_t)l_id[i] << 32) | (uint32_t)i;
-            } else {
-                int kx = coarse_of(rx[i], g.nc[0], g.inv_cs[0]);
-                int ky = coarse_of(ry[i], g.nc[1], g.inv_cs[1]);
-                int kz = coarse_of(rz[i], g.nc[2], g.inv_cs[2]);
-                int32_t key = (kz * g.nc[1] + ky) * g.nc[0] + kx;
-                v = ((uint64_t)(uint32_t)key << 32) | (uint32_t)i;
-            }
-        }
-        A[i] = v;
-    }
+    for (int i = threadIdx.x; i < P; i += SORT_THREADS)
+        A[i] = i < n ? ((uint64_t)(uint32_t)l_id[i] << 32) | (uint32_t)i : ~0ull;
     __syncthreads();
     for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -225,18 +188,15 @@ __device__ __forceinline__ void sort_body(uint64_t *__restrict__ buf, int mode,
         for (int i = threadIdx.x; i < n; i += SORT_THREADS) buf[i] = sh[i];
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_sort(uint64_t *__restrict__ buf, int mode,
-                                                        Counters *__restrict__ cnt, int64_t rcap,
-                                                        const int32_t *__restrict__ l_id,
-                                                        const double *__restrict__ rx, const double *__restrict__ ry,
-                                                        const double *__restrict__ rz, Geom g,
+__global__ __launch_bounds__(SORT_THREADS) void k_sort(uint64_t *__restrict__ buf, Counters *__restrict__ cnt,
+                                                        int64_t rcap, const int32_t *__restrict__ l_id,
                                                         double *__restrict__ scal) {
-    sort_body(buf, mode, cnt, rcap, l_id, rx, ry, rz, g, scal);
+    sort_body(buf, cnt, rcap, l_id, scal);
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void kb_sort(const BoxRef *__restrict__ boxes, int mode) {
+__global__ __launch_bounds__(SORT_THREADS) void kb_sort(const BoxRef *__restrict__ boxes) {
     const BoxRef &B = boxes[blockIdx.y];
-    sort_body(B.sc.sortbuf, mode, B.sc.cnt, B.rcap, B.sc.l_id, B.S.r_x, B.S.r_y, B.S.r_z, B.g, B.sc.scal);
+    sort_body(B.sc.sortbuf, B.sc.cnt, B.rcap, B.sc.l_id, B.sc.scal);
 }
 
 
@@ -413,65 +373,227 @@ __global__ __launch_bounds__(1024) void kb_compact(const BoxRef *__restrict__ bo
 
 
 // ---------------------------------------------------------------------------
-// device hash of run-away atoms
+// run-away atoms by coarse cell (edge >= rc): a counting sort into a dense grid
+//
+// count: run-aways per cell; scan: cell_s[c] = run-aways in cells before c (three
+// kernels: block totals, their scan, the block scans); scatter: each run-away takes a
+// place in its cell's stretch (counting the cell back down to zero, which leaves the
+// grid ready for the next build); order: each stretch is put in ascending list index
+// (so every later pass sees the same order whatever the scatter's timing), the sorted
+// copies are written, and the cell (or its atoms) is listed for the density and force
+// passes.  cell_s[c + 1] - cell_s[c] is then the cell's run-away count.
 
-// The sorted run-aways: keys, list indices and positions in sorted order; the first
-// entry of each cell enters the cell's key with its start and length.
-__device__ __forceinline__ void hash_insert_body(const State &S, Scratch sc) {
+// Cells with at least this many run-aways have their sums taken by cell (one block
+// stages the cell's neighbourhood); the atoms of sparser cells are taken one by one.
+constexpr int RC_MIN_HOME = 5;
+
+__device__ __forceinline__ void cell_count_body(const State &S, Scratch sc, const Geom &g) {
+    const int n = sc.cnt->n_run;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc.cnt->n_cells = sc.cnt->n_lone = 0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        atomicAdd(&sc.cell_n[run_key(S, g, r)], 1);
+}
+
+__global__ void k_cell_count(State S, Scratch sc, Geom g) {
+    cell_count_body(S, sc, g);
+}
+
+__global__ void kb_cell_count(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    cell_count_body(B.S, B.sc, B.g);
+}
+
+// Exclusive scan of one value per lane over a CS_THREADS block; total: the block's sum.
+__device__ __forceinline__ int cs_block_scan(int v, int *sh_waves, int &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) sh_waves[w] = incl;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+    for (int k = 0; k < CS_THREADS / 64; ++k) {
+        if (k < w) off += sh_waves[k];
+        total += sh_waves[k];
+    }
+    return off + incl - v;
+}
+
+// This lane's CS_ITEMS counts (the grid is padded with zero cells to whole blocks).
+__device__ __forceinline__ int cs_load(const Scratch &sc, int (&m)[CS_ITEMS]) {
+    const int64_t c0 = ((int64_t)blockIdx.x * CS_THREADS + threadIdx.x) * CS_ITEMS;
+    const int4 *p = reinterpret_cast<const int4 *>(sc.cell_n + c0);
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < CS_ITEMS / 4; ++k) {
+        const int4 v = p[k];
+        m[4 * k] = v.x, m[4 * k + 1] = v.y, m[4 * k + 2] = v.z, m[4 * k + 3] = v.w;
+        c += v.x + v.y + v.z + v.w;
+    }
+    return c;
+}
+
+__device__ __forceinline__ void cell_sum_body(Scratch sc) {
+    __shared__ int shw[CS_THREADS / 64];
+    if ((int)blockIdx.x >= sc.cs_nblk) return;  // a batched grid sized for a larger box
+    int m[CS_ITEMS], total;
+    cs_block_scan(cs_load(sc, m), shw, total);
+    if (threadIdx.x == 0) sc.cs_blk[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(CS_THREADS) void k_cell_sum(Scratch sc) {
+    cell_sum_body(sc);
+}
+
+__global__ __launch_bounds__(CS_THREADS) void kb_cell_sum(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    cell_sum_body(B.sc);
+}
+
+// Exclusive scan of the block totals in place; cell_s past the last cell gets the total.
+__device__ __forceinline__ void cell_top_body(Scratch sc) {
+    __shared__ int base_sh;
+    __shared__ int wsum[1024 / 64];
+    if (threadIdx.x == 0) base_sh = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nblk = sc.cs_nblk;
+    for (int c0 = 0; c0 < nblk; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nblk ? sc.cs_blk[i] : 0;
+        int incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int off = base_sh, tot = 0;
+        for (int k = 0; k < 1024 / 64; ++k) {
+            if (k < w) off += wsum[k];
+            tot += wsum[k];
+        }
+        if (i < nblk) sc.cs_blk[i] = off + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0) base_sh += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc.cell_s[(int64_t)nblk * CS_CHUNK] = base_sh;
+}
+
+__global__ __launch_bounds__(1024) void k_cell_top(Scratch sc) {
+    cell_top_body(sc);
+}
+
+__global__ __launch_bounds__(1024) void kb_cell_top(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    cell_top_body(B.sc);
+}
+
+__device__ __forceinline__ void cell_down_body(Scratch sc) {
+    __shared__ int shw[CS_THREADS / 64];
+    if ((int)blockIdx.x >= sc.cs_nblk) return;
+    int m[CS_ITEMS], total;
+    int pos = sc.cs_blk[blockIdx.x] + cs_block_scan(cs_load(sc, m), shw, total);
+    const int64_t c0 = ((int64_t)blockIdx.x * CS_THREADS + threadIdx.x) * CS_ITEMS;
+    int4 *out = reinterpret_cast<int4 *>(sc.cell_s + c0);
+#pragma unroll
+    for (int k = 0; k < CS_ITEMS / 4; ++k) {
+        int4 v;
+        v.x = pos;
+        pos += m[4 * k];
+        v.y = pos;
+        pos += m[4 * k + 1];
+        v.z = pos;
+        pos += m[4 * k + 2];
+        v.w = pos;
+        pos += m[4 * k + 3];
+        out[k] = v;
+    }
+}
+
+__global__ __launch_bounds__(CS_THREADS) void k_cell_down(Scratch sc) {
+    cell_down_body(sc);
+}
+
+__global__ __launch_bounds__(CS_THREADS) void kb_cell_down(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    cell_down_body(B.sc);
+}
+
+__device__ __forceinline__ void cell_scatter_body(const State &S, Scratch sc, const Geom &g) {
+    const int n = sc.cnt->n_run;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int32_t key = run_key(S, g, r);
+        const int q = sc.cell_s[key] + atomicSub(&sc.cell_n[key], 1) - 1;
+        sc.skey[q] = key;
+        sc.sidx[q] = r;
+    }
+}
+
+__global__ void k_cell_scatter(State S, Scratch sc, Geom g) {
+    cell_scatter_body(S, sc, g);
+}
+
+__global__ void kb_cell_scatter(const BoxRef *__restrict__ boxes) {
+    const BoxRef &B = boxes[blockIdx.y];
+    cell_scatter_body(B.S, B.sc, B.g);
+}
+
+__device__ __forceinline__ void cell_order_body(const State &S, Scratch sc) {
     const int n = sc.cnt->n_run;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        const uint64_t v = sc.sortbuf[q];
-        const int32_t key = (int32_t)(v >> 32);
-        const int32_t o = (int32_t)(v & 0xffffffffu);
-        sc.skey[q] = key;
-        sc.sidx[q] = o;
-        sc.srx[q] = S.r_x[o];
-        sc.sry[q] = S.r_y[o];
-        sc.srz[q] = S.r_z[o];
-        const bool start = q == 0 || (int32_t)(sc.sortbuf[q - 1] >> 32) != key;
-        if (start) {
-            int end = q + 1;  // a cell holds a few dozen atoms at most (its edge is about rc)
-            while (end < n && (int32_t)(sc.sortbuf[end] >> 32) == key) ++end;
-            uint32_t h = hash_slot(key, sc.hmask);
-            for (int probe = 0; probe <= sc.hmask; ++probe) {
-                if (atomicCAS(&sc.hkey[h], -1, key) == -1) {
-                    sc.hval[h] = q;
-                    sc.hcnt[h] = end - q;
-                    sc.hslot[q] = (int32_t)h;
-                    break;
-                }
-                h = (h + 1) & (uint32_t)sc.hmask;
+        const int32_t key = sc.skey[q];
+        if (sc.cell_s[key] != q) continue;  // one lane per cell: the one at its first place
+        const int end = sc.cell_s[key + 1];
+        for (int i = q + 1; i < end; ++i) {  // insertion sort; a cell holds a few dozen at most
+            const int32_t v = sc.sidx[i];
+            int j = i - 1;
+            while (j >= q && sc.sidx[j] > v) {
+                sc.sidx[j + 1] = sc.sidx[j];
+                --j;
             }
+            sc.sidx[j + 1] = v;
+        }
+        for (int i = q; i < end; ++i) {
+            const int32_t o = sc.sidx[i];
+            sc.srx[i] = S.r_x[o];
+            sc.sry[i] = S.r_y[o];
+            sc.srz[i] = S.r_z[o];
+        }
+        if (end - q >= RC_MIN_HOME) {
+            sc.cellq[atomicAdd(&sc.cnt->n_cells, 1)] = q;
+        } else {
+            const int b = atomicAdd(&sc.cnt->n_lone, end - q);
+            for (int i = q; i < end; ++i) sc.loneq[b + i - q] = i;
         }
     }
 }
 
-__global__ void k_hash_insert(State S, Scratch sc) {
-    hash_insert_body(S, sc);
+__global__ void k_cell_order(State S, Scratch sc) {
+    cell_order_body(S, sc);
 }
 
-__global__ void kb_hash_insert(const BoxRef *__restrict__ boxes) {
+__global__ void kb_cell_order(const BoxRef *__restrict__ boxes) {
     const BoxRef &B = boxes[blockIdx.y];
-    hash_insert_body(B.S, B.sc);
+    cell_order_body(B.S, B.sc);
 }
 
-
-__device__ __forceinline__ void hash_clear_body(Scratch sc) {
-    const int n = sc.cnt->n_run;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        const bool start = q == 0 || sc.skey[q - 1] != sc.skey[q];
-        if (start) sc.hkey[sc.hslot[q]] = -1;
-    }
+// End of a pass: the affected list is spent (the step statistics have read it).
+__device__ __forceinline__ void runaway_clear_body(Scratch sc) {
     if (blockIdx.x == 0 && threadIdx.x == 0) sc.cnt->n_affected = 0;
 }
 
-__global__ void k_hash_clear(Scratch sc) {
-    hash_clear_body(sc);
+__global__ void k_runaway_clear(Scratch sc) {
+    runaway_clear_body(sc);
 }
 
-__global__ void kb_hash_clear(const BoxRef *__restrict__ boxes) {
+__global__ void kb_runaway_clear(const BoxRef *__restrict__ boxes) {
     const BoxRef &B = boxes[blockIdx.y];
-    hash_clear_body(B.sc);
+    runaway_clear_body(B.sc);
 }
 
 
@@ -487,9 +609,7 @@ __device__ __forceinline__ void for_runaways_in_cell(const double x[3], int cell
     if (ay >= axis_cells(coarse_of(x[1], g.nc[1], g.inv_cs[1]), g.nc[1], cy)) return;
     if (az >= axis_cells(coarse_of(x[2], g.nc[2], g.inv_cs[2]), g.nc[2], cz)) return;
     const int32_t key = (cz[az] * g.nc[1] + cy[ay]) * g.nc[0] + cx[ax];
-    const int32_t slot = hash_find(key, sc.hkey, sc.hmask);
-    if (slot < 0) return;
-    const int start = sc.hval[slot], end = start + sc.hcnt[slot];
+    const int start = sc.cell_s[key], end = sc.cell_s[key + 1];
 #pragma unroll 2
     for (int q = start + first; q < end; q += stride) {
         const double xo[3] = {sc.srx[q], sc.sry[q], sc.srz[q]};
@@ -547,10 +667,12 @@ __device__ __forceinline__ bool affected_pair(const double xo[3], const int cj[3
 // ---------------------------------------------------------------------------
 // densities
 
-// One wave per run-away atom: rho from lattice sites in its window and from other
-// run-aways; marks every lattice atom it pairs with (they need the reaction term).
+// One wave per run-away atom (the form for home cells too crowded to stage): rho from
+// lattice sites in its window and from other run-aways; marks every lattice atom it
+// pairs with (they need the reaction term).
+// q: the atom's place in the sorted order.
 __device__ __forceinline__ void runaway_rho_one(const State &S, const Scratch &sc, const Geom &g,
-                                                const Tables<double> &T, int r, int lane) {
+                                                const Tables<double> &T, int r, int q, int lane) {
     const int win = g.win, win3 = win * win * win;
     {
         const double x[3] = {S.r_x[r], S.r_y[r], S.r_z[r]};
@@ -584,25 +706,12 @@ __device__ __forceinline__ void runaway_rho_one(const State &S, const Scratch &s
             const double d = emb_any<double>(acc, T.emb, T.em, Fv, beyond);
             S.r_rho[r] = acc;
             S.r_fp[r] = d;
+            sc.sfp[q] = d;
             S.r_e[2 * r] = Fv;
             if (beyond) atomicAdd(&sc.cnt->range_viol, 1u);
         }
     }
 }
-
-__device__ __forceinline__ void runaway_rho_body(State S, Scratch sc, Geom g, Tables<double> T) {
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
-    const int n = sc.cnt->n_run;
-    for (int r = wave; r < n; r += nwaves) runaway_rho_one(S, sc, g, T, r, lane);
-}
-
-__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_rho(State S, Scratch sc, Geom g,
-                                                                              Tables<double> T) {
-    runaway_rho_body(S, sc, g, T);
-}
-
 
 // The float32 band pairs of lattice atom s, one team lane per stencil entry (entries
 // cell, cell + AFF_TEAM, ...): for each pair whose float32 r^2 fell within RC_BAND_Q of
@@ -777,19 +886,462 @@ __device__ __forceinline__ void runaway_force_one(const State &S, const Scratch 
     }
 }
 
-__device__ __forceinline__ void runaway_force_body(State S, Scratch sc, Geom g, Tables<double> T, int real_is_f32,
-                                                   int energy) {
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
-    const int n = sc.cnt->n_run;
-    for (int r = wave; r < n; r += nwaves) runaway_force_one(S, sc, g, T, real_is_f32, energy, r, lane);
+// ---------------------------------------------------------------------------
+// Run-away sums by coarse cell.
+//
+// A block takes one coarse cell that holds run-aways (the home cell) and stages in LDS
+// what its atoms pair with: the run-aways of the (up to) 27 cells around it, from the
+// sorted copies, and the slotted lattice atoms of one lattice window that contains every
+// home atom's own search window.  RC_SPLIT lanes serve one home atom: lane k takes the
+// staged entries k, k + RC_SPLIT, ... in order, lattice atoms first, then run-aways, and
+// the lanes' sums meet in a fixed butterfly.  Each pair's separation is formed as in the
+// per-atom form (lat_sep from the atom's own window for a lattice partner, min_image3 of
+// the difference for a run-away partner), so the lattice side's reaction terms still see
+// the same pair.  A cell whose neighbourhood exceeds the staging capacities is served by
+// the per-atom form, one wave per home atom.  Which form serves an atom depends only on
+// the state, so results do not depend on how cells are dealt out.
+constexpr int RC_THREADS = 256;
+constexpr int RC_SPLIT = 16;
+constexpr int RC_HOME = RC_THREADS / RC_SPLIT;
+constexpr int RC_CAND = 640;  // run-away partners staged per home cell
+constexpr int RC_LAT = 608;   // slotted lattice atoms staged per home cell (the density pass fits 4 blocks per CU)
+
+template <bool FORCE>
+struct CellStage {
+    double cx[RC_CAND], cy[RC_CAND], cz[RC_CAND];
+    double cfp[FORCE ? RC_CAND : 1];  // F' of the run-away partners
+    int32_t co[RC_CAND];              // their list indices
+    double lx[RC_LAT], ly[RC_LAT], lz[RC_LAT];  // displacements of the lattice partners
+    double lfp[FORCE ? RC_LAT : 1];
+    int64_t ls[RC_LAT];               // their storage indices
+    uint32_t lw[RC_LAT];              // window offsets x | y << 8 | z << 16, parity << 24
+    int32_t cstart[27], cpre[28];
+    int32_t wcnt[RC_THREADS / 64];
+};
+
+// The lattice window of home cell c along one axis: cells [lo, lo + w) (w <= n) contain
+// the search window [window_lo(q), window_lo(q) + win) of every q = x / a with x in the
+// cell (the coarse cell spans n / nc lattice cells; the margin absorbs rounding of x / a).
+__device__ __forceinline__ void cell_window(int c, int n, int nc, const Geom &g, int &lo, int &w) {
+    const double span = (double)n / (double)nc;
+    lo = window_lo((double)c * span - 1e-3, g.reach);
+    const int hi = window_lo((double)(c + 1) * span + 1e-3, g.reach) + g.win;
+    w = hi - lo < n ? hi - lo : n;
 }
 
-__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void k_runaway_force(State S, Scratch sc, Geom g,
-                                                                                Tables<double> T, int real_is_f32,
-                                                                                int energy) {
-    runaway_force_body(S, sc, g, T, real_is_f32, energy);
+__device__ __forceinline__ double split_sum(double v) {
+    // fixed butterfly over the RC_SPLIT lanes of one home atom
+    for (int o = RC_SPLIT / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, RC_SPLIT);
+    return v;
+}
+
+// Stages the home cell whose sorted run-aways start at hs.  Returns false (nothing
+// usable staged) when its partners exceed the capacities; every thread of the block
+// calls it and gets the same answer.  The loads are grouped so that a cell costs a few
+// dependent memory round trips: the window's occupancy words and the neighbour cells'
+// stretches together, then every partner's data together.
+constexpr int RC_WIN_BATCHES = 4;  // window sites examined per thread per round
+
+template <bool FORCE>
+__device__ bool stage_cell(const State &S, const Scratch &sc, const Geom &g, int real_is_f32, int hs,
+                           CellStage<FORCE> &st, int &n_cand, int &n_lat, int wlo[3], int ww[3]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int32_t key = sc.skey[hs];
+    const int hc[3] = {key % g.nc[0], (key / g.nc[0]) % g.nc[1], key / (g.nc[0] * g.nc[1])};
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    for (int k = 0; k < 3; ++k) cell_window(hc[k], n3[k], g.nc[k], g, wlo[k], ww[k]);
+    const bool wide = ww[0] > 255 || ww[1] > 255 || ww[2] > 255;
+    const int w01 = ww[0] * ww[1], w012 = w01 * ww[2];
+    const int nwin = wide ? 0 : 2 * w012;
+
+    // round 1 of the window's occupancy words, issued before the cell look-ups
+    auto site_of = [&](int w, uint32_t &pack) -> int64_t {
+        const int p = w >= w012 ? 1 : 0;
+        const int rem = w - p * w012;
+        const int ox = rem % ww[0], oy = (rem / ww[0]) % ww[1], oz = rem / w01;
+        pack = (uint32_t)ox | ((uint32_t)oy << 8) | ((uint32_t)oz << 16) | ((uint32_t)p << 24);
+        return (int64_t)p * g.ncell +
+               ((int64_t)wrap_index(wlo[2] + oz, g.nz) * g.ny + wrap_index(wlo[1] + oy, g.ny)) * g.nx +
+               wrap_index(wlo[0] + ox, g.nx);
+    };
+    double ux[RC_WIN_BATCHES];
+    int64_t ws[RC_WIN_BATCHES];
+    uint32_t wp[RC_WIN_BATCHES];
+    auto load_round = [&](int g0) {
+#pragma unroll
+        for (int b = 0; b < RC_WIN_BATCHES; ++b) {
+            const int w = g0 + b * RC_THREADS + tid;
+            ux[b] = 2.0 * VACANT_TEST;
+            ws[b] = 0;
+            wp[b] = 0;
+            if (w < nwin) {
+                ws[b] = site_of(w, wp[b]);
+                ux[b] = S.ux[ws[b]];
+            }
+        }
+    };
+    load_round(0);
+
+    if (wave == 0) {
+        int cnt = 0;
+        if (lane < 27) {
+            int cx[3], cy[3], cz[3];
+            const int ax = lane % 3, ay = (lane / 3) % 3, az = lane / 9;
+            if (ax < axis_cells(hc[0], g.nc[0], cx) && ay < axis_cells(hc[1], g.nc[1], cy) &&
+                az < axis_cells(hc[2], g.nc[2], cz)) {
+                const int32_t nk = (cz[az] * g.nc[1] + cy[ay]) * g.nc[0] + cx[ax];
+                const int c0 = sc.cell_s[nk];
+                st.cstart[lane] = c0;
+                cnt = sc.cell_s[nk + 1] - c0;
+            }
+        }
+        int incl = cnt;
+        for (int o = 1; o < 32; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane < 27) st.cpre[lane + 1] = incl;
+        if (lane == 0) st.cpre[0] = 0;
+    }
+
+    // lattice window, compacted in window order (sublattice, z, y, x)
+    int base = 0;
+    for (int g0 = 0; g0 < nwin; g0 += RC_WIN_BATCHES * RC_THREADS) {
+        if (g0 > 0) load_round(g0);
+#pragma unroll
+        for (int b = 0; b < RC_WIN_BATCHES; ++b) {
+            const bool occ = !(ux[b] > VACANT_TEST);
+            const uint64_t m = __ballot(occ);
+            if (lane == 0) st.wcnt[wave] = __popcll(m);
+            __syncthreads();
+            int before = base, total = 0;
+            for (int k = 0; k < RC_THREADS / 64; ++k) {
+                if (k < wave) before += st.wcnt[k];
+                total += st.wcnt[k];
+            }
+            const int idx = before + __popcll(m & ((1ull << lane) - 1ull));
+            if (occ && idx < RC_LAT) {
+                st.lx[idx] = ux[b];
+                st.ls[idx] = ws[b];
+                st.lw[idx] = wp[b];
+            }
+            base += total;
+            __syncthreads();  // wcnt is rewritten by the next batch
+        }
+        if (base > RC_LAT) break;
+    }
+    n_lat = base;
+    n_cand = st.cpre[27];  // visible: the batches above passed barriers (at least one: nwin > 0)
+    if (wide || n_cand > RC_CAND || n_lat > RC_LAT) return false;
+
+    // every partner's data in one round: the lattice atoms' other components (and F'),
+    // the run-aways in cell order, each cell's stretch in sorted order
+    for (int e = tid; e < n_lat; e += RC_THREADS) {
+        const int64_t si = st.ls[e];
+        st.ly[e] = S.uy[si];
+        st.lz[e] = S.uz[si];
+        if (FORCE) st.lfp[e] = real_is_f32 ? (double)((const float *)S.fp)[si] : ((const double *)S.fp)[si];
+    }
+    for (int e = tid; e < n_cand; e += RC_THREADS) {
+        int k = 0;
+        while (st.cpre[k + 1] <= e) ++k;
+        const int q = st.cstart[k] + (e - st.cpre[k]);
+        st.cx[e] = sc.srx[q];
+        st.cy[e] = sc.sry[q];
+        st.cz[e] = sc.srz[q];
+        st.co[e] = sc.sidx[q];
+        if (FORCE) st.cfp[e] = sc.sfp[q];
+    }
+    __syncthreads();
+    return true;
+}
+
+// Lattice partner e of a home atom with search window lo[]: its cell in that window
+// (false if outside), as the per-atom form enumerates it.
+__device__ __forceinline__ bool staged_site(uint32_t pack, const int wlo[3], const int ww[3], const int lo[3],
+                                            const Geom &g, int cc[3], int &p) {
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    for (int k = 0; k < 3; ++k) {
+        int t = wlo[k] + (int)((pack >> (8 * k)) & 0xffu) - lo[k];  // in (-ww, ww), ww <= n
+        t = t < 0 ? t + n3[k] : t;
+        if (t >= g.win) return false;
+        cc[k] = lo[k] + t;
+    }
+    p = (int)(pack >> 24);
+    return true;
+}
+
+// Separation of staged lattice partner e from a home atom at x with search window lo
+// (false if the partner lies outside that window), and of staged run-away partner e.
+template <bool FORCE>
+__device__ __forceinline__ bool lat_pair(const CellStage<FORCE> &st, int e, const int wlo[3], const int ww[3],
+                                         const int lo[3], const double x[3], const Geom &g, double d[3],
+                                         double &r2) {
+    int cc[3], p;
+    if (!staged_site(st.lw[e], wlo, ww, lo, g, cc, p)) return false;
+    const double u[3] = {st.lx[e], st.ly[e], st.lz[e]};
+    lat_sep(cc[0], cc[1], cc[2], p, u, x, g.a, d);
+    r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    return true;
+}
+
+template <bool FORCE>
+__device__ __forceinline__ void run_pair(const CellStage<FORCE> &st, int e, const double x[3], const Geom &g,
+                                         double d[3], double &r2) {
+    d[0] = st.cx[e] - x[0];
+    d[1] = st.cy[e] - x[1];
+    d[2] = st.cz[e] - x[2];
+    min_image3(d, g);
+    r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+}
+
+// A lane's staged entries are e = k + RC_SPLIT i.  The pairs are found first (bit i of
+// a mask per kind, at most 64 entries per lane: RC_LAT and RC_CAND are below 64 RC_SPLIT),
+// then taken up in groups whose table records are loaded together, lowest i first, so
+// the sums keep the entry order.
+static_assert(RC_LAT <= 64 * RC_SPLIT && RC_CAND <= 64 * RC_SPLIT, "one 64-bit mask per lane and kind");
+
+// The next (up to) G entries of mask m: e[t] = k + RC_SPLIT * bit; slots past the last
+// repeat the first entry and are marked invalid.
+template <int G>
+__device__ __forceinline__ void take_group(uint64_t &m, int k, int e[G], bool v[G]) {
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        v[t] = m != 0;
+        e[t] = v[t] ? k + RC_SPLIT * __builtin_ctzll(m) : e[0];
+        m &= m - 1;
+    }
+}
+
+constexpr int RC_RHO_GROUP = 4;    // f records in flight per lane
+constexpr int RC_FORCE_GROUP = 2;  // f', phi' and phi records in flight per lane
+
+__device__ __forceinline__ void runaway_rho_cell(const State &S, const Scratch &sc, const Geom &g,
+                                                 const Tables<double> &T, int hs, CellStage<false> &st) {
+    int n_cand = 0, n_lat = 0, wlo[3], ww[3];
+    const int nh = sc.cell_s[sc.skey[hs] + 1] - hs;
+    if (!stage_cell<false>(S, sc, g, 0, hs, st, n_cand, n_lat, wlo, ww)) {
+        const int lane = threadIdx.x & 63;
+        for (int j = threadIdx.x >> 6; j < nh; j += RC_THREADS / 64)
+            runaway_rho_one(S, sc, g, T, sc.sidx[hs + j], hs + j, lane);
+        return;
+    }
+    const int k = threadIdx.x % RC_SPLIT;
+    for (int hb = 0; hb < nh; hb += RC_HOME) {
+        const int j = hb + (int)threadIdx.x / RC_SPLIT;
+        const bool act = j < nh;
+        double acc = 0.0;
+        int o = -1;
+        if (act) {
+            const int q = hs + j;
+            o = sc.sidx[q];
+            const double x[3] = {sc.srx[q], sc.sry[q], sc.srz[q]};
+            const int lo[3] = {window_lo(x[0] * g.inv_a, g.reach), window_lo(x[1] * g.inv_a, g.reach),
+                               window_lo(x[2] * g.inv_a, g.reach)};
+            uint64_t ml = 0, mc = 0;
+            int i = 0;
+            for (int e = k; e < n_lat; e += RC_SPLIT, ++i) {
+                double d[3], r2;
+                if (lat_pair(st, e, wlo, ww, lo, x, g, d, r2) && r2 < g.rc2) ml |= 1ull << i;
+            }
+            i = 0;
+            for (int e = k; e < n_cand; e += RC_SPLIT, ++i) {
+                if (st.co[e] == o) continue;
+                double d[3], r2;
+                run_pair(st, e, x, g, d, r2);
+                if (r2 < g.rc2) mc |= 1ull << i;
+            }
+            while (ml) {
+                int e[RC_RHO_GROUP];
+                bool v[RC_RHO_GROUP];
+                take_group<RC_RHO_GROUP>(ml, k, e, v);
+                double f[RC_RHO_GROUP];
+#pragma unroll
+                for (int t = 0; t < RC_RHO_GROUP; ++t) {
+                    double d[3], r2;
+                    (void)lat_pair(st, e[t], wlo, ww, lo, x, g, d, r2);
+                    f[t] = f_val(sqrt(r2), T);
+                }
+#pragma unroll
+                for (int t = 0; t < RC_RHO_GROUP; ++t)
+                    if (v[t]) {
+                        acc += f[t];
+                        const int64_t s = st.ls[e[t]];
+                        atomicOr(&sc.mark[s >> 5], 1u << (s & 31));  // listed in site order by k_mark_emit
+                    }
+            }
+            while (mc) {
+                int e[RC_RHO_GROUP];
+                bool v[RC_RHO_GROUP];
+                take_group<RC_RHO_GROUP>(mc, k, e, v);
+                double f[RC_RHO_GROUP];
+#pragma unroll
+                for (int t = 0; t < RC_RHO_GROUP; ++t) {
+                    double d[3], r2;
+                    run_pair(st, e[t], x, g, d, r2);
+                    f[t] = f_val(sqrt(r2), T);
+                }
+#pragma unroll
+                for (int t = 0; t < RC_RHO_GROUP; ++t)
+                    if (v[t]) acc += f[t];
+            }
+        }
+        acc = split_sum(acc);
+        if (act && k == 0) {
+            double Fv;
+            bool beyond = false;
+            const double d = emb_any<double>(acc, T.emb, T.em, Fv, beyond);
+            S.r_rho[o] = acc;
+            S.r_fp[o] = d;
+            sc.sfp[hs + j] = d;
+            S.r_e[2 * o] = Fv;
+            if (beyond) atomicAdd(&sc.cnt->range_viol, 1u);
+        }
+    }
+}
+
+// (f'(r) (F'_i + F'_j) + phi'(r)) / r times the separation, and phi, of one pair.
+__device__ __forceinline__ void pair_force(const double d[3], double r2, double fpsum, const Tables<double> &T,
+                                           double &fx, double &fy, double &fz, double &phi) {
+    const double rr = sqrt(r2);
+    double df, dphi;
+    fp_phi(rr, T, df, dphi, phi);
+    const double sc_ = (fpsum * df + dphi) / rr;
+    fx = sc_ * d[0];
+    fy = sc_ * d[1];
+    fz = sc_ * d[2];
+}
+
+__device__ __forceinline__ void runaway_force_cell(const State &S, const Scratch &sc, const Geom &g,
+                                                   const Tables<double> &T, int real_is_f32, int energy, int hs,
+                                                   CellStage<true> &st) {
+    int n_cand = 0, n_lat = 0, wlo[3], ww[3];
+    const int nh = sc.cell_s[sc.skey[hs] + 1] - hs;
+    if (!stage_cell<true>(S, sc, g, real_is_f32, hs, st, n_cand, n_lat, wlo, ww)) {
+        const int lane = threadIdx.x & 63;
+        for (int j = threadIdx.x >> 6; j < nh; j += RC_THREADS / 64)
+            runaway_force_one(S, sc, g, T, real_is_f32, energy, sc.sidx[hs + j], lane);
+        return;
+    }
+    const int k = threadIdx.x % RC_SPLIT;
+    for (int hb = 0; hb < nh; hb += RC_HOME) {
+        const int j = hb + (int)threadIdx.x / RC_SPLIT;
+        const bool act = j < nh;
+        double fx = 0.0, fy = 0.0, fz = 0.0, ep = 0.0;
+        int o = -1;
+        if (act) {
+            const int q = hs + j;
+            o = sc.sidx[q];
+            const double x[3] = {sc.srx[q], sc.sry[q], sc.srz[q]};
+            const double fpr = sc.sfp[q];
+            const int lo[3] = {window_lo(x[0] * g.inv_a, g.reach), window_lo(x[1] * g.inv_a, g.reach),
+                               window_lo(x[2] * g.inv_a, g.reach)};
+            uint64_t ml = 0, mc = 0;
+            int i = 0;
+            for (int e = k; e < n_lat; e += RC_SPLIT, ++i) {
+                double d[3], r2;
+                if (lat_pair(st, e, wlo, ww, lo, x, g, d, r2) && r2 < g.rc2) ml |= 1ull << i;
+            }
+            i = 0;
+            for (int e = k; e < n_cand; e += RC_SPLIT, ++i) {
+                if (st.co[e] == o) continue;
+                double d[3], r2;
+                run_pair(st, e, x, g, d, r2);
+                if (r2 < g.rc2) mc |= 1ull << i;
+            }
+            while (ml) {
+                int e[RC_FORCE_GROUP];
+                bool v[RC_FORCE_GROUP];
+                take_group<RC_FORCE_GROUP>(ml, k, e, v);
+                double gx[RC_FORCE_GROUP], gy[RC_FORCE_GROUP], gz[RC_FORCE_GROUP], ph[RC_FORCE_GROUP];
+#pragma unroll
+                for (int t = 0; t < RC_FORCE_GROUP; ++t) {
+                    double d[3], r2;
+                    (void)lat_pair(st, e[t], wlo, ww, lo, x, g, d, r2);
+                    pair_force(d, r2, fpr + st.lfp[e[t]], T, gx[t], gy[t], gz[t], ph[t]);
+                }
+#pragma unroll
+                for (int t = 0; t < RC_FORCE_GROUP; ++t)
+                    if (v[t]) {
+                        fx += gx[t];
+                        fy += gy[t];
+                        fz += gz[t];
+                        ep += ph[t];  // lattice partner has no other record of this pair's energy
+                    }
+            }
+            while (mc) {
+                int e[RC_FORCE_GROUP];
+                bool v[RC_FORCE_GROUP];
+                take_group<RC_FORCE_GROUP>(mc, k, e, v);
+                double gx[RC_FORCE_GROUP], gy[RC_FORCE_GROUP], gz[RC_FORCE_GROUP], ph[RC_FORCE_GROUP];
+#pragma unroll
+                for (int t = 0; t < RC_FORCE_GROUP; ++t) {
+                    double d[3], r2;
+                    run_pair(st, e[t], x, g, d, r2);
+                    pair_force(d, r2, fpr + st.cfp[e[t]], T, gx[t], gy[t], gz[t], ph[t]);
+                }
+#pragma unroll
+                for (int t = 0; t < RC_FORCE_GROUP; ++t)
+                    if (v[t]) {
+                        fx += gx[t];
+                        fy += gy[t];
+                        fz += gz[t];
+                        ep += 0.5 * ph[t];
+                    }
+            }
+        }
+        fx = split_sum(fx);
+        fy = split_sum(fy);
+        fz = split_sum(fz);
+        ep = split_sum(ep);
+        if (act && k == 0) {
+            S.r_fx[o] = fx;
+            S.r_fy[o] = fy;
+            S.r_fz[o] = fz;
+            if (energy) S.r_e[2 * o + 1] = ep;
+        }
+    }
+}
+
+// Run-aways of sparse cells: one wave each.
+constexpr int LONE_WAVES = 4;
+
+__global__ __launch_bounds__(64 * LONE_WAVES) void k_runaway_rho_lone(State S, Scratch sc, Geom g, Tables<double> T) {
+    const int lane = threadIdx.x & 63;
+    const int n = sc.cnt->n_lone;
+    for (int i = blockIdx.x * LONE_WAVES + (threadIdx.x >> 6); i < n; i += gridDim.x * LONE_WAVES)
+    {
+        const int q = sc.loneq[i];
+        runaway_rho_one(S, sc, g, T, sc.sidx[q], q, lane);
+    }
+}
+
+__global__ __launch_bounds__(64 * LONE_WAVES) void k_runaway_force_lone(State S, Scratch sc, Geom g,
+                                                                        Tables<double> T, int real_is_f32,
+                                                                        int energy) {
+    const int lane = threadIdx.x & 63;
+    const int n = sc.cnt->n_lone;
+    for (int i = blockIdx.x * LONE_WAVES + (threadIdx.x >> 6); i < n; i += gridDim.x * LONE_WAVES)
+        runaway_force_one(S, sc, g, T, real_is_f32, energy, sc.sidx[sc.loneq[i]], lane);
+}
+
+__global__ __launch_bounds__(RC_THREADS) void k_runaway_rho_cells(State S, Scratch sc, Geom g, Tables<double> T) {
+    __shared__ CellStage<false> st;
+    const int n = sc.cnt->n_cells;
+    for (int ci = blockIdx.x; ci < n; ci += gridDim.x) {
+        __syncthreads();  // the previous cell's staging is no longer read
+        runaway_rho_cell(S, sc, g, T, sc.cellq[ci], st);
+    }
+}
+
+__global__ __launch_bounds__(RC_THREADS) void k_runaway_force_cells(State S, Scratch sc, Geom g, Tables<double> T,
+                                                                    int real_is_f32, int energy) {
+    __shared__ CellStage<true> st;
+    const int n = sc.cnt->n_cells;
+    for (int ci = blockIdx.x; ci < n; ci += gridDim.x) {
+        __syncthreads();
+        runaway_force_cell(S, sc, g, T, real_is_f32, energy, sc.cellq[ci], st);
+    }
 }
 
 
@@ -902,8 +1454,9 @@ __global__ __launch_bounds__(AFF_THREADS) void k_affected_force(State S, Scratch
 
 constexpr int FLAT_BLOCKS = 1024;  // off[] (at most BATCH_MAX_BOXES + 1 ints) is staged in LDS
 
-// off[0] = 0, off[b + 1] = off[b] + items of box b; which = 0: run-aways, 1: affected
-// lattice atoms (capped at the list's capacity, as the passes over it are).
+// off[0] = 0, off[b + 1] = off[b] + items of box b; which = 0: coarse cells whose
+// run-aways are summed by cell, 1: affected lattice atoms (capped at the list's capacity,
+// as the passes over it are), 2: run-aways summed one by one.
 __global__ __launch_bounds__(1024) void kb_flat_offsets(const BoxRef *__restrict__ boxes, int nbox, int which,
                                                         int32_t *__restrict__ off) {
     __shared__ int sw[16];
@@ -913,7 +1466,9 @@ __global__ __launch_bounds__(1024) void kb_flat_offsets(const BoxRef *__restrict
     for (int base = 0; base < nbox; base += 1024) {
         const int i = base + (int)threadIdx.x;
         int v = 0;
-        if (i < nbox) v = which == 0 ? boxes[i].sc.cnt->n_run : affected_count(boxes[i].sc);
+        if (i < nbox)
+            v = which == 0 ? boxes[i].sc.cnt->n_cells
+                           : (which == 1 ? affected_count(boxes[i].sc) : boxes[i].sc.cnt->n_lone);
         int incl = v;
         for (int o = 1; o < 64; o <<= 1) {
             const int t = __shfl_up(incl, o, 64);
@@ -951,31 +1506,57 @@ __device__ __forceinline__ int flat_box(const int *s_off, int nbox, int q) {
     return lo;
 }
 
-__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kf_runaway_rho(const BoxRef *__restrict__ boxes,
-                                                                               int nbox, const int32_t *off,
-                                                                               Tables<double> T) {
+// Run-aways of sparse cells, one wave per item, and of crowded cells, one block per
+// item, as in the single-box passes.
+__global__ __launch_bounds__(64 * LONE_WAVES) void kf_runaway_rho_lone(const BoxRef *__restrict__ boxes, int nbox,
+                                                                       const int32_t *off, Tables<double> T) {
     extern __shared__ int s_off[];
     const int total = stage_offsets(s_off, off, nbox);
     const int lane = threadIdx.x & 63;
-    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
-    for (int q = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6); q < total; q += nwaves) {
+    for (int q = blockIdx.x * LONE_WAVES + (threadIdx.x >> 6); q < total; q += gridDim.x * LONE_WAVES) {
         const int b = __builtin_amdgcn_readfirstlane(flat_box(s_off, nbox, q));  // one item per wave
         const BoxRef &B = boxes[b];
-        runaway_rho_one(B.S, B.sc, B.g, T, q - s_off[b], lane);
+        const int qs = B.sc.loneq[q - s_off[b]];
+        runaway_rho_one(B.S, B.sc, B.g, T, B.sc.sidx[qs], qs, lane);
     }
 }
 
-__global__ __launch_bounds__(64 * RUNAWAY_WAVES_PER_BLOCK) void kf_runaway_force(const BoxRef *__restrict__ boxes,
-                                                                                 int nbox, const int32_t *off,
-                                                                                 Tables<double> T, int energy) {
+__global__ __launch_bounds__(64 * LONE_WAVES) void kf_runaway_force_lone(const BoxRef *__restrict__ boxes,
+                                                                         int nbox, const int32_t *off,
+                                                                         Tables<double> T, int energy) {
     extern __shared__ int s_off[];
     const int total = stage_offsets(s_off, off, nbox);
     const int lane = threadIdx.x & 63;
-    const int nwaves = gridDim.x * RUNAWAY_WAVES_PER_BLOCK;
-    for (int q = blockIdx.x * RUNAWAY_WAVES_PER_BLOCK + (threadIdx.x >> 6); q < total; q += nwaves) {
+    for (int q = blockIdx.x * LONE_WAVES + (threadIdx.x >> 6); q < total; q += gridDim.x * LONE_WAVES) {
         const int b = __builtin_amdgcn_readfirstlane(flat_box(s_off, nbox, q));
         const BoxRef &B = boxes[b];
-        runaway_force_one(B.S, B.sc, B.g, T, 1, energy, q - s_off[b], lane);
+        runaway_force_one(B.S, B.sc, B.g, T, 1, energy, B.sc.sidx[B.sc.loneq[q - s_off[b]]], lane);
+    }
+}
+
+__global__ __launch_bounds__(RC_THREADS) void kf_runaway_rho(const BoxRef *__restrict__ boxes, int nbox,
+                                                             const int32_t *off, Tables<double> T) {
+    extern __shared__ int s_off[];
+    __shared__ CellStage<false> st;
+    const int total = stage_offsets(s_off, off, nbox);
+    for (int q = blockIdx.x; q < total; q += gridDim.x) {
+        const int b = flat_box(s_off, nbox, q);
+        const BoxRef &B = boxes[b];
+        __syncthreads();  // the previous cell's staging is no longer read
+        runaway_rho_cell(B.S, B.sc, B.g, T, B.sc.cellq[q - s_off[b]], st);
+    }
+}
+
+__global__ __launch_bounds__(RC_THREADS) void kf_runaway_force(const BoxRef *__restrict__ boxes, int nbox,
+                                                               const int32_t *off, Tables<double> T, int energy) {
+    extern __shared__ int s_off[];
+    __shared__ CellStage<true> st;
+    const int total = stage_offsets(s_off, off, nbox);
+    for (int q = blockIdx.x; q < total; q += gridDim.x) {
+        const int b = flat_box(s_off, nbox, q);
+        const BoxRef &B = boxes[b];
+        __syncthreads();
+        runaway_force_cell(B.S, B.sc, B.g, T, 1, energy, B.sc.cellq[q - s_off[b]], st);
     }
 }
 
@@ -1166,10 +1747,19 @@ static Tables<float> t32_of(misa_lattice *h) {
     return T;
 }
 
+// Blocks of the cell-staged run-away passes on one box: as many as stay resident, since
+// the number of occupied cells is known on the device only.
+static int cell_grid(const misa_lattice *h) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_runaway_force_cells, RC_THREADS, 0) != hipSuccess)
+        per_cu = 0;
+    return std::max(SMALL_GRID, per_cu * h->n_cu);
+}
+
 hipError_t launch_rehash(misa_lattice *h) {
     hipStream_t st = h->stream;
-    hipLaunchKernelGGL(k_sort, dim3(1), dim3(SORT_THREADS), 0, st, h->sc.sortbuf, 0, h->sc.cnt, h->rcap, h->sc.l_id,
-                       nullptr, nullptr, nullptr, h->g, h->sc.scal);
+    hipLaunchKernelGGL(k_sort, dim3(1), dim3(SORT_THREADS), 0, st, h->sc.sortbuf, h->sc.cnt, h->rcap, h->sc.l_id,
+                       h->sc.scal);
     hipLaunchKernelGGL(k_claim, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g);
     hipLaunchKernelGGL(k_settle, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, h->S, h->sc);
@@ -1178,16 +1768,22 @@ hipError_t launch_rehash(misa_lattice *h) {
 
 hipError_t launch_runaway_build(misa_lattice *h) {
     hipStream_t st = h->stream;
-    hipLaunchKernelGGL(k_sort, dim3(1), dim3(SORT_THREADS), 0, st, h->sc.sortbuf, 1, h->sc.cnt, h->rcap, nullptr,
-                       h->S.r_x, h->S.r_y, h->S.r_z, h->g, h->sc.scal);
-    hipLaunchKernelGGL(k_hash_insert, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc);
+    const int nb = h->sc.cs_nblk;
+    hipLaunchKernelGGL(k_cell_count, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g);
+    hipLaunchKernelGGL(k_cell_sum, dim3(nb), dim3(CS_THREADS), 0, st, h->sc);
+    hipLaunchKernelGGL(k_cell_top, dim3(1), dim3(1024), 0, st, h->sc);
+    hipLaunchKernelGGL(k_cell_down, dim3(nb), dim3(CS_THREADS), 0, st, h->sc);
+    hipLaunchKernelGGL(k_cell_scatter, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g);
+    hipLaunchKernelGGL(k_cell_order, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc);
     return hipGetLastError();
 }
 
 hipError_t launch_runaway_rho(misa_lattice *h) {
     hipStream_t st = h->stream;
-    hipLaunchKernelGGL(k_runaway_rho, dim3(SMALL_GRID), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, h->S, h->sc,
-                       h->g, t64_of(h));
+    hipLaunchKernelGGL(k_runaway_rho_lone, dim3(SMALL_GRID), dim3(64 * LONE_WAVES), 0, st, h->S, h->sc, h->g,
+                       t64_of(h));
+    hipLaunchKernelGGL(k_runaway_rho_cells, dim3(cell_grid(h)), dim3(RC_THREADS), 0, st, h->S, h->sc, h->g,
+                       t64_of(h));
     hipLaunchKernelGGL(k_mark_count, dim3(h->sc.mark_nblk), dim3(MARK_THREADS), 0, st, h->sc);
     hipLaunchKernelGGL(k_mark_scan, dim3(1), dim3(1024), 0, st, h->sc, h->sc.mark_nblk);
     hipLaunchKernelGGL(k_mark_emit, dim3(h->sc.mark_nblk), dim3(MARK_THREADS), 0, st, h->sc);
@@ -1202,8 +1798,10 @@ hipError_t launch_runaway_rho(misa_lattice *h) {
 
 hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick) {
     hipStream_t st = h->stream;
-    hipLaunchKernelGGL(k_runaway_force, dim3(SMALL_GRID), dim3(64 * RUNAWAY_WAVES_PER_BLOCK), 0, st, h->S, h->sc,
-                       h->g, t64_of(h), h->precision == MISA_FP32 ? 1 : 0, energy ? 1 : 0);
+    hipLaunchKernelGGL(k_runaway_force_lone, dim3(SMALL_GRID), dim3(64 * LONE_WAVES), 0, st, h->S, h->sc, h->g,
+                       t64_of(h), h->precision == MISA_FP32 ? 1 : 0, energy ? 1 : 0);
+    hipLaunchKernelGGL(k_runaway_force_cells, dim3(cell_grid(h)), dim3(RC_THREADS), 0, st, h->S, h->sc, h->g,
+                       t64_of(h), h->precision == MISA_FP32 ? 1 : 0, energy ? 1 : 0);
     const double kf = ACC_UNIT / h->mass;
     if (h->precision == MISA_FP32)
         hipLaunchKernelGGL(k_affected_force<float>, dim3(AFF_GRID), dim3(AFF_THREADS), 0, st, h->S, h->sc, h->g,
@@ -1216,16 +1814,21 @@ hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick) {
 
 // Batched launches (blockIdx.y = box).  gx_*: blocks per box of the grid-stride kernels.
 hipError_t launchb_rehash(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small) {
-    hipLaunchKernelGGL(kb_sort, dim3(1, nbox), dim3(SORT_THREADS), 0, st, boxes, 0);
+    hipLaunchKernelGGL(kb_sort, dim3(1, nbox), dim3(SORT_THREADS), 0, st, boxes);
     hipLaunchKernelGGL(kb_claim, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
     hipLaunchKernelGGL(kb_settle, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
     hipLaunchKernelGGL(kb_compact, dim3(1, nbox), dim3(1024), 0, st, boxes);
     return hipGetLastError();
 }
 
-hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small) {
-    hipLaunchKernelGGL(kb_sort, dim3(1, nbox), dim3(SORT_THREADS), 0, st, boxes, 1);
-    hipLaunchKernelGGL(kb_hash_insert, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
+// gx_cells: the largest cell-scan block count of the boxes.
+hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small, int gx_cells) {
+    hipLaunchKernelGGL(kb_cell_count, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
+    hipLaunchKernelGGL(kb_cell_sum, dim3(gx_cells, nbox), dim3(CS_THREADS), 0, st, boxes);
+    hipLaunchKernelGGL(kb_cell_top, dim3(1, nbox), dim3(1024), 0, st, boxes);
+    hipLaunchKernelGGL(kb_cell_down, dim3(gx_cells, nbox), dim3(CS_THREADS), 0, st, boxes);
+    hipLaunchKernelGGL(kb_cell_scatter, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
+    hipLaunchKernelGGL(kb_cell_order, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
     return hipGetLastError();
 }
 
@@ -1239,14 +1842,18 @@ static int fill_grid(const misa_lattice *h0, Kernel k, int threads, size_t lds) 
     return std::max(FLAT_BLOCKS, per_cu * h0->n_cu);
 }
 
-// off: 2 (nbox + 1) ints for the offsets of the run-away and affected-atom lists.  The
-// force half reuses the offsets the density half computed (neither count changes in between).
+// off: 3 (nbox + 1) ints for the offsets of the crowded-cell, affected-atom and lone
+// run-away lists.  The force half reuses the offsets the density half computed (no count
+// changes in between).
 hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, int mark_blocks, int32_t *off) {
     hipStream_t st = h0->stream;
     const size_t lds = sizeof(int32_t) * (nbox + 1);
     hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 0, off);
-    hipLaunchKernelGGL(kf_runaway_rho, dim3(fill_grid(h0, kf_runaway_rho, 64 * RUNAWAY_WAVES_PER_BLOCK, lds)),
-                       dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes, nbox, off, t64_of(h0));
+    hipLaunchKernelGGL(kb_flat_offsets, dim3(1), dim3(1024), 0, st, boxes, nbox, 2, off + 2 * (nbox + 1));
+    hipLaunchKernelGGL(kf_runaway_rho_lone, dim3(fill_grid(h0, kf_runaway_rho_lone, 64 * LONE_WAVES, lds)),
+                       dim3(64 * LONE_WAVES), lds, st, boxes, nbox, off + 2 * (nbox + 1), t64_of(h0));
+    hipLaunchKernelGGL(kf_runaway_rho, dim3(fill_grid(h0, kf_runaway_rho, RC_THREADS, lds)), dim3(RC_THREADS), lds,
+                       st, boxes, nbox, off, t64_of(h0));
     hipLaunchKernelGGL(kb_mark_count, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
     hipLaunchKernelGGL(kb_mark_scan, dim3(1, nbox), dim3(1024), 0, st, boxes);
     hipLaunchKernelGGL(kb_mark_emit, dim3(mark_blocks, nbox), dim3(MARK_THREADS), 0, st, boxes);
@@ -1259,21 +1866,24 @@ hipError_t launchb_runaway_rho(misa_lattice *h0, const BoxRef *boxes, int nbox, 
 hipError_t launchb_runaway_force(misa_lattice *h0, const BoxRef *boxes, int nbox, bool energy, const int32_t *off) {
     hipStream_t st = h0->stream;
     const size_t lds = sizeof(int32_t) * (nbox + 1);
-    hipLaunchKernelGGL(kf_runaway_force, dim3(fill_grid(h0, kf_runaway_force, 64 * RUNAWAY_WAVES_PER_BLOCK, lds)),
-                       dim3(64 * RUNAWAY_WAVES_PER_BLOCK), lds, st, boxes, nbox, off, t64_of(h0), energy ? 1 : 0);
+    hipLaunchKernelGGL(kf_runaway_force_lone, dim3(fill_grid(h0, kf_runaway_force_lone, 64 * LONE_WAVES, lds)),
+                       dim3(64 * LONE_WAVES), lds, st, boxes, nbox, off + 2 * (nbox + 1), t64_of(h0),
+                       energy ? 1 : 0);
+    hipLaunchKernelGGL(kf_runaway_force, dim3(fill_grid(h0, kf_runaway_force, RC_THREADS, lds)), dim3(RC_THREADS),
+                       lds, st, boxes, nbox, off, t64_of(h0), energy ? 1 : 0);
     hipLaunchKernelGGL(kf_affected_force, dim3(fill_grid(h0, kf_affected_force, AFF_THREADS, lds)),
                        dim3(AFF_THREADS), lds, st, boxes, nbox, off + nbox + 1, t64_of(h0), ACC_UNIT / h0->mass,
                        near_fix_of(h0), energy ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launchb_runaway_clear(hipStream_t st, const BoxRef *boxes, int nbox, int gx_small) {
-    hipLaunchKernelGGL(kb_hash_clear, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
+hipError_t launchb_runaway_clear(hipStream_t st, const BoxRef *boxes, int nbox) {
+    hipLaunchKernelGGL(kb_runaway_clear, dim3(1, nbox), dim3(64), 0, st, boxes);
     return hipGetLastError();
 }
 
 hipError_t launch_runaway_clear(misa_lattice *h) {
-    hipLaunchKernelGGL(k_hash_clear, dim3(SMALL_GRID), dim3(256), 0, h->stream, h->sc);
+    hipLaunchKernelGGL(k_runaway_clear, dim3(1), dim3(64), 0, h->stream, h->sc);
     return hipGetLastError();
 }
 
