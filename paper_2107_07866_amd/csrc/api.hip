@@ -754,7 +754,7 @@ int misa_destroy_lattice(misa_lattice *h) {
         (void)hipDeviceSynchronize();
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->near_g, h->near_h, h->lds64.nodes, h->sth, h->hmeta, h->lds32.f, h->lds32.force, h->lds32h.f,
+    void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->near_g, h->near_h, h->lds64.nodes, h->sth, h->hmeta, h->lds32.lf, h->lds32.lg, h->lds32h.f,
                     h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t64.force6, h->t32.force6, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
@@ -832,13 +832,16 @@ int set_tables_impl(misa_lattice *h, const misa_table *f, const misa_table *phi,
     if (rc) return rc;
     rc = upload_tables<float>(h, h->t32, sf, sp, se, *f, *emb);
     if (rc) return rc;
-    // LDS windows for the persistent float32 kernels (gather passes: 4095 segments;
-    // half-stencil passes, which also hold accumulators in LDS: 2879): two slotted
+    // LDS windows for the persistent float32 kernels (gather passes: 6143 linear
+    // segments; half-stencil passes, which also hold accumulators in LDS: 2879 cubic /
+    // quadratic segments): two slotted
     // atoms are never closer than the nearest-neighbour site distance minus 2 delta.
     for (int wi = 0; wi < 2; ++wi) {
         LdsTables &W = wi == 0 ? h->lds32 : h->lds32h;
         (void)hipFree(W.f);
         (void)hipFree(W.force);
+        (void)hipFree(W.lf);
+        (void)hipFree(W.lg);
         W = LdsTables{};
         const double delta = std::sqrt(h->g.delta2);
         const double r_lo = h->d_min - 2.0 * delta - 2.0 * f->dx;
@@ -859,44 +862,69 @@ int set_tables_impl(misa_lattice *h, const misa_table *f, const misa_table *phi,
             v = ((c.c3 * t + c.c2) * t + c.c1) * t + c.c0;
             d = (c.d2 * t + c.d1) * t + c.d0;
         };
-        std::vector<Q4<float>> wf(nwin);
-        std::vector<FRec32> wr(nwin);
-        for (int64_t s = 0; s < nwin; ++s) {
-            double fv[4], gf[3], gp[3];
-            for (int i = 0; i < 4; ++i) {  // f at t = 0, 1/3, 2/3, 1
-                const double r = std::sqrt(q0 + ((double)s + i / 3.0) * hq);
-                double d;
-                spline(sf, r, fv[i], d);
+        if (wi == 0) {  // gather window: linear records between the spline's values at the q nodes
+            std::vector<float2> lf(nwin);
+            std::vector<float4> lg(nwin);
+            double fv0 = 0.0, gf0 = 0.0, gp0 = 0.0;
+            for (int64_t s = 0; s <= nwin; ++s) {
+                const double r = std::sqrt(q0 + (double)s * hq);
+                double fv, fd, pv, pd;
+                spline(sf, r, fv, fd);
+                spline(sp, r, pv, pd);
+                const double gf = fd / r, gp = pd / r;
+                if (s > 0) {
+                    lf[s - 1] = make_float2((float)fv0, (float)(fv - fv0));
+                    lg[s - 1] = make_float4((float)gf0, (float)(gf - gf0), (float)gp0, (float)(gp - gp0));
+                }
+                fv0 = fv;
+                gf0 = gf;
+                gp0 = gp;
             }
-            for (int i = 0; i < 3; ++i) {  // f'/r and phi'/r at t = 0, 1/2, 1
-                const double r = std::sqrt(q0 + ((double)s + 0.5 * i) * hq);
-                double v, d;
-                spline(sf, r, v, d);
-                gf[i] = d / r;
-                spline(sp, r, v, d);
-                gp[i] = d / r;
+            HIPCHK(h, dev_alloc(&W.lf, nwin));
+            HIPCHK(h, dev_alloc(&W.lg, nwin));
+            HIPCHK(h, hipMemcpy(W.lf, lf.data(), sizeof(float2) * nwin, hipMemcpyHostToDevice));
+            HIPCHK(h, hipMemcpy(W.lg, lg.data(), sizeof(float4) * nwin, hipMemcpyHostToDevice));
+        } else {  // half-stencil window: cubic value and quadratic force records
+            std::vector<Q4<float>> wf(nwin);
+            std::vector<FRec32> wr(nwin);
+            for (int64_t s = 0; s < nwin; ++s) {
+                double fv[4], gf[3], gp[3];
+                for (int i = 0; i < 4; ++i) {  // f at t = 0, 1/3, 2/3, 1
+                    const double r = std::sqrt(q0 + ((double)s + i / 3.0) * hq);
+                    double d;
+                    spline(sf, r, fv[i], d);
+                }
+                for (int i = 0; i < 3; ++i) {  // f'/r and phi'/r at t = 0, 1/2, 1
+                    const double r = std::sqrt(q0 + ((double)s + 0.5 * i) * hq);
+                    double v, d;
+                    spline(sf, r, v, d);
+                    gf[i] = d / r;
+                    spline(sp, r, v, d);
+                    gp[i] = d / r;
+                }
+                // Newton forward differences -> power basis in t
+                const double d1 = fv[1] - fv[0], d2 = fv[2] - 2.0 * fv[1] + fv[0],
+                             d3 = fv[3] - 3.0 * fv[2] + 3.0 * fv[1] - fv[0];
+                wf[s] = {(float)fv[0], (float)(3.0 * d1 - 1.5 * d2 + d3), (float)(4.5 * d2 - 4.5 * d3),
+                         (float)(4.5 * d3)};
+                auto quad = [](const double y[3], double &a0, double &a1, double &a2) {
+                    const double e1 = y[1] - y[0], e2 = y[2] - 2.0 * y[1] + y[0];
+                    a0 = y[0];
+                    a1 = 2.0 * e1 - e2;
+                    a2 = 2.0 * e2;
+                };
+                double f0, f1, f2, p0, p1, p2;
+                quad(gf, f0, f1, f2);
+                quad(gp, p0, p1, p2);
+                wr[s].a = make_float2((float)f0, (float)f1);
+                wr[s].b = make_float2((float)f2, (float)p0);
+                wr[s].c = make_float2((float)p1, (float)p2);
             }
-            // Newton forward differences -> power basis in t
-            const double d1 = fv[1] - fv[0], d2 = fv[2] - 2.0 * fv[1] + fv[0],
-                         d3 = fv[3] - 3.0 * fv[2] + 3.0 * fv[1] - fv[0];
-            wf[s] = {(float)fv[0], (float)(3.0 * d1 - 1.5 * d2 + d3), (float)(4.5 * d2 - 4.5 * d3), (float)(4.5 * d3)};
-            auto quad = [](const double y[3], double &a0, double &a1, double &a2) {
-                const double e1 = y[1] - y[0], e2 = y[2] - 2.0 * y[1] + y[0];
-                a0 = y[0];
-                a1 = 2.0 * e1 - e2;
-                a2 = 2.0 * e2;
-            };
-            double f0, f1, f2, p0, p1, p2;
-            quad(gf, f0, f1, f2);
-            quad(gp, p0, p1, p2);
-            wr[s].a = make_float2((float)f0, (float)f1);
-            wr[s].b = make_float2((float)f2, (float)p0);
-            wr[s].c = make_float2((float)p1, (float)p2);
+            HIPCHK(h, dev_alloc(&W.f, nwin));
+            HIPCHK(h, dev_alloc(&W.force, nwin));
+            HIPCHK(h, hipMemcpy(W.f, wf.data(), sizeof(Q4<float>) * nwin, hipMemcpyHostToDevice));
+            HIPCHK(h, hipMemcpy(W.force, wr.data(), sizeof(FRec32) * nwin, hipMemcpyHostToDevice));
         }
-        HIPCHK(h, dev_alloc(&W.f, nwin));
-        HIPCHK(h, dev_alloc(&W.force, nwin));
-        HIPCHK(h, hipMemcpy(W.f, wf.data(), sizeof(Q4<float>) * nwin, hipMemcpyHostToDevice));
-        HIPCHK(h, hipMemcpy(W.force, wr.data(), sizeof(FRec32) * nwin, hipMemcpyHostToDevice));
         W.k0 = (int32_t)k0;
         W.nwin = (int32_t)nwin;
         W.inv_hq = (float)(1.0 / hq);

@@ -13,7 +13,11 @@
 //
 // The window is re-tabulated from the spline on an equidistant grid in q = r^2,
 // with the force records holding f'(r)/r and phi'(r)/r, so a pair costs no square
-// root and no reciprocal (each a quarter-rate transcendental).
+// root and no reciprocal (each a quarter-rate transcendental).  The records are
+// linear in t between the spline's values at the grid nodes, on a grid fine enough
+// (6143 segments) that the interpolation error stays near float32 rounding: a pair
+// then costs one LDS read of 8 bytes (density) or 16 bytes (force) and one or two
+// multiply-adds for the table.
 //
 // The pair loop is branch-free and unrolled: every stencil candidate runs the
 // full arithmetic and out-of-range pairs are dropped by a select (or read a zero
@@ -260,18 +264,15 @@ __device__ __forceinline__ int tile_stencil_length(float m, unsigned *slot, unsi
 template <class Src, bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const StencilEntry<float> *__restrict__ st,
                                                           int K, int kin, float u_cut2,
-                                                          const Q4<float> *__restrict__ fwin, float inv_hq,
+                                                          const float2 *__restrict__ fwin, float inv_hq,
                                                           float pcq, int nwin, const Q4<float> *__restrict__ etab,
                                                           TabMeta<float> em, float rc2, const NearTab *__restrict__ nt) {
     __shared__ Q4<float> tile[Src::kMaxSites];
-    __shared__ float4 ftab[LDS_TAB_SEGS];
+    __shared__ float2 ftab[LDS_TAB_SEGS];  // {f_0, f_1 - f_0} per segment
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
-    for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) {
-        const Q4<float> c = fwin[e];
-        ftab[e] = make_float4(c.x, c.y, c.z, c.w);
-    }
-    if (kNodeCut && threadIdx.x == 0) ftab[nwin] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) ftab[e] = fwin[e];
+    if (kNodeCut && threadIdx.x == 0) ftab[nwin] = make_float2(0.0f, 0.0f);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // wave-uniform parity: the stencil entries below become scalar loads
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);
@@ -326,8 +327,8 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
                 const float r2 = pair_r2_f32(dx, dy, dz);
                 float t;
                 const int s = win_seg<kNodeCut>(win_pos(r2, inv_hq, pcq), nwin, t);  // q = r^2 grid
-                const float4 c = ftab[s];
-                const float vr = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                const float2 c = ftab[s];
+                const float vr = c.y * t + c.x;
                 acc += (kNodeCut || r2 < rc2) ? vr : 0.0f;
                 return r2 - rc2;
             };
@@ -384,24 +385,16 @@ __device__ __forceinline__ double wave_max_l(double v) {
 template <class Src, bool kEnergy, bool kNodeCut, bool kKick>
 __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const StencilEntry<float> *__restrict__ st,
                                                             int K, int kin, float u_cut2,
-                                                            const FRec32 *__restrict__ fwin, float inv_hq,
+                                                            const float4 *__restrict__ fwin, float inv_hq,
                                                             float pcq, int nwin, Tables<float> T, float rc2,
                                                             double kf) {
     __shared__ Q4<float> tile[Src::kMaxSites];
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
-    __shared__ float4 fab[LDS_TAB_SEGS];  // {f'0, f'1, f'2, phi'0} per segment
-    __shared__ float2 fcc[LDS_TAB_SEGS];  // {phi'1, phi'2}
+    __shared__ float4 fab[LDS_TAB_SEGS];  // {gf_0, gf_1 - gf_0, gp_0, gp_1 - gp_0} per segment
     __shared__ double red[4][TILE2_THREADS / 64];
-    for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) {
-        const FRec32 c = fwin[e];
-        fab[e] = make_float4(c.a.x, c.a.y, c.b.x, c.b.y);
-        fcc[e] = c.c;
-    }
-    if (kNodeCut && threadIdx.x == 0) {
-        fab[nwin] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        fcc[nwin] = make_float2(0.0f, 0.0f);
-    }
+    for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) fab[e] = fwin[e];
+    if (kNodeCut && threadIdx.x == 0) fab[nwin] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);
     TileGeo Gf{};  // the fixed shape's lane site and stencil, computed once
@@ -469,9 +462,8 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
                 float t;
                 const int s = win_seg<kNodeCut>(win_pos(r2, inv_hq, pcq), nwin, t);  // q = r^2 grid
                 const float4 a = fab[s];
-                const float2 c = fcc[s];
-                const float gf = (a.z * t + a.y) * t + a.x;  // f'(r) / r
-                const float gp = (c.y * t + c.x) * t + a.w;  // phi'(r) / r
+                const float gf = a.y * t + a.x;  // f'(r) / r
+                const float gp = a.w * t + a.z;  // phi'(r) / r
                 float sc = (ui.w + uj.w) * gf + gp;
                 if (!kNodeCut) sc = r2 < rc2 ? sc : 0.0f;
                 ax += sc * dx;
@@ -566,8 +558,8 @@ bool lds_path(const misa_lattice *h) {
 NearFix32 near_fix_of(const misa_lattice *h) {
     NearFix32 nf;
     if (!lds_path(h) || half_path(h)) return nf;  // the half-stencil passes decide in float64 themselves
-    nf.frec = h->lds32.f;
-    nf.rec = h->lds32.force;
+    nf.frec = h->lds32.lf;
+    nf.rec = h->lds32.lg;
     nf.nt = h->near_g;
     nf.phi = h->t32.phi;
     nf.fm = h->t32.fm;
@@ -1012,7 +1004,7 @@ template <class Src>
 static hipError_t rho_lds_src(misa_lattice *h, const Src &src, int grid, const StencilEntry<float> *st) {
     auto kern = h->lds32.node_cut ? k_rho_lds<Src, true> : k_rho_lds<Src, false>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, st, h->K, h->K_in,
-                       h->u_cut2, h->lds32.f, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, h->t32.emb, h->t32.em,
+                       h->u_cut2, h->lds32.lf, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, h->t32.emb, h->t32.em,
                        (float)h->g.rc2, near_args(h, false));
     return hipGetLastError();
 }
@@ -1021,7 +1013,7 @@ template <class Src, bool kEnergy, bool kKick>
 static void force_lds_variant(misa_lattice *h, const Src &src, int grid, const StencilEntry<float> *st) {
     auto kern = h->lds32.node_cut ? k_force_lds<Src, kEnergy, true, kKick> : k_force_lds<Src, kEnergy, false, kKick>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE2_THREADS), 0, h->stream, src, st, h->K, h->K_in,
-                       h->u_cut2, h->lds32.force, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, t32_tab(h),
+                       h->u_cut2, h->lds32.lg, h->lds32.inv_hq, h->lds32.pcq, h->lds32.nwin, t32_tab(h),
                        (float)h->g.rc2, ACC_UNIT / h->mass);
 }
 

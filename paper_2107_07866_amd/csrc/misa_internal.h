@@ -40,7 +40,7 @@ constexpr int T2X = 8, T2Y = 8, T2Z = 8;
 constexpr int P2X = T2X + 2 * HALO, P2Y = T2Y + 2 * HALO, P2Z = T2Z + 2 * HALO;
 constexpr int TILE2_SITES = 2 * P2X * P2Y * P2Z;
 constexpr int TILE2_THREADS = 2 * T2X * T2Y * T2Z;  // 1024
-constexpr int LDS_TAB_SEGS = 4096;                  // max table segments held in LDS
+constexpr int LDS_TAB_SEGS = 6144;                  // table segments of the gather passes' LDS window (+ zero record)
 
 // Tile shapes of the batched persistent passes: tx ty tz = 512 cells (1024 lanes for
 // both sublattices) whose staged block (with halo) fits beside the table window.
@@ -315,21 +315,29 @@ struct DevTables {
     TabMeta<Real> fm{}, em{};
 };
 
-// Force record of one q segment as staged in LDS: {g_f0, g_f1}, {g_f2, g_p0}, {g_p1, g_p2} with
-// g_f = f'(r) / r and g_p = phi'(r) / r as quadratics in t.
+// Force record of one q segment of the half-stencil passes' window: {g_f0, g_f1},
+// {g_f2, g_p0}, {g_p1, g_p2} with g_f = f'(r) / r and g_p = phi'(r) / r as quadratics in t.
 struct alignas(8) FRec32 {
     float2 a, b, c;
 };
 
 // Window of f and phi that pairs of slotted atoms can reach (r >= nearest-site
 // distance - 2 delta), re-tabulated on an equidistant grid in q = r^2 for the LDS:
-// segment s covers q in [q0 + s hq, q0 + (s + 1) hq], local t in [0, 1].
-//   f records:     f(q)                 = ((c3 t + c2) t + c1) t + c0
-//   force records: f'(r) / r, phi'(r)/r = (a2 t + a1) t + a0 (quadratics)
-// so the pair loops need neither sqrt(q) nor 1/r.
+// segment s covers q in [q0 + s hq, q0 + (s + 1) hq], local t in [0, 1], so the pair
+// loops need neither sqrt(q) nor 1/r.  Two record forms:
+//   gather passes (LDS_TAB_SEGS segments), linear in t between the spline's values at
+//   the segment's two grid nodes:
+//     lf: {f_0, f_1 - f_0}                                 (8 bytes)
+//     lg: {gf_0, gf_1 - gf_0, gp_0, gp_1 - gp_0}           (16 bytes, one LDS read)
+//   with gf = f'(r) / r and gp = phi'(r) / r;
+//   half-stencil passes (HALF_TAB_SEGS segments, which share LDS with accumulators):
+//     f:     f(q)                 = ((c3 t + c2) t + c1) t + c0
+//     force: f'(r) / r, phi'(r)/r = (a2 t + a1) t + a0 (quadratics)
 struct LdsTables {
-    Q4<float> *f = nullptr;   // nwin value records of f
-    FRec32 *force = nullptr;  // nwin force records
+    float2 *lf = nullptr;     // gather window: nwin linear value records of f
+    float4 *lg = nullptr;     // gather window: nwin linear force records
+    Q4<float> *f = nullptr;   // half window: nwin cubic value records of f
+    FRec32 *force = nullptr;  // half window: nwin quadratic force records
     int32_t k0 = 0, nwin = 0; // k0: first r segment of the source tables inside the window
     float inv_hq = 0.f;       // 1 / hq
     float pcq = 0.f;          // -q0 / hq:  pp = q inv_hq + pcq
@@ -342,8 +350,8 @@ struct LdsTables {
 // the float64 stencil, the r-grid records of phi for the pair energy).  rec null:
 // the force pass used takes that decision itself, or computes in float64.
 struct NearFix32 {
-    const Q4<float> *frec = nullptr;  // value records of f (density)
-    const FRec32 *rec = nullptr;      // force records
+    const float2 *frec = nullptr;     // linear value records of f (density)
+    const float4 *rec = nullptr;      // linear force records
     const NearTab *nt = nullptr;
     const Q4<float> *phi = nullptr;
     TabMeta<float> fm{};

@@ -754,8 +754,8 @@ __device__ __forceinline__ double near_rho_fix(const State &S, const Geom &g, co
     double acc = 0.0;
     for_band_flips(S, g, nf, s, c, p, cell,
                    [&](int64_t, int sg, float t, double sgn, float, float, float, float) {
-                       const Q4<float> cf = nf.frec[sg];
-                       acc += sgn * (double)(((cf.w * t + cf.z) * t + cf.y) * t + cf.x);
+                       const float2 cf = nf.frec[sg];
+                       acc += sgn * (double)(cf.y * t + cf.x);
                    });
     return acc;
 }
@@ -1354,9 +1354,9 @@ __device__ __forceinline__ void near_pair_fix(const State &S, const Geom &g, con
     const float fpi = fpa[s];
     for_band_flips(S, g, nf, s, c, p, cell,
                    [&](int64_t j, int sg, float t, double sgn, float dx, float dy, float dz, float r2) {
-                       const FRec32 rc_ = nf.rec[sg];
-                       const float gf = (rc_.b.x * t + rc_.a.y) * t + rc_.a.x;  // f'(r) / r
-                       const float gp = (rc_.c.y * t + rc_.c.x) * t + rc_.b.y;  // phi'(r) / r
+                       const float4 rc_ = nf.rec[sg];
+                       const float gf = rc_.y * t + rc_.x;  // f'(r) / r
+                       const float gp = rc_.w * t + rc_.z;  // phi'(r) / r
                        const float sc_ = (fpi + fpa[j]) * gf + gp;
                        ax += sgn * (double)(sc_ * dx);
                        ay += sgn * (double)(sc_ * dy);
