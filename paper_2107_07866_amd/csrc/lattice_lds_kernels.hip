@@ -654,6 +654,10 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds64(OneBox src, const S
     const LaneSite L = lane_site(d, p, w, lane);
     const StencilEntry<double> *sp = st + p * KMAX;
     const int lmax = nn - 2;  // last segment of the window
+    // pp = (r - x0) / h - k0: the window-local position, capped at the window's last
+    // node (pairs at or past it are past the cut-off, which drops them)
+    const double pcl = -fm.x0 * fm.inv_h - (double)k0;
+    const double dlmax = (double)(lmax + 1);
     int it = 0;
     int item = src.next(blockIdx.x, it, gridDim.x);
     TileRegs R;
@@ -695,11 +699,11 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds64(OneBox src, const S
                 const double dz = (tz[me + e.lds] - zi) + e.oz;
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 const bool in = r2 < rc2;
-                int s;
-                double t;
-                seg_index(pair_r<double>(in ? r2 : rc2), fm, s, t);
-                // inside the window for every pair of slotted atoms; clamped otherwise
-                const int l = min(max(s - k0, 0), lmax);
+                // window-local segment l and offset t, clamped into the window (every pair
+                // of slotted atoms lies inside it; pairs past rc are dropped below)
+                const double pp = fmin(fma(sqrt_nr1(r2), fm.inv_h, pcl), dlmax);
+                const int l = min(max((int)pp, 0), lmax);
+                const double t = pp - (double)l;
                 const double2 a = nwin[l], b = nwin[l + 1];
                 const double dyn = b.x - a.x;
                 const double c2 = 3.0 * dyn - 2.0 * a.y - b.y;
@@ -795,24 +799,29 @@ __device__ __forceinline__ float store_tile64w(double2 *__restrict__ txy, double
 // F_i = sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (x_j - x_i) / r  (Eq. eam_force_ij), float64,
 // with the fused second half-kick and per-tile partials as in k_force_lds.
 // kw0: first table segment held in LDS; nw: segments held.
-template <bool kEnergy, bool kKick>
+template <bool kEnergy, bool kKick, bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const StencilEntry<double> *__restrict__ st,
                                                               int K, int kin, float u_cut2, Tables<double> T,
                                                               int kw0, int nw, double rc2, double kf) {
     __shared__ double2 txy[TILE2_SITES];
     __shared__ double2 tzw[TILE2_SITES];
-    __shared__ double2 fw[3 * FWIN64_MAX];
+    __shared__ double2 fw[3 * (FWIN64_MAX + 1)];
     __shared__ double red[4][TILE2_THREADS / 64];
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
     const double2 *__restrict__ f6 = reinterpret_cast<const double2 *>(T.force6);
     for (int e = threadIdx.x; e < 3 * nw; e += TILE2_THREADS) fw[e] = f6[3 * kw0 + e];
+    if (threadIdx.x < 3) fw[3 * nw + threadIdx.x] = make_double2(0.0, 0.0);  // segment nseg: past the cut-off
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);
     TileGeo Gf{};
     const Dims d = dims_of<OneBox>(Gf);
     const LaneSite L = lane_site(d, p, w, lane);
     const StencilEntry<double> *sp = st + p * KMAX;
+    const int nlast = T.fm.nseg - 1;
+    // pp = (r - x0) / h, capped at nseg (kNodeCut: the zero record) or at the last node
+    const double pc0 = -T.fm.x0 * T.fm.inv_h;
+    const double dtop = kNodeCut ? (double)T.fm.nseg : (double)nlast + 1.0;
     int it = 0;
     int item = src.next(blockIdx.x, it, gridDim.x);
     TileRegs64 R;
@@ -858,31 +867,35 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const
                 const double dy = (pj.y - pi.y) + e.oy;
                 const double dz = (zwj.x - zwi.x) + e.oz;
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                const bool in = r2 < rc2;
                 double r, rinv;
-                pair_r_rinv<double>(in ? r2 : rc2, r, rinv);
-                int s;
-                double t;
-                seg_index(r, T.fm, s, t);
+                sqrt_rsqrt_nr1(r2, r, rinv);
+                // table segment s and offset t; with kNodeCut pairs at or past the cut-off
+                // (the last node) take s = nseg, whose LDS record is zero
+                const double pp = fmin(fma(r, T.fm.inv_h, pc0), dtop);
+                const int s = max((int)pp, 0);
+                const double t = pp - (double)s;
                 const int l = s - kw0;
-                double2 q0, q1, q2;  // {f'0, f'1}, {f'2, phi'0}, {phi'1, phi'2}
-                if (l >= 0) {
-                    q0 = fw[3 * l];
-                    q1 = fw[3 * l + 1];
-                    q2 = fw[3 * l + 2];
-                } else {
-                    q0 = f6[3 * s];
-                    q1 = f6[3 * s + 1];
-                    q2 = f6[3 * s + 2];
+                // {f'0, f'1}, {f'2, phi'0}, {phi'1, phi'2}: read from LDS unconditionally (a
+                // select between the two sources would turn every read into a generic load
+                // through the vector memory path), replaced from global memory below the window
+                const int lw = max(l, 0);
+                double2 q0 = fw[3 * lw], q1 = fw[3 * lw + 1], q2 = fw[3 * lw + 2];
+                if (l < 0) {  // read as scalars: keeps the compiler from merging it with the LDS read
+                    const double *g6 = T.force6 + 6 * s;
+                    q0 = make_double2(g6[0], g6[1]);
+                    q1 = make_double2(g6[2], g6[3]);
+                    q2 = make_double2(g6[4], g6[5]);
                 }
                 const double dfr = (q1.x * t + q0.y) * t + q0.x;
                 const double dph = (q2.y * t + q2.x) * t + q1.y;
-                const double sc = in ? ((zwi.y + zwj.y) * dfr + dph) * rinv : 0.0;
+                double sc = ((zwi.y + zwj.y) * dfr + dph) * rinv;
+                if (!kNodeCut) sc = r2 < rc2 ? sc : 0.0;
                 ax += sc * dx;
                 ay += sc * dy;
                 az += sc * dz;
-                if (kEnergy) {
-                    const Q4<double> c = T.phi[s];
+                if (kEnergy) {  // last step only
+                    const bool in = kNodeCut ? s < nlast + 1 : r2 < rc2;
+                    const Q4<double> c = T.phi[min(s, nlast)];
                     const double v = ((c.w * t + c.z) * t + c.y) * t + c.x;
                     ep += in ? v : 0.0;
                 }
@@ -963,9 +976,11 @@ template <bool kEnergy, bool kKick>
 static void force_lds64_variant(misa_lattice *h) {
     const int nseg = h->t64.fm.nseg;
     const int nw = nseg < FWIN64_MAX ? nseg : FWIN64_MAX;
-    hipLaunchKernelGGL((k_force_lds64<kEnergy, kKick>), dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream,
-                       one_box(h), h->st64p, h->K, h->K_in, h->u_cut2, t64_tab(h), nseg - nw, nw, h->g.rc2,
-                       ACC_UNIT / h->mass);
+    // the tables' last node at rc: pairs past it read the zero record instead of a select
+    const bool node_cut = std::fabs(h->t64.fm.x_last - h->g.rc) <= 1e-12 * h->g.rc;
+    auto kern = node_cut ? k_force_lds64<kEnergy, kKick, true> : k_force_lds64<kEnergy, kKick, false>;
+    hipLaunchKernelGGL(kern, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, one_box(h), h->st64p, h->K,
+                       h->K_in, h->u_cut2, t64_tab(h), nseg - nw, nw, h->g.rc2, ACC_UNIT / h->mass);
 }
 
 hipError_t launch_force_lds64(misa_lattice *h, bool energy, bool kick) {
