@@ -274,6 +274,11 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
     for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) ftab[e] = fwin[e];
     if (kNodeCut && threadIdx.x == 0) ftab[nwin] = make_float2(0.0f, 0.0f);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // pcq kept in a vector register for the pair loop: the table position's multiply-add
+    // takes one scalar operand (inv_hq), and re-copying pcq would cost an instruction per
+    // unrolled iteration
+    float pcq_v = pcq;
+    asm volatile("" : "+v"(pcq_v));
     // wave-uniform parity: the stencil entries below become scalar loads
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);
     const float thr = nt->thr2[p][lane];
@@ -326,7 +331,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds(Src src, const Stenci
                 const float dz = (uj.z - ui.z) + e.oz;
                 const float r2 = pair_r2_f32(dx, dy, dz);
                 float t;
-                const int s = win_seg<kNodeCut>(win_pos(r2, inv_hq, pcq), nwin, t);  // q = r^2 grid
+                const int s = win_seg<kNodeCut>(win_pos(r2, inv_hq, pcq_v), nwin, t);  // q = r^2 grid
                 const float2 c = ftab[s];
                 const float vr = c.y * t + c.x;
                 acc += (kNodeCut || r2 < rc2) ? vr : 0.0f;
@@ -396,6 +401,11 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
     for (int e = threadIdx.x; e < nwin; e += TILE2_THREADS) fab[e] = fwin[e];
     if (kNodeCut && threadIdx.x == 0) fab[nwin] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // pcq kept in a vector register for the pair loop: the table position's multiply-add
+    // takes one scalar operand (inv_hq), and re-copying pcq would cost an instruction per
+    // unrolled iteration
+    float pcq_v = pcq;
+    asm volatile("" : "+v"(pcq_v));
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);
     TileGeo Gf{};  // the fixed shape's lane site and stencil, computed once
     const LaneSite Lf = lane_site(dims_of<Src>(Gf), p, w, lane);
@@ -460,7 +470,7 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds(Src src, const Sten
                 const float dz = (uj.z - ui.z) + e.oz;
                 const float r2 = pair_r2_f32(dx, dy, dz);
                 float t;
-                const int s = win_seg<kNodeCut>(win_pos(r2, inv_hq, pcq), nwin, t);  // q = r^2 grid
+                const int s = win_seg<kNodeCut>(win_pos(r2, inv_hq, pcq_v), nwin, t);  // q = r^2 grid
                 const float4 a = fab[s];
                 const float gf = a.y * t + a.x;  // f'(r) / r
                 const float gp = a.w * t + a.z;  // phi'(r) / r
