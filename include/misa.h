@@ -76,6 +76,9 @@ typedef struct {
                                  0 < delta < a sqrt(3) / 4 (half the nearest-neighbour distance) */
     double mass;              /* atom mass, > 0 */
     int64_t runaway_capacity; /* max atoms outside the lattice array; <= 0 picks max(16384, sites / 1024) */
+    int32_t periodic[3];      /* boundary per axis: 1 (or 0, the default) = periodic; the lattice store wraps
+                                 every axis (Sec. 3 ghost regions), so other values are rejected */
+    int32_t ntypes;           /* atom species: 1 (or 0, the default); one set of f, phi, F tables (Sec. 2.2) */
 } misa_lattice_desc;
 
 /* Equidistant samples y[k] = g(x0 + k dx), k = 0 .. n - 1 (host memory; copied, not retained). */

@@ -476,6 +476,10 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
         return fail(nullptr, MISA_EINVAL, "delta must lie in (0, a sqrt(3)/4)");
     if (d->pair_precision != MISA_FP64 && d->pair_precision != MISA_FP32 && d->pair_precision != MISA_MLP)
         return fail(nullptr, MISA_EINVAL, "pair_precision must be MISA_FP64, MISA_FP32 or MISA_MLP");
+    for (int k = 0; k < 3; ++k)
+        if (d->periodic[k] != 0 && d->periodic[k] != 1)
+            return fail(nullptr, MISA_EINVAL, "periodic must be 1 (or 0, the default) on every axis: only periodic boxes");
+    if (d->ntypes != 0 && d->ntypes != 1) return fail(nullptr, MISA_EINVAL, "ntypes must be 1 (or 0, the default)");
     const double R = d->rc + 2.0 * d->delta;
     for (int k = 0; k < 3; ++k)
         if (!(d->n_cells[k] * d->a > 2.0 * R))

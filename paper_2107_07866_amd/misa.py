@@ -42,7 +42,7 @@ class MisaError(RuntimeError):
 class misa_lattice_desc(C.Structure):
     _fields_ = [("n_cells", C.c_int32 * 3), ("pair_precision", C.c_int32), ("a", C.c_double),
                 ("rc", C.c_double), ("delta", C.c_double), ("mass", C.c_double),
-                ("runaway_capacity", C.c_int64)]
+                ("runaway_capacity", C.c_int64), ("periodic", C.c_int32 * 3), ("ntypes", C.c_int32)]
 
 
 class misa_table(C.Structure):
@@ -171,11 +171,13 @@ def _ptr(a):
 # entry points, same names as the C ABI
 
 def misa_create_lattice(n_cells, a, rc, delta, mass, pair_precision=MISA_FP64, runaway_capacity=0,
-                        hip_stream=None):
+                        hip_stream=None, periodic=(1, 1, 1), ntypes=1):
     d = misa_lattice_desc()
     d.n_cells[:] = [int(k) for k in n_cells]
     d.pair_precision, d.a, d.rc, d.delta, d.mass = int(pair_precision), float(a), float(rc), float(delta), float(mass)
     d.runaway_capacity = int(runaway_capacity)
+    d.periodic[:] = [int(k) for k in periodic]
+    d.ntypes = int(ntypes)
     h = C.c_void_p()
     _check(lib.misa_create_lattice(C.byref(d), C.c_void_p(hip_stream or 0), C.byref(h)))
     return h
@@ -491,6 +493,8 @@ def misa_batch_create(boxes, a, rc, delta, mass, runaway_capacity=0, hip_stream=
         d.n_cells[:] = [int(c) for c in nc]
         d.pair_precision, d.a, d.rc, d.delta, d.mass = MISA_FP32, float(a), float(rc), float(delta), float(mass)
         d.runaway_capacity = int(caps[k])
+        d.periodic[:] = [1, 1, 1]
+        d.ntypes = 1
     b = C.c_void_p()
     _bcheck(lib.misa_batch_create(descs, n, C.c_void_p(hip_stream or 0), C.byref(b)))
     return b

@@ -61,6 +61,12 @@ def test_descriptor_validation_without_gpu():
         assert M.misa_last_error(None)
     with pytest.raises(M.MisaError):
         M.misa_create_lattice((16, 16, 16), 2.855, 5.0, 0.6, 55.845, pair_precision=7)
+    # only periodic boxes of one species (the descriptor's periodic[3] and ntypes)
+    for kw in (dict(periodic=(1, 2, 1)), dict(periodic=(1, 1, -1)), dict(ntypes=2)):
+        with pytest.raises(M.MisaError) as ei:
+            M.misa_create_lattice((16, 16, 16), 2.855, 5.0, 0.6, 55.845, **kw)
+        assert ei.value.code == M.MISA_EINVAL
+        assert "periodic" in M.misa_last_error(None) or "ntypes" in M.misa_last_error(None)
 
 
 def test_batch_limits_without_gpu():
