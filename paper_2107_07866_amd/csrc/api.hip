@@ -758,7 +758,7 @@ int misa_destroy_lattice(misa_lattice *h) {
         (void)hipDeviceSynchronize();
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->near_g, h->near_h, h->lds64.nodes, h->sth, h->hmeta, h->lds32.lf, h->lds32.lg, h->lds32h.f,
+    void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->near_g, h->near_h, h->lds64.nodes, h->sth, h->hmeta, h->lds32.lf, h->lds32.lg, h->fwin64.recs, h->fwin64.band, h->lds32h.f,
                     h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t64.force6, h->t32.force6, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
@@ -798,6 +798,98 @@ int misa_bind_state(misa_lattice *h, void *device_ptr, int64_t bytes) {
     h->state_set = h->rho_valid = h->force_valid = false;
     return MISA_OK;
 }
+
+namespace {
+// The float64 force records held in LDS (ForceWin64): the whole table when it has at
+// most FWIN64_MAX segments, else bands around the distances of the stencil's shells.
+int build_force_window64(misa_lattice *h, const misa_table &f, const std::vector<SegCoef> &sf,
+                         const std::vector<SegCoef> &sp) {
+    ForceWin64 &W = h->fwin64;
+    (void)hipFree(W.recs);
+    (void)hipFree(W.band);
+    W = ForceWin64{};
+    const int nseg = (int)sf.size();
+    std::vector<StencilEntry<double>> st(2 * KMAX);
+    HIPCHK(h, hipMemcpy(st.data(), h->st64p, sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyDeviceToHost));
+    // segment range [a, b) of the r interval [r0, r1]
+    auto seg_lo = [&](double r) { return std::max(0, std::min(nseg, (int)std::floor((r - f.x0) / f.dx))); };
+    auto seg_hi = [&](double r) { return std::max(0, std::min(nseg, (int)std::ceil((r - f.x0) / f.dx))); };
+    std::vector<double> shells;  // distinct shell distances within rc
+    for (int k = 0; k < h->K; ++k) {
+        const StencilEntry<double> &e = st[k];
+        const double d = std::sqrt(e.ox * e.ox + e.oy * e.oy + e.oz * e.oz);
+        if (d >= h->g.rc) continue;
+        bool seen = false;
+        for (double c : shells) seen = seen || std::fabs(c - d) < 1e-9;
+        if (!seen) shells.push_back(d);
+    }
+    std::sort(shells.begin(), shells.end());
+    // bands [a, b) of segments for half-width w, merged; the last reaches nseg
+    auto bands_for = [&](double w, std::vector<int2> &out) {
+        std::vector<int2> b;
+        for (double c : shells) b.push_back(make_int2(seg_lo(c - w), seg_hi(c + w)));
+        b.push_back(make_int2(seg_lo(h->g.rc - w), nseg));
+        std::sort(b.begin(), b.end(), [](int2 x, int2 y) { return x.x < y.x; });
+        out.clear();
+        for (const int2 &x : b) {
+            if (!out.empty() && x.x <= out.back().y)
+                out.back().y = std::max(out.back().y, x.y);
+            else
+                out.push_back(x);
+        }
+        out.back().y = nseg;
+        int n = 1;  // the zero record
+        for (const int2 &x : out) n += x.y - x.x;
+        return n;
+    };
+    std::vector<int2> bands;
+    if (nseg + 1 <= FWIN64_MAX + 1) {
+        bands.assign(1, make_int2(0, nseg));
+    } else {
+        double lo = 0.0, hi = 2.0 * h->g.rc;  // widest half-width whose bands fit
+        for (int it = 0; it < 60; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (bands_for(mid, bands) <= FWIN64_MAX + 1) lo = mid;
+            else hi = mid;
+        }
+        bands_for(lo, bands);
+        W.halfwidth = lo;
+    }
+    // records in LDS order, then the zero record; band starts in LDS records
+    std::vector<double2> recs;
+    std::vector<int> base;
+    for (const int2 &b : bands) {
+        base.push_back((int)(recs.size() / 3));
+        for (int s = b.x; s < b.y; ++s) {
+            recs.push_back(make_double2(sf[s].d0, sf[s].d1));
+            recs.push_back(make_double2(sf[s].d2, sp[s].d0));
+            recs.push_back(make_double2(sp[s].d1, sp[s].d2));
+        }
+    }
+    for (int i = 0; i < 3; ++i) recs.push_back(make_double2(0.0, 0.0));
+    const int nrec = (int)(recs.size() / 3);
+    if (nrec > FWIN64_MAX + 1) return fail(h, MISA_EINVAL, "float64 force window exceeds its LDS records");
+    // each stencil entry: the band around its shell distance (entries past rc: the top band)
+    std::vector<int4> bandv(2 * KMAX, make_int4(0, 0, 0, 0));
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < h->K; ++k) {
+            const StencilEntry<double> &e = st[p * KMAX + k];
+            const double d = std::sqrt(e.ox * e.ox + e.oy * e.oy + e.oz * e.oz);
+            const int sd = seg_lo(std::min(d, h->g.rc));
+            size_t bi = bands.size() - 1;
+            for (size_t i = 0; i < bands.size(); ++i)
+                if (sd >= bands[i].x && sd < bands[i].y) bi = i;
+            const bool top = bi + 1 == bands.size();
+            bandv[p * KMAX + k] = make_int4(bands[bi].x, bands[bi].y - bands[bi].x + (top ? 1 : 0), base[bi], 0);
+        }
+    HIPCHK(h, dev_alloc(&W.recs, (int64_t)recs.size()));
+    HIPCHK(h, dev_alloc(&W.band, (int64_t)(2 * KMAX)));
+    HIPCHK(h, hipMemcpy(W.recs, recs.data(), sizeof(double2) * recs.size(), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(W.band, bandv.data(), sizeof(int4) * 2 * KMAX, hipMemcpyHostToDevice));
+    W.nrec = nrec;
+    return MISA_OK;
+}
+}  // namespace
 
 namespace {
 int set_tables_impl(misa_lattice *h, const misa_table *f, const misa_table *phi, const misa_table *emb);
@@ -957,6 +1049,11 @@ int set_tables_impl(misa_lattice *h, const misa_table *f, const misa_table *phi,
             W.nn = (int32_t)nn;
             W.usable = true;
         }
+    }
+    // LDS force records of the persistent float64 force pass (ForceWin64)
+    if (h->precision == MISA_FP64 && !h->use_mlp) {
+        const int rc = build_force_window64(h, *f, sf, sp);
+        if (rc) return rc;
     }
     h->tables_set = true;
     h->rho_valid = h->force_valid = false;

@@ -752,13 +752,12 @@ static Tables<double> t64_tab(const misa_lattice *h) {
 
 // Float64 force pass on the same persistent scheme.  The tile holds {x, y} and
 // {z, F'} per site (32 bytes, 110.6 KiB for 8 x 8 x 8 cells), which leaves room for
-// the top FWIN64_MAX dense force records (48 bytes each: f' and phi' as quadratics
-// in t) of the table.  With 5000-point tables that is r >= rc - 1.08 A: the third to
-// fifth BCC neighbour shells.  Segments below the window (the first two shells) are
-// gathered from global memory; the branch is nearly always uniform across a wave,
-// whose lanes share one stencil offset.  Per-tile partials use the 8 x 8 x 8 tiling.
-constexpr int FWIN64_MAX = 1080;
-
+// FWIN64_MAX dense force records (48 bytes each: f' and phi' as quadratics in t) and a
+// zero record.  With 5000-point tables these are bands of the table around the five BCC
+// neighbour shells within rc (ForceWin64): a pair outside its stencil entry's band, as in
+// a cascade, gathers its record from global memory; the branch is nearly always uniform
+// across a wave, whose lanes share one stencil offset.  Per-tile partials use the
+// 8 x 8 x 8 tiling.
 struct TileRegs64 {
     double x[TILE2_PER_LANE], y[TILE2_PER_LANE], z[TILE2_PER_LANE], w[TILE2_PER_LANE];
 };
@@ -808,11 +807,13 @@ __device__ __forceinline__ float store_tile64w(double2 *__restrict__ txy, double
 
 // F_i = sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (x_j - x_i) / r  (Eq. eam_force_ij), float64,
 // with the fused second half-kick and per-tile partials as in k_force_lds.
-// kw0: first table segment held in LDS; nw: segments held.
+// recs, nrec: the LDS records in LDS order; band: per parity and stencil entry, the
+// segments held and where (ForceWin64).
 template <bool kEnergy, bool kKick, bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const StencilEntry<double> *__restrict__ st,
                                                               int K, int kin, float u_cut2, Tables<double> T,
-                                                              int kw0, int nw, double rc2, double kf) {
+                                                              const double2 *__restrict__ recs, int nrec,
+                                                              const int4 *__restrict__ band, double rc2, double kf) {
     __shared__ double2 txy[TILE2_SITES];
     __shared__ double2 tzw[TILE2_SITES];
     __shared__ double2 fw[3 * (FWIN64_MAX + 1)];
@@ -820,14 +821,14 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
     const double2 *__restrict__ f6 = reinterpret_cast<const double2 *>(T.force6);
-    for (int e = threadIdx.x; e < 3 * nw; e += TILE2_THREADS) fw[e] = f6[3 * kw0 + e];
-    if (threadIdx.x < 3) fw[3 * nw + threadIdx.x] = make_double2(0.0, 0.0);  // segment nseg: past the cut-off
+    for (int e = threadIdx.x; e < 3 * nrec; e += TILE2_THREADS) fw[e] = recs[e];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);
     TileGeo Gf{};
     const Dims d = dims_of<OneBox>(Gf);
     const LaneSite L = lane_site(d, p, w, lane);
     const StencilEntry<double> *sp = st + p * KMAX;
+    const int4 *bp = band + p * KMAX;
     const int nlast = T.fm.nseg - 1;
     // pp = (r - x0) / h, capped at nseg (kNodeCut: the zero record) or at the last node
     const double pc0 = -T.fm.x0 * T.fm.inv_h;
@@ -884,17 +885,22 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const
                 const double pp = fmin(fma(r, T.fm.inv_h, pc0), dtop);
                 const int s = max((int)pp, 0);
                 const double t = pp - (double)s;
-                const int l = s - kw0;
+                // this entry's band of LDS records, else global memory (zeros past the last
+                // segment: pairs at or past the cut-off)
+                const int4 bw = bp[k];
+                const int l = s - bw.x;
+                const bool inw = (unsigned)l < (unsigned)bw.y;
                 // {f'0, f'1}, {f'2, phi'0}, {phi'1, phi'2}: read from LDS unconditionally (a
                 // select between the two sources would turn every read into a generic load
-                // through the vector memory path), replaced from global memory below the window
-                const int lw = max(l, 0);
+                // through the vector memory path), replaced from global memory outside the band
+                const int lw = bw.z + (inw ? l : 0);
                 double2 q0 = fw[3 * lw], q1 = fw[3 * lw + 1], q2 = fw[3 * lw + 2];
-                if (l < 0) {  // read as scalars: keeps the compiler from merging it with the LDS read
-                    const double *g6 = T.force6 + 6 * s;
-                    q0 = make_double2(g6[0], g6[1]);
-                    q1 = make_double2(g6[2], g6[3]);
-                    q2 = make_double2(g6[4], g6[5]);
+                if (!inw) {  // read as scalars: keeps the compiler from merging it with the LDS read
+                    const double *g6 = T.force6 + 6 * min(s, nlast);
+                    const double z = s <= nlast ? 1.0 : 0.0;
+                    q0 = make_double2(z * g6[0], z * g6[1]);
+                    q1 = make_double2(z * g6[2], z * g6[3]);
+                    q2 = make_double2(z * g6[4], z * g6[5]);
                 }
                 const double dfr = (q1.x * t + q0.y) * t + q0.x;
                 const double dph = (q2.y * t + q2.x) * t + q1.y;
@@ -979,18 +985,18 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const
 }
 
 bool lds64f_path(const misa_lattice *h) {
-    return h->precision == MISA_FP64 && !h->use_mlp && h->persistent_grid > 0 && h->g.nsites > 0;
+    return h->precision == MISA_FP64 && !h->use_mlp && h->persistent_grid > 0 && h->g.nsites > 0 &&
+           h->fwin64.nrec > 0;
 }
 
 template <bool kEnergy, bool kKick>
 static void force_lds64_variant(misa_lattice *h) {
-    const int nseg = h->t64.fm.nseg;
-    const int nw = nseg < FWIN64_MAX ? nseg : FWIN64_MAX;
     // the tables' last node at rc: pairs past it read the zero record instead of a select
     const bool node_cut = std::fabs(h->t64.fm.x_last - h->g.rc) <= 1e-12 * h->g.rc;
     auto kern = node_cut ? k_force_lds64<kEnergy, kKick, true> : k_force_lds64<kEnergy, kKick, false>;
     hipLaunchKernelGGL(kern, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, one_box(h), h->st64p, h->K,
-                       h->K_in, h->u_cut2, t64_tab(h), nseg - nw, nw, h->g.rc2, ACC_UNIT / h->mass);
+                       h->K_in, h->u_cut2, t64_tab(h), h->fwin64.recs, h->fwin64.nrec, h->fwin64.band, h->g.rc2,
+                       ACC_UNIT / h->mass);
 }
 
 hipError_t launch_force_lds64(misa_lattice *h, bool energy, bool kick) {

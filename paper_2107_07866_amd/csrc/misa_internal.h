@@ -359,6 +359,23 @@ struct NearFix32 {
     int32_t nwin = 0, node_cut = 0, K = 0;
 };
 
+// Force records of the persistent float64 force pass held in LDS beside its tile: at
+// most FWIN64_MAX table segments (48 bytes each: f' and phi' as quadratics in t) plus
+// one zero record.  Tables of at most FWIN64_MAX segments are held whole.  Larger
+// tables are held as bands of segments around the distances of the stencil's shells
+// (r in [d - w, d + w], w as wide as the records allow, overlapping bands merged, the
+// top band reaching the last node); the zero record follows the top band and stands for
+// segment nseg, where pairs at or past the cut-off land.  band[p KMAX + k] = {first
+// segment, segments (zero record included), first LDS record, 0} for stencil entry k of
+// parity p; a pair outside its entry's band reads its record from global memory.
+constexpr int FWIN64_MAX = 1080;
+struct ForceWin64 {
+    double2 *recs = nullptr;  // nrec records of 3 double2, in LDS order
+    int4 *band = nullptr;     // 2 KMAX entries
+    int32_t nrec = 0;
+    double halfwidth = 0.0;   // w of the shell bands (0 when the table is held whole)
+};
+
 // Window of the f spline's nodes for the persistent float64 density pass: node
 // k0 + i holds {y, m} (value, and slope in units of the sample spacing), i < nn.
 constexpr int NODE64_MAX = 4096;
@@ -441,6 +458,7 @@ struct misa_lattice {
     misa::StencilEntry<float> *st32p = nullptr;   // stencil with LDS offsets of the 8x8x8 tiles
     misa::StencilEntry<double> *st64p = nullptr;  // the same offsets, float64 separations
     misa::NodeWin64 lds64;                        // f nodes for the persistent float64 density pass
+    misa::ForceWin64 fwin64;                      // force records of the persistent float64 force pass
     int pair_schedule = 0;                        // MISA_PAIRS_GATHER or MISA_PAIRS_HALF
     bool half_fits = false;                       // every axis a multiple of 16 cells (8 colours of tiles)
     misa::StencilEntry<float> *sth = nullptr;     // half-stencil entries (device [2][KMAX])
