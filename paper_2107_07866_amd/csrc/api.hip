@@ -758,7 +758,7 @@ int misa_destroy_lattice(misa_lattice *h) {
         (void)hipDeviceSynchronize();
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->near_g, h->near_h, h->lds64.nodes, h->sth, h->hmeta, h->lds32.lf, h->lds32.lg, h->fwin64.recs, h->fwin64.band, h->lds32h.f,
+    void *ptrs[] = {h->st64, h->st32, h->st32p, h->st64p, h->near_g, h->near_h, h->sth, h->hmeta, h->lds32.lf, h->lds32.lg, h->fwin64.recs, h->fwin64.band, h->rwin64.recs, h->rwin64.band, h->lds32h.f,
                     h->lds32h.force, h->t64.f, h->t64.force, h->t64.phi, h->t64.emb, h->t64.force6, h->t32.force6, h->t32.f, h->t32.force,
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
@@ -800,18 +800,14 @@ int misa_bind_state(misa_lattice *h, void *device_ptr, int64_t bytes) {
 }
 
 namespace {
-// The float64 force records held in LDS (ForceWin64): the whole table when it has at
-// most FWIN64_MAX segments, else bands around the distances of the stencil's shells.
-int build_force_window64(misa_lattice *h, const misa_table &f, const std::vector<SegCoef> &sf,
-                         const std::vector<SegCoef> &sp) {
-    ForceWin64 &W = h->fwin64;
-    (void)hipFree(W.recs);
-    (void)hipFree(W.band);
-    W = ForceWin64{};
-    const int nseg = (int)sf.size();
+// Bands of table segments for a persistent float64 pass with room for cap LDS records
+// (BandWin64): per stencil entry the band around its shell distance (entries past rc:
+// the top band).  Returns the bands (in LDS order) and the records they take, the zero
+// record included.
+int shell_bands(misa_lattice *h, const misa_table &f, int nseg, int cap, std::vector<int2> &bands,
+                std::vector<int4> &bandv, double &halfwidth) {
     std::vector<StencilEntry<double>> st(2 * KMAX);
     HIPCHK(h, hipMemcpy(st.data(), h->st64p, sizeof(StencilEntry<double>) * 2 * KMAX, hipMemcpyDeviceToHost));
-    // segment range [a, b) of the r interval [r0, r1]
     auto seg_lo = [&](double r) { return std::max(0, std::min(nseg, (int)std::floor((r - f.x0) / f.dx))); };
     auto seg_hi = [&](double r) { return std::max(0, std::min(nseg, (int)std::ceil((r - f.x0) / f.dx))); };
     std::vector<double> shells;  // distinct shell distances within rc
@@ -824,7 +820,7 @@ int build_force_window64(misa_lattice *h, const misa_table &f, const std::vector
         if (!seen) shells.push_back(d);
     }
     std::sort(shells.begin(), shells.end());
-    // bands [a, b) of segments for half-width w, merged; the last reaches nseg
+    // bands [a, b) for half-width w, merged, the last reaching nseg; records incl. the zero one
     auto bands_for = [&](double w, std::vector<int2> &out) {
         std::vector<int2> b;
         for (double c : shells) b.push_back(make_int2(seg_lo(c - w), seg_hi(c + w)));
@@ -838,39 +834,30 @@ int build_force_window64(misa_lattice *h, const misa_table &f, const std::vector
                 out.push_back(x);
         }
         out.back().y = nseg;
-        int n = 1;  // the zero record
+        int n = 1;
         for (const int2 &x : out) n += x.y - x.x;
         return n;
     };
-    std::vector<int2> bands;
-    if (nseg + 1 <= FWIN64_MAX + 1) {
+    halfwidth = 0.0;
+    if (nseg + 1 <= cap) {
         bands.assign(1, make_int2(0, nseg));
     } else {
         double lo = 0.0, hi = 2.0 * h->g.rc;  // widest half-width whose bands fit
         for (int it = 0; it < 60; ++it) {
             const double mid = 0.5 * (lo + hi);
-            if (bands_for(mid, bands) <= FWIN64_MAX + 1) lo = mid;
+            if (bands_for(mid, bands) <= cap) lo = mid;
             else hi = mid;
         }
-        bands_for(lo, bands);
-        W.halfwidth = lo;
+        if (bands_for(lo, bands) > cap) return fail(h, MISA_EINVAL, "float64 table bands exceed their LDS records");
+        halfwidth = lo;
     }
-    // records in LDS order, then the zero record; band starts in LDS records
-    std::vector<double2> recs;
     std::vector<int> base;
+    int n = 0;
     for (const int2 &b : bands) {
-        base.push_back((int)(recs.size() / 3));
-        for (int s = b.x; s < b.y; ++s) {
-            recs.push_back(make_double2(sf[s].d0, sf[s].d1));
-            recs.push_back(make_double2(sf[s].d2, sp[s].d0));
-            recs.push_back(make_double2(sp[s].d1, sp[s].d2));
-        }
+        base.push_back(n);
+        n += b.y - b.x;
     }
-    for (int i = 0; i < 3; ++i) recs.push_back(make_double2(0.0, 0.0));
-    const int nrec = (int)(recs.size() / 3);
-    if (nrec > FWIN64_MAX + 1) return fail(h, MISA_EINVAL, "float64 force window exceeds its LDS records");
-    // each stencil entry: the band around its shell distance (entries past rc: the top band)
-    std::vector<int4> bandv(2 * KMAX, make_int4(0, 0, 0, 0));
+    bandv.assign(2 * KMAX, make_int4(0, 0, 0, 0));
     for (int p = 0; p < 2; ++p)
         for (int k = 0; k < h->K; ++k) {
             const StencilEntry<double> &e = st[p * KMAX + k];
@@ -882,11 +869,45 @@ int build_force_window64(misa_lattice *h, const misa_table &f, const std::vector
             const bool top = bi + 1 == bands.size();
             bandv[p * KMAX + k] = make_int4(bands[bi].x, bands[bi].y - bands[bi].x + (top ? 1 : 0), base[bi], 0);
         }
-    HIPCHK(h, dev_alloc(&W.recs, (int64_t)recs.size()));
-    HIPCHK(h, dev_alloc(&W.band, (int64_t)(2 * KMAX)));
-    HIPCHK(h, hipMemcpy(W.recs, recs.data(), sizeof(double2) * recs.size(), hipMemcpyHostToDevice));
-    HIPCHK(h, hipMemcpy(W.band, bandv.data(), sizeof(int4) * 2 * KMAX, hipMemcpyHostToDevice));
-    W.nrec = nrec;
+    return MISA_OK;
+}
+
+// The LDS records of the persistent float64 passes (BandWin64): force records (f' and
+// phi' quadratics, 3 double2) and density records (f cubic, 2 double2).
+int build_windows64(misa_lattice *h, const misa_table &f, const std::vector<SegCoef> &sf,
+                    const std::vector<SegCoef> &sp) {
+    const int nseg = (int)sf.size();
+    for (int which = 0; which < 2; ++which) {
+        BandWin64 &W = which == 0 ? h->fwin64 : h->rwin64;
+        (void)hipFree(W.recs);
+        (void)hipFree(W.band);
+        W = BandWin64{};
+        std::vector<int2> bands;
+        std::vector<int4> bandv;
+        double w = 0.0;
+        const int rc = shell_bands(h, f, nseg, which == 0 ? FWIN64_MAX + 1 : RWIN64_MAX, bands, bandv, w);
+        if (rc) return rc;
+        std::vector<double2> recs;
+        for (const int2 &b : bands)
+            for (int s = b.x; s < b.y; ++s) {
+                if (which == 0) {
+                    recs.push_back(make_double2(sf[s].d0, sf[s].d1));
+                    recs.push_back(make_double2(sf[s].d2, sp[s].d0));
+                    recs.push_back(make_double2(sp[s].d1, sp[s].d2));
+                } else {
+                    recs.push_back(make_double2(sf[s].c0, sf[s].c1));
+                    recs.push_back(make_double2(sf[s].c2, sf[s].c3));
+                }
+            }
+        const int per = which == 0 ? 3 : 2;
+        for (int i = 0; i < per; ++i) recs.push_back(make_double2(0.0, 0.0));  // segment nseg
+        HIPCHK(h, dev_alloc(&W.recs, (int64_t)recs.size()));
+        HIPCHK(h, dev_alloc(&W.band, (int64_t)(2 * KMAX)));
+        HIPCHK(h, hipMemcpy(W.recs, recs.data(), sizeof(double2) * recs.size(), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(W.band, bandv.data(), sizeof(int4) * 2 * KMAX, hipMemcpyHostToDevice));
+        W.nrec = (int32_t)(recs.size() / per);
+        W.halfwidth = w;
+    }
     return MISA_OK;
 }
 }  // namespace
@@ -1028,31 +1049,9 @@ int set_tables_impl(misa_lattice *h, const misa_table *f, const misa_table *phi,
         W.usable = q1 > q0;
         W.node_cut = std::fabs(x_last - h->g.rc) <= 1e-12 * h->g.rc;
     }
-    // Node window of f for the persistent float64 density pass: the nodes of every
-    // segment a pair of slotted atoms can reach (the same lower bound as above).
-    {
-        NodeWin64 &W = h->lds64;
-        (void)hipFree(W.nodes);
-        W = NodeWin64{};
-        const double r_lo = h->d_min - 2.0 * std::sqrt(h->g.delta2) - 2.0 * f->dx;
-        int64_t k0 = (int64_t)std::floor((r_lo - f->x0) / f->dx);
-        k0 = std::max<int64_t>(0, std::min<int64_t>(k0, f->n - 2));
-        const int64_t nn = f->n - k0;
-        if (nn <= NODE64_MAX) {
-            std::vector<double> m;
-            node_slopes(f->y, f->n, m);
-            std::vector<double2> nodes(nn);
-            for (int64_t i = 0; i < nn; ++i) nodes[i] = make_double2(f->y[k0 + i], m[k0 + i]);
-            HIPCHK(h, dev_alloc(&W.nodes, nn));
-            HIPCHK(h, hipMemcpy(W.nodes, nodes.data(), sizeof(double2) * nn, hipMemcpyHostToDevice));
-            W.k0 = (int32_t)k0;
-            W.nn = (int32_t)nn;
-            W.usable = true;
-        }
-    }
-    // LDS force records of the persistent float64 force pass (ForceWin64)
+    // LDS records of the persistent float64 passes (BandWin64)
     if (h->precision == MISA_FP64 && !h->use_mlp) {
-        const int rc = build_force_window64(h, *f, sf, sp);
+        const int rc = build_windows64(h, *f, sf, sp);
         if (rc) return rc;
     }
     h->tables_set = true;

@@ -619,13 +619,11 @@ static OneBox one_box(misa_lattice *h) {
 }
 
 // ---------------------------------------------------------------------------
-// Float64 density pass on the same persistent scheme.  The float64 spline records
-// (32 bytes per segment) of the window would not fit beside a float64 tile, but its
-// nodes do: node i holds {y_i, m_i}, and segment i is the cubic Hermite through nodes
-// i and i + 1 in t in [0, 1], c2 = 3 dy - 2 m_i - m_{i+1}, c3 = m_i + m_{i+1} - 2 dy
-// (dy = y_{i+1} - y_i), the same coefficients the float64 table records hold.  The
-// window (at most NODE64_MAX nodes, 16 bytes each) sits beside an 8 x 8 x 8 tile of
-// float64 displacements (x and y as one 16-byte word, z apart): 147 KiB of LDS.
+// Float64 density pass on the same persistent scheme.  Beside an 8 x 8 x 8 tile of
+// float64 displacements (x and y as one 16-byte word, z apart: 81 KiB) sit RWIN64_MAX
+// float64 spline records of f (32 bytes: the segment's cubic in t) as bands around the
+// stencil's shell distances, with a zero record for pairs at or past the cut-off
+// (BandWin64); a pair outside its entry's band reads the table record from global memory.
 
 // Stores this lane's share of the tile; returns the largest |u|^2 among the occupied
 // sites it stored (in float32, as the stencil-length test takes it).
@@ -646,28 +644,33 @@ __device__ __forceinline__ float store_tile64(double2 *__restrict__ txy, double 
 
 // rho_i = sum_j f(r_ij) over the stencil, then F'(rho_i) (Sec. 2.2 steps 1-2), float64.
 // nodes: nn nodes of f from source node k0 on; fm: the source table's grid.
+// recs, nrec: the LDS records ({c0, c1}, {c2, c3} each) in LDS order; band: per parity
+// and stencil entry, the segments held and where; ftab: the table's records.
+template <bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds64(OneBox src, const StencilEntry<double> *__restrict__ st,
                                                             int K, int kin, float u_cut2,
-                                                            const double2 *__restrict__ nodes, int k0, int nn,
-                                                            TabMeta<double> fm, const Q4<double> *__restrict__ etab,
-                                                            TabMeta<double> em, double rc2) {
+                                                            const double2 *__restrict__ recs, int nrec,
+                                                            const int4 *__restrict__ band,
+                                                            const Q4<double> *__restrict__ ftab, TabMeta<double> fm,
+                                                            const Q4<double> *__restrict__ etab, TabMeta<double> em,
+                                                            double rc2) {
     __shared__ double2 txy[TILE2_SITES];
     __shared__ double tz[TILE2_SITES];
-    __shared__ double2 nwin[NODE64_MAX];
+    __shared__ double2 rw[2 * RWIN64_MAX];
     __shared__ unsigned umax_slot[2];
     if (threadIdx.x < 2) umax_slot[threadIdx.x] = 0u;
-    for (int e = threadIdx.x; e < nn; e += TILE2_THREADS) nwin[e] = nodes[e];
+    for (int e = threadIdx.x; e < 2 * nrec; e += TILE2_THREADS) rw[e] = recs[e];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(w >> 3);  // wave-uniform parity: scalar stencil loads
     TileGeo Gf{};
     const Dims d = dims_of<OneBox>(Gf);
     const LaneSite L = lane_site(d, p, w, lane);
     const StencilEntry<double> *sp = st + p * KMAX;
-    const int lmax = nn - 2;  // last segment of the window
-    // pp = (r - x0) / h - k0: the window-local position, capped at the window's last
-    // node (pairs at or past it are past the cut-off, which drops them)
-    const double pcl = -fm.x0 * fm.inv_h - (double)k0;
-    const double dlmax = (double)(lmax + 1);
+    const int4 *bp = band + p * KMAX;
+    const int nlast = fm.nseg - 1;
+    // pp = (r - x0) / h, capped at nseg (kNodeCut: the zero record) or at the last node
+    const double pc0 = -fm.x0 * fm.inv_h;
+    const double dtop = (double)fm.nseg;
     int it = 0;
     int item = src.next(blockIdx.x, it, gridDim.x);
     TileRegs R;
@@ -708,18 +711,26 @@ __global__ __launch_bounds__(TILE2_THREADS) void k_rho_lds64(OneBox src, const S
                 const double dy = (pj.y - pi.y) + e.oy;
                 const double dz = (tz[me + e.lds] - zi) + e.oz;
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                const bool in = r2 < rc2;
-                // window-local segment l and offset t, clamped into the window (every pair
-                // of slotted atoms lies inside it; pairs past rc are dropped below)
-                const double pp = fmin(fma(sqrt_nr1(r2), fm.inv_h, pcl), dlmax);
-                const int l = min(max((int)pp, 0), lmax);
-                const double t = pp - (double)l;
-                const double2 a = nwin[l], b = nwin[l + 1];
-                const double dyn = b.x - a.x;
-                const double c2 = 3.0 * dyn - 2.0 * a.y - b.y;
-                const double c3 = a.y + b.y - 2.0 * dyn;
-                const double v = ((c3 * t + c2) * t + a.y) * t + a.x;
-                acc += in ? v : 0.0;
+                // table segment s and offset t; with kNodeCut pairs at or past the cut-off
+                // (the last node) take s = nseg, whose record is zero
+                const double pp = fmin(fma(sqrt_nr1(r2), fm.inv_h, pc0), dtop);
+                const int s = max((int)pp, 0);
+                const double t = pp - (double)s;
+                // this entry's band of LDS records (read unconditionally, see k_force_lds64),
+                // else the table's record in global memory (zeros past the last segment)
+                const int4 bw = bp[k];
+                const int l = s - bw.x;
+                const bool inw = (unsigned)l < (unsigned)bw.y;
+                const int lw = bw.z + (inw ? l : 0);
+                double2 a = rw[2 * lw], b = rw[2 * lw + 1];
+                if (!inw) {
+                    const double *g4 = &ftab[min(s, nlast)].x;
+                    const double z = s <= nlast ? 1.0 : 0.0;
+                    a = make_double2(z * g4[0], z * g4[1]);
+                    b = make_double2(z * g4[2], z * g4[3]);
+                }
+                const double v = ((b.y * t + b.x) * t + a.y) * t + a.x;
+                acc += (kNodeCut || r2 < rc2) ? v : 0.0;
             }
             const int64_t idx = (int64_t)p * G.ncell + ((int64_t)gz * G.ny + gy) * G.nx + gx;
             double fpv = 0.0;
@@ -754,7 +765,7 @@ static Tables<double> t64_tab(const misa_lattice *h) {
 // {z, F'} per site (32 bytes, 110.6 KiB for 8 x 8 x 8 cells), which leaves room for
 // FWIN64_MAX dense force records (48 bytes each: f' and phi' as quadratics in t) and a
 // zero record.  With 5000-point tables these are bands of the table around the five BCC
-// neighbour shells within rc (ForceWin64): a pair outside its stencil entry's band, as in
+// neighbour shells within rc (BandWin64): a pair outside its stencil entry's band, as in
 // a cascade, gathers its record from global memory; the branch is nearly always uniform
 // across a wave, whose lanes share one stencil offset.  Per-tile partials use the
 // 8 x 8 x 8 tiling.
@@ -808,7 +819,7 @@ __device__ __forceinline__ float store_tile64w(double2 *__restrict__ txy, double
 // F_i = sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (x_j - x_i) / r  (Eq. eam_force_ij), float64,
 // with the fused second half-kick and per-tile partials as in k_force_lds.
 // recs, nrec: the LDS records in LDS order; band: per parity and stencil entry, the
-// segments held and where (ForceWin64).
+// segments held and where (BandWin64).
 template <bool kEnergy, bool kKick, bool kNodeCut>
 __global__ __launch_bounds__(TILE2_THREADS) void k_force_lds64(OneBox src, const StencilEntry<double> *__restrict__ st,
                                                               int K, int kin, float u_cut2, Tables<double> T,
@@ -1008,13 +1019,15 @@ hipError_t launch_force_lds64(misa_lattice *h, bool energy, bool kick) {
 }
 
 bool lds64_path(const misa_lattice *h) {
-    return h->precision == MISA_FP64 && !h->use_mlp && h->lds64.usable && h->persistent_grid > 0;
+    return h->precision == MISA_FP64 && !h->use_mlp && h->rwin64.nrec > 0 && h->persistent_grid > 0;
 }
 
 hipError_t launch_rho_lds64(misa_lattice *h) {
     OneBox o = one_box(h);
-    hipLaunchKernelGGL(k_rho_lds64, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, o, h->st64p, h->K,
-                       h->K_in, h->u_cut2, h->lds64.nodes, h->lds64.k0, h->lds64.nn, h->t64.fm, h->t64.emb,
+    const bool node_cut = std::fabs(h->t64.fm.x_last - h->g.rc) <= 1e-12 * h->g.rc;
+    auto kern = node_cut ? k_rho_lds64<true> : k_rho_lds64<false>;
+    hipLaunchKernelGGL(kern, dim3(h->persistent_grid), dim3(TILE2_THREADS), 0, h->stream, o, h->st64p, h->K, h->K_in,
+                       h->u_cut2, h->rwin64.recs, h->rwin64.nrec, h->rwin64.band, h->t64.f, h->t64.fm, h->t64.emb,
                        h->t64.em, h->g.rc2);
     return hipGetLastError();
 }

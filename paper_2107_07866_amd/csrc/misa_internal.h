@@ -359,31 +359,25 @@ struct NearFix32 {
     int32_t nwin = 0, node_cut = 0, K = 0;
 };
 
-// Force records of the persistent float64 force pass held in LDS beside its tile: at
-// most FWIN64_MAX table segments (48 bytes each: f' and phi' as quadratics in t) plus
-// one zero record.  Tables of at most FWIN64_MAX segments are held whole.  Larger
-// tables are held as bands of segments around the distances of the stencil's shells
-// (r in [d - w, d + w], w as wide as the records allow, overlapping bands merged, the
-// top band reaching the last node); the zero record follows the top band and stands for
-// segment nseg, where pairs at or past the cut-off land.  band[p KMAX + k] = {first
-// segment, segments (zero record included), first LDS record, 0} for stencil entry k of
-// parity p; a pair outside its entry's band reads its record from global memory.
+// Table records of a persistent float64 pass held in LDS beside its tile, as bands of
+// segments: the whole table when it has at most cap - 1 segments (cap: the records the
+// pass has room for), else bands around the distances of the stencil's shells (r in
+// [d - w, d + w], w as wide as the records allow, overlapping bands merged, the top band
+// reaching the last node).  A zero record follows the top band and stands for segment
+// nseg, where pairs at or past the cut-off land.  band[p KMAX + k] = {first segment,
+// segments (zero record included), first LDS record, 0} for stencil entry k of parity p;
+// a pair outside its entry's band reads its record from global memory.
+//   force pass: FWIN64_MAX + 1 records of 48 bytes (f' and phi' as quadratics in t);
+//   density pass: RWIN64_MAX records of 32 bytes (f as a cubic in t).
 constexpr int FWIN64_MAX = 1080;
-struct ForceWin64 {
-    double2 *recs = nullptr;  // nrec records of 3 double2, in LDS order
+constexpr int RWIN64_MAX = 2520;
+struct BandWin64 {
+    double2 *recs = nullptr;  // nrec records (3 or 2 double2 each), in LDS order
     int4 *band = nullptr;     // 2 KMAX entries
     int32_t nrec = 0;
     double halfwidth = 0.0;   // w of the shell bands (0 when the table is held whole)
 };
 
-// Window of the f spline's nodes for the persistent float64 density pass: node
-// k0 + i holds {y, m} (value, and slope in units of the sample spacing), i < nn.
-constexpr int NODE64_MAX = 4096;
-struct NodeWin64 {
-    double2 *nodes = nullptr;
-    int32_t k0 = 0, nn = 0;
-    bool usable = false;
-};
 
 // Forward half of the stencil for the half-stencil passes, per parity: entries
 // grouped by phase (dZ, partner parity != own), nearest first inside a phase,
@@ -457,8 +451,8 @@ struct misa_lattice {
     misa::NearTab *near_h = nullptr;              // the same in half-stencil order
     misa::StencilEntry<float> *st32p = nullptr;   // stencil with LDS offsets of the 8x8x8 tiles
     misa::StencilEntry<double> *st64p = nullptr;  // the same offsets, float64 separations
-    misa::NodeWin64 lds64;                        // f nodes for the persistent float64 density pass
-    misa::ForceWin64 fwin64;                      // force records of the persistent float64 force pass
+    misa::BandWin64 fwin64;                       // force records of the persistent float64 force pass
+    misa::BandWin64 rwin64;                       // f records of the persistent float64 density pass
     int pair_schedule = 0;                        // MISA_PAIRS_GATHER or MISA_PAIRS_HALF
     bool half_fits = false;                       // every axis a multiple of 16 cells (8 colours of tiles)
     misa::StencilEntry<float> *sth = nullptr;     // half-stencil entries (device [2][KMAX])
