@@ -221,11 +221,10 @@ def test_shifted_force_tables(torch_cuda, orc):
 
 @pytest.mark.parametrize("npts", [1000, 20000])
 def test_fp64_table_resolution(torch_cuda, orc, npts):
-    """Float64 passes with coarse and fine tables.  1000 points: the whole force table
-    sits in the LDS window.  20 000 points: the f node window (r >= nearest-site
-    distance - 2 delta) exceeds 4096 nodes, so the density pass takes the tile kernel
-    with global spline records, and the force pass's LDS window holds only r >= 4.73 A,
-    so the fourth shell straddles its edge (mixed LDS / global reads within a wave)."""
+    """Float64 passes with coarse and fine tables.  1000 points: both passes hold the
+    whole table in LDS.  20 000 points: the LDS records are narrow bands around the
+    shell distances (about +-0.03 A for the force pass), so at sigma = 0.08 A most pairs
+    read their records from global memory and a wave mixes LDS and global reads."""
     _say(f"fp64 tables of {npts} points")
     tabs = w.potential_samples(n_points=npts)
     p = orc.Potential(orc.TABLE, tables=tabs)
@@ -234,6 +233,40 @@ def test_fp64_table_resolution(torch_cuda, orc, npts):
     lat.set_state(x, v)
     r = _compare_state(orc, p, lat, x, box)
     _say(f"  {npts}: {r}")
+    lat.close()
+
+
+def test_fp64_band_misses(torch_cuda, orc, pot):
+    """Float64 passes with 5000-point tables hold bands of records around the shell
+    distances in LDS (about +-0.12 A for the force pass, +-0.3 A for the density pass);
+    at sigma = 0.2 A a large share of the pairs falls outside them and reads the
+    table's records from global memory, and some atoms leave their slots."""
+    _say("fp64 band misses, sigma 0.2 A")
+    x, v, box = w.thermal_state(6, sigma=0.2, seed=21)
+    lat = _lattice(6, cap=4096)
+    lat.set_state(x, v)
+    r = _compare_state(orc, pot, lat, x, box)
+    _say(f"  {r}")
+    lat.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cutoff_inside_table(torch_cuda, orc, precision):
+    """rc = 4.6 A with tables that run to 5.0 A: the last node is not at the cut-off, so
+    the passes drop pairs past rc by a comparison instead of the zero record."""
+    rc = 4.6
+    _say(f"{precision}: rc {rc} inside the tables")
+    from paper_2107_07866_amd import Lattice
+    p = orc.Potential(orc.TABLE, rc=rc, tables=TABLES)
+    x, v, box = w.thermal_state(6, sigma=0.08, seed=23)
+    lat = Lattice(6, A, rc, DELTA, M, precision, runaway_capacity=0)
+    lat.set_tables(TABLES)
+    lat.set_state(x, v)
+    if precision == "fp64":
+        r = _compare_state(orc, p, lat, x, box)
+    else:
+        r = _compare_state(orc, p, lat, x, box, ftol=1e-3, rtol=1e-5, etol=1e-5)
+    _say(f"  {r}")
     lat.close()
 
 
