@@ -903,8 +903,15 @@ __device__ __forceinline__ void runaway_force_one(const State &S, const Scratch 
 constexpr int RC_THREADS = 256;
 constexpr int RC_SPLIT = 16;
 constexpr int RC_HOME = RC_THREADS / RC_SPLIT;
-constexpr int RC_CAND = 640;  // run-away partners staged per home cell
-constexpr int RC_LAT = 608;   // slotted lattice atoms staged per home cell (the density pass fits 4 blocks per CU)
+constexpr int RC_CAND = 512;  // run-away partners staged per home cell
+constexpr int RC_LAT = 448;   // slotted lattice atoms staged per home cell
+// Blocks per CU the cell-staged passes are compiled for.  A cell's staging is a few
+// dependent memory round trips for about a dozen home atoms, so the passes gain from
+// more cells in flight: 5 density blocks (96 VGPRs, 31 KB of LDS each) and 4 force
+// blocks (128 VGPRs with a few spills outside the pair loops, 39 KB) instead of the 4
+// and 3 that 126 and 147 VGPRs and the larger capacities (640 / 608) allowed.
+constexpr int RC_RHO_BLOCKS = 5;
+constexpr int RC_FORCE_BLOCKS = 4;
 
 template <bool FORCE>
 struct CellStage {
@@ -1325,7 +1332,7 @@ __global__ __launch_bounds__(64 * LONE_WAVES) void k_runaway_force_lone(State S,
         runaway_force_one(S, sc, g, T, real_is_f32, energy, sc.sidx[sc.loneq[i]], lane);
 }
 
-__global__ __launch_bounds__(RC_THREADS) void k_runaway_rho_cells(State S, Scratch sc, Geom g, Tables<double> T) {
+__global__ __launch_bounds__(RC_THREADS, RC_RHO_BLOCKS) void k_runaway_rho_cells(State S, Scratch sc, Geom g, Tables<double> T) {
     __shared__ CellStage<false> st;
     const int n = sc.cnt->n_cells;
     for (int ci = blockIdx.x; ci < n; ci += gridDim.x) {
@@ -1334,7 +1341,7 @@ __global__ __launch_bounds__(RC_THREADS) void k_runaway_rho_cells(State S, Scrat
     }
 }
 
-__global__ __launch_bounds__(RC_THREADS) void k_runaway_force_cells(State S, Scratch sc, Geom g, Tables<double> T,
+__global__ __launch_bounds__(RC_THREADS, RC_FORCE_BLOCKS) void k_runaway_force_cells(State S, Scratch sc, Geom g, Tables<double> T,
                                                                     int real_is_f32, int energy) {
     __shared__ CellStage<true> st;
     const int n = sc.cnt->n_cells;
@@ -1534,7 +1541,7 @@ __global__ __launch_bounds__(64 * LONE_WAVES) void kf_runaway_force_lone(const B
     }
 }
 
-__global__ __launch_bounds__(RC_THREADS) void kf_runaway_rho(const BoxRef *__restrict__ boxes, int nbox,
+__global__ __launch_bounds__(RC_THREADS, RC_RHO_BLOCKS) void kf_runaway_rho(const BoxRef *__restrict__ boxes, int nbox,
                                                              const int32_t *off, Tables<double> T) {
     extern __shared__ int s_off[];
     __shared__ CellStage<false> st;
@@ -1547,7 +1554,7 @@ __global__ __launch_bounds__(RC_THREADS) void kf_runaway_rho(const BoxRef *__res
     }
 }
 
-__global__ __launch_bounds__(RC_THREADS) void kf_runaway_force(const BoxRef *__restrict__ boxes, int nbox,
+__global__ __launch_bounds__(RC_THREADS, RC_FORCE_BLOCKS) void kf_runaway_force(const BoxRef *__restrict__ boxes, int nbox,
                                                                const int32_t *off, Tables<double> T, int energy) {
     extern __shared__ int s_off[];
     __shared__ CellStage<true> st;
@@ -1749,10 +1756,10 @@ static Tables<float> t32_of(misa_lattice *h) {
 
 // Blocks of the cell-staged run-away passes on one box: as many as stay resident, since
 // the number of occupied cells is known on the device only.
-static int cell_grid(const misa_lattice *h) {
+template <typename Kernel>
+static int cell_grid(const misa_lattice *h, Kernel k) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_runaway_force_cells, RC_THREADS, 0) != hipSuccess)
-        per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, RC_THREADS, 0) != hipSuccess) per_cu = 0;
     return std::max(SMALL_GRID, per_cu * h->n_cu);
 }
 
@@ -1782,7 +1789,7 @@ hipError_t launch_runaway_rho(misa_lattice *h) {
     hipStream_t st = h->stream;
     hipLaunchKernelGGL(k_runaway_rho_lone, dim3(SMALL_GRID), dim3(64 * LONE_WAVES), 0, st, h->S, h->sc, h->g,
                        t64_of(h));
-    hipLaunchKernelGGL(k_runaway_rho_cells, dim3(cell_grid(h)), dim3(RC_THREADS), 0, st, h->S, h->sc, h->g,
+    hipLaunchKernelGGL(k_runaway_rho_cells, dim3(cell_grid(h, k_runaway_rho_cells)), dim3(RC_THREADS), 0, st, h->S, h->sc, h->g,
                        t64_of(h));
     hipLaunchKernelGGL(k_mark_count, dim3(h->sc.mark_nblk), dim3(MARK_THREADS), 0, st, h->sc);
     hipLaunchKernelGGL(k_mark_scan, dim3(1), dim3(1024), 0, st, h->sc, h->sc.mark_nblk);
@@ -1800,7 +1807,7 @@ hipError_t launch_runaway_force(misa_lattice *h, bool energy, bool kick) {
     hipStream_t st = h->stream;
     hipLaunchKernelGGL(k_runaway_force_lone, dim3(SMALL_GRID), dim3(64 * LONE_WAVES), 0, st, h->S, h->sc, h->g,
                        t64_of(h), h->precision == MISA_FP32 ? 1 : 0, energy ? 1 : 0);
-    hipLaunchKernelGGL(k_runaway_force_cells, dim3(cell_grid(h)), dim3(RC_THREADS), 0, st, h->S, h->sc, h->g,
+    hipLaunchKernelGGL(k_runaway_force_cells, dim3(cell_grid(h, k_runaway_force_cells)), dim3(RC_THREADS), 0, st, h->S, h->sc, h->g,
                        t64_of(h), h->precision == MISA_FP32 ? 1 : 0, energy ? 1 : 0);
     const double kf = ACC_UNIT / h->mass;
     if (h->precision == MISA_FP32)
