@@ -908,8 +908,8 @@ constexpr int RC_LAT = 448;   // slotted lattice atoms staged per home cell
 // Blocks per CU the cell-staged passes are compiled for.  A cell's staging is a few
 // dependent memory round trips for about a dozen home atoms, so the passes gain from
 // more cells in flight: 5 density blocks (96 VGPRs, 31 KB of LDS each) and 4 force
-// blocks (128 VGPRs with a few spills outside the pair loops, 39 KB) instead of the 4
-// and 3 that 126 and 147 VGPRs and the larger capacities (640 / 608) allowed.
+// blocks (127 VGPRs, 39 KB) instead of the 4 and 3 that 126 and 147 VGPRs and the
+// larger capacities (640 / 608) allowed.
 constexpr int RC_RHO_BLOCKS = 5;
 constexpr int RC_FORCE_BLOCKS = 4;
 
@@ -1121,7 +1121,7 @@ __device__ __forceinline__ void take_group(uint64_t &m, int k, int e[G], bool v[
 }
 
 constexpr int RC_RHO_GROUP = 4;    // f records in flight per lane
-constexpr int RC_FORCE_GROUP = 2;  // f', phi' and phi records in flight per lane
+constexpr int RC_FORCE_GROUP = 1;  // f', phi' and phi records in flight per lane (2 spilled at 4 blocks per CU)
 
 __device__ __forceinline__ void runaway_rho_cell(const State &S, const Scratch &sc, const Geom &g,
                                                  const Tables<double> &T, int hs, CellStage<false> &st) {
