@@ -31,6 +31,14 @@ __device__ __forceinline__ double wave_sum64(double v) {
     return v;
 }
 
+// i mod n for i in (-n, 2n): the lattice cells of a search window around a point of the
+// box (the box spans more than two search reaches on every axis), wrapped with two
+// conditional corrections instead of an integer division.
+__device__ __forceinline__ int wrap_near(int i, int n) {
+    i = i < 0 ? i + n : i;
+    return i >= n ? i - n : i;
+}
+
 template <typename Real>
 __device__ __forceinline__ void seg64(double x, const TabMeta<Real> &m, int &k, double &t) {
     const double p = (x - (double)m.x0) * (double)m.inv_h;
@@ -656,7 +664,7 @@ __device__ __forceinline__ bool affected_pair(const double xo[3], const int cj[3
     const int nn[3] = {g.nx, g.ny, g.nz};
     for (int k = 0; k < 3; ++k) {
         const int lo = window_lo(xo[k] * g.inv_a, g.reach);
-        cc[k] = lo + wrap_index(cj[k] - lo, nn[k]);
+        cc[k] = lo + wrap_near(cj[k] - lo, nn[k]);
         if (cc[k] - lo >= g.win) return false;
     }
     lat_sep(cc[0], cc[1], cc[2], p, u, xo, g.a, d);
@@ -684,8 +692,8 @@ __device__ __forceinline__ void runaway_rho_one(const State &S, const Scratch &s
             const int rem = c - p * win3;
             const int cx = lo[0] + rem % win, cy = lo[1] + (rem / win) % win, cz = lo[2] + rem / (win * win);
             const int64_t s = (int64_t)p * g.ncell +
-                              ((int64_t)wrap_index(cz, g.nz) * g.ny + wrap_index(cy, g.ny)) * g.nx +
-                              wrap_index(cx, g.nx);
+                              ((int64_t)wrap_near(cz, g.nz) * g.ny + wrap_near(cy, g.ny)) * g.nx +
+                              wrap_near(cx, g.nx);
             const double ux = S.ux[s];
             if (ux > VACANT_TEST) continue;
             const double u[3] = {ux, S.uy[s], S.uz[s]};
@@ -843,8 +851,8 @@ __device__ __forceinline__ void runaway_force_one(const State &S, const Scratch 
             const int rem = c - p * win3;
             const int cx = lo[0] + rem % win, cy = lo[1] + (rem / win) % win, cz = lo[2] + rem / (win * win);
             const int64_t s = (int64_t)p * g.ncell +
-                              ((int64_t)wrap_index(cz, g.nz) * g.ny + wrap_index(cy, g.ny)) * g.nx +
-                              wrap_index(cx, g.nx);
+                              ((int64_t)wrap_near(cz, g.nz) * g.ny + wrap_near(cy, g.ny)) * g.nx +
+                              wrap_near(cx, g.nx);
             const double ux = S.ux[s];
             if (ux > VACANT_TEST) continue;
             const double u[3] = {ux, S.uy[s], S.uz[s]};
@@ -968,8 +976,8 @@ __device__ bool stage_cell(const State &S, const Scratch &sc, const Geom &g, int
         const int ox = rem % ww[0], oy = (rem / ww[0]) % ww[1], oz = rem / w01;
         pack = (uint32_t)ox | ((uint32_t)oy << 8) | ((uint32_t)oz << 16) | ((uint32_t)p << 24);
         return (int64_t)p * g.ncell +
-               ((int64_t)wrap_index(wlo[2] + oz, g.nz) * g.ny + wrap_index(wlo[1] + oy, g.ny)) * g.nx +
-               wrap_index(wlo[0] + ox, g.nx);
+               ((int64_t)wrap_near(wlo[2] + oz, g.nz) * g.ny + wrap_near(wlo[1] + oy, g.ny)) * g.nx +
+               wrap_near(wlo[0] + ox, g.nx);
     };
     double ux[RC_WIN_BATCHES];
     int64_t ws[RC_WIN_BATCHES];
