@@ -715,6 +715,7 @@ int misa_create_lattice(const misa_lattice_desc *d, void *hip_stream, misa_latti
     ALLOC(sc.cellq, rcap);
     ALLOC(sc.sfp, rcap);
     ALLOC(sc.loneq, rcap);
+    ALLOC(sc.sorder, rcap);
     ALLOC(sc.mark, sc.mark_nwords);
     ALLOC(sc.mark_blk, sc.mark_nblk);
     ALLOC(sc.mark_off, sc.mark_nblk);
@@ -763,7 +764,7 @@ int misa_destroy_lattice(misa_lattice *h) {
                     h->t32.phi, h->t32.emb, h->sc.cnt, h->sc.scal, h->sc.part, h->sc.l_site, h->sc.l_id, h->sc.l_x,
                     h->sc.l_y, h->sc.l_z, h->sc.l_vx, h->sc.l_vy, h->sc.l_vz, h->sc.cand, h->sc.settled,
                     h->sc.sortbuf, h->sc.skey, h->sc.sidx, h->sc.cell_n, h->sc.cell_s, h->sc.cs_blk,
-                    h->sc.srx, h->sc.sry, h->sc.srz, h->sc.cellq, h->sc.loneq, h->sc.sfp, h->sc.mark,
+                    h->sc.srx, h->sc.sry, h->sc.srz, h->sc.cellq, h->sc.loneq, h->sc.sorder, h->sc.sfp, h->sc.mark,
                     h->sc.mark_blk, h->sc.mark_off, h->sc.affected, h->sc.aff_v2, h->sc.aff_e, h->sc.part_kick, h->staging,
                     h->mlp.p[0], h->mlp.p[1], h->mlp.p[2], h->mlp.w2b[0], h->mlp.w2b[1], h->mlp.w2b[2],
                     h->pairbuf};

@@ -291,6 +291,7 @@ struct Scratch {
     int32_t *cs_blk;               // per-block totals of the cell scan
     int32_t cs_nblk;
     int32_t *skey, *sidx;          // cell and list index of each sorted place
+    int32_t *sorder;               // list indices in (cell, list index) order while a build is ordered
     double *srx, *sry, *srz;       // run-away positions in the sorted (cell, list index) order
     double *sfp;                   // run-away F' in that order (written by the density pass)
     int32_t *cellq;                // sorted position of the first run-away of each crowded cell (any order)

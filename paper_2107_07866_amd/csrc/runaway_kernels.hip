@@ -386,10 +386,11 @@ __global__ __launch_bounds__(1024) void kb_compact(const BoxRef *__restrict__ bo
 // count: run-aways per cell; scan: cell_s[c] = run-aways in cells before c (three
 // kernels: block totals, their scan, the block scans); scatter: each run-away takes a
 // place in its cell's stretch (counting the cell back down to zero, which leaves the
-// grid ready for the next build); order: each stretch is put in ascending list index
-// (so every later pass sees the same order whatever the scatter's timing), the sorted
-// copies are written, and the cell (or its atoms) is listed for the density and force
-// passes.  cell_s[c + 1] - cell_s[c] is then the cell's run-away count.
+// grid ready for the next build); rank and order: each stretch is put in ascending list
+// index, one lane per run-away (so every later pass sees the same order whatever the
+// scatter's timing), the sorted copies are written, and the cell (or its atoms) is listed
+// for the density and force passes.  cell_s[c + 1] - cell_s[c] is then the cell's
+// run-away count.
 
 // Cells with at least this many run-aways have their sums taken by cell (one block
 // stages the cell's neighbourhood); the atoms of sparser cells are taken one by one.
@@ -551,27 +552,42 @@ __global__ void kb_cell_scatter(const BoxRef *__restrict__ boxes) {
     cell_scatter_body(B.S, B.sc, B.g);
 }
 
-__device__ __forceinline__ void cell_order_body(const State &S, Scratch sc) {
+// rank: each run-away's place inside its cell's stretch is the count of the stretch's
+// entries with a smaller list index (distinct), so the stretch comes out in ascending
+// list index whatever order the scatter left it in.
+__device__ __forceinline__ void cell_rank_body(Scratch sc) {
     const int n = sc.cnt->n_run;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
         const int32_t key = sc.skey[q];
+        const int start = sc.cell_s[key], end = sc.cell_s[key + 1];
+        const int32_t v = sc.sidx[q];
+        int rank = 0;
+        for (int i = start; i < end; ++i) rank += sc.sidx[i] < v ? 1 : 0;
+        sc.sorder[start + rank] = v;
+    }
+}
+
+__global__ void k_cell_rank(Scratch sc) {
+    cell_rank_body(sc);
+}
+
+__global__ void kb_cell_rank(const BoxRef *__restrict__ boxes) {
+    cell_rank_body(boxes[blockIdx.y].sc);
+}
+
+// order: the ranked list indices and the sorted position copies, and each cell (or its
+// atoms) listed for the density and force passes by the run-away at its first place.
+__device__ __forceinline__ void cell_order_body(const State &S, Scratch sc) {
+    const int n = sc.cnt->n_run;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const int32_t o = sc.sorder[q];
+        sc.sidx[q] = o;
+        sc.srx[q] = S.r_x[o];
+        sc.sry[q] = S.r_y[o];
+        sc.srz[q] = S.r_z[o];
+        const int32_t key = sc.skey[q];
         if (sc.cell_s[key] != q) continue;  // one lane per cell: the one at its first place
         const int end = sc.cell_s[key + 1];
-        for (int i = q + 1; i < end; ++i) {  // insertion sort; a cell holds a few dozen at most
-            const int32_t v = sc.sidx[i];
-            int j = i - 1;
-            while (j >= q && sc.sidx[j] > v) {
-                sc.sidx[j + 1] = sc.sidx[j];
-                --j;
-            }
-            sc.sidx[j + 1] = v;
-        }
-        for (int i = q; i < end; ++i) {
-            const int32_t o = sc.sidx[i];
-            sc.srx[i] = S.r_x[o];
-            sc.sry[i] = S.r_y[o];
-            sc.srz[i] = S.r_z[o];
-        }
         if (end - q >= RC_MIN_HOME) {
             sc.cellq[atomicAdd(&sc.cnt->n_cells, 1)] = q;
         } else {
@@ -1789,6 +1805,7 @@ hipError_t launch_runaway_build(misa_lattice *h) {
     hipLaunchKernelGGL(k_cell_top, dim3(1), dim3(1024), 0, st, h->sc);
     hipLaunchKernelGGL(k_cell_down, dim3(nb), dim3(CS_THREADS), 0, st, h->sc);
     hipLaunchKernelGGL(k_cell_scatter, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc, h->g);
+    hipLaunchKernelGGL(k_cell_rank, dim3(SMALL_GRID), dim3(256), 0, st, h->sc);
     hipLaunchKernelGGL(k_cell_order, dim3(SMALL_GRID), dim3(256), 0, st, h->S, h->sc);
     return hipGetLastError();
 }
@@ -1843,6 +1860,7 @@ hipError_t launchb_runaway_build(hipStream_t st, const BoxRef *boxes, int nbox, 
     hipLaunchKernelGGL(kb_cell_top, dim3(1, nbox), dim3(1024), 0, st, boxes);
     hipLaunchKernelGGL(kb_cell_down, dim3(gx_cells, nbox), dim3(CS_THREADS), 0, st, boxes);
     hipLaunchKernelGGL(kb_cell_scatter, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
+    hipLaunchKernelGGL(kb_cell_rank, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
     hipLaunchKernelGGL(kb_cell_order, dim3(gx_small, nbox), dim3(256), 0, st, boxes);
     return hipGetLastError();
 }
