@@ -659,8 +659,9 @@ __device__ __forceinline__ void for_runaway_neighbours(const double x[3], int se
     });
 }
 
-// Affected lattice atoms are handled by teams of 32 lanes, lane k scanning coarse cell k
-// (lanes 27..31 idle), so one atom's 27 cell look-ups run side by side, not in series.
+// Affected lattice atoms are handled by teams of 32 lanes: lane k looks up coarse cell k
+// (lanes 27..31 none), so one atom's 27 cell look-ups run side by side, and the cells'
+// run-aways are then dealt over all 32 lanes (for_runaways_around).
 constexpr int AFF_TEAM = 32;
 constexpr int AFF_THREADS = 256;
 constexpr int AFF_GRID = 2048;
@@ -669,6 +670,67 @@ __device__ __forceinline__ double team_sum32(double v) {
     // fixed butterfly: the same lanes meet in the same order on every call
     for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, AFF_TEAM);
     return v;
+}
+
+// Run-aways of the (up to) 27 coarse cells around x, dealt over the AFF_TEAM lanes of a
+// team as one list: the cells' stretches laid end to end (cell 0 first), lane k taking
+// entries k, k + AFF_TEAM, ..., AFF_G at a time with their loads issued together.  Every
+// lane gets about the same number of entries (one lane per cell would wait on the
+// fullest cell, one memory round trip per entry).  fn(o, xo) as for_runaways_in_cell.
+// All lanes of the team must call it together.
+constexpr int AFF_G = 4;
+template <typename Fn>
+__device__ __forceinline__ void for_runaways_around(const double x[3], int lane, const Scratch &sc, const Geom &g,
+                                                    Fn fn) {
+    int start = 0, cnt = 0;
+    if (lane < 27) {
+        const int ax = lane % 3, ay = (lane / 3) % 3, az = lane / 9;
+        int cx[3], cy[3], cz[3];
+        if (ax < axis_cells(coarse_of(x[0], g.nc[0], g.inv_cs[0]), g.nc[0], cx) &&
+            ay < axis_cells(coarse_of(x[1], g.nc[1], g.inv_cs[1]), g.nc[1], cy) &&
+            az < axis_cells(coarse_of(x[2], g.nc[2], g.inv_cs[2]), g.nc[2], cz)) {
+            const int32_t key = (cz[az] * g.nc[1] + cy[ay]) * g.nc[0] + cx[ax];
+            start = sc.cell_s[key];
+            cnt = sc.cell_s[key + 1] - start;
+        }
+    }
+    int incl = cnt;  // inclusive prefix over the team's cells
+    for (int o = 1; o < AFF_TEAM; o <<= 1) {
+        const int t = __shfl_up(incl, o, AFF_TEAM);
+        if (lane >= o) incl += t;
+    }
+    const int total = __shfl(incl, AFF_TEAM - 1, AFF_TEAM);
+    const int base = start - (incl - cnt);  // entry f of this lane's cell sits at base + f
+    for (int f0 = 0; f0 < total; f0 += AFF_G * AFF_TEAM) {
+        int qv[AFF_G];
+        bool ok[AFF_G];
+#pragma unroll
+        for (int t = 0; t < AFF_G; ++t) {
+            const int f = f0 + t * AFF_TEAM + lane;
+            // the cell holding entry f: how many cells end at or before f (5 uniform steps)
+            int c = 0;
+#pragma unroll
+            for (int step = 16; step > 0; step >>= 1)
+                if (__shfl(incl, c + step - 1, AFF_TEAM) <= f) c += step;
+            // every lane reads (an operand of ?: would be read only by the lanes that take
+            // it, and a shuffle from a lane that does not take part returns garbage)
+            const int bq = __shfl(base, c, AFF_TEAM);
+            ok[t] = f < total;
+            qv[t] = ok[t] ? bq + f : 0;
+        }
+        double xo[AFF_G][3];
+        int32_t ov[AFF_G];
+#pragma unroll
+        for (int t = 0; t < AFF_G; ++t) {
+            xo[t][0] = sc.srx[qv[t]];
+            xo[t][1] = sc.sry[qv[t]];
+            xo[t][2] = sc.srz[qv[t]];
+            ov[t] = sc.sidx[qv[t]];
+        }
+#pragma unroll
+        for (int t = 0; t < AFF_G; ++t)
+            if (ok[t]) fn(ov[t], xo[t]);
+    }
 }
 
 // Separation x_j - x_o of lattice atom j (cell cj, parity p, displacement u) from
@@ -801,11 +863,10 @@ __device__ __forceinline__ void affected_rho_one(const State &S, const Scratch &
         site_pos(cj[0], cj[1], cj[2], p, g.a, xj);
         for (int k = 0; k < 3; ++k) xj[k] = wrap_coord(xj[k] + u[k], g.L[k]);
         double acc = 0.0;
-        if (cell < 27)
-            for_runaways_in_cell(xj, cell, 0, 1, sc, g, [&](int, const double *xo) {
-                double d[3], r2;
-                if (affected_pair(xo, cj, p, u, g, d, r2)) acc += f_val(sqrt(r2), T);
-            });
+        for_runaways_around(xj, cell, sc, g, [&](int, const double *xo) {
+            double d[3], r2;
+            if (affected_pair(xo, cj, p, u, g, d, r2)) acc += f_val(sqrt(r2), T);
+        });
         if (nf.frec) acc += near_rho_fix(S, g, nf, s, cj, p, cell);
         acc = team_sum32(acc);
         if (cell == 0) {
@@ -1420,18 +1481,17 @@ __device__ __forceinline__ void affected_force_one(const State &S, const Scratch
         site_pos(cj[0], cj[1], cj[2], p, g.a, xj);
         for (int k = 0; k < 3; ++k) xj[k] = wrap_coord(xj[k] + u[k], g.L[k]);
         double ax = 0.0, ay = 0.0, az = 0.0;
-        if (cell < 27)
-            for_runaways_in_cell(xj, cell, 0, 1, sc, g, [&](int o, const double *xo) {
-                double d[3], r2;  // d = x_j - x_o
-                if (!affected_pair(xo, cj, p, u, g, d, r2)) return;
-                const double rr = sqrt(r2);
-                double df, dphi, phi;
-                fp_phi(rr, T, df, dphi, phi);
-                const double sc_ = ((fpj + S.r_fp[o]) * df + dphi) / rr;
-                ax -= sc_ * d[0];  // separation from j to the run-away is -d
-                ay -= sc_ * d[1];
-                az -= sc_ * d[2];
-            });
+        for_runaways_around(xj, cell, sc, g, [&](int o, const double *xo) {
+            double d[3], r2;  // d = x_j - x_o
+            if (!affected_pair(xo, cj, p, u, g, d, r2)) return;
+            const double rr = sqrt(r2);
+            double df, dphi, phi;
+            fp_phi(rr, T, df, dphi, phi);
+            const double sc_ = ((fpj + S.r_fp[o]) * df + dphi) / rr;
+            ax -= sc_ * d[0];  // separation from j to the run-away is -d
+            ay -= sc_ * d[1];
+            az -= sc_ * d[2];
+        });
         double ae = 0.0;
         if (nf.rec) near_pair_fix(S, g, nf, s, cj, p, cell, ax, ay, az, ae);
         ax = team_sum32(ax);
