@@ -1135,8 +1135,9 @@ __device__ bool stage_cell(const State &S, const Scratch &sc, const Geom &g, int
         if (FORCE) st.lfp[e] = real_is_f32 ? (double)((const float *)S.fp)[si] : ((const double *)S.fp)[si];
     }
     for (int e = tid; e < n_cand; e += RC_THREADS) {
-        int k = 0;
-        while (st.cpre[k + 1] <= e) ++k;
+        int k = 0;  // the cell holding entry e: how many cells end at or before e (5 steps)
+        for (int step = 16; step > 0; step >>= 1)
+            if (k + step <= 27 && st.cpre[k + step] <= e) k += step;
         const int q = st.cstart[k] + (e - st.cpre[k]);
         st.cx[e] = sc.srx[q];
         st.cy[e] = sc.sry[q];
