@@ -641,45 +641,14 @@ __device__ __forceinline__ void for_runaways_in_cell(const double x[3], int cell
     }
 }
 
-// Run-away atoms other than self closer than sqrt(cut2) to x, searched by a whole wave:
-// lanes k and k + 32 share coarse cell k (k < 27) and take alternate entries of it.
-// Calls fn(o, d, r2) with d = x_o - x (minimum image).
-template <typename Fn>
-__device__ __forceinline__ void for_runaway_neighbours(const double x[3], int self, int lane, double cut2,
-                                                       const State &S, const Scratch &sc, const Geom &g,
-                                                       Fn fn) {
-    const int cell = lane & 31;
-    if (cell >= 27) return;
-    for_runaways_in_cell(x, cell, lane >> 5, 2, sc, g, [&](int o, const double *xo) {
-        if (o == self) return;
-        double d[3] = {xo[0] - x[0], xo[1] - x[1], xo[2] - x[2]};
-        min_image3(d, g);
-        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        if (r2 < cut2) fn(o, d, r2);
-    });
-}
-
-// Affected lattice atoms are handled by teams of 32 lanes: lane k looks up coarse cell k
-// (lanes 27..31 none), so one atom's 27 cell look-ups run side by side, and the cells'
-// run-aways are then dealt over all 32 lanes (for_runaways_around).
-constexpr int AFF_TEAM = 32;
-constexpr int AFF_THREADS = 256;
-constexpr int AFF_GRID = 2048;
-
-__device__ __forceinline__ double team_sum32(double v) {
-    // fixed butterfly: the same lanes meet in the same order on every call
-    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, AFF_TEAM);
-    return v;
-}
-
-// Run-aways of the (up to) 27 coarse cells around x, dealt over the AFF_TEAM lanes of a
-// team as one list: the cells' stretches laid end to end (cell 0 first), lane k taking
-// entries k, k + AFF_TEAM, ..., AFF_G at a time with their loads issued together.  Every
-// lane gets about the same number of entries (one lane per cell would wait on the
-// fullest cell, one memory round trip per entry).  fn(o, xo) as for_runaways_in_cell.
-// All lanes of the team must call it together.
-constexpr int AFF_G = 4;
-template <typename Fn>
+// Run-aways of the (up to) 27 coarse cells around x, dealt over the W lanes of a team
+// (W = 32: a team of the affected-atom passes; W = 64: a wave of the per-atom forms) as
+// one list: the cells' stretches laid end to end (cell 0 first), lane k taking entries
+// k, k + W, ..., G at a time with their loads issued together.  Every lane gets
+// about the same number of entries (one lane per cell would wait on the fullest cell,
+// one memory round trip per entry).  fn(o, xo) as for_runaways_in_cell.  All W lanes
+// must call it together.
+template <int W, int G, typename Fn>
 __device__ __forceinline__ void for_runaways_around(const double x[3], int lane, const Scratch &sc, const Geom &g,
                                                     Fn fn) {
     int start = 0, cnt = 0;
@@ -695,42 +664,80 @@ __device__ __forceinline__ void for_runaways_around(const double x[3], int lane,
         }
     }
     int incl = cnt;  // inclusive prefix over the team's cells
-    for (int o = 1; o < AFF_TEAM; o <<= 1) {
-        const int t = __shfl_up(incl, o, AFF_TEAM);
+    for (int o = 1; o < W; o <<= 1) {
+        const int t = __shfl_up(incl, o, W);
         if (lane >= o) incl += t;
     }
-    const int total = __shfl(incl, AFF_TEAM - 1, AFF_TEAM);
+    const int total = __shfl(incl, W - 1, W);
     const int base = start - (incl - cnt);  // entry f of this lane's cell sits at base + f
-    for (int f0 = 0; f0 < total; f0 += AFF_G * AFF_TEAM) {
-        int qv[AFF_G];
-        bool ok[AFF_G];
+    for (int f0 = 0; f0 < total; f0 += G * W) {
+        int qv[G];
+        bool ok[G];
 #pragma unroll
-        for (int t = 0; t < AFF_G; ++t) {
-            const int f = f0 + t * AFF_TEAM + lane;
-            // the cell holding entry f: how many cells end at or before f (5 uniform steps)
+        for (int t = 0; t < G; ++t) {
+            const int f = f0 + t * W + lane;
+            // the cell holding entry f: how many cells end at or before f (log2 W uniform steps)
             int c = 0;
 #pragma unroll
-            for (int step = 16; step > 0; step >>= 1)
-                if (__shfl(incl, c + step - 1, AFF_TEAM) <= f) c += step;
+            for (int step = W / 2; step > 0; step >>= 1)
+                if (__shfl(incl, c + step - 1, W) <= f) c += step;
             // every lane reads (an operand of ?: would be read only by the lanes that take
             // it, and a shuffle from a lane that does not take part returns garbage)
-            const int bq = __shfl(base, c, AFF_TEAM);
+            const int bq = __shfl(base, c, W);
             ok[t] = f < total;
             qv[t] = ok[t] ? bq + f : 0;
         }
-        double xo[AFF_G][3];
-        int32_t ov[AFF_G];
+        double xo[G][3];
+        int32_t ov[G];
 #pragma unroll
-        for (int t = 0; t < AFF_G; ++t) {
+        for (int t = 0; t < G; ++t) {
             xo[t][0] = sc.srx[qv[t]];
             xo[t][1] = sc.sry[qv[t]];
             xo[t][2] = sc.srz[qv[t]];
             ov[t] = sc.sidx[qv[t]];
         }
 #pragma unroll
-        for (int t = 0; t < AFF_G; ++t)
+        for (int t = 0; t < G; ++t)
             if (ok[t]) fn(ov[t], xo[t]);
     }
+}
+
+// Run-away atoms other than self closer than sqrt(cut2) to x, searched by a whole wave:
+// with kDealt the 27 cells' run-aways dealt over the 64 lanes (for_runaways_around; the
+// per-atom passes of sparse cells), else lanes k and k + 32 share coarse cell k (k < 27)
+// and take alternate entries of it (the fall-back inside the cell-staged passes, whose
+// registers are budgeted for their occupancy).
+// Calls fn(o, d, r2) with d = x_o - x (minimum image).
+template <bool kDealt, typename Fn>
+__device__ __forceinline__ void for_runaway_neighbours(const double x[3], int self, int lane, double cut2,
+                                                       const State &S, const Scratch &sc, const Geom &g,
+                                                       Fn fn) {
+    auto pair = [&](int o, const double *xo) {
+        if (o == self) return;
+        double d[3] = {xo[0] - x[0], xo[1] - x[1], xo[2] - x[2]};
+        min_image3(d, g);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 < cut2) fn(o, d, r2);
+    };
+    if (kDealt) {
+        for_runaways_around<64, 2>(x, lane, sc, g, pair);
+    } else {
+        const int cell = lane & 31;
+        if (cell < 27) for_runaways_in_cell(x, cell, lane >> 5, 2, sc, g, pair);
+    }
+}
+
+// Affected lattice atoms are handled by teams of 32 lanes: lane k looks up coarse cell k
+// (lanes 27..31 none), so one atom's 27 cell look-ups run side by side, and the cells'
+// run-aways are then dealt over all 32 lanes (for_runaways_around).
+constexpr int AFF_TEAM = 32;
+constexpr int AFF_THREADS = 256;
+constexpr int AFF_GRID = 2048;
+
+__device__ __forceinline__ double team_sum32(double v) {
+    // fixed butterfly: the same lanes meet in the same order on every call
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, AFF_TEAM);
+    return v;
 }
 
 // Separation x_j - x_o of lattice atom j (cell cj, parity p, displacement u) from
@@ -757,6 +764,7 @@ __device__ __forceinline__ bool affected_pair(const double xo[3], const int cj[3
 // lattice sites in its window and from other run-aways; marks every lattice atom it
 // pairs with (they need the reaction term).
 // q: the atom's place in the sorted order.
+template <bool kDealt>
 __device__ __forceinline__ void runaway_rho_one(const State &S, const Scratch &sc, const Geom &g,
                                                 const Tables<double> &T, int r, int q, int lane) {
     const int win = g.win, win3 = win * win * win;
@@ -783,7 +791,7 @@ __device__ __forceinline__ void runaway_rho_one(const State &S, const Scratch &s
                 atomicOr(&sc.mark[s >> 5], 1u << (s & 31));  // listed in site order by k_mark_emit
             }
         }
-        for_runaway_neighbours(x, r, lane, g.rc2, S, sc, g,
+        for_runaway_neighbours<kDealt>(x, r, lane, g.rc2, S, sc, g,
                                [&](int, const double *, double r2) { acc += f_val(sqrt(r2), T); });
         acc = wave_sum64(acc);
         if (lane == 0) {
@@ -863,7 +871,7 @@ __device__ __forceinline__ void affected_rho_one(const State &S, const Scratch &
         site_pos(cj[0], cj[1], cj[2], p, g.a, xj);
         for (int k = 0; k < 3; ++k) xj[k] = wrap_coord(xj[k] + u[k], g.L[k]);
         double acc = 0.0;
-        for_runaways_around(xj, cell, sc, g, [&](int, const double *xo) {
+        for_runaways_around<AFF_TEAM, 4>(xj, cell, sc, g, [&](int, const double *xo) {
             double d[3], r2;
             if (affected_pair(xo, cj, p, u, g, d, r2)) acc += f_val(sqrt(r2), T);
         });
@@ -913,6 +921,7 @@ __global__ __launch_bounds__(AFF_THREADS) void k_affected_rho(State S, Scratch s
 // ---------------------------------------------------------------------------
 // forces
 
+template <bool kDealt>
 __device__ __forceinline__ void runaway_force_one(const State &S, const Scratch &sc, const Geom &g,
                                                   const Tables<double> &T, int real_is_f32, int energy, int r,
                                                   int lane) {
@@ -948,7 +957,7 @@ __device__ __forceinline__ void runaway_force_one(const State &S, const Scratch 
                 ep += phi;  // lattice partner has no other record of this pair's energy
             }
         }
-        for_runaway_neighbours(x, r, lane, g.rc2, S, sc, g, [&](int o, const double *d, double r2) {
+        for_runaway_neighbours<kDealt>(x, r, lane, g.rc2, S, sc, g, [&](int o, const double *d, double r2) {
             const double rr = sqrt(r2);
             double df, dphi, phi;
             fp_phi(rr, T, df, dphi, phi);
@@ -1216,7 +1225,7 @@ __device__ __forceinline__ void runaway_rho_cell(const State &S, const Scratch &
     if (!stage_cell<false>(S, sc, g, 0, hs, st, n_cand, n_lat, wlo, ww)) {
         const int lane = threadIdx.x & 63;
         for (int j = threadIdx.x >> 6; j < nh; j += RC_THREADS / 64)
-            runaway_rho_one(S, sc, g, T, sc.sidx[hs + j], hs + j, lane);
+            runaway_rho_one<false>(S, sc, g, T, sc.sidx[hs + j], hs + j, lane);
         return;
     }
     const int k = threadIdx.x % RC_SPLIT;
@@ -1313,7 +1322,7 @@ __device__ __forceinline__ void runaway_force_cell(const State &S, const Scratch
     if (!stage_cell<true>(S, sc, g, real_is_f32, hs, st, n_cand, n_lat, wlo, ww)) {
         const int lane = threadIdx.x & 63;
         for (int j = threadIdx.x >> 6; j < nh; j += RC_THREADS / 64)
-            runaway_force_one(S, sc, g, T, real_is_f32, energy, sc.sidx[hs + j], lane);
+            runaway_force_one<false>(S, sc, g, T, real_is_f32, energy, sc.sidx[hs + j], lane);
         return;
     }
     const int k = threadIdx.x % RC_SPLIT;
@@ -1405,7 +1414,7 @@ __global__ __launch_bounds__(64 * LONE_WAVES) void k_runaway_rho_lone(State S, S
     for (int i = blockIdx.x * LONE_WAVES + (threadIdx.x >> 6); i < n; i += gridDim.x * LONE_WAVES)
     {
         const int q = sc.loneq[i];
-        runaway_rho_one(S, sc, g, T, sc.sidx[q], q, lane);
+        runaway_rho_one<true>(S, sc, g, T, sc.sidx[q], q, lane);
     }
 }
 
@@ -1415,7 +1424,7 @@ __global__ __launch_bounds__(64 * LONE_WAVES) void k_runaway_force_lone(State S,
     const int lane = threadIdx.x & 63;
     const int n = sc.cnt->n_lone;
     for (int i = blockIdx.x * LONE_WAVES + (threadIdx.x >> 6); i < n; i += gridDim.x * LONE_WAVES)
-        runaway_force_one(S, sc, g, T, real_is_f32, energy, sc.sidx[sc.loneq[i]], lane);
+        runaway_force_one<true>(S, sc, g, T, real_is_f32, energy, sc.sidx[sc.loneq[i]], lane);
 }
 
 __global__ __launch_bounds__(RC_THREADS, RC_RHO_BLOCKS) void k_runaway_rho_cells(State S, Scratch sc, Geom g, Tables<double> T) {
@@ -1482,7 +1491,7 @@ __device__ __forceinline__ void affected_force_one(const State &S, const Scratch
         site_pos(cj[0], cj[1], cj[2], p, g.a, xj);
         for (int k = 0; k < 3; ++k) xj[k] = wrap_coord(xj[k] + u[k], g.L[k]);
         double ax = 0.0, ay = 0.0, az = 0.0;
-        for_runaways_around(xj, cell, sc, g, [&](int o, const double *xo) {
+        for_runaways_around<AFF_TEAM, 4>(xj, cell, sc, g, [&](int o, const double *xo) {
             double d[3], r2;  // d = x_j - x_o
             if (!affected_pair(xo, cj, p, u, g, d, r2)) return;
             const double rr = sqrt(r2);
@@ -1609,7 +1618,7 @@ __global__ __launch_bounds__(64 * LONE_WAVES) void kf_runaway_rho_lone(const Box
         const int b = __builtin_amdgcn_readfirstlane(flat_box(s_off, nbox, q));  // one item per wave
         const BoxRef &B = boxes[b];
         const int qs = B.sc.loneq[q - s_off[b]];
-        runaway_rho_one(B.S, B.sc, B.g, T, B.sc.sidx[qs], qs, lane);
+        runaway_rho_one<true>(B.S, B.sc, B.g, T, B.sc.sidx[qs], qs, lane);
     }
 }
 
@@ -1622,7 +1631,7 @@ __global__ __launch_bounds__(64 * LONE_WAVES) void kf_runaway_force_lone(const B
     for (int q = blockIdx.x * LONE_WAVES + (threadIdx.x >> 6); q < total; q += gridDim.x * LONE_WAVES) {
         const int b = __builtin_amdgcn_readfirstlane(flat_box(s_off, nbox, q));
         const BoxRef &B = boxes[b];
-        runaway_force_one(B.S, B.sc, B.g, T, 1, energy, B.sc.sidx[B.sc.loneq[q - s_off[b]]], lane);
+        runaway_force_one<true>(B.S, B.sc, B.g, T, 1, energy, B.sc.sidx[B.sc.loneq[q - s_off[b]]], lane);
     }
 }
 
