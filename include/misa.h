@@ -173,6 +173,16 @@ int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n_
 #define MISA_NOALLOC_MAX_ATOMS 4194304 /* 16 MiB of bids per GPU */
 int misa_set_state_noalloc(misa_lattice *h, const double *x, const double *v, int64_t n_atoms);
 
+/*
+ * misa_set_state with explicit atom ids (Sec. 2.1: the problem starts from every
+ * atom's position and velocity; the ids name the atoms): row i of the host arrays
+ * x, v ((n_atoms, 3) float64) belongs to atom ids[i] (host int64).  The ids must be
+ * a permutation of 0 .. n_atoms - 1, else MISA_EINVAL before anything is loaded.
+ * The placement, its id priority and its errors are those of misa_set_state with
+ * the rows in id order; misa_get_state returns the atoms in id order.
+ */
+int misa_set_state_ids(misa_lattice *h, const double *x, const double *v, const int64_t *ids, int64_t n_atoms);
+
 /* Copy positions (wrapped into the box) and velocities out, in atom-id order,
  * to (n_atoms, 3) float64 arrays in host or device memory; either may be NULL. */
 int misa_get_state(misa_lattice *h, double *x, double *v, int where);

@@ -1119,6 +1119,25 @@ int check_set_state(misa_lattice *h, const double *x, const double *v, int64_t n
 
 extern "C" {
 
+int misa_set_state_ids(misa_lattice *h, const double *x, const double *v, const int64_t *ids, int64_t n) {
+    if (!h) return fail(nullptr, MISA_EINVAL, "null handle");
+    if (n < 0 || (n > 0 && (!x || !v || !ids))) return fail(h, MISA_EINVAL, "need x, v and ids for n_atoms > 0");
+    // rows in id order; the ids must name every atom once
+    std::vector<double> xs((size_t)3 * n), vs((size_t)3 * n);
+    std::vector<char> seen((size_t)n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t id = ids[i];
+        if (id < 0 || id >= n || seen[(size_t)id])
+            return fail(h, MISA_EINVAL, "ids must be a permutation of 0 .. n_atoms - 1");
+        seen[(size_t)id] = 1;
+        for (int k = 0; k < 3; ++k) {
+            xs[(size_t)3 * id + k] = x[3 * i + k];
+            vs[(size_t)3 * id + k] = v[3 * i + k];
+        }
+    }
+    return misa_set_state(h, n ? xs.data() : x, n ? vs.data() : v, n, MISA_HOST);
+}
+
 int misa_set_state(misa_lattice *h, const double *x, const double *v, int64_t n, int where) {
     int rc = check_set_state(h, x, v, n);
     if (rc) return rc;

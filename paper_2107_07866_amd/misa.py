@@ -93,6 +93,7 @@ def _load():
                                       C.c_int),
         "misa_set_state": ([vp, vp, vp, i64, C.c_int], C.c_int),
         "misa_set_state_noalloc": ([vp, vp, vp, i64], C.c_int),
+        "misa_set_state_ids": ([vp, vp, vp, vp, i64], C.c_int),
         "misa_checkpoint_bytes": ([vp, C.POINTER(i64)], C.c_int),
         "misa_save_checkpoint": ([vp, vp, i64], C.c_int),
         "misa_load_checkpoint": ([vp, vp, i64], C.c_int),
@@ -226,6 +227,20 @@ def misa_set_state(h, x, v):
     if where != where_v:
         raise ValueError("x and v must live in the same memory")
     return _check(lib.misa_set_state(h, px, pv, n, where), h)
+
+
+def misa_set_state_ids(h, x, v, ids):
+    """x, v: (N, 3) float64 host arrays whose row i belongs to atom ids[i]; ids: a
+    permutation of 0 .. N - 1 (int64)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)
+    ids = np.ascontiguousarray(ids, dtype=np.int64).reshape(-1)
+    n = x.shape[0]
+    if v.shape[0] != n or ids.shape[0] != n:
+        raise ValueError("x, v and ids must have the same number of rows")
+    vp = C.c_void_p
+    return _check(lib.misa_set_state_ids(h, x.ctypes.data_as(vp), v.ctypes.data_as(vp),
+                                         ids.ctypes.data_as(vp), n), h)
 
 
 def misa_checkpoint_bytes(h):

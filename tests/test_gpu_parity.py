@@ -153,6 +153,32 @@ def test_placement_from_device_memory_and_failures(torch_cuda, orc):
     lat.close()
 
 
+def test_set_state_with_ids(torch_cuda, orc):
+    """Rows given in any order with their atom ids place exactly as the rows in id order;
+    ids that are not a permutation are refused before anything is loaded."""
+    from paper_2107_07866_amd import misa as M
+    n = 7
+    states, box = _defect_states(n, seed=9)
+    x, v = states["many_runaways"]
+    _say("set_state_ids: shuffled rows with their ids")
+    lat = _lattice(n, cap=4096)
+    lat.set_state(x, v)
+    ref_slots = lat.slots()
+    ref_x, ref_v = lat.get_state()
+    perm = np.random.default_rng(5).permutation(len(x))
+    M.misa_set_state_ids(lat.h, x[perm], v[perm], perm)
+    assert np.array_equal(lat.slots(), ref_slots)
+    gx, gv = lat.get_state()
+    assert np.array_equal(gx, ref_x) and np.array_equal(gv, ref_v)
+    bad = perm.copy()
+    bad[3] = bad[4]
+    with pytest.raises(M.MisaError) as err:
+        M.misa_set_state_ids(lat.h, x[perm], v[perm], bad)
+    assert err.value.code == M.MISA_EINVAL
+    assert np.array_equal(lat.slots(), ref_slots)  # refused before anything was loaded
+    lat.close()
+
+
 # ---------------------------------------------------------------------------
 # per-state densities, forces, energies (FP64)
 
